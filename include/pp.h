@@ -1,0 +1,212 @@
+/*
+ * pp.h -- C interface of the MI355X (gfx950) seed-bitset propagation library.
+ *
+ * The library computes PROPAGATE-P (Amati et al., "PROPAGATE: a seed
+ * propagation framework to compute distance-based metrics on very large
+ * graphs", Section 4, Algorithm 1): every node u keeps an s-bit signature
+ * Sig(u), bit i set when u can reach seed x_i within the rounds run so far.
+ * One synchronous round computes, for every u,
+ *     Sig_r(u) = Sig_{r-1}(u)  OR  OR_{u -> v} Sig_{r-1}(v)
+ * (the ball recurrence of Section 4, with u's own ball kept as Algorithm 1
+ * does), and counts the newly set bits c[r] = sum_u popcount(Sig_r(u) XOR
+ * Sig_{r-1}(u)) -- the number of (node, seed) pairs at distance exactly r.
+ * The loop stops at the first round that sets no bit.  The metrics of the
+ * paper's Section 3 are then estimated from c[0..D].
+ *
+ * Conventions shared by every entry point
+ *   - Every function returns a pp_status (0 = success, < 0 = error); none
+ *     throws or aborts.  pp_last_error() gives a message for the calling
+ *     thread's last failure.
+ *   - Node ids are int32 in [0, n).  Signature bit i (seed i) is word i >> 6,
+ *     bit i & 63 of the node's row; rows are W uint64 words, W the smallest
+ *     power of two >= ceil(s / 64) (pp_run_words), stored node-major
+ *     ([n][W]).  Bits >= s stay zero.
+ *   - Round numbering: c[0] = s counts the seeds' own pairs; round r >= 1
+ *     adds the pairs at distance exactly r.  D is the last round with
+ *     c[D] > 0 (the diameter lower bound); D + 1 rounds run, the last one
+ *     finding no new bit.
+ *   - Device work is ordered on the HIP stream given at handle creation
+ *     (NULL = the library makes its own non-blocking stream).  Calls that
+ *     write host memory synchronise that stream before returning.
+ *   - Arguments are validated before any device work; a failed validation
+ *     leaves the handles unchanged.
+ *   - Handles are not thread-safe: use one thread per handle at a time.
+ *   - Device memory is owned by the handles and released by the *_free calls.
+ */
+#ifndef PP_H
+#define PP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PP_OK = 0,
+    PP_EINVAL = -1,     /* malformed argument (sizes, flags, s out of range, NULL) */
+    PP_ERANGE = -2,     /* a node id outside [0, n) or outside its graph */
+    PP_ENOMEM = -3,     /* device or host allocation failed */
+    PP_EDEVICE = -4,    /* a HIP runtime call failed */
+    PP_ENOTCONV = -5,   /* the round cap was reached before convergence */
+    PP_ESTATE = -6      /* call not valid in the handle's current state */
+} pp_status;
+
+typedef struct pp_graph_s *pp_graph;   /* device CSR + predecessor lists + tiling */
+typedef struct pp_run_s *pp_run;       /* signatures, frontier, per-round logs */
+
+/* pp_csr_build flags */
+enum {
+    PP_UNDIRECTED = 1,       /* each input pair (a, b) stands for arcs a->b and b->a */
+    PP_INPUT_ON_DEVICE = 2,  /* src/dst point to device memory */
+    PP_TRANSPOSE = 4         /* propagate along reversed arcs: bit i reaches u when
+                                x_i can reach u (instead of u reaching x_i) */
+};
+
+/* per-round direction policy */
+enum {
+    PP_SCHED_HEURISTIC = 0,  /* fixed-threshold push/pull switch on frontier arcs */
+    PP_SCHED_PULL = 1,       /* every round a dense pull over all arcs */
+    PP_SCHED_PUSH = 2,       /* every round a push from the changed nodes */
+    PP_SCHED_FUZZ = 3,       /* pseudo-random choice per round (testing: outputs must not change) */
+    PP_SCHED_MLP = 4         /* learned cost model, heuristic fallback */
+};
+
+/* Options of a run.  Zero-initialise and set what you need; pp_options_default
+ * fills the defaults. */
+typedef struct {
+    int32_t scheduler;          /* PP_SCHED_* */
+    int32_t seed_counts;        /* 1: also record per-seed counts c_i[r] */
+    int32_t max_rounds;         /* capacity of the per-round logs (0: n + 1, at most 1<<20) */
+    int32_t rounds_per_sync;    /* rounds launched between host convergence checks (0: adaptive) */
+    int32_t use_graph;          /* 1: replay the round batch as a captured hipGraph */
+    int32_t push_div;           /* heuristic: push while frontier arcs * push_div < arcs (0: 8) */
+    uint64_t fuzz_seed;         /* PP_SCHED_FUZZ stream */
+} pp_options;
+
+/* Metrics estimated from c[0..D] (paper Section 3 and Algorithm 1's closing
+ * steps).  T = c[0] + ... + c[D] counts (node, seed) pairs within reach,
+ * seeds' own pairs included; every value is computed from exact integers
+ * with one final rounding per operand, in the order documented at
+ * pp_estimate_metrics. */
+typedef struct {
+    int32_t diameter;           /* D, the diameter lower bound */
+    int32_t rounds_executed;    /* D + 1 */
+    int64_t R_final;            /* T */
+    double eff_diam;            /* least k with tau_den * R[k] >= tau_num * T */
+    double eff_diam_interp;     /* linear interpolation of the crossing between k-1 and k */
+    double avg_dist;            /* sum_r r c[r] / (T - s): pairs u != v */
+    double avg_dist_paper;      /* sum_r r c[r] / T: self-pairs in the denominator */
+    double reachable_pairs;     /* n * T / s, self-pairs included */
+    double alpha;               /* (T - s) / (s (n - 1)); 0 when n = 1 */
+} pp_metrics;
+
+/* Fills *opt with the defaults (heuristic scheduler, no per-seed counts,
+ * adaptive sync, graph replay on). */
+void pp_options_default(pp_options *opt);
+
+/*
+ * pp_csr_build -- the graph G = (V, E) of Algorithm 1's input.
+ *   n, m        nodes and input pairs (m >= 0, 1 <= n < 2^31).
+ *   src, dst    m node ids each: pair k is the arc src[k] -> dst[k] (both
+ *               directions with PP_UNDIRECTED).  Host memory unless
+ *               PP_INPUT_ON_DEVICE; the caller keeps ownership.
+ *   flags       PP_UNDIRECTED | PP_INPUT_ON_DEVICE | PP_TRANSPOSE.
+ *   node_offsets, num_graphs
+ *               a batch of num_graphs disjoint graphs: graph g owns node ids
+ *               [node_offsets[g], node_offsets[g+1]) (host array of
+ *               num_graphs + 1 entries, node_offsets[0] = 0,
+ *               node_offsets[num_graphs] = n, non-decreasing).  NULL with
+ *               num_graphs <= 1 means one graph.  An arc joining two graphs
+ *               is PP_ERANGE.
+ *   stream      hipStream_t the build is ordered on (NULL: legacy default).
+ * Self-loops and repeated arcs are removed (they cannot change a bit); the
+ * stored arc count is pp_graph_arcs().  Errors: PP_EINVAL, PP_ERANGE,
+ * PP_ENOMEM, PP_EDEVICE; *out is written only on success.
+ */
+int pp_csr_build(int64_t n, int64_t m, const int32_t *src, const int32_t *dst, uint32_t flags,
+                 const int64_t *node_offsets, int32_t num_graphs, void *stream, pp_graph *out);
+
+/* Stored arcs (after dedup, both directions for undirected input) and nodes. */
+int64_t pp_graph_arcs(pp_graph g);
+int64_t pp_graph_nodes(pp_graph g);
+int32_t pp_graph_count(pp_graph g);
+
+/*
+ * pp_seeds_init -- Algorithm 1's initialisation: Sig(u) = 0 for all u, then
+ * bit i of Sig(x_i) set for every seed, c[0] = s.
+ *   seeds       host array of num_graphs * s node ids: seeds[g*s + i] is
+ *               seed i of graph g and must lie in graph g's node range.
+ *               Repeated seeds are allowed (each owns its own bit).
+ *   s           1 <= s <= 512 seeds per graph (W = ceil(s/64) <= 8 words).
+ *   opt         NULL for defaults.
+ *   stream      hipStream_t for all of the run's device work (NULL: the run
+ *               creates its own non-blocking stream).
+ * Errors: PP_EINVAL, PP_ERANGE, PP_ENOMEM, PP_EDEVICE.
+ */
+int pp_seeds_init(pp_graph g, const int32_t *seeds, int32_t s, const pp_options *opt,
+                  void *stream, pp_run *out);
+
+/*
+ * pp_propagate_round -- one synchronous round (one pass of Algorithm 1's
+ * do-while body) for every graph of the batch not yet converged.
+ *   new_bits        host [num_graphs]: c_g[r] of the round just run (0 for a
+ *                   graph already converged).  May be NULL.
+ *   all_converged   host int: 1 once every graph has had a round with no new bit.
+ * Synchronises the stream.  After convergence further calls are no-ops that
+ * return PP_OK with zeros.  PP_ENOTCONV when the round log is full.
+ */
+int pp_propagate_round(pp_run r, int64_t *new_bits, int32_t *all_converged);
+
+/*
+ * pp_propagate_until_converged -- rounds until every graph converged or
+ * max_rounds rounds in total have run (max_rounds <= 0: the log capacity).
+ *   counts   host [num_graphs][cap_rounds]: counts[g*cap_rounds + r] = c_g[r]
+ *            for r <= D_g, zeros after.  May be NULL.
+ *   D        host [num_graphs]: D_g.  May be NULL.
+ * Returns PP_ENOTCONV (with the counts so far) if the cap stopped it.
+ */
+int pp_propagate_until_converged(pp_run r, int32_t max_rounds, int64_t *counts,
+                                 int32_t cap_rounds, int32_t *D);
+
+/*
+ * pp_estimate_metrics -- host only, pure: the distance metrics from
+ * c[0..len-1] of one graph with n nodes and s seeds, tau = tau_num/tau_den
+ * (the paper uses 0.9 = 9/10).  Trailing zero rounds are ignored.
+ * Errors: PP_EINVAL for len < 1, s < 1, n < 1, tau_den = 0 or
+ * tau_num > tau_den.
+ */
+int pp_estimate_metrics(const int64_t *counts, int32_t len, int64_t n, int32_t s,
+                        uint32_t tau_num, uint32_t tau_den, pp_metrics *out);
+
+/* Signatures of the current round into dst ([n][W] uint64 words; device
+ * memory when dst_on_device, else host; the caller owns dst). */
+int pp_get_signatures(pp_run r, uint64_t *dst, int32_t dst_on_device);
+
+/* Per-seed counts (needs opt.seed_counts): dst host [num_graphs][cap_rounds][s],
+ * dst[(g*cap_rounds + r)*s + i] = c_{g,i}[r]. */
+int pp_get_seed_counts(pp_run r, uint32_t *dst, int32_t cap_rounds);
+
+/* Rounds run so far (the next round's index) and the number of words W. */
+int32_t pp_run_round(pp_run r);
+int32_t pp_run_words(pp_run r);
+
+/* Per-round record of the last pp_propagate_* call: for each round r <= the
+ * current round, mode[r] (0 pull, 1 push) and arcs[r] (arcs the round
+ * touched).  Host arrays of cap entries; either may be NULL. */
+int pp_get_round_log(pp_run r, int32_t *mode, int64_t *arcs, int32_t cap);
+
+/* Copy of a run's whole state (signatures, frontier, logs) / restore from a
+ * copy of the same graph and s.  A restored run continues bit-identically. */
+int pp_run_snapshot(pp_run r, pp_run *copy);
+int pp_run_restore(pp_run r, pp_run from);
+
+void pp_run_free(pp_run r);
+void pp_graph_free(pp_graph g);
+const char *pp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PP_H */

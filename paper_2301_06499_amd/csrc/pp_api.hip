@@ -1,0 +1,772 @@
+// C interface of the propagation library: argument checks, graph
+// construction, run state and the round driver.  Every device step is a
+// kernel in pp_kernels.hip (or pp_csr.hip for the graph build).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "pp_internal.h"
+
+using pp::Chunk;
+using pp::Ctrl;
+using pp::GraphDev;
+using pp::RunDev;
+using pp::Tile;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                      \
+    do {                                                                                   \
+        hipError_t e_ = (expr);                                                            \
+        if (e_ != hipSuccess) return fail(PP_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+template <typename T> int dev_alloc(T **p, int64_t count) {
+    *p = nullptr;
+    if (count <= 0) count = 1;
+    hipError_t e = hipMalloc((void **)p, sizeof(T) * (size_t)count);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return fail(PP_ENOMEM, "hipMalloc of %lld bytes failed: %s", (long long)(sizeof(T) * count),
+                    hipGetErrorString(e));
+    }
+    return PP_OK;
+}
+
+template <typename T> void dev_free(T *&p) {
+    if (p) (void)hipFree((void *)p);
+    p = nullptr;
+}
+
+unsigned hw_threads() {
+    unsigned t = std::thread::hardware_concurrency();
+    return t == 0 ? 1 : (t > 32 ? 32 : t);
+}
+
+template <typename F> void parallel_for(int64_t n, F f) {
+    unsigned T = hw_threads();
+    if (n < 1 << 16 || T == 1) {
+        f((int64_t)0, n);
+        return;
+    }
+    std::vector<std::thread> th;
+    for (unsigned t = 0; t < T; ++t) {
+        int64_t a = n * t / T, b = n * (t + 1) / T;
+        th.emplace_back([=] { f(a, b); });
+    }
+    for (auto &x : th) x.join();
+}
+
+struct TileSet {
+    Tile *tiles = nullptr;
+    int32_t ntiles = 0;
+    int32_t *hub_nchunks = nullptr;
+    int32_t nhubs = 0;
+};
+
+}  // namespace
+
+struct pp_graph_s {
+    int64_t n = 0, m = 0;
+    int32_t G = 1;
+    uint32_t flags = 0;
+    hipStream_t stream = nullptr;
+    std::vector<int64_t> node_offsets;
+    std::vector<int64_t> rp_host;   // kept for tiling at each signature width
+    int64_t *rp = nullptr, *trp = nullptr;
+    int32_t *col = nullptr, *tcol = nullptr;
+    int32_t *node_graph = nullptr;
+    std::map<int, TileSet> tiles;   // by pull arc budget
+};
+
+struct pp_run_s {
+    pp_graph g = nullptr;
+    int32_t s = 0, W = 0, cap = 0, G = 1;
+    pp_options opt{};
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    RunDev dev{};
+    Ctrl host_ctrl{};
+    std::map<int, hipGraphExec_t> graphs;   // captured batches by round count
+    std::map<int, hipGraph_t> graph_defs;
+};
+
+extern "C" {
+
+const char *pp_last_error(void) { return g_err.c_str(); }
+
+void pp_options_default(pp_options *opt) {
+    if (!opt) return;
+    std::memset(opt, 0, sizeof(*opt));
+    opt->scheduler = PP_SCHED_HEURISTIC;
+    opt->use_graph = 1;
+    opt->push_div = 8;
+}
+
+int64_t pp_graph_arcs(pp_graph g) { return g ? g->m : -1; }
+int64_t pp_graph_nodes(pp_graph g) { return g ? g->n : -1; }
+int32_t pp_graph_count(pp_graph g) { return g ? g->G : -1; }
+
+}  // extern "C"
+
+// --------------------------------------------------------------------------
+// graph construction (host adjacency build, then one upload)
+// --------------------------------------------------------------------------
+
+namespace {
+
+// rows[u] = sorted, distinct heads v of arcs u -> v in the propagation
+// direction (u ORs in v's signature), self-loops removed.
+void build_rows(int64_t n, int64_t m, const int32_t *a, const int32_t *b, bool undirected,
+                std::vector<int64_t> &rp, std::vector<int32_t> &col) {
+    std::vector<int64_t> cnt((size_t)n + 1, 0);
+    for (int64_t k = 0; k < m; ++k) {
+        if (a[k] == b[k]) continue;
+        cnt[(size_t)a[k] + 1]++;
+        if (undirected) cnt[(size_t)b[k] + 1]++;
+    }
+    for (int64_t u = 0; u < n; ++u) cnt[(size_t)u + 1] += cnt[(size_t)u];
+    std::vector<int32_t> tmp((size_t)cnt[(size_t)n]);
+    std::vector<int64_t> fill(cnt.begin(), cnt.end() - 1);
+    for (int64_t k = 0; k < m; ++k) {
+        if (a[k] == b[k]) continue;
+        tmp[(size_t)fill[(size_t)a[k]]++] = b[k];
+        if (undirected) tmp[(size_t)fill[(size_t)b[k]]++] = a[k];
+    }
+    std::vector<int64_t> uniq((size_t)n, 0);
+    parallel_for(n, [&](int64_t lo, int64_t hi) {
+        for (int64_t u = lo; u < hi; ++u) {
+            int32_t *p = tmp.data() + cnt[(size_t)u];
+            int32_t *q = tmp.data() + cnt[(size_t)u + 1];
+            std::sort(p, q);
+            uniq[(size_t)u] = std::unique(p, q) - p;
+        }
+    });
+    rp.assign((size_t)n + 1, 0);
+    for (int64_t u = 0; u < n; ++u) rp[(size_t)u + 1] = rp[(size_t)u] + uniq[(size_t)u];
+    col.resize((size_t)rp[(size_t)n]);
+    parallel_for(n, [&](int64_t lo, int64_t hi) {
+        for (int64_t u = lo; u < hi; ++u)
+            std::memcpy(col.data() + rp[(size_t)u], tmp.data() + cnt[(size_t)u], sizeof(int32_t) * (size_t)uniq[(size_t)u]);
+    });
+}
+
+// Transpose of a CSR: trow[v] = sorted {u : v in row u}.
+void transpose_rows(int64_t n, const std::vector<int64_t> &rp, const std::vector<int32_t> &col,
+                    std::vector<int64_t> &trp, std::vector<int32_t> &tcol) {
+    trp.assign((size_t)n + 1, 0);
+    for (size_t k = 0; k < col.size(); ++k) trp[(size_t)col[k] + 1]++;
+    for (int64_t v = 0; v < n; ++v) trp[(size_t)v + 1] += trp[(size_t)v];
+    tcol.resize(col.size());
+    std::vector<int64_t> fill(trp.begin(), trp.end() - 1);
+    for (int64_t u = 0; u < n; ++u)
+        for (int64_t e = rp[(size_t)u]; e < rp[(size_t)u + 1]; ++e) tcol[(size_t)fill[(size_t)col[(size_t)e]]++] = (int32_t)u;
+}
+
+// Pull tiles: runs of consecutive nodes with at most `edges` arcs and
+// pp::TILE_NODES nodes; a node with more than `edges` arcs is split into
+// chunks that combine through the hub tables.  Runs without arcs are
+// dropped (their nodes can never gain a bit in a pull).  Hub chunks come
+// first so the longest-latency work starts early.
+void build_tiles(const std::vector<int64_t> &rp, const std::vector<int64_t> &noff, int G, int edges,
+                 std::vector<Tile> &tiles, std::vector<int32_t> &hub_nchunks) {
+    std::vector<Tile> hubs, runs;
+    for (int g = 0; g < G; ++g) {
+        int64_t u = noff[(size_t)g];
+        const int64_t end = noff[(size_t)g + 1];
+        while (u < end) {
+            const int64_t deg = rp[(size_t)u + 1] - rp[(size_t)u];
+            if (deg > edges) {
+                const int32_t h = (int32_t)hub_nchunks.size();
+                const int32_t nch = (int32_t)((deg + edges - 1) / edges);
+                hub_nchunks.push_back(nch);
+                for (int32_t j = 0; j < nch; ++j) {
+                    const int64_t e0 = rp[(size_t)u] + (int64_t)j * edges;
+                    const int64_t e1 = std::min(rp[(size_t)u + 1], e0 + edges);
+                    hubs.push_back(Tile{(int32_t)u, (int32_t)u + 1, e0, e1, h, g});
+                }
+                ++u;
+                continue;
+            }
+            const int64_t s = u;
+            while (u < end && u - s < pp::TILE_NODES) {
+                const int64_t d = rp[(size_t)u + 1] - rp[(size_t)u];
+                if (d > edges || rp[(size_t)u + 1] - rp[(size_t)s] > edges) break;
+                ++u;
+            }
+            if (rp[(size_t)u] > rp[(size_t)s]) runs.push_back(Tile{(int32_t)s, (int32_t)u, rp[(size_t)s], rp[(size_t)u], -1, g});
+        }
+    }
+    tiles = std::move(hubs);
+    tiles.insert(tiles.end(), runs.begin(), runs.end());
+}
+
+int pull_edges_for_words(int W) {
+    switch (W) {
+        case 1: return pp::PullShape<1>::EDGES;
+        case 2: return pp::PullShape<2>::EDGES;
+        case 4: return pp::PullShape<4>::EDGES;
+        default: return pp::PullShape<8>::EDGES;
+    }
+}
+
+int ensure_tiles(pp_graph g, int W, TileSet **out) {
+    const int edges = pull_edges_for_words(W);
+    auto it = g->tiles.find(edges);
+    if (it != g->tiles.end()) {
+        *out = &it->second;
+        return PP_OK;
+    }
+    std::vector<Tile> tiles;
+    std::vector<int32_t> hubs;
+    build_tiles(g->rp_host, g->node_offsets, g->G, edges, tiles, hubs);
+    TileSet ts;
+    int rc;
+    if ((rc = dev_alloc(&ts.tiles, (int64_t)tiles.size())) != PP_OK) return rc;
+    if ((rc = dev_alloc(&ts.hub_nchunks, (int64_t)hubs.size())) != PP_OK) {
+        dev_free(ts.tiles);
+        return rc;
+    }
+    ts.ntiles = (int32_t)tiles.size();
+    ts.nhubs = (int32_t)hubs.size();
+    hipError_t e = hipSuccess;
+    if (!tiles.empty()) e = hipMemcpy(ts.tiles, tiles.data(), sizeof(Tile) * tiles.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess && !hubs.empty())
+        e = hipMemcpy(ts.hub_nchunks, hubs.data(), sizeof(int32_t) * hubs.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        dev_free(ts.tiles);
+        dev_free(ts.hub_nchunks);
+        return fail(PP_EDEVICE, "tile upload: %s", hipGetErrorString(e));
+    }
+    g->tiles[edges] = ts;
+    *out = &g->tiles[edges];
+    return PP_OK;
+}
+
+void free_graph(pp_graph g) {
+    if (!g) return;
+    dev_free(g->rp);
+    dev_free(g->trp);
+    dev_free(g->col);
+    dev_free(g->tcol);
+    dev_free(g->node_graph);
+    for (auto &kv : g->tiles) {
+        dev_free(kv.second.tiles);
+        dev_free(kv.second.hub_nchunks);
+    }
+    delete g;
+}
+
+GraphDev graph_view(pp_graph g, const TileSet *ts) {
+    GraphDev d{};
+    d.n = g->n;
+    d.m = g->m;
+    d.rp = g->rp;
+    d.col = g->col;
+    d.trp = g->trp;
+    d.tcol = g->tcol;
+    d.tiles = ts ? ts->tiles : nullptr;
+    d.ntiles = ts ? ts->ntiles : 0;
+    d.nhubs = ts ? ts->nhubs : 0;
+    d.hub_nchunks = ts ? ts->hub_nchunks : nullptr;
+    d.node_graph = g->node_graph;
+    d.G = g->G;
+    return d;
+}
+
+}  // namespace
+
+extern "C" int pp_csr_build(int64_t n, int64_t m, const int32_t *src, const int32_t *dst, uint32_t flags,
+                            const int64_t *node_offsets, int32_t num_graphs, void *stream, pp_graph *out) {
+    if (!out) return fail(PP_EINVAL, "out is NULL");
+    if (n < 1 || n > INT32_MAX - 1) return fail(PP_EINVAL, "n = %lld outside [1, 2^31-2]", (long long)n);
+    if (m < 0) return fail(PP_EINVAL, "m < 0");
+    if (m > 0 && (!src || !dst)) return fail(PP_EINVAL, "src/dst NULL with m > 0");
+    if (flags & ~(uint32_t)(PP_UNDIRECTED | PP_INPUT_ON_DEVICE | PP_TRANSPOSE)) return fail(PP_EINVAL, "unknown flag bits");
+    const int G = (num_graphs <= 1 && !node_offsets) ? 1 : num_graphs;
+    if (G < 1) return fail(PP_EINVAL, "num_graphs < 1");
+    std::vector<int64_t> noff((size_t)G + 1);
+    if (node_offsets && G >= 1) {
+        for (int g = 0; g <= G; ++g) noff[(size_t)g] = node_offsets[g];
+        if (noff[0] != 0 || noff[(size_t)G] != n) return fail(PP_EINVAL, "node_offsets must start at 0 and end at n");
+        for (int g = 0; g < G; ++g)
+            if (noff[(size_t)g + 1] < noff[(size_t)g]) return fail(PP_EINVAL, "node_offsets not non-decreasing");
+    } else {
+        noff[0] = 0;
+        noff[1] = n;
+    }
+    const bool und = flags & PP_UNDIRECTED;
+    const bool tr = flags & PP_TRANSPOSE;
+    hipStream_t st = (hipStream_t)stream;
+
+    // input arcs on the host
+    std::vector<int32_t> hs, hd;
+    const int32_t *ps = src, *pd = dst;
+    if ((flags & PP_INPUT_ON_DEVICE) && m > 0) {
+        hs.resize((size_t)m);
+        hd.resize((size_t)m);
+        HIP_TRY(hipMemcpyAsync(hs.data(), src, sizeof(int32_t) * (size_t)m, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(hd.data(), dst, sizeof(int32_t) * (size_t)m, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        ps = hs.data();
+        pd = hd.data();
+    }
+    // validation
+    std::vector<int32_t> ng;
+    if (G > 1) {
+        ng.resize((size_t)n);
+        for (int g = 0; g < G; ++g)
+            for (int64_t u = noff[(size_t)g]; u < noff[(size_t)g + 1]; ++u) ng[(size_t)u] = g;
+    }
+    {
+        std::atomic<int64_t> bad{-1};
+        parallel_for(m, [&](int64_t lo, int64_t hi) {
+            for (int64_t k = lo; k < hi; ++k) {
+                const int32_t a = ps[k], b = pd[k];
+                if (a < 0 || a >= n || b < 0 || b >= n || (G > 1 && ng[(size_t)a] != ng[(size_t)b])) {
+                    bad.store(k);
+                    return;
+                }
+            }
+        });
+        if (bad.load() >= 0) {
+            const int64_t k = bad.load();
+            return fail(PP_ERANGE, "arc %lld (%d -> %d) outside [0, n) or across graphs", (long long)k, ps[k], pd[k]);
+        }
+    }
+    // propagation rows: u ORs in v for arc u -> v (or v -> u transposed)
+    std::vector<int64_t> rp, trp;
+    std::vector<int32_t> col, tcol;
+    try {
+        if (tr) build_rows(n, m, pd, ps, und, rp, col);
+        else build_rows(n, m, ps, pd, und, rp, col);
+        transpose_rows(n, rp, col, trp, tcol);
+    } catch (const std::bad_alloc &) {
+        return fail(PP_ENOMEM, "host memory for the adjacency build");
+    }
+    pp_graph g = new (std::nothrow) pp_graph_s();
+    if (!g) return fail(PP_ENOMEM, "graph handle");
+    g->n = n;
+    g->m = (int64_t)col.size();
+    g->G = G;
+    g->flags = flags;
+    g->stream = st;
+    g->node_offsets = noff;
+    int rc;
+    if ((rc = dev_alloc(&g->rp, n + 1)) || (rc = dev_alloc(&g->trp, n + 1)) || (rc = dev_alloc(&g->col, g->m)) ||
+        (rc = dev_alloc(&g->tcol, g->m)) || (G > 1 && (rc = dev_alloc(&g->node_graph, n)))) {
+        free_graph(g);
+        return rc;
+    }
+    hipError_t e = hipMemcpyAsync(g->rp, rp.data(), sizeof(int64_t) * (size_t)(n + 1), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(g->trp, trp.data(), sizeof(int64_t) * (size_t)(n + 1), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && g->m) e = hipMemcpyAsync(g->col, col.data(), sizeof(int32_t) * (size_t)g->m, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && g->m) e = hipMemcpyAsync(g->tcol, tcol.data(), sizeof(int32_t) * (size_t)g->m, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && G > 1) e = hipMemcpyAsync(g->node_graph, ng.data(), sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        free_graph(g);
+        return fail(PP_EDEVICE, "graph upload: %s", hipGetErrorString(e));
+    }
+    g->rp_host = std::move(rp);
+    *out = g;
+    return PP_OK;
+}
+
+extern "C" void pp_graph_free(pp_graph g) { free_graph(g); }
+
+// --------------------------------------------------------------------------
+// runs
+// --------------------------------------------------------------------------
+
+namespace {
+
+int words_for(int s) {
+    const int w = (s + 63) / 64;
+    int p = 1;
+    while (p < w) p <<= 1;
+    return p;
+}
+
+void free_run_dev(RunDev &d) {
+    dev_free(d.sig);
+    dev_free(d.acc);
+    dev_free(d.stamp);
+    for (int k = 0; k < 2; ++k) {
+        dev_free(d.f_ids[k]);
+        dev_free(d.f_delta[k]);
+        dev_free(d.chunks[k]);
+    }
+    dev_free(d.hub_acc);
+    dev_free(d.hub_done);
+    dev_free(d.counts);
+    dev_free(d.seed_counts);
+    dev_free(d.D);
+    dev_free(d.gconv);
+    dev_free(d.mode_log);
+    dev_free(d.arcs_log);
+    dev_free(d.ctrl);
+}
+
+void drop_graphs(pp_run r) {
+    for (auto &kv : r->graphs) (void)hipGraphExecDestroy(kv.second);
+    for (auto &kv : r->graph_defs) (void)hipGraphDestroy(kv.second);
+    r->graphs.clear();
+    r->graph_defs.clear();
+}
+
+void free_run(pp_run r) {
+    if (!r) return;
+    if (r->stream) (void)hipStreamSynchronize(r->stream);
+    drop_graphs(r);
+    free_run_dev(r->dev);
+    if (r->own_stream && r->stream) (void)hipStreamDestroy(r->stream);
+    delete r;
+}
+
+int64_t chunk_capacity(pp_graph g) { return g->n + g->m / pp::PUSH_CHUNK + 2; }
+
+// Allocates every device buffer of a run with the sizes fixed by (g, s, cap).
+int alloc_run_dev(pp_graph g, RunDev &d, int s, int W, int cap, bool seed_counts, int nhubs) {
+    const int64_t n = g->n;
+    const int G = g->G;
+    int rc;
+    d.s = s;
+    d.W = W;
+    d.cap = cap;
+    d.G = G;
+    if ((rc = dev_alloc(&d.sig, n * W)) || (rc = dev_alloc(&d.acc, n * W)) || (rc = dev_alloc(&d.stamp, n)) ||
+        (rc = dev_alloc(&d.f_ids[0], n)) || (rc = dev_alloc(&d.f_ids[1], n)) ||
+        (rc = dev_alloc(&d.f_delta[0], n * W)) || (rc = dev_alloc(&d.f_delta[1], n * W)) ||
+        (rc = dev_alloc(&d.chunks[0], chunk_capacity(g))) || (rc = dev_alloc(&d.chunks[1], chunk_capacity(g))) ||
+        (rc = dev_alloc(&d.hub_acc, (int64_t)nhubs * W)) || (rc = dev_alloc(&d.hub_done, nhubs)) ||
+        (rc = dev_alloc(&d.counts, (int64_t)cap * G)) || (rc = dev_alloc(&d.D, G)) || (rc = dev_alloc(&d.gconv, G)) ||
+        (rc = dev_alloc(&d.mode_log, cap)) || (rc = dev_alloc(&d.arcs_log, cap)) || (rc = dev_alloc(&d.ctrl, 1)))
+        return rc;
+    if (seed_counts && (rc = dev_alloc(&d.seed_counts, (int64_t)cap * G * s))) return rc;
+    if (!seed_counts) d.seed_counts = nullptr;
+    return PP_OK;
+}
+
+hipError_t clear_run_dev(pp_graph g, RunDev &d, int nhubs, hipStream_t st) {
+    const int64_t n = g->n;
+    hipError_t e;
+    if ((e = pp::launch_fill_u64(d.sig, 0, n * d.W, st))) return e;
+    if ((e = pp::launch_fill_u64(d.acc, 0, n * d.W, st))) return e;
+    if ((e = pp::launch_fill_i32(d.stamp, -1, n, st))) return e;
+    if ((e = pp::launch_fill_u64(d.hub_acc, 0, (int64_t)nhubs * d.W, st))) return e;
+    if ((e = pp::launch_fill_i32((int32_t *)d.hub_done, 0, nhubs, st))) return e;
+    if ((e = pp::launch_fill_u64((uint64_t *)d.counts, 0, (int64_t)d.cap * d.G, st))) return e;
+    if (d.seed_counts && (e = pp::launch_fill_i32((int32_t *)d.seed_counts, 0, (int64_t)d.cap * d.G * d.s, st))) return e;
+    if ((e = pp::launch_fill_i32(d.D, 0, d.G, st))) return e;
+    if ((e = pp::launch_fill_i32(d.gconv, 0, d.G, st))) return e;
+    if ((e = pp::launch_fill_i32(d.mode_log, -1, d.cap, st))) return e;
+    if ((e = pp::launch_fill_u64((uint64_t *)d.arcs_log, 0, d.cap, st))) return e;
+    return pp::launch_fill_i32((int32_t *)d.ctrl, 0, (int64_t)(sizeof(Ctrl) / 4), st);
+}
+
+TileSet *run_tiles(pp_run r) { return &r->g->tiles[pull_edges_for_words(r->W)]; }
+
+int sync_ctrl(pp_run r) {
+    HIP_TRY(hipMemcpyAsync(&r->host_ctrl, r->dev.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, r->stream));
+    HIP_TRY(hipStreamSynchronize(r->stream));
+    return PP_OK;
+}
+
+}  // namespace
+
+extern "C" int pp_seeds_init(pp_graph g, const int32_t *seeds, int32_t s, const pp_options *opt, void *stream,
+                             pp_run *out) {
+    if (!g || !out) return fail(PP_EINVAL, "graph or out is NULL");
+    if (s < 1 || s > 512) return fail(PP_EINVAL, "s = %d outside [1, 512]", s);
+    if (!seeds) return fail(PP_EINVAL, "seeds is NULL");
+    pp_options o;
+    pp_options_default(&o);
+    if (opt) o = *opt;
+    if (o.push_div <= 0) o.push_div = 8;
+    if (o.scheduler < PP_SCHED_HEURISTIC || o.scheduler > PP_SCHED_MLP) return fail(PP_EINVAL, "unknown scheduler %d", o.scheduler);
+    if (o.max_rounds < 0 || o.rounds_per_sync < 0) return fail(PP_EINVAL, "negative max_rounds / rounds_per_sync");
+    const int G = g->G;
+    for (int gi = 0; gi < G; ++gi)
+        for (int i = 0; i < s; ++i) {
+            const int64_t x = seeds[(int64_t)gi * s + i];
+            if (x < g->node_offsets[(size_t)gi] || x >= g->node_offsets[(size_t)gi + 1])
+                return fail(PP_ERANGE, "seed %d of graph %d (%lld) outside the graph's nodes", i, gi, (long long)x);
+        }
+    int64_t cap = o.max_rounds > 0 ? (int64_t)o.max_rounds + 1 : std::min<int64_t>(g->n + 1, 1 << 20);
+    if (cap < 2) cap = 2;
+    if (o.seed_counts && cap * G * (int64_t)s * 4 > (int64_t)1 << 31)
+        return fail(PP_EINVAL, "per-seed count log of %lld bytes: lower max_rounds", (long long)(cap * G * (int64_t)s * 4));
+    const int W = words_for(s);
+
+    pp_run r = new (std::nothrow) pp_run_s();
+    if (!r) return fail(PP_ENOMEM, "run handle");
+    r->g = g;
+    r->s = s;
+    r->W = W;
+    r->cap = (int32_t)cap;
+    r->G = G;
+    r->opt = o;
+    if (stream) {
+        r->stream = (hipStream_t)stream;
+    } else {
+        hipError_t e = hipStreamCreateWithFlags(&r->stream, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            delete r;
+            return fail(PP_EDEVICE, "stream: %s", hipGetErrorString(e));
+        }
+        r->own_stream = true;
+    }
+    TileSet *ts = nullptr;
+    int rc = ensure_tiles(g, W, &ts);
+    if (rc == PP_OK) rc = alloc_run_dev(g, r->dev, s, W, (int)cap, o.seed_counts != 0, ts->nhubs);
+    if (rc != PP_OK) {
+        free_run(r);
+        return rc;
+    }
+    r->dev.sched = o.scheduler == PP_SCHED_MLP ? PP_SCHED_HEURISTIC : o.scheduler;
+    r->dev.push_div = o.push_div;
+    r->dev.fuzz_seed = o.fuzz_seed;
+    r->dev.mlp = nullptr;
+
+    int32_t *dseeds = nullptr;
+    if ((rc = dev_alloc(&dseeds, (int64_t)G * s)) != PP_OK) {
+        free_run(r);
+        return rc;
+    }
+    GraphDev gv = graph_view(g, ts);
+    hipError_t e = hipMemcpyAsync(dseeds, seeds, sizeof(int32_t) * (size_t)G * s, hipMemcpyHostToDevice, r->stream);
+    if (e == hipSuccess) e = clear_run_dev(g, r->dev, ts->nhubs, r->stream);
+    if (e == hipSuccess) e = pp::launch_seed_init(gv, r->dev, dseeds, r->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(r->stream);
+    (void)hipFree(dseeds);
+    if (e != hipSuccess) {
+        free_run(r);
+        return fail(PP_EDEVICE, "seed initialisation: %s", hipGetErrorString(e));
+    }
+    if ((rc = sync_ctrl(r)) != PP_OK) {
+        free_run(r);
+        return rc;
+    }
+    *out = r;
+    return PP_OK;
+}
+
+extern "C" void pp_run_free(pp_run r) { free_run(r); }
+extern "C" int32_t pp_run_round(pp_run r) { return r ? r->host_ctrl.round : -1; }
+extern "C" int32_t pp_run_words(pp_run r) { return r ? r->W : -1; }
+
+extern "C" int pp_propagate_round(pp_run r, int64_t *new_bits, int32_t *all_converged) {
+    if (!r) return fail(PP_EINVAL, "run is NULL");
+    const int G = r->G;
+    if (r->host_ctrl.converged) {
+        if (new_bits) std::memset(new_bits, 0, sizeof(int64_t) * (size_t)G);
+        if (all_converged) *all_converged = 1;
+        return r->host_ctrl.overflow ? fail(PP_ENOTCONV, "round log full (max_rounds)") : PP_OK;
+    }
+    const int rr = r->host_ctrl.round;
+    GraphDev gv = graph_view(r->g, run_tiles(r));
+    HIP_TRY(pp::launch_round(gv, r->dev, r->stream));
+    if (new_bits)
+        HIP_TRY(hipMemcpyAsync(new_bits, r->dev.counts + (int64_t)rr * G, sizeof(int64_t) * (size_t)G,
+                               hipMemcpyDeviceToHost, r->stream));
+    int rc = sync_ctrl(r);
+    if (rc) return rc;
+    if (all_converged) *all_converged = r->host_ctrl.converged;
+    if (r->host_ctrl.overflow) return fail(PP_ENOTCONV, "round log full (max_rounds)");
+    return PP_OK;
+}
+
+namespace {
+
+int launch_batch(pp_run r, int k) {
+    GraphDev gv = graph_view(r->g, run_tiles(r));
+    if (!r->opt.use_graph) {
+        for (int i = 0; i < k; ++i) HIP_TRY(pp::launch_round(gv, r->dev, r->stream));
+        return PP_OK;
+    }
+    auto it = r->graphs.find(k);
+    if (it == r->graphs.end()) {
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        HIP_TRY(hipStreamBeginCapture(r->stream, hipStreamCaptureModeThreadLocal));
+        hipError_t le = hipSuccess;
+        for (int i = 0; i < k && le == hipSuccess; ++i) le = pp::launch_round(gv, r->dev, r->stream);
+        hipError_t ce = hipStreamEndCapture(r->stream, &graph);
+        if (le != hipSuccess) return fail(PP_EDEVICE, "round capture: %s", hipGetErrorString(le));
+        if (ce != hipSuccess) return fail(PP_EDEVICE, "end capture: %s", hipGetErrorString(ce));
+        HIP_TRY(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+        r->graph_defs[k] = graph;
+        r->graphs[k] = exec;
+        it = r->graphs.find(k);
+    }
+    HIP_TRY(hipGraphLaunch(it->second, r->stream));
+    return PP_OK;
+}
+
+}  // namespace
+
+extern "C" int pp_propagate_until_converged(pp_run r, int32_t max_rounds, int64_t *counts, int32_t cap_rounds,
+                                            int32_t *D) {
+    if (!r) return fail(PP_EINVAL, "run is NULL");
+    if (counts && cap_rounds < 1) return fail(PP_EINVAL, "cap_rounds < 1");
+    const int G = r->G;
+    const int limit = (max_rounds > 0 && max_rounds < r->cap - 1) ? max_rounds : r->cap - 1;
+    int K = r->opt.rounds_per_sync > 0 ? r->opt.rounds_per_sync : 2;
+    while (!r->host_ctrl.converged && r->host_ctrl.round <= limit) {
+        const int left = limit - r->host_ctrl.round + 1;
+        int k = std::min(K, left);
+        // replayed batches come in powers of two so few graphs are captured
+        if (r->opt.use_graph) {
+            int p = 1;
+            while (p * 2 <= k) p *= 2;
+            k = p;
+        }
+        int rc = launch_batch(r, k);
+        if (rc) return rc;
+        if ((rc = sync_ctrl(r))) return rc;
+        if (r->opt.rounds_per_sync <= 0) K = std::min(K * 2, 64);
+    }
+    // results
+    const int last = std::min(r->host_ctrl.round, r->cap - 1);
+    if (counts) {
+        std::vector<int64_t> buf((size_t)(last + 1) * G);
+        HIP_TRY(hipMemcpyAsync(buf.data(), r->dev.counts, sizeof(int64_t) * buf.size(), hipMemcpyDeviceToHost, r->stream));
+        HIP_TRY(hipStreamSynchronize(r->stream));
+        std::memset(counts, 0, sizeof(int64_t) * (size_t)G * cap_rounds);
+        for (int g = 0; g < G; ++g)
+            for (int k = 0; k <= last && k < cap_rounds; ++k) counts[(int64_t)g * cap_rounds + k] = buf[(size_t)k * G + g];
+    }
+    if (D) {
+        HIP_TRY(hipMemcpyAsync(D, r->dev.D, sizeof(int32_t) * (size_t)G, hipMemcpyDeviceToHost, r->stream));
+        HIP_TRY(hipStreamSynchronize(r->stream));
+    }
+    if (!r->host_ctrl.converged || r->host_ctrl.overflow) return fail(PP_ENOTCONV, "stopped after %d rounds without convergence", r->host_ctrl.round);
+    return PP_OK;
+}
+
+extern "C" int pp_get_signatures(pp_run r, uint64_t *dst, int32_t dst_on_device) {
+    if (!r || !dst) return fail(PP_EINVAL, "run or dst is NULL");
+    HIP_TRY(hipMemcpyAsync(dst, r->dev.sig, sizeof(uint64_t) * (size_t)r->g->n * r->W,
+                           dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, r->stream));
+    HIP_TRY(hipStreamSynchronize(r->stream));
+    return PP_OK;
+}
+
+extern "C" int pp_get_seed_counts(pp_run r, uint32_t *dst, int32_t cap_rounds) {
+    if (!r || !dst) return fail(PP_EINVAL, "run or dst is NULL");
+    if (!r->dev.seed_counts) return fail(PP_ESTATE, "run was created without seed_counts");
+    if (cap_rounds < 1) return fail(PP_EINVAL, "cap_rounds < 1");
+    const int G = r->G, s = r->s;
+    const int rows = std::min(cap_rounds, r->cap);
+    std::vector<uint32_t> buf((size_t)rows * G * s);
+    HIP_TRY(hipMemcpyAsync(buf.data(), r->dev.seed_counts, sizeof(uint32_t) * buf.size(), hipMemcpyDeviceToHost, r->stream));
+    HIP_TRY(hipStreamSynchronize(r->stream));
+    std::memset(dst, 0, sizeof(uint32_t) * (size_t)G * cap_rounds * s);
+    for (int g = 0; g < G; ++g)
+        for (int k = 0; k < rows; ++k)
+            std::memcpy(dst + ((int64_t)g * cap_rounds + k) * s, buf.data() + ((size_t)k * G + g) * s, sizeof(uint32_t) * s);
+    return PP_OK;
+}
+
+extern "C" int pp_get_round_log(pp_run r, int32_t *mode, int64_t *arcs, int32_t cap) {
+    if (!r) return fail(PP_EINVAL, "run is NULL");
+    const int rows = std::min(cap, r->cap);
+    if (rows < 1) return fail(PP_EINVAL, "cap < 1");
+    if (mode) HIP_TRY(hipMemcpyAsync(mode, r->dev.mode_log, sizeof(int32_t) * rows, hipMemcpyDeviceToHost, r->stream));
+    if (arcs) HIP_TRY(hipMemcpyAsync(arcs, r->dev.arcs_log, sizeof(int64_t) * rows, hipMemcpyDeviceToHost, r->stream));
+    HIP_TRY(hipStreamSynchronize(r->stream));
+    return PP_OK;
+}
+
+extern "C" int pp_run_snapshot(pp_run r, pp_run *copy) {
+    if (!r || !copy) return fail(PP_EINVAL, "run or copy is NULL");
+    pp_run c = new (std::nothrow) pp_run_s();
+    if (!c) return fail(PP_ENOMEM, "run handle");
+    c->g = r->g;
+    c->s = r->s;
+    c->W = r->W;
+    c->cap = r->cap;
+    c->G = r->G;
+    c->opt = r->opt;
+    if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+        delete c;
+        return fail(PP_EDEVICE, "snapshot stream");
+    }
+    c->own_stream = true;
+    TileSet *ts = run_tiles(r);
+    int rc = alloc_run_dev(r->g, c->dev, r->s, r->W, r->cap, r->dev.seed_counts != nullptr, ts->nhubs);
+    if (rc) {
+        free_run(c);
+        return rc;
+    }
+    c->dev.sched = r->dev.sched;
+    c->dev.push_div = r->dev.push_div;
+    c->dev.fuzz_seed = r->dev.fuzz_seed;
+    c->dev.mlp = r->dev.mlp;
+    rc = pp_run_restore(c, r);
+    if (rc) {
+        free_run(c);
+        return rc;
+    }
+    *copy = c;
+    return PP_OK;
+}
+
+extern "C" int pp_run_restore(pp_run r, pp_run from) {
+    if (!r || !from) return fail(PP_EINVAL, "run is NULL");
+    if (r->g != from->g || r->s != from->s || r->cap != from->cap ||
+        (r->dev.seed_counts == nullptr) != (from->dev.seed_counts == nullptr))
+        return fail(PP_EINVAL, "runs differ in graph, s, max_rounds or seed_counts");
+    if (r == from) return PP_OK;
+    if (from->stream != r->stream) HIP_TRY(hipStreamSynchronize(from->stream));
+    const int64_t n = r->g->n, W = r->W, G = r->G, cap = r->cap;
+    TileSet *ts = run_tiles(r);
+    hipStream_t st = r->stream;
+    auto cp = [&](void *d, const void *s, size_t bytes) { return hipMemcpyAsync(d, s, bytes, hipMemcpyDeviceToDevice, st); };
+    const RunDev &a = from->dev;
+    RunDev &b = r->dev;
+    hipError_t e = cp(b.sig, a.sig, 8 * n * W);
+    if (!e) e = cp(b.acc, a.acc, 8 * n * W);
+    if (!e) e = cp(b.stamp, a.stamp, 4 * n);
+    for (int k = 0; k < 2 && !e; ++k) {
+        e = cp(b.f_ids[k], a.f_ids[k], 4 * n);
+        if (!e) e = cp(b.f_delta[k], a.f_delta[k], 8 * n * W);
+        if (!e) e = cp(b.chunks[k], a.chunks[k], sizeof(Chunk) * chunk_capacity(r->g));
+    }
+    if (!e && ts->nhubs) e = cp(b.hub_acc, a.hub_acc, 8 * (size_t)ts->nhubs * W);
+    if (!e && ts->nhubs) e = cp(b.hub_done, a.hub_done, 4 * (size_t)ts->nhubs);
+    if (!e) e = cp(b.counts, a.counts, 8 * cap * G);
+    if (!e && b.seed_counts) e = cp(b.seed_counts, a.seed_counts, 4 * cap * G * r->s);
+    if (!e) e = cp(b.D, a.D, 4 * G);
+    if (!e) e = cp(b.gconv, a.gconv, 4 * G);
+    if (!e) e = cp(b.mode_log, a.mode_log, 4 * cap);
+    if (!e) e = cp(b.arcs_log, a.arcs_log, 8 * cap);
+    if (!e) e = cp(b.ctrl, a.ctrl, sizeof(Ctrl));
+    if (!e) e = hipStreamSynchronize(st);
+    if (e) return fail(PP_EDEVICE, "restore: %s", hipGetErrorString(e));
+    r->host_ctrl = from->host_ctrl;
+    return PP_OK;
+}

@@ -1,0 +1,304 @@
+"""ctypes binding of libpp.so with the C interface's entry-point names.
+
+Argument marshalling only: every step of the propagation runs in the HIP
+library.  Loading fails loudly if the library has not been built; there is
+no fallback.  Host arrays are numpy; device arrays may be torch tensors
+(their data pointers are passed through) and streams are torch streams or
+raw hipStream_t integers.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libpp.so")
+
+PP_OK, PP_EINVAL, PP_ERANGE, PP_ENOMEM, PP_EDEVICE, PP_ENOTCONV, PP_ESTATE = 0, -1, -2, -3, -4, -5, -6
+PP_UNDIRECTED, PP_INPUT_ON_DEVICE, PP_TRANSPOSE = 1, 2, 4
+PP_SCHED_HEURISTIC, PP_SCHED_PULL, PP_SCHED_PUSH, PP_SCHED_FUZZ, PP_SCHED_MLP = 0, 1, 2, 3, 4
+_NAMES = {0: "PP_OK", -1: "PP_EINVAL", -2: "PP_ERANGE", -3: "PP_ENOMEM", -4: "PP_EDEVICE",
+          -5: "PP_ENOTCONV", -6: "PP_ESTATE"}
+
+
+class PPError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("scheduler", ctypes.c_int32), ("seed_counts", ctypes.c_int32), ("max_rounds", ctypes.c_int32),
+                ("rounds_per_sync", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("push_div", ctypes.c_int32),
+                ("fuzz_seed", ctypes.c_uint64)]
+
+
+class Metrics(ctypes.Structure):
+    _fields_ = [("diameter", ctypes.c_int32), ("rounds_executed", ctypes.c_int32), ("R_final", ctypes.c_int64),
+                ("eff_diam", ctypes.c_double), ("eff_diam_interp", ctypes.c_double), ("avg_dist", ctypes.c_double),
+                ("avg_dist_paper", ctypes.c_double), ("reachable_pairs", ctypes.c_double),
+                ("alpha", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+EXPORTS = ["pp_options_default", "pp_csr_build", "pp_graph_arcs", "pp_graph_nodes", "pp_graph_count",
+           "pp_seeds_init", "pp_propagate_round", "pp_propagate_until_converged", "pp_estimate_metrics",
+           "pp_get_signatures", "pp_get_seed_counts", "pp_run_round", "pp_run_words", "pp_get_round_log",
+           "pp_run_snapshot", "pp_run_restore", "pp_run_free", "pp_graph_free", "pp_last_error"]
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if libpp.so is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2301_06499_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    P, I32, I64, U32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
+    sig = {
+        "pp_options_default": (None, [P]),
+        "pp_csr_build": (ctypes.c_int, [I64, I64, P, P, U32, P, I32, P, P]),
+        "pp_graph_arcs": (I64, [P]), "pp_graph_nodes": (I64, [P]), "pp_graph_count": (I32, [P]),
+        "pp_seeds_init": (ctypes.c_int, [P, P, I32, P, P, P]),
+        "pp_propagate_round": (ctypes.c_int, [P, P, P]),
+        "pp_propagate_until_converged": (ctypes.c_int, [P, I32, P, I32, P]),
+        "pp_estimate_metrics": (ctypes.c_int, [P, I32, I64, I32, U32, U32, P]),
+        "pp_get_signatures": (ctypes.c_int, [P, P, I32]),
+        "pp_get_seed_counts": (ctypes.c_int, [P, P, I32]),
+        "pp_run_round": (I32, [P]), "pp_run_words": (I32, [P]),
+        "pp_get_round_log": (ctypes.c_int, [P, P, P, I32]),
+        "pp_run_snapshot": (ctypes.c_int, [P, P]), "pp_run_restore": (ctypes.c_int, [P, P]),
+        "pp_run_free": (None, [P]), "pp_graph_free": (None, [P]),
+        "pp_last_error": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(rc: int):
+    if rc != PP_OK:
+        raise PPError(rc, lib().pp_last_error().decode())
+
+
+def _np_ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(int(stream.cuda_stream))
+
+
+def _is_device(a) -> bool:
+    return hasattr(a, "is_cuda") and a.is_cuda
+
+
+def options(scheduler=PP_SCHED_HEURISTIC, seed_counts=False, max_rounds=0, rounds_per_sync=0,
+            use_graph=True, push_div=0, fuzz_seed=0) -> Options:
+    o = Options()
+    lib().pp_options_default(ctypes.byref(o))
+    o.scheduler = scheduler
+    o.seed_counts = int(bool(seed_counts))
+    o.max_rounds = int(max_rounds)
+    o.rounds_per_sync = int(rounds_per_sync)
+    o.use_graph = int(bool(use_graph))
+    if push_div:
+        o.push_div = int(push_div)
+    o.fuzz_seed = int(fuzz_seed)
+    return o
+
+
+class Graph:
+    """Owns a pp_graph handle (device CSR, predecessor lists, tiling)."""
+
+    def __init__(self, handle):
+        self._h = handle
+
+    @property
+    def handle(self):
+        return self._h
+
+    @property
+    def arcs(self) -> int:
+        return int(lib().pp_graph_arcs(self._h))
+
+    @property
+    def nodes(self) -> int:
+        return int(lib().pp_graph_nodes(self._h))
+
+    @property
+    def count(self) -> int:
+        return int(lib().pp_graph_count(self._h))
+
+    def free(self):
+        if self._h:
+            lib().pp_graph_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def pp_csr_build(n, src, dst, undirected=False, transpose=False, node_offsets=None, stream=None) -> Graph:
+    """Build the device graph from m arcs src[k] -> dst[k] (numpy int32 or device tensors)."""
+    flags = (PP_UNDIRECTED if undirected else 0) | (PP_TRANSPOSE if transpose else 0)
+    keep = []
+    if _is_device(src):
+        flags |= PP_INPUT_ON_DEVICE
+        m = int(src.numel())
+        ps, pd = ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr())
+    else:
+        s = np.ascontiguousarray(src, dtype=np.int32)
+        d = np.ascontiguousarray(dst, dtype=np.int32)
+        keep += [s, d]
+        m = int(s.shape[0])
+        ps, pd = _np_ptr(s), _np_ptr(d)
+    if node_offsets is not None:
+        off = np.ascontiguousarray(node_offsets, dtype=np.int64)
+        keep.append(off)
+        po, G = _np_ptr(off), int(off.shape[0] - 1)
+    else:
+        po, G = None, 1
+    h = ctypes.c_void_p()
+    _check(lib().pp_csr_build(int(n), m, ps, pd, flags, po, G, _stream_ptr(stream), ctypes.byref(h)))
+    return Graph(h)
+
+
+class Run:
+    """Owns a pp_run handle (signatures, frontier, per-round logs)."""
+
+    def __init__(self, handle, graph: Graph, s: int, opts: Options):
+        self._h = handle
+        self.graph = graph
+        self.s = s
+        self.opts = opts
+
+    @property
+    def handle(self):
+        return self._h
+
+    @property
+    def round(self) -> int:
+        return int(lib().pp_run_round(self._h))
+
+    @property
+    def words(self) -> int:
+        return int(lib().pp_run_words(self._h))
+
+    def free(self):
+        if self._h:
+            lib().pp_run_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def pp_seeds_init(graph: Graph, seeds, s=None, opts: Options | None = None, stream=None) -> Run:
+    seeds = np.ascontiguousarray(seeds, dtype=np.int32)
+    G = graph.count
+    if s is None:
+        s = int(seeds.size // G)
+    h = ctypes.c_void_p()
+    o = opts if opts is not None else options()
+    _check(lib().pp_seeds_init(graph.handle, _np_ptr(seeds.reshape(-1)), int(s), ctypes.byref(o),
+                               _stream_ptr(stream), ctypes.byref(h)))
+    return Run(h, graph, int(s), o)
+
+
+def pp_propagate_round(run: Run):
+    """One round; returns (new bits per graph as int64 array, all_converged)."""
+    G = run.graph.count
+    nb = np.zeros(G, dtype=np.int64)
+    conv = ctypes.c_int32(0)
+    _check(lib().pp_propagate_round(run.handle, _np_ptr(nb), ctypes.byref(conv)))
+    return nb, bool(conv.value)
+
+
+def pp_propagate_until_converged(run: Run, max_rounds: int = 0, cap_rounds: int | None = None,
+                                 raise_on_cap: bool = True):
+    """Rounds to convergence; returns (counts [G][D_max+1] int64, D [G] int32)."""
+    G = run.graph.count
+    D = np.zeros(G, dtype=np.int32)
+    rc = lib().pp_propagate_until_converged(run.handle, int(max_rounds), None, 0, _np_ptr(D))
+    if rc not in (PP_OK, PP_ENOTCONV) or (rc == PP_ENOTCONV and raise_on_cap):
+        _check(rc)
+    # the run has stopped: a second call only copies the logs out
+    cap = int(cap_rounds) if cap_rounds else max(int(D.max()), run.round) + 1
+    counts = np.zeros((G, cap), dtype=np.int64)
+    rc2 = lib().pp_propagate_until_converged(run.handle, int(max_rounds), _np_ptr(counts), cap, _np_ptr(D))
+    if rc2 not in (PP_OK, PP_ENOTCONV):
+        _check(rc2)
+    return counts[:, :int(D.max()) + 1].copy(), D
+
+
+def pp_estimate_metrics(counts, n: int, s: int, tau_num: int = 9, tau_den: int = 10) -> dict:
+    c = np.ascontiguousarray(counts, dtype=np.int64)
+    out = Metrics()
+    _check(lib().pp_estimate_metrics(_np_ptr(c), int(c.shape[0]), int(n), int(s), int(tau_num), int(tau_den),
+                                     ctypes.byref(out)))
+    return out.as_dict()
+
+
+def pp_get_signatures(run: Run, out=None):
+    """Signatures [n][W] uint64: into a device tensor `out` if given, else a new numpy array."""
+    n, W = run.graph.nodes, run.words
+    if out is not None and _is_device(out):
+        _check(lib().pp_get_signatures(run.handle, ctypes.c_void_p(out.data_ptr()), 1))
+        return out
+    a = np.zeros((n, W), dtype=np.uint64)
+    _check(lib().pp_get_signatures(run.handle, _np_ptr(a), 0))
+    return a
+
+
+def pp_get_seed_counts(run: Run, cap_rounds: int):
+    G = run.graph.count
+    a = np.zeros((G, cap_rounds, run.s), dtype=np.uint32)
+    _check(lib().pp_get_seed_counts(run.handle, _np_ptr(a), int(cap_rounds)))
+    return a
+
+
+def pp_get_round_log(run: Run, cap: int):
+    mode = np.zeros(cap, dtype=np.int32)
+    arcs = np.zeros(cap, dtype=np.int64)
+    _check(lib().pp_get_round_log(run.handle, _np_ptr(mode), _np_ptr(arcs), int(cap)))
+    return mode, arcs
+
+
+def pp_run_snapshot(run: Run) -> Run:
+    h = ctypes.c_void_p()
+    _check(lib().pp_run_snapshot(run.handle, ctypes.byref(h)))
+    return Run(h, run.graph, run.s, run.opts)
+
+
+def pp_run_restore(run: Run, src: Run):
+    _check(lib().pp_run_restore(run.handle, src.handle))
+
+
+def propagate(n, src, dst, seeds, undirected=False, transpose=False, opts=None, stream=None):
+    """Convenience: build, initialise, run to convergence; returns (counts, D, run)."""
+    g = pp_csr_build(n, src, dst, undirected=undirected, transpose=transpose, stream=stream)
+    r = pp_seeds_init(g, seeds, opts=opts, stream=stream)
+    counts, D = pp_propagate_until_converged(r)
+    return counts[0], int(D[0]), r

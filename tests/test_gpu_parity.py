@@ -1,0 +1,242 @@
+"""GPU parity: the HIP path against the CPU oracle, element by element.
+
+Integer work, so the bar is bit-exact: per-round counts, per-seed counts,
+signatures (final and at sampled rounds), D, and the metrics (same exact
+integer formulas on both sides).  Every direction policy is checked, since
+the push/pull choice may never change an output bit.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2301_06499_amd import inputs as gen
+from paper_2301_06499_amd import pp
+
+pytestmark = pytest.mark.gpu
+
+SCHEDS = [pp.PP_SCHED_PULL, pp.PP_SCHED_PUSH, pp.PP_SCHED_HEURISTIC, pp.PP_SCHED_FUZZ]
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def pad_words(sig, W):
+    """Oracle signatures [n][ceil(s/64)] padded to the library's W words."""
+    if sig.shape[1] == W:
+        return sig
+    out = np.zeros((sig.shape[0], W), dtype=np.uint64)
+    out[:, :sig.shape[1]] = sig
+    return out
+
+
+def check_run(n, src, dst, seeds, undirected, transpose=False, sched=pp.PP_SCHED_HEURISTIC,
+              fuzz_seed=0, use_graph=True, want=None, max_rounds=0):
+    s = len(seeds)
+    if want is None:
+        want = oracle.propagate(n, src, dst, seeds, undirected, transpose=transpose,
+                                seed_counts=True, final_sig=True)
+    g = pp.pp_csr_build(n, src, dst, undirected=undirected, transpose=transpose)
+    cap = max_rounds or want["D"] + 4
+    opts = pp.options(scheduler=sched, seed_counts=True, max_rounds=cap, fuzz_seed=fuzz_seed,
+                      use_graph=use_graph)
+    r = pp.pp_seeds_init(g, seeds, opts=opts)
+    counts, D = pp.pp_propagate_until_converged(r)
+    assert int(D[0]) == want["D"]
+    assert list(counts[0]) == list(want["counts"])
+    sig = pp.pp_get_signatures(r)
+    assert np.array_equal(sig, pad_words(want["final_sig"], r.words))
+    sc = pp.pp_get_seed_counts(r, want["D"] + 1)[0]
+    assert np.array_equal(sc, want["seed_counts"])
+    return r, g, counts[0]
+
+
+# ------------------------------------------------------------ closed forms
+
+CLOSED = [gen.path_graph(50), gen.cycle_graph(31), gen.cycle_graph(32), gen.star_graph(3000),
+          gen.complete_graph(40), gen.grid_graph(13, 9), gen.path_graph(30, directed=True),
+          gen.cycle_graph(17, directed=True), gen.path_graph(1), gen.path_graph(2)]
+
+
+@pytest.mark.parametrize("gi", range(len(CLOSED)))
+@pytest.mark.parametrize("sched", SCHEDS)
+def test_closed_form_graphs(gi, sched):
+    g = CLOSED[gi]
+    s = min(g.n, 512)
+    seeds = gen.sample_seeds(g.n, s, 3 + gi)
+    say("closed", g.name, "s", s, "sched", sched)
+    check_run(g.n, g.src, g.dst, seeds, g.undirected, sched=sched, fuzz_seed=gi)
+
+
+@pytest.mark.parametrize("sched", SCHEDS)
+def test_transposed_direction(sched):
+    g = gen.path_graph(40, directed=True)
+    seeds = np.array([0, 5, 39, 20], np.int32)
+    say("transpose", sched)
+    r, _, counts = check_run(g.n, g.src, g.dst, seeds, False, transpose=True, sched=sched)
+    # seed x reaches x+1..n-1 along reversed arcs: c_i[r] = 1 for r <= n-1-x
+    assert counts[1] == 3
+
+
+# ------------------------------------------------------------ random graphs
+
+@pytest.mark.parametrize("trial", range(24))
+def test_random_graphs_word_boundaries(trial):
+    rng = np.random.default_rng(500 + trial)
+    s = [1, 63, 64, 65, 127, 129, 200, 256, 300, 448, 511, 512][trial % 12]
+    n = int(rng.integers(max(2, s // 4), 3000))
+    m = int(rng.integers(0, 8 * n))
+    src = rng.integers(0, n, m).astype(np.int32)
+    dst = rng.integers(0, n, m).astype(np.int32)
+    und = bool(trial % 3 == 0)
+    tr = bool(trial % 4 == 1)
+    seeds = rng.integers(0, n, s).astype(np.int32)          # repeats allowed
+    sched = SCHEDS[trial % 4]
+    say("random", trial, "n", n, "m", m, "s", s, "und", und, "tr", tr, "sched", sched)
+    check_run(n, src, dst, seeds, und, transpose=tr, sched=sched, fuzz_seed=trial)
+
+
+@pytest.mark.parametrize("sched", SCHEDS)
+def test_rmat_with_hubs(sched):
+    """R-MAT scale 14: nodes with more arcs than a pull tile holds (hub chunks)."""
+    g = gen.rmat(14, 16, 77)
+    seeds = gen.sample_seeds(g.n, 256, 8)
+    say("rmat14", sched)
+    check_run(g.n, g.src, g.dst, seeds, False, sched=sched, fuzz_seed=5)
+
+
+def test_empty_and_isolated():
+    say("empty")
+    check_run(10, np.zeros(0, np.int32), np.zeros(0, np.int32), np.array([3, 3, 9], np.int32), False)
+    check_run(5, np.array([0, 1, 2], np.int32), np.array([0, 1, 2], np.int32), np.array([4], np.int32), True)
+
+
+# ------------------------------------------------------------ round by round
+
+@pytest.mark.parametrize("sched", [pp.PP_SCHED_PULL, pp.PP_SCHED_PUSH, pp.PP_SCHED_FUZZ])
+def test_er_workload_round_by_round(sched):
+    """The ER workload, signatures after every round, and the metrics."""
+    g, seeds = gen.workload_er(1)
+    want = oracle.propagate(g.n, g.src, g.dst, seeds, True, sig_rounds=list(range(0, 16)),
+                            seed_counts=True, final_sig=True)
+    say("er rounds", sched, "D", want["D"])
+    G = pp.pp_csr_build(g.n, g.src, g.dst, undirected=True)
+    r = pp.pp_seeds_init(G, seeds, opts=pp.options(scheduler=sched, seed_counts=True, max_rounds=64,
+                                                    fuzz_seed=9))
+    assert np.array_equal(pp.pp_get_signatures(r), want["sigs"][0])
+    got = [len(seeds)]
+    for k in range(1, want["D"] + 2):
+        nb, conv = pp.pp_propagate_round(r)
+        got.append(int(nb[0]))
+        assert np.array_equal(pp.pp_get_signatures(r), want["sigs"][min(k, 15)]), k
+        assert conv == (k == want["D"] + 1)
+    assert got[:-1] == list(want["counts"]) and got[-1] == 0
+    counts, D = pp.pp_propagate_until_converged(r)
+    m_gpu = pp.pp_estimate_metrics(counts[0], g.n, len(seeds))
+    m_cpu = oracle.metrics(want["counts"], g.n, len(seeds))
+    for k, v in m_cpu.items():
+        assert m_gpu[k] == v
+
+
+def test_snapshot_restore_and_graph_replay():
+    g, seeds = gen.workload_er(2)
+    want = oracle.propagate(g.n, g.src, g.dst, seeds, True, final_sig=True)
+    G = pp.pp_csr_build(g.n, g.src, g.dst, undirected=True)
+    r = pp.pp_seeds_init(G, seeds, opts=pp.options(scheduler=pp.PP_SCHED_FUZZ, fuzz_seed=3, max_rounds=64))
+    pp.pp_propagate_round(r)
+    pp.pp_propagate_round(r)
+    snap = pp.pp_run_snapshot(r)
+    c1, D1 = pp.pp_propagate_until_converged(r)
+    sig1 = pp.pp_get_signatures(r)
+    pp.pp_run_restore(r, snap)
+    assert r.round == 3
+    c2, D2 = pp.pp_propagate_until_converged(r)
+    assert np.array_equal(c1, c2) and np.array_equal(sig1, pp.pp_get_signatures(r))
+    assert list(c1[0]) == list(want["counts"])
+    # the same run replayed without graph capture, one round per sync
+    r2 = pp.pp_seeds_init(G, seeds, opts=pp.options(scheduler=pp.PP_SCHED_FUZZ, fuzz_seed=3, max_rounds=64,
+                                                     use_graph=False, rounds_per_sync=1))
+    c3, _ = pp.pp_propagate_until_converged(r2)
+    assert np.array_equal(c1, c3)
+    say("snapshot ok")
+
+
+def test_round_cap_reports_not_converged():
+    g = gen.path_graph(200)
+    seeds = np.array([0], np.int32)
+    G = pp.pp_csr_build(g.n, g.src, g.dst, undirected=True)
+    r = pp.pp_seeds_init(G, seeds, opts=pp.options(max_rounds=50))
+    with pytest.raises(pp.PPError) as e:
+        pp.pp_propagate_until_converged(r)
+    assert e.value.code == pp.PP_ENOTCONV
+    counts, D = pp.pp_propagate_until_converged(r, raise_on_cap=False)
+    assert list(counts[0][:50]) == [1] * 50
+
+
+# ------------------------------------------------------------ batches
+
+def test_batched_union_matches_solo_runs():
+    graphs = [gen.grid_graph(20, 15), gen.path_graph(300), gen.rmat(10, 8, 4), gen.star_graph(2500),
+              gen.cycle_graph(7, directed=True), gen.path_graph(1)]
+    s = 64
+    offs = [0]
+    srcs, dsts, seeds = [], [], []
+    wants = []
+    for k, g in enumerate(graphs):
+        sd = gen.sample_seeds(g.n, min(s, g.n), 20 + k)
+        if len(sd) < s:
+            sd = np.resize(sd, s)
+        wants.append(oracle.propagate(g.n, g.src, g.dst, sd, g.undirected, seed_counts=True))
+        src, dst = g.src.astype(np.int64), g.dst.astype(np.int64)
+        if g.undirected:
+            src, dst = np.concatenate([src, dst]), np.concatenate([dst, src])
+        srcs.append(src + offs[-1])
+        dsts.append(dst + offs[-1])
+        seeds.append(sd + offs[-1])
+        offs.append(offs[-1] + g.n)
+    n = offs[-1]
+    for sched in SCHEDS:
+        say("batch", sched)
+        G = pp.pp_csr_build(n, np.concatenate(srcs).astype(np.int32), np.concatenate(dsts).astype(np.int32),
+                            node_offsets=offs)
+        r = pp.pp_seeds_init(G, np.concatenate(seeds), s=s,
+                             opts=pp.options(scheduler=sched, seed_counts=True, max_rounds=400, fuzz_seed=1))
+        counts, D = pp.pp_propagate_until_converged(r)
+        sc = pp.pp_get_seed_counts(r, 400)
+        for k, w in enumerate(wants):
+            assert int(D[k]) == w["D"], k
+            assert list(counts[k][:w["D"] + 1]) == list(w["counts"]), k
+            assert not counts[k][w["D"] + 1:].any()
+            assert np.array_equal(sc[k][:w["D"] + 1], w["seed_counts"]), k
+
+
+# ------------------------------------------------------------ full size
+
+def test_rmat20_full_size_sampled_seeds():
+    """R-MAT scale 20, s = 256, in the benchmark's launch configuration.
+
+    Per-round totals come from the GPU only; the oracle checks 24 sampled
+    seeds one by one (per-seed counts and the seeds' signature bit columns)
+    and the totals are checked against the per-seed counts' sums.
+    """
+    g, seeds = gen.workload_rmat(20, 16, 256, 1)
+    say("rmat20 build")
+    G = pp.pp_csr_build(g.n, g.src, g.dst)
+    r = pp.pp_seeds_init(G, seeds, opts=pp.options(seed_counts=True, max_rounds=256))
+    counts, D = pp.pp_propagate_until_converged(r)
+    Dg = int(D[0])
+    sc = pp.pp_get_seed_counts(r, Dg + 1)[0]
+    sig = pp.pp_get_signatures(r)
+    assert np.array_equal(sc.sum(axis=1).astype(np.int64), counts[0])
+    pick = np.random.default_rng(0).choice(256, 24, replace=False)
+    want = oracle.propagate(g.n, g.src, g.dst, seeds[pick], False, seed_counts=True, dist=True)
+    for j, i in enumerate(pick):
+        col = want["seed_counts"][:, j]
+        L = max(len(col), Dg + 1)
+        assert np.array_equal(np.pad(sc[:, i], (0, L - Dg - 1)), np.pad(col, (0, L - len(col)))), i
+        bits = (sig[:, i >> 6] >> np.uint64(i & 63)) & np.uint64(1)
+        assert np.array_equal(bits.astype(bool), want["dist"][j] >= 0), i
+    say("rmat20 D", Dg, "counts", list(counts[0]))
