@@ -1,0 +1,178 @@
+#!/usr/bin/env python
+"""Throughput of the PROPAGATE-P hot path on one MI355X.
+
+One step = Algorithm 1 end to end on one batch of synthetic input: the seed
+initialisation (pp_seeds_reset) and the synchronous rounds until the first
+round with no new bit (pp_propagate_until_converged), with the per-round
+counts copied to the host.  The graph is built once, before timing (the
+paper does not time graph loading either); the seed list is already in HBM.
+
+Metric: edge-words OR'd per second, full-scan accounting: every executed
+round (D + 1 of them) is credited with m arcs x s/64 words, as Algorithm 1
+scans every arc every round.  The edge-words the kernels actually touched
+(push rounds touch only the frontier's arcs) are reported beside it.
+
+Prints one JSON line.  `roofline` covers the dense pull kernel (HIP events
+around each launch, on the run's stream, over the timed steps);
+`cpu_baseline` times the CPU oracle (one BFS per seed, all host cores) on
+the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0       # MI355X HBM3E, published
+METRIC = "edge-words OR'd/sec (edges x s/64 per round) and achieved HBM GB/s vs peak, bit-exact"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def workload(name: str):
+    from paper_2301_06499_amd import inputs
+    if name == "rmat20":
+        g, seeds = inputs.workload_rmat(20, 16, 256, 1)
+        return g, seeds, {"workload": "rmat_scale20_ef16_s256", "generator": "R-MAT a,b,c,d=.57,.19,.19,.05, "
+                          "self-loops and duplicates removed, all 2^20 nodes kept", "seeds": 256}
+    if name == "er":
+        g, seeds = inputs.workload_er(1)
+        return g, seeds, {"workload": "er_n10000_m50000_lcc_s64", "seeds": 64}
+    raise SystemExit(f"unknown workload {name}")
+
+
+def cpu_baseline(g, seeds, nominal_edge_words: float, budget_s: float):
+    """The oracle (not tuned) on the host cores; a seed sample sized to the budget."""
+    import oracle
+    nth = oracle.default_threads()
+    s = len(seeds)
+    k = min(s, max(nth, 8))
+    t0 = time.perf_counter()
+    oracle.propagate(g.n, g.src, g.dst, seeds[:k], g.undirected, nthreads=nth)
+    t1 = time.perf_counter() - t0
+    # grow the sample toward the budget, in whole thread-rounds of seeds
+    if t1 < budget_s / 4 and k < s:
+        k2 = min(s, int(k * max(1.0, (budget_s / 2) / max(t1, 1e-3))))
+        k2 = max(k, (k2 // nth) * nth) if k2 >= nth else k2
+        t0 = time.perf_counter()
+        oracle.propagate(g.n, g.src, g.dst, seeds[:k2], g.undirected, nthreads=nth)
+        t1 = time.perf_counter() - t0
+        k = k2
+    t_full = t1 * s / k
+    return {"value": nominal_edge_words / t_full, "unit": "edge-words/s", "cores": min(nth, k),
+            "kind": "oracle",
+            "sample": f"per-seed BFS over {k} of {s} seeds in {t1:.2f} s, scaled by {s}/{k} "
+                      f"to the full seed set ({t_full:.2f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="rmat20")
+    ap.add_argument("--scheduler", default="heuristic", choices=["heuristic", "pull", "push"])
+    ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work for cpu_baseline")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: the propagation runs on a single MI355X and has no multi-GPU "
+              "path in this build (seed groups would shard across GPUs with one final all-reduce of the "
+              "per-round counts). Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2301_06499_amd import pp
+
+    if not torch.cuda.is_available():
+        raise SystemExit("no GPU visible")
+    torch.cuda.set_device(0)
+    sched = {"heuristic": pp.PP_SCHED_HEURISTIC, "pull": pp.PP_SCHED_PULL, "push": pp.PP_SCHED_PUSH}[args.scheduler]
+
+    t0 = time.perf_counter()
+    g, seeds, cfg = workload(args.workload)
+    log(f"[bench] generated {cfg['workload']} in {time.perf_counter() - t0:.1f} s")
+    stream = torch.cuda.Stream()                       # default priority
+    t0 = time.perf_counter()
+    G = pp.pp_csr_build(g.n, g.src, g.dst, undirected=g.undirected, stream=stream)
+    log(f"[bench] csr_build {time.perf_counter() - t0:.1f} s: n={G.nodes} arcs={G.arcs}")
+    dseeds = torch.from_numpy(seeds.astype(np.int32)).to("cuda")
+    torch.cuda.synchronize()
+    run = pp.pp_seeds_init(G, seeds, opts=pp.options(scheduler=sched, max_rounds=4096, time_kernels=True),
+                           stream=stream)
+    W = run.words
+    s = len(seeds)
+
+    def step():
+        pp.pp_seeds_reset(run, dseeds)
+        return pp.pp_propagate_until_converged(run)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    cap = 4097
+    ms_before = pp.pp_get_kernel_times(run, cap).astype(np.float64)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        counts, D = step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_after = pp.pp_get_kernel_times(run, cap).astype(np.float64)
+    Dv = int(D[0])
+    rounds = Dv + 1
+    modes, arcs = pp.pp_get_round_log(run, cap)
+    m, n = G.arcs, G.nodes
+
+    words_per_arc = s / 64.0
+    nominal = m * words_per_arc * rounds
+    touched = float(arcs[1:rounds + 1].sum()) * words_per_arc
+    ms_step = elapsed * 1000.0 / args.steps
+
+    # roofline of the dense pull kernel: algorithmic bytes per launch
+    #   per arc gathered: 4 B column index + 8W B source row
+    #   per node: 8 B row offset + 8W B own row
+    pull_rounds = [r for r in range(1, rounds + 1) if modes[r] == pp.MODE_PULL]
+    pull_ms = (ms_after - ms_before) / args.steps
+    bytes_pull = sum(float(arcs[r]) * (4 + 8 * W) + n * (8 + 8 * W) for r in pull_rounds)
+    t_pull = sum(pull_ms[r] for r in pull_rounds) / 1000.0
+    achieved = bytes_pull / t_pull / 1e9 if t_pull > 0 else 0.0
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "kernel": f"k_pull<{W}>", "launches_per_step": len(pull_rounds),
+            "avg_launch_ms": round(t_pull * 1000.0 / max(1, len(pull_rounds)), 4),
+            "bytes_per_launch": round(bytes_pull / max(1, len(pull_rounds)))}
+
+    out = {
+        "metric": METRIC,
+        "value": nominal * args.steps / elapsed,
+        "unit": "edge-words/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u64", "data": "synthetic",
+        "config": dict(cfg, nodes=n, arcs=m, words=W, rounds=rounds, diameter_lb=Dv,
+                       scheduler=args.scheduler,
+                       modes="".join("P" if modes[r] == pp.MODE_PULL else "S" for r in range(1, rounds + 1))),
+        "touched_edge_words_per_s": touched * args.steps / elapsed,
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        log("[bench] timing the CPU oracle")
+        out["cpu_baseline"] = cpu_baseline(g, seeds, nominal, args.cpu_budget)
+    print(json.dumps(out), flush=True)
+    run.free()
+    G.free()
+
+
+if __name__ == "__main__":
+    main()

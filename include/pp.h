@@ -83,6 +83,8 @@ typedef struct {
     int32_t use_graph;          /* 1: replay the round batch as a captured hipGraph */
     int32_t push_div;           /* heuristic: push while frontier arcs * push_div < arcs (0: 8) */
     uint64_t fuzz_seed;         /* PP_SCHED_FUZZ stream */
+    int32_t time_kernels;       /* 1: HIP events around every pull launch (pp_get_kernel_times) */
+    int32_t reserved;
 } pp_options;
 
 /* Metrics estimated from c[0..D] (paper Section 3 and Algorithm 1's closing
@@ -149,6 +151,17 @@ int pp_seeds_init(pp_graph g, const int32_t *seeds, int32_t s, const pp_options 
                   void *stream, pp_run *out);
 
 /*
+ * pp_seeds_reset -- the same initialisation on an existing run, reusing its
+ * device memory (no allocation): num_graphs * s seed ids, host memory or,
+ * with seeds_on_device, device memory the caller owns.  Seeds are checked
+ * against the graphs' node ranges on the device path too: an out-of-range
+ * id makes the call fail with PP_ERANGE after the stream is synchronised
+ * and leaves the run unusable until a successful reset.  Round logs
+ * restart; kernel times keep accumulating.
+ */
+int pp_seeds_reset(pp_run r, const int32_t *seeds, int32_t seeds_on_device);
+
+/*
  * pp_propagate_round -- one synchronous round (one pass of Algorithm 1's
  * do-while body) for every graph of the batch not yet converged.
  *   new_bits        host [num_graphs]: c_g[r] of the round just run (0 for a
@@ -196,6 +209,13 @@ int32_t pp_run_words(pp_run r);
  * current round, mode[r] (0 pull, 1 push) and arcs[r] (arcs the round
  * touched).  Host arrays of cap entries; either may be NULL. */
 int pp_get_round_log(pp_run r, int32_t *mode, int64_t *arcs, int32_t cap);
+
+/* With opt.time_kernels: pull_ms[r] = total duration in ms of round r's
+ * pull launches (HIP events on the run's stream), summed over every
+ * propagation since the run was created (pp_seeds_reset keeps the sums, so
+ * a caller differences two reads around repeated runs).  A launch in a push
+ * round returns at once and is still timed.  Host array of cap entries. */
+int pp_get_kernel_times(pp_run r, float *pull_ms, int32_t cap);
 
 /* Copy of a run's whole state (signatures, frontier, logs) / restore from a
  * copy of the same graph and s.  A restored run continues bit-identically. */

@@ -82,7 +82,7 @@ template <typename F> void parallel_for(int64_t n, F f) {
 struct TileSet {
     Tile *tiles = nullptr;
     int32_t ntiles = 0;
-    int32_t *hub_nchunks = nullptr;
+    int32_t *hub_node = nullptr;   // node of each high-degree entry
     int32_t nhubs = 0;
 };
 
@@ -98,6 +98,7 @@ struct pp_graph_s {
     int64_t *rp = nullptr, *trp = nullptr;
     int32_t *col = nullptr, *tcol = nullptr;
     int32_t *node_graph = nullptr;
+    int64_t *node_off = nullptr;
     std::map<int, TileSet> tiles;   // by pull arc budget
 };
 
@@ -111,6 +112,11 @@ struct pp_run_s {
     Ctrl host_ctrl{};
     std::map<int, hipGraphExec_t> graphs;   // captured batches by round count
     std::map<int, hipGraph_t> graph_defs;
+    int32_t *dseeds = nullptr;              // [G*s] staging for host seed lists
+    bool timing = false;
+    bool graph_events = true;               // events recorded inside captured graphs work
+    std::vector<hipEvent_t> ev;             // 2 per round slot of a batch
+    std::vector<float> pull_ms;             // [cap]
 };
 
 extern "C" {
@@ -187,11 +193,12 @@ void transpose_rows(int64_t n, const std::vector<int64_t> &rp, const std::vector
 
 // Pull tiles: runs of consecutive nodes with at most `edges` arcs and
 // pp::TILE_NODES nodes; a node with more than `edges` arcs is split into
-// chunks that combine through the hub tables.  Runs without arcs are
-// dropped (their nodes can never gain a bit in a pull).  Hub chunks come
-// first so the longest-latency work starts early.
+// chunks whose partial rows meet in the accumulator (hub_node lists those
+// nodes).  Runs without arcs are dropped: their nodes have no successor and
+// never gain a bit after initialisation.  Hub chunks come first so the
+// longest-latency work starts early.
 void build_tiles(const std::vector<int64_t> &rp, const std::vector<int64_t> &noff, int G, int edges,
-                 std::vector<Tile> &tiles, std::vector<int32_t> &hub_nchunks) {
+                 std::vector<Tile> &tiles, std::vector<int32_t> &hub_node) {
     std::vector<Tile> hubs, runs;
     for (int g = 0; g < G; ++g) {
         int64_t u = noff[(size_t)g];
@@ -199,9 +206,9 @@ void build_tiles(const std::vector<int64_t> &rp, const std::vector<int64_t> &nof
         while (u < end) {
             const int64_t deg = rp[(size_t)u + 1] - rp[(size_t)u];
             if (deg > edges) {
-                const int32_t h = (int32_t)hub_nchunks.size();
+                const int32_t h = (int32_t)hub_node.size();
                 const int32_t nch = (int32_t)((deg + edges - 1) / edges);
-                hub_nchunks.push_back(nch);
+                hub_node.push_back((int32_t)u);
                 for (int32_t j = 0; j < nch; ++j) {
                     const int64_t e0 = rp[(size_t)u] + (int64_t)j * edges;
                     const int64_t e1 = std::min(rp[(size_t)u + 1], e0 + edges);
@@ -245,7 +252,7 @@ int ensure_tiles(pp_graph g, int W, TileSet **out) {
     TileSet ts;
     int rc;
     if ((rc = dev_alloc(&ts.tiles, (int64_t)tiles.size())) != PP_OK) return rc;
-    if ((rc = dev_alloc(&ts.hub_nchunks, (int64_t)hubs.size())) != PP_OK) {
+    if ((rc = dev_alloc(&ts.hub_node, (int64_t)hubs.size())) != PP_OK) {
         dev_free(ts.tiles);
         return rc;
     }
@@ -254,10 +261,10 @@ int ensure_tiles(pp_graph g, int W, TileSet **out) {
     hipError_t e = hipSuccess;
     if (!tiles.empty()) e = hipMemcpy(ts.tiles, tiles.data(), sizeof(Tile) * tiles.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess && !hubs.empty())
-        e = hipMemcpy(ts.hub_nchunks, hubs.data(), sizeof(int32_t) * hubs.size(), hipMemcpyHostToDevice);
+        e = hipMemcpy(ts.hub_node, hubs.data(), sizeof(int32_t) * hubs.size(), hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         dev_free(ts.tiles);
-        dev_free(ts.hub_nchunks);
+        dev_free(ts.hub_node);
         return fail(PP_EDEVICE, "tile upload: %s", hipGetErrorString(e));
     }
     g->tiles[edges] = ts;
@@ -272,9 +279,10 @@ void free_graph(pp_graph g) {
     dev_free(g->col);
     dev_free(g->tcol);
     dev_free(g->node_graph);
+    dev_free(g->node_off);
     for (auto &kv : g->tiles) {
         dev_free(kv.second.tiles);
-        dev_free(kv.second.hub_nchunks);
+        dev_free(kv.second.hub_node);
     }
     delete g;
 }
@@ -290,9 +298,11 @@ GraphDev graph_view(pp_graph g, const TileSet *ts) {
     d.tiles = ts ? ts->tiles : nullptr;
     d.ntiles = ts ? ts->ntiles : 0;
     d.nhubs = ts ? ts->nhubs : 0;
-    d.hub_nchunks = ts ? ts->hub_nchunks : nullptr;
+    d.hub_node = ts ? ts->hub_node : nullptr;
     d.node_graph = g->node_graph;
+    d.node_off = g->node_off;
     d.G = g->G;
+    d.pull_grid = pp::pull_grid_for(d.ntiles);
     return d;
 }
 
@@ -376,7 +386,8 @@ extern "C" int pp_csr_build(int64_t n, int64_t m, const int32_t *src, const int3
     g->node_offsets = noff;
     int rc;
     if ((rc = dev_alloc(&g->rp, n + 1)) || (rc = dev_alloc(&g->trp, n + 1)) || (rc = dev_alloc(&g->col, g->m)) ||
-        (rc = dev_alloc(&g->tcol, g->m)) || (G > 1 && (rc = dev_alloc(&g->node_graph, n)))) {
+        (rc = dev_alloc(&g->tcol, g->m)) || (G > 1 && (rc = dev_alloc(&g->node_graph, n))) ||
+        (rc = dev_alloc(&g->node_off, (int64_t)G + 1))) {
         free_graph(g);
         return rc;
     }
@@ -385,6 +396,7 @@ extern "C" int pp_csr_build(int64_t n, int64_t m, const int32_t *src, const int3
     if (e == hipSuccess && g->m) e = hipMemcpyAsync(g->col, col.data(), sizeof(int32_t) * (size_t)g->m, hipMemcpyHostToDevice, st);
     if (e == hipSuccess && g->m) e = hipMemcpyAsync(g->tcol, tcol.data(), sizeof(int32_t) * (size_t)g->m, hipMemcpyHostToDevice, st);
     if (e == hipSuccess && G > 1) e = hipMemcpyAsync(g->node_graph, ng.data(), sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(g->node_off, noff.data(), sizeof(int64_t) * (size_t)(G + 1), hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) {
         free_graph(g);
@@ -411,7 +423,8 @@ int words_for(int s) {
 }
 
 void free_run_dev(RunDev &d) {
-    dev_free(d.sig);
+    dev_free(d.sig[0]);
+    dev_free(d.sig[1]);
     dev_free(d.acc);
     dev_free(d.stamp);
     for (int k = 0; k < 2; ++k) {
@@ -419,8 +432,10 @@ void free_run_dev(RunDev &d) {
         dev_free(d.f_delta[k]);
         dev_free(d.chunks[k]);
     }
-    dev_free(d.hub_acc);
-    dev_free(d.hub_done);
+    dev_free(d.blk_cnt);
+    dev_free(d.blk_nodes);
+    dev_free(d.blk_arcs);
+    dev_free(d.blk_pulled);
     dev_free(d.counts);
     dev_free(d.seed_counts);
     dev_free(d.D);
@@ -442,14 +457,17 @@ void free_run(pp_run r) {
     if (r->stream) (void)hipStreamSynchronize(r->stream);
     drop_graphs(r);
     free_run_dev(r->dev);
+    dev_free(r->dseeds);
+    for (hipEvent_t e : r->ev) (void)hipEventDestroy(e);
     if (r->own_stream && r->stream) (void)hipStreamDestroy(r->stream);
     delete r;
 }
 
-int64_t chunk_capacity(pp_graph g) { return g->n + g->m / pp::PUSH_CHUNK + 2; }
+// push chunks: at most one per listed entry plus one per chunk of arcs
+int64_t chunk_capacity(pp_graph g) { return g->n + g->m / pp::PUSH_CHUNK_MIN + 2; }
 
 // Allocates every device buffer of a run with the sizes fixed by (g, s, cap).
-int alloc_run_dev(pp_graph g, RunDev &d, int s, int W, int cap, bool seed_counts, int nhubs) {
+int alloc_run_dev(pp_graph g, RunDev &d, int s, int W, int cap, bool seed_counts, int pull_grid) {
     const int64_t n = g->n;
     const int G = g->G;
     int rc;
@@ -457,11 +475,13 @@ int alloc_run_dev(pp_graph g, RunDev &d, int s, int W, int cap, bool seed_counts
     d.W = W;
     d.cap = cap;
     d.G = G;
-    if ((rc = dev_alloc(&d.sig, n * W)) || (rc = dev_alloc(&d.acc, n * W)) || (rc = dev_alloc(&d.stamp, n)) ||
+    if ((rc = dev_alloc(&d.sig[0], n * W)) || (rc = dev_alloc(&d.sig[1], n * W)) || (rc = dev_alloc(&d.acc, n * W)) ||
+        (rc = dev_alloc(&d.stamp, n)) ||
         (rc = dev_alloc(&d.f_ids[0], n)) || (rc = dev_alloc(&d.f_ids[1], n)) ||
         (rc = dev_alloc(&d.f_delta[0], n * W)) || (rc = dev_alloc(&d.f_delta[1], n * W)) ||
         (rc = dev_alloc(&d.chunks[0], chunk_capacity(g))) || (rc = dev_alloc(&d.chunks[1], chunk_capacity(g))) ||
-        (rc = dev_alloc(&d.hub_acc, (int64_t)nhubs * W)) || (rc = dev_alloc(&d.hub_done, nhubs)) ||
+        (rc = dev_alloc(&d.blk_cnt, pull_grid)) || (rc = dev_alloc(&d.blk_nodes, pull_grid)) ||
+        (rc = dev_alloc(&d.blk_arcs, pull_grid)) || (rc = dev_alloc(&d.blk_pulled, pull_grid)) ||
         (rc = dev_alloc(&d.counts, (int64_t)cap * G)) || (rc = dev_alloc(&d.D, G)) || (rc = dev_alloc(&d.gconv, G)) ||
         (rc = dev_alloc(&d.mode_log, cap)) || (rc = dev_alloc(&d.arcs_log, cap)) || (rc = dev_alloc(&d.ctrl, 1)))
         return rc;
@@ -470,14 +490,13 @@ int alloc_run_dev(pp_graph g, RunDev &d, int s, int W, int cap, bool seed_counts
     return PP_OK;
 }
 
-hipError_t clear_run_dev(pp_graph g, RunDev &d, int nhubs, hipStream_t st) {
+hipError_t clear_run_dev(pp_graph g, RunDev &d, hipStream_t st) {
     const int64_t n = g->n;
     hipError_t e;
-    if ((e = pp::launch_fill_u64(d.sig, 0, n * d.W, st))) return e;
+    if ((e = pp::launch_fill_u64(d.sig[0], 0, n * d.W, st))) return e;
+    if ((e = pp::launch_fill_u64(d.sig[1], 0, n * d.W, st))) return e;
     if ((e = pp::launch_fill_u64(d.acc, 0, n * d.W, st))) return e;
     if ((e = pp::launch_fill_i32(d.stamp, -1, n, st))) return e;
-    if ((e = pp::launch_fill_u64(d.hub_acc, 0, (int64_t)nhubs * d.W, st))) return e;
-    if ((e = pp::launch_fill_i32((int32_t *)d.hub_done, 0, nhubs, st))) return e;
     if ((e = pp::launch_fill_u64((uint64_t *)d.counts, 0, (int64_t)d.cap * d.G, st))) return e;
     if (d.seed_counts && (e = pp::launch_fill_i32((int32_t *)d.seed_counts, 0, (int64_t)d.cap * d.G * d.s, st))) return e;
     if ((e = pp::launch_fill_i32(d.D, 0, d.G, st))) return e;
@@ -497,6 +516,35 @@ int sync_ctrl(pp_run r) {
 
 }  // namespace
 
+namespace {
+
+// Algorithm 1's initialisation on an allocated run: clear every buffer, place
+// the seed bits (device seeds), run the round-0 commit.  Synchronises.
+int reset_run(pp_run r, const int32_t *dseeds) {
+    pp_graph g = r->g;
+    TileSet *ts = run_tiles(r);
+    GraphDev gv = graph_view(g, ts);
+    hipError_t e = clear_run_dev(g, r->dev, r->stream);
+    if (e == hipSuccess) e = pp::launch_seed_init(gv, r->dev, dseeds, r->stream);
+    if (e != hipSuccess) return fail(PP_EDEVICE, "seed initialisation: %s", hipGetErrorString(e));
+    int rc = sync_ctrl(r);
+    if (rc) return rc;
+    if (r->host_ctrl.bad_seed) return fail(PP_ERANGE, "a seed id lies outside its graph's node range");
+    return PP_OK;
+}
+
+int check_host_seeds(pp_graph g, const int32_t *seeds, int s) {
+    for (int gi = 0; gi < g->G; ++gi)
+        for (int i = 0; i < s; ++i) {
+            const int64_t x = seeds[(int64_t)gi * s + i];
+            if (x < g->node_offsets[(size_t)gi] || x >= g->node_offsets[(size_t)gi + 1])
+                return fail(PP_ERANGE, "seed %d of graph %d (%lld) outside the graph's nodes", i, gi, (long long)x);
+        }
+    return PP_OK;
+}
+
+}  // namespace
+
 extern "C" int pp_seeds_init(pp_graph g, const int32_t *seeds, int32_t s, const pp_options *opt, void *stream,
                              pp_run *out) {
     if (!g || !out) return fail(PP_EINVAL, "graph or out is NULL");
@@ -509,12 +557,8 @@ extern "C" int pp_seeds_init(pp_graph g, const int32_t *seeds, int32_t s, const 
     if (o.scheduler < PP_SCHED_HEURISTIC || o.scheduler > PP_SCHED_MLP) return fail(PP_EINVAL, "unknown scheduler %d", o.scheduler);
     if (o.max_rounds < 0 || o.rounds_per_sync < 0) return fail(PP_EINVAL, "negative max_rounds / rounds_per_sync");
     const int G = g->G;
-    for (int gi = 0; gi < G; ++gi)
-        for (int i = 0; i < s; ++i) {
-            const int64_t x = seeds[(int64_t)gi * s + i];
-            if (x < g->node_offsets[(size_t)gi] || x >= g->node_offsets[(size_t)gi + 1])
-                return fail(PP_ERANGE, "seed %d of graph %d (%lld) outside the graph's nodes", i, gi, (long long)x);
-        }
+    int rc = check_host_seeds(g, seeds, s);
+    if (rc) return rc;
     int64_t cap = o.max_rounds > 0 ? (int64_t)o.max_rounds + 1 : std::min<int64_t>(g->n + 1, 1 << 20);
     if (cap < 2) cap = 2;
     if (o.seed_counts && cap * G * (int64_t)s * 4 > (int64_t)1 << 31)
@@ -529,6 +573,7 @@ extern "C" int pp_seeds_init(pp_graph g, const int32_t *seeds, int32_t s, const 
     r->cap = (int32_t)cap;
     r->G = G;
     r->opt = o;
+    r->timing = o.time_kernels != 0;
     if (stream) {
         r->stream = (hipStream_t)stream;
     } else {
@@ -540,8 +585,18 @@ extern "C" int pp_seeds_init(pp_graph g, const int32_t *seeds, int32_t s, const 
         r->own_stream = true;
     }
     TileSet *ts = nullptr;
-    int rc = ensure_tiles(g, W, &ts);
-    if (rc == PP_OK) rc = alloc_run_dev(g, r->dev, s, W, (int)cap, o.seed_counts != 0, ts->nhubs);
+    rc = ensure_tiles(g, W, &ts);
+    if (rc == PP_OK) rc = alloc_run_dev(g, r->dev, s, W, (int)cap, o.seed_counts != 0, pp::pull_grid_for(ts->ntiles));
+    if (rc == PP_OK) rc = dev_alloc(&r->dseeds, (int64_t)G * s);
+    if (rc == PP_OK && r->timing) {
+        r->pull_ms.assign((size_t)cap, 0.0f);
+        r->ev.resize(2 * 64, nullptr);
+        for (auto &e : r->ev)
+            if (hipEventCreate(&e) != hipSuccess) {
+                rc = fail(PP_EDEVICE, "event creation");
+                break;
+            }
+    }
     if (rc != PP_OK) {
         free_run(r);
         return rc;
@@ -550,28 +605,29 @@ extern "C" int pp_seeds_init(pp_graph g, const int32_t *seeds, int32_t s, const 
     r->dev.push_div = o.push_div;
     r->dev.fuzz_seed = o.fuzz_seed;
     r->dev.mlp = nullptr;
-
-    int32_t *dseeds = nullptr;
-    if ((rc = dev_alloc(&dseeds, (int64_t)G * s)) != PP_OK) {
-        free_run(r);
-        return rc;
-    }
-    GraphDev gv = graph_view(g, ts);
-    hipError_t e = hipMemcpyAsync(dseeds, seeds, sizeof(int32_t) * (size_t)G * s, hipMemcpyHostToDevice, r->stream);
-    if (e == hipSuccess) e = clear_run_dev(g, r->dev, ts->nhubs, r->stream);
-    if (e == hipSuccess) e = pp::launch_seed_init(gv, r->dev, dseeds, r->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(r->stream);
-    (void)hipFree(dseeds);
+    hipError_t e = hipMemcpyAsync(r->dseeds, seeds, sizeof(int32_t) * (size_t)G * s, hipMemcpyHostToDevice, r->stream);
     if (e != hipSuccess) {
         free_run(r);
-        return fail(PP_EDEVICE, "seed initialisation: %s", hipGetErrorString(e));
+        return fail(PP_EDEVICE, "seed upload: %s", hipGetErrorString(e));
     }
-    if ((rc = sync_ctrl(r)) != PP_OK) {
+    if ((rc = reset_run(r, r->dseeds)) != PP_OK) {
         free_run(r);
         return rc;
     }
     *out = r;
     return PP_OK;
+}
+
+extern "C" int pp_seeds_reset(pp_run r, const int32_t *seeds, int32_t seeds_on_device) {
+    if (!r || !seeds) return fail(PP_EINVAL, "run or seeds is NULL");
+    const int64_t total = (int64_t)r->G * r->s;
+    if (!seeds_on_device) {
+        int rc = check_host_seeds(r->g, seeds, r->s);
+        if (rc) return rc;
+        HIP_TRY(hipMemcpyAsync(r->dseeds, seeds, sizeof(int32_t) * (size_t)total, hipMemcpyHostToDevice, r->stream));
+        return reset_run(r, r->dseeds);
+    }
+    return reset_run(r, seeds);
 }
 
 extern "C" void pp_run_free(pp_run r) { free_run(r); }
@@ -588,12 +644,18 @@ extern "C" int pp_propagate_round(pp_run r, int64_t *new_bits, int32_t *all_conv
     }
     const int rr = r->host_ctrl.round;
     GraphDev gv = graph_view(r->g, run_tiles(r));
-    HIP_TRY(pp::launch_round(gv, r->dev, r->stream));
+    hipEvent_t e0 = r->timing ? r->ev[0] : nullptr, e1 = r->timing ? r->ev[1] : nullptr;
+    HIP_TRY(pp::launch_round(gv, r->dev, r->stream, e0, e1));
     if (new_bits)
         HIP_TRY(hipMemcpyAsync(new_bits, r->dev.counts + (int64_t)rr * G, sizeof(int64_t) * (size_t)G,
                                hipMemcpyDeviceToHost, r->stream));
     int rc = sync_ctrl(r);
     if (rc) return rc;
+    if (r->timing) {
+        float ms = 0.0f;
+        HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+        r->pull_ms[(size_t)rr] += ms;
+    }
     if (all_converged) *all_converged = r->host_ctrl.converged;
     if (r->host_ctrl.overflow) return fail(PP_ENOTCONV, "round log full (max_rounds)");
     return PP_OK;
@@ -601,10 +663,13 @@ extern "C" int pp_propagate_round(pp_run r, int64_t *new_bits, int32_t *all_conv
 
 namespace {
 
+hipEvent_t slot_event(pp_run r, int i, int which) { return r->timing ? r->ev[(size_t)(2 * i + which)] : nullptr; }
+
 int launch_batch(pp_run r, int k) {
     GraphDev gv = graph_view(r->g, run_tiles(r));
-    if (!r->opt.use_graph) {
-        for (int i = 0; i < k; ++i) HIP_TRY(pp::launch_round(gv, r->dev, r->stream));
+    if (!r->opt.use_graph || (r->timing && !r->graph_events)) {
+        for (int i = 0; i < k; ++i)
+            HIP_TRY(pp::launch_round(gv, r->dev, r->stream, slot_event(r, i, 0), slot_event(r, i, 1)));
         return PP_OK;
     }
     auto it = r->graphs.find(k);
@@ -613,8 +678,16 @@ int launch_batch(pp_run r, int k) {
         hipGraphExec_t exec = nullptr;
         HIP_TRY(hipStreamBeginCapture(r->stream, hipStreamCaptureModeThreadLocal));
         hipError_t le = hipSuccess;
-        for (int i = 0; i < k && le == hipSuccess; ++i) le = pp::launch_round(gv, r->dev, r->stream);
+        for (int i = 0; i < k && le == hipSuccess; ++i)
+            le = pp::launch_round(gv, r->dev, r->stream, slot_event(r, i, 0), slot_event(r, i, 1));
         hipError_t ce = hipStreamEndCapture(r->stream, &graph);
+        if (le != hipSuccess && r->timing) {
+            // events inside a capture are not supported here: time direct launches instead
+            if (graph) (void)hipGraphDestroy(graph);
+            (void)hipGetLastError();
+            r->graph_events = false;
+            return launch_batch(r, k);
+        }
         if (le != hipSuccess) return fail(PP_EDEVICE, "round capture: %s", hipGetErrorString(le));
         if (ce != hipSuccess) return fail(PP_EDEVICE, "end capture: %s", hipGetErrorString(ce));
         HIP_TRY(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
@@ -644,9 +717,26 @@ extern "C" int pp_propagate_until_converged(pp_run r, int32_t max_rounds, int64_
             while (p * 2 <= k) p *= 2;
             k = p;
         }
+        const int before = r->host_ctrl.round;
         int rc = launch_batch(r, k);
         if (rc) return rc;
         if ((rc = sync_ctrl(r))) return rc;
+        if (r->timing) {
+            // rounds before..last ran; launches after convergence returned at once
+            const int last = r->host_ctrl.converged ? r->host_ctrl.round : before + k - 1;
+            for (int i = 0; i < k && before + i <= last && before + i < r->cap; ++i) {
+                float ms = 0.0f;
+                const hipError_t te = hipEventElapsedTime(&ms, slot_event(r, i, 0), slot_event(r, i, 1));
+                if (te != hipSuccess && r->opt.use_graph && r->graph_events) {
+                    // no timing from events replayed in a graph: time direct launches from now on
+                    (void)hipGetLastError();
+                    r->graph_events = false;
+                    break;
+                }
+                if (te != hipSuccess) return fail(PP_EDEVICE, "event timing: %s", hipGetErrorString(te));
+                r->pull_ms[(size_t)(before + i)] += ms;
+            }
+        }
         if (r->opt.rounds_per_sync <= 0) K = std::min(K * 2, 64);
     }
     // results
@@ -669,7 +759,7 @@ extern "C" int pp_propagate_until_converged(pp_run r, int32_t max_rounds, int64_
 
 extern "C" int pp_get_signatures(pp_run r, uint64_t *dst, int32_t dst_on_device) {
     if (!r || !dst) return fail(PP_EINVAL, "run or dst is NULL");
-    HIP_TRY(hipMemcpyAsync(dst, r->dev.sig, sizeof(uint64_t) * (size_t)r->g->n * r->W,
+    HIP_TRY(hipMemcpyAsync(dst, r->dev.sig[r->host_ctrl.cur & 1], sizeof(uint64_t) * (size_t)r->g->n * r->W,
                            dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, r->stream));
     HIP_TRY(hipStreamSynchronize(r->stream));
     return PP_OK;
@@ -717,7 +807,7 @@ extern "C" int pp_run_snapshot(pp_run r, pp_run *copy) {
     }
     c->own_stream = true;
     TileSet *ts = run_tiles(r);
-    int rc = alloc_run_dev(r->g, c->dev, r->s, r->W, r->cap, r->dev.seed_counts != nullptr, ts->nhubs);
+    int rc = alloc_run_dev(r->g, c->dev, r->s, r->W, r->cap, r->dev.seed_counts != nullptr, pp::pull_grid_for(ts->ntiles));
     if (rc) {
         free_run(c);
         return rc;
@@ -743,12 +833,12 @@ extern "C" int pp_run_restore(pp_run r, pp_run from) {
     if (r == from) return PP_OK;
     if (from->stream != r->stream) HIP_TRY(hipStreamSynchronize(from->stream));
     const int64_t n = r->g->n, W = r->W, G = r->G, cap = r->cap;
-    TileSet *ts = run_tiles(r);
     hipStream_t st = r->stream;
     auto cp = [&](void *d, const void *s, size_t bytes) { return hipMemcpyAsync(d, s, bytes, hipMemcpyDeviceToDevice, st); };
     const RunDev &a = from->dev;
     RunDev &b = r->dev;
-    hipError_t e = cp(b.sig, a.sig, 8 * n * W);
+    hipError_t e = cp(b.sig[0], a.sig[0], 8 * n * W);
+    if (!e) e = cp(b.sig[1], a.sig[1], 8 * n * W);
     if (!e) e = cp(b.acc, a.acc, 8 * n * W);
     if (!e) e = cp(b.stamp, a.stamp, 4 * n);
     for (int k = 0; k < 2 && !e; ++k) {
@@ -756,8 +846,6 @@ extern "C" int pp_run_restore(pp_run r, pp_run from) {
         if (!e) e = cp(b.f_delta[k], a.f_delta[k], 8 * n * W);
         if (!e) e = cp(b.chunks[k], a.chunks[k], sizeof(Chunk) * chunk_capacity(r->g));
     }
-    if (!e && ts->nhubs) e = cp(b.hub_acc, a.hub_acc, 8 * (size_t)ts->nhubs * W);
-    if (!e && ts->nhubs) e = cp(b.hub_done, a.hub_done, 4 * (size_t)ts->nhubs);
     if (!e) e = cp(b.counts, a.counts, 8 * cap * G);
     if (!e && b.seed_counts) e = cp(b.seed_counts, a.seed_counts, 4 * cap * G * r->s);
     if (!e) e = cp(b.D, a.D, 4 * G);
@@ -768,5 +856,12 @@ extern "C" int pp_run_restore(pp_run r, pp_run from) {
     if (!e) e = hipStreamSynchronize(st);
     if (e) return fail(PP_EDEVICE, "restore: %s", hipGetErrorString(e));
     r->host_ctrl = from->host_ctrl;
+    return PP_OK;
+}
+
+extern "C" int pp_get_kernel_times(pp_run r, float *pull_ms, int32_t cap) {
+    if (!r || !pull_ms) return fail(PP_EINVAL, "run or pull_ms is NULL");
+    if (!r->timing) return fail(PP_ESTATE, "run was created without time_kernels");
+    for (int32_t k = 0; k < cap; ++k) pull_ms[k] = k < r->cap ? r->pull_ms[(size_t)k] : 0.0f;
     return PP_OK;
 }

@@ -4,19 +4,16 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#include <string>
-#include <vector>
-
 #include "pp.h"
 
 namespace pp {
 
-// Round directions.  INIT is the seed-initialisation commit (round 0).
+// Round directions.  INIT marks the seed initialisation (round 0).
 enum Mode : int32_t { MODE_PULL = 0, MODE_PUSH = 1, MODE_INIT = 2 };
 
 // A pull work unit: a run of consecutive nodes [u0, u1) whose successor
 // lists occupy arcs [e0, e1) (at most the tile's arc budget), or one chunk of
-// a high-degree node's list (hub >= 0: index into the hub tables).
+// a high-degree node's list (hub >= 0: index into the hub table).
 struct Tile {
     int32_t u0, u1;
     int64_t e0, e1;
@@ -24,37 +21,48 @@ struct Tile {
     int32_t graph;    // graph of the batch the nodes belong to
 };
 
-// Push work unit: arcs [off, off + PUSH_CHUNK) of frontier entry `entry`'s
-// predecessor list.
+// Push work unit for a frontier entry with many predecessors: arcs
+// [off, off + chunk) of entry `entry`'s predecessor list, the chunk being
+// four passes of a wave (256 / W arcs for W-word rows).
 struct Chunk {
     int32_t entry;
     int32_t off;
 };
 
-constexpr int PUSH_CHUNK = 16;   // predecessor arcs per push chunk
 constexpr int BLOCK = 256;       // threads per block of every bulk kernel
 constexpr int TILE_NODES = 256;  // node budget of a pull tile
+constexpr int PUSH_SLOTS = 4;    // predecessor slots per frontier entry in a push
+constexpr int PUSH_LIGHT = 16;   // entries with more predecessors go through chunks
+constexpr int PUSH_CHUNK_MIN = 32;   // smallest chunk (W = 8)
+constexpr int PULL_GRID_MAX = 256 * 8;
 
-// Edges per thread in the pull gather, per signature width W (words).
+// Arcs per thread in the pull gather and the tile arc budget, per signature
+// width W (words); items per thread in a tile's finalisation.
 template <int W> struct PullShape {
     static constexpr int K = W >= 8 ? 4 : 8;
-    static constexpr int EDGES = K * BLOCK;   // arc budget of a pull tile
+    static constexpr int EDGES = K * BLOCK;
+    static constexpr int ITEMS = TILE_NODES * W / BLOCK;   // >= 1
 };
 
 // Device control block: the round counter and everything the per-round
-// kernels hand to each other.  List p = round parity.
+// kernels hand to each other.  Frontier list p holds the nodes that changed
+// in a round of parity p.
 struct Ctrl {
     int32_t round;        // round to run next (>= 1 after initialisation)
     int32_t converged;    // every graph has converged (or the log is full)
     int32_t mode;         // direction of the round about to run
+    int32_t prev_mode;    // direction of the round before it
+    int32_t cur;          // signature buffer holding Sig_{round-1}
     int32_t active;       // graphs not yet converged
     int32_t overflow;     // the round log is full
-    int32_t pad0;
+    int32_t bad_seed;     // a seed id outside its graph was seen (nothing written for it)
     int32_t f_count[2];   // entries in frontier list p
-    int32_t ch_count[2];  // push chunks built from frontier list p
+    int32_t ch_count[2];  // push chunks of frontier list p
     int64_t f_arcs[2];    // predecessor arcs of frontier list p (push work)
-    int64_t pull_arcs;    // arcs gathered by the last pull round
-    int64_t pad1;
+    int64_t hub_cnt;      // new bits found by the hub kernel this round
+    int64_t hub_nodes;    // hubs that changed this round
+    int64_t hub_arcs;     // their predecessor arcs
+    int64_t pad;
 };
 
 struct GraphDev {
@@ -66,22 +74,25 @@ struct GraphDev {
     const Tile *tiles;
     int32_t ntiles;
     int32_t nhubs;
-    const int32_t *hub_nchunks;
+    const int32_t *hub_node;     // [nhubs]
     const int32_t *node_graph;   // [n], NULL for a single graph
+    const int64_t *node_off;     // [G+1] node range of each graph
     int32_t G;
-    int32_t pad;
+    int32_t pull_grid;           // blocks of the pull launch (= per-block partial slots)
 };
 
 struct RunDev {
     int32_t s, W, cap, G;
-    uint64_t *sig;        // [n][W]
-    uint64_t *acc;        // [n][W] push accumulator, zero between rounds
+    uint64_t *sig[2];     // [n][W] each: Sig_{r-1} in sig[cur], the pull writes the other
+    uint64_t *acc;        // [n][W] push / hub accumulator, zero between rounds
     int32_t *stamp;       // [n] last round the node was queued
     int32_t *f_ids[2];    // frontier node ids
     uint64_t *f_delta[2]; // frontier delta words [entries][W]
     Chunk *chunks[2];
-    uint64_t *hub_acc;    // [nhubs][W]
-    uint32_t *hub_done;   // [nhubs]
+    int64_t *blk_cnt;     // [pull_grid] per-block new bits of a pull round
+    int64_t *blk_nodes;   // [pull_grid] changed nodes
+    int64_t *blk_arcs;    // [pull_grid] predecessor arcs of changed nodes
+    int64_t *blk_pulled;  // [pull_grid] arcs gathered
     int64_t *counts;      // [cap][G]
     uint32_t *seed_counts;// [cap][G][s] or NULL
     int32_t *D;           // [G]
@@ -100,7 +111,9 @@ struct RunDev {
 hipError_t launch_fill_u64(uint64_t *p, uint64_t v, int64_t count, hipStream_t st);
 hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t count, hipStream_t st);
 hipError_t launch_seed_init(const GraphDev &g, const RunDev &r, const int32_t *seeds_dev, hipStream_t st);
-hipError_t launch_round(const GraphDev &g, const RunDev &r, hipStream_t st);
-int pull_grid(const GraphDev &g);
+// One round; when e0/e1 are given they are recorded around the pull launch.
+hipError_t launch_round(const GraphDev &g, const RunDev &r, hipStream_t st, hipEvent_t e0 = nullptr,
+                        hipEvent_t e1 = nullptr);
+int pull_grid_for(int32_t ntiles);
 
 }  // namespace pp

@@ -1,29 +1,32 @@
 // HIP kernels for PROPAGATE-P rounds on gfx950 (wave64).
 //
-// One round r (Algorithm 1's do-while body) is four launches that hand work
-// to each other through the device control block, so a round needs no host
-// decision and a batch of rounds can be replayed as a captured graph:
+// A round r (one pass of Algorithm 1's do-while body) is a fixed sequence of
+// launches that hand work to each other through the device control block,
+// so no host decision is needed between rounds and a batch of rounds can be
+// replayed as a captured graph.  Kernels of the direction not chosen for the
+// round return at once.
 //
-//   k_pull<W>       dense pull: for every node u, OR the rows of u's
-//                   successors (the ball recurrence of Section 4) into an LDS
-//                   accumulator; nodes whose accumulated bits are not all in
-//                   Sig(u) are appended to frontier list r&1 with their new
-//                   bits.  Sig is only read, so the update is synchronous.
-//   k_push<W>       sparse push: for every predecessor u of a node v that
-//                   changed in round r-1, atomically OR v's new bits of round
-//                   r-1 into Sig(u); bits u did not have are collected in the
-//                   accumulator and u is queued once.  Only new bits of round
-//                   r-1 can produce new bits in round r (every older bit of v
-//                   already reached u), so this equals the pull.
-//   k_commit<W>     applies (pull) or collects (push) the new bits of the
-//                   frontier entries, counts them (c[r] = popcount of the new
-//                   bits, Algorithm 1's XOR count), optionally per seed with
-//                   wave ballots, and prepares the push chunks for round r+1.
-//   k_round_end     convergence (a graph converges at its first round with no
-//                   new bit), diameter bookkeeping, the per-round log, and the
-//                   direction of round r+1.
-//
-// Whichever of pull/push is not selected returns at once.
+// Dense pull (the ball recurrence of Section 4, Sig_r(u) = Sig_{r-1}(u) OR
+// the rows of u's successors):
+//   k_pull<W>        tiles of consecutive nodes: successor ids staged in LDS,
+//                    each thread ORs the rows of K consecutive arcs in
+//                    registers and flushes them into the node's LDS row; the
+//                    new row is written to the other signature buffer (the
+//                    update is synchronous because Sig_{r-1} is only read).
+//                    New bits are counted per block (Algorithm 1's XOR count).
+//                    Chunks of high-degree nodes OR into the accumulator.
+//   k_pull_hubs<W>   finishes the high-degree nodes.
+// Sparse push (equal to the pull: only the bits a node gained in round r-1
+// can give new bits in round r, every older bit having reached its
+// predecessors already):
+//   k_frontier<W>    after a pull round, lists the nodes that changed in it.
+//   k_push<W>        ORs those new bits into the predecessors' rows with
+//                    atomics; a bit is new when the atomic that sets it saw
+//                    it clear; nodes that gained bits are queued once.
+//   k_push_commit<W> collects the gained bits, counts them, lists them.
+// k_round_end        counts, convergence (a graph converges at its first
+//                    round without a new bit), diameter bookkeeping, the
+//                    per-round log and the direction of the next round.
 #include "pp_internal.h"
 
 namespace pp {
@@ -33,9 +36,14 @@ namespace pp {
 PP_DEV int lane_id() { return __lane_id(); }
 
 template <int W> struct WordMask {
-    // lanes holding word w of a row when W consecutive lanes share a row
-    static constexpr uint64_t rep = ~0ull / ((W == 64) ? ~0ull : ((1ull << W) - 1));
-    static constexpr uint64_t row = (W == 64) ? ~0ull : ((1ull << W) - 1);
+    static constexpr uint64_t rep = ~0ull / ((1ull << W) - 1);   // lanes with (lane % W) == 0
+    static constexpr uint64_t row = (1ull << W) - 1;              // the W lanes of one row
+};
+
+// arcs of a push chunk: four passes of a whole wave (64 / W slots)
+template <int W> struct PushShape {
+    static constexpr int SLOTS = 64 / W;
+    static constexpr int CHUNK = 4 * SLOTS;
 };
 
 PP_DEV uint64_t mix64(uint64_t z) {
@@ -74,6 +82,19 @@ PP_DEV int32_t wave_append(int32_t *counter, bool want) {
     return want ? base + (int32_t)__popcll(m & ((1ull << ln) - 1ull)) : -1;
 }
 
+// Block-wide sum of a per-thread value (all threads must call).
+template <typename T> PP_DEV T block_sum(T v, T *scratch) {
+    v = wave_sum(v);
+    const int wv = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane_id() == 0) scratch[wv] = v;
+    __syncthreads();
+    T t = 0;
+#pragma unroll
+    for (int k = 0; k < BLOCK / 64; ++k) t += scratch[k];
+    return t;
+}
+
 template <int W> PP_DEV void load_row(const uint64_t *__restrict__ p, uint64_t (&out)[W]) {
     if constexpr (W == 1) {
         out[0] = p[0];
@@ -94,6 +115,102 @@ template <int W> PP_DEV void flush_lds(unsigned long long *dst, uint64_t (&acc)[
         acc[w] = 0;
     }
 }
+
+// Per-seed counts, wave-wide: lane b accumulates how many lanes holding word
+// k have bit b set in d (lanes hold word lane % W).  Call with the whole
+// wave active.
+template <int W> PP_DEV void seed_ballot(uint64_t d, uint32_t (&sc)[W]) {
+    if (__ballot(d != 0) == 0) return;
+    const int ln = lane_id();
+    for (int bit = 0; bit < 64; ++bit) {
+        const uint64_t m = __ballot((int)((d >> bit) & 1ull));
+        if (m) {
+#pragma unroll
+            for (int k = 0; k < W; ++k) {
+                const uint32_t c = (uint32_t)__popcll(m & (WordMask<W>::rep << k));
+                if (ln == bit) sc[k] += c;
+            }
+        }
+    }
+}
+
+template <int W> PP_DEV void seed_flush(const RunDev &R, int r, const uint32_t (&sc)[W]) {
+    const int ln = lane_id();
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+        const int bitidx = k * 64 + ln;
+        if (sc[k] && bitidx < R.s) atomicAdd(&R.seed_counts[(int64_t)r * R.s + bitidx], sc[k]);
+    }
+}
+
+// Per-seed counts of one word for a graph of a batch (one atomic per set bit).
+PP_DEV void seed_bits(const RunDev &R, int r, int gi, int w, uint64_t d) {
+    while (d) {
+        const int bit = __ffsll((long long)d) - 1;
+        d &= d - 1;
+        atomicAdd(&R.seed_counts[((int64_t)r * R.G + gi) * R.s + w * 64 + bit], 1u);
+    }
+}
+
+// Block-wide exclusive prefix sum of v in thread order, with the block total;
+// every thread of the block must call (scratch: BLOCK/64 ints of LDS).
+PP_DEV int block_scan(int v, int *scratch, int &total) {
+    const int incl = wave_inclusive_scan(v);
+    const int wv = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane_id() == 63) scratch[wv] = incl;
+    __syncthreads();
+    int before = 0;
+    total = 0;
+#pragma unroll
+    for (int k = 0; k < BLOCK / 64; ++k) {
+        const int c = scratch[k];
+        if (k < wv) before += c;
+        total += c;
+    }
+    return before + incl - v;
+}
+
+// Push chunks needed by a frontier entry with `deg` predecessors (0 when the
+// light path walks its list).
+template <int W> PP_DEV int chunks_for(int64_t deg) {
+    constexpr int CH = PushShape<W>::CHUNK;
+    return deg > PUSH_LIGHT ? (int)((deg + CH - 1) / CH) : 0;
+}
+
+// Lists nodes in a block-private LDS queue and moves the queue to the global
+// list with one atomic per block (fewer same-address atomics than a per-wave
+// append).  An entry that does not fit falls back to a global atomic.
+struct BlockQueue {
+    static constexpr int CAP = 2048;
+    int32_t *q;      // LDS [CAP]
+    int *n;          // LDS counter
+    PP_DEV void push(bool want, int32_t u, int32_t *gcount, int32_t *glist) {
+        const uint64_t m = __ballot(want);
+        if (m == 0) return;
+        const int ln = lane_id();
+        const int leader = __ffsll((long long)m) - 1;
+        int base = 0;
+        if (ln == leader) base = atomicAdd(n, (int)__popcll(m));
+        base = __shfl(base, leader);
+        if (want) {
+            const int pos = base + (int)__popcll(m & ((1ull << ln) - 1ull));
+            if (pos < CAP) {
+                q[pos] = u;
+            } else {
+                glist[atomicAdd(gcount, 1)] = u;
+            }
+        }
+    }
+    // all threads of the block; ends with the queue moved out
+    PP_DEV void flush(int32_t *gcount, int32_t *glist, int *s_base) {
+        __syncthreads();
+        const int cnt = *n < CAP ? *n : CAP;
+        if (threadIdx.x == 0) *s_base = cnt ? atomicAdd(gcount, cnt) : 0;
+        __syncthreads();
+        for (int i = threadIdx.x; i < cnt; i += BLOCK) glist[*s_base + i] = q[i];
+    }
+};
 
 // ---------------------------------------------------------------- fills
 
@@ -130,17 +247,106 @@ hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t count, hipStream_t st)
 
 // Seed bit i of graph g goes to node seeds[g*s + i] (Algorithm 1's
 // initialisation).  Bits are gathered in the accumulator first so that a node
-// holding several seeds is queued once; the INIT commit then writes them.
+// holding several seeds is listed once; the round-0 commit writes them.  A
+// seed outside its graph's node range is skipped and flagged.
 template <int W>
-__global__ void __launch_bounds__(BLOCK) k_seed_scatter(RunDev R, const int32_t *seeds, int64_t total) {
+__global__ void __launch_bounds__(BLOCK) k_seed_scatter(GraphDev g, RunDev R, const int32_t *seeds, int64_t total) {
     for (int64_t j = blockIdx.x * (int64_t)BLOCK + threadIdx.x; j < total; j += (int64_t)gridDim.x * BLOCK) {
         const int i = (int)(j % R.s);
+        const int gi = (int)(j / R.s);
         const int32_t x = seeds[j];
-        atomicOr((unsigned long long *)&R.acc[(int64_t)x * W + (i >> 6)], 1ull << (i & 63));
-        const bool want = atomicMax(&R.stamp[x], 0) < 0;
+        const bool ok = x >= g.node_off[gi] && x < g.node_off[gi + 1];
+        if (!ok) atomicOr(&R.ctrl->bad_seed, 1);
+        if (ok) atomicOr((unsigned long long *)&R.acc[(int64_t)x * W + (i >> 6)], 1ull << (i & 63));
+        const bool want = ok && atomicMax(&R.stamp[x], 0) < 0;
         const int pos = wave_append(&R.ctrl->f_count[0], want);
         if (want) R.f_ids[0][pos] = x;
     }
+}
+
+// ---------------------------------------------------------------- list commit
+
+// Collects the bits gathered in the accumulator for the entries of frontier
+// list r&1, writes them into the list, counts them, and reserves push chunks
+// for the next round.  Round 0 (init) also writes them into both signature
+// buffers; a push round has set them in Sig already.
+template <int W>
+__global__ void __launch_bounds__(BLOCK) k_push_commit(GraphDev g, RunDev R, int init) {
+    Ctrl *C = R.ctrl;
+    if (C->converged) return;
+    if (!init && C->mode != MODE_PUSH) return;
+    const int r = init ? 0 : C->round;
+    const int p = r & 1;
+    const int32_t cnt = C->f_count[p];
+    const int64_t items = (int64_t)cnt * W;
+    const int32_t *ids = R.f_ids[p];
+    uint64_t *dl = R.f_delta[p];
+    Chunk *chunks = R.chunks[p];
+    const int ln = lane_id();
+    const int w = ln & (W - 1);
+    const bool per_seed = R.seed_counts != nullptr;
+    __shared__ int s_scan[BLOCK / 64];
+    __shared__ int s_cbase;
+    uint64_t pop = 0;
+    int64_t arcs = 0;
+    uint32_t sc[W];
+#pragma unroll
+    for (int k = 0; k < W; ++k) sc[k] = 0;
+    const int64_t stride = (int64_t)gridDim.x * BLOCK;
+    for (int64_t bb = blockIdx.x * (int64_t)BLOCK; bb < items; bb += stride) {   // block-uniform
+        const int64_t idx = bb + threadIdx.x;
+        const bool valid = idx < items;
+        const int32_t e = (int32_t)(idx / W);
+        uint64_t d = 0;
+        int32_t u = 0;
+        int64_t deg = 0;
+        if (valid) {
+            u = ids[e];
+            uint64_t *ap = R.acc + (int64_t)u * W + w;
+            d = *ap;
+            *ap = 0;
+            dl[idx] = d;
+            if (init) {
+                R.sig[0][(int64_t)u * W + w] |= d;
+                R.sig[1][(int64_t)u * W + w] |= d;
+            }
+            if (w == 0) {
+                deg = g.trp[u + 1] - g.trp[u];
+                arcs += deg;
+            }
+        }
+        const int pc = __popcll(d);
+        int gi = 0;
+        if (R.G == 1) {
+            pop += (uint64_t)pc;
+        } else if (valid) {
+            gi = g.node_graph[u];
+            if (pc) atomicAdd((unsigned long long *)&R.counts[(int64_t)r * R.G + gi], (unsigned long long)pc);
+        }
+        // push chunks of long predecessor lists, one reservation per block
+        const int nchk = (valid && w == 0) ? chunks_for<W>(deg) : 0;
+        int total = 0;
+        const int before = block_scan(nchk, s_scan, total);
+        if (total) {
+            if (threadIdx.x == 0) s_cbase = atomicAdd(&C->ch_count[p], total);
+            __syncthreads();
+            const int first = s_cbase + before;
+            for (int j = 0; j < nchk; ++j) chunks[first + j] = Chunk{e, j * PushShape<W>::CHUNK};
+            __syncthreads();
+        }
+        if (per_seed) {
+            if (R.G == 1) seed_ballot<W>(d, sc);
+            else if (valid) seed_bits(R, r, gi, w, d);
+        }
+    }
+    __shared__ unsigned long long s_red[BLOCK / 64];
+    const unsigned long long tp = block_sum<unsigned long long>(pop, s_red);
+    const unsigned long long ta = block_sum<unsigned long long>((unsigned long long)arcs, s_red);
+    if (threadIdx.x == 0) {
+        if (R.G == 1 && tp) atomicAdd((unsigned long long *)&R.counts[r], tp);
+        if (ta) atomicAdd((unsigned long long *)&C->f_arcs[p], ta);
+    }
+    if (per_seed && R.G == 1) seed_flush<W>(R, r, sc);
 }
 
 // ---------------------------------------------------------------- pull
@@ -151,15 +357,23 @@ __global__ void __launch_bounds__(BLOCK) k_pull(GraphDev g, RunDev R) {
     if (C->converged || C->mode != MODE_PULL) return;
     constexpr int K = PullShape<W>::K;
     constexpr int EDGES = PullShape<W>::EDGES;
+    constexpr int ITEMS = PullShape<W>::ITEMS;
     __shared__ int32_t s_col[EDGES];
     __shared__ int32_t s_rp[TILE_NODES + 1];
     __shared__ unsigned long long s_acc[TILE_NODES * W];
-    __shared__ int s_last;
+    __shared__ unsigned long long s_red[BLOCK / 64];
     const int r = C->round;
-    const int p = r & 1;
+    const int cur = C->cur;
+    const uint64_t *__restrict__ sig = R.sig[cur];
+    uint64_t *__restrict__ nxt = R.sig[cur ^ 1];
     const int tid = threadIdx.x;
     const int ln = lane_id();
-    int64_t arcs_done = 0;
+    const bool per_seed = R.seed_counts != nullptr;
+    uint64_t pop = 0;
+    int64_t nodes = 0, parcs = 0, pulled = 0;
+    uint32_t sc[W];
+#pragma unroll
+    for (int k = 0; k < W; ++k) sc[k] = 0;
 
     for (int t = blockIdx.x; t < g.ntiles; t += gridDim.x) {
         const Tile T = g.tiles[t];
@@ -167,14 +381,35 @@ __global__ void __launch_bounds__(BLOCK) k_pull(GraphDev g, RunDev R) {
         const int nn = T.u1 - T.u0;
         const int ne = (int)(T.e1 - T.e0);
         const bool hub = T.hub >= 0;
-        for (int i = tid; i <= nn; i += BLOCK)
-            s_rp[i] = hub ? (i == 0 ? 0 : ne) : (int)(g.rp[T.u0 + i] - T.e0);
-        for (int i = tid; i < ne; i += BLOCK) s_col[i] = g.col[T.e0 + i];
+        // stage the tile: every load issued before the first wait
+        int32_t cv[K];
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            const int i = tid + j * BLOCK;
+            cv[j] = i < ne ? g.col[T.e0 + i] : 0;
+        }
+        int32_t rv0 = 0, rv1 = 0;
+        if (hub) {
+            rv0 = tid == 0 ? 0 : ne;
+        } else {
+            if (tid <= nn) rv0 = (int)(g.rp[T.u0 + tid] - T.e0);
+            if (tid + BLOCK <= nn) rv1 = (int)(g.rp[T.u0 + tid + BLOCK] - T.e0);
+        }
+        uint64_t own[ITEMS];
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j) {
+            const int idx = tid + j * BLOCK;
+            own[j] = (!hub && idx < nn * W) ? sig[(int64_t)T.u0 * W + idx] : 0;
+        }
+#pragma unroll
+        for (int j = 0; j < K; ++j) s_col[tid + j * BLOCK] = cv[j];
+        if (tid <= nn) s_rp[tid] = rv0;
+        if (tid + BLOCK <= nn) s_rp[tid + BLOCK] = rv1;
         for (int i = tid; i < nn * W; i += BLOCK) s_acc[i] = 0ull;
         __syncthreads();
 
-        // gather: thread tid ORs the rows of arcs [a, a+K) into its running
-        // accumulator and flushes it to the LDS row of each node it leaves
+        // gather: thread tid ORs the rows of arcs [a, a+K) into a running
+        // accumulator and flushes it into the LDS row of each node it leaves
         const int a = tid * K;
         if (a < ne) {
             const int b = min(a + K, ne);
@@ -188,7 +423,7 @@ __global__ void __launch_bounds__(BLOCK) k_pull(GraphDev g, RunDev R) {
 #pragma unroll
             for (int j = 0; j < K; ++j) {
                 if (a + j < b) {
-                    load_row<W>(R.sig + (int64_t)s_col[a + j] * W, rows[j]);
+                    load_row<W>(sig + (int64_t)s_col[a + j] * W, rows[j]);
                 } else {
 #pragma unroll
                     for (int w = 0; w < W; ++w) rows[j][w] = 0;
@@ -197,15 +432,15 @@ __global__ void __launch_bounds__(BLOCK) k_pull(GraphDev g, RunDev R) {
             uint64_t acc[W];
 #pragma unroll
             for (int w = 0; w < W; ++w) acc[w] = 0;
-            int nxt = s_rp[i + 1];
+            int nx = s_rp[i + 1];
 #pragma unroll
             for (int j = 0; j < K; ++j) {
                 const int e = a + j;
                 if (e < b) {
-                    while (e >= nxt) {
+                    while (e >= nx) {
                         flush_lds<W>(s_acc + i * W, acc);
                         ++i;
-                        nxt = s_rp[i + 1];
+                        nx = s_rp[i + 1];
                     }
 #pragma unroll
                     for (int w = 0; w < W; ++w) acc[w] |= rows[j][w];
@@ -213,157 +448,101 @@ __global__ void __launch_bounds__(BLOCK) k_pull(GraphDev g, RunDev R) {
             }
             flush_lds<W>(s_acc + i * W, acc);
         }
-        arcs_done += ne;
+        pulled += ne;
         __syncthreads();
 
-        bool finalize = true;
         if (hub) {
-            // combine the chunks of a high-degree node; the last one finishes it
-            if (tid < W && s_acc[tid]) atomicOr((unsigned long long *)&R.hub_acc[(int64_t)T.hub * W + tid], s_acc[tid]);
-            __threadfence();
-            __syncthreads();
-            if (tid == 0) {
-                const uint32_t prev = atomicAdd(&R.hub_done[T.hub], 1u);
-                s_last = (int)(prev + 1 == (uint32_t)g.hub_nchunks[T.hub]);
-            }
-            __syncthreads();
-            finalize = s_last != 0;
-            if (finalize) {
-                __threadfence();
-                if (tid < W) s_acc[tid] = atomicExch((unsigned long long *)&R.hub_acc[(int64_t)T.hub * W + tid], 0ull);
-                if (tid == 0) atomicExch(&R.hub_done[T.hub], 0u);
-                __syncthreads();
-            }
-        }
-        if (finalize) {
-            for (int idx0 = 0; idx0 < nn * W; idx0 += BLOCK) {   // same trip count for all lanes
-                const int idx = idx0 + tid;
+            // a chunk of a high-degree node: combined by k_pull_hubs
+            if (tid < W && s_acc[tid]) atomicOr((unsigned long long *)&R.acc[(int64_t)T.u0 * W + tid], s_acc[tid]);
+        } else {
+            uint64_t tpop = 0;
+#pragma unroll
+            for (int j = 0; j < ITEMS; ++j) {   // same trip count for every lane
+                const int idx = tid + j * BLOCK;
                 const bool valid = idx < nn * W;
                 uint64_t nw = 0;
-                int32_t u = 0;
+                const int32_t u = T.u0 + idx / W;
                 if (valid) {
-                    u = T.u0 + idx / W;
                     const uint64_t av = s_acc[idx];
-                    if (av) nw = av & ~R.sig[(int64_t)u * W + (idx & (W - 1))];
+                    nw = av & ~own[j];
+                    nxt[(int64_t)T.u0 * W + idx] = own[j] | av;
                 }
+                tpop += (uint64_t)__popcll(nw);
                 const uint64_t bal = __ballot(nw != 0);
                 const int gb = ln & ~(W - 1);
-                const bool changed = valid && ((bal >> gb) & WordMask<W>::row) != 0;
-                const bool leader = changed && ((ln & (W - 1)) == 0);
-                int pos = wave_append(&C->f_count[p], leader);
-                pos = __shfl(pos, gb);
-                if (changed) {
-                    if (leader) R.f_ids[p][pos] = u;
-                    R.f_delta[p][(int64_t)pos * W + (ln & (W - 1))] = nw;
+                const bool lead = valid && (ln & (W - 1)) == 0 && ((bal >> gb) & WordMask<W>::row) != 0;
+                if (lead) {
+                    nodes += 1;
+                    parcs += g.trp[u + 1] - g.trp[u];
                 }
+                if (per_seed) {
+                    if (R.G == 1) seed_ballot<W>(nw, sc);
+                    else if (valid) seed_bits(R, r, T.graph, idx & (W - 1), nw);
+                }
+            }
+            if (R.G == 1) {
+                pop += tpop;
+            } else {
+                const unsigned long long tt = block_sum<unsigned long long>(tpop, s_red);
+                if (tid == 0 && tt) atomicAdd((unsigned long long *)&R.counts[(int64_t)r * R.G + T.graph], tt);
             }
         }
         __syncthreads();
     }
-    if (tid == 0 && arcs_done) atomicAdd((unsigned long long *)&C->pull_arcs, (unsigned long long)arcs_done);
-}
-
-// ---------------------------------------------------------------- push
-
-template <int W>
-__global__ void __launch_bounds__(BLOCK) k_push(GraphDev g, RunDev R) {
-    Ctrl *C = R.ctrl;
-    if (C->converged || C->mode != MODE_PUSH) return;
-    constexpr int P = 4;            // slots per chunk
-    constexpr int L = W * P;        // lanes per chunk
-    constexpr int GPW = 64 / L;     // chunks per wave
-    const int r = C->round;
-    const int pp = (r - 1) & 1, pn = r & 1;
-    const int32_t nch = C->ch_count[pp];
-    const Chunk *ch = R.chunks[pp];
-    const int32_t *ids = R.f_ids[pp];
-    const uint64_t *dl = R.f_delta[pp];
-    const int ln = lane_id();
-    const int grp = ln / L, sub = ln % L, w = sub % W, slot = sub / W;
-    const int64_t wave = (blockIdx.x * (int64_t)BLOCK + threadIdx.x) >> 6;
-    const int64_t nwaves = ((int64_t)gridDim.x * BLOCK) >> 6;
-    for (int64_t c0 = wave * GPW; c0 < nch; c0 += nwaves * GPW) {   // wave-uniform loop
-        const int64_t c = c0 + grp;
-        const bool cv = c < nch;
-        int64_t b = 0, end = 0;
-        uint64_t d = 0;
-        if (cv) {
-            const Chunk cd = ch[c];
-            const int32_t v = ids[cd.entry];
-            d = dl[(int64_t)cd.entry * W + w];
-            b = g.trp[v] + cd.off;
-            const int64_t lim = g.trp[v + 1];
-            end = (b + PUSH_CHUNK < lim) ? b + PUSH_CHUNK : lim;
-        }
-#pragma unroll
-        for (int it = 0; it < PUSH_CHUNK / P; ++it) {
-            const int64_t k = b + slot + it * P;
-            const bool kv = cv && k < end;
-            int32_t u = 0;
-            uint64_t nb = 0;
-            if (kv) {
-                u = g.tcol[k];
-                if (d) {
-                    const uint64_t old = atomicOr((unsigned long long *)&R.sig[(int64_t)u * W + w], (unsigned long long)d);
-                    nb = d & ~old;
-                    if (nb) atomicOr((unsigned long long *)&R.acc[(int64_t)u * W + w], (unsigned long long)nb);
-                }
-            }
-            const uint64_t bal = __ballot(nb != 0);
-            const int gb = ln & ~(W - 1);
-            const bool any = kv && ((bal >> gb) & WordMask<W>::row) != 0;
-            bool want = false;
-            if (any && (ln & (W - 1)) == 0) want = atomicMax(&R.stamp[u], r) < r;
-            const int pos = wave_append(&C->f_count[pn], want);
-            if (want) R.f_ids[pn][pos] = u;
-        }
+    const unsigned long long tp = block_sum<unsigned long long>(pop, s_red);
+    const unsigned long long tn = block_sum<unsigned long long>((unsigned long long)nodes, s_red);
+    const unsigned long long ta = block_sum<unsigned long long>((unsigned long long)parcs, s_red);
+    if (tid == 0) {
+        R.blk_cnt[blockIdx.x] = (int64_t)tp;
+        R.blk_nodes[blockIdx.x] = (int64_t)tn;
+        R.blk_arcs[blockIdx.x] = (int64_t)ta;
+        R.blk_pulled[blockIdx.x] = pulled;
     }
+    if (per_seed && R.G == 1) seed_flush<W>(R, r, sc);
 }
 
-// ---------------------------------------------------------------- commit
-
+// High-degree nodes of a pull round: the chunks left their ORed rows in the
+// accumulator.
 template <int W>
-__global__ void __launch_bounds__(BLOCK) k_commit(GraphDev g, RunDev R, int init) {
+__global__ void __launch_bounds__(BLOCK) k_pull_hubs(GraphDev g, RunDev R) {
     Ctrl *C = R.ctrl;
-    if (C->converged) return;
-    const int r = init ? 0 : C->round;
-    const int p = r & 1;
-    const int mode = init ? MODE_INIT : C->mode;
-    const int32_t cnt = C->f_count[p];
-    const int64_t items = (int64_t)cnt * W;
-    int32_t *ids = R.f_ids[p];
-    uint64_t *dl = R.f_delta[p];
-    Chunk *chunks = R.chunks[p];
+    if (C->converged || C->mode != MODE_PULL || g.nhubs == 0) return;
+    const int r = C->round;
+    const int cur = C->cur;
+    const uint64_t *sig = R.sig[cur];
+    uint64_t *nxt = R.sig[cur ^ 1];
     const int ln = lane_id();
     const int w = ln & (W - 1);
     const bool per_seed = R.seed_counts != nullptr;
     uint64_t pop = 0;
-    int64_t arcs = 0;
+    int64_t nodes = 0, parcs = 0;
     uint32_t sc[W];
 #pragma unroll
     for (int k = 0; k < W; ++k) sc[k] = 0;
+    const int64_t items = (int64_t)g.nhubs * W;
     const int64_t stride = (int64_t)gridDim.x * BLOCK;
     for (int64_t base = blockIdx.x * (int64_t)BLOCK + (threadIdx.x & ~63); base < items; base += stride) {
         const int64_t idx = base + ln;
         const bool valid = idx < items;
-        const int64_t e = idx / W;
-        uint64_t d = 0;
+        uint64_t nw = 0;
         int32_t u = 0;
         if (valid) {
-            u = ids[e];
-            uint64_t *sp = R.sig + (int64_t)u * W + w;
-            if (mode == MODE_PULL) {
-                d = dl[idx];
-                *sp |= d;
-            } else {
-                uint64_t *ap = R.acc + (int64_t)u * W + w;
-                d = *ap;
-                *ap = 0;
-                dl[idx] = d;
-                if (mode == MODE_INIT) *sp |= d;
-            }
+            u = g.hub_node[idx / W];
+            const int64_t o = (int64_t)u * W + w;
+            const uint64_t av = R.acc[o];
+            R.acc[o] = 0;
+            const uint64_t ow = sig[o];
+            nw = av & ~ow;
+            nxt[o] = ow | av;
         }
-        const int pc = __popcll(d);
+        const uint64_t bal = __ballot(nw != 0);
+        const int gb = ln & ~(W - 1);
+        const bool lead = valid && w == 0 && ((bal >> gb) & WordMask<W>::row) != 0;
+        if (lead) {
+            nodes += 1;
+            parcs += g.trp[u + 1] - g.trp[u];
+        }
+        const int pc = __popcll(nw);
         int gi = 0;
         if (R.G == 1) {
             pop += (uint64_t)pc;
@@ -371,96 +550,255 @@ __global__ void __launch_bounds__(BLOCK) k_commit(GraphDev g, RunDev R, int init
             gi = g.node_graph[u];
             if (pc) atomicAdd((unsigned long long *)&R.counts[(int64_t)r * R.G + gi], (unsigned long long)pc);
         }
-        // push chunks of this entry for round r+1 (one slot block per wave)
-        int nchk = 0;
-        if (valid && w == 0) {
-            const int64_t deg = g.trp[u + 1] - g.trp[u];
-            nchk = (int)((deg + PUSH_CHUNK - 1) / PUSH_CHUNK);
-            arcs += deg;
-        }
-        const int incl = wave_inclusive_scan(nchk);
-        const int total = __shfl(incl, 63);
-        if (total) {
-            int cbase = 0;
-            if (ln == 0) cbase = atomicAdd(&C->ch_count[p], total);
-            cbase = __shfl(cbase, 0);
-            const int first = cbase + incl - nchk;
-            for (int j = 0; j < nchk; ++j) chunks[first + j] = Chunk{(int32_t)e, j * PUSH_CHUNK};
-        }
         if (per_seed) {
-            if (R.G == 1) {
-                if (__ballot(d != 0)) {
-                    for (int bit = 0; bit < 64; ++bit) {
-                        const uint64_t m = __ballot((int)((d >> bit) & 1ull));
-                        if (m) {
-#pragma unroll
-                            for (int k = 0; k < W; ++k) {
-                                const uint32_t c = (uint32_t)__popcll(m & (WordMask<W>::rep << k));
-                                if (ln == bit) sc[k] += c;
-                            }
-                        }
-                    }
-                }
-            } else if (valid) {
-                uint64_t x = d;
-                while (x) {
-                    const int bit = __ffsll((long long)x) - 1;
-                    x &= x - 1;
-                    atomicAdd(&R.seed_counts[((int64_t)r * R.G + gi) * R.s + w * 64 + bit], 1u);
-                }
-            }
+            if (R.G == 1) seed_ballot<W>(nw, sc);
+            else if (valid) seed_bits(R, r, gi, w, nw);
         }
     }
-    __shared__ unsigned long long s_red[2][BLOCK / 64];
-    pop = wave_sum(pop);
-    uint64_t ua = wave_sum((uint64_t)arcs);
-    const int wv = threadIdx.x >> 6;
-    if (ln == 0) {
-        s_red[0][wv] = pop;
-        s_red[1][wv] = ua;
-    }
-    __syncthreads();
+    __shared__ unsigned long long s_red[BLOCK / 64];
+    const unsigned long long tp = block_sum<unsigned long long>(pop, s_red);
+    const unsigned long long tn = block_sum<unsigned long long>((unsigned long long)nodes, s_red);
+    const unsigned long long ta = block_sum<unsigned long long>((unsigned long long)parcs, s_red);
     if (threadIdx.x == 0) {
-        unsigned long long tp = 0, ta = 0;
-        for (int k = 0; k < BLOCK / 64; ++k) {
-            tp += s_red[0][k];
-            ta += s_red[1][k];
+        if (tp) atomicAdd((unsigned long long *)&C->hub_cnt, tp);
+        if (tn) atomicAdd((unsigned long long *)&C->hub_nodes, tn);
+        if (ta) atomicAdd((unsigned long long *)&C->hub_arcs, ta);
+    }
+    if (per_seed && R.G == 1) seed_flush<W>(R, r, sc);
+}
+
+// ---------------------------------------------------------------- push
+
+// After a pull round the frontier is not listed; this lists the nodes that
+// changed in round r-1 (Sig_{r-1} and Sig_{r-2} are the two buffers) with
+// their new bits, into list (r-1)&1.  Each block owns a contiguous node range:
+// a first pass counts its entries and push chunks, one atomic per block
+// reserves their slots, a second pass writes them in node order.
+template <int W>
+__global__ void __launch_bounds__(BLOCK) k_frontier(GraphDev g, RunDev R) {
+    Ctrl *C = R.ctrl;
+    if (C->converged || C->mode != MODE_PUSH || C->prev_mode != MODE_PULL) return;
+    constexpr int NPI = BLOCK / W;   // nodes per block iteration
+    const int r = C->round;
+    const int p = (r - 1) & 1;
+    const int cur = C->cur;
+    const uint64_t *now = R.sig[cur];
+    const uint64_t *old = R.sig[cur ^ 1];
+    const int ln = lane_id();
+    const int w = ln & (W - 1);
+    const int gb = ln & ~(W - 1);
+    const int64_t per = ((g.n + gridDim.x - 1) / gridDim.x + NPI - 1) / NPI * NPI;
+    const int64_t u_begin = (int64_t)blockIdx.x * per;
+    const int64_t u_end = u_begin + per < g.n ? u_begin + per : g.n;
+    __shared__ int s_scan[BLOCK / 64];
+    __shared__ unsigned long long s_red[BLOCK / 64];
+    __shared__ int s_nbase, s_cbase;
+
+    int nodes = 0, nchunks = 0;
+    int64_t arcs = 0;
+    for (int64_t ub = u_begin; ub < u_end; ub += NPI) {   // block-uniform
+        const int64_t u = ub + threadIdx.x / W;
+        const bool valid = u < u_end;
+        const int64_t idx = u * W + w;
+        const uint64_t d = valid ? (now[idx] & ~old[idx]) : 0;
+        const uint64_t bal = __ballot(d != 0);
+        const bool lead = valid && w == 0 && ((bal >> gb) & WordMask<W>::row) != 0;
+        if (lead) {
+            const int64_t deg = g.trp[u + 1] - g.trp[u];
+            nodes += 1;
+            arcs += deg;
+            nchunks += chunks_for<W>(deg);
         }
-        if (R.G == 1 && tp) atomicAdd((unsigned long long *)&R.counts[r], tp);
+    }
+    int tn = 0, tc = 0;
+    (void)block_scan(nodes, s_scan, tn);
+    (void)block_scan(nchunks, s_scan, tc);
+    const unsigned long long ta = block_sum<unsigned long long>((unsigned long long)arcs, s_red);
+    if (threadIdx.x == 0) {
+        s_nbase = tn ? atomicAdd(&C->f_count[p], tn) : 0;
+        s_cbase = tc ? atomicAdd(&C->ch_count[p], tc) : 0;
         if (ta) atomicAdd((unsigned long long *)&C->f_arcs[p], ta);
     }
-    if (per_seed && R.G == 1) {
+    __syncthreads();
+    if (tn == 0) return;   // same for the whole block
+    int nrun = s_nbase, crun = s_cbase;
+    for (int64_t ub = u_begin; ub < u_end; ub += NPI) {   // block-uniform
+        const int64_t u = ub + threadIdx.x / W;
+        const bool valid = u < u_end;
+        const int64_t idx = u * W + w;
+        const uint64_t d = valid ? (now[idx] & ~old[idx]) : 0;
+        const uint64_t bal = __ballot(d != 0);
+        const bool changed = valid && ((bal >> gb) & WordMask<W>::row) != 0;
+        const bool lead = changed && w == 0;
+        int64_t deg = 0;
+        if (lead) deg = g.trp[u + 1] - g.trp[u];
+        const int nchk = lead ? chunks_for<W>(deg) : 0;
+        int it_nodes = 0, it_chunks = 0;
+        int pos = nrun + block_scan(lead ? 1 : 0, s_scan, it_nodes);
+        const int cfirst = crun + block_scan(nchk, s_scan, it_chunks);
+        pos = __shfl(pos, gb);
+        if (changed) {
+            if (lead) R.f_ids[p][pos] = (int32_t)u;
+            R.f_delta[p][(int64_t)pos * W + w] = d;
+        }
+        for (int j = 0; j < nchk; ++j) R.chunks[p][cfirst + j] = Chunk{pos, j * PushShape<W>::CHUNK};
+        nrun += it_nodes;
+        crun += it_chunks;
+    }
+}
+
+// Pushes the new bits d of one frontier entry to up to IT predecessors per
+// lane (the W lanes of a slot share the predecessor and hold its words).  All
+// predecessor ids are loaded, then all atomic ORs issued, before any result is
+// used; a bit is new when the atomic that set it saw it clear.  Predecessors
+// that gained a bit are queued once per round (stamp).
+template <int W, int IT>
+PP_DEV void push_slots(const RunDev &R, uint64_t *sig, int r, const int64_t (&k)[IT], const bool (&kv)[IT],
+                       const int32_t *tcol, int w, uint64_t d, BlockQueue &bq, Ctrl *C, int pn) {
+    int32_t u[IT];
 #pragma unroll
-        for (int k = 0; k < W; ++k) {
-            const int bitidx = k * 64 + ln;
-            if (sc[k] && bitidx < R.s) atomicAdd(&R.seed_counts[(int64_t)r * R.s + bitidx], sc[k]);
+    for (int it = 0; it < IT; ++it) u[it] = kv[it] ? tcol[k[it]] : 0;
+    uint64_t nb[IT];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        nb[it] = 0;
+        if (kv[it] && d) {
+            const uint64_t oldv = atomicOr((unsigned long long *)&sig[(int64_t)u[it] * W + w], (unsigned long long)d);
+            nb[it] = d & ~oldv;
         }
     }
+    const int ln = lane_id();
+    const int gb = ln & ~(W - 1);
+    bool want[IT];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        if (nb[it]) atomicOr((unsigned long long *)&R.acc[(int64_t)u[it] * W + w], (unsigned long long)nb[it]);
+        const uint64_t bal = __ballot(nb[it] != 0);
+        const bool any = kv[it] && ((bal >> gb) & WordMask<W>::row) != 0;
+        want[it] = any && w == 0 && atomicMax(&R.stamp[u[it]], r) < r;
+    }
+#pragma unroll
+    for (int it = 0; it < IT; ++it) bq.push(want[it], u[it], &C->f_count[pn], R.f_ids[pn]);
+}
+
+template <int W>
+__global__ void __launch_bounds__(BLOCK) k_push(GraphDev g, RunDev R) {
+    Ctrl *C = R.ctrl;
+    if (C->converged || C->mode != MODE_PUSH) return;
+    const int r = C->round;
+    const int pp = (r - 1) & 1, pn = r & 1;
+    uint64_t *sig = R.sig[C->cur];
+    const int32_t cnt = C->f_count[pp];
+    const int32_t nch = C->ch_count[pp];
+    const int32_t *ids = R.f_ids[pp];
+    const uint64_t *dl = R.f_delta[pp];
+    const int ln = lane_id();
+    const int w = ln & (W - 1);
+    const int64_t wave = (blockIdx.x * (int64_t)BLOCK + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * BLOCK) >> 6;
+    __shared__ int32_t s_q[BlockQueue::CAP];
+    __shared__ int s_qn, s_qbase;
+    BlockQueue bq{s_q, &s_qn};
+    if (threadIdx.x == 0) s_qn = 0;
+    __syncthreads();
+
+    // light entries: PUSH_SLOTS slots of W lanes each walk the whole list
+    {
+        constexpr int L = W * PUSH_SLOTS;
+        constexpr int GPW = 64 / L;
+        constexpr int IT = PUSH_LIGHT / PUSH_SLOTS;
+        const int grp = ln / L, slot = (ln % L) / W;
+        for (int64_t e0 = wave * GPW; e0 < cnt; e0 += nwaves * GPW) {   // wave-uniform
+            const int64_t e = e0 + grp;
+            bool ev = e < cnt;
+            int64_t b = 0, end = 0;
+            uint64_t d = 0;
+            if (ev) {
+                const int32_t v = ids[e];
+                b = g.trp[v];
+                end = g.trp[v + 1];
+                ev = end - b <= PUSH_LIGHT;
+                d = dl[e * W + w];
+            }
+            int64_t k[IT];
+            bool kv[IT];
+#pragma unroll
+            for (int it = 0; it < IT; ++it) {
+                k[it] = b + slot + it * PUSH_SLOTS;
+                kv[it] = ev && k[it] < end;
+            }
+            push_slots<W, IT>(R, sig, r, k, kv, g.tcol, w, d, bq, C, pn);
+        }
+    }
+    // long lists: chunks of CHUNK arcs, one wave each
+    {
+        constexpr int SL = PushShape<W>::SLOTS;
+        constexpr int CH = PushShape<W>::CHUNK;
+        constexpr int IT = CH / SL;
+        const int slot = ln / W;
+        for (int64_t c = wave; c < nch; c += nwaves) {   // wave-uniform
+            const Chunk cd = R.chunks[pp][c];
+            const int32_t v = ids[cd.entry];
+            const uint64_t d = dl[(int64_t)cd.entry * W + w];
+            const int64_t b = g.trp[v] + cd.off;
+            const int64_t lim = g.trp[v + 1];
+            const int64_t end = (b + CH < lim) ? b + CH : lim;
+            int64_t k[IT];
+            bool kv[IT];
+#pragma unroll
+            for (int it = 0; it < IT; ++it) {
+                k[it] = b + slot + it * SL;
+                kv[it] = k[it] < end;
+            }
+            push_slots<W, IT>(R, sig, r, k, kv, g.tcol, w, d, bq, C, pn);
+        }
+    }
+    bq.flush(&C->f_count[pn], R.f_ids[pn], &s_qbase);
 }
 
 // ---------------------------------------------------------------- round end
 
-PP_DEV int32_t schedule(const GraphDev &g, const RunDev &R, int32_t r, int32_t fcount, int64_t farcs) {
+PP_DEV int32_t schedule(const GraphDev &g, const RunDev &R, int32_t r, int64_t fnodes, int64_t farcs) {
     switch (R.sched) {
         case PP_SCHED_PULL: return MODE_PULL;
         case PP_SCHED_PUSH: return MODE_PUSH;
         case PP_SCHED_FUZZ:
             return (mix64(R.fuzz_seed + (uint64_t)r * 0x9E3779B97F4A7C15ull) >> 63) ? MODE_PUSH : MODE_PULL;
         default:
-            (void)fcount;
+            (void)fnodes;
             return (farcs * (int64_t)R.push_div < g.m) ? MODE_PUSH : MODE_PULL;
     }
 }
 
-__global__ void k_round_end(GraphDev g, RunDev R, int init) {
+__global__ void __launch_bounds__(BLOCK) k_round_end(GraphDev g, RunDev R, int init) {
     Ctrl *C = R.ctrl;
     if (C->converged) return;
     const int r = init ? 0 : C->round;
+    const int mode = init ? MODE_INIT : C->mode;
+    __shared__ long long s_red[BLOCK / 64];
     __shared__ int s_active;
+    long long fnodes = 0, farcs = 0, pulled = 0;
+    if (mode == MODE_PULL) {
+        long long c = 0, nn = 0, na = 0, np = 0;
+        for (int b = threadIdx.x; b < g.pull_grid; b += BLOCK) {
+            c += R.blk_cnt[b];
+            nn += R.blk_nodes[b];
+            na += R.blk_arcs[b];
+            np += R.blk_pulled[b];
+        }
+        c = block_sum<long long>(c, s_red);
+        fnodes = block_sum<long long>(nn, s_red) + C->hub_nodes;
+        farcs = block_sum<long long>(na, s_red) + C->hub_arcs;
+        pulled = block_sum<long long>(np, s_red);
+        if (R.G == 1 && threadIdx.x == 0) R.counts[r] = c + C->hub_cnt;
+    } else {
+        fnodes = C->f_count[r & 1];
+        farcs = C->f_arcs[r & 1];
+    }
     if (threadIdx.x == 0) s_active = 0;
     __syncthreads();
     int act = 0;
-    for (int gi = threadIdx.x; gi < R.G; gi += blockDim.x) {
+    for (int gi = threadIdx.x; gi < R.G; gi += BLOCK) {
         if (R.gconv[gi]) continue;
         if (R.counts[(int64_t)r * R.G + gi] == 0) {
             R.gconv[gi] = 1;
@@ -472,10 +810,13 @@ __global__ void k_round_end(GraphDev g, RunDev R, int init) {
     if (act) atomicAdd(&s_active, act);
     __syncthreads();
     if (threadIdx.x == 0) {
-        const int mode = init ? MODE_INIT : C->mode;
         R.mode_log[r] = mode;
-        R.arcs_log[r] = init ? 0 : (mode == MODE_PULL ? C->pull_arcs : C->f_arcs[(r - 1) & 1]);
-        C->pull_arcs = 0;
+        R.arcs_log[r] = mode == MODE_PULL ? pulled : (mode == MODE_PUSH ? C->f_arcs[(r - 1) & 1] : 0);
+        if (mode == MODE_PULL) C->cur ^= 1;
+        C->prev_mode = mode;
+        C->hub_cnt = 0;
+        C->hub_nodes = 0;
+        C->hub_arcs = 0;
         C->active = s_active;
         if (s_active == 0) {
             C->converged = 1;
@@ -487,7 +828,7 @@ __global__ void k_round_end(GraphDev g, RunDev R, int init) {
             C->f_count[q] = 0;
             C->ch_count[q] = 0;
             C->f_arcs[q] = 0;
-            C->mode = schedule(g, R, nr, C->f_count[r & 1], C->f_arcs[r & 1]);
+            C->mode = schedule(g, R, nr, fnodes, farcs);
             C->round = nr;
         }
     }
@@ -495,24 +836,40 @@ __global__ void k_round_end(GraphDev g, RunDev R, int init) {
 
 // ---------------------------------------------------------------- launchers
 
-int pull_grid(const GraphDev &g) {
-    const int cap = 256 * 8;
-    return g.ntiles < 1 ? 1 : (g.ntiles < cap ? g.ntiles : cap);
+int pull_grid_for(int32_t ntiles) {
+    return ntiles < 1 ? 1 : (ntiles < PULL_GRID_MAX ? ntiles : PULL_GRID_MAX);
+}
+
+static int list_grid(const GraphDev &g) {
+    const int64_t b = (g.n + BLOCK - 1) / BLOCK;
+    return (int)(b < 64 ? 64 : (b > 1024 ? 1024 : b));
 }
 
 template <int W> static hipError_t seed_init_impl(const GraphDev &g, const RunDev &R, const int32_t *seeds, hipStream_t st) {
     const int64_t total = (int64_t)R.G * R.s;
-    hipLaunchKernelGGL(k_seed_scatter<W>, dim3(fill_grid(total)), dim3(BLOCK), 0, st, R, seeds, total);
-    hipLaunchKernelGGL(k_commit<W>, dim3(fill_grid(total * W)), dim3(BLOCK), 0, st, g, R, 1);
-    hipLaunchKernelGGL(k_round_end, dim3(1), dim3(256), 0, st, g, R, 1);
+    hipLaunchKernelGGL(k_seed_scatter<W>, dim3(fill_grid(total)), dim3(BLOCK), 0, st, g, R, seeds, total);
+    hipLaunchKernelGGL(k_push_commit<W>, dim3(fill_grid(total * W)), dim3(BLOCK), 0, st, g, R, 1);
+    hipLaunchKernelGGL(k_round_end, dim3(1), dim3(BLOCK), 0, st, g, R, 1);
     return hipGetLastError();
 }
 
-template <int W> static hipError_t round_impl(const GraphDev &g, const RunDev &R, hipStream_t st) {
-    hipLaunchKernelGGL(k_pull<W>, dim3(pull_grid(g)), dim3(BLOCK), 0, st, g, R);
-    hipLaunchKernelGGL(k_push<W>, dim3(1024), dim3(BLOCK), 0, st, g, R);
-    hipLaunchKernelGGL(k_commit<W>, dim3(1024), dim3(BLOCK), 0, st, g, R, 0);
-    hipLaunchKernelGGL(k_round_end, dim3(1), dim3(256), 0, st, g, R, 0);
+template <int W>
+static hipError_t round_impl(const GraphDev &g, const RunDev &R, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+    const int lg = list_grid(g);
+    hipLaunchKernelGGL(k_frontier<W>, dim3(lg), dim3(BLOCK), 0, st, g, R);
+    hipLaunchKernelGGL(k_push<W>, dim3(lg), dim3(BLOCK), 0, st, g, R);
+    hipLaunchKernelGGL(k_push_commit<W>, dim3(lg), dim3(BLOCK), 0, st, g, R, 0);
+    if (e0) {
+        const hipError_t e = hipEventRecord(e0, st);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_pull<W>, dim3(g.pull_grid), dim3(BLOCK), 0, st, g, R);
+    if (e1) {
+        const hipError_t e = hipEventRecord(e1, st);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_pull_hubs<W>, dim3(64), dim3(BLOCK), 0, st, g, R);
+    hipLaunchKernelGGL(k_round_end, dim3(1), dim3(BLOCK), 0, st, g, R, 0);
     return hipGetLastError();
 }
 
@@ -526,12 +883,12 @@ hipError_t launch_seed_init(const GraphDev &g, const RunDev &R, const int32_t *s
     }
 }
 
-hipError_t launch_round(const GraphDev &g, const RunDev &R, hipStream_t st) {
+hipError_t launch_round(const GraphDev &g, const RunDev &R, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
     switch (R.W) {
-        case 1: return round_impl<1>(g, R, st);
-        case 2: return round_impl<2>(g, R, st);
-        case 4: return round_impl<4>(g, R, st);
-        case 8: return round_impl<8>(g, R, st);
+        case 1: return round_impl<1>(g, R, st, e0, e1);
+        case 2: return round_impl<2>(g, R, st, e0, e1);
+        case 4: return round_impl<4>(g, R, st, e0, e1);
+        case 8: return round_impl<8>(g, R, st, e0, e1);
         default: return hipErrorInvalidValue;
     }
 }

@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_PKG, "libpp.so")
 PP_OK, PP_EINVAL, PP_ERANGE, PP_ENOMEM, PP_EDEVICE, PP_ENOTCONV, PP_ESTATE = 0, -1, -2, -3, -4, -5, -6
 PP_UNDIRECTED, PP_INPUT_ON_DEVICE, PP_TRANSPOSE = 1, 2, 4
 PP_SCHED_HEURISTIC, PP_SCHED_PULL, PP_SCHED_PUSH, PP_SCHED_FUZZ, PP_SCHED_MLP = 0, 1, 2, 3, 4
+MODE_PULL, MODE_PUSH, MODE_INIT = 0, 1, 2      # entries of the per-round mode log
 _NAMES = {0: "PP_OK", -1: "PP_EINVAL", -2: "PP_ERANGE", -3: "PP_ENOMEM", -4: "PP_EDEVICE",
           -5: "PP_ENOTCONV", -6: "PP_ESTATE"}
 
@@ -33,7 +34,7 @@ class PPError(RuntimeError):
 class Options(ctypes.Structure):
     _fields_ = [("scheduler", ctypes.c_int32), ("seed_counts", ctypes.c_int32), ("max_rounds", ctypes.c_int32),
                 ("rounds_per_sync", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("push_div", ctypes.c_int32),
-                ("fuzz_seed", ctypes.c_uint64)]
+                ("fuzz_seed", ctypes.c_uint64), ("time_kernels", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class Metrics(ctypes.Structure):
@@ -49,7 +50,8 @@ class Metrics(ctypes.Structure):
 EXPORTS = ["pp_options_default", "pp_csr_build", "pp_graph_arcs", "pp_graph_nodes", "pp_graph_count",
            "pp_seeds_init", "pp_propagate_round", "pp_propagate_until_converged", "pp_estimate_metrics",
            "pp_get_signatures", "pp_get_seed_counts", "pp_run_round", "pp_run_words", "pp_get_round_log",
-           "pp_run_snapshot", "pp_run_restore", "pp_run_free", "pp_graph_free", "pp_last_error"]
+           "pp_run_snapshot", "pp_run_restore", "pp_run_free", "pp_graph_free", "pp_last_error",
+           "pp_seeds_reset", "pp_get_kernel_times"]
 
 _lib = None
 
@@ -78,6 +80,8 @@ def lib():
         "pp_run_snapshot": (ctypes.c_int, [P, P]), "pp_run_restore": (ctypes.c_int, [P, P]),
         "pp_run_free": (None, [P]), "pp_graph_free": (None, [P]),
         "pp_last_error": (ctypes.c_char_p, []),
+        "pp_seeds_reset": (ctypes.c_int, [P, P, I32]),
+        "pp_get_kernel_times": (ctypes.c_int, [P, P, I32]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -109,7 +113,7 @@ def _is_device(a) -> bool:
 
 
 def options(scheduler=PP_SCHED_HEURISTIC, seed_counts=False, max_rounds=0, rounds_per_sync=0,
-            use_graph=True, push_div=0, fuzz_seed=0) -> Options:
+            use_graph=True, push_div=0, fuzz_seed=0, time_kernels=False) -> Options:
     o = Options()
     lib().pp_options_default(ctypes.byref(o))
     o.scheduler = scheduler
@@ -120,6 +124,7 @@ def options(scheduler=PP_SCHED_HEURISTIC, seed_counts=False, max_rounds=0, round
     if push_div:
         o.push_div = int(push_div)
     o.fuzz_seed = int(fuzz_seed)
+    o.time_kernels = int(bool(time_kernels))
     return o
 
 
@@ -225,6 +230,24 @@ def pp_seeds_init(graph: Graph, seeds, s=None, opts: Options | None = None, stre
     _check(lib().pp_seeds_init(graph.handle, _np_ptr(seeds.reshape(-1)), int(s), ctypes.byref(o),
                                _stream_ptr(stream), ctypes.byref(h)))
     return Run(h, graph, int(s), o)
+
+
+def pp_seeds_reset(run: Run, seeds):
+    """Re-run the initialisation on an existing run (no allocation).
+
+    ``seeds`` is a numpy int32 array (host) or an int32 device tensor.
+    """
+    if _is_device(seeds):
+        _check(lib().pp_seeds_reset(run.handle, ctypes.c_void_p(seeds.data_ptr()), 1))
+    else:
+        a = np.ascontiguousarray(seeds, dtype=np.int32).reshape(-1)
+        _check(lib().pp_seeds_reset(run.handle, _np_ptr(a), 0))
+
+
+def pp_get_kernel_times(run: Run, cap: int):
+    a = np.zeros(cap, dtype=np.float32)
+    _check(lib().pp_get_kernel_times(run.handle, _np_ptr(a), int(cap)))
+    return a
 
 
 def pp_propagate_round(run: Run):
