@@ -81,8 +81,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="rmat20")
     ap.add_argument("--scheduler", default="heuristic", choices=["heuristic", "pull", "push"])
+    ap.add_argument("--persistent", action="store_true",
+                    help="all rounds in one cooperative launch instead of launches per round")
     ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="first copy MIB MiB device-to-device with a plain torch copy, so that a "
+                         "hardware-counter run has a kernel of known traffic to scale against")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the propagation runs on a single MI355X and has no multi-GPU "
@@ -107,9 +112,19 @@ def main():
     log(f"[bench] csr_build {time.perf_counter() - t0:.1f} s: n={G.nodes} arcs={G.arcs}")
     dseeds = torch.from_numpy(seeds.astype(np.int32)).to("cuda")
     torch.cuda.synchronize()
-    run = pp.pp_seeds_init(G, seeds, opts=pp.options(scheduler=sched, max_rounds=4096, time_kernels=True),
+    run = pp.pp_seeds_init(G, seeds, opts=pp.options(scheduler=sched, max_rounds=4096, time_kernels=True,
+                                                     persistent=args.persistent),
                            stream=stream)
     W = run.words
+    if args.copy_calibration:
+        nb = args.copy_calibration << 20
+        a = torch.empty(nb // 4, dtype=torch.int32, device="cuda").fill_(1)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy of {nb} bytes read + {nb} bytes written")
+        del a, b
     s = len(seeds)
 
     def step():
@@ -148,7 +163,9 @@ def main():
     achieved = bytes_pull / t_pull / 1e9 if t_pull > 0 else 0.0
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-            "kernel": f"k_pull<{W}>", "launches_per_step": len(pull_rounds),
+            "kernel": f"k_rounds<{W}> pull phase" if args.persistent else f"k_pull<{W}>",
+            "timing": "device clock between grid barriers" if args.persistent else "HIP events around each launch",
+            "launches_per_step": len(pull_rounds),
             "avg_launch_ms": round(t_pull * 1000.0 / max(1, len(pull_rounds)), 4),
             "bytes_per_launch": round(bytes_pull / max(1, len(pull_rounds)))}
 
@@ -161,7 +178,7 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "u64", "data": "synthetic",
         "config": dict(cfg, nodes=n, arcs=m, words=W, rounds=rounds, diameter_lb=Dv,
-                       scheduler=args.scheduler,
+                       scheduler=args.scheduler, engine="persistent" if args.persistent else "rounds",
                        modes="".join("P" if modes[r] == pp.MODE_PULL else "S" for r in range(1, rounds + 1))),
         "touched_edge_words_per_s": touched * args.steps / elapsed,
         "roofline": roof,

@@ -84,7 +84,8 @@ typedef struct {
     int32_t push_div;           /* heuristic: push while frontier arcs * push_div < arcs (0: 8) */
     uint64_t fuzz_seed;         /* PP_SCHED_FUZZ stream */
     int32_t time_kernels;       /* 1: HIP events around every pull launch (pp_get_kernel_times) */
-    int32_t reserved;
+    int32_t persistent;         /* 1: all rounds in one cooperative launch (grid barriers
+                                   between phases) instead of launches per round */
 } pp_options;
 
 /* Metrics estimated from c[0..D] (paper Section 3 and Algorithm 1's closing
@@ -214,7 +215,10 @@ int pp_get_round_log(pp_run r, int32_t *mode, int64_t *arcs, int32_t cap);
  * pull launches (HIP events on the run's stream), summed over every
  * propagation since the run was created (pp_seeds_reset keeps the sums, so
  * a caller differences two reads around repeated runs).  A launch in a push
- * round returns at once and is still timed.  Host array of cap entries. */
+ * round returns at once and is still timed.  With opt.persistent the value
+ * is the main phase of round r (pull, or push for a push round) measured by
+ * the device clock between the grid barriers around it.  Host array of cap
+ * entries. */
 int pp_get_kernel_times(pp_run r, float *pull_ms, int32_t cap);
 
 /* Copy of a run's whole state (signatures, frontier, logs) / restore from a

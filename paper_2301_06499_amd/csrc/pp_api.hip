@@ -117,6 +117,8 @@ struct pp_run_s {
     bool graph_events = true;               // events recorded inside captured graphs work
     std::vector<hipEvent_t> ev;             // 2 per round slot of a batch
     std::vector<float> pull_ms;             // [cap]
+    int pgrid = 0;                          // blocks of the persistent round loop (0: not used)
+    double clock_khz = 100000.0;            // device wall clock rate
 };
 
 extern "C" {
@@ -443,6 +445,8 @@ void free_run_dev(RunDev &d) {
     dev_free(d.mode_log);
     dev_free(d.arcs_log);
     dev_free(d.ctrl);
+    dev_free(d.bar);
+    dev_free(d.phase_log);
 }
 
 void drop_graphs(pp_run r) {
@@ -483,7 +487,8 @@ int alloc_run_dev(pp_graph g, RunDev &d, int s, int W, int cap, bool seed_counts
         (rc = dev_alloc(&d.blk_cnt, pull_grid)) || (rc = dev_alloc(&d.blk_nodes, pull_grid)) ||
         (rc = dev_alloc(&d.blk_arcs, pull_grid)) || (rc = dev_alloc(&d.blk_pulled, pull_grid)) ||
         (rc = dev_alloc(&d.counts, (int64_t)cap * G)) || (rc = dev_alloc(&d.D, G)) || (rc = dev_alloc(&d.gconv, G)) ||
-        (rc = dev_alloc(&d.mode_log, cap)) || (rc = dev_alloc(&d.arcs_log, cap)) || (rc = dev_alloc(&d.ctrl, 1)))
+        (rc = dev_alloc(&d.mode_log, cap)) || (rc = dev_alloc(&d.arcs_log, cap)) || (rc = dev_alloc(&d.ctrl, 1)) ||
+        (rc = dev_alloc(&d.bar, 1)) || (rc = dev_alloc(&d.phase_log, (int64_t)cap * 3)))
         return rc;
     if (seed_counts && (rc = dev_alloc(&d.seed_counts, (int64_t)cap * G * s))) return rc;
     if (!seed_counts) d.seed_counts = nullptr;
@@ -503,6 +508,8 @@ hipError_t clear_run_dev(pp_graph g, RunDev &d, hipStream_t st) {
     if ((e = pp::launch_fill_i32(d.gconv, 0, d.G, st))) return e;
     if ((e = pp::launch_fill_i32(d.mode_log, -1, d.cap, st))) return e;
     if ((e = pp::launch_fill_u64((uint64_t *)d.arcs_log, 0, d.cap, st))) return e;
+    if ((e = pp::launch_fill_i32((int32_t *)d.bar, 0, (int64_t)(sizeof(pp::GridBar) / 4), st))) return e;
+    if ((e = pp::launch_fill_u64((uint64_t *)d.phase_log, 0, (int64_t)d.cap * 3, st))) return e;
     return pp::launch_fill_i32((int32_t *)d.ctrl, 0, (int64_t)(sizeof(Ctrl) / 4), st);
 }
 
@@ -574,6 +581,17 @@ extern "C" int pp_seeds_init(pp_graph g, const int32_t *seeds, int32_t s, const 
     r->G = G;
     r->opt = o;
     r->timing = o.time_kernels != 0;
+    if (o.persistent) {
+        r->pgrid = pp::persistent_grid(words_for(s));
+        if (r->pgrid < 1) {
+            delete r;
+            return fail(PP_EDEVICE, "no co-resident grid for the persistent round loop");
+        }
+        int dev = 0, khz = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) == hipSuccess && khz > 0)
+            r->clock_khz = khz;
+    }
     if (stream) {
         r->stream = (hipStream_t)stream;
     } else {
@@ -586,7 +604,8 @@ extern "C" int pp_seeds_init(pp_graph g, const int32_t *seeds, int32_t s, const 
     }
     TileSet *ts = nullptr;
     rc = ensure_tiles(g, W, &ts);
-    if (rc == PP_OK) rc = alloc_run_dev(g, r->dev, s, W, (int)cap, o.seed_counts != 0, pp::pull_grid_for(ts->ntiles));
+    if (rc == PP_OK)
+        rc = alloc_run_dev(g, r->dev, s, W, (int)cap, o.seed_counts != 0, std::max(pp::pull_grid_for(ts->ntiles), r->pgrid));
     if (rc == PP_OK) rc = dev_alloc(&r->dseeds, (int64_t)G * s);
     if (rc == PP_OK && r->timing) {
         r->pull_ms.assign((size_t)cap, 0.0f);
@@ -631,6 +650,36 @@ extern "C" int pp_seeds_reset(pp_run r, const int32_t *seeds, int32_t seeds_on_d
 }
 
 extern "C" void pp_run_free(pp_run r) { free_run(r); }
+
+namespace {
+
+// Rounds up to max_round in one cooperative launch; synchronises.  The
+// per-round device-clock stamps of the launch feed the kernel times.
+int run_persistent(pp_run r, int max_round) {
+    const int before = r->host_ctrl.round;
+    GraphDev gv = graph_view(r->g, run_tiles(r));
+    HIP_TRY(pp::launch_rounds_persistent(gv, r->dev, r->pgrid, max_round, r->stream));
+    int rc = sync_ctrl(r);
+    if (rc) return rc;
+    pp::GridBar bar;
+    HIP_TRY(hipMemcpy(&bar, r->dev.bar, sizeof(bar), hipMemcpyDeviceToHost));
+    if (bar.abort) return fail(PP_EDEVICE, "persistent round loop: a grid barrier timed out");
+    if (r->timing) {
+        const int last = std::min(r->host_ctrl.converged ? r->host_ctrl.round : r->host_ctrl.round - 1, r->cap - 1);
+        if (last >= before) {
+            std::vector<int64_t> st((size_t)(last - before + 1) * 3);
+            HIP_TRY(hipMemcpy(st.data(), r->dev.phase_log + (int64_t)before * 3, sizeof(int64_t) * st.size(),
+                              hipMemcpyDeviceToHost));
+            for (int k = before; k <= last; ++k) {
+                const int64_t *s = st.data() + (size_t)(k - before) * 3;
+                if (s[1] > s[0]) r->pull_ms[(size_t)k] += (float)((double)(s[1] - s[0]) / r->clock_khz);
+            }
+        }
+    }
+    return PP_OK;
+}
+
+}  // namespace
 extern "C" int32_t pp_run_round(pp_run r) { return r ? r->host_ctrl.round : -1; }
 extern "C" int32_t pp_run_words(pp_run r) { return r ? r->W : -1; }
 
@@ -643,6 +692,16 @@ extern "C" int pp_propagate_round(pp_run r, int64_t *new_bits, int32_t *all_conv
         return r->host_ctrl.overflow ? fail(PP_ENOTCONV, "round log full (max_rounds)") : PP_OK;
     }
     const int rr = r->host_ctrl.round;
+    if (r->pgrid) {
+        int rc = run_persistent(r, rr);
+        if (rc) return rc;
+        if (new_bits)
+            HIP_TRY(hipMemcpy(new_bits, r->dev.counts + (int64_t)rr * G, sizeof(int64_t) * (size_t)G,
+                              hipMemcpyDeviceToHost));
+        if (all_converged) *all_converged = r->host_ctrl.converged;
+        if (r->host_ctrl.overflow) return fail(PP_ENOTCONV, "round log full (max_rounds)");
+        return PP_OK;
+    }
     GraphDev gv = graph_view(r->g, run_tiles(r));
     hipEvent_t e0 = r->timing ? r->ev[0] : nullptr, e1 = r->timing ? r->ev[1] : nullptr;
     HIP_TRY(pp::launch_round(gv, r->dev, r->stream, e0, e1));
@@ -708,7 +767,11 @@ extern "C" int pp_propagate_until_converged(pp_run r, int32_t max_rounds, int64_
     const int G = r->G;
     const int limit = (max_rounds > 0 && max_rounds < r->cap - 1) ? max_rounds : r->cap - 1;
     int K = r->opt.rounds_per_sync > 0 ? r->opt.rounds_per_sync : 2;
-    while (!r->host_ctrl.converged && r->host_ctrl.round <= limit) {
+    if (r->pgrid && !r->host_ctrl.converged && r->host_ctrl.round <= limit) {
+        int rc = run_persistent(r, limit);
+        if (rc) return rc;
+    }
+    while (!r->pgrid && !r->host_ctrl.converged && r->host_ctrl.round <= limit) {
         const int left = limit - r->host_ctrl.round + 1;
         int k = std::min(K, left);
         // replayed batches come in powers of two so few graphs are captured
@@ -807,7 +870,10 @@ extern "C" int pp_run_snapshot(pp_run r, pp_run *copy) {
     }
     c->own_stream = true;
     TileSet *ts = run_tiles(r);
-    int rc = alloc_run_dev(r->g, c->dev, r->s, r->W, r->cap, r->dev.seed_counts != nullptr, pp::pull_grid_for(ts->ntiles));
+    c->pgrid = r->pgrid;
+    c->clock_khz = r->clock_khz;
+    int rc = alloc_run_dev(r->g, c->dev, r->s, r->W, r->cap, r->dev.seed_counts != nullptr,
+                           std::max(pp::pull_grid_for(ts->ntiles), r->pgrid));
     if (rc) {
         free_run(c);
         return rc;

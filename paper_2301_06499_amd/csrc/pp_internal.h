@@ -30,18 +30,32 @@ struct Chunk {
 };
 
 constexpr int BLOCK = 256;       // threads per block of every bulk kernel
-constexpr int TILE_NODES = 256;  // node budget of a pull tile
+constexpr int TILE_NODES = 64;   // node budget of a pull tile (one wave)
 constexpr int PUSH_SLOTS = 4;    // predecessor slots per frontier entry in a push
 constexpr int PUSH_LIGHT = 16;   // entries with more predecessors go through chunks
 constexpr int PUSH_CHUNK_MIN = 32;   // smallest chunk (W = 8)
-constexpr int PULL_GRID_MAX = 256 * 8;
+#ifndef PP_PULL_GRID_MAX
+#define PP_PULL_GRID_MAX 2048
+#endif
+constexpr int PULL_GRID_MAX = PP_PULL_GRID_MAX;
 
-// Arcs per thread in the pull gather and the tile arc budget, per signature
-// width W (words); items per thread in a tile's finalisation.
+#ifndef PP_PULL_K
+#define PP_PULL_K 4
+#endif
+#ifndef PP_PULL_K8
+#define PP_PULL_K8 4
+#endif
+#ifndef PP_STREAM_NT
+#define PP_STREAM_NT 0
+#endif
+
+// A pull tile is the work of one wave: arcs per lane in the gather (K), the
+// tile's arc budget (K per lane) and node budget (one row word per lane and
+// pass), per signature width W (words).
 template <int W> struct PullShape {
-    static constexpr int K = W >= 8 ? 4 : 8;
-    static constexpr int EDGES = K * BLOCK;
-    static constexpr int ITEMS = TILE_NODES * W / BLOCK;   // >= 1
+    static constexpr int K = W >= 8 ? PP_PULL_K8 : PP_PULL_K;
+    static constexpr int EDGES = K * 64;
+    static constexpr int NODES = 64;
 };
 
 // Device control block: the round counter and everything the per-round
@@ -63,6 +77,15 @@ struct Ctrl {
     int64_t hub_nodes;    // hubs that changed this round
     int64_t hub_arcs;     // their predecessor arcs
     int64_t pad;
+};
+
+// State of the grid barrier of the persistent round loop (zero at start).
+struct GridBar {
+    uint32_t grp[8];      // arrivals per block group
+    uint32_t top;         // groups complete
+    uint32_t gen;         // barrier generation
+    int32_t abort;        // a wait timed out: every block leaves
+    uint32_t pad[5];
 };
 
 struct GraphDev {
@@ -99,6 +122,8 @@ struct RunDev {
     int32_t *gconv;       // [G]
     int32_t *mode_log;    // [cap]
     int64_t *arcs_log;    // [cap]
+    int64_t *phase_log;   // [cap][3] device-clock stamps of the persistent loop
+    GridBar *bar;
     Ctrl *ctrl;
     // scheduler
     int32_t sched;
@@ -114,6 +139,10 @@ hipError_t launch_seed_init(const GraphDev &g, const RunDev &r, const int32_t *s
 // One round; when e0/e1 are given they are recorded around the pull launch.
 hipError_t launch_round(const GraphDev &g, const RunDev &r, hipStream_t st, hipEvent_t e0 = nullptr,
                         hipEvent_t e1 = nullptr);
+// Rounds up to max_round in one cooperative launch of `grid` blocks.
+hipError_t launch_rounds_persistent(const GraphDev &g, const RunDev &r, int grid, int max_round, hipStream_t st);
+// Largest co-resident grid for the persistent loop at width W.
+int persistent_grid(int W);
 int pull_grid_for(int32_t ntiles);
 
 }  // namespace pp

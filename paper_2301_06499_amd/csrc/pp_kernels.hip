@@ -33,6 +33,10 @@ namespace pp {
 
 #define PP_DEV __device__ __forceinline__
 
+// Reads of the control block: atomic loads, so they are never served from
+// the scalar cache, which a persistent launch would leave stale.
+#define CTL(x) __hip_atomic_load(&(x), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+
 PP_DEV int lane_id() { return __lane_id(); }
 
 template <int W> struct WordMask {
@@ -50,6 +54,24 @@ PP_DEV uint64_t mix64(uint64_t z) {
     z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
     z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
     return z ^ (z >> 31);
+}
+
+// Loads and stores of data read or written once per round (arc lists, the
+// node's own row, the new row): optionally marked non-temporal so they do not
+// displace the gathered successor rows from the caches.
+template <typename T> PP_DEV T stream_ld(const T *p) {
+#if PP_STREAM_NT
+    return __builtin_nontemporal_load(p);
+#else
+    return *p;
+#endif
+}
+template <typename T> PP_DEV void stream_st(T *p, T v) {
+#if PP_STREAM_NT
+    __builtin_nontemporal_store(v, p);
+#else
+    *p = v;
+#endif
 }
 
 template <typename T> PP_DEV T wave_sum(T v) {
@@ -271,13 +293,11 @@ __global__ void __launch_bounds__(BLOCK) k_seed_scatter(GraphDev g, RunDev R, co
 // for the next round.  Round 0 (init) also writes them into both signature
 // buffers; a push round has set them in Sig already.
 template <int W>
-__global__ void __launch_bounds__(BLOCK) k_push_commit(GraphDev g, RunDev R, int init) {
+PP_DEV void phase_push_commit(const GraphDev &g, const RunDev &R, int init) {
     Ctrl *C = R.ctrl;
-    if (C->converged) return;
-    if (!init && C->mode != MODE_PUSH) return;
-    const int r = init ? 0 : C->round;
+    const int r = init ? 0 : CTL(C->round);
     const int p = r & 1;
-    const int32_t cnt = C->f_count[p];
+    const int32_t cnt = CTL(C->f_count[p]);
     const int64_t items = (int64_t)cnt * W;
     const int32_t *ids = R.f_ids[p];
     uint64_t *dl = R.f_delta[p];
@@ -352,22 +372,27 @@ __global__ void __launch_bounds__(BLOCK) k_push_commit(GraphDev g, RunDev R, int
 // ---------------------------------------------------------------- pull
 
 template <int W>
-__global__ void __launch_bounds__(BLOCK) k_pull(GraphDev g, RunDev R) {
+PP_DEV void phase_pull(const GraphDev &g, const RunDev &R) {
     Ctrl *C = R.ctrl;
-    if (C->converged || C->mode != MODE_PULL) return;
-    constexpr int K = PullShape<W>::K;
-    constexpr int EDGES = PullShape<W>::EDGES;
-    constexpr int ITEMS = PullShape<W>::ITEMS;
-    __shared__ int32_t s_col[EDGES];
-    __shared__ int32_t s_rp[TILE_NODES + 1];
-    __shared__ unsigned long long s_acc[TILE_NODES * W];
+    using PS = PullShape<W>;
+    constexpr int K = PS::K;
+    constexpr int EDGES = PS::EDGES;
+    constexpr int NODES = PS::NODES;
+    constexpr int WAVES = BLOCK / 64;
+    // each wave stages its own tile: no block barrier inside the tile loop
+    __shared__ int32_t s_col[WAVES][EDGES];
+    __shared__ int32_t s_rp[WAVES][NODES + 1];
+    __shared__ unsigned long long s_acc[WAVES][NODES * W];
     __shared__ unsigned long long s_red[BLOCK / 64];
-    const int r = C->round;
-    const int cur = C->cur;
+    const int r = CTL(C->round);
+    const int cur = CTL(C->cur);
     const uint64_t *__restrict__ sig = R.sig[cur];
     uint64_t *__restrict__ nxt = R.sig[cur ^ 1];
-    const int tid = threadIdx.x;
     const int ln = lane_id();
+    const int wv = threadIdx.x >> 6;
+    int32_t *col_l = s_col[wv];
+    int32_t *rp_l = s_rp[wv];
+    unsigned long long *acc_l = s_acc[wv];
     const bool per_seed = R.seed_counts != nullptr;
     uint64_t pop = 0;
     int64_t nodes = 0, parcs = 0, pulled = 0;
@@ -375,9 +400,10 @@ __global__ void __launch_bounds__(BLOCK) k_pull(GraphDev g, RunDev R) {
 #pragma unroll
     for (int k = 0; k < W; ++k) sc[k] = 0;
 
-    for (int t = blockIdx.x; t < g.ntiles; t += gridDim.x) {
+    const int64_t nw = (int64_t)gridDim.x * WAVES;
+    for (int64_t t = (int64_t)blockIdx.x * WAVES + wv; t < g.ntiles; t += nw) {   // wave-uniform
         const Tile T = g.tiles[t];
-        if (R.G > 1 && R.gconv[T.graph]) continue;  // same for the whole block
+        if (R.G > 1 && R.gconv[T.graph]) continue;
         const int nn = T.u1 - T.u0;
         const int ne = (int)(T.e1 - T.e0);
         const bool hub = T.hub >= 0;
@@ -385,45 +411,45 @@ __global__ void __launch_bounds__(BLOCK) k_pull(GraphDev g, RunDev R) {
         int32_t cv[K];
 #pragma unroll
         for (int j = 0; j < K; ++j) {
-            const int i = tid + j * BLOCK;
-            cv[j] = i < ne ? g.col[T.e0 + i] : 0;
+            const int i = ln + j * 64;
+            cv[j] = i < ne ? stream_ld(g.col + T.e0 + i) : 0;
         }
         int32_t rv0 = 0, rv1 = 0;
         if (hub) {
-            rv0 = tid == 0 ? 0 : ne;
+            rv0 = ln == 0 ? 0 : ne;
         } else {
-            if (tid <= nn) rv0 = (int)(g.rp[T.u0 + tid] - T.e0);
-            if (tid + BLOCK <= nn) rv1 = (int)(g.rp[T.u0 + tid + BLOCK] - T.e0);
+            if (ln <= nn) rv0 = (int)(stream_ld(g.rp + T.u0 + ln) - T.e0);
+            if (ln == 0 && nn == NODES) rv1 = (int)(stream_ld(g.rp + T.u0 + NODES) - T.e0);
         }
-        uint64_t own[ITEMS];
+        uint64_t own[W];
 #pragma unroll
-        for (int j = 0; j < ITEMS; ++j) {
-            const int idx = tid + j * BLOCK;
-            own[j] = (!hub && idx < nn * W) ? sig[(int64_t)T.u0 * W + idx] : 0;
+        for (int j = 0; j < W; ++j) {
+            const int idx = ln + j * 64;
+            own[j] = (!hub && idx < nn * W) ? stream_ld(sig + (int64_t)T.u0 * W + idx) : 0;
         }
 #pragma unroll
-        for (int j = 0; j < K; ++j) s_col[tid + j * BLOCK] = cv[j];
-        if (tid <= nn) s_rp[tid] = rv0;
-        if (tid + BLOCK <= nn) s_rp[tid + BLOCK] = rv1;
-        for (int i = tid; i < nn * W; i += BLOCK) s_acc[i] = 0ull;
-        __syncthreads();
+        for (int j = 0; j < K; ++j) col_l[ln + j * 64] = cv[j];
+        if (ln <= nn) rp_l[ln] = rv0;
+        if (ln == 0 && nn == NODES) rp_l[NODES] = rv1;
+#pragma unroll
+        for (int j = 0; j < W; ++j) acc_l[ln + j * 64] = 0ull;
 
-        // gather: thread tid ORs the rows of arcs [a, a+K) into a running
+        // gather: lane ln ORs the rows of arcs [a, a+K) into a running
         // accumulator and flushes it into the LDS row of each node it leaves
-        const int a = tid * K;
+        const int a = ln * K;
         if (a < ne) {
             const int b = min(a + K, ne);
-            int lo = 0, hi = nn - 1;          // node i with s_rp[i] <= a < s_rp[i+1]
+            int lo = 0, hi = nn - 1;          // node i with rp[i] <= a < rp[i+1]
             while (lo < hi) {
                 const int mid = (lo + hi + 1) >> 1;
-                if (s_rp[mid] <= a) lo = mid; else hi = mid - 1;
+                if (rp_l[mid] <= a) lo = mid; else hi = mid - 1;
             }
             int i = lo;
             uint64_t rows[K][W];
 #pragma unroll
             for (int j = 0; j < K; ++j) {
                 if (a + j < b) {
-                    load_row<W>(sig + (int64_t)s_col[a + j] * W, rows[j]);
+                    load_row<W>(sig + (int64_t)col_l[a + j] * W, rows[j]);
                 } else {
 #pragma unroll
                     for (int w = 0; w < W; ++w) rows[j][w] = 0;
@@ -432,43 +458,42 @@ __global__ void __launch_bounds__(BLOCK) k_pull(GraphDev g, RunDev R) {
             uint64_t acc[W];
 #pragma unroll
             for (int w = 0; w < W; ++w) acc[w] = 0;
-            int nx = s_rp[i + 1];
+            int nx = rp_l[i + 1];
 #pragma unroll
             for (int j = 0; j < K; ++j) {
                 const int e = a + j;
                 if (e < b) {
                     while (e >= nx) {
-                        flush_lds<W>(s_acc + i * W, acc);
+                        flush_lds<W>(acc_l + i * W, acc);
                         ++i;
-                        nx = s_rp[i + 1];
+                        nx = rp_l[i + 1];
                     }
 #pragma unroll
                     for (int w = 0; w < W; ++w) acc[w] |= rows[j][w];
                 }
             }
-            flush_lds<W>(s_acc + i * W, acc);
+            flush_lds<W>(acc_l + i * W, acc);
         }
-        pulled += ne;
-        __syncthreads();
+        if (ln == 0) pulled += ne;
 
         if (hub) {
-            // a chunk of a high-degree node: combined by k_pull_hubs
-            if (tid < W && s_acc[tid]) atomicOr((unsigned long long *)&R.acc[(int64_t)T.u0 * W + tid], s_acc[tid]);
+            // a chunk of a high-degree node: combined by the hub phase
+            if (ln < W && acc_l[ln]) atomicOr((unsigned long long *)&R.acc[(int64_t)T.u0 * W + ln], acc_l[ln]);
         } else {
             uint64_t tpop = 0;
 #pragma unroll
-            for (int j = 0; j < ITEMS; ++j) {   // same trip count for every lane
-                const int idx = tid + j * BLOCK;
+            for (int j = 0; j < W; ++j) {   // same trip count for every lane
+                const int idx = ln + j * 64;
                 const bool valid = idx < nn * W;
-                uint64_t nw = 0;
+                uint64_t nw2 = 0;
                 const int32_t u = T.u0 + idx / W;
                 if (valid) {
-                    const uint64_t av = s_acc[idx];
-                    nw = av & ~own[j];
-                    nxt[(int64_t)T.u0 * W + idx] = own[j] | av;
+                    const uint64_t av = acc_l[idx];
+                    nw2 = av & ~own[j];
+                    stream_st(nxt + (int64_t)T.u0 * W + idx, own[j] | av);
                 }
-                tpop += (uint64_t)__popcll(nw);
-                const uint64_t bal = __ballot(nw != 0);
+                tpop += (uint64_t)__popcll(nw2);
+                const uint64_t bal = __ballot(nw2 != 0);
                 const int gb = ln & ~(W - 1);
                 const bool lead = valid && (ln & (W - 1)) == 0 && ((bal >> gb) & WordMask<W>::row) != 0;
                 if (lead) {
@@ -476,27 +501,27 @@ __global__ void __launch_bounds__(BLOCK) k_pull(GraphDev g, RunDev R) {
                     parcs += g.trp[u + 1] - g.trp[u];
                 }
                 if (per_seed) {
-                    if (R.G == 1) seed_ballot<W>(nw, sc);
-                    else if (valid) seed_bits(R, r, T.graph, idx & (W - 1), nw);
+                    if (R.G == 1) seed_ballot<W>(nw2, sc);
+                    else if (valid) seed_bits(R, r, T.graph, idx & (W - 1), nw2);
                 }
             }
             if (R.G == 1) {
                 pop += tpop;
             } else {
-                const unsigned long long tt = block_sum<unsigned long long>(tpop, s_red);
-                if (tid == 0 && tt) atomicAdd((unsigned long long *)&R.counts[(int64_t)r * R.G + T.graph], tt);
+                const uint64_t tt = wave_sum(tpop);
+                if (ln == 0 && tt) atomicAdd((unsigned long long *)&R.counts[(int64_t)r * R.G + T.graph], (unsigned long long)tt);
             }
         }
-        __syncthreads();
     }
     const unsigned long long tp = block_sum<unsigned long long>(pop, s_red);
     const unsigned long long tn = block_sum<unsigned long long>((unsigned long long)nodes, s_red);
     const unsigned long long ta = block_sum<unsigned long long>((unsigned long long)parcs, s_red);
-    if (tid == 0) {
+    const unsigned long long tq = block_sum<unsigned long long>((unsigned long long)pulled, s_red);
+    if (threadIdx.x == 0) {
         R.blk_cnt[blockIdx.x] = (int64_t)tp;
         R.blk_nodes[blockIdx.x] = (int64_t)tn;
         R.blk_arcs[blockIdx.x] = (int64_t)ta;
-        R.blk_pulled[blockIdx.x] = pulled;
+        R.blk_pulled[blockIdx.x] = (int64_t)tq;
     }
     if (per_seed && R.G == 1) seed_flush<W>(R, r, sc);
 }
@@ -504,11 +529,11 @@ __global__ void __launch_bounds__(BLOCK) k_pull(GraphDev g, RunDev R) {
 // High-degree nodes of a pull round: the chunks left their ORed rows in the
 // accumulator.
 template <int W>
-__global__ void __launch_bounds__(BLOCK) k_pull_hubs(GraphDev g, RunDev R) {
+PP_DEV void phase_pull_hubs(const GraphDev &g, const RunDev &R) {
     Ctrl *C = R.ctrl;
-    if (C->converged || C->mode != MODE_PULL || g.nhubs == 0) return;
-    const int r = C->round;
-    const int cur = C->cur;
+    if (g.nhubs == 0) return;
+    const int r = CTL(C->round);
+    const int cur = CTL(C->cur);
     const uint64_t *sig = R.sig[cur];
     uint64_t *nxt = R.sig[cur ^ 1];
     const int ln = lane_id();
@@ -575,13 +600,12 @@ __global__ void __launch_bounds__(BLOCK) k_pull_hubs(GraphDev g, RunDev R) {
 // a first pass counts its entries and push chunks, one atomic per block
 // reserves their slots, a second pass writes them in node order.
 template <int W>
-__global__ void __launch_bounds__(BLOCK) k_frontier(GraphDev g, RunDev R) {
+PP_DEV void phase_frontier(const GraphDev &g, const RunDev &R) {
     Ctrl *C = R.ctrl;
-    if (C->converged || C->mode != MODE_PUSH || C->prev_mode != MODE_PULL) return;
     constexpr int NPI = BLOCK / W;   // nodes per block iteration
-    const int r = C->round;
+    const int r = CTL(C->round);
     const int p = (r - 1) & 1;
-    const int cur = C->cur;
+    const int cur = CTL(C->cur);
     const uint64_t *now = R.sig[cur];
     const uint64_t *old = R.sig[cur ^ 1];
     const int ln = lane_id();
@@ -682,14 +706,13 @@ PP_DEV void push_slots(const RunDev &R, uint64_t *sig, int r, const int64_t (&k)
 }
 
 template <int W>
-__global__ void __launch_bounds__(BLOCK) k_push(GraphDev g, RunDev R) {
+PP_DEV void phase_push(const GraphDev &g, const RunDev &R) {
     Ctrl *C = R.ctrl;
-    if (C->converged || C->mode != MODE_PUSH) return;
-    const int r = C->round;
+    const int r = CTL(C->round);
     const int pp = (r - 1) & 1, pn = r & 1;
-    uint64_t *sig = R.sig[C->cur];
-    const int32_t cnt = C->f_count[pp];
-    const int32_t nch = C->ch_count[pp];
+    uint64_t *sig = R.sig[CTL(C->cur)];
+    const int32_t cnt = CTL(C->f_count[pp]);
+    const int32_t nch = CTL(C->ch_count[pp]);
     const int32_t *ids = R.f_ids[pp];
     const uint64_t *dl = R.f_delta[pp];
     const int ln = lane_id();
@@ -770,30 +793,30 @@ PP_DEV int32_t schedule(const GraphDev &g, const RunDev &R, int32_t r, int64_t f
     }
 }
 
-__global__ void __launch_bounds__(BLOCK) k_round_end(GraphDev g, RunDev R, int init) {
+// nparts: blocks of the pull that left per-block partials.
+PP_DEV void phase_round_end(const GraphDev &g, const RunDev &R, int init, int nparts) {
     Ctrl *C = R.ctrl;
-    if (C->converged) return;
-    const int r = init ? 0 : C->round;
-    const int mode = init ? MODE_INIT : C->mode;
+    const int r = init ? 0 : CTL(C->round);
+    const int mode = init ? MODE_INIT : CTL(C->mode);
     __shared__ long long s_red[BLOCK / 64];
     __shared__ int s_active;
     long long fnodes = 0, farcs = 0, pulled = 0;
     if (mode == MODE_PULL) {
         long long c = 0, nn = 0, na = 0, np = 0;
-        for (int b = threadIdx.x; b < g.pull_grid; b += BLOCK) {
+        for (int b = threadIdx.x; b < nparts; b += BLOCK) {
             c += R.blk_cnt[b];
             nn += R.blk_nodes[b];
             na += R.blk_arcs[b];
             np += R.blk_pulled[b];
         }
         c = block_sum<long long>(c, s_red);
-        fnodes = block_sum<long long>(nn, s_red) + C->hub_nodes;
-        farcs = block_sum<long long>(na, s_red) + C->hub_arcs;
+        fnodes = block_sum<long long>(nn, s_red) + CTL(C->hub_nodes);
+        farcs = block_sum<long long>(na, s_red) + CTL(C->hub_arcs);
         pulled = block_sum<long long>(np, s_red);
-        if (R.G == 1 && threadIdx.x == 0) R.counts[r] = c + C->hub_cnt;
+        if (R.G == 1 && threadIdx.x == 0) R.counts[r] = c + CTL(C->hub_cnt);
     } else {
-        fnodes = C->f_count[r & 1];
-        farcs = C->f_arcs[r & 1];
+        fnodes = CTL(C->f_count[r & 1]);
+        farcs = CTL(C->f_arcs[r & 1]);
     }
     if (threadIdx.x == 0) s_active = 0;
     __syncthreads();
@@ -811,7 +834,7 @@ __global__ void __launch_bounds__(BLOCK) k_round_end(GraphDev g, RunDev R, int i
     __syncthreads();
     if (threadIdx.x == 0) {
         R.mode_log[r] = mode;
-        R.arcs_log[r] = mode == MODE_PULL ? pulled : (mode == MODE_PUSH ? C->f_arcs[(r - 1) & 1] : 0);
+        R.arcs_log[r] = mode == MODE_PULL ? pulled : (mode == MODE_PUSH ? CTL(C->f_arcs[(r - 1) & 1]) : 0);
         if (mode == MODE_PULL) C->cur ^= 1;
         C->prev_mode = mode;
         C->hub_cnt = 0;
@@ -834,10 +857,132 @@ __global__ void __launch_bounds__(BLOCK) k_round_end(GraphDev g, RunDev R, int i
     }
 }
 
+
+// ---------------------------------------------------------------- kernels
+
+// One launch per phase; a phase whose direction is not the round's returns.
+template <int W> __global__ void __launch_bounds__(BLOCK) k_push_commit(GraphDev g, RunDev R, int init) {
+    if (R.ctrl->converged || (!init && R.ctrl->mode != MODE_PUSH)) return;
+    phase_push_commit<W>(g, R, init);
+}
+template <int W> __global__ void __launch_bounds__(BLOCK) k_pull(GraphDev g, RunDev R) {
+    if (R.ctrl->converged || R.ctrl->mode != MODE_PULL) return;
+    phase_pull<W>(g, R);
+}
+template <int W> __global__ void __launch_bounds__(BLOCK) k_pull_hubs(GraphDev g, RunDev R) {
+    if (R.ctrl->converged || R.ctrl->mode != MODE_PULL) return;
+    phase_pull_hubs<W>(g, R);
+}
+template <int W> __global__ void __launch_bounds__(BLOCK) k_frontier(GraphDev g, RunDev R) {
+    if (R.ctrl->converged || R.ctrl->mode != MODE_PUSH || R.ctrl->prev_mode != MODE_PULL) return;
+    phase_frontier<W>(g, R);
+}
+template <int W> __global__ void __launch_bounds__(BLOCK) k_push(GraphDev g, RunDev R) {
+    if (R.ctrl->converged || R.ctrl->mode != MODE_PUSH) return;
+    phase_push<W>(g, R);
+}
+__global__ void __launch_bounds__(BLOCK) k_round_end(GraphDev g, RunDev R, int init) {
+    if (R.ctrl->converged) return;
+    phase_round_end(g, R, init, g.pull_grid);
+}
+
+// ---------------------------------------------------------------- persistent rounds
+
+// Grid-wide barrier for a cooperative launch.  Blocks arrive on one of up to
+// eight group counters (block i in group i % 8, matching the round-robin
+// placement of blocks on the XCDs), the last of a group arrives on the top
+// counter, the last group advances the generation everyone waits on.  The
+// agent-scope fences publish each block's writes before it arrives and make
+// the others' writes visible after it leaves.  A wait longer than about ten
+// seconds sets `abort`; every later barrier and the round loop then return,
+// so the grid always drains.
+PP_DEV bool grid_barrier(GridBar *b) {
+    __shared__ int s_abort;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint32_t nb = gridDim.x;
+        const uint32_t ng = nb < 8 ? nb : 8;
+        const uint32_t grp = blockIdx.x % ng;
+        const uint32_t gsize = nb / ng + (grp < nb % ng ? 1u : 0u);
+        int ab = __hip_atomic_load(&b->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (!ab) {
+            const uint32_t gen = __hip_atomic_load(&b->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __threadfence();
+            if (atomicAdd(&b->grp[grp], 1u) + 1 == gsize) {
+                atomicExch(&b->grp[grp], 0u);
+                __threadfence();
+                if (atomicAdd(&b->top, 1u) + 1 == ng) {
+                    atomicExch(&b->top, 0u);
+                    __threadfence();
+                    atomicAdd(&b->gen, 1u);
+                }
+            }
+            const uint64_t t0 = wall_clock64();
+            while (__hip_atomic_load(&b->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+                __builtin_amdgcn_s_sleep(2);
+                if (wall_clock64() - t0 > 1000000000ull) {   // ~10 s at 100 MHz
+                    atomicExch(&b->abort, 1);
+                    break;
+                }
+                if (__hip_atomic_load(&b->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+            }
+            __threadfence();
+            ab = __hip_atomic_load(&b->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        s_abort = ab;
+    }
+    __syncthreads();
+    return s_abort == 0;
+}
+
+// All rounds up to max_round in one cooperative launch.  Every block runs
+// every phase and every barrier; the loop condition is read by all blocks
+// after a barrier, so they leave together.  Block 0 also logs device-clock
+// stamps per round: [start, after the main phase, end].
+template <int W>
+__global__ void __launch_bounds__(BLOCK) k_rounds(GraphDev g, RunDev R, int max_round) {
+    Ctrl *C = R.ctrl;
+    GridBar *bar = R.bar;
+    const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+    for (;;) {
+        const int conv = CTL(C->converged);
+        const int r = CTL(C->round);
+        const int mode = CTL(C->mode);
+        const int prev = CTL(C->prev_mode);
+        if (conv || r > max_round || CTL(bar->abort)) break;
+        int64_t *stamp = (R.phase_log && r < R.cap) ? R.phase_log + (int64_t)r * 3 : nullptr;
+        if (lead && stamp) stamp[0] = (int64_t)wall_clock64();
+        if (mode == MODE_PUSH) {
+            if (prev == MODE_PULL) {
+                phase_frontier<W>(g, R);
+                if (!grid_barrier(bar)) break;
+            }
+            phase_push<W>(g, R);
+            if (!grid_barrier(bar)) break;
+            if (lead && stamp) stamp[1] = (int64_t)wall_clock64();
+            phase_push_commit<W>(g, R, 0);
+            if (!grid_barrier(bar)) break;
+        } else {
+            phase_pull<W>(g, R);
+            if (!grid_barrier(bar)) break;
+            if (lead && stamp) stamp[1] = (int64_t)wall_clock64();
+            if (g.nhubs) {
+                phase_pull_hubs<W>(g, R);
+                if (!grid_barrier(bar)) break;
+            }
+        }
+        if (blockIdx.x == 0) phase_round_end(g, R, 0, gridDim.x);
+        if (lead && stamp) stamp[2] = (int64_t)wall_clock64();
+        if (!grid_barrier(bar)) break;
+    }
+}
+
 // ---------------------------------------------------------------- launchers
 
+// blocks of a pull launch: one wave per tile, four waves per block
 int pull_grid_for(int32_t ntiles) {
-    return ntiles < 1 ? 1 : (ntiles < PULL_GRID_MAX ? ntiles : PULL_GRID_MAX);
+    const int b = (ntiles + BLOCK / 64 - 1) / (BLOCK / 64);
+    return b < 1 ? 1 : (b < PULL_GRID_MAX ? b : PULL_GRID_MAX);
 }
 
 static int list_grid(const GraphDev &g) {
@@ -891,6 +1036,38 @@ hipError_t launch_round(const GraphDev &g, const RunDev &R, hipStream_t st, hipE
         case 8: return round_impl<8>(g, R, st, e0, e1);
         default: return hipErrorInvalidValue;
     }
+}
+
+}  // namespace pp
+
+namespace pp {
+
+template <int W> static const void *rounds_fn() { return reinterpret_cast<const void *>(&k_rounds<W>); }
+
+static const void *rounds_kernel(int W) {
+    switch (W) {
+        case 1: return rounds_fn<1>();
+        case 2: return rounds_fn<2>();
+        case 4: return rounds_fn<4>();
+        default: return rounds_fn<8>();
+    }
+}
+
+int persistent_grid(int W) {
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, rounds_kernel(W), BLOCK, 0) != hipSuccess) return 0;
+    if (per > 4) per = 4;
+    return per * cus;
+}
+
+hipError_t launch_rounds_persistent(const GraphDev &g, const RunDev &R, int grid, int max_round, hipStream_t st) {
+    GraphDev gg = g;
+    RunDev rr = R;
+    int mr = max_round;
+    void *args[] = {&gg, &rr, &mr};
+    return hipLaunchCooperativeKernel(rounds_kernel(R.W), dim3(grid), dim3(BLOCK), args, 0, st);
 }
 
 }  // namespace pp

@@ -34,7 +34,7 @@ class PPError(RuntimeError):
 class Options(ctypes.Structure):
     _fields_ = [("scheduler", ctypes.c_int32), ("seed_counts", ctypes.c_int32), ("max_rounds", ctypes.c_int32),
                 ("rounds_per_sync", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("push_div", ctypes.c_int32),
-                ("fuzz_seed", ctypes.c_uint64), ("time_kernels", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("fuzz_seed", ctypes.c_uint64), ("time_kernels", ctypes.c_int32), ("persistent", ctypes.c_int32)]
 
 
 class Metrics(ctypes.Structure):
@@ -113,7 +113,7 @@ def _is_device(a) -> bool:
 
 
 def options(scheduler=PP_SCHED_HEURISTIC, seed_counts=False, max_rounds=0, rounds_per_sync=0,
-            use_graph=True, push_div=0, fuzz_seed=0, time_kernels=False) -> Options:
+            use_graph=True, push_div=0, fuzz_seed=0, time_kernels=False, persistent=False) -> Options:
     o = Options()
     lib().pp_options_default(ctypes.byref(o))
     o.scheduler = scheduler
@@ -125,6 +125,7 @@ def options(scheduler=PP_SCHED_HEURISTIC, seed_counts=False, max_rounds=0, round
         o.push_div = int(push_div)
     o.fuzz_seed = int(fuzz_seed)
     o.time_kernels = int(bool(time_kernels))
+    o.persistent = int(bool(persistent))
     return o
 
 

@@ -34,7 +34,7 @@ def pad_words(sig, W):
 
 
 def check_run(n, src, dst, seeds, undirected, transpose=False, sched=pp.PP_SCHED_HEURISTIC,
-              fuzz_seed=0, use_graph=True, want=None, max_rounds=0):
+              fuzz_seed=0, use_graph=True, want=None, max_rounds=0, persistent=False):
     s = len(seeds)
     if want is None:
         want = oracle.propagate(n, src, dst, seeds, undirected, transpose=transpose,
@@ -42,7 +42,7 @@ def check_run(n, src, dst, seeds, undirected, transpose=False, sched=pp.PP_SCHED
     g = pp.pp_csr_build(n, src, dst, undirected=undirected, transpose=transpose)
     cap = max_rounds or want["D"] + 4
     opts = pp.options(scheduler=sched, seed_counts=True, max_rounds=cap, fuzz_seed=fuzz_seed,
-                      use_graph=use_graph)
+                      use_graph=use_graph, persistent=persistent)
     r = pp.pp_seeds_init(g, seeds, opts=opts)
     counts, D = pp.pp_propagate_until_converged(r)
     assert int(D[0]) == want["D"]
@@ -63,12 +63,13 @@ CLOSED = [gen.path_graph(50), gen.cycle_graph(31), gen.cycle_graph(32), gen.star
 
 @pytest.mark.parametrize("gi", range(len(CLOSED)))
 @pytest.mark.parametrize("sched", SCHEDS)
-def test_closed_form_graphs(gi, sched):
+@pytest.mark.parametrize("persistent", [False, True])
+def test_closed_form_graphs(gi, sched, persistent):
     g = CLOSED[gi]
     s = min(g.n, 512)
     seeds = gen.sample_seeds(g.n, s, 3 + gi)
     say("closed", g.name, "s", s, "sched", sched)
-    check_run(g.n, g.src, g.dst, seeds, g.undirected, sched=sched, fuzz_seed=gi)
+    check_run(g.n, g.src, g.dst, seeds, g.undirected, sched=sched, fuzz_seed=gi, persistent=persistent)
 
 
 @pytest.mark.parametrize("sched", SCHEDS)
@@ -96,16 +97,17 @@ def test_random_graphs_word_boundaries(trial):
     seeds = rng.integers(0, n, s).astype(np.int32)          # repeats allowed
     sched = SCHEDS[trial % 4]
     say("random", trial, "n", n, "m", m, "s", s, "und", und, "tr", tr, "sched", sched)
-    check_run(n, src, dst, seeds, und, transpose=tr, sched=sched, fuzz_seed=trial)
+    check_run(n, src, dst, seeds, und, transpose=tr, sched=sched, fuzz_seed=trial, persistent=trial % 2 == 1)
 
 
 @pytest.mark.parametrize("sched", SCHEDS)
-def test_rmat_with_hubs(sched):
+@pytest.mark.parametrize("persistent", [False, True])
+def test_rmat_with_hubs(sched, persistent):
     """R-MAT scale 14: nodes with more arcs than a pull tile holds (hub chunks)."""
     g = gen.rmat(14, 16, 77)
     seeds = gen.sample_seeds(g.n, 256, 8)
-    say("rmat14", sched)
-    check_run(g.n, g.src, g.dst, seeds, False, sched=sched, fuzz_seed=5)
+    say("rmat14", sched, "persistent", persistent)
+    check_run(g.n, g.src, g.dst, seeds, False, sched=sched, fuzz_seed=5, persistent=persistent)
 
 
 def test_empty_and_isolated():
@@ -117,15 +119,16 @@ def test_empty_and_isolated():
 # ------------------------------------------------------------ round by round
 
 @pytest.mark.parametrize("sched", [pp.PP_SCHED_PULL, pp.PP_SCHED_PUSH, pp.PP_SCHED_FUZZ])
-def test_er_workload_round_by_round(sched):
+@pytest.mark.parametrize("persistent", [False, True])
+def test_er_workload_round_by_round(sched, persistent):
     """The ER workload, signatures after every round, and the metrics."""
     g, seeds = gen.workload_er(1)
     want = oracle.propagate(g.n, g.src, g.dst, seeds, True, sig_rounds=list(range(0, 16)),
                             seed_counts=True, final_sig=True)
-    say("er rounds", sched, "D", want["D"])
+    say("er rounds", sched, "D", want["D"], "persistent", persistent)
     G = pp.pp_csr_build(g.n, g.src, g.dst, undirected=True)
     r = pp.pp_seeds_init(G, seeds, opts=pp.options(scheduler=sched, seed_counts=True, max_rounds=64,
-                                                    fuzz_seed=9))
+                                                    fuzz_seed=9, persistent=persistent))
     assert np.array_equal(pp.pp_get_signatures(r), want["sigs"][0])
     got = [len(seeds)]
     for k in range(1, want["D"] + 2):
@@ -164,11 +167,12 @@ def test_snapshot_restore_and_graph_replay():
     say("snapshot ok")
 
 
-def test_round_cap_reports_not_converged():
+@pytest.mark.parametrize("persistent", [False, True])
+def test_round_cap_reports_not_converged(persistent):
     g = gen.path_graph(200)
     seeds = np.array([0], np.int32)
     G = pp.pp_csr_build(g.n, g.src, g.dst, undirected=True)
-    r = pp.pp_seeds_init(G, seeds, opts=pp.options(max_rounds=50))
+    r = pp.pp_seeds_init(G, seeds, opts=pp.options(max_rounds=50, persistent=persistent))
     with pytest.raises(pp.PPError) as e:
         pp.pp_propagate_until_converged(r)
     assert e.value.code == pp.PP_ENOTCONV
@@ -198,12 +202,13 @@ def test_batched_union_matches_solo_runs():
         seeds.append(sd + offs[-1])
         offs.append(offs[-1] + g.n)
     n = offs[-1]
-    for sched in SCHEDS:
-        say("batch", sched)
+    for sched, persistent in [(sc_, p_) for sc_ in SCHEDS for p_ in (False, True)]:
+        say("batch", sched, "persistent", persistent)
         G = pp.pp_csr_build(n, np.concatenate(srcs).astype(np.int32), np.concatenate(dsts).astype(np.int32),
                             node_offsets=offs)
         r = pp.pp_seeds_init(G, np.concatenate(seeds), s=s,
-                             opts=pp.options(scheduler=sched, seed_counts=True, max_rounds=400, fuzz_seed=1))
+                             opts=pp.options(scheduler=sched, seed_counts=True, max_rounds=400, fuzz_seed=1,
+                                             persistent=persistent))
         counts, D = pp.pp_propagate_until_converged(r)
         sc = pp.pp_get_seed_counts(r, 400)
         for k, w in enumerate(wants):
