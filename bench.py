@@ -50,6 +50,25 @@ def workload(name: str):
     raise SystemExit(f"unknown workload {name}")
 
 
+def measured_traffic(profile: str):
+    """HBM bytes per launch from the committed counter summary, if the kernel is unchanged.
+
+    profiles/<profile>_traffic.json holds FETCH_SIZE + WRITE_SIZE per launch
+    (scaled by a copy of known size) and the hash of the kernel sources the
+    counters were taken on; a different hash means the figure is stale.
+    """
+    import hashlib
+    path = os.path.join(ROOT, "profiles", profile + "_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    csrc = os.path.join(ROOT, "paper_2301_06499_amd", "csrc")
+    src = b"".join(open(os.path.join(csrc, f), "rb").read() for f in ("pp_kernels.hip", "pp_internal.h"))
+    if hashlib.sha256(src).hexdigest() != rec.get("source_sha256"):
+        return None
+    return int(rec["fetch_bytes_per_launch"]) + int(rec["write_bytes_per_launch"])
+
+
 def cpu_baseline(g, seeds, nominal_edge_words: float, budget_s: float):
     """The oracle (not tuned) on the host cores; a seed sample sized to the budget."""
     import oracle
@@ -162,7 +181,9 @@ def main():
     t_pull = sum(pull_ms[r] for r in pull_rounds) / 1000.0
     achieved = bytes_pull / t_pull / 1e9 if t_pull > 0 else 0.0
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": (measured_traffic("k_pull_rmat20_s256")
+                        if args.workload == "rmat20" and not args.persistent and W == 4 else None),
             "kernel": f"k_rounds<{W}> pull phase" if args.persistent else f"k_pull<{W}>",
             "timing": "device clock between grid barriers" if args.persistent else "HIP events around each launch",
             "launches_per_step": len(pull_rounds),
