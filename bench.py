@@ -69,6 +69,89 @@ def measured_traffic(profile: str):
     return int(rec["fetch_bytes_per_launch"]) + int(rec["write_bytes_per_launch"])
 
 
+def bench_batch(args, torch, pp):
+    """The 64-graph batch (R-MAT, grids, paths; 64 seeds each) in one launch vs plain runs.
+
+    Batched: the disjoint union, every graph run by its own cluster of
+    co-resident blocks in one cooperative launch (each graph converges on its
+    own).  Plain: each graph alone, per-round launches, fixed-threshold
+    heuristic.  Both give the same per-graph counts (checked here).
+    """
+    from paper_2301_06499_amd import inputs
+    t0 = time.perf_counter()
+    graphs, seeds = inputs.workload_batch(1, 64)
+    offs, srcs, dsts, sds = [0], [], [], []
+    for g, sd in zip(graphs, seeds):
+        src, dst = g.src.astype(np.int64), g.dst.astype(np.int64)
+        if g.undirected:
+            src, dst = np.concatenate([src, dst]), np.concatenate([dst, src])
+        srcs.append(src + offs[-1])
+        dsts.append(dst + offs[-1])
+        sds.append(sd.astype(np.int64) + offs[-1])
+        offs.append(offs[-1] + g.n)
+    n = offs[-1]
+    allseeds = np.concatenate(sds).astype(np.int32)
+    log(f"[bench] generated the batch in {time.perf_counter() - t0:.1f} s: {len(graphs)} graphs, n={n}")
+    stream = torch.cuda.Stream()
+    GB = pp.pp_csr_build(n, np.concatenate(srcs).astype(np.int32), np.concatenate(dsts).astype(np.int32),
+                         node_offsets=offs, stream=stream)
+    run = pp.pp_seeds_init(GB, allseeds, s=64, opts=pp.options(max_rounds=25000, persistent=True), stream=stream)
+    dseeds = torch.from_numpy(allseeds).to("cuda")
+
+    def step():
+        pp.pp_seeds_reset(run, dseeds)
+        return pp.pp_propagate_until_converged(run)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        counts, D = step()
+    torch.cuda.synchronize()
+    t_batch = (time.perf_counter() - t0) / args.steps
+    # stored arcs per graph, from solo builds (also used by the plain runs)
+    solo_graphs, solo_runs, arcs_g = [], [], []
+    for g, sd in zip(graphs, seeds):
+        Gs = pp.pp_csr_build(g.n, g.src, g.dst, undirected=g.undirected, stream=stream)
+        solo_graphs.append(Gs)
+        arcs_g.append(Gs.arcs)
+        solo_runs.append(pp.pp_seeds_init(Gs, sd, opts=pp.options(max_rounds=25000), stream=stream))
+    nominal = float(sum(arcs_g[k] * (int(D[k]) + 1) for k in range(len(graphs))))   # W = 1
+    plain_steps = max(1, min(args.steps, 2))
+    plain_counts = None
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(plain_steps):
+        plain_counts = []
+        for r_, sd in zip(solo_runs, seeds):
+            pp.pp_seeds_reset(r_, sd)
+            c, _ = pp.pp_propagate_until_converged(r_)
+            plain_counts.append(c[0])
+    torch.cuda.synchronize()
+    t_plain = (time.perf_counter() - t0) / plain_steps
+    for k, c in enumerate(plain_counts):
+        assert list(c) == list(counts[k][:int(D[k]) + 1]), f"graph {k}: batched and plain counts differ"
+    out = {
+        "metric": METRIC,
+        "value": nominal / t_batch,
+        "unit": "edge-words/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(t_batch * 1000.0, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u64", "data": "synthetic",
+        "config": {"workload": "batch64: 22 R-MAT (scale 10-16, edge factor 8-16), 21 grids (64^2..512^2), "
+                               "21 paths (1000..20000 edges), 64 seeds each",
+                   "graphs": len(graphs), "nodes": n, "arcs": int(GB.arcs), "words": 1,
+                   "max_rounds": int(D.max()) + 1, "engine": "clustered persistent launch"},
+        "plain": {"ms_per_step": round(t_plain * 1000.0, 3), "value": nominal / t_plain,
+                  "engine": "64 solo runs, per-round launches, fixed-threshold heuristic"},
+        "speedup_vs_plain": round(t_plain / t_batch, 2),
+        "roofline": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def cpu_baseline(g, seeds, nominal_edge_words: float, budget_s: float):
     """The oracle (not tuned) on the host cores; a seed sample sized to the budget."""
     import oracle
@@ -121,6 +204,8 @@ def main():
         raise SystemExit("no GPU visible")
     torch.cuda.set_device(0)
     sched = {"heuristic": pp.PP_SCHED_HEURISTIC, "pull": pp.PP_SCHED_PULL, "push": pp.PP_SCHED_PUSH}[args.scheduler]
+    if args.workload == "batch64":
+        return bench_batch(args, torch, pp)
 
     t0 = time.perf_counter()
     g, seeds, cfg = workload(args.workload)

@@ -84,6 +84,8 @@ struct TileSet {
     int32_t ntiles = 0;
     int32_t *hub_node = nullptr;   // node of each high-degree entry
     int32_t nhubs = 0;
+    std::vector<int32_t> gtile;    // [G+1] first tile of each graph
+    std::vector<int32_t> ghub;     // [G+1] first hub of each graph
 };
 
 }  // namespace
@@ -118,6 +120,9 @@ struct pp_run_s {
     std::vector<hipEvent_t> ev;             // 2 per round slot of a batch
     std::vector<float> pull_ms;             // [cap]
     int pgrid = 0;                          // blocks of the persistent round loop (0: not used)
+    std::vector<pp::Cluster> clusters;      // persistent engine: block ranges per graph
+    pp::Cluster *dclusters = nullptr;
+    std::vector<int> cur;                   // signature buffer of Sig_{round-1}, per control block
     double clock_khz = 100000.0;            // device wall clock rate
 };
 
@@ -197,12 +202,18 @@ void transpose_rows(int64_t n, const std::vector<int64_t> &rp, const std::vector
 // pp::TILE_NODES nodes; a node with more than `edges` arcs is split into
 // chunks whose partial rows meet in the accumulator (hub_node lists those
 // nodes).  Runs without arcs are dropped: their nodes have no successor and
-// never gain a bit after initialisation.  Hub chunks come first so the
-// longest-latency work starts early.
+// never gain a bit after initialisation.  Tiles are grouped by graph
+// (gtile/ghub give each graph's first tile and hub); within a graph, hub
+// chunks come first so the longest-latency work starts early.
 void build_tiles(const std::vector<int64_t> &rp, const std::vector<int64_t> &noff, int G, int edges,
-                 std::vector<Tile> &tiles, std::vector<int32_t> &hub_node) {
-    std::vector<Tile> hubs, runs;
+                 std::vector<Tile> &tiles, std::vector<int32_t> &hub_node, std::vector<int32_t> &gtile,
+                 std::vector<int32_t> &ghub) {
+    gtile.assign((size_t)G + 1, 0);
+    ghub.assign((size_t)G + 1, 0);
     for (int g = 0; g < G; ++g) {
+        std::vector<Tile> hubs, runs;
+        gtile[(size_t)g] = (int32_t)tiles.size();
+        ghub[(size_t)g] = (int32_t)hub_node.size();
         int64_t u = noff[(size_t)g];
         const int64_t end = noff[(size_t)g + 1];
         while (u < end) {
@@ -227,9 +238,11 @@ void build_tiles(const std::vector<int64_t> &rp, const std::vector<int64_t> &nof
             }
             if (rp[(size_t)u] > rp[(size_t)s]) runs.push_back(Tile{(int32_t)s, (int32_t)u, rp[(size_t)s], rp[(size_t)u], -1, g});
         }
+        tiles.insert(tiles.end(), hubs.begin(), hubs.end());
+        tiles.insert(tiles.end(), runs.begin(), runs.end());
     }
-    tiles = std::move(hubs);
-    tiles.insert(tiles.end(), runs.begin(), runs.end());
+    gtile[(size_t)G] = (int32_t)tiles.size();
+    ghub[(size_t)G] = (int32_t)hub_node.size();
 }
 
 int pull_edges_for_words(int W) {
@@ -250,8 +263,8 @@ int ensure_tiles(pp_graph g, int W, TileSet **out) {
     }
     std::vector<Tile> tiles;
     std::vector<int32_t> hubs;
-    build_tiles(g->rp_host, g->node_offsets, g->G, edges, tiles, hubs);
     TileSet ts;
+    build_tiles(g->rp_host, g->node_offsets, g->G, edges, tiles, hubs, ts.gtile, ts.ghub);
     int rc;
     if ((rc = dev_alloc(&ts.tiles, (int64_t)tiles.size())) != PP_OK) return rc;
     if ((rc = dev_alloc(&ts.hub_node, (int64_t)hubs.size())) != PP_OK) {
@@ -462,13 +475,15 @@ void free_run(pp_run r) {
     drop_graphs(r);
     free_run_dev(r->dev);
     dev_free(r->dseeds);
+    dev_free(r->dclusters);
     for (hipEvent_t e : r->ev) (void)hipEventDestroy(e);
     if (r->own_stream && r->stream) (void)hipStreamDestroy(r->stream);
     delete r;
 }
 
-// push chunks: at most one per listed entry plus one per chunk of arcs
-int64_t chunk_capacity(pp_graph g) { return g->n + g->m / pp::PUSH_CHUNK_MIN + 2; }
+// push chunks: at most one per listed entry plus one per chunk of arcs, in a
+// region of its own for each graph of a batch
+int64_t chunk_capacity(pp_graph g) { return g->n + g->m / pp::PUSH_CHUNK_MIN + 2 * (int64_t)g->G + 2; }
 
 // Allocates every device buffer of a run with the sizes fixed by (g, s, cap).
 int alloc_run_dev(pp_graph g, RunDev &d, int s, int W, int cap, bool seed_counts, int pull_grid) {
@@ -479,6 +494,8 @@ int alloc_run_dev(pp_graph g, RunDev &d, int s, int W, int cap, bool seed_counts
     d.W = W;
     d.cap = cap;
     d.G = G;
+    d.cstride = G;
+    d.sstride = G * s;
     if ((rc = dev_alloc(&d.sig[0], n * W)) || (rc = dev_alloc(&d.sig[1], n * W)) || (rc = dev_alloc(&d.acc, n * W)) ||
         (rc = dev_alloc(&d.stamp, n)) ||
         (rc = dev_alloc(&d.f_ids[0], n)) || (rc = dev_alloc(&d.f_ids[1], n)) ||
@@ -487,8 +504,9 @@ int alloc_run_dev(pp_graph g, RunDev &d, int s, int W, int cap, bool seed_counts
         (rc = dev_alloc(&d.blk_cnt, pull_grid)) || (rc = dev_alloc(&d.blk_nodes, pull_grid)) ||
         (rc = dev_alloc(&d.blk_arcs, pull_grid)) || (rc = dev_alloc(&d.blk_pulled, pull_grid)) ||
         (rc = dev_alloc(&d.counts, (int64_t)cap * G)) || (rc = dev_alloc(&d.D, G)) || (rc = dev_alloc(&d.gconv, G)) ||
-        (rc = dev_alloc(&d.mode_log, cap)) || (rc = dev_alloc(&d.arcs_log, cap)) || (rc = dev_alloc(&d.ctrl, 1)) ||
-        (rc = dev_alloc(&d.bar, 1)) || (rc = dev_alloc(&d.phase_log, (int64_t)cap * 3)))
+        (rc = dev_alloc(&d.mode_log, (int64_t)cap * G)) || (rc = dev_alloc(&d.arcs_log, (int64_t)cap * G)) ||
+        (rc = dev_alloc(&d.ctrl, G)) || (rc = dev_alloc(&d.bar, G)) ||
+        (rc = dev_alloc(&d.phase_log, (int64_t)cap * 3 * G)))
         return rc;
     if (seed_counts && (rc = dev_alloc(&d.seed_counts, (int64_t)cap * G * s))) return rc;
     if (!seed_counts) d.seed_counts = nullptr;
@@ -497,33 +515,56 @@ int alloc_run_dev(pp_graph g, RunDev &d, int s, int W, int cap, bool seed_counts
 
 hipError_t clear_run_dev(pp_graph g, RunDev &d, hipStream_t st) {
     const int64_t n = g->n;
+    const int64_t G = d.G;
     hipError_t e;
     if ((e = pp::launch_fill_u64(d.sig[0], 0, n * d.W, st))) return e;
     if ((e = pp::launch_fill_u64(d.sig[1], 0, n * d.W, st))) return e;
     if ((e = pp::launch_fill_u64(d.acc, 0, n * d.W, st))) return e;
     if ((e = pp::launch_fill_i32(d.stamp, -1, n, st))) return e;
-    if ((e = pp::launch_fill_u64((uint64_t *)d.counts, 0, (int64_t)d.cap * d.G, st))) return e;
-    if (d.seed_counts && (e = pp::launch_fill_i32((int32_t *)d.seed_counts, 0, (int64_t)d.cap * d.G * d.s, st))) return e;
-    if ((e = pp::launch_fill_i32(d.D, 0, d.G, st))) return e;
-    if ((e = pp::launch_fill_i32(d.gconv, 0, d.G, st))) return e;
-    if ((e = pp::launch_fill_i32(d.mode_log, -1, d.cap, st))) return e;
-    if ((e = pp::launch_fill_u64((uint64_t *)d.arcs_log, 0, d.cap, st))) return e;
-    if ((e = pp::launch_fill_i32((int32_t *)d.bar, 0, (int64_t)(sizeof(pp::GridBar) / 4), st))) return e;
-    if ((e = pp::launch_fill_u64((uint64_t *)d.phase_log, 0, (int64_t)d.cap * 3, st))) return e;
-    return pp::launch_fill_i32((int32_t *)d.ctrl, 0, (int64_t)(sizeof(Ctrl) / 4), st);
+    if ((e = pp::launch_fill_u64((uint64_t *)d.counts, 0, (int64_t)d.cap * G, st))) return e;
+    if (d.seed_counts && (e = pp::launch_fill_i32((int32_t *)d.seed_counts, 0, (int64_t)d.cap * G * d.s, st))) return e;
+    if ((e = pp::launch_fill_i32(d.D, 0, G, st))) return e;
+    if ((e = pp::launch_fill_i32(d.gconv, 0, G, st))) return e;
+    if ((e = pp::launch_fill_i32(d.mode_log, -1, (int64_t)d.cap * G, st))) return e;
+    if ((e = pp::launch_fill_u64((uint64_t *)d.arcs_log, 0, (int64_t)d.cap * G, st))) return e;
+    if ((e = pp::launch_fill_i32((int32_t *)d.bar, 0, G * (int64_t)(sizeof(pp::GridBar) / 4), st))) return e;
+    if ((e = pp::launch_fill_u64((uint64_t *)d.phase_log, 0, (int64_t)d.cap * 3 * G, st))) return e;
+    return pp::launch_fill_i32((int32_t *)d.ctrl, 0, G * (int64_t)(sizeof(Ctrl) / 4), st);
 }
 
 TileSet *run_tiles(pp_run r) { return &r->g->tiles[pull_edges_for_words(r->W)]; }
 
+// Host copy of the control state.  The clustered engine keeps one control
+// block per graph: the summary has the largest round, converged when every
+// graph has, and the flags of any.
 int sync_ctrl(pp_run r) {
-    HIP_TRY(hipMemcpyAsync(&r->host_ctrl, r->dev.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, r->stream));
+    const int nc = r->pgrid ? r->G : 1;
+    std::vector<Ctrl> c((size_t)nc);
+    HIP_TRY(hipMemcpyAsync(c.data(), r->dev.ctrl, sizeof(Ctrl) * (size_t)nc, hipMemcpyDeviceToHost, r->stream));
     HIP_TRY(hipStreamSynchronize(r->stream));
+    r->host_ctrl = c[0];
+    r->cur.assign((size_t)nc, 0);
+    for (int k = 0; k < nc; ++k) {
+        r->cur[(size_t)k] = c[(size_t)k].cur & 1;
+        if (k == 0) continue;
+        r->host_ctrl.round = std::max(r->host_ctrl.round, c[(size_t)k].round);
+        r->host_ctrl.converged = r->host_ctrl.converged && c[(size_t)k].converged;
+        r->host_ctrl.overflow |= c[(size_t)k].overflow;
+        r->host_ctrl.bad_seed |= c[(size_t)k].bad_seed;
+    }
     return PP_OK;
 }
 
 }  // namespace
 
 namespace {
+
+int launch_clusters(pp_run r, int max_round) {
+    GraphDev gv = graph_view(r->g, run_tiles(r));
+    HIP_TRY(pp::launch_batch_persistent(gv, r->dev, r->dclusters, (int)r->clusters.size(), r->pgrid, max_round,
+                                        r->stream));
+    return PP_OK;
+}
 
 // Algorithm 1's initialisation on an allocated run: clear every buffer, place
 // the seed bits (device seeds), run the round-0 commit.  Synchronises.
@@ -532,12 +573,62 @@ int reset_run(pp_run r, const int32_t *dseeds) {
     TileSet *ts = run_tiles(r);
     GraphDev gv = graph_view(g, ts);
     hipError_t e = clear_run_dev(g, r->dev, r->stream);
-    if (e == hipSuccess) e = pp::launch_seed_init(gv, r->dev, dseeds, r->stream);
+    if (e == hipSuccess) {
+        if (r->pgrid) e = pp::launch_seed_scatter_batch(gv, r->dev, dseeds, r->stream);
+        else e = pp::launch_seed_init(gv, r->dev, dseeds, r->stream);
+    }
     if (e != hipSuccess) return fail(PP_EDEVICE, "seed initialisation: %s", hipGetErrorString(e));
+    if (r->pgrid) {
+        int rc = launch_clusters(r, 0);   // round 0 of every graph only
+        if (rc) return rc;
+    }
     int rc = sync_ctrl(r);
     if (rc) return rc;
     if (r->host_ctrl.bad_seed) return fail(PP_ERANGE, "a seed id lies outside its graph's node range");
     return PP_OK;
+}
+
+// Splits the persistent grid among the graphs of a batch, in proportion to
+// their arcs plus nodes, at least one block each; graph order is kept.
+std::vector<pp::Cluster> make_clusters(pp_graph g, const TileSet *ts, int grid) {
+    const int G = g->G;
+    std::vector<double> w((size_t)G);
+    double tot = 0.0;
+    for (int k = 0; k < G; ++k) {
+        const int64_t n0 = g->node_offsets[(size_t)k], n1 = g->node_offsets[(size_t)k + 1];
+        w[(size_t)k] = (double)(g->rp_host[(size_t)n1] - g->rp_host[(size_t)n0]) + (double)(n1 - n0) + 1.0;
+        tot += w[(size_t)k];
+    }
+    std::vector<int> nb((size_t)G, 1);
+    int used = G;
+    for (int k = 0; k < G; ++k) {
+        const int extra = (int)((double)(grid - G) * w[(size_t)k] / tot);
+        nb[(size_t)k] += extra;
+        used += extra;
+    }
+    for (int k = 0; used < grid; k = (k + 1) % G, ++used) nb[(size_t)k] += 1;   // leftovers, round robin
+    std::vector<pp::Cluster> cl((size_t)G);
+    int b0 = 0;
+    int64_t ch0 = 0;
+    for (int k = 0; k < G; ++k) {
+        pp::Cluster &c = cl[(size_t)k];
+        const int64_t n0 = g->node_offsets[(size_t)k], n1 = g->node_offsets[(size_t)k + 1];
+        c.g = k;
+        c.b0 = b0;
+        c.nb = nb[(size_t)k];
+        c.t0 = ts->gtile[(size_t)k];
+        c.t1 = ts->gtile[(size_t)k + 1];
+        c.h0 = ts->ghub[(size_t)k];
+        c.h1 = ts->ghub[(size_t)k + 1];
+        c.pad = 0;
+        c.n0 = n0;
+        c.n1 = n1;
+        c.m = g->rp_host[(size_t)n1] - g->rp_host[(size_t)n0];
+        c.ch0 = ch0;
+        b0 += c.nb;
+        ch0 += (n1 - n0) + c.m / pp::PUSH_CHUNK_MIN + 2;
+    }
+    return cl;
 }
 
 int check_host_seeds(pp_graph g, const int32_t *seeds, int s) {
@@ -587,6 +678,11 @@ extern "C" int pp_seeds_init(pp_graph g, const int32_t *seeds, int32_t s, const 
             delete r;
             return fail(PP_EDEVICE, "no co-resident grid for the persistent round loop");
         }
+        if (G > r->pgrid) {
+            const int p = r->pgrid;
+            delete r;
+            return fail(PP_EINVAL, "%d graphs but only %d co-resident blocks: use the per-round engine", G, p);
+        }
         int dev = 0, khz = 0;
         if (hipGetDevice(&dev) == hipSuccess &&
             hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) == hipSuccess && khz > 0)
@@ -607,6 +703,13 @@ extern "C" int pp_seeds_init(pp_graph g, const int32_t *seeds, int32_t s, const 
     if (rc == PP_OK)
         rc = alloc_run_dev(g, r->dev, s, W, (int)cap, o.seed_counts != 0, std::max(pp::pull_grid_for(ts->ntiles), r->pgrid));
     if (rc == PP_OK) rc = dev_alloc(&r->dseeds, (int64_t)G * s);
+    if (rc == PP_OK && r->pgrid) {
+        r->clusters = make_clusters(g, ts, r->pgrid);
+        rc = dev_alloc(&r->dclusters, (int64_t)r->clusters.size());
+        if (rc == PP_OK && hipMemcpy(r->dclusters, r->clusters.data(), sizeof(pp::Cluster) * r->clusters.size(),
+                                     hipMemcpyHostToDevice) != hipSuccess)
+            rc = fail(PP_EDEVICE, "cluster upload");
+    }
     if (rc == PP_OK && r->timing) {
         r->pull_ms.assign((size_t)cap, 0.0f);
         r->ev.resize(2 * 64, nullptr);
@@ -657,13 +760,13 @@ namespace {
 // per-round device-clock stamps of the launch feed the kernel times.
 int run_persistent(pp_run r, int max_round) {
     const int before = r->host_ctrl.round;
-    GraphDev gv = graph_view(r->g, run_tiles(r));
-    HIP_TRY(pp::launch_rounds_persistent(gv, r->dev, r->pgrid, max_round, r->stream));
-    int rc = sync_ctrl(r);
+    int rc = launch_clusters(r, max_round);
     if (rc) return rc;
-    pp::GridBar bar;
-    HIP_TRY(hipMemcpy(&bar, r->dev.bar, sizeof(bar), hipMemcpyDeviceToHost));
-    if (bar.abort) return fail(PP_EDEVICE, "persistent round loop: a grid barrier timed out");
+    if ((rc = sync_ctrl(r))) return rc;
+    std::vector<pp::GridBar> bars((size_t)r->G);
+    HIP_TRY(hipMemcpy(bars.data(), r->dev.bar, sizeof(pp::GridBar) * bars.size(), hipMemcpyDeviceToHost));
+    for (const pp::GridBar &b : bars)
+        if (b.abort) return fail(PP_EDEVICE, "persistent round loop: a cluster barrier timed out");
     if (r->timing) {
         const int last = std::min(r->host_ctrl.converged ? r->host_ctrl.round : r->host_ctrl.round - 1, r->cap - 1);
         if (last >= before) {
@@ -822,8 +925,19 @@ extern "C" int pp_propagate_until_converged(pp_run r, int32_t max_rounds, int64_
 
 extern "C" int pp_get_signatures(pp_run r, uint64_t *dst, int32_t dst_on_device) {
     if (!r || !dst) return fail(PP_EINVAL, "run or dst is NULL");
-    HIP_TRY(hipMemcpyAsync(dst, r->dev.sig[r->host_ctrl.cur & 1], sizeof(uint64_t) * (size_t)r->g->n * r->W,
-                           dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, r->stream));
+    const hipMemcpyKind kind = dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    if (r->cur.size() <= 1) {
+        HIP_TRY(hipMemcpyAsync(dst, r->dev.sig[r->host_ctrl.cur & 1], sizeof(uint64_t) * (size_t)r->g->n * r->W, kind,
+                               r->stream));
+    } else {
+        // clustered batch: each graph's rows sit in the buffer its own round count selects
+        for (int k = 0; k < r->G; ++k) {
+            const int64_t n0 = r->g->node_offsets[(size_t)k], n1 = r->g->node_offsets[(size_t)k + 1];
+            if (n1 == n0) continue;
+            HIP_TRY(hipMemcpyAsync(dst + n0 * r->W, r->dev.sig[r->cur[(size_t)k]] + n0 * r->W,
+                                   sizeof(uint64_t) * (size_t)(n1 - n0) * r->W, kind, r->stream));
+        }
+    }
     HIP_TRY(hipStreamSynchronize(r->stream));
     return PP_OK;
 }
@@ -872,6 +986,15 @@ extern "C" int pp_run_snapshot(pp_run r, pp_run *copy) {
     TileSet *ts = run_tiles(r);
     c->pgrid = r->pgrid;
     c->clock_khz = r->clock_khz;
+    c->clusters = r->clusters;
+    if (r->pgrid) {
+        if (dev_alloc(&c->dclusters, (int64_t)c->clusters.size()) != PP_OK ||
+            hipMemcpy(c->dclusters, c->clusters.data(), sizeof(pp::Cluster) * c->clusters.size(),
+                      hipMemcpyHostToDevice) != hipSuccess) {
+            free_run(c);
+            return fail(PP_ENOMEM, "snapshot clusters");
+        }
+    }
     int rc = alloc_run_dev(r->g, c->dev, r->s, r->W, r->cap, r->dev.seed_counts != nullptr,
                            std::max(pp::pull_grid_for(ts->ntiles), r->pgrid));
     if (rc) {
@@ -916,12 +1039,15 @@ extern "C" int pp_run_restore(pp_run r, pp_run from) {
     if (!e && b.seed_counts) e = cp(b.seed_counts, a.seed_counts, 4 * cap * G * r->s);
     if (!e) e = cp(b.D, a.D, 4 * G);
     if (!e) e = cp(b.gconv, a.gconv, 4 * G);
-    if (!e) e = cp(b.mode_log, a.mode_log, 4 * cap);
-    if (!e) e = cp(b.arcs_log, a.arcs_log, 8 * cap);
-    if (!e) e = cp(b.ctrl, a.ctrl, sizeof(Ctrl));
+    if (!e) e = cp(b.mode_log, a.mode_log, 4 * cap * G);
+    if (!e) e = cp(b.arcs_log, a.arcs_log, 8 * cap * G);
+    if (!e) e = cp(b.phase_log, a.phase_log, 8 * cap * 3 * G);
+    if (!e) e = cp(b.ctrl, a.ctrl, sizeof(Ctrl) * G);
+    if (!e) e = cp(b.bar, a.bar, sizeof(pp::GridBar) * G);
     if (!e) e = hipStreamSynchronize(st);
     if (e) return fail(PP_EDEVICE, "restore: %s", hipGetErrorString(e));
     r->host_ctrl = from->host_ctrl;
+    r->cur = from->cur;
     return PP_OK;
 }
 

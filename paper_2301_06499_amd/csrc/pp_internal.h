@@ -88,8 +88,23 @@ struct GridBar {
     uint32_t pad[5];
 };
 
+// One graph of a batch as run by the clustered persistent engine: the
+// graph's node range, tiles, hubs and push-chunk region, and the range of
+// co-resident blocks [b0, b0 + nb) that runs it.
+struct Cluster {
+    int32_t g;            // graph index
+    int32_t b0, nb;       // first block, blocks
+    int32_t t0, t1;       // pull tiles
+    int32_t h0, h1;       // high-degree nodes
+    int32_t pad;
+    int64_t n0, n1;       // nodes
+    int64_t m;            // stored arcs (scheduler)
+    int64_t ch0;          // first push-chunk slot
+};
+
 struct GraphDev {
-    int64_t n, m;
+    int64_t n0;               // first node of the view (0 for a whole graph)
+    int64_t n, m;             // end of the node range, stored arcs
     const int64_t *rp;        // successor offsets [n+1] (pull)
     const int32_t *col;       // successors [m]
     const int64_t *trp;       // predecessor offsets [n+1] (push)
@@ -106,6 +121,8 @@ struct GraphDev {
 
 struct RunDev {
     int32_t s, W, cap, G;
+    int32_t cstride;      // distance between rounds in counts (graphs of the run)
+    int32_t sstride;      // distance between rounds in seed_counts (graphs * s)
     uint64_t *sig[2];     // [n][W] each: Sig_{r-1} in sig[cur], the pull writes the other
     uint64_t *acc;        // [n][W] push / hub accumulator, zero between rounds
     int32_t *stamp;       // [n] last round the node was queued
@@ -120,11 +137,11 @@ struct RunDev {
     uint32_t *seed_counts;// [cap][G][s] or NULL
     int32_t *D;           // [G]
     int32_t *gconv;       // [G]
-    int32_t *mode_log;    // [cap]
-    int64_t *arcs_log;    // [cap]
-    int64_t *phase_log;   // [cap][3] device-clock stamps of the persistent loop
-    GridBar *bar;
-    Ctrl *ctrl;
+    int32_t *mode_log;    // [G][cap] (row 0 when the graphs run as one union)
+    int64_t *arcs_log;    // [G][cap]
+    int64_t *phase_log;   // [G][cap][3] device-clock stamps of the persistent loop
+    GridBar *bar;         // [G] barrier state per cluster
+    Ctrl *ctrl;           // [G]: ctrl[0] for the per-round engine, one per graph when clustered
     // scheduler
     int32_t sched;
     int32_t push_div;
@@ -139,8 +156,12 @@ hipError_t launch_seed_init(const GraphDev &g, const RunDev &r, const int32_t *s
 // One round; when e0/e1 are given they are recorded around the pull launch.
 hipError_t launch_round(const GraphDev &g, const RunDev &r, hipStream_t st, hipEvent_t e0 = nullptr,
                         hipEvent_t e1 = nullptr);
-// Rounds up to max_round in one cooperative launch of `grid` blocks.
-hipError_t launch_rounds_persistent(const GraphDev &g, const RunDev &r, int grid, int max_round, hipStream_t st);
+// Rounds up to max_round of every graph in one cooperative launch of `grid`
+// blocks split into clusters (device array), initialising graphs at round 0.
+hipError_t launch_batch_persistent(const GraphDev &g, const RunDev &r, const Cluster *clusters, int nclusters,
+                                   int grid, int max_round, hipStream_t st);
+// Seed bits of the clustered engine (per-graph list regions and control blocks).
+hipError_t launch_seed_scatter_batch(const GraphDev &g, const RunDev &r, const int32_t *seeds, hipStream_t st);
 // Largest co-resident grid for the persistent loop at width W.
 int persistent_grid(int W);
 int pull_grid_for(int32_t ntiles);

@@ -161,7 +161,7 @@ template <int W> PP_DEV void seed_flush(const RunDev &R, int r, const uint32_t (
 #pragma unroll
     for (int k = 0; k < W; ++k) {
         const int bitidx = k * 64 + ln;
-        if (sc[k] && bitidx < R.s) atomicAdd(&R.seed_counts[(int64_t)r * R.s + bitidx], sc[k]);
+        if (sc[k] && bitidx < R.s) atomicAdd(&R.seed_counts[(int64_t)r * R.sstride + bitidx], sc[k]);
     }
 }
 
@@ -170,7 +170,7 @@ PP_DEV void seed_bits(const RunDev &R, int r, int gi, int w, uint64_t d) {
     while (d) {
         const int bit = __ffsll((long long)d) - 1;
         d &= d - 1;
-        atomicAdd(&R.seed_counts[((int64_t)r * R.G + gi) * R.s + w * 64 + bit], 1u);
+        atomicAdd(&R.seed_counts[(int64_t)r * R.sstride + (int64_t)gi * R.s + w * 64 + bit], 1u);
     }
 }
 
@@ -293,7 +293,7 @@ __global__ void __launch_bounds__(BLOCK) k_seed_scatter(GraphDev g, RunDev R, co
 // for the next round.  Round 0 (init) also writes them into both signature
 // buffers; a push round has set them in Sig already.
 template <int W>
-PP_DEV void phase_push_commit(const GraphDev &g, const RunDev &R, int init) {
+PP_DEV void phase_push_commit(const GraphDev &g, const RunDev &R, int init, int bid, int nb) {
     Ctrl *C = R.ctrl;
     const int r = init ? 0 : CTL(C->round);
     const int p = r & 1;
@@ -312,8 +312,8 @@ PP_DEV void phase_push_commit(const GraphDev &g, const RunDev &R, int init) {
     uint32_t sc[W];
 #pragma unroll
     for (int k = 0; k < W; ++k) sc[k] = 0;
-    const int64_t stride = (int64_t)gridDim.x * BLOCK;
-    for (int64_t bb = blockIdx.x * (int64_t)BLOCK; bb < items; bb += stride) {   // block-uniform
+    const int64_t stride = (int64_t)nb * BLOCK;
+    for (int64_t bb = bid * (int64_t)BLOCK; bb < items; bb += stride) {   // block-uniform
         const int64_t idx = bb + threadIdx.x;
         const bool valid = idx < items;
         const int32_t e = (int32_t)(idx / W);
@@ -341,7 +341,7 @@ PP_DEV void phase_push_commit(const GraphDev &g, const RunDev &R, int init) {
             pop += (uint64_t)pc;
         } else if (valid) {
             gi = g.node_graph[u];
-            if (pc) atomicAdd((unsigned long long *)&R.counts[(int64_t)r * R.G + gi], (unsigned long long)pc);
+            if (pc) atomicAdd((unsigned long long *)&R.counts[(int64_t)r * R.cstride + gi], (unsigned long long)pc);
         }
         // push chunks of long predecessor lists, one reservation per block
         const int nchk = (valid && w == 0) ? chunks_for<W>(deg) : 0;
@@ -363,7 +363,7 @@ PP_DEV void phase_push_commit(const GraphDev &g, const RunDev &R, int init) {
     const unsigned long long tp = block_sum<unsigned long long>(pop, s_red);
     const unsigned long long ta = block_sum<unsigned long long>((unsigned long long)arcs, s_red);
     if (threadIdx.x == 0) {
-        if (R.G == 1 && tp) atomicAdd((unsigned long long *)&R.counts[r], tp);
+        if (R.G == 1 && tp) atomicAdd((unsigned long long *)&R.counts[(int64_t)r * R.cstride], tp);
         if (ta) atomicAdd((unsigned long long *)&C->f_arcs[p], ta);
     }
     if (per_seed && R.G == 1) seed_flush<W>(R, r, sc);
@@ -372,7 +372,7 @@ PP_DEV void phase_push_commit(const GraphDev &g, const RunDev &R, int init) {
 // ---------------------------------------------------------------- pull
 
 template <int W>
-PP_DEV void phase_pull(const GraphDev &g, const RunDev &R) {
+PP_DEV void phase_pull(const GraphDev &g, const RunDev &R, int bid, int nb) {
     Ctrl *C = R.ctrl;
     using PS = PullShape<W>;
     constexpr int K = PS::K;
@@ -400,8 +400,8 @@ PP_DEV void phase_pull(const GraphDev &g, const RunDev &R) {
 #pragma unroll
     for (int k = 0; k < W; ++k) sc[k] = 0;
 
-    const int64_t nw = (int64_t)gridDim.x * WAVES;
-    for (int64_t t = (int64_t)blockIdx.x * WAVES + wv; t < g.ntiles; t += nw) {   // wave-uniform
+    const int64_t nw = (int64_t)nb * WAVES;
+    for (int64_t t = (int64_t)bid * WAVES + wv; t < g.ntiles; t += nw) {   // wave-uniform
         const Tile T = g.tiles[t];
         if (R.G > 1 && R.gconv[T.graph]) continue;
         const int nn = T.u1 - T.u0;
@@ -509,7 +509,7 @@ PP_DEV void phase_pull(const GraphDev &g, const RunDev &R) {
                 pop += tpop;
             } else {
                 const uint64_t tt = wave_sum(tpop);
-                if (ln == 0 && tt) atomicAdd((unsigned long long *)&R.counts[(int64_t)r * R.G + T.graph], (unsigned long long)tt);
+                if (ln == 0 && tt) atomicAdd((unsigned long long *)&R.counts[(int64_t)r * R.cstride + T.graph], (unsigned long long)tt);
             }
         }
     }
@@ -518,10 +518,10 @@ PP_DEV void phase_pull(const GraphDev &g, const RunDev &R) {
     const unsigned long long ta = block_sum<unsigned long long>((unsigned long long)parcs, s_red);
     const unsigned long long tq = block_sum<unsigned long long>((unsigned long long)pulled, s_red);
     if (threadIdx.x == 0) {
-        R.blk_cnt[blockIdx.x] = (int64_t)tp;
-        R.blk_nodes[blockIdx.x] = (int64_t)tn;
-        R.blk_arcs[blockIdx.x] = (int64_t)ta;
-        R.blk_pulled[blockIdx.x] = (int64_t)tq;
+        R.blk_cnt[bid] = (int64_t)tp;
+        R.blk_nodes[bid] = (int64_t)tn;
+        R.blk_arcs[bid] = (int64_t)ta;
+        R.blk_pulled[bid] = (int64_t)tq;
     }
     if (per_seed && R.G == 1) seed_flush<W>(R, r, sc);
 }
@@ -529,7 +529,7 @@ PP_DEV void phase_pull(const GraphDev &g, const RunDev &R) {
 // High-degree nodes of a pull round: the chunks left their ORed rows in the
 // accumulator.
 template <int W>
-PP_DEV void phase_pull_hubs(const GraphDev &g, const RunDev &R) {
+PP_DEV void phase_pull_hubs(const GraphDev &g, const RunDev &R, int bid, int nb) {
     Ctrl *C = R.ctrl;
     if (g.nhubs == 0) return;
     const int r = CTL(C->round);
@@ -545,8 +545,8 @@ PP_DEV void phase_pull_hubs(const GraphDev &g, const RunDev &R) {
 #pragma unroll
     for (int k = 0; k < W; ++k) sc[k] = 0;
     const int64_t items = (int64_t)g.nhubs * W;
-    const int64_t stride = (int64_t)gridDim.x * BLOCK;
-    for (int64_t base = blockIdx.x * (int64_t)BLOCK + (threadIdx.x & ~63); base < items; base += stride) {
+    const int64_t stride = (int64_t)nb * BLOCK;
+    for (int64_t base = bid * (int64_t)BLOCK + (threadIdx.x & ~63); base < items; base += stride) {
         const int64_t idx = base + ln;
         const bool valid = idx < items;
         uint64_t nw = 0;
@@ -573,7 +573,7 @@ PP_DEV void phase_pull_hubs(const GraphDev &g, const RunDev &R) {
             pop += (uint64_t)pc;
         } else if (valid) {
             gi = g.node_graph[u];
-            if (pc) atomicAdd((unsigned long long *)&R.counts[(int64_t)r * R.G + gi], (unsigned long long)pc);
+            if (pc) atomicAdd((unsigned long long *)&R.counts[(int64_t)r * R.cstride + gi], (unsigned long long)pc);
         }
         if (per_seed) {
             if (R.G == 1) seed_ballot<W>(nw, sc);
@@ -600,7 +600,7 @@ PP_DEV void phase_pull_hubs(const GraphDev &g, const RunDev &R) {
 // a first pass counts its entries and push chunks, one atomic per block
 // reserves their slots, a second pass writes them in node order.
 template <int W>
-PP_DEV void phase_frontier(const GraphDev &g, const RunDev &R) {
+PP_DEV void phase_frontier(const GraphDev &g, const RunDev &R, int bid, int nb) {
     Ctrl *C = R.ctrl;
     constexpr int NPI = BLOCK / W;   // nodes per block iteration
     const int r = CTL(C->round);
@@ -611,8 +611,9 @@ PP_DEV void phase_frontier(const GraphDev &g, const RunDev &R) {
     const int ln = lane_id();
     const int w = ln & (W - 1);
     const int gb = ln & ~(W - 1);
-    const int64_t per = ((g.n + gridDim.x - 1) / gridDim.x + NPI - 1) / NPI * NPI;
-    const int64_t u_begin = (int64_t)blockIdx.x * per;
+    const int64_t span = g.n - g.n0;   // the view's node range [n0, n)
+    const int64_t per = ((span + nb - 1) / nb + NPI - 1) / NPI * NPI;
+    const int64_t u_begin = g.n0 + (int64_t)bid * per;
     const int64_t u_end = u_begin + per < g.n ? u_begin + per : g.n;
     __shared__ int s_scan[BLOCK / 64];
     __shared__ unsigned long long s_red[BLOCK / 64];
@@ -706,7 +707,7 @@ PP_DEV void push_slots(const RunDev &R, uint64_t *sig, int r, const int64_t (&k)
 }
 
 template <int W>
-PP_DEV void phase_push(const GraphDev &g, const RunDev &R) {
+PP_DEV void phase_push(const GraphDev &g, const RunDev &R, int bid, int nb) {
     Ctrl *C = R.ctrl;
     const int r = CTL(C->round);
     const int pp = (r - 1) & 1, pn = r & 1;
@@ -717,8 +718,8 @@ PP_DEV void phase_push(const GraphDev &g, const RunDev &R) {
     const uint64_t *dl = R.f_delta[pp];
     const int ln = lane_id();
     const int w = ln & (W - 1);
-    const int64_t wave = (blockIdx.x * (int64_t)BLOCK + threadIdx.x) >> 6;
-    const int64_t nwaves = ((int64_t)gridDim.x * BLOCK) >> 6;
+    const int64_t wave = (bid * (int64_t)BLOCK + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)nb * BLOCK) >> 6;
     __shared__ int32_t s_q[BlockQueue::CAP];
     __shared__ int s_qn, s_qbase;
     BlockQueue bq{s_q, &s_qn};
@@ -813,7 +814,7 @@ PP_DEV void phase_round_end(const GraphDev &g, const RunDev &R, int init, int np
         fnodes = block_sum<long long>(nn, s_red) + CTL(C->hub_nodes);
         farcs = block_sum<long long>(na, s_red) + CTL(C->hub_arcs);
         pulled = block_sum<long long>(np, s_red);
-        if (R.G == 1 && threadIdx.x == 0) R.counts[r] = c + CTL(C->hub_cnt);
+        if (R.G == 1 && threadIdx.x == 0) R.counts[(int64_t)r * R.cstride] = c + CTL(C->hub_cnt);
     } else {
         fnodes = CTL(C->f_count[r & 1]);
         farcs = CTL(C->f_arcs[r & 1]);
@@ -823,7 +824,7 @@ PP_DEV void phase_round_end(const GraphDev &g, const RunDev &R, int init, int np
     int act = 0;
     for (int gi = threadIdx.x; gi < R.G; gi += BLOCK) {
         if (R.gconv[gi]) continue;
-        if (R.counts[(int64_t)r * R.G + gi] == 0) {
+        if (R.counts[(int64_t)r * R.cstride + gi] == 0) {
             R.gconv[gi] = 1;
         } else {
             R.D[gi] = r;
@@ -863,23 +864,23 @@ PP_DEV void phase_round_end(const GraphDev &g, const RunDev &R, int init, int np
 // One launch per phase; a phase whose direction is not the round's returns.
 template <int W> __global__ void __launch_bounds__(BLOCK) k_push_commit(GraphDev g, RunDev R, int init) {
     if (R.ctrl->converged || (!init && R.ctrl->mode != MODE_PUSH)) return;
-    phase_push_commit<W>(g, R, init);
+    phase_push_commit<W>(g, R, init, blockIdx.x, gridDim.x);
 }
 template <int W> __global__ void __launch_bounds__(BLOCK) k_pull(GraphDev g, RunDev R) {
     if (R.ctrl->converged || R.ctrl->mode != MODE_PULL) return;
-    phase_pull<W>(g, R);
+    phase_pull<W>(g, R, blockIdx.x, gridDim.x);
 }
 template <int W> __global__ void __launch_bounds__(BLOCK) k_pull_hubs(GraphDev g, RunDev R) {
     if (R.ctrl->converged || R.ctrl->mode != MODE_PULL) return;
-    phase_pull_hubs<W>(g, R);
+    phase_pull_hubs<W>(g, R, blockIdx.x, gridDim.x);
 }
 template <int W> __global__ void __launch_bounds__(BLOCK) k_frontier(GraphDev g, RunDev R) {
     if (R.ctrl->converged || R.ctrl->mode != MODE_PUSH || R.ctrl->prev_mode != MODE_PULL) return;
-    phase_frontier<W>(g, R);
+    phase_frontier<W>(g, R, blockIdx.x, gridDim.x);
 }
 template <int W> __global__ void __launch_bounds__(BLOCK) k_push(GraphDev g, RunDev R) {
     if (R.ctrl->converged || R.ctrl->mode != MODE_PUSH) return;
-    phase_push<W>(g, R);
+    phase_push<W>(g, R, blockIdx.x, gridDim.x);
 }
 __global__ void __launch_bounds__(BLOCK) k_round_end(GraphDev g, RunDev R, int init) {
     if (R.ctrl->converged) return;
@@ -888,25 +889,26 @@ __global__ void __launch_bounds__(BLOCK) k_round_end(GraphDev g, RunDev R, int i
 
 // ---------------------------------------------------------------- persistent rounds
 
-// Grid-wide barrier for a cooperative launch.  Blocks arrive on one of up to
-// eight group counters (block i in group i % 8, matching the round-robin
-// placement of blocks on the XCDs), the last of a group arrives on the top
-// counter, the last group advances the generation everyone waits on.  The
-// agent-scope fences publish each block's writes before it arrives and make
-// the others' writes visible after it leaves.  A wait longer than about ten
-// seconds sets `abort`; every later barrier and the round loop then return,
-// so the grid always drains.
-PP_DEV bool grid_barrier(GridBar *b) {
+// Barrier among the nb blocks of one cluster (block rank bid).  A cluster of
+// one block only needs the block barrier.  Otherwise blocks arrive on one of
+// up to eight group counters (rank i in group i % 8, matching the
+// round-robin placement of blocks on the XCDs), the last of a group arrives
+// on the top counter, and the last group advances the generation everyone
+// waits on.  The agent-scope fences publish each block's writes before it
+// arrives and make the others' writes visible after it leaves.  A wait longer
+// than about ten seconds sets `abort`; every later barrier and the round loop
+// then return, so the grid always drains.
+PP_DEV bool cluster_barrier(GridBar *b, int bid, int nb) {
     __shared__ int s_abort;
     __syncthreads();
+    if (nb == 1) return CTL(b->abort) == 0;
     if (threadIdx.x == 0) {
-        const uint32_t nb = gridDim.x;
-        const uint32_t ng = nb < 8 ? nb : 8;
-        const uint32_t grp = blockIdx.x % ng;
-        const uint32_t gsize = nb / ng + (grp < nb % ng ? 1u : 0u);
-        int ab = __hip_atomic_load(&b->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t ng = nb < 8 ? (uint32_t)nb : 8u;
+        const uint32_t grp = (uint32_t)bid % ng;
+        const uint32_t gsize = (uint32_t)nb / ng + (grp < (uint32_t)nb % ng ? 1u : 0u);
+        int ab = CTL(b->abort);
         if (!ab) {
-            const uint32_t gen = __hip_atomic_load(&b->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const uint32_t gen = CTL(b->gen);
             __threadfence();
             if (atomicAdd(&b->grp[grp], 1u) + 1 == gsize) {
                 atomicExch(&b->grp[grp], 0u);
@@ -918,16 +920,16 @@ PP_DEV bool grid_barrier(GridBar *b) {
                 }
             }
             const uint64_t t0 = wall_clock64();
-            while (__hip_atomic_load(&b->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+            while (CTL(b->gen) == gen) {
                 __builtin_amdgcn_s_sleep(2);
                 if (wall_clock64() - t0 > 1000000000ull) {   // ~10 s at 100 MHz
                     atomicExch(&b->abort, 1);
                     break;
                 }
-                if (__hip_atomic_load(&b->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+                if (CTL(b->abort)) break;
             }
             __threadfence();
-            ab = __hip_atomic_load(&b->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            ab = CTL(b->abort);
         }
         s_abort = ab;
     }
@@ -935,45 +937,124 @@ PP_DEV bool grid_barrier(GridBar *b) {
     return s_abort == 0;
 }
 
-// All rounds up to max_round in one cooperative launch.  Every block runs
-// every phase and every barrier; the loop condition is read by all blocks
-// after a barrier, so they leave together.  Block 0 also logs device-clock
-// stamps per round: [start, after the main phase, end].
+// The slice of a batch that one cluster runs: graph cl.g as a graph of its
+// own (its node range, tiles, hubs, list regions, log rows, control block).
+PP_DEV void cluster_view(const GraphDev &g, const RunDev &R, const Cluster &cl, GraphDev &gv, RunDev &rv) {
+    gv = g;
+    gv.n0 = cl.n0;
+    gv.n = cl.n1;
+    gv.m = cl.m;
+    gv.tiles = g.tiles + cl.t0;
+    gv.ntiles = cl.t1 - cl.t0;
+    gv.hub_node = g.hub_node + cl.h0;
+    gv.nhubs = cl.h1 - cl.h0;
+    gv.G = 1;
+    gv.pull_grid = cl.nb;
+    rv = R;
+    rv.G = 1;
+    rv.ctrl = R.ctrl + cl.g;
+    rv.bar = R.bar + cl.g;
+    rv.counts = R.counts + cl.g;
+    rv.seed_counts = R.seed_counts ? R.seed_counts + (int64_t)cl.g * R.s : nullptr;
+    rv.D = R.D + cl.g;
+    rv.gconv = R.gconv + cl.g;
+    rv.mode_log = R.mode_log + (int64_t)cl.g * R.cap;
+    rv.arcs_log = R.arcs_log + (int64_t)cl.g * R.cap;
+    rv.phase_log = R.phase_log + (int64_t)cl.g * R.cap * 3;
+    const int W = R.W;
+    for (int k = 0; k < 2; ++k) {
+        rv.f_ids[k] = R.f_ids[k] + cl.n0;
+        rv.f_delta[k] = R.f_delta[k] + cl.n0 * W;
+        rv.chunks[k] = R.chunks[k] + cl.ch0;
+    }
+    rv.blk_cnt = R.blk_cnt + cl.b0;
+    rv.blk_nodes = R.blk_nodes + cl.b0;
+    rv.blk_arcs = R.blk_arcs + cl.b0;
+    rv.blk_pulled = R.blk_pulled + cl.b0;
+}
+
+// Every graph of a batch in one cooperative launch: cluster c (a range of
+// co-resident blocks) runs graph clusters[c].g round after round, with
+// barriers among its own blocks only, until the graph converges or its round
+// passes max_round.  A graph still at round 0 is first initialised (its seed
+// bits were scattered by k_seed_scatter_batch).  Every block of a cluster
+// runs every phase and every barrier of its cluster; the loop condition is
+// read by all of them after a barrier, so they leave together.  Rank 0 logs
+// device-clock stamps per round: [start, after the main phase, end].
 template <int W>
-__global__ void __launch_bounds__(BLOCK) k_rounds(GraphDev g, RunDev R, int max_round) {
-    Ctrl *C = R.ctrl;
-    GridBar *bar = R.bar;
-    const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+__global__ void __launch_bounds__(BLOCK) k_batch(GraphDev g, RunDev R, const Cluster *clusters, int nclusters,
+                                                 int max_round) {
+    int lo = 0, hi = nclusters - 1;   // cluster holding this block
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (clusters[mid].b0 <= (int)blockIdx.x) lo = mid; else hi = mid - 1;
+    }
+    const Cluster cl = clusters[lo];
+    const int bid = (int)blockIdx.x - cl.b0;
+    const int nb = cl.nb;
+    if (bid >= nb) return;   // spare block outside every cluster: never waited for
+    GraphDev gv;
+    RunDev rv;
+    cluster_view(g, R, cl, gv, rv);
+    Ctrl *C = rv.ctrl;
+    GridBar *bar = rv.bar;
+    const bool lead = bid == 0 && threadIdx.x == 0;
+    if (CTL(C->round) == 0 && !CTL(C->converged)) {
+        phase_push_commit<W>(gv, rv, 1, bid, nb);
+        if (!cluster_barrier(bar, bid, nb)) return;
+        if (bid == 0) phase_round_end(gv, rv, 1, nb);
+        if (!cluster_barrier(bar, bid, nb)) return;
+    }
     for (;;) {
         const int conv = CTL(C->converged);
         const int r = CTL(C->round);
         const int mode = CTL(C->mode);
         const int prev = CTL(C->prev_mode);
         if (conv || r > max_round || CTL(bar->abort)) break;
-        int64_t *stamp = (R.phase_log && r < R.cap) ? R.phase_log + (int64_t)r * 3 : nullptr;
+        int64_t *stamp = r < rv.cap ? rv.phase_log + (int64_t)r * 3 : nullptr;
         if (lead && stamp) stamp[0] = (int64_t)wall_clock64();
         if (mode == MODE_PUSH) {
             if (prev == MODE_PULL) {
-                phase_frontier<W>(g, R);
-                if (!grid_barrier(bar)) break;
+                phase_frontier<W>(gv, rv, bid, nb);
+                if (!cluster_barrier(bar, bid, nb)) break;
             }
-            phase_push<W>(g, R);
-            if (!grid_barrier(bar)) break;
+            phase_push<W>(gv, rv, bid, nb);
+            if (!cluster_barrier(bar, bid, nb)) break;
             if (lead && stamp) stamp[1] = (int64_t)wall_clock64();
-            phase_push_commit<W>(g, R, 0);
-            if (!grid_barrier(bar)) break;
+            phase_push_commit<W>(gv, rv, 0, bid, nb);
+            if (!cluster_barrier(bar, bid, nb)) break;
         } else {
-            phase_pull<W>(g, R);
-            if (!grid_barrier(bar)) break;
+            phase_pull<W>(gv, rv, bid, nb);
+            if (!cluster_barrier(bar, bid, nb)) break;
             if (lead && stamp) stamp[1] = (int64_t)wall_clock64();
-            if (g.nhubs) {
-                phase_pull_hubs<W>(g, R);
-                if (!grid_barrier(bar)) break;
+            if (gv.nhubs) {
+                phase_pull_hubs<W>(gv, rv, bid, nb);
+                if (!cluster_barrier(bar, bid, nb)) break;
             }
         }
-        if (blockIdx.x == 0) phase_round_end(g, R, 0, gridDim.x);
+        if (bid == 0) phase_round_end(gv, rv, 0, nb);
         if (lead && stamp) stamp[2] = (int64_t)wall_clock64();
-        if (!grid_barrier(bar)) break;
+        if (!cluster_barrier(bar, bid, nb)) break;
+    }
+}
+
+// Seed bits for the clustered engine: like k_seed_scatter, but each graph's
+// seed nodes go to its own region of list 0 and its own control block.
+template <int W>
+__global__ void __launch_bounds__(BLOCK) k_seed_scatter_batch(GraphDev g, RunDev R, const int32_t *seeds, int64_t total) {
+    for (int64_t j = blockIdx.x * (int64_t)BLOCK + threadIdx.x; j < total; j += (int64_t)gridDim.x * BLOCK) {
+        const int i = (int)(j % R.s);
+        const int gi = (int)(j / R.s);
+        const int32_t x = seeds[j];
+        const int64_t n0 = g.node_off[gi];
+        const bool ok = x >= n0 && x < g.node_off[gi + 1];
+        if (!ok) atomicOr(&R.ctrl[0].bad_seed, 1);
+        if (!ok) continue;
+        atomicOr((unsigned long long *)&R.acc[(int64_t)x * W + (i >> 6)], 1ull << (i & 63));
+        if (atomicMax(&R.stamp[x], 0) < 0) {
+            const int pos = atomicAdd(&R.ctrl[gi].f_count[0], 1);
+            R.f_ids[0][n0 + pos] = x;
+        }
     }
 }
 
@@ -1042,14 +1123,14 @@ hipError_t launch_round(const GraphDev &g, const RunDev &R, hipStream_t st, hipE
 
 namespace pp {
 
-template <int W> static const void *rounds_fn() { return reinterpret_cast<const void *>(&k_rounds<W>); }
+template <int W> static const void *batch_fn() { return reinterpret_cast<const void *>(&k_batch<W>); }
 
-static const void *rounds_kernel(int W) {
+static const void *batch_kernel(int W) {
     switch (W) {
-        case 1: return rounds_fn<1>();
-        case 2: return rounds_fn<2>();
-        case 4: return rounds_fn<4>();
-        default: return rounds_fn<8>();
+        case 1: return batch_fn<1>();
+        case 2: return batch_fn<2>();
+        case 4: return batch_fn<4>();
+        default: return batch_fn<8>();
     }
 }
 
@@ -1057,17 +1138,36 @@ int persistent_grid(int W) {
     int dev = 0, cus = 0, per = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, rounds_kernel(W), BLOCK, 0) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, batch_kernel(W), BLOCK, 0) != hipSuccess) return 0;
     if (per > 4) per = 4;
     return per * cus;
 }
 
-hipError_t launch_rounds_persistent(const GraphDev &g, const RunDev &R, int grid, int max_round, hipStream_t st) {
+hipError_t launch_batch_persistent(const GraphDev &g, const RunDev &R, const Cluster *clusters, int nclusters,
+                                   int grid, int max_round, hipStream_t st) {
     GraphDev gg = g;
     RunDev rr = R;
+    const Cluster *cc = clusters;
+    int nc = nclusters;
     int mr = max_round;
-    void *args[] = {&gg, &rr, &mr};
-    return hipLaunchCooperativeKernel(rounds_kernel(R.W), dim3(grid), dim3(BLOCK), args, 0, st);
+    void *args[] = {&gg, &rr, &cc, &nc, &mr};
+    return hipLaunchCooperativeKernel(batch_kernel(R.W), dim3(grid), dim3(BLOCK), args, 0, st);
+}
+
+template <int W> static hipError_t scatter_batch_impl(const GraphDev &g, const RunDev &R, const int32_t *seeds, hipStream_t st) {
+    const int64_t total = (int64_t)R.G * R.s;
+    hipLaunchKernelGGL(k_seed_scatter_batch<W>, dim3(fill_grid(total)), dim3(BLOCK), 0, st, g, R, seeds, total);
+    return hipGetLastError();
+}
+
+hipError_t launch_seed_scatter_batch(const GraphDev &g, const RunDev &R, const int32_t *seeds, hipStream_t st) {
+    switch (R.W) {
+        case 1: return scatter_batch_impl<1>(g, R, seeds, st);
+        case 2: return scatter_batch_impl<2>(g, R, seeds, st);
+        case 4: return scatter_batch_impl<4>(g, R, seeds, st);
+        case 8: return scatter_batch_impl<8>(g, R, seeds, st);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace pp
