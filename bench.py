@@ -152,6 +152,77 @@ def bench_batch(args, torch, pp):
     print(json.dumps(out), flush=True)
 
 
+def bench_grid(args, torch, pp):
+    """Large-diameter grid with the learned direction scheduler vs the fixed heuristic.
+
+    The cost model is trained on this method's own round timings: every round
+    of two training graphs (same family, other generator seeds) is timed in
+    both directions after both kinds of previous round, the best schedule of
+    each is solved exactly, and the model is fitted to the resulting per-round
+    direction costs by the library's device training kernels.  The held-out
+    graph (generator seed 1) is then run to convergence with the heuristic and
+    with the model; both give the same counts (checked here).
+    """
+    from paper_2301_06499_amd import inputs
+    from paper_2301_06499_amd import scheduler as S
+    side = args.grid_side
+    tables = []
+    t_prep = time.perf_counter()
+    for gs in (2, 3):
+        g, sd = inputs.workload_grid_shortcuts(side, 128, gs)
+        Gt = pp.pp_csr_build(g.n, g.src, g.dst, undirected=True)
+        tables.append(S.measure(Gt, sd))
+        Gt.free()
+        log(f"[bench] timed {len(tables[-1])} rounds of training graph {gs} both ways")
+    samples = S.Samples.concat(S.label(t) for t in tables)
+    t0 = time.perf_counter()
+    params, losses = S.train(samples, steps=4000)
+    t_train = time.perf_counter() - t0
+    log(f"[bench] trained on {len(samples)} samples in {t_train:.2f} s, loss {losses[0]:.3f} -> {losses[-1]:.5f}")
+    g, seeds = inputs.workload_grid_shortcuts(side, 128, 1)
+    G = pp.pp_csr_build(g.n, g.src, g.dst, undirected=True)
+    held = S.measure(G, seeds)
+    _, best_ms, _ = S.optimal_schedule(held)
+    t_prep = time.perf_counter() - t_prep
+    reps = max(1, args.steps)
+    runs = {}
+    for name, sch, params_ in (("heuristic", pp.PP_SCHED_HEURISTIC, None), ("learned", pp.PP_SCHED_MLP, params)):
+        S.timed_run(G, seeds, sch, params_, repeats=max(1, args.warmup))
+        runs[name] = S.timed_run(G, seeds, sch, params_, repeats=reps)
+        log(f"[bench] {name}: {runs[name][0]:.3f} ms")
+    (t_h, c_h, D_h, m_h), (t_l, c_l, D_l, m_l) = runs["heuristic"], runs["learned"]
+    assert int(D_h[0]) == int(D_l[0]) and list(c_h[0]) == list(c_l[0]), "schedules changed the counts"
+    rounds = int(D_l[0]) + 1
+    W = 2
+    nominal = float(G.arcs) * W * rounds
+    out = {
+        "metric": METRIC,
+        "value": nominal / (t_l / 1000.0),
+        "unit": "edge-words/s",
+        "n_gpus": 1, "steps": reps, "warmup": args.warmup,
+        "ms_per_step": round(t_l, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u64", "data": "synthetic",
+        "config": {"workload": f"grid{side}x{side}_del10pct_sc1000_lcc_s128", "nodes": G.nodes, "arcs": G.arcs,
+                   "words": W, "rounds": rounds, "scheduler": "learned (MLP 8-32-32-2), heuristic fallback",
+                   "timing": "best of steps, whole propagation with graph replay, host clock around "
+                             "synchronous library calls"},
+        "heuristic": {"ms_per_step": round(t_h, 4), "value": nominal / (t_h / 1000.0),
+                      "pulls": int((m_h[1:rounds + 1] == pp.MODE_PULL).sum())},
+        "learned": {"pulls": int((m_l[1:rounds + 1] == pp.MODE_PULL).sum()),
+                    "training_samples": len(samples), "train_s": round(t_train, 3),
+                    "final_loss": float(losses[-1])},
+        "speedup_vs_heuristic": round(t_h / t_l, 4),
+        "held_out_table_ms": {"optimal": round(best_ms, 3),
+                              "heuristic": round(S.policy_cost(held, S.heuristic_policy())[0], 3),
+                              "learned": round(S.policy_cost(held, S.model_policy(params, held))[0], 3),
+                              "all_pull": round(S.policy_cost(held, lambda r, f: pp.MODE_PULL)[0], 3)},
+        "prep_s": round(t_prep, 1),
+        "roofline": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def cpu_baseline(g, seeds, nominal_edge_words: float, budget_s: float):
     """The oracle (not tuned) on the host cores; a seed sample sized to the budget."""
     import oracle
@@ -183,6 +254,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="rmat20")
     ap.add_argument("--scheduler", default="heuristic", choices=["heuristic", "pull", "push"])
+    ap.add_argument("--grid-side", type=int, default=4096, help="side of the grid4096 workload")
     ap.add_argument("--persistent", action="store_true",
                     help="all rounds in one cooperative launch instead of launches per round")
     ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work for cpu_baseline")
@@ -206,6 +278,8 @@ def main():
     sched = {"heuristic": pp.PP_SCHED_HEURISTIC, "pull": pp.PP_SCHED_PULL, "push": pp.PP_SCHED_PUSH}[args.scheduler]
     if args.workload == "batch64":
         return bench_batch(args, torch, pp)
+    if args.workload == "grid4096":
+        return bench_grid(args, torch, pp)
 
     t0 = time.perf_counter()
     g, seeds, cfg = workload(args.workload)

@@ -226,6 +226,67 @@ int pp_get_kernel_times(pp_run r, float *pull_ms, int32_t cap);
 int pp_run_snapshot(pp_run r, pp_run *copy);
 int pp_run_restore(pp_run r, pp_run from);
 
+/*
+ * Learned direction scheduler.  Every round of PROPAGATE-P (Algorithm 1)
+ * computes the same Sig_r whether it pulls (each node ORs its successors'
+ * signatures) or pushes (each changed node ORs its delta into its
+ * predecessors); the direction only changes the cost.  PP_SCHED_MLP picks,
+ * before each round, the direction with the smaller predicted cost of a
+ * cost model evaluated on the device from eight features of the last round
+ * (all normalised to about [0, 1]):
+ *   f0 nodes changed / n            f1 their predecessor arcs / stored arcs
+ *   f2 pairs reached past the seeds / (n s)
+ *   f3 new pairs of the round / (n s)
+ *   f4 min(c[r] / max(c[r-1], 1), 4) / 4   (c[-1] = 0)
+ *   f5 log2(index of the next round + 1) / 16
+ *   f6 log2(f1's arcs / max(f0's nodes, 1) + 1) / 16
+ *   f7 1 if the last round pulled, else 0
+ * The model is a fully connected network 8 -> 32 -> 32 -> 2, ReLU on both
+ * hidden layers, outputs y0 (pull) and y1 (push) in log-milliseconds; pull
+ * is taken when y0 <= y1.  Weights are PP_MLP_PARAMS floats in the order
+ * W1[32][8], b1[32], W2[32][32], b2[32], W3[2][32], b3[2] (row = output
+ * unit).  A non-finite output, or weights never set, falls back to the
+ * heuristic.  The scheduler never changes a result bit, only the work.
+ */
+#define PP_MLP_PARAMS 1410
+
+/* Sets the run's cost-model weights (host array of PP_MLP_PARAMS floats,
+ * copied) or clears them (NULL: the heuristic decides).  Used only when the
+ * run was created with scheduler = PP_SCHED_MLP.  The direction of the
+ * round about to run (taken at the end of the last round, for a new run at
+ * pp_seeds_init) is taken again with the new weights.  The weights persist
+ * across pp_seeds_reset.  Synchronises. */
+int pp_run_set_mlp(pp_run r, const float *params);
+
+/* Scheduler features of every round: feat[r][8] (host, cap rows) holds the
+ * features computed at the end of round r-1 for round r; row 0 is zero. */
+int pp_get_round_features(pp_run r, float *feat, int32_t cap);
+
+/* Training samples for the cost model.  Runs the next round of a run on the
+ * per-round engine in the given direction (PP_MODE_PULL or PP_MODE_PUSH)
+ * instead of the scheduler's, and stores its duration in milliseconds in
+ * *ms (HIP events around the whole round, every launch of the round
+ * included).  features (host [8] or NULL) receives the round's features.
+ * With pp_run_snapshot / pp_run_restore a caller times a round both ways,
+ * and after either kind of previous round.  PP_ESTATE if the run has
+ * converged or is persistent; PP_ENOTCONV if its round log is full. */
+enum { PP_MODE_PULL = 0, PP_MODE_PUSH = 1 };
+int pp_time_round(pp_run r, int32_t mode, float *features, float *ms);
+
+/* The cost model on the device, for training and its tests.  All arrays
+ * are host memory owned by the caller; n samples, 1 <= n <= 2^26; rows are
+ * samples (x[n][8], t and y [n][2]); fp32 arithmetic, sums over samples in
+ * double in a fixed order (bit-reproducible).  Synchronous. */
+/* y = model(x). */
+int pp_mlp_forward(const float *params, const float *x, int64_t n, float *y);
+/* loss = 1/(2n) sum_n sum_k (y_nk - t_nk)^2 and its gradient with respect to
+ * every parameter (grad [PP_MLP_PARAMS]); either output may be NULL. */
+int pp_mlp_loss_grad(const float *params, const float *x, const float *t, int64_t n, float *grad, float *loss);
+/* `steps` full-batch Adam steps (beta1 0.9, beta2 0.999, eps 1e-8, learning
+ * rate lr, moments starting at zero) on that loss; params is updated in
+ * place; loss_log (host [steps] or NULL) receives the loss before each step. */
+int pp_mlp_train(float *params, const float *x, const float *t, int64_t n, int32_t steps, float lr, float *loss_log);
+
 void pp_run_free(pp_run r);
 void pp_graph_free(pp_graph g);
 const char *pp_last_error(void);

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <atomic>
 #include <cstdarg>
 #include <cstdio>
@@ -25,6 +26,8 @@ using pp::Tile;
 namespace {
 
 thread_local std::string g_err;
+
+constexpr int32_t kNaNBits = 0x7fc00000;   // quiet NaN (unset cost-model weights)
 
 int fail(int code, const char *fmt, ...) {
     char buf[512];
@@ -124,6 +127,7 @@ struct pp_run_s {
     pp::Cluster *dclusters = nullptr;
     std::vector<int> cur;                   // signature buffer of Sig_{round-1}, per control block
     double clock_khz = 100000.0;            // device wall clock rate
+    hipEvent_t tev[2] = {nullptr, nullptr}; // events of pp_time_round
 };
 
 extern "C" {
@@ -460,6 +464,8 @@ void free_run_dev(RunDev &d) {
     dev_free(d.ctrl);
     dev_free(d.bar);
     dev_free(d.phase_log);
+    dev_free(d.feat_log);
+    dev_free(d.mlp);
 }
 
 void drop_graphs(pp_run r) {
@@ -477,6 +483,8 @@ void free_run(pp_run r) {
     dev_free(r->dseeds);
     dev_free(r->dclusters);
     for (hipEvent_t e : r->ev) (void)hipEventDestroy(e);
+    for (hipEvent_t e : r->tev)
+        if (e) (void)hipEventDestroy(e);
     if (r->own_stream && r->stream) (void)hipStreamDestroy(r->stream);
     delete r;
 }
@@ -506,7 +514,8 @@ int alloc_run_dev(pp_graph g, RunDev &d, int s, int W, int cap, bool seed_counts
         (rc = dev_alloc(&d.counts, (int64_t)cap * G)) || (rc = dev_alloc(&d.D, G)) || (rc = dev_alloc(&d.gconv, G)) ||
         (rc = dev_alloc(&d.mode_log, (int64_t)cap * G)) || (rc = dev_alloc(&d.arcs_log, (int64_t)cap * G)) ||
         (rc = dev_alloc(&d.ctrl, G)) || (rc = dev_alloc(&d.bar, G)) ||
-        (rc = dev_alloc(&d.phase_log, (int64_t)cap * 3 * G)))
+        (rc = dev_alloc(&d.phase_log, (int64_t)cap * 3 * G)) ||
+        (rc = dev_alloc(&d.feat_log, (int64_t)cap * pp::MLP_IN * G)) || (rc = dev_alloc(&d.mlp, pp::MLP_PARAMS)))
         return rc;
     if (seed_counts && (rc = dev_alloc(&d.seed_counts, (int64_t)cap * G * s))) return rc;
     if (!seed_counts) d.seed_counts = nullptr;
@@ -529,6 +538,7 @@ hipError_t clear_run_dev(pp_graph g, RunDev &d, hipStream_t st) {
     if ((e = pp::launch_fill_u64((uint64_t *)d.arcs_log, 0, (int64_t)d.cap * G, st))) return e;
     if ((e = pp::launch_fill_i32((int32_t *)d.bar, 0, G * (int64_t)(sizeof(pp::GridBar) / 4), st))) return e;
     if ((e = pp::launch_fill_u64((uint64_t *)d.phase_log, 0, (int64_t)d.cap * 3 * G, st))) return e;
+    if ((e = pp::launch_fill_i32((int32_t *)d.feat_log, 0, (int64_t)d.cap * pp::MLP_IN * G, st))) return e;
     return pp::launch_fill_i32((int32_t *)d.ctrl, 0, G * (int64_t)(sizeof(Ctrl) / 4), st);
 }
 
@@ -556,6 +566,16 @@ int sync_ctrl(pp_run r) {
 }
 
 }  // namespace
+
+int pp::set_error(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
 
 namespace {
 
@@ -723,11 +743,13 @@ extern "C" int pp_seeds_init(pp_graph g, const int32_t *seeds, int32_t s, const 
         free_run(r);
         return rc;
     }
-    r->dev.sched = o.scheduler == PP_SCHED_MLP ? PP_SCHED_HEURISTIC : o.scheduler;
+    r->dev.sched = o.scheduler;
     r->dev.push_div = o.push_div;
     r->dev.fuzz_seed = o.fuzz_seed;
-    r->dev.mlp = nullptr;
-    hipError_t e = hipMemcpyAsync(r->dseeds, seeds, sizeof(int32_t) * (size_t)G * s, hipMemcpyHostToDevice, r->stream);
+    // cost-model weights start as NaN: the heuristic decides until they are set
+    hipError_t e = pp::launch_fill_i32((int32_t *)r->dev.mlp, kNaNBits, pp::MLP_PARAMS, r->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(r->dseeds, seeds, sizeof(int32_t) * (size_t)G * s, hipMemcpyHostToDevice, r->stream);
     if (e != hipSuccess) {
         free_run(r);
         return fail(PP_EDEVICE, "seed upload: %s", hipGetErrorString(e));
@@ -1004,7 +1026,6 @@ extern "C" int pp_run_snapshot(pp_run r, pp_run *copy) {
     c->dev.sched = r->dev.sched;
     c->dev.push_div = r->dev.push_div;
     c->dev.fuzz_seed = r->dev.fuzz_seed;
-    c->dev.mlp = r->dev.mlp;
     rc = pp_run_restore(c, r);
     if (rc) {
         free_run(c);
@@ -1042,6 +1063,8 @@ extern "C" int pp_run_restore(pp_run r, pp_run from) {
     if (!e) e = cp(b.mode_log, a.mode_log, 4 * cap * G);
     if (!e) e = cp(b.arcs_log, a.arcs_log, 8 * cap * G);
     if (!e) e = cp(b.phase_log, a.phase_log, 8 * cap * 3 * G);
+    if (!e) e = cp(b.feat_log, a.feat_log, sizeof(float) * pp::MLP_IN * cap * G);
+    if (!e) e = cp(b.mlp, a.mlp, sizeof(float) * pp::MLP_PARAMS);
     if (!e) e = cp(b.ctrl, a.ctrl, sizeof(Ctrl) * G);
     if (!e) e = cp(b.bar, a.bar, sizeof(pp::GridBar) * G);
     if (!e) e = hipStreamSynchronize(st);
@@ -1056,4 +1079,50 @@ extern "C" int pp_get_kernel_times(pp_run r, float *pull_ms, int32_t cap) {
     if (!r->timing) return fail(PP_ESTATE, "run was created without time_kernels");
     for (int32_t k = 0; k < cap; ++k) pull_ms[k] = k < r->cap ? r->pull_ms[(size_t)k] : 0.0f;
     return PP_OK;
+}
+
+extern "C" int pp_run_set_mlp(pp_run r, const float *params) {
+    if (!r) return fail(PP_EINVAL, "run is NULL");
+    if (params) {
+        HIP_TRY(hipMemcpyAsync(r->dev.mlp, params, sizeof(float) * pp::MLP_PARAMS, hipMemcpyHostToDevice, r->stream));
+    } else {
+        HIP_TRY(pp::launch_fill_i32((int32_t *)r->dev.mlp, kNaNBits, pp::MLP_PARAMS, r->stream));
+    }
+    // the next round's direction was taken with the old weights
+    if (params) HIP_TRY(pp::launch_redecide(r->dev, r->G, r->stream));
+    HIP_TRY(hipStreamSynchronize(r->stream));
+    return sync_ctrl(r);
+}
+
+extern "C" int pp_get_round_features(pp_run r, float *feat, int32_t cap) {
+    if (!r || !feat) return fail(PP_EINVAL, "run or feat is NULL");
+    const int rows = std::min(cap, r->cap);
+    if (rows < 1) return fail(PP_EINVAL, "cap < 1");
+    HIP_TRY(hipMemcpyAsync(feat, r->dev.feat_log, sizeof(float) * pp::MLP_IN * rows, hipMemcpyDeviceToHost, r->stream));
+    HIP_TRY(hipStreamSynchronize(r->stream));
+    return PP_OK;
+}
+
+extern "C" int pp_time_round(pp_run r, int32_t mode, float *features, float *ms) {
+    if (!r || !ms) return fail(PP_EINVAL, "run or ms is NULL");
+    if (mode != pp::MODE_PULL && mode != pp::MODE_PUSH) return fail(PP_EINVAL, "mode %d is neither pull (0) nor push (1)", mode);
+    if (r->pgrid) return fail(PP_ESTATE, "timing of single rounds needs the per-round engine");
+    int rc = sync_ctrl(r);
+    if (rc) return rc;
+    if (r->host_ctrl.converged) return fail(PP_ESTATE, "run has converged");
+    if (r->host_ctrl.round >= r->cap - 1) return fail(PP_ENOTCONV, "round log full (max_rounds)");
+    if (features)
+        for (int i = 0; i < pp::MLP_IN; ++i) features[i] = r->host_ctrl.feat[i];
+    for (auto &e : r->tev)
+        if (!e) HIP_TRY(hipEventCreate(&e));
+    GraphDev gv = graph_view(r->g, run_tiles(r));
+    // every direction is valid in every round: forcing one changes the work
+    // done, never the result
+    HIP_TRY(hipMemcpyAsync(&r->dev.ctrl[0].mode, &mode, sizeof(int32_t), hipMemcpyHostToDevice, r->stream));
+    HIP_TRY(hipEventRecord(r->tev[0], r->stream));
+    HIP_TRY(pp::launch_round(gv, r->dev, r->stream));
+    HIP_TRY(hipEventRecord(r->tev[1], r->stream));
+    HIP_TRY(hipEventSynchronize(r->tev[1]));
+    HIP_TRY(hipEventElapsedTime(ms, r->tev[0], r->tev[1]));
+    return sync_ctrl(r);
 }

@@ -76,8 +76,23 @@ struct Ctrl {
     int64_t hub_cnt;      // new bits found by the hub kernel this round
     int64_t hub_nodes;    // hubs that changed this round
     int64_t hub_arcs;     // their predecessor arcs
-    int64_t pad;
+    int64_t reached;      // new bits of every round so far (R[r] - s)
+    int64_t last_count;   // new bits of the last round
+    float feat[8];        // scheduler features of the round about to run
 };
+
+// Learned cost model: an MLP 8 -> 32 -> 32 -> 2 (ReLU) predicting the log of a
+// round's duration under pull (output 0) and push (output 1).  Parameter
+// layout (floats): W1[32][8], b1[32], W2[32][32], b2[32], W3[2][32], b3[2].
+constexpr int MLP_IN = 8, MLP_HID = 32, MLP_OUT = 2;
+constexpr int MLP_W1 = 0;
+constexpr int MLP_B1 = MLP_W1 + MLP_HID * MLP_IN;
+constexpr int MLP_W2 = MLP_B1 + MLP_HID;
+constexpr int MLP_B2 = MLP_W2 + MLP_HID * MLP_HID;
+constexpr int MLP_W3 = MLP_B2 + MLP_HID;
+constexpr int MLP_B3 = MLP_W3 + MLP_OUT * MLP_HID;
+constexpr int MLP_PARAMS = MLP_B3 + MLP_OUT;   // 1410
+static_assert(MLP_PARAMS == PP_MLP_PARAMS, "cost-model layout");
 
 // State of the grid barrier of the persistent round loop (zero at start).
 struct GridBar {
@@ -140,18 +155,25 @@ struct RunDev {
     int32_t *mode_log;    // [G][cap] (row 0 when the graphs run as one union)
     int64_t *arcs_log;    // [G][cap]
     int64_t *phase_log;   // [G][cap][3] device-clock stamps of the persistent loop
+    float *feat_log;      // [G][cap][8] scheduler features of each round (row 0 unused)
     GridBar *bar;         // [G] barrier state per cluster
     Ctrl *ctrl;           // [G]: ctrl[0] for the per-round engine, one per graph when clustered
     // scheduler
     int32_t sched;
     int32_t push_div;
     uint64_t fuzz_seed;
-    const float *mlp;     // cost-model weights or NULL
+    float *mlp;           // [MLP_PARAMS] cost-model weights (NaN: not set, heuristic decides)
 };
+
+// Records the message returned by pp_last_error and returns `code`.
+int set_error(int code, const char *fmt, ...);
 
 // Launchers (pp_kernels.hip).  All enqueue on `st` and return the launch status.
 hipError_t launch_fill_u64(uint64_t *p, uint64_t v, int64_t count, hipStream_t st);
 hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t count, hipStream_t st);
+// Re-takes the pending direction of each of the first nctrl control blocks
+// with the run's current cost-model weights (PP_SCHED_MLP runs only).
+hipError_t launch_redecide(const RunDev &r, int nctrl, hipStream_t st);
 hipError_t launch_seed_init(const GraphDev &g, const RunDev &r, const int32_t *seeds_dev, hipStream_t st);
 // One round; when e0/e1 are given they are recorded around the pull launch.
 hipError_t launch_round(const GraphDev &g, const RunDev &r, hipStream_t st, hipEvent_t e0 = nullptr,

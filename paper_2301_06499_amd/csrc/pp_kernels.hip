@@ -794,6 +794,49 @@ PP_DEV int32_t schedule(const GraphDev &g, const RunDev &R, int32_t r, int64_t f
     }
 }
 
+// The eight frontier features of the round after `r` (each roughly in [0, 1]):
+// changed nodes / n, their predecessor arcs / m, reached (node, seed) pairs /
+// (n s), new bits of round r / (n s), growth of the new-bit count (ratio to
+// the round before, clipped at 4, / 4), log2(r + 1) / 16, log2 of the mean
+// predecessor degree of the changed nodes / 16, and whether round r pulled.
+PP_DEV void sched_features(const GraphDev &g, const RunDev &R, int r, int mode, int64_t fnodes, int64_t farcs,
+                           int64_t cnt, int64_t reached, int64_t last, float (&f)[MLP_IN]) {
+    const double nv = (double)(g.n - g.n0 > 0 ? g.n - g.n0 : 1);
+    const double mv = (double)(g.m > 0 ? g.m : 1);
+    const double pairs = nv * (double)R.s;
+    f[0] = (float)((double)fnodes / nv);
+    f[1] = (float)((double)farcs / mv);
+    f[2] = (float)((double)reached / pairs);
+    f[3] = (float)((double)cnt / pairs);
+    const double grow = (double)cnt / (double)(last > 0 ? last : 1);
+    f[4] = (float)((grow < 4.0 ? grow : 4.0) / 4.0);
+    f[5] = (float)(log2((double)r + 1.0) / 16.0);
+    f[6] = (float)(log2((double)farcs / (double)(fnodes > 0 ? fnodes : 1) + 1.0) / 16.0);
+    f[7] = mode == MODE_PULL ? 1.0f : 0.0f;
+}
+
+// MLP inference by one wave: lane j < 32 computes hidden unit j of each layer;
+// the hidden values move between lanes by shuffles.  Returns the direction
+// with the smaller predicted time, or `fallback` if a prediction is not
+// finite.  The whole wave must call.
+PP_DEV int32_t mlp_decide(const float *w, const float (&f)[MLP_IN], int32_t fallback) {
+    const int j = lane_id();
+    const int jj = j & (MLP_HID - 1);
+    float h1 = w[MLP_B1 + jj];
+#pragma unroll
+    for (int i = 0; i < MLP_IN; ++i) h1 += w[MLP_W1 + jj * MLP_IN + i] * f[i];
+    h1 = h1 > 0.0f ? h1 : 0.0f;
+    float h2 = w[MLP_B2 + jj];
+    for (int i = 0; i < MLP_HID; ++i) h2 += w[MLP_W2 + jj * MLP_HID + i] * __shfl(h1, i);
+    h2 = h2 > 0.0f ? h2 : 0.0f;
+    const int k = j & 1;
+    float o = w[MLP_B3 + k];
+    for (int i = 0; i < MLP_HID; ++i) o += w[MLP_W3 + k * MLP_HID + i] * __shfl(h2, i);
+    const float o0 = __shfl(o, 0), o1 = __shfl(o, 1);
+    if (!__builtin_isfinite(o0) || !__builtin_isfinite(o1)) return fallback;
+    return o0 <= o1 ? MODE_PULL : MODE_PUSH;
+}
+
 // nparts: blocks of the pull that left per-block partials.
 PP_DEV void phase_round_end(const GraphDev &g, const RunDev &R, int init, int nparts) {
     Ctrl *C = R.ctrl;
@@ -801,6 +844,7 @@ PP_DEV void phase_round_end(const GraphDev &g, const RunDev &R, int init, int np
     const int mode = init ? MODE_INIT : CTL(C->mode);
     __shared__ long long s_red[BLOCK / 64];
     __shared__ int s_active;
+    __shared__ int s_next;
     long long fnodes = 0, farcs = 0, pulled = 0;
     if (mode == MODE_PULL) {
         long long c = 0, nn = 0, na = 0, np = 0;
@@ -822,9 +866,12 @@ PP_DEV void phase_round_end(const GraphDev &g, const RunDev &R, int init, int np
     if (threadIdx.x == 0) s_active = 0;
     __syncthreads();
     int act = 0;
+    long long cnt = 0;
     for (int gi = threadIdx.x; gi < R.G; gi += BLOCK) {
+        const long long c = R.counts[(int64_t)r * R.cstride + gi];
+        cnt += c;
         if (R.gconv[gi]) continue;
-        if (R.counts[(int64_t)r * R.cstride + gi] == 0) {
+        if (c == 0) {
             R.gconv[gi] = 1;
         } else {
             R.D[gi] = r;
@@ -832,6 +879,16 @@ PP_DEV void phase_round_end(const GraphDev &g, const RunDev &R, int init, int np
         }
     }
     if (act) atomicAdd(&s_active, act);
+    cnt = block_sum<long long>(cnt, s_red);
+    const int64_t reached = CTL(C->reached) + (init ? 0 : cnt);
+    const int64_t last = CTL(C->last_count);
+    float f[MLP_IN];
+    sched_features(g, R, r + 1, mode, fnodes, farcs, cnt, reached, last, f);
+    const int32_t fallback = schedule(g, R, r + 1, fnodes, farcs);
+    if (threadIdx.x < 64) {
+        const int32_t d = R.sched == PP_SCHED_MLP ? mlp_decide(R.mlp, f, fallback) : fallback;
+        if (threadIdx.x == 0) s_next = d;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
         R.mode_log[r] = mode;
@@ -842,6 +899,14 @@ PP_DEV void phase_round_end(const GraphDev &g, const RunDev &R, int init, int np
         C->hub_nodes = 0;
         C->hub_arcs = 0;
         C->active = s_active;
+        C->reached = reached;
+        C->last_count = cnt;
+#pragma unroll
+        for (int i = 0; i < MLP_IN; ++i) C->feat[i] = f[i];
+        if (r + 1 < R.cap) {
+#pragma unroll
+            for (int i = 0; i < MLP_IN; ++i) R.feat_log[(int64_t)(r + 1) * MLP_IN + i] = f[i];
+        }
         if (s_active == 0) {
             C->converged = 1;
         } else if (r + 1 >= R.cap) {
@@ -852,7 +917,7 @@ PP_DEV void phase_round_end(const GraphDev &g, const RunDev &R, int init, int np
             C->f_count[q] = 0;
             C->ch_count[q] = 0;
             C->f_arcs[q] = 0;
-            C->mode = schedule(g, R, nr, fnodes, farcs);
+            C->mode = s_next;
             C->round = nr;
         }
     }
@@ -885,6 +950,27 @@ template <int W> __global__ void __launch_bounds__(BLOCK) k_push(GraphDev g, Run
 __global__ void __launch_bounds__(BLOCK) k_round_end(GraphDev g, RunDev R, int init) {
     if (R.ctrl->converged) return;
     phase_round_end(g, R, init, g.pull_grid);
+}
+
+// New cost-model weights for a run in progress: the direction of the round
+// about to run was taken at the end of the last one, so take it again from
+// the features saved in each live control block (one wave per block).
+__global__ void __launch_bounds__(64) k_redecide(RunDev R, int nctrl) {
+    Ctrl *C = R.ctrl + blockIdx.x;
+    if ((int)blockIdx.x >= nctrl || R.sched != PP_SCHED_MLP) return;
+    const int32_t mode = CTL(C->mode);
+    if (CTL(C->round) < 1 || CTL(C->converged) || (mode != MODE_PULL && mode != MODE_PUSH)) return;
+    float f[MLP_IN];
+#pragma unroll
+    for (int i = 0; i < MLP_IN; ++i) f[i] = C->feat[i];
+    const int32_t d = mlp_decide(R.mlp, f, mode);
+    if (threadIdx.x == 0) C->mode = d;
+}
+
+hipError_t launch_redecide(const RunDev &R, int nctrl, hipStream_t st) {
+    if (nctrl <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_redecide, dim3(nctrl), dim3(64), 0, st, R, nctrl);
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------- persistent rounds
@@ -961,6 +1047,7 @@ PP_DEV void cluster_view(const GraphDev &g, const RunDev &R, const Cluster &cl, 
     rv.mode_log = R.mode_log + (int64_t)cl.g * R.cap;
     rv.arcs_log = R.arcs_log + (int64_t)cl.g * R.cap;
     rv.phase_log = R.phase_log + (int64_t)cl.g * R.cap * 3;
+    rv.feat_log = R.feat_log + (int64_t)cl.g * R.cap * MLP_IN;
     const int W = R.W;
     for (int k = 0; k < 2; ++k) {
         rv.f_ids[k] = R.f_ids[k] + cl.n0;

@@ -51,7 +51,11 @@ EXPORTS = ["pp_options_default", "pp_csr_build", "pp_graph_arcs", "pp_graph_node
            "pp_seeds_init", "pp_propagate_round", "pp_propagate_until_converged", "pp_estimate_metrics",
            "pp_get_signatures", "pp_get_seed_counts", "pp_run_round", "pp_run_words", "pp_get_round_log",
            "pp_run_snapshot", "pp_run_restore", "pp_run_free", "pp_graph_free", "pp_last_error",
-           "pp_seeds_reset", "pp_get_kernel_times"]
+           "pp_seeds_reset", "pp_get_kernel_times", "pp_run_set_mlp", "pp_get_round_features",
+           "pp_time_round", "pp_mlp_forward", "pp_mlp_loss_grad", "pp_mlp_train"]
+
+MLP_IN, MLP_HID, MLP_OUT = 8, 32, 2
+MLP_PARAMS = MLP_HID * MLP_IN + MLP_HID + MLP_HID * MLP_HID + MLP_HID + MLP_OUT * MLP_HID + MLP_OUT   # 1410
 
 _lib = None
 
@@ -82,6 +86,12 @@ def lib():
         "pp_last_error": (ctypes.c_char_p, []),
         "pp_seeds_reset": (ctypes.c_int, [P, P, I32]),
         "pp_get_kernel_times": (ctypes.c_int, [P, P, I32]),
+        "pp_run_set_mlp": (ctypes.c_int, [P, P]),
+        "pp_get_round_features": (ctypes.c_int, [P, P, I32]),
+        "pp_time_round": (ctypes.c_int, [P, I32, P, P]),
+        "pp_mlp_forward": (ctypes.c_int, [P, P, I64, P]),
+        "pp_mlp_loss_grad": (ctypes.c_int, [P, P, P, I64, P, P]),
+        "pp_mlp_train": (ctypes.c_int, [P, P, P, I64, I32, ctypes.c_float, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -318,6 +328,70 @@ def pp_run_snapshot(run: Run) -> Run:
 
 def pp_run_restore(run: Run, src: Run):
     _check(lib().pp_run_restore(run.handle, src.handle))
+
+
+def _f32(a, shape=None):
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    if shape is not None and a.shape != shape:
+        raise ValueError(f"expected shape {shape}, got {a.shape}")
+    return a
+
+
+def pp_run_set_mlp(run: Run, params):
+    """Cost-model weights of a PP_SCHED_MLP run ([1410] float32), or None to clear them."""
+    if params is None:
+        _check(lib().pp_run_set_mlp(run.handle, None))
+    else:
+        _check(lib().pp_run_set_mlp(run.handle, _np_ptr(_f32(params, (MLP_PARAMS,)))))
+
+
+def pp_get_round_features(run: Run, cap: int):
+    a = np.zeros((cap, MLP_IN), dtype=np.float32)
+    _check(lib().pp_get_round_features(run.handle, _np_ptr(a), int(cap)))
+    return a
+
+
+def pp_time_round(run: Run, mode: int):
+    """Runs the next round in direction `mode` (MODE_PULL / MODE_PUSH); returns (features [8], ms)."""
+    f = np.zeros(MLP_IN, dtype=np.float32)
+    ms = ctypes.c_float(0.0)
+    _check(lib().pp_time_round(run.handle, int(mode), _np_ptr(f), ctypes.byref(ms)))
+    return f, float(ms.value)
+
+
+def pp_mlp_forward(params, x):
+    p = _f32(params, (MLP_PARAMS,))
+    x = _f32(x)
+    n = int(x.shape[0])
+    y = np.zeros((n, MLP_OUT), dtype=np.float32)
+    _check(lib().pp_mlp_forward(_np_ptr(p), _np_ptr(x.reshape(n, MLP_IN)), n, _np_ptr(y)))
+    return y
+
+
+def pp_mlp_loss_grad(params, x, t):
+    p = _f32(params, (MLP_PARAMS,))
+    x = _f32(x)
+    t = _f32(t)
+    n = int(x.shape[0])
+    if t.shape != (n, MLP_OUT) or x.shape != (n, MLP_IN):
+        raise ValueError("x must be [n][8] and t [n][2]")
+    g = np.zeros(MLP_PARAMS, dtype=np.float32)
+    loss = ctypes.c_float(0.0)
+    _check(lib().pp_mlp_loss_grad(_np_ptr(p), _np_ptr(x), _np_ptr(t), n, _np_ptr(g), ctypes.byref(loss)))
+    return float(loss.value), g
+
+
+def pp_mlp_train(params, x, t, steps: int, lr: float):
+    """Full-batch Adam; returns (trained params, loss before each step)."""
+    p = _f32(params, (MLP_PARAMS,)).copy()
+    x = _f32(x)
+    t = _f32(t)
+    n = int(x.shape[0])
+    if t.shape != (n, MLP_OUT) or x.shape != (n, MLP_IN):
+        raise ValueError("x must be [n][8] and t [n][2]")
+    log = np.zeros(max(int(steps), 1), dtype=np.float32)
+    _check(lib().pp_mlp_train(_np_ptr(p), _np_ptr(x), _np_ptr(t), n, int(steps), float(lr), _np_ptr(log)))
+    return p, log[:int(steps)]
 
 
 def propagate(n, src, dst, seeds, undirected=False, transpose=False, opts=None, stream=None):

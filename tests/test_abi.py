@@ -82,3 +82,27 @@ def test_metrics_argument_errors():
         pp.pp_estimate_metrics([1, 2], 4, 1, 11, 10)
     with pytest.raises(pp.PPError):
         pp.pp_estimate_metrics([1, -2], 4, 1)
+
+
+def test_cost_model_layout_and_argument_errors():
+    text = open(os.path.join(ROOT, "include", "pp.h")).read()
+    assert int(re.search(r"#define PP_MLP_PARAMS (\d+)", text).group(1)) == pp.MLP_PARAMS == 1410
+    L = pp.lib()
+    ptr = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    p = np.zeros(pp.MLP_PARAMS, np.float32)
+    x = np.zeros((4, 8), np.float32)
+    t = np.zeros((4, 2), np.float32)
+    y = np.zeros((4, 2), np.float32)
+    assert L.pp_run_set_mlp(None, None) == pp.PP_EINVAL
+    assert L.pp_time_round(None, 0, None, None) == pp.PP_EINVAL
+    assert L.pp_get_round_features(None, None, 1) == pp.PP_EINVAL
+    assert L.pp_mlp_forward(None, ptr(x), 4, ptr(y)) == pp.PP_EINVAL
+    assert L.pp_mlp_forward(ptr(p), ptr(x), 4, None) == pp.PP_EINVAL
+    assert L.pp_mlp_forward(ptr(p), ptr(x), 0, ptr(y)) == pp.PP_EINVAL
+    assert L.pp_mlp_loss_grad(ptr(p), ptr(x), None, 4, None, None) == pp.PP_EINVAL
+    assert L.pp_mlp_train(ptr(p), ptr(x), ptr(t), 4, 10, 0.0, None) == pp.PP_EINVAL
+    assert L.pp_mlp_train(ptr(p), ptr(x), ptr(t), 4, 10, float("nan"), None) == pp.PP_EINVAL
+    assert L.pp_mlp_train(ptr(p), ptr(x), ptr(t), 4, -1, 0.01, None) == pp.PP_EINVAL
+    assert "steps" in L.pp_last_error().decode()
+    with pytest.raises(ValueError):
+        pp.pp_mlp_loss_grad(p, x, np.zeros((3, 2), np.float32))
