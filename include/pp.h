@@ -79,7 +79,8 @@ typedef struct {
     int32_t scheduler;          /* PP_SCHED_* */
     int32_t seed_counts;        /* 1: also record per-seed counts c_i[r] */
     int32_t max_rounds;         /* capacity of the per-round logs (0: n + 1, at most 1<<20) */
-    int32_t rounds_per_sync;    /* rounds launched between host convergence checks (0: adaptive) */
+    int32_t rounds_per_sync;    /* rounds launched between host convergence checks (0: adaptive:
+                                   8, then the rounds run so far, at most 64) */
     int32_t use_graph;          /* 1: replay the round batch as a captured hipGraph */
     int32_t push_div;           /* heuristic: push while frontier arcs * push_div < arcs (0: 8) */
     uint64_t fuzz_seed;         /* PP_SCHED_FUZZ stream */

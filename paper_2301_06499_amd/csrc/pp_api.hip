@@ -442,15 +442,17 @@ int words_for(int s) {
 }
 
 void free_run_dev(RunDev &d) {
+    // each pair is one allocation owned by member 0
     dev_free(d.sig[0]);
-    dev_free(d.sig[1]);
     dev_free(d.acc);
     dev_free(d.stamp);
-    for (int k = 0; k < 2; ++k) {
-        dev_free(d.f_ids[k]);
-        dev_free(d.f_delta[k]);
-        dev_free(d.chunks[k]);
-    }
+    dev_free(d.f_ids[0]);
+    dev_free(d.f_delta[0]);
+    dev_free(d.chunks[0]);
+    d.sig[1] = nullptr;
+    d.f_ids[1] = nullptr;
+    d.f_delta[1] = nullptr;
+    d.chunks[1] = nullptr;
     dev_free(d.blk_cnt);
     dev_free(d.blk_nodes);
     dev_free(d.blk_arcs);
@@ -504,11 +506,12 @@ int alloc_run_dev(pp_graph g, RunDev &d, int s, int W, int cap, bool seed_counts
     d.G = G;
     d.cstride = G;
     d.sstride = G * s;
-    if ((rc = dev_alloc(&d.sig[0], n * W)) || (rc = dev_alloc(&d.sig[1], n * W)) || (rc = dev_alloc(&d.acc, n * W)) ||
-        (rc = dev_alloc(&d.stamp, n)) ||
-        (rc = dev_alloc(&d.f_ids[0], n)) || (rc = dev_alloc(&d.f_ids[1], n)) ||
-        (rc = dev_alloc(&d.f_delta[0], n * W)) || (rc = dev_alloc(&d.f_delta[1], n * W)) ||
-        (rc = dev_alloc(&d.chunks[0], chunk_capacity(g))) || (rc = dev_alloc(&d.chunks[1], chunk_capacity(g))) ||
+    // the double buffers come in pairs, each pair one allocation (the kernels
+    // pick a member by pointer arithmetic)
+    const int64_t cc = chunk_capacity(g);
+    if ((rc = dev_alloc(&d.sig[0], 2 * n * W)) || (rc = dev_alloc(&d.acc, n * W)) || (rc = dev_alloc(&d.stamp, n)) ||
+        (rc = dev_alloc(&d.f_ids[0], 2 * n)) || (rc = dev_alloc(&d.f_delta[0], 2 * n * W)) ||
+        (rc = dev_alloc(&d.chunks[0], 2 * cc)) ||
         (rc = dev_alloc(&d.blk_cnt, pull_grid)) || (rc = dev_alloc(&d.blk_nodes, pull_grid)) ||
         (rc = dev_alloc(&d.blk_arcs, pull_grid)) || (rc = dev_alloc(&d.blk_pulled, pull_grid)) ||
         (rc = dev_alloc(&d.counts, (int64_t)cap * G)) || (rc = dev_alloc(&d.D, G)) || (rc = dev_alloc(&d.gconv, G)) ||
@@ -517,6 +520,10 @@ int alloc_run_dev(pp_graph g, RunDev &d, int s, int W, int cap, bool seed_counts
         (rc = dev_alloc(&d.phase_log, (int64_t)cap * 3 * G)) ||
         (rc = dev_alloc(&d.feat_log, (int64_t)cap * pp::MLP_IN * G)) || (rc = dev_alloc(&d.mlp, pp::MLP_PARAMS)))
         return rc;
+    d.sig[1] = d.sig[0] + n * W;
+    d.f_ids[1] = d.f_ids[0] + n;
+    d.f_delta[1] = d.f_delta[0] + n * W;
+    d.chunks[1] = d.chunks[0] + cc;
     if (seed_counts && (rc = dev_alloc(&d.seed_counts, (int64_t)cap * G * s))) return rc;
     if (!seed_counts) d.seed_counts = nullptr;
     return PP_OK;
@@ -891,7 +898,11 @@ extern "C" int pp_propagate_until_converged(pp_run r, int32_t max_rounds, int64_
     if (counts && cap_rounds < 1) return fail(PP_EINVAL, "cap_rounds < 1");
     const int G = r->G;
     const int limit = (max_rounds > 0 && max_rounds < r->cap - 1) ? max_rounds : r->cap - 1;
-    int K = r->opt.rounds_per_sync > 0 ? r->opt.rounds_per_sync : 2;
+    // adaptive batches: 8 rounds, then as many rounds as have run so far (at
+    // most 64) -- a host check costs about as much as a few replayed rounds
+    // that find the run converged and return at once
+    const int start = r->host_ctrl.round;
+    int K = r->opt.rounds_per_sync > 0 ? r->opt.rounds_per_sync : 8;
     if (r->pgrid && !r->host_ctrl.converged && r->host_ctrl.round <= limit) {
         int rc = run_persistent(r, limit);
         if (rc) return rc;
@@ -925,7 +936,7 @@ extern "C" int pp_propagate_until_converged(pp_run r, int32_t max_rounds, int64_
                 r->pull_ms[(size_t)(before + i)] += ms;
             }
         }
-        if (r->opt.rounds_per_sync <= 0) K = std::min(K * 2, 64);
+        if (r->opt.rounds_per_sync <= 0) K = std::min(std::max(8, r->host_ctrl.round - start), 64);
     }
     // results
     const int last = std::min(r->host_ctrl.round, r->cap - 1);

@@ -59,6 +59,11 @@ PP_DEV uint64_t mix64(uint64_t z) {
 // Loads and stores of data read or written once per round (arc lists, the
 // node's own row, the new row): optionally marked non-temporal so they do not
 // displace the gathered successor rows from the caches.
+// Buffer k & 1 of a pair by arithmetic on both pointers rather than a
+// run-time index into the pair (which would keep a struct copy of the run in
+// scratch memory).  Both members of every pair live in one allocation.
+template <typename T> PP_DEV T *sel(T *const (&a)[2], int k) { return a[0] + (ptrdiff_t)(k & 1) * (a[1] - a[0]); }
+
 template <typename T> PP_DEV T stream_ld(const T *p) {
 #if PP_STREAM_NT
     return __builtin_nontemporal_load(p);
@@ -299,9 +304,9 @@ PP_DEV void phase_push_commit(const GraphDev &g, const RunDev &R, int init, int 
     const int p = r & 1;
     const int32_t cnt = CTL(C->f_count[p]);
     const int64_t items = (int64_t)cnt * W;
-    const int32_t *ids = R.f_ids[p];
-    uint64_t *dl = R.f_delta[p];
-    Chunk *chunks = R.chunks[p];
+    const int32_t *ids = sel(R.f_ids, p);
+    uint64_t *dl = sel(R.f_delta, p);
+    Chunk *chunks = sel(R.chunks, p);
     const int ln = lane_id();
     const int w = ln & (W - 1);
     const bool per_seed = R.seed_counts != nullptr;
@@ -371,6 +376,27 @@ PP_DEV void phase_push_commit(const GraphDev &g, const RunDev &R, int init, int 
 
 // ---------------------------------------------------------------- pull
 
+// Issues the loads that stage a pull tile: K column ids per lane and the
+// tile's row offsets (relative to its first arc; a hub chunk is one row).
+template <int K, int NODES>
+PP_DEV void stage_tile(const GraphDev &g, const Tile &T, int ln, int32_t (&cv)[K], int32_t &rv0, int32_t &rv1) {
+    const int nn = T.u1 - T.u0;
+    const int ne = (int)(T.e1 - T.e0);
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        const int i = ln + j * 64;
+        cv[j] = i < ne ? stream_ld(g.col + T.e0 + i) : 0;
+    }
+    rv0 = 0;
+    rv1 = 0;
+    if (T.hub >= 0) {
+        rv0 = ln == 0 ? 0 : ne;
+    } else {
+        if (ln <= nn) rv0 = (int)(stream_ld(g.rp + T.u0 + ln) - T.e0);
+        if (ln == 0 && nn == NODES) rv1 = (int)(stream_ld(g.rp + T.u0 + NODES) - T.e0);
+    }
+}
+
 template <int W>
 PP_DEV void phase_pull(const GraphDev &g, const RunDev &R, int bid, int nb) {
     Ctrl *C = R.ctrl;
@@ -386,8 +412,8 @@ PP_DEV void phase_pull(const GraphDev &g, const RunDev &R, int bid, int nb) {
     __shared__ unsigned long long s_red[BLOCK / 64];
     const int r = CTL(C->round);
     const int cur = CTL(C->cur);
-    const uint64_t *__restrict__ sig = R.sig[cur];
-    uint64_t *__restrict__ nxt = R.sig[cur ^ 1];
+    const uint64_t *__restrict__ sig = sel(R.sig, cur);
+    uint64_t *__restrict__ nxt = sel(R.sig, cur ^ 1);
     const int ln = lane_id();
     const int wv = threadIdx.x >> 6;
     int32_t *col_l = s_col[wv];
@@ -401,25 +427,33 @@ PP_DEV void phase_pull(const GraphDev &g, const RunDev &R, int bid, int nb) {
     for (int k = 0; k < W; ++k) sc[k] = 0;
 
     const int64_t nw = (int64_t)nb * WAVES;
-    for (int64_t t = (int64_t)bid * WAVES + wv; t < g.ntiles; t += nw) {   // wave-uniform
-        const Tile T = g.tiles[t];
-        if (R.G > 1 && R.gconv[T.graph]) continue;
+    // Software pipeline over the wave's tiles: the column and offset loads of
+    // the next tile are issued before this tile's row gathers, so one memory
+    // latency per tile is exposed instead of two.
+    int64_t t = (int64_t)bid * WAVES + wv;
+    Tile T = t < g.ntiles ? g.tiles[t] : Tile{0, 0, 0, 0, -1, 0};
+    int32_t cv[K];
+    int32_t rv0 = 0, rv1 = 0;
+    stage_tile<K, NODES>(g, T, ln, cv, rv0, rv1);
+    for (; t < g.ntiles; t += nw) {   // wave-uniform
+        const int64_t tn = t + nw;
+        const Tile Tn = tn < g.ntiles ? g.tiles[tn] : T;
         const int nn = T.u1 - T.u0;
         const int ne = (int)(T.e1 - T.e0);
         const bool hub = T.hub >= 0;
-        // stage the tile: every load issued before the first wait
-        int32_t cv[K];
+        const bool skip = R.G > 1 && R.gconv[T.graph];
+        if (!skip) {
 #pragma unroll
-        for (int j = 0; j < K; ++j) {
-            const int i = ln + j * 64;
-            cv[j] = i < ne ? stream_ld(g.col + T.e0 + i) : 0;
+            for (int j = 0; j < K; ++j) col_l[ln + j * 64] = cv[j];
+            if (ln <= nn) rp_l[ln] = rv0;
+            if (ln == 0 && nn == NODES) rp_l[NODES] = rv1;
+#pragma unroll
+            for (int j = 0; j < W; ++j) acc_l[ln + j * 64] = 0ull;
         }
-        int32_t rv0 = 0, rv1 = 0;
-        if (hub) {
-            rv0 = ln == 0 ? 0 : ne;
-        } else {
-            if (ln <= nn) rv0 = (int)(stream_ld(g.rp + T.u0 + ln) - T.e0);
-            if (ln == 0 && nn == NODES) rv1 = (int)(stream_ld(g.rp + T.u0 + NODES) - T.e0);
+        if (tn < g.ntiles) stage_tile<K, NODES>(g, Tn, ln, cv, rv0, rv1);
+        if (skip) {
+            T = Tn;
+            continue;
         }
         uint64_t own[W];
 #pragma unroll
@@ -427,12 +461,6 @@ PP_DEV void phase_pull(const GraphDev &g, const RunDev &R, int bid, int nb) {
             const int idx = ln + j * 64;
             own[j] = (!hub && idx < nn * W) ? stream_ld(sig + (int64_t)T.u0 * W + idx) : 0;
         }
-#pragma unroll
-        for (int j = 0; j < K; ++j) col_l[ln + j * 64] = cv[j];
-        if (ln <= nn) rp_l[ln] = rv0;
-        if (ln == 0 && nn == NODES) rp_l[NODES] = rv1;
-#pragma unroll
-        for (int j = 0; j < W; ++j) acc_l[ln + j * 64] = 0ull;
 
         // gather: lane ln ORs the rows of arcs [a, a+K) into a running
         // accumulator and flushes it into the LDS row of each node it leaves
@@ -512,6 +540,7 @@ PP_DEV void phase_pull(const GraphDev &g, const RunDev &R, int bid, int nb) {
                 if (ln == 0 && tt) atomicAdd((unsigned long long *)&R.counts[(int64_t)r * R.cstride + T.graph], (unsigned long long)tt);
             }
         }
+        T = Tn;
     }
     const unsigned long long tp = block_sum<unsigned long long>(pop, s_red);
     const unsigned long long tn = block_sum<unsigned long long>((unsigned long long)nodes, s_red);
@@ -534,8 +563,8 @@ PP_DEV void phase_pull_hubs(const GraphDev &g, const RunDev &R, int bid, int nb)
     if (g.nhubs == 0) return;
     const int r = CTL(C->round);
     const int cur = CTL(C->cur);
-    const uint64_t *sig = R.sig[cur];
-    uint64_t *nxt = R.sig[cur ^ 1];
+    const uint64_t *sig = sel(R.sig, cur);
+    uint64_t *nxt = sel(R.sig, cur ^ 1);
     const int ln = lane_id();
     const int w = ln & (W - 1);
     const bool per_seed = R.seed_counts != nullptr;
@@ -606,8 +635,8 @@ PP_DEV void phase_frontier(const GraphDev &g, const RunDev &R, int bid, int nb) 
     const int r = CTL(C->round);
     const int p = (r - 1) & 1;
     const int cur = CTL(C->cur);
-    const uint64_t *now = R.sig[cur];
-    const uint64_t *old = R.sig[cur ^ 1];
+    const uint64_t *now = sel(R.sig, cur);
+    const uint64_t *old = sel(R.sig, cur ^ 1);
     const int ln = lane_id();
     const int w = ln & (W - 1);
     const int gb = ln & ~(W - 1);
@@ -663,10 +692,10 @@ PP_DEV void phase_frontier(const GraphDev &g, const RunDev &R, int bid, int nb) 
         const int cfirst = crun + block_scan(nchk, s_scan, it_chunks);
         pos = __shfl(pos, gb);
         if (changed) {
-            if (lead) R.f_ids[p][pos] = (int32_t)u;
-            R.f_delta[p][(int64_t)pos * W + w] = d;
+            if (lead) sel(R.f_ids, p)[pos] = (int32_t)u;
+            sel(R.f_delta, p)[(int64_t)pos * W + w] = d;
         }
-        for (int j = 0; j < nchk; ++j) R.chunks[p][cfirst + j] = Chunk{pos, j * PushShape<W>::CHUNK};
+        for (int j = 0; j < nchk; ++j) sel(R.chunks, p)[cfirst + j] = Chunk{pos, j * PushShape<W>::CHUNK};
         nrun += it_nodes;
         crun += it_chunks;
     }
@@ -703,7 +732,7 @@ PP_DEV void push_slots(const RunDev &R, uint64_t *sig, int r, const int64_t (&k)
         want[it] = any && w == 0 && atomicMax(&R.stamp[u[it]], r) < r;
     }
 #pragma unroll
-    for (int it = 0; it < IT; ++it) bq.push(want[it], u[it], &C->f_count[pn], R.f_ids[pn]);
+    for (int it = 0; it < IT; ++it) bq.push(want[it], u[it], &C->f_count[pn], sel(R.f_ids, pn));
 }
 
 template <int W>
@@ -711,11 +740,11 @@ PP_DEV void phase_push(const GraphDev &g, const RunDev &R, int bid, int nb) {
     Ctrl *C = R.ctrl;
     const int r = CTL(C->round);
     const int pp = (r - 1) & 1, pn = r & 1;
-    uint64_t *sig = R.sig[CTL(C->cur)];
+    uint64_t *sig = sel(R.sig, CTL(C->cur));
     const int32_t cnt = CTL(C->f_count[pp]);
     const int32_t nch = CTL(C->ch_count[pp]);
-    const int32_t *ids = R.f_ids[pp];
-    const uint64_t *dl = R.f_delta[pp];
+    const int32_t *ids = sel(R.f_ids, pp);
+    const uint64_t *dl = sel(R.f_delta, pp);
     const int ln = lane_id();
     const int w = ln & (W - 1);
     const int64_t wave = (bid * (int64_t)BLOCK + threadIdx.x) >> 6;
@@ -761,7 +790,7 @@ PP_DEV void phase_push(const GraphDev &g, const RunDev &R, int bid, int nb) {
         constexpr int IT = CH / SL;
         const int slot = ln / W;
         for (int64_t c = wave; c < nch; c += nwaves) {   // wave-uniform
-            const Chunk cd = R.chunks[pp][c];
+            const Chunk cd = sel(R.chunks, pp)[c];
             const int32_t v = ids[cd.entry];
             const uint64_t d = dl[(int64_t)cd.entry * W + w];
             const int64_t b = g.trp[v] + cd.off;
@@ -777,7 +806,7 @@ PP_DEV void phase_push(const GraphDev &g, const RunDev &R, int bid, int nb) {
             push_slots<W, IT>(R, sig, r, k, kv, g.tcol, w, d, bq, C, pn);
         }
     }
-    bq.flush(&C->f_count[pn], R.f_ids[pn], &s_qbase);
+    bq.flush(&C->f_count[pn], sel(R.f_ids, pn), &s_qbase);
 }
 
 // ---------------------------------------------------------------- round end
@@ -1049,6 +1078,7 @@ PP_DEV void cluster_view(const GraphDev &g, const RunDev &R, const Cluster &cl, 
     rv.phase_log = R.phase_log + (int64_t)cl.g * R.cap * 3;
     rv.feat_log = R.feat_log + (int64_t)cl.g * R.cap * MLP_IN;
     const int W = R.W;
+#pragma unroll
     for (int k = 0; k < 2; ++k) {
         rv.f_ids[k] = R.f_ids[k] + cl.n0;
         rv.f_delta[k] = R.f_delta[k] + cl.n0 * W;
