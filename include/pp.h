@@ -60,8 +60,12 @@ typedef struct pp_run_s *pp_run;       /* signatures, frontier, per-round logs *
 enum {
     PP_UNDIRECTED = 1,       /* each input pair (a, b) stands for arcs a->b and b->a */
     PP_INPUT_ON_DEVICE = 2,  /* src/dst point to device memory */
-    PP_TRANSPOSE = 4         /* propagate along reversed arcs: bit i reaches u when
+    PP_TRANSPOSE = 4,        /* propagate along reversed arcs: bit i reaches u when
                                 x_i can reach u (instead of u reaching x_i) */
+    PP_KEEP_ORDER = 8        /* store the nodes in input order (by default the nodes
+                                with the most predecessors are stored first, which
+                                only changes the layout: every result is reported
+                                by input node id) */
 };
 
 /* per-round direction policy */
@@ -116,7 +120,7 @@ void pp_options_default(pp_options *opt);
  *   src, dst    m node ids each: pair k is the arc src[k] -> dst[k] (both
  *               directions with PP_UNDIRECTED).  Host memory unless
  *               PP_INPUT_ON_DEVICE; the caller keeps ownership.
- *   flags       PP_UNDIRECTED | PP_INPUT_ON_DEVICE | PP_TRANSPOSE.
+ *   flags       PP_UNDIRECTED | PP_INPUT_ON_DEVICE | PP_TRANSPOSE | PP_KEEP_ORDER.
  *   node_offsets, num_graphs
  *               a batch of num_graphs disjoint graphs: graph g owns node ids
  *               [node_offsets[g], node_offsets[g+1]) (host array of

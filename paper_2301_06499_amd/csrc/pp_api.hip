@@ -105,6 +105,8 @@ struct pp_graph_s {
     int32_t *node_graph = nullptr;
     int64_t *node_off = nullptr;
     std::map<int, TileSet> tiles;   // by pull arc budget
+    std::vector<int32_t> perm;      // stored id of each input node (empty: identity)
+    int32_t *perm_d = nullptr;      // the same on the device
 };
 
 struct pp_run_s {
@@ -200,6 +202,68 @@ void transpose_rows(int64_t n, const std::vector<int64_t> &rp, const std::vector
     std::vector<int64_t> fill(trp.begin(), trp.end() - 1);
     for (int64_t u = 0; u < n; ++u)
         for (int64_t e = rp[(size_t)u]; e < rp[(size_t)u + 1]; ++e) tcol[(size_t)fill[(size_t)col[(size_t)e]]++] = (int32_t)u;
+}
+
+// Storage order of the nodes (hub-first grouping): within each graph of a
+// batch, the nodes whose rows many arcs gather -- at least max(8, twice the
+// graph's mean) predecessors -- come first, by decreasing predecessor count,
+// then every other node in input order.  Packing the most-gathered rows into
+// few cache lines raises the caches' hit rate in the pull; graphs without
+// such nodes (lattices) keep their order.  perm[x] is the stored id of input
+// node x.  Returns false when the order is the identity.
+bool hub_first_order(const std::vector<int64_t> &noff, int G, const std::vector<int64_t> &rp,
+                     const std::vector<int32_t> &col, std::vector<int32_t> &perm) {
+    const int64_t n = (int64_t)rp.size() - 1;
+    std::vector<int64_t> indeg((size_t)n, 0);
+    for (size_t k = 0; k < col.size(); ++k) indeg[(size_t)col[k]]++;
+    perm.resize((size_t)n);
+    bool moved = false;
+    for (int g = 0; g < G; ++g) {
+        const int64_t a = noff[(size_t)g], b = noff[(size_t)g + 1];
+        if (b <= a) continue;
+        const double mean = (double)(rp[(size_t)b] - rp[(size_t)a]) / (double)(b - a);
+        const double thr = std::max(8.0, 2.0 * mean);
+        std::vector<int32_t> hot;
+        for (int64_t x = a; x < b; ++x)
+            if ((double)indeg[(size_t)x] >= thr) hot.push_back((int32_t)x);
+        std::stable_sort(hot.begin(), hot.end(), [&](int32_t x, int32_t y) { return indeg[(size_t)x] > indeg[(size_t)y]; });
+        int64_t pos = a;
+        std::vector<char> is_hot;
+        if (!hot.empty()) is_hot.assign((size_t)(b - a), 0);
+        for (int32_t x : hot) {
+            is_hot[(size_t)(x - a)] = 1;
+            moved |= pos != x;
+            perm[(size_t)x] = (int32_t)pos++;
+        }
+        for (int64_t x = a; x < b; ++x) {
+            if (!hot.empty() && is_hot[(size_t)(x - a)]) continue;
+            moved |= pos != x;
+            perm[(size_t)x] = (int32_t)pos++;
+        }
+    }
+    return moved;
+}
+
+// Rows of a CSR under a node renumbering: row perm[u] of the result holds
+// perm[v] for every v in row u of the input, sorted.
+void relabel_rows(const std::vector<int32_t> &perm, std::vector<int64_t> &rp, std::vector<int32_t> &col) {
+    const int64_t n = (int64_t)rp.size() - 1;
+    std::vector<int32_t> inv((size_t)n);
+    for (int64_t x = 0; x < n; ++x) inv[(size_t)perm[(size_t)x]] = (int32_t)x;
+    std::vector<int64_t> rp2((size_t)n + 1, 0);
+    for (int64_t y = 0; y < n; ++y) rp2[(size_t)y + 1] = rp2[(size_t)y] + (rp[(size_t)inv[(size_t)y] + 1] - rp[(size_t)inv[(size_t)y]]);
+    std::vector<int32_t> col2(col.size());
+    parallel_for(n, [&](int64_t lo, int64_t hi) {
+        for (int64_t y = lo; y < hi; ++y) {
+            const int64_t u = inv[(size_t)y];
+            int32_t *out = col2.data() + rp2[(size_t)y];
+            const int64_t len = rp[(size_t)u + 1] - rp[(size_t)u];
+            for (int64_t k = 0; k < len; ++k) out[k] = perm[(size_t)col[(size_t)(rp[(size_t)u] + k)]];
+            std::sort(out, out + len);
+        }
+    });
+    rp.swap(rp2);
+    col.swap(col2);
 }
 
 // Pull tiles: runs of consecutive nodes with at most `edges` arcs and
@@ -299,6 +363,7 @@ void free_graph(pp_graph g) {
     dev_free(g->tcol);
     dev_free(g->node_graph);
     dev_free(g->node_off);
+    dev_free(g->perm_d);
     for (auto &kv : g->tiles) {
         dev_free(kv.second.tiles);
         dev_free(kv.second.hub_node);
@@ -333,7 +398,8 @@ extern "C" int pp_csr_build(int64_t n, int64_t m, const int32_t *src, const int3
     if (n < 1 || n > INT32_MAX - 1) return fail(PP_EINVAL, "n = %lld outside [1, 2^31-2]", (long long)n);
     if (m < 0) return fail(PP_EINVAL, "m < 0");
     if (m > 0 && (!src || !dst)) return fail(PP_EINVAL, "src/dst NULL with m > 0");
-    if (flags & ~(uint32_t)(PP_UNDIRECTED | PP_INPUT_ON_DEVICE | PP_TRANSPOSE)) return fail(PP_EINVAL, "unknown flag bits");
+    if (flags & ~(uint32_t)(PP_UNDIRECTED | PP_INPUT_ON_DEVICE | PP_TRANSPOSE | PP_KEEP_ORDER))
+        return fail(PP_EINVAL, "unknown flag bits");
     const int G = (num_graphs <= 1 && !node_offsets) ? 1 : num_graphs;
     if (G < 1) return fail(PP_EINVAL, "num_graphs < 1");
     std::vector<int64_t> noff((size_t)G + 1);
@@ -387,10 +453,12 @@ extern "C" int pp_csr_build(int64_t n, int64_t m, const int32_t *src, const int3
     }
     // propagation rows: u ORs in v for arc u -> v (or v -> u transposed)
     std::vector<int64_t> rp, trp;
-    std::vector<int32_t> col, tcol;
+    std::vector<int32_t> col, tcol, perm;
     try {
         if (tr) build_rows(n, m, pd, ps, und, rp, col);
         else build_rows(n, m, ps, pd, und, rp, col);
+        if (!(flags & PP_KEEP_ORDER) && hub_first_order(noff, G, rp, col, perm)) relabel_rows(perm, rp, col);
+        else perm.clear();
         transpose_rows(n, rp, col, trp, tcol);
     } catch (const std::bad_alloc &) {
         return fail(PP_ENOMEM, "host memory for the adjacency build");
@@ -406,7 +474,7 @@ extern "C" int pp_csr_build(int64_t n, int64_t m, const int32_t *src, const int3
     int rc;
     if ((rc = dev_alloc(&g->rp, n + 1)) || (rc = dev_alloc(&g->trp, n + 1)) || (rc = dev_alloc(&g->col, g->m)) ||
         (rc = dev_alloc(&g->tcol, g->m)) || (G > 1 && (rc = dev_alloc(&g->node_graph, n))) ||
-        (rc = dev_alloc(&g->node_off, (int64_t)G + 1))) {
+        (rc = dev_alloc(&g->node_off, (int64_t)G + 1)) || (!perm.empty() && (rc = dev_alloc(&g->perm_d, n)))) {
         free_graph(g);
         return rc;
     }
@@ -416,12 +484,15 @@ extern "C" int pp_csr_build(int64_t n, int64_t m, const int32_t *src, const int3
     if (e == hipSuccess && g->m) e = hipMemcpyAsync(g->tcol, tcol.data(), sizeof(int32_t) * (size_t)g->m, hipMemcpyHostToDevice, st);
     if (e == hipSuccess && G > 1) e = hipMemcpyAsync(g->node_graph, ng.data(), sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipMemcpyAsync(g->node_off, noff.data(), sizeof(int64_t) * (size_t)(G + 1), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && !perm.empty())
+        e = hipMemcpyAsync(g->perm_d, perm.data(), sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) {
         free_graph(g);
         return fail(PP_EDEVICE, "graph upload: %s", hipGetErrorString(e));
     }
     g->rp_host = std::move(rp);
+    g->perm = std::move(perm);
     *out = g;
     return PP_OK;
 }
@@ -658,6 +729,14 @@ std::vector<pp::Cluster> make_clusters(pp_graph g, const TileSet *ts, int grid) 
     return cl;
 }
 
+// Input node ids -> stored ids (hub-first order), for ids already checked.
+std::vector<int32_t> stored_ids(pp_graph g, const int32_t *ids, int64_t count) {
+    std::vector<int32_t> out(ids, ids + count);
+    if (!g->perm.empty())
+        for (auto &x : out) x = g->perm[(size_t)x];
+    return out;
+}
+
 int check_host_seeds(pp_graph g, const int32_t *seeds, int s) {
     for (int gi = 0; gi < g->G; ++gi)
         for (int i = 0; i < s; ++i) {
@@ -755,8 +834,9 @@ extern "C" int pp_seeds_init(pp_graph g, const int32_t *seeds, int32_t s, const 
     r->dev.fuzz_seed = o.fuzz_seed;
     // cost-model weights start as NaN: the heuristic decides until they are set
     hipError_t e = pp::launch_fill_i32((int32_t *)r->dev.mlp, kNaNBits, pp::MLP_PARAMS, r->stream);
+    const std::vector<int32_t> stored = stored_ids(g, seeds, (int64_t)G * s);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(r->dseeds, seeds, sizeof(int32_t) * (size_t)G * s, hipMemcpyHostToDevice, r->stream);
+        e = hipMemcpyAsync(r->dseeds, stored.data(), sizeof(int32_t) * (size_t)G * s, hipMemcpyHostToDevice, r->stream);
     if (e != hipSuccess) {
         free_run(r);
         return fail(PP_EDEVICE, "seed upload: %s", hipGetErrorString(e));
@@ -775,7 +855,13 @@ extern "C" int pp_seeds_reset(pp_run r, const int32_t *seeds, int32_t seeds_on_d
     if (!seeds_on_device) {
         int rc = check_host_seeds(r->g, seeds, r->s);
         if (rc) return rc;
-        HIP_TRY(hipMemcpyAsync(r->dseeds, seeds, sizeof(int32_t) * (size_t)total, hipMemcpyHostToDevice, r->stream));
+        const std::vector<int32_t> stored = stored_ids(r->g, seeds, total);
+        HIP_TRY(hipMemcpyAsync(r->dseeds, stored.data(), sizeof(int32_t) * (size_t)total, hipMemcpyHostToDevice, r->stream));
+        return reset_run(r, r->dseeds);   // synchronises before `stored` goes
+    }
+    if (r->g->perm_d) {
+        // ids outside [0, n) become -1, which the seed placement reports
+        HIP_TRY(pp::launch_map_ids(r->dseeds, seeds, r->g->perm_d, total, r->g->n, r->stream));
         return reset_run(r, r->dseeds);
     }
     return reset_run(r, seeds);
@@ -956,9 +1042,40 @@ extern "C" int pp_propagate_until_converged(pp_run r, int32_t max_rounds, int64_
     return PP_OK;
 }
 
+namespace {
+int copy_signatures(pp_run r, uint64_t *dst, hipMemcpyKind kind);
+}  // namespace
+
 extern "C" int pp_get_signatures(pp_run r, uint64_t *dst, int32_t dst_on_device) {
     if (!r || !dst) return fail(PP_EINVAL, "run or dst is NULL");
-    const hipMemcpyKind kind = dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    if (r->g->perm_d) {
+        // stored order -> input order: assemble the rows, then gather them by id
+        const int64_t words = r->g->n * r->W;
+        uint64_t *tmp = nullptr, *out = nullptr;
+        int rc = dev_alloc(&tmp, words);
+        if (!rc && !dst_on_device) rc = dev_alloc(&out, words);
+        if (!rc) rc = copy_signatures(r, tmp, hipMemcpyDeviceToDevice);
+        hipError_t e = hipSuccess;
+        if (!rc) e = pp::launch_gather_rows(dst_on_device ? dst : out, tmp, r->g->perm_d, r->g->n, r->W, r->stream);
+        if (!rc && !e && !dst_on_device)
+            e = hipMemcpyAsync(dst, out, sizeof(uint64_t) * (size_t)words, hipMemcpyDeviceToHost, r->stream);
+        if (!rc && !e) e = hipStreamSynchronize(r->stream);
+        dev_free(tmp);
+        dev_free(out);
+        if (rc) return rc;
+        if (e) return fail(PP_EDEVICE, "signature gather: %s", hipGetErrorString(e));
+        return PP_OK;
+    }
+    int rc = copy_signatures(r, dst, dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost);
+    if (rc) return rc;
+    HIP_TRY(hipStreamSynchronize(r->stream));
+    return PP_OK;
+}
+
+namespace {
+
+// The current signature rows in stored order into dst (not synchronised).
+int copy_signatures(pp_run r, uint64_t *dst, hipMemcpyKind kind) {
     if (r->cur.size() <= 1) {
         HIP_TRY(hipMemcpyAsync(dst, r->dev.sig[r->host_ctrl.cur & 1], sizeof(uint64_t) * (size_t)r->g->n * r->W, kind,
                                r->stream));
@@ -971,9 +1088,10 @@ extern "C" int pp_get_signatures(pp_run r, uint64_t *dst, int32_t dst_on_device)
                                    sizeof(uint64_t) * (size_t)(n1 - n0) * r->W, kind, r->stream));
         }
     }
-    HIP_TRY(hipStreamSynchronize(r->stream));
     return PP_OK;
 }
+
+}  // namespace
 
 extern "C" int pp_get_seed_counts(pp_run r, uint32_t *dst, int32_t cap_rounds) {
     if (!r || !dst) return fail(PP_EINVAL, "run or dst is NULL");

@@ -45,17 +45,25 @@ constexpr int PULL_GRID_MAX = PP_PULL_GRID_MAX;
 #ifndef PP_PULL_K8
 #define PP_PULL_K8 4
 #endif
+#ifndef PP_PULL_WAVES
+#define PP_PULL_WAVES 4   // occupancy the pull kernel is compiled for (W <= 4)
+#endif
 #ifndef PP_STREAM_NT
 #define PP_STREAM_NT 0
 #endif
 
-// A pull tile is the work of one wave: arcs per lane in the gather (K), the
+// A pull tile is the work of one wave, per signature width W (words): the
 // tile's arc budget (K per lane) and node budget (one row word per lane and
-// pass), per signature width W (words).
+// pass).  In the gather, L lanes share each source row, each loading P
+// words (16 bytes when W >= 2), and every group of L lanes takes KG = K L
+// consecutive arcs.
 template <int W> struct PullShape {
     static constexpr int K = W >= 8 ? PP_PULL_K8 : PP_PULL_K;
     static constexpr int EDGES = K * 64;
     static constexpr int NODES = 64;
+    static constexpr int L = W >= 2 ? W / 2 : 1;
+    static constexpr int P = W / L;
+    static constexpr int KG = K * L;
 };
 
 // Device control block: the round counter and everything the per-round
@@ -174,6 +182,12 @@ hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t count, hipStream_t st)
 // Re-takes the pending direction of each of the first nctrl control blocks
 // with the run's current cost-model weights (PP_SCHED_MLP runs only).
 hipError_t launch_redecide(const RunDev &r, int nctrl, hipStream_t st);
+// out[j] = perm[in[j]] (ids outside [0, n) become -1).
+hipError_t launch_map_ids(int32_t *out, const int32_t *in, const int32_t *perm, int64_t count, int64_t n,
+                          hipStream_t st);
+// dst row x = src row perm[x], rows of W words.
+hipError_t launch_gather_rows(uint64_t *dst, const uint64_t *src, const int32_t *perm, int64_t n, int W,
+                              hipStream_t st);
 hipError_t launch_seed_init(const GraphDev &g, const RunDev &r, const int32_t *seeds_dev, hipStream_t st);
 // One round; when e0/e1 are given they are recorded around the pull launch.
 hipError_t launch_round(const GraphDev &g, const RunDev &r, hipStream_t st, hipEvent_t e0 = nullptr,

@@ -270,6 +270,41 @@ hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t count, hipStream_t st)
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------- node ids
+
+// out[j] = perm[in[j]] for ids in [0, n), -1 otherwise.
+__global__ void __launch_bounds__(BLOCK) k_map_ids(int32_t *out, const int32_t *in, const int32_t *perm, int64_t count,
+                                                   int64_t n) {
+    for (int64_t j = blockIdx.x * (int64_t)BLOCK + threadIdx.x; j < count; j += (int64_t)gridDim.x * BLOCK) {
+        const int32_t x = in[j];
+        out[j] = (x >= 0 && x < n) ? perm[x] : -1;
+    }
+}
+
+hipError_t launch_map_ids(int32_t *out, const int32_t *in, const int32_t *perm, int64_t count, int64_t n,
+                          hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_map_ids, dim3(fill_grid(count)), dim3(BLOCK), 0, st, out, in, perm, count, n);
+    return hipGetLastError();
+}
+
+// dst row x = src row perm[x] (W words per row).
+__global__ void __launch_bounds__(BLOCK) k_gather_rows(uint64_t *dst, const uint64_t *src, const int32_t *perm,
+                                                       int64_t n, int W) {
+    const int64_t total = n * W;
+    for (int64_t j = blockIdx.x * (int64_t)BLOCK + threadIdx.x; j < total; j += (int64_t)gridDim.x * BLOCK) {
+        const int64_t x = j / W;
+        dst[j] = src[(int64_t)perm[x] * W + (j - x * W)];
+    }
+}
+
+hipError_t launch_gather_rows(uint64_t *dst, const uint64_t *src, const int32_t *perm, int64_t n, int W,
+                              hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gather_rows, dim3(fill_grid(n * W)), dim3(BLOCK), 0, st, dst, src, perm, n, W);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- seeds
 
 // Seed bit i of graph g goes to node seeds[g*s + i] (Algorithm 1's
@@ -462,45 +497,50 @@ PP_DEV void phase_pull(const GraphDev &g, const RunDev &R, int bid, int nb) {
             own[j] = (!hub && idx < nn * W) ? stream_ld(sig + (int64_t)T.u0 * W + idx) : 0;
         }
 
-        // gather: lane ln ORs the rows of arcs [a, a+K) into a running
-        // accumulator and flushes it into the LDS row of each node it leaves
-        const int a = ln * K;
+        // gather: a group of L lanes shares arcs [a, a + KG); each lane loads
+        // and ORs its P-word slice of every source row (one 16-byte load per
+        // lane, so the group's loads of one row fall in one cache line and
+        // cost one L2 request), keeps a running accumulator, and flushes it
+        // into the LDS row of each node it leaves
+        constexpr int L = PS::L, P = PS::P, KG = PS::KG;
+        const int sub = ln % L;
+        const int a = (ln / L) * KG;
         if (a < ne) {
-            const int b = min(a + K, ne);
+            const int b = min(a + KG, ne);
             int lo = 0, hi = nn - 1;          // node i with rp[i] <= a < rp[i+1]
             while (lo < hi) {
                 const int mid = (lo + hi + 1) >> 1;
                 if (rp_l[mid] <= a) lo = mid; else hi = mid - 1;
             }
             int i = lo;
-            uint64_t rows[K][W];
+            uint64_t rows[KG][P];
 #pragma unroll
-            for (int j = 0; j < K; ++j) {
+            for (int j = 0; j < KG; ++j) {
                 if (a + j < b) {
-                    load_row<W>(sig + (int64_t)col_l[a + j] * W, rows[j]);
+                    load_row<P>(sig + (int64_t)col_l[a + j] * W + sub * P, rows[j]);
                 } else {
 #pragma unroll
-                    for (int w = 0; w < W; ++w) rows[j][w] = 0;
+                    for (int w = 0; w < P; ++w) rows[j][w] = 0;
                 }
             }
-            uint64_t acc[W];
+            uint64_t acc[P];
 #pragma unroll
-            for (int w = 0; w < W; ++w) acc[w] = 0;
+            for (int w = 0; w < P; ++w) acc[w] = 0;
             int nx = rp_l[i + 1];
 #pragma unroll
-            for (int j = 0; j < K; ++j) {
+            for (int j = 0; j < KG; ++j) {
                 const int e = a + j;
                 if (e < b) {
                     while (e >= nx) {
-                        flush_lds<W>(acc_l + i * W, acc);
+                        flush_lds<P>(acc_l + i * W + sub * P, acc);
                         ++i;
                         nx = rp_l[i + 1];
                     }
 #pragma unroll
-                    for (int w = 0; w < W; ++w) acc[w] |= rows[j][w];
+                    for (int w = 0; w < P; ++w) acc[w] |= rows[j][w];
                 }
             }
-            flush_lds<W>(acc_l + i * W, acc);
+            flush_lds<P>(acc_l + i * W + sub * P, acc);
         }
         if (ln == 0) pulled += ne;
 
@@ -960,7 +1000,7 @@ template <int W> __global__ void __launch_bounds__(BLOCK) k_push_commit(GraphDev
     if (R.ctrl->converged || (!init && R.ctrl->mode != MODE_PUSH)) return;
     phase_push_commit<W>(g, R, init, blockIdx.x, gridDim.x);
 }
-template <int W> __global__ void __launch_bounds__(BLOCK) k_pull(GraphDev g, RunDev R) {
+template <int W> __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(W >= 8 ? 2 : PP_PULL_WAVES))) k_pull(GraphDev g, RunDev R) {
     if (R.ctrl->converged || R.ctrl->mode != MODE_PULL) return;
     phase_pull<W>(g, R, blockIdx.x, gridDim.x);
 }

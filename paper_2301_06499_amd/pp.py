@@ -18,7 +18,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libpp.so")
 
 PP_OK, PP_EINVAL, PP_ERANGE, PP_ENOMEM, PP_EDEVICE, PP_ENOTCONV, PP_ESTATE = 0, -1, -2, -3, -4, -5, -6
-PP_UNDIRECTED, PP_INPUT_ON_DEVICE, PP_TRANSPOSE = 1, 2, 4
+PP_UNDIRECTED, PP_INPUT_ON_DEVICE, PP_TRANSPOSE, PP_KEEP_ORDER = 1, 2, 4, 8
 PP_SCHED_HEURISTIC, PP_SCHED_PULL, PP_SCHED_PUSH, PP_SCHED_FUZZ, PP_SCHED_MLP = 0, 1, 2, 3, 4
 MODE_PULL, MODE_PUSH, MODE_INIT = 0, 1, 2      # entries of the per-round mode log
 _NAMES = {0: "PP_OK", -1: "PP_EINVAL", -2: "PP_ERANGE", -3: "PP_ENOMEM", -4: "PP_EDEVICE",
@@ -173,9 +173,11 @@ class Graph:
             pass
 
 
-def pp_csr_build(n, src, dst, undirected=False, transpose=False, node_offsets=None, stream=None) -> Graph:
+def pp_csr_build(n, src, dst, undirected=False, transpose=False, node_offsets=None, stream=None,
+                 keep_order=False) -> Graph:
     """Build the device graph from m arcs src[k] -> dst[k] (numpy int32 or device tensors)."""
-    flags = (PP_UNDIRECTED if undirected else 0) | (PP_TRANSPOSE if transpose else 0)
+    flags = ((PP_UNDIRECTED if undirected else 0) | (PP_TRANSPOSE if transpose else 0) |
+             (PP_KEEP_ORDER if keep_order else 0))
     keep = []
     if _is_device(src):
         flags |= PP_INPUT_ON_DEVICE

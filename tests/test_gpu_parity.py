@@ -34,12 +34,12 @@ def pad_words(sig, W):
 
 
 def check_run(n, src, dst, seeds, undirected, transpose=False, sched=pp.PP_SCHED_HEURISTIC,
-              fuzz_seed=0, use_graph=True, want=None, max_rounds=0, persistent=False):
+              fuzz_seed=0, use_graph=True, want=None, max_rounds=0, persistent=False, keep_order=False):
     s = len(seeds)
     if want is None:
         want = oracle.propagate(n, src, dst, seeds, undirected, transpose=transpose,
                                 seed_counts=True, final_sig=True)
-    g = pp.pp_csr_build(n, src, dst, undirected=undirected, transpose=transpose)
+    g = pp.pp_csr_build(n, src, dst, undirected=undirected, transpose=transpose, keep_order=keep_order)
     cap = max_rounds or want["D"] + 4
     opts = pp.options(scheduler=sched, seed_counts=True, max_rounds=cap, fuzz_seed=fuzz_seed,
                       use_graph=use_graph, persistent=persistent)
@@ -102,12 +102,46 @@ def test_random_graphs_word_boundaries(trial):
 
 @pytest.mark.parametrize("sched", SCHEDS)
 @pytest.mark.parametrize("persistent", [False, True])
-def test_rmat_with_hubs(sched, persistent):
-    """R-MAT scale 14: nodes with more arcs than a pull tile holds (hub chunks)."""
+@pytest.mark.parametrize("keep_order", [False, True])
+def test_rmat_with_hubs(sched, persistent, keep_order):
+    """R-MAT scale 14: nodes with more arcs than a pull tile holds (hub chunks);
+    stored in hub-first order (results reported by input id) or in input order."""
     g = gen.rmat(14, 16, 77)
     seeds = gen.sample_seeds(g.n, 256, 8)
-    say("rmat14", sched, "persistent", persistent)
-    check_run(g.n, g.src, g.dst, seeds, False, sched=sched, fuzz_seed=5, persistent=persistent)
+    say("rmat14", sched, "persistent", persistent, "keep_order", keep_order)
+    check_run(g.n, g.src, g.dst, seeds, False, sched=sched, fuzz_seed=5, persistent=persistent,
+              keep_order=keep_order)
+
+
+@pytest.mark.parametrize("keep_order", [False, True])
+def test_device_arcs_seeds_and_signatures(keep_order):
+    """Device-resident input arcs, device seeds for a reset, signatures into device memory."""
+    from hipmem import DeviceArray
+    g = gen.rmat(12, 16, 5)
+    s1 = gen.sample_seeds(g.n, 100, 1)
+    s2 = gen.sample_seeds(g.n, 100, 2)
+    say("device io", keep_order)
+    w1 = oracle.propagate(g.n, g.src, g.dst, s1, False, final_sig=True)
+    w2 = oracle.propagate(g.n, g.src, g.dst, s2, False, final_sig=True)
+    dsrc, ddst = DeviceArray(g.src.astype(np.int32)), DeviceArray(g.dst.astype(np.int32))
+    G = pp.pp_csr_build(g.n, dsrc, ddst, keep_order=keep_order)
+    host_G = pp.pp_csr_build(g.n, g.src, g.dst, keep_order=keep_order)
+    assert G.arcs == host_G.arcs
+    r = pp.pp_seeds_init(G, s1)
+    c, D = pp.pp_propagate_until_converged(r)
+    assert list(c[0]) == list(w1["counts"])
+    out = DeviceArray(dtype=np.uint64, count=g.n * r.words)
+    pp.pp_get_signatures(r, out)
+    assert np.array_equal(out.to_host().reshape(g.n, r.words), pad_words(w1["final_sig"], r.words))
+    pp.pp_seeds_reset(r, DeviceArray(s2.astype(np.int32)))
+    c, D = pp.pp_propagate_until_converged(r)
+    assert list(c[0]) == list(w2["counts"])
+    assert np.array_equal(pp.pp_get_signatures(r), pad_words(w2["final_sig"], r.words))
+    bad = s2.astype(np.int32).copy()
+    bad[7] = g.n
+    with pytest.raises(pp.PPError) as e:
+        pp.pp_seeds_reset(r, DeviceArray(bad))
+    assert e.value.code == pp.PP_ERANGE
 
 
 def test_empty_and_isolated():
