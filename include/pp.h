@@ -159,11 +159,14 @@ int pp_seeds_init(pp_graph g, const int32_t *seeds, int32_t s, const pp_options 
 /*
  * pp_seeds_reset -- the same initialisation on an existing run, reusing its
  * device memory (no allocation): num_graphs * s seed ids, host memory or,
- * with seeds_on_device, device memory the caller owns.  Seeds are checked
- * against the graphs' node ranges on the device path too: an out-of-range
- * id makes the call fail with PP_ERANGE after the stream is synchronised
- * and leaves the run unusable until a successful reset.  Round logs
- * restart; kernel times keep accumulating.
+ * with seeds_on_device, device memory the caller owns.  The call does not
+ * wait for the device (with the per-round engine): the initialisation is
+ * ordered on the run's stream, and a device seed list must stay valid until
+ * the next call that waits.  Host seeds are checked here (PP_ERANGE); device
+ * seeds are checked by the device, and an id outside its graph makes the
+ * next call that waits (a propagation) fail with PP_ERANGE and leaves the
+ * run unusable until a successful reset.  Round logs restart; kernel times
+ * keep accumulating.
  */
 int pp_seeds_reset(pp_run r, const int32_t *seeds, int32_t seeds_on_device);
 

@@ -130,7 +130,21 @@ struct pp_run_s {
     std::vector<int> cur;                   // signature buffer of Sig_{round-1}, per control block
     double clock_khz = 100000.0;            // device wall clock rate
     hipEvent_t tev[2] = {nullptr, nullptr}; // events of pp_time_round
+    // what the host knows of the device's logs: counts rows [0, staged) and D,
+    // refreshed by the same wait that reads the control blocks back
+    void *pinned = nullptr;                 // staging: control blocks, D, count rows
+    Ctrl *h_ctrl = nullptr;
+    int32_t *h_D = nullptr;
+    int64_t *h_rows = nullptr;
+    int32_t *h_seeds = nullptr;             // host seed list on its way to dseeds
+    hipEvent_t seeds_sent = nullptr;        // its copy has been read
+    std::vector<int64_t> counts_host;       // [staged][G]
+    std::vector<int32_t> D_host;            // [G]
+    int staged = 0;
 };
+
+// count rows copied back per wait at most
+constexpr int STAGE_ROWS = 128;
 
 extern "C" {
 
@@ -558,6 +572,8 @@ void free_run(pp_run r) {
     for (hipEvent_t e : r->ev) (void)hipEventDestroy(e);
     for (hipEvent_t e : r->tev)
         if (e) (void)hipEventDestroy(e);
+    if (r->seeds_sent) (void)hipEventDestroy(r->seeds_sent);
+    if (r->pinned) (void)hipHostFree(r->pinned);
     if (r->own_stream && r->stream) (void)hipStreamDestroy(r->stream);
     delete r;
 }
@@ -603,21 +619,24 @@ int alloc_run_dev(pp_graph g, RunDev &d, int s, int W, int cap, bool seed_counts
 hipError_t clear_run_dev(pp_graph g, RunDev &d, hipStream_t st) {
     const int64_t n = g->n;
     const int64_t G = d.G;
-    hipError_t e;
-    if ((e = pp::launch_fill_u64(d.sig[0], 0, n * d.W, st))) return e;
-    if ((e = pp::launch_fill_u64(d.sig[1], 0, n * d.W, st))) return e;
-    if ((e = pp::launch_fill_u64(d.acc, 0, n * d.W, st))) return e;
-    if ((e = pp::launch_fill_i32(d.stamp, -1, n, st))) return e;
-    if ((e = pp::launch_fill_u64((uint64_t *)d.counts, 0, (int64_t)d.cap * G, st))) return e;
-    if (d.seed_counts && (e = pp::launch_fill_i32((int32_t *)d.seed_counts, 0, (int64_t)d.cap * G * d.s, st))) return e;
-    if ((e = pp::launch_fill_i32(d.D, 0, G, st))) return e;
-    if ((e = pp::launch_fill_i32(d.gconv, 0, G, st))) return e;
-    if ((e = pp::launch_fill_i32(d.mode_log, -1, (int64_t)d.cap * G, st))) return e;
-    if ((e = pp::launch_fill_u64((uint64_t *)d.arcs_log, 0, (int64_t)d.cap * G, st))) return e;
-    if ((e = pp::launch_fill_i32((int32_t *)d.bar, 0, G * (int64_t)(sizeof(pp::GridBar) / 4), st))) return e;
-    if ((e = pp::launch_fill_u64((uint64_t *)d.phase_log, 0, (int64_t)d.cap * 3 * G, st))) return e;
-    if ((e = pp::launch_fill_i32((int32_t *)d.feat_log, 0, (int64_t)d.cap * pp::MLP_IN * G, st))) return e;
-    return pp::launch_fill_i32((int32_t *)d.ctrl, 0, G * (int64_t)(sizeof(Ctrl) / 4), st);
+    const int64_t cap = d.cap;
+    auto seg = [](void *p, int64_t bytes, uint32_t v) { return pp::FillSeg{(uint32_t *)p, bytes / 4, v}; };
+    const pp::FillSeg segs[] = {
+        seg(d.sig[0], 2 * 8 * n * d.W, 0u),      // both signature buffers (one allocation)
+        seg(d.acc, 8 * n * d.W, 0u),
+        seg(d.stamp, 4 * n, 0xFFFFFFFFu),        // -1: never queued
+        seg(d.counts, 8 * cap * G, 0u),
+        seg(d.seed_counts, d.seed_counts ? 4 * cap * G * d.s : 0, 0u),
+        seg(d.D, 4 * G, 0u),
+        seg(d.gconv, 4 * G, 0u),
+        seg(d.mode_log, 4 * cap * G, 0xFFFFFFFFu),
+        seg(d.arcs_log, 8 * cap * G, 0u),
+        seg(d.bar, (int64_t)sizeof(pp::GridBar) * G, 0u),
+        seg(d.phase_log, 8 * cap * 3 * G, 0u),
+        seg(d.feat_log, 4 * cap * pp::MLP_IN * G, 0u),
+        seg(d.ctrl, (int64_t)sizeof(Ctrl) * G, 0u),
+    };
+    return pp::launch_fills(segs, (int)(sizeof(segs) / sizeof(segs[0])), st);
 }
 
 TileSet *run_tiles(pp_run r) { return &r->g->tiles[pull_edges_for_words(r->W)]; }
@@ -625,21 +644,92 @@ TileSet *run_tiles(pp_run r) { return &r->g->tiles[pull_edges_for_words(r->W)]; 
 // Host copy of the control state.  The clustered engine keeps one control
 // block per graph: the summary has the largest round, converged when every
 // graph has, and the flags of any.
-int sync_ctrl(pp_run r) {
+// Pinned host staging of a run: G control blocks, G values of D,
+// STAGE_ROWS rows of G counts and a seed list of G s ids.
+int alloc_staging(pp_run r) {
+    const size_t G = (size_t)r->G;
+    const size_t bytes = sizeof(Ctrl) * G + 8 * ((G + 1) / 2) + sizeof(int64_t) * STAGE_ROWS * G +
+                         sizeof(int32_t) * G * (size_t)r->s;
+    if (hipHostMalloc(&r->pinned, bytes, hipHostMallocDefault) != hipSuccess) {
+        r->pinned = nullptr;
+        (void)hipGetLastError();
+        return fail(PP_ENOMEM, "pinned host staging of %zu bytes", bytes);
+    }
+    r->h_ctrl = (Ctrl *)r->pinned;
+    r->h_D = (int32_t *)(r->h_ctrl + G);
+    r->h_rows = (int64_t *)((char *)r->h_D + 8 * ((G + 1) / 2));
+    r->h_seeds = (int32_t *)(r->h_rows + STAGE_ROWS * G);
+    r->D_host.assign(G, 0);
+    if (hipEventCreateWithFlags(&r->seeds_sent, hipEventDisableTiming) != hipSuccess) {
+        r->seeds_sent = nullptr;
+        return fail(PP_EDEVICE, "event creation");
+    }
+    return PP_OK;
+}
+
+// Input seed ids (already checked) -> stored ids in the pinned list, then
+// its copy to the device seed list, both ordered on the run's stream.
+int send_host_seeds(pp_run r, const int32_t *seeds) {
+    const int64_t total = (int64_t)r->G * r->s;
+    HIP_TRY(hipEventSynchronize(r->seeds_sent));   // the last list has been read
+    const std::vector<int32_t> &perm = r->g->perm;
+    for (int64_t j = 0; j < total; ++j) r->h_seeds[j] = perm.empty() ? seeds[j] : perm[(size_t)seeds[j]];
+    HIP_TRY(hipMemcpyAsync(r->dseeds, r->h_seeds, sizeof(int32_t) * (size_t)total, hipMemcpyHostToDevice, r->stream));
+    HIP_TRY(hipEventRecord(r->seeds_sent, r->stream));
+    return PP_OK;
+}
+
+// One wait for the host copy of the control state: the control blocks, D,
+// and the count rows [staged, upto) (at most STAGE_ROWS of them).  The
+// clustered engine keeps one control block per graph: the summary has the
+// largest round, converged when every graph has, and the flags of any.  A
+// seed outside its graph (device seed lists are checked by the device) is
+// reported here.
+int sync_state(pp_run r, int upto) {
     const int nc = r->pgrid ? r->G : 1;
-    std::vector<Ctrl> c((size_t)nc);
-    HIP_TRY(hipMemcpyAsync(c.data(), r->dev.ctrl, sizeof(Ctrl) * (size_t)nc, hipMemcpyDeviceToHost, r->stream));
+    const int G = r->G;
+    HIP_TRY(hipMemcpyAsync(r->h_ctrl, r->dev.ctrl, sizeof(Ctrl) * (size_t)nc, hipMemcpyDeviceToHost, r->stream));
+    HIP_TRY(hipMemcpyAsync(r->h_D, r->dev.D, sizeof(int32_t) * (size_t)G, hipMemcpyDeviceToHost, r->stream));
+    const int rows = std::max(0, std::min({upto, r->cap, r->staged + STAGE_ROWS}) - r->staged);
+    if (rows > 0)
+        HIP_TRY(hipMemcpyAsync(r->h_rows, r->dev.counts + (int64_t)r->staged * G, sizeof(int64_t) * (size_t)rows * G,
+                               hipMemcpyDeviceToHost, r->stream));
     HIP_TRY(hipStreamSynchronize(r->stream));
-    r->host_ctrl = c[0];
+    r->host_ctrl = r->h_ctrl[0];
     r->cur.assign((size_t)nc, 0);
     for (int k = 0; k < nc; ++k) {
-        r->cur[(size_t)k] = c[(size_t)k].cur & 1;
+        const Ctrl &c = r->h_ctrl[k];
+        r->cur[(size_t)k] = c.cur & 1;
         if (k == 0) continue;
-        r->host_ctrl.round = std::max(r->host_ctrl.round, c[(size_t)k].round);
-        r->host_ctrl.converged = r->host_ctrl.converged && c[(size_t)k].converged;
-        r->host_ctrl.overflow |= c[(size_t)k].overflow;
-        r->host_ctrl.bad_seed |= c[(size_t)k].bad_seed;
+        r->host_ctrl.round = std::max(r->host_ctrl.round, c.round);
+        r->host_ctrl.converged = r->host_ctrl.converged && c.converged;
+        r->host_ctrl.overflow |= c.overflow;
+        r->host_ctrl.bad_seed |= c.bad_seed;
     }
+    r->D_host.assign(r->h_D, r->h_D + G);
+    if (rows > 0) {
+        r->counts_host.insert(r->counts_host.end(), r->h_rows, r->h_rows + (size_t)rows * G);
+        r->staged += rows;
+    }
+    if (r->host_ctrl.bad_seed) return fail(PP_ERANGE, "a seed id lies outside its graph's node range");
+    return PP_OK;
+}
+
+int sync_ctrl(pp_run r) { return sync_state(r, 0); }
+
+// Count rows [0, upto) on the host (a wait only for rows not copied yet;
+// many rows at once go straight into the host array).
+int ensure_staged(pp_run r, int upto) {
+    upto = std::min(upto, r->cap);
+    if (r->staged >= upto) return PP_OK;
+    if (upto - r->staged <= STAGE_ROWS) return sync_state(r, upto);
+    const size_t G = (size_t)r->G;
+    const size_t have = r->counts_host.size();
+    r->counts_host.resize((size_t)upto * G);
+    HIP_TRY(hipMemcpyAsync(r->counts_host.data() + have, r->dev.counts + have, sizeof(int64_t) * ((size_t)upto * G - have),
+                           hipMemcpyDeviceToHost, r->stream));
+    HIP_TRY(hipStreamSynchronize(r->stream));
+    r->staged = upto;
     return PP_OK;
 }
 
@@ -676,13 +766,21 @@ int reset_run(pp_run r, const int32_t *dseeds) {
         else e = pp::launch_seed_init(gv, r->dev, dseeds, r->stream);
     }
     if (e != hipSuccess) return fail(PP_EDEVICE, "seed initialisation: %s", hipGetErrorString(e));
+    r->staged = 0;
+    r->counts_host.clear();
+    r->D_host.assign((size_t)r->G, 0);
     if (r->pgrid) {
         int rc = launch_clusters(r, 0);   // round 0 of every graph only
         if (rc) return rc;
+        return sync_ctrl(r);
     }
-    int rc = sync_ctrl(r);
-    if (rc) return rc;
-    if (r->host_ctrl.bad_seed) return fail(PP_ERANGE, "a seed id lies outside its graph's node range");
+    // The per-round engine does not wait: after the initialisation every
+    // graph has c[0] = s > 0, so the state is known -- round 1 next, not
+    // converged, signatures in buffer 0.  A device seed outside its graph is
+    // reported by the next call that waits.
+    r->host_ctrl = Ctrl{};
+    r->host_ctrl.round = 1;
+    r->cur.assign(1, 0);
     return PP_OK;
 }
 
@@ -727,14 +825,6 @@ std::vector<pp::Cluster> make_clusters(pp_graph g, const TileSet *ts, int grid) 
         ch0 += (n1 - n0) + c.m / pp::PUSH_CHUNK_MIN + 2;
     }
     return cl;
-}
-
-// Input node ids -> stored ids (hub-first order), for ids already checked.
-std::vector<int32_t> stored_ids(pp_graph g, const int32_t *ids, int64_t count) {
-    std::vector<int32_t> out(ids, ids + count);
-    if (!g->perm.empty())
-        for (auto &x : out) x = g->perm[(size_t)x];
-    return out;
 }
 
 int check_host_seeds(pp_graph g, const int32_t *seeds, int s) {
@@ -834,12 +924,13 @@ extern "C" int pp_seeds_init(pp_graph g, const int32_t *seeds, int32_t s, const 
     r->dev.fuzz_seed = o.fuzz_seed;
     // cost-model weights start as NaN: the heuristic decides until they are set
     hipError_t e = pp::launch_fill_i32((int32_t *)r->dev.mlp, kNaNBits, pp::MLP_PARAMS, r->stream);
-    const std::vector<int32_t> stored = stored_ids(g, seeds, (int64_t)G * s);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(r->dseeds, stored.data(), sizeof(int32_t) * (size_t)G * s, hipMemcpyHostToDevice, r->stream);
     if (e != hipSuccess) {
         free_run(r);
-        return fail(PP_EDEVICE, "seed upload: %s", hipGetErrorString(e));
+        return fail(PP_EDEVICE, "cost-model reset: %s", hipGetErrorString(e));
+    }
+    if ((rc = alloc_staging(r)) != PP_OK || (rc = send_host_seeds(r, seeds)) != PP_OK) {
+        free_run(r);
+        return rc;
     }
     if ((rc = reset_run(r, r->dseeds)) != PP_OK) {
         free_run(r);
@@ -855,9 +946,8 @@ extern "C" int pp_seeds_reset(pp_run r, const int32_t *seeds, int32_t seeds_on_d
     if (!seeds_on_device) {
         int rc = check_host_seeds(r->g, seeds, r->s);
         if (rc) return rc;
-        const std::vector<int32_t> stored = stored_ids(r->g, seeds, total);
-        HIP_TRY(hipMemcpyAsync(r->dseeds, stored.data(), sizeof(int32_t) * (size_t)total, hipMemcpyHostToDevice, r->stream));
-        return reset_run(r, r->dseeds);   // synchronises before `stored` goes
+        if ((rc = send_host_seeds(r, seeds))) return rc;
+        return reset_run(r, r->dseeds);
     }
     if (r->g->perm_d) {
         // ids outside [0, n) become -1, which the seed placement reports
@@ -910,28 +1000,27 @@ extern "C" int pp_propagate_round(pp_run r, int64_t *new_bits, int32_t *all_conv
         return r->host_ctrl.overflow ? fail(PP_ENOTCONV, "round log full (max_rounds)") : PP_OK;
     }
     const int rr = r->host_ctrl.round;
+    int rc;
     if (r->pgrid) {
-        int rc = run_persistent(r, rr);
-        if (rc) return rc;
-        if (new_bits)
-            HIP_TRY(hipMemcpy(new_bits, r->dev.counts + (int64_t)rr * G, sizeof(int64_t) * (size_t)G,
-                              hipMemcpyDeviceToHost));
-        if (all_converged) *all_converged = r->host_ctrl.converged;
-        if (r->host_ctrl.overflow) return fail(PP_ENOTCONV, "round log full (max_rounds)");
-        return PP_OK;
+        if ((rc = run_persistent(r, rr))) return rc;
+    } else {
+        GraphDev gv = graph_view(r->g, run_tiles(r));
+        hipEvent_t e0 = r->timing ? r->ev[0] : nullptr, e1 = r->timing ? r->ev[1] : nullptr;
+        HIP_TRY(pp::launch_round(gv, r->dev, r->stream, e0, e1));
+        if ((rc = sync_state(r, rr + 1))) return rc;
+        if (r->timing) {
+            float ms = 0.0f;
+            HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+            r->pull_ms[(size_t)rr] += ms;
+        }
     }
-    GraphDev gv = graph_view(r->g, run_tiles(r));
-    hipEvent_t e0 = r->timing ? r->ev[0] : nullptr, e1 = r->timing ? r->ev[1] : nullptr;
-    HIP_TRY(pp::launch_round(gv, r->dev, r->stream, e0, e1));
-    if (new_bits)
-        HIP_TRY(hipMemcpyAsync(new_bits, r->dev.counts + (int64_t)rr * G, sizeof(int64_t) * (size_t)G,
-                               hipMemcpyDeviceToHost, r->stream));
-    int rc = sync_ctrl(r);
-    if (rc) return rc;
-    if (r->timing) {
-        float ms = 0.0f;
-        HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-        r->pull_ms[(size_t)rr] += ms;
+    if (new_bits) {
+        if (rr < r->cap) {
+            if ((rc = ensure_staged(r, rr + 1))) return rc;
+            std::memcpy(new_bits, r->counts_host.data() + (size_t)rr * G, sizeof(int64_t) * (size_t)G);
+        } else {
+            std::memset(new_bits, 0, sizeof(int64_t) * (size_t)G);
+        }
     }
     if (all_converged) *all_converged = r->host_ctrl.converged;
     if (r->host_ctrl.overflow) return fail(PP_ENOTCONV, "round log full (max_rounds)");
@@ -1005,7 +1094,7 @@ extern "C" int pp_propagate_until_converged(pp_run r, int32_t max_rounds, int64_
         const int before = r->host_ctrl.round;
         int rc = launch_batch(r, k);
         if (rc) return rc;
-        if ((rc = sync_ctrl(r))) return rc;
+        if ((rc = sync_state(r, before + k))) return rc;
         if (r->timing) {
             // rounds before..last ran; launches after convergence returned at once
             const int last = r->host_ctrl.converged ? r->host_ctrl.round : before + k - 1;
@@ -1024,20 +1113,17 @@ extern "C" int pp_propagate_until_converged(pp_run r, int32_t max_rounds, int64_
         }
         if (r->opt.rounds_per_sync <= 0) K = std::min(std::max(8, r->host_ctrl.round - start), 64);
     }
-    // results
+    // results, from what the waits above copied back
     const int last = std::min(r->host_ctrl.round, r->cap - 1);
     if (counts) {
-        std::vector<int64_t> buf((size_t)(last + 1) * G);
-        HIP_TRY(hipMemcpyAsync(buf.data(), r->dev.counts, sizeof(int64_t) * buf.size(), hipMemcpyDeviceToHost, r->stream));
-        HIP_TRY(hipStreamSynchronize(r->stream));
+        int rc = ensure_staged(r, last + 1);
+        if (rc) return rc;
         std::memset(counts, 0, sizeof(int64_t) * (size_t)G * cap_rounds);
         for (int g = 0; g < G; ++g)
-            for (int k = 0; k <= last && k < cap_rounds; ++k) counts[(int64_t)g * cap_rounds + k] = buf[(size_t)k * G + g];
+            for (int k = 0; k <= last && k < cap_rounds; ++k)
+                counts[(int64_t)g * cap_rounds + k] = r->counts_host[(size_t)k * G + g];
     }
-    if (D) {
-        HIP_TRY(hipMemcpyAsync(D, r->dev.D, sizeof(int32_t) * (size_t)G, hipMemcpyDeviceToHost, r->stream));
-        HIP_TRY(hipStreamSynchronize(r->stream));
-    }
+    if (D) std::memcpy(D, r->D_host.data(), sizeof(int32_t) * (size_t)G);
     if (!r->host_ctrl.converged || r->host_ctrl.overflow) return fail(PP_ENOTCONV, "stopped after %d rounds without convergence", r->host_ctrl.round);
     return PP_OK;
 }
@@ -1148,6 +1234,7 @@ extern "C" int pp_run_snapshot(pp_run r, pp_run *copy) {
     }
     int rc = alloc_run_dev(r->g, c->dev, r->s, r->W, r->cap, r->dev.seed_counts != nullptr,
                            std::max(pp::pull_grid_for(ts->ntiles), r->pgrid));
+    if (!rc) rc = alloc_staging(c);
     if (rc) {
         free_run(c);
         return rc;
@@ -1200,6 +1287,9 @@ extern "C" int pp_run_restore(pp_run r, pp_run from) {
     if (e) return fail(PP_EDEVICE, "restore: %s", hipGetErrorString(e));
     r->host_ctrl = from->host_ctrl;
     r->cur = from->cur;
+    r->staged = from->staged;
+    r->counts_host = from->counts_host;
+    r->D_host = from->D_host;
     return PP_OK;
 }
 

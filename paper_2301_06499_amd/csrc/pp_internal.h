@@ -182,6 +182,14 @@ hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t count, hipStream_t st)
 // Re-takes the pending direction of each of the first nctrl control blocks
 // with the run's current cost-model weights (PP_SCHED_MLP runs only).
 hipError_t launch_redecide(const RunDev &r, int nctrl, hipStream_t st);
+// A fill of n 4-byte words at p (16-byte aligned) with the value v.
+struct FillSeg {
+    uint32_t *p;
+    int64_t n;
+    uint32_t v;
+};
+// Every segment in as few launches as possible (one for up to 16 segments).
+hipError_t launch_fills(const FillSeg *segs, int nseg, hipStream_t st);
 // out[j] = perm[in[j]] (ids outside [0, n) become -1).
 hipError_t launch_map_ids(int32_t *out, const int32_t *in, const int32_t *perm, int64_t count, int64_t n,
                           hipStream_t st);

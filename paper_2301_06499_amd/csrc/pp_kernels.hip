@@ -270,6 +270,59 @@ hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t count, hipStream_t st)
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------- fused fills
+
+// Several fills in one launch: block b fills chunk b - first_block[k] of
+// segment k (FILL_CHUNK 4-byte words; 16-byte stores for whole quadruples).
+constexpr int FILL_SEGS = 16;
+constexpr int64_t FILL_CHUNK = (int64_t)BLOCK * 16;
+struct FillPlan {
+    FillSeg seg[FILL_SEGS];
+    int64_t first_block[FILL_SEGS + 1];
+    int32_t nseg;
+};
+
+__global__ void __launch_bounds__(BLOCK) k_fill_plan(FillPlan P) {
+    const int64_t b = blockIdx.x;
+    int k = 0;
+    while (k + 1 < P.nseg && P.first_block[k + 1] <= b) ++k;
+    const FillSeg S = P.seg[k];
+    const int64_t w0 = (b - P.first_block[k]) * FILL_CHUNK;
+    const int64_t w1 = w0 + FILL_CHUNK < S.n ? w0 + FILL_CHUNK : S.n;
+    const int64_t body = w0 + ((w1 - w0) & ~(int64_t)3);
+    const uint4 q = make_uint4(S.v, S.v, S.v, S.v);
+    for (int64_t i = w0 + threadIdx.x * 4; i < body; i += BLOCK * 4) *reinterpret_cast<uint4 *>(S.p + i) = q;
+    for (int64_t i = body + threadIdx.x; i < w1; i += BLOCK) S.p[i] = S.v;
+}
+
+hipError_t launch_fills(const FillSeg *segs, int nseg, hipStream_t st) {
+    FillPlan P{};
+    int k = 0;
+    int64_t blocks = 0;
+    auto flush = [&]() -> hipError_t {
+        if (k == 0) return hipSuccess;
+        P.nseg = k;
+        P.first_block[k] = blocks;
+        hipLaunchKernelGGL(k_fill_plan, dim3((unsigned)blocks), dim3(BLOCK), 0, st, P);
+        P = FillPlan{};
+        k = 0;
+        blocks = 0;
+        return hipGetLastError();
+    };
+    for (int i = 0; i < nseg; ++i) {
+        if (segs[i].n <= 0) continue;
+        if (k == FILL_SEGS) {
+            const hipError_t e = flush();
+            if (e != hipSuccess) return e;
+        }
+        P.seg[k] = segs[i];
+        P.first_block[k] = blocks;
+        blocks += (segs[i].n + FILL_CHUNK - 1) / FILL_CHUNK;
+        ++k;
+    }
+    return flush();
+}
+
 // ---------------------------------------------------------------- node ids
 
 // out[j] = perm[in[j]] for ids in [0, n), -1 otherwise.

@@ -137,11 +137,14 @@ def test_device_arcs_seeds_and_signatures(keep_order):
     c, D = pp.pp_propagate_until_converged(r)
     assert list(c[0]) == list(w2["counts"])
     assert np.array_equal(pp.pp_get_signatures(r), pad_words(w2["final_sig"], r.words))
-    bad = s2.astype(np.int32).copy()
-    bad[7] = g.n
+    bad = DeviceArray(np.where(np.arange(100) == 7, g.n, s2).astype(np.int32))
+    pp.pp_seeds_reset(r, bad)   # checked on the device: reported by the next wait
     with pytest.raises(pp.PPError) as e:
-        pp.pp_seeds_reset(r, DeviceArray(bad))
+        pp.pp_propagate_until_converged(r)
     assert e.value.code == pp.PP_ERANGE
+    pp.pp_seeds_reset(r, s1)
+    c, D = pp.pp_propagate_until_converged(r)
+    assert list(c[0]) == list(w1["counts"])
 
 
 def test_empty_and_isolated():
