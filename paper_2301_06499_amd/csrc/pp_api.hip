@@ -552,6 +552,7 @@ void free_run_dev(RunDev &d) {
     dev_free(d.bar);
     dev_free(d.phase_log);
     dev_free(d.feat_log);
+    dev_free(d.tickets);
     dev_free(d.mlp);
 }
 
@@ -605,7 +606,8 @@ int alloc_run_dev(pp_graph g, RunDev &d, int s, int W, int cap, bool seed_counts
         (rc = dev_alloc(&d.mode_log, (int64_t)cap * G)) || (rc = dev_alloc(&d.arcs_log, (int64_t)cap * G)) ||
         (rc = dev_alloc(&d.ctrl, G)) || (rc = dev_alloc(&d.bar, G)) ||
         (rc = dev_alloc(&d.phase_log, (int64_t)cap * 3 * G)) ||
-        (rc = dev_alloc(&d.feat_log, (int64_t)cap * pp::MLP_IN * G)) || (rc = dev_alloc(&d.mlp, pp::MLP_PARAMS)))
+        (rc = dev_alloc(&d.feat_log, (int64_t)cap * pp::MLP_IN * G)) || (rc = dev_alloc(&d.mlp, pp::MLP_PARAMS)) ||
+        (rc = dev_alloc(&d.tickets, pp::TICKET_INTS)))
         return rc;
     d.sig[1] = d.sig[0] + n * W;
     d.f_ids[1] = d.f_ids[0] + n;
@@ -635,6 +637,7 @@ hipError_t clear_run_dev(pp_graph g, RunDev &d, hipStream_t st) {
         seg(d.phase_log, 8 * cap * 3 * G, 0u),
         seg(d.feat_log, 4 * cap * pp::MLP_IN * G, 0u),
         seg(d.ctrl, (int64_t)sizeof(Ctrl) * G, 0u),
+        seg(d.tickets, 4 * pp::TICKET_INTS, 0u),
     };
     return pp::launch_fills(segs, (int)(sizeof(segs) / sizeof(segs[0])), st);
 }
@@ -1281,6 +1284,7 @@ extern "C" int pp_run_restore(pp_run r, pp_run from) {
     if (!e) e = cp(b.phase_log, a.phase_log, 8 * cap * 3 * G);
     if (!e) e = cp(b.feat_log, a.feat_log, sizeof(float) * pp::MLP_IN * cap * G);
     if (!e) e = cp(b.mlp, a.mlp, sizeof(float) * pp::MLP_PARAMS);
+    if (!e) e = cp(b.tickets, a.tickets, sizeof(int32_t) * pp::TICKET_INTS);
     if (!e) e = cp(b.ctrl, a.ctrl, sizeof(Ctrl) * G);
     if (!e) e = cp(b.bar, a.bar, sizeof(pp::GridBar) * G);
     if (!e) e = hipStreamSynchronize(st);

@@ -89,6 +89,13 @@ struct Ctrl {
     float feat[8];        // scheduler features of the round about to run
 };
 
+// Counters of the closing launch's two-level ticket: TICKET_GROUP group
+// counters, each on its own 128-byte line, then the top counter (launches of
+// at most TICKET_GROUP^2 blocks).
+constexpr int TICKET_GROUP = 32;
+constexpr int TICKET_STRIDE = 32;   // int32 per cache line
+constexpr int TICKET_INTS = (TICKET_GROUP + 1) * TICKET_STRIDE;
+
 // Learned cost model: an MLP 8 -> 32 -> 32 -> 2 (ReLU) predicting the log of a
 // round's duration under pull (output 0) and push (output 1).  Parameter
 // layout (floats): W1[32][8], b1[32], W2[32][32], b2[32], W3[2][32], b3[2].
@@ -164,6 +171,7 @@ struct RunDev {
     int64_t *arcs_log;    // [G][cap]
     int64_t *phase_log;   // [G][cap][3] device-clock stamps of the persistent loop
     float *feat_log;      // [G][cap][8] scheduler features of each round (row 0 unused)
+    int32_t *tickets;     // [TICKET_INTS] the closing launch's ticket counters (zero between launches)
     GridBar *bar;         // [G] barrier state per cluster
     Ctrl *ctrl;           // [G]: ctrl[0] for the per-round engine, one per graph when clustered
     // scheduler

@@ -1,21 +1,21 @@
 // HIP kernels for PROPAGATE-P rounds on gfx950 (wave64).
 //
 // A round r (one pass of Algorithm 1's do-while body) is a fixed sequence of
-// launches that hand work to each other through the device control block,
-// so no host decision is needed between rounds and a batch of rounds can be
-// replayed as a captured graph.  Kernels of the direction not chosen for the
-// round return at once.
+// four launches that hand work to each other through the device control
+// block, so no host decision is needed between rounds and a batch of rounds
+// can be replayed as a captured graph.  Kernels of the direction not chosen
+// for the round return at once.
 //
 // Dense pull (the ball recurrence of Section 4, Sig_r(u) = Sig_{r-1}(u) OR
 // the rows of u's successors):
-//   k_pull<W>        tiles of consecutive nodes: successor ids staged in LDS,
-//                    each thread ORs the rows of K consecutive arcs in
-//                    registers and flushes them into the node's LDS row; the
-//                    new row is written to the other signature buffer (the
-//                    update is synchronous because Sig_{r-1} is only read).
-//                    New bits are counted per block (Algorithm 1's XOR count).
-//                    Chunks of high-degree nodes OR into the accumulator.
-//   k_pull_hubs<W>   finishes the high-degree nodes.
+//   k_pull<W>        tiles of consecutive nodes: successor ids staged in LDS;
+//                    groups of lanes share each source row (one 16-byte load
+//                    per lane), OR K consecutive arcs in registers and flush
+//                    them into the node's LDS row; the new row is written to
+//                    the other signature buffer (the update is synchronous
+//                    because Sig_{r-1} is only read).  New bits are counted
+//                    per block (Algorithm 1's XOR count).  Chunks of
+//                    high-degree nodes OR into the accumulator.
 // Sparse push (equal to the pull: only the bits a node gained in round r-1
 // can give new bits in round r, every older bit having reached its
 // predecessors already):
@@ -23,10 +23,13 @@
 //   k_push<W>        ORs those new bits into the predecessors' rows with
 //                    atomics; a bit is new when the atomic that sets it saw
 //                    it clear; nodes that gained bits are queued once.
-//   k_push_commit<W> collects the gained bits, counts them, lists them.
-// k_round_end        counts, convergence (a graph converges at its first
-//                    round without a new bit), diameter bookkeeping, the
-//                    per-round log and the direction of the next round.
+// Closing launch:
+//   k_post<W>        a push round's commit (collects the gained bits, counts
+//                    and lists them) or a pull round's high-degree nodes;
+//                    then its last block runs the round's end: counts,
+//                    convergence (a graph converges at its first round
+//                    without a new bit), diameter bookkeeping, the per-round
+//                    log, the features and direction of the next round.
 #include "pp_internal.h"
 
 namespace pp {
@@ -990,7 +993,7 @@ PP_DEV void phase_round_end(const GraphDev &g, const RunDev &R, int init, int np
     int act = 0;
     long long cnt = 0;
     for (int gi = threadIdx.x; gi < R.G; gi += BLOCK) {
-        const long long c = R.counts[(int64_t)r * R.cstride + gi];
+        const long long c = CTL(R.counts[(int64_t)r * R.cstride + gi]);
         cnt += c;
         if (R.gconv[gi]) continue;
         if (c == 0) {
@@ -1072,6 +1075,46 @@ template <int W> __global__ void __launch_bounds__(BLOCK) k_push(GraphDev g, Run
 __global__ void __launch_bounds__(BLOCK) k_round_end(GraphDev g, RunDev R, int init) {
     if (R.ctrl->converged) return;
     phase_round_end(g, R, init, g.pull_grid);
+}
+
+// Two-level ticket (one thread per block): true for the block that finishes
+// last.  Blocks count off in groups of TICKET_GROUP, each group on its own
+// cache line, and the last block of each group counts off at the top, so no
+// address takes more than TICKET_GROUP atomics.  Whoever completes a counter
+// resets it for the next launch.
+PP_DEV bool last_block(int32_t *tickets, int bid, int nb) {
+    const int ngroups = (nb + TICKET_GROUP - 1) / TICKET_GROUP;
+    const int gi = bid / TICKET_GROUP;
+    const int gsize = nb - gi * TICKET_GROUP < TICKET_GROUP ? nb - gi * TICKET_GROUP : TICKET_GROUP;
+    int32_t *gc = tickets + gi * TICKET_STRIDE;
+    if (__hip_atomic_fetch_add(gc, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != gsize - 1) return false;
+    __hip_atomic_store(gc, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    int32_t *top = tickets + TICKET_GROUP * TICKET_STRIDE;
+    if (__hip_atomic_fetch_add(top, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != ngroups - 1) return false;
+    __hip_atomic_store(top, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return true;
+}
+
+// The closing launch of a round: the list commit of a push round or the
+// high-degree nodes of a pull round, then the round's end, run by the last
+// block to finish.  Everything the round's end reads from the other blocks
+// of this launch was written by device-scope atomics (counts, list sizes,
+// hub totals) and is read back with atomic loads; a block takes its ticket
+// only after its own memory operations have completed (a workgroup-scope
+// release waits for them without writing back the caches).
+template <int W> __global__ void __launch_bounds__(BLOCK) k_post(GraphDev g, RunDev R) {
+    Ctrl *C = R.ctrl;
+    if (CTL(C->converged)) return;   // set only by the last block, after every block has finished
+    if (CTL(C->mode) == MODE_PUSH) phase_push_commit<W>(g, R, 0, blockIdx.x, gridDim.x);
+    else phase_pull_hubs<W>(g, R, blockIdx.x, gridDim.x);
+    __shared__ int s_last;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __syncthreads();
+    if (threadIdx.x == 0) s_last = last_block(R.tickets, (int)blockIdx.x, (int)gridDim.x);
+    __syncthreads();
+    if (!s_last) return;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    phase_round_end(g, R, 0, g.pull_grid);
 }
 
 // New cost-model weights for a run in progress: the direction of the round
@@ -1276,6 +1319,9 @@ int pull_grid_for(int32_t ntiles) {
     return b < 1 ? 1 : (b < PULL_GRID_MAX ? b : PULL_GRID_MAX);
 }
 
+// blocks of the frontier, push and closing launches (at most 1024, which the
+// closing launch's ticket covers)
+static_assert(TICKET_GROUP * TICKET_GROUP >= 1024, "ticket groups");
 static int list_grid(const GraphDev &g) {
     const int64_t b = (g.n + BLOCK - 1) / BLOCK;
     return (int)(b < 64 ? 64 : (b > 1024 ? 1024 : b));
@@ -1294,7 +1340,6 @@ static hipError_t round_impl(const GraphDev &g, const RunDev &R, hipStream_t st,
     const int lg = list_grid(g);
     hipLaunchKernelGGL(k_frontier<W>, dim3(lg), dim3(BLOCK), 0, st, g, R);
     hipLaunchKernelGGL(k_push<W>, dim3(lg), dim3(BLOCK), 0, st, g, R);
-    hipLaunchKernelGGL(k_push_commit<W>, dim3(lg), dim3(BLOCK), 0, st, g, R, 0);
     if (e0) {
         const hipError_t e = hipEventRecord(e0, st);
         if (e != hipSuccess) return e;
@@ -1304,8 +1349,7 @@ static hipError_t round_impl(const GraphDev &g, const RunDev &R, hipStream_t st,
         const hipError_t e = hipEventRecord(e1, st);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(k_pull_hubs<W>, dim3(64), dim3(BLOCK), 0, st, g, R);
-    hipLaunchKernelGGL(k_round_end, dim3(1), dim3(BLOCK), 0, st, g, R, 0);
+    hipLaunchKernelGGL(k_post<W>, dim3(lg), dim3(BLOCK), 0, st, g, R);
     return hipGetLastError();
 }
 
