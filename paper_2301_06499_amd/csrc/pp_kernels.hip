@@ -138,6 +138,19 @@ template <int W> PP_DEV void load_row(const uint64_t *__restrict__ p, uint64_t (
     }
 }
 
+template <int W> PP_DEV void store_row(uint64_t *__restrict__ p, const uint64_t (&v)[W]) {
+    if constexpr (W == 1) {
+        p[0] = v[0];
+    } else {
+#pragma unroll
+        for (int k = 0; k < W; k += 2) {
+            ulonglong2 q;
+            q.x = v[k];
+            q.y = v[k + 1];
+            *reinterpret_cast<ulonglong2 *>(p + k) = q;
+        }
+    }
+}
 template <int W> PP_DEV void flush_lds(unsigned long long *dst, uint64_t (&acc)[W]) {
 #pragma unroll
     for (int w = 0; w < W; ++w) {
@@ -206,6 +219,29 @@ PP_DEV int block_scan(int v, int *scratch, int &total) {
 template <int W> PP_DEV int chunks_for(int64_t deg) {
     constexpr int CH = PushShape<W>::CHUNK;
     return deg > PUSH_LIGHT ? (int)((deg + CH - 1) / CH) : 0;
+}
+
+// Push chunk records of one block iteration, written by the whole block:
+// thread t owns nchk chunks of entry `entry` at slots [before, before + nchk)
+// of out (before: the block's exclusive scan of nchk; total: its sum).  Each
+// thread writes every BLOCK-th slot, finding the owner by binary search over
+// the block's scan, so one long list costs no thread more than total/BLOCK
+// stores.  All threads of the block call; ends with a barrier.
+PP_DEV void write_chunks(Chunk *out, int before, int nchk, int32_t entry, int total, int chunk, int *s_pre,
+                         int32_t *s_ent) {
+    s_pre[threadIdx.x] = before;
+    s_ent[threadIdx.x] = entry;
+    (void)nchk;
+    __syncthreads();
+    for (int c = threadIdx.x; c < total; c += BLOCK) {
+        int lo = 0, hi = BLOCK - 1;   // last thread whose first slot is <= c: it owns slot c
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (s_pre[mid] <= c) lo = mid; else hi = mid - 1;
+        }
+        out[c] = Chunk{s_ent[lo], (c - s_pre[lo]) * chunk};
+    }
+    __syncthreads();
 }
 
 // Lists nodes in a block-private LDS queue and moves the queue to the global
@@ -403,6 +439,8 @@ PP_DEV void phase_push_commit(const GraphDev &g, const RunDev &R, int init, int 
     const bool per_seed = R.seed_counts != nullptr;
     __shared__ int s_scan[BLOCK / 64];
     __shared__ int s_cbase;
+    __shared__ int s_pre[BLOCK];
+    __shared__ int32_t s_ent[BLOCK];
     uint64_t pop = 0;
     int64_t arcs = 0;
     uint32_t sc[W];
@@ -446,9 +484,7 @@ PP_DEV void phase_push_commit(const GraphDev &g, const RunDev &R, int init, int 
         if (total) {
             if (threadIdx.x == 0) s_cbase = atomicAdd(&C->ch_count[p], total);
             __syncthreads();
-            const int first = s_cbase + before;
-            for (int j = 0; j < nchk; ++j) chunks[first + j] = Chunk{e, j * PushShape<W>::CHUNK};
-            __syncthreads();
+            write_chunks(chunks + s_cbase, before, nchk, e, total, PushShape<W>::CHUNK, s_pre, s_ent);
         }
         if (per_seed) {
             if (R.G == 1) seed_ballot<W>(d, sc);
@@ -623,6 +659,7 @@ PP_DEV void phase_pull(const GraphDev &g, const RunDev &R, int bid, int nb) {
                 if (lead) {
                     nodes += 1;
                     parcs += g.trp[u + 1] - g.trp[u];
+                    R.stamp[u] = r;   // changed in this round: listed by a push that follows
                 }
                 if (per_seed) {
                     if (R.G == 1) seed_ballot<W>(nw2, sc);
@@ -691,6 +728,7 @@ PP_DEV void phase_pull_hubs(const GraphDev &g, const RunDev &R, int bid, int nb)
         if (lead) {
             nodes += 1;
             parcs += g.trp[u + 1] - g.trp[u];
+            R.stamp[u] = r;
         }
         const int pc = __popcll(nw);
         int gi = 0;
@@ -720,49 +758,58 @@ PP_DEV void phase_pull_hubs(const GraphDev &g, const RunDev &R, int bid, int nb)
 // ---------------------------------------------------------------- push
 
 // After a pull round the frontier is not listed; this lists the nodes that
-// changed in round r-1 (Sig_{r-1} and Sig_{r-2} are the two buffers) with
-// their new bits, into list (r-1)&1.  Each block owns a contiguous node range:
-// a first pass counts its entries and push chunks, one atomic per block
-// reserves their slots, a second pass writes them in node order.
+// changed in round r-1 (the pull stamped them with r-1) with their new bits
+// (Sig_{r-1} and Sig_{r-2} are the two buffers), into list (r-1)&1.  Each
+// block owns a contiguous node range, one thread per node: a first pass
+// counts its entries and push chunks from the stamps alone, one atomic per
+// block reserves their slots, a second pass writes them in node order (rows
+// read for the changed nodes only) and stops once the block's entries are
+// written.
 template <int W>
 PP_DEV void phase_frontier(const GraphDev &g, const RunDev &R, int bid, int nb) {
     Ctrl *C = R.ctrl;
-    constexpr int NPI = BLOCK / W;   // nodes per block iteration
     const int r = CTL(C->round);
     const int p = (r - 1) & 1;
     const int cur = CTL(C->cur);
     const uint64_t *now = sel(R.sig, cur);
     const uint64_t *old = sel(R.sig, cur ^ 1);
-    const int ln = lane_id();
-    const int w = ln & (W - 1);
-    const int gb = ln & ~(W - 1);
     const int64_t span = g.n - g.n0;   // the view's node range [n0, n)
-    const int64_t per = ((span + nb - 1) / nb + NPI - 1) / NPI * NPI;
+    const int64_t per = ((span + nb - 1) / nb + BLOCK - 1) / BLOCK * BLOCK;
     const int64_t u_begin = g.n0 + (int64_t)bid * per;
     const int64_t u_end = u_begin + per < g.n ? u_begin + per : g.n;
     __shared__ int s_scan[BLOCK / 64];
     __shared__ unsigned long long s_red[BLOCK / 64];
     __shared__ int s_nbase, s_cbase;
+    __shared__ int s_pre[BLOCK];
+    __shared__ int32_t s_ent[BLOCK];
 
     int nodes = 0, nchunks = 0;
     int64_t arcs = 0;
-    for (int64_t ub = u_begin; ub < u_end; ub += NPI) {   // block-uniform
-        const int64_t u = ub + threadIdx.x / W;
-        const bool valid = u < u_end;
-        const int64_t idx = u * W + w;
-        const uint64_t d = valid ? (now[idx] & ~old[idx]) : 0;
-        const uint64_t bal = __ballot(d != 0);
-        const bool lead = valid && w == 0 && ((bal >> gb) & WordMask<W>::row) != 0;
-        if (lead) {
-            const int64_t deg = g.trp[u + 1] - g.trp[u];
-            nodes += 1;
+    constexpr int U = 4;   // nodes per thread whose loads are in flight together
+    for (int64_t u0 = u_begin + threadIdx.x; u0 < u_end; u0 += (int64_t)U * BLOCK) {
+        bool ch[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            const int64_t u = u0 + (int64_t)k * BLOCK;
+            ch[k] = u < u_end && R.stamp[u] == r - 1;
+        }
+        int64_t lo[U], hi[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            const int64_t u = u0 + (int64_t)k * BLOCK;
+            lo[k] = ch[k] ? g.trp[u] : 0;
+            hi[k] = ch[k] ? g.trp[u + 1] : 0;
+        }
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            const int64_t deg = hi[k] - lo[k];
+            nodes += ch[k] ? 1 : 0;
             arcs += deg;
             nchunks += chunks_for<W>(deg);
         }
     }
-    int tn = 0, tc = 0;
-    (void)block_scan(nodes, s_scan, tn);
-    (void)block_scan(nchunks, s_scan, tc);
+    const int tn = block_sum<int>(nodes, s_scan);
+    const int tc = block_sum<int>(nchunks, s_scan);
     const unsigned long long ta = block_sum<unsigned long long>((unsigned long long)arcs, s_red);
     if (threadIdx.x == 0) {
         s_nbase = tn ? atomicAdd(&C->f_count[p], tn) : 0;
@@ -771,28 +818,29 @@ PP_DEV void phase_frontier(const GraphDev &g, const RunDev &R, int bid, int nb) 
     }
     __syncthreads();
     if (tn == 0) return;   // same for the whole block
-    int nrun = s_nbase, crun = s_cbase;
-    for (int64_t ub = u_begin; ub < u_end; ub += NPI) {   // block-uniform
-        const int64_t u = ub + threadIdx.x / W;
-        const bool valid = u < u_end;
-        const int64_t idx = u * W + w;
-        const uint64_t d = valid ? (now[idx] & ~old[idx]) : 0;
-        const uint64_t bal = __ballot(d != 0);
-        const bool changed = valid && ((bal >> gb) & WordMask<W>::row) != 0;
-        const bool lead = changed && w == 0;
-        int64_t deg = 0;
-        if (lead) deg = g.trp[u + 1] - g.trp[u];
-        const int nchk = lead ? chunks_for<W>(deg) : 0;
+    int32_t *ids = sel(R.f_ids, p);
+    uint64_t *dl = sel(R.f_delta, p);
+    Chunk *chunks = sel(R.chunks, p);
+    int done = 0, crun = s_cbase;
+    for (int64_t ub = u_begin; ub < u_end && done < tn; ub += BLOCK) {   // block-uniform
+        const int64_t u = ub + threadIdx.x;
+        const bool changed = u < u_end && R.stamp[u] == r - 1;
+        const int64_t deg = changed ? g.trp[u + 1] - g.trp[u] : 0;
+        const int nchk = changed ? chunks_for<W>(deg) : 0;
         int it_nodes = 0, it_chunks = 0;
-        int pos = nrun + block_scan(lead ? 1 : 0, s_scan, it_nodes);
+        const int pos = s_nbase + done + block_scan(changed ? 1 : 0, s_scan, it_nodes);
         const int cfirst = crun + block_scan(nchk, s_scan, it_chunks);
-        pos = __shfl(pos, gb);
         if (changed) {
-            if (lead) sel(R.f_ids, p)[pos] = (int32_t)u;
-            sel(R.f_delta, p)[(int64_t)pos * W + w] = d;
+            uint64_t a[W], b[W];
+            load_row<W>(now + u * W, a);
+            load_row<W>(old + u * W, b);
+#pragma unroll
+            for (int w = 0; w < W; ++w) a[w] &= ~b[w];
+            ids[pos] = (int32_t)u;
+            store_row<W>(dl + (int64_t)pos * W, a);
         }
-        for (int j = 0; j < nchk; ++j) sel(R.chunks, p)[cfirst + j] = Chunk{pos, j * PushShape<W>::CHUNK};
-        nrun += it_nodes;
+        if (it_chunks) write_chunks(chunks + crun, cfirst - crun, nchk, pos, it_chunks, PushShape<W>::CHUNK, s_pre, s_ent);
+        done += it_nodes;
         crun += it_chunks;
     }
 }
@@ -1349,7 +1397,9 @@ static hipError_t round_impl(const GraphDev &g, const RunDev &R, hipStream_t st,
         const hipError_t e = hipEventRecord(e1, st);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(k_post<W>, dim3(lg), dim3(BLOCK), 0, st, g, R);
+    // the closing launch is light (the push's gained nodes, the hubs): one
+    // block per compute unit keeps its same-address atomics few
+    hipLaunchKernelGGL(k_post<W>, dim3(lg < 256 ? lg : 256), dim3(BLOCK), 0, st, g, R);
     return hipGetLastError();
 }
 
