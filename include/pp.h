@@ -91,6 +91,11 @@ typedef struct {
     int32_t time_kernels;       /* 1: HIP events around every pull launch (pp_get_kernel_times) */
     int32_t persistent;         /* 1: all rounds in one cooperative launch (grid barriers
                                    between phases) instead of launches per round */
+    int32_t pull_k;             /* arcs per lane of the pull, 2 or 4 (0: 4); sets the pull
+                                   tile (64 K arcs) and so the high-degree threshold
+                                   (longer lists are split into tile-sized chunks).
+                                   The persistent engine uses 4. */
+    int32_t pad;                /* zero */
 } pp_options;
 
 /* Metrics estimated from c[0..D] (paper Section 3 and Algorithm 1's closing
@@ -294,6 +299,34 @@ int pp_mlp_loss_grad(const float *params, const float *x, const float *t, int64_
  * rate lr, moments starting at zero) on that loss; params is updated in
  * place; loss_log (host [steps] or NULL) receives the loss before each step. */
 int pp_mlp_train(float *params, const float *x, const float *t, int64_t n, int32_t steps, float lr, float *loss_log);
+
+/* One configuration tried by pp_autotune and its best time. */
+typedef struct {
+    int32_t pull_k, push_div, rounds_per_sync, persistent;
+    float ms;                   /* least wall time of a reset plus a propagation to convergence */
+} pp_tune_entry;
+
+/*
+ * pp_autotune -- picks run options for a graph by measurement.  Candidates:
+ * the pull tile (2 or 4 arcs per lane, which also sets the length above
+ * which a list is split into tile-sized chunks) times the push threshold
+ * (push_div 4, 8, 16, 32) on the per-round engine, and the persistent
+ * engine.  Each is run once to warm up (graph capture), then `reps` times
+ * (>= 1) from pp_seeds_reset to convergence; the least wall time counts.
+ *   seeds, s    a representative seed list (host, as for pp_seeds_init).
+ *   base        options to start from (NULL: defaults); the scheduler,
+ *               per-seed counts, round cap and replay settings are kept
+ *               (the learned scheduler runs without weights, i.e. as the
+ *               heuristic, during tuning).
+ *   best        receives the fastest candidate's options.
+ *   table, cap  host array for every candidate tried (may be NULL if cap is
+ *               0); *ntried (may be NULL) receives how many were tried.
+ * A candidate whose run cannot be created (the persistent engine with more
+ * graphs than co-resident blocks) is skipped.  Outputs never depend on the
+ * options, only the time does.  Allocates and frees a run per candidate.
+ */
+int pp_autotune(pp_graph g, const int32_t *seeds, int32_t s, const pp_options *base, int32_t reps,
+                pp_options *best, pp_tune_entry *table, int32_t cap, int32_t *ntried);
 
 void pp_run_free(pp_run r);
 void pp_graph_free(pp_graph g);

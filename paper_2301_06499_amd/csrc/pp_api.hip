@@ -12,6 +12,7 @@
 #include <map>
 #include <new>
 #include <string>
+#include <chrono>
 #include <thread>
 #include <vector>
 
@@ -327,7 +328,9 @@ void build_tiles(const std::vector<int64_t> &rp, const std::vector<int64_t> &nof
     ghub[(size_t)G] = (int32_t)hub_node.size();
 }
 
-int pull_edges_for_words(int W) {
+// arc budget of a pull tile: K arcs per lane (0: the width's default)
+int pull_edges(int W, int K) {
+    if (K > 0) return K * 64;
     switch (W) {
         case 1: return pp::PullShape<1>::EDGES;
         case 2: return pp::PullShape<2>::EDGES;
@@ -336,8 +339,8 @@ int pull_edges_for_words(int W) {
     }
 }
 
-int ensure_tiles(pp_graph g, int W, TileSet **out) {
-    const int edges = pull_edges_for_words(W);
+int ensure_tiles(pp_graph g, int W, int K, TileSet **out) {
+    const int edges = pull_edges(W, K);
     auto it = g->tiles.find(edges);
     if (it != g->tiles.end()) {
         *out = &it->second;
@@ -642,7 +645,7 @@ hipError_t clear_run_dev(pp_graph g, RunDev &d, hipStream_t st) {
     return pp::launch_fills(segs, (int)(sizeof(segs) / sizeof(segs[0])), st);
 }
 
-TileSet *run_tiles(pp_run r) { return &r->g->tiles[pull_edges_for_words(r->W)]; }
+TileSet *run_tiles(pp_run r) { return &r->g->tiles[pull_edges(r->W, r->dev.pull_k)]; }
 
 // Host copy of the control state.  The clustered engine keeps one control
 // block per graph: the summary has the largest round, converged when every
@@ -851,6 +854,9 @@ extern "C" int pp_seeds_init(pp_graph g, const int32_t *seeds, int32_t s, const 
     pp_options_default(&o);
     if (opt) o = *opt;
     if (o.push_div <= 0) o.push_div = 8;
+    if (o.pull_k == 0) o.pull_k = 4;
+    if (o.pull_k != 2 && o.pull_k != 4) return fail(PP_EINVAL, "pull_k = %d: 2 or 4 arcs per lane", o.pull_k);
+    if (o.persistent && o.pull_k != 4) return fail(PP_EINVAL, "the persistent engine pulls with 4 arcs per lane");
     if (o.scheduler < PP_SCHED_HEURISTIC || o.scheduler > PP_SCHED_MLP) return fail(PP_EINVAL, "unknown scheduler %d", o.scheduler);
     if (o.max_rounds < 0 || o.rounds_per_sync < 0) return fail(PP_EINVAL, "negative max_rounds / rounds_per_sync");
     const int G = g->G;
@@ -870,6 +876,7 @@ extern "C" int pp_seeds_init(pp_graph g, const int32_t *seeds, int32_t s, const 
     r->cap = (int32_t)cap;
     r->G = G;
     r->opt = o;
+    r->dev.pull_k = o.pull_k;
     r->timing = o.time_kernels != 0;
     if (o.persistent) {
         r->pgrid = pp::persistent_grid(words_for(s));
@@ -898,7 +905,7 @@ extern "C" int pp_seeds_init(pp_graph g, const int32_t *seeds, int32_t s, const 
         r->own_stream = true;
     }
     TileSet *ts = nullptr;
-    rc = ensure_tiles(g, W, &ts);
+    rc = ensure_tiles(g, W, r->dev.pull_k, &ts);
     if (rc == PP_OK)
         rc = alloc_run_dev(g, r->dev, s, W, (int)cap, o.seed_counts != 0, std::max(pp::pull_grid_for(ts->ntiles), r->pgrid));
     if (rc == PP_OK) rc = dev_alloc(&r->dseeds, (int64_t)G * s);
@@ -1244,6 +1251,7 @@ extern "C" int pp_run_snapshot(pp_run r, pp_run *copy) {
     }
     c->dev.sched = r->dev.sched;
     c->dev.push_div = r->dev.push_div;
+    c->dev.pull_k = r->dev.pull_k;
     c->dev.fuzz_seed = r->dev.fuzz_seed;
     rc = pp_run_restore(c, r);
     if (rc) {
@@ -1348,4 +1356,62 @@ extern "C" int pp_time_round(pp_run r, int32_t mode, float *features, float *ms)
     HIP_TRY(hipEventSynchronize(r->tev[1]));
     HIP_TRY(hipEventElapsedTime(ms, r->tev[0], r->tev[1]));
     return sync_ctrl(r);
+}
+
+extern "C" int pp_autotune(pp_graph g, const int32_t *seeds, int32_t s, const pp_options *base, int32_t reps,
+                           pp_options *best, pp_tune_entry *table, int32_t cap, int32_t *ntried) {
+    if (!g || !seeds || !best) return fail(PP_EINVAL, "graph, seeds or best is NULL");
+    if (reps < 1) return fail(PP_EINVAL, "reps < 1");
+    if (cap < 0 || (cap > 0 && !table)) return fail(PP_EINVAL, "table is NULL with cap > 0");
+    int rc = check_host_seeds(g, seeds, s);
+    if (rc) return rc;
+    pp_options o0;
+    pp_options_default(&o0);
+    if (base) o0 = *base;
+    o0.time_kernels = 0;
+    // candidates: tile shape (arcs per lane, hence the high-degree threshold)
+    // x push threshold on the per-round engine, then the persistent engine
+    std::vector<pp_options> cands;
+    for (int k : {4, 2})
+        for (int d : {8, 4, 16, 32}) {
+            pp_options o = o0;
+            o.persistent = 0;
+            o.pull_k = k;
+            o.push_div = d;
+            cands.push_back(o);
+        }
+    {
+        pp_options o = o0;
+        o.persistent = 1;
+        o.pull_k = 4;
+        o.push_div = 8;
+        cands.push_back(o);
+    }
+    float best_ms = INFINITY;
+    int tried = 0;
+    for (const pp_options &o : cands) {
+        pp_run r = nullptr;
+        if (pp_seeds_init(g, seeds, s, &o, nullptr, &r) != PP_OK) continue;   // e.g. too many graphs to co-schedule
+        float ms = INFINITY;
+        int err = pp_propagate_until_converged(r, 0, nullptr, 0, nullptr);   // warm-up (graph capture)
+        for (int k = 0; k < reps && err == PP_OK; ++k) {
+            const auto t0 = std::chrono::steady_clock::now();
+            err = pp_seeds_reset(r, seeds, 0);
+            if (err == PP_OK) err = pp_propagate_until_converged(r, 0, nullptr, 0, nullptr);
+            const auto t1 = std::chrono::steady_clock::now();
+            ms = std::min(ms, (float)std::chrono::duration<double, std::milli>(t1 - t0).count());
+        }
+        pp_run_free(r);
+        if (err != PP_OK) return err;
+        if (tried < cap)
+            table[tried] = pp_tune_entry{o.pull_k, o.push_div, o.rounds_per_sync, o.persistent, ms};
+        ++tried;
+        if (ms < best_ms) {
+            best_ms = ms;
+            *best = o;
+        }
+    }
+    if (ntried) *ntried = tried;
+    if (tried == 0) return fail(PP_EDEVICE, "no candidate configuration could run");
+    return PP_OK;
 }

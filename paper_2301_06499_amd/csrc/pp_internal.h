@@ -52,13 +52,13 @@ constexpr int PULL_GRID_MAX = PP_PULL_GRID_MAX;
 #define PP_STREAM_NT 0
 #endif
 
-// A pull tile is the work of one wave, per signature width W (words): the
-// tile's arc budget (K per lane) and node budget (one row word per lane and
-// pass).  In the gather, L lanes share each source row, each loading P
+// A pull tile is the work of one wave, per signature width W (words) and
+// arcs per lane K (KK, or the default when KK = 0): the tile's arc budget
+// (K per lane) and node budget (one row word per lane and pass).  In the gather, L lanes share each source row, each loading P
 // words (16 bytes when W >= 2), and every group of L lanes takes KG = K L
 // consecutive arcs.
-template <int W> struct PullShape {
-    static constexpr int K = W >= 8 ? PP_PULL_K8 : PP_PULL_K;
+template <int W, int KK = 0> struct PullShape {
+    static constexpr int K = KK > 0 ? KK : (W >= 8 ? PP_PULL_K8 : PP_PULL_K);
     static constexpr int EDGES = K * 64;
     static constexpr int NODES = 64;
     static constexpr int L = W >= 2 ? W / 2 : 1;
@@ -177,6 +177,8 @@ struct RunDev {
     // scheduler
     int32_t sched;
     int32_t push_div;
+    int32_t pull_k;       // arcs per lane of the pull (the tile set was built for it)
+    int32_t pad2;
     uint64_t fuzz_seed;
     float *mlp;           // [MLP_PARAMS] cost-model weights (NaN: not set, heuristic decides)
 };

@@ -524,10 +524,10 @@ PP_DEV void stage_tile(const GraphDev &g, const Tile &T, int ln, int32_t (&cv)[K
     }
 }
 
-template <int W>
+template <int W, int KK = 0>
 PP_DEV void phase_pull(const GraphDev &g, const RunDev &R, int bid, int nb) {
     Ctrl *C = R.ctrl;
-    using PS = PullShape<W>;
+    using PS = PullShape<W, KK>;
     constexpr int K = PS::K;
     constexpr int EDGES = PS::EDGES;
     constexpr int NODES = PS::NODES;
@@ -1104,9 +1104,11 @@ template <int W> __global__ void __launch_bounds__(BLOCK) k_push_commit(GraphDev
     if (R.ctrl->converged || (!init && R.ctrl->mode != MODE_PUSH)) return;
     phase_push_commit<W>(g, R, init, blockIdx.x, gridDim.x);
 }
-template <int W> __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(W >= 8 ? 2 : PP_PULL_WAVES))) k_pull(GraphDev g, RunDev R) {
+template <int W, int KK>
+__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(W >= 8 ? 2 : PP_PULL_WAVES)))
+k_pull(GraphDev g, RunDev R) {
     if (R.ctrl->converged || R.ctrl->mode != MODE_PULL) return;
-    phase_pull<W>(g, R, blockIdx.x, gridDim.x);
+    phase_pull<W, KK>(g, R, blockIdx.x, gridDim.x);
 }
 template <int W> __global__ void __launch_bounds__(BLOCK) k_pull_hubs(GraphDev g, RunDev R) {
     if (R.ctrl->converged || R.ctrl->mode != MODE_PULL) return;
@@ -1392,7 +1394,8 @@ static hipError_t round_impl(const GraphDev &g, const RunDev &R, hipStream_t st,
         const hipError_t e = hipEventRecord(e0, st);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(k_pull<W>, dim3(g.pull_grid), dim3(BLOCK), 0, st, g, R);
+    if (R.pull_k == 2) hipLaunchKernelGGL((k_pull<W, 2>), dim3(g.pull_grid), dim3(BLOCK), 0, st, g, R);
+    else hipLaunchKernelGGL((k_pull<W, 0>), dim3(g.pull_grid), dim3(BLOCK), 0, st, g, R);
     if (e1) {
         const hipError_t e = hipEventRecord(e1, st);
         if (e != hipSuccess) return e;

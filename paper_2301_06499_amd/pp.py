@@ -34,7 +34,13 @@ class PPError(RuntimeError):
 class Options(ctypes.Structure):
     _fields_ = [("scheduler", ctypes.c_int32), ("seed_counts", ctypes.c_int32), ("max_rounds", ctypes.c_int32),
                 ("rounds_per_sync", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("push_div", ctypes.c_int32),
-                ("fuzz_seed", ctypes.c_uint64), ("time_kernels", ctypes.c_int32), ("persistent", ctypes.c_int32)]
+                ("fuzz_seed", ctypes.c_uint64), ("time_kernels", ctypes.c_int32), ("persistent", ctypes.c_int32),
+                ("pull_k", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
+class TuneEntry(ctypes.Structure):
+    _fields_ = [("pull_k", ctypes.c_int32), ("push_div", ctypes.c_int32), ("rounds_per_sync", ctypes.c_int32),
+                ("persistent", ctypes.c_int32), ("ms", ctypes.c_float)]
 
 
 class Metrics(ctypes.Structure):
@@ -52,7 +58,7 @@ EXPORTS = ["pp_options_default", "pp_csr_build", "pp_graph_arcs", "pp_graph_node
            "pp_get_signatures", "pp_get_seed_counts", "pp_run_round", "pp_run_words", "pp_get_round_log",
            "pp_run_snapshot", "pp_run_restore", "pp_run_free", "pp_graph_free", "pp_last_error",
            "pp_seeds_reset", "pp_get_kernel_times", "pp_run_set_mlp", "pp_get_round_features",
-           "pp_time_round", "pp_mlp_forward", "pp_mlp_loss_grad", "pp_mlp_train"]
+           "pp_time_round", "pp_mlp_forward", "pp_mlp_loss_grad", "pp_mlp_train", "pp_autotune"]
 
 MLP_IN, MLP_HID, MLP_OUT = 8, 32, 2
 MLP_PARAMS = MLP_HID * MLP_IN + MLP_HID + MLP_HID * MLP_HID + MLP_HID + MLP_OUT * MLP_HID + MLP_OUT   # 1410
@@ -92,6 +98,7 @@ def lib():
         "pp_mlp_forward": (ctypes.c_int, [P, P, I64, P]),
         "pp_mlp_loss_grad": (ctypes.c_int, [P, P, P, I64, P, P]),
         "pp_mlp_train": (ctypes.c_int, [P, P, P, I64, I32, ctypes.c_float, P]),
+        "pp_autotune": (ctypes.c_int, [P, P, I32, P, I32, P, P, I32, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -123,7 +130,7 @@ def _is_device(a) -> bool:
 
 
 def options(scheduler=PP_SCHED_HEURISTIC, seed_counts=False, max_rounds=0, rounds_per_sync=0,
-            use_graph=True, push_div=0, fuzz_seed=0, time_kernels=False, persistent=False) -> Options:
+            use_graph=True, push_div=0, fuzz_seed=0, time_kernels=False, persistent=False, pull_k=0) -> Options:
     o = Options()
     lib().pp_options_default(ctypes.byref(o))
     o.scheduler = scheduler
@@ -136,6 +143,7 @@ def options(scheduler=PP_SCHED_HEURISTIC, seed_counts=False, max_rounds=0, round
     o.fuzz_seed = int(fuzz_seed)
     o.time_kernels = int(bool(time_kernels))
     o.persistent = int(bool(persistent))
+    o.pull_k = int(pull_k)
     return o
 
 
@@ -394,6 +402,21 @@ def pp_mlp_train(params, x, t, steps: int, lr: float):
     log = np.zeros(max(int(steps), 1), dtype=np.float32)
     _check(lib().pp_mlp_train(_np_ptr(p), _np_ptr(x), _np_ptr(t), n, int(steps), float(lr), _np_ptr(log)))
     return p, log[:int(steps)]
+
+
+def pp_autotune(graph: Graph, seeds, s=None, base: Options | None = None, reps: int = 3):
+    """Options picked by measurement; returns (best Options, list of dicts for every candidate tried)."""
+    seeds = np.ascontiguousarray(seeds, dtype=np.int32).reshape(-1)
+    if s is None:
+        s = int(seeds.size // graph.count)
+    best = Options()
+    cap = 32
+    table = (TuneEntry * cap)()
+    n = ctypes.c_int32(0)
+    _check(lib().pp_autotune(graph.handle, _np_ptr(seeds), int(s), ctypes.byref(base) if base is not None else None,
+                             int(reps), ctypes.byref(best), table, cap, ctypes.byref(n)))
+    rows = [{k: getattr(table[i], k) for k, _ in TuneEntry._fields_} for i in range(min(n.value, cap))]
+    return best, rows
 
 
 def propagate(n, src, dst, seeds, undirected=False, transpose=False, opts=None, stream=None):

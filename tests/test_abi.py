@@ -29,7 +29,7 @@ def test_every_declared_symbol_is_exported():
 
 
 def test_struct_layouts_match_header():
-    assert ctypes.sizeof(pp.Options) == 40
+    assert ctypes.sizeof(pp.Options) == 48
     assert ctypes.sizeof(pp.Metrics) == 4 + 4 + 8 + 6 * 8
 
 

@@ -34,7 +34,8 @@ def pad_words(sig, W):
 
 
 def check_run(n, src, dst, seeds, undirected, transpose=False, sched=pp.PP_SCHED_HEURISTIC,
-              fuzz_seed=0, use_graph=True, want=None, max_rounds=0, persistent=False, keep_order=False):
+              fuzz_seed=0, use_graph=True, want=None, max_rounds=0, persistent=False, keep_order=False,
+              pull_k=0):
     s = len(seeds)
     if want is None:
         want = oracle.propagate(n, src, dst, seeds, undirected, transpose=transpose,
@@ -42,7 +43,7 @@ def check_run(n, src, dst, seeds, undirected, transpose=False, sched=pp.PP_SCHED
     g = pp.pp_csr_build(n, src, dst, undirected=undirected, transpose=transpose, keep_order=keep_order)
     cap = max_rounds or want["D"] + 4
     opts = pp.options(scheduler=sched, seed_counts=True, max_rounds=cap, fuzz_seed=fuzz_seed,
-                      use_graph=use_graph, persistent=persistent)
+                      use_graph=use_graph, persistent=persistent, pull_k=pull_k)
     r = pp.pp_seeds_init(g, seeds, opts=opts)
     counts, D = pp.pp_propagate_until_converged(r)
     assert int(D[0]) == want["D"]
@@ -96,8 +97,10 @@ def test_random_graphs_word_boundaries(trial):
     tr = bool(trial % 4 == 1)
     seeds = rng.integers(0, n, s).astype(np.int32)          # repeats allowed
     sched = SCHEDS[trial % 4]
-    say("random", trial, "n", n, "m", m, "s", s, "und", und, "tr", tr, "sched", sched)
-    check_run(n, src, dst, seeds, und, transpose=tr, sched=sched, fuzz_seed=trial, persistent=trial % 2 == 1)
+    pers = trial % 2 == 1
+    k = 2 if (not pers and trial % 4 == 2) else 0
+    say("random", trial, "n", n, "m", m, "s", s, "und", und, "tr", tr, "sched", sched, "pull_k", k)
+    check_run(n, src, dst, seeds, und, transpose=tr, sched=sched, fuzz_seed=trial, persistent=pers, pull_k=k)
 
 
 @pytest.mark.parametrize("sched", SCHEDS)
@@ -110,7 +113,7 @@ def test_rmat_with_hubs(sched, persistent, keep_order):
     seeds = gen.sample_seeds(g.n, 256, 8)
     say("rmat14", sched, "persistent", persistent, "keep_order", keep_order)
     check_run(g.n, g.src, g.dst, seeds, False, sched=sched, fuzz_seed=5, persistent=persistent,
-              keep_order=keep_order)
+              keep_order=keep_order, pull_k=2 if (keep_order and not persistent) else 0)
 
 
 @pytest.mark.parametrize("keep_order", [False, True])
@@ -282,3 +285,31 @@ def test_rmat20_full_size_sampled_seeds():
         bits = (sig[:, i >> 6] >> np.uint64(i & 63)) & np.uint64(1)
         assert np.array_equal(bits.astype(bool), want["dist"][j] >= 0), i
     say("rmat20 D", Dg, "counts", list(counts[0]))
+
+
+def test_autotune_candidates_keep_results():
+    """Every autotuner candidate runs the same propagation; the tuned options reproduce it."""
+    g = gen.rmat(13, 16, 21)
+    seeds = gen.sample_seeds(g.n, 128, 4)
+    say("autotune rmat13")
+    want = oracle.propagate(g.n, g.src, g.dst, seeds, False, final_sig=True)
+    G = pp.pp_csr_build(g.n, g.src, g.dst)
+    best, table = pp.pp_autotune(G, seeds, reps=2)
+    assert len(table) == 9
+    assert {(t["pull_k"], t["push_div"]) for t in table if not t["persistent"]} == \
+        {(k, d) for k in (2, 4) for d in (4, 8, 16, 32)}
+    assert all(np.isfinite(t["ms"]) and t["ms"] > 0 for t in table)
+    best_ms = min(t["ms"] for t in table)
+    assert any(t["ms"] == best_ms and t["pull_k"] == best.pull_k and t["push_div"] == best.push_div
+               and t["persistent"] == best.persistent for t in table)
+    for k in (2, 4):
+        for pers in ((False, True) if k == 4 else (False,)):
+            opts = pp.options(pull_k=k, persistent=pers, push_div=best.push_div, max_rounds=want["D"] + 4)
+            r = pp.pp_seeds_init(G, seeds, opts=opts)
+            c, D = pp.pp_propagate_until_converged(r)
+            assert int(D[0]) == want["D"] and list(c[0]) == list(want["counts"])
+            assert np.array_equal(pp.pp_get_signatures(r), pad_words(want["final_sig"], r.words))
+    with pytest.raises(pp.PPError):
+        pp.pp_seeds_init(G, seeds, opts=pp.options(pull_k=3))
+    with pytest.raises(pp.PPError):
+        pp.pp_seeds_init(G, seeds, opts=pp.options(pull_k=2, persistent=True))
