@@ -257,6 +257,8 @@ def main():
     ap.add_argument("--grid-side", type=int, default=4096, help="side of the grid4096 workload")
     ap.add_argument("--persistent", action="store_true",
                     help="all rounds in one cooperative launch instead of launches per round")
+    ap.add_argument("--tune", action="store_true",
+                    help="run options from the autotuner (measured before the timed steps, cached per workload)")
     ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -290,13 +292,22 @@ def main():
     log(f"[bench] csr_build {time.perf_counter() - t0:.1f} s: n={G.nodes} arcs={G.arcs}")
     dseeds = torch.from_numpy(seeds.astype(np.int32)).to("cuda")
     torch.cuda.synchronize()
+    base = pp.options(scheduler=sched, max_rounds=4096, persistent=args.persistent)
+    tuned = None
+    if args.tune:
+        from paper_2301_06499_amd import autotune
+        t0 = time.perf_counter()
+        base, tuned = autotune.tune(G, seeds, base=base, reps=3, name=cfg["workload"],
+                                    cache_path=os.path.join(ROOT, "gpurun_out", "pp_tune.json"))
+        tuned = {k: v for k, v in tuned.items() if k != "candidates"} | {"tune_s": round(time.perf_counter() - t0, 2)}
+        log(f"[bench] tuned options {tuned}")
     # two runs of the same workload: the throughput is timed without kernel
     # events (each event in a replayed round costs a few microseconds), the
     # pull kernel's launches are timed with HIP events on the run's stream
-    run = pp.pp_seeds_init(G, seeds, opts=pp.options(scheduler=sched, max_rounds=4096,
-                                                     persistent=args.persistent), stream=stream)
-    run_t = pp.pp_seeds_init(G, seeds, opts=pp.options(scheduler=sched, max_rounds=4096, time_kernels=True,
-                                                       persistent=args.persistent), stream=stream)
+    run = pp.pp_seeds_init(G, seeds, opts=base, stream=stream)
+    opts_t = pp.Options.from_buffer_copy(base)
+    opts_t.time_kernels = 1
+    run_t = pp.pp_seeds_init(G, seeds, opts=opts_t, stream=stream)
     W = run.words
     if args.copy_calibration:
         nb = args.copy_calibration << 20
@@ -356,9 +367,10 @@ def main():
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": (measured_traffic("k_pull_rmat20_s256")
-                        if args.workload == "rmat20" and not args.persistent and W == 4 else None),
-            "kernel": f"k_rounds<{W}> pull phase" if args.persistent else f"k_pull<{W}>",
-            "timing": ("device clock between grid barriers" if args.persistent else
+                        if (args.workload == "rmat20" and not base.persistent and W == 4
+                            and (base.pull_k or 4) == 4) else None),
+            "kernel": f"k_batch<{W}> pull phase" if base.persistent else f"k_pull<{W}>",
+            "timing": ("device clock between grid barriers" if base.persistent else
                        "HIP events around each launch, on the run's stream, over a second timed region of "
                        "the same steps"),
             "ms_per_step_with_events": round(elapsed_t * 1000.0 / args.steps, 4),
@@ -375,7 +387,8 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "u64", "data": "synthetic",
         "config": dict(cfg, nodes=n, arcs=m, words=W, rounds=rounds, diameter_lb=Dv,
-                       scheduler=args.scheduler, engine="persistent" if args.persistent else "rounds",
+                       scheduler=args.scheduler, engine="persistent" if base.persistent else "rounds",
+                       pull_k=int(base.pull_k) or 4, push_div=int(base.push_div) or 8, tuned=tuned,
                        modes="".join("P" if modes[r] == pp.MODE_PULL else "S" for r in range(1, rounds + 1))),
         "touched_edge_words_per_s": touched * args.steps / elapsed,
         "roofline": roof,
