@@ -23,6 +23,9 @@ consumer, which adds the reverse arc.
 """
 from __future__ import annotations
 
+import ctypes
+import os
+import subprocess
 from dataclasses import dataclass, field
 from fractions import Fraction
 
@@ -163,17 +166,66 @@ def rmat_thresholds(a=Fraction(57, 100), b=Fraction(19, 100), c=Fraction(19, 100
     return int(t1), int(t2), int(t3)
 
 
+_GEN_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "gen")
+_GEN_SRC = os.path.join(_GEN_DIR, "rmat_gen.c")
+_GEN_LIB = os.path.join(_GEN_DIR, "librmat_gen.so")
+_gen_lib = None
+
+
+def build_native(force: bool = True) -> str:
+    """Compile the native R-MAT generator (plain C, pthreads) with gcc."""
+    if force or not os.path.exists(_GEN_LIB):
+        tmp = _GEN_LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-shared", "-fPIC", "-pthread", _GEN_SRC, "-o", tmp])
+        os.replace(tmp, _GEN_LIB)
+    return _GEN_LIB
+
+
+def _native():
+    global _gen_lib
+    if _gen_lib is None:
+        if not os.path.exists(_GEN_LIB):
+            build_native(force=False)
+        lib = ctypes.CDLL(_GEN_LIB)
+        U64, P = ctypes.c_uint64, ctypes.c_void_p
+        lib.rmat_edges.restype = ctypes.c_int
+        lib.rmat_edges.argtypes = [ctypes.c_int, ctypes.c_int64, U64, U64, U64, U64, P, P, ctypes.c_int]
+        _gen_lib = lib
+    return _gen_lib
+
+
+def _host_threads() -> int:
+    try:
+        return max(1, min(64, len(os.sched_getaffinity(0))))
+    except AttributeError:  # pragma: no cover
+        return os.cpu_count() or 1
+
+
 def rmat(scale: int, edge_factor: int, seed: int, chunk: int = 1 << 22,
-         a=Fraction(57, 100), b=Fraction(19, 100), c=Fraction(19, 100)) -> Graph:
+         a=Fraction(57, 100), b=Fraction(19, 100), c=Fraction(19, 100), native: bool | None = None) -> Graph:
     """Directed R-MAT edge list (Chakrabarti, Zhan, Faloutsos 2004), no noise.
 
     Edge k, level l (0 = most significant bit) uses the 32-bit half
     (high half for even l) of draw k*ceil(scale/2) + l//2, compared against
     integer thresholds; quadrant a=(0,0), b=(0,1), c=(1,0), d=(1,1) sets the
     (src, dst) bits at position scale-1-l.  Duplicates and self-loops are kept
-    here; the consumer removes them.
+    here; the consumer removes them.  ``native`` (default: from scale 15 on)
+    uses the C generator of the same definition on every host core.
     """
     m = edge_factor << scale
+    if native is None:
+        native = scale >= 15
+    if native:
+        t = rmat_thresholds(a, b, c)
+        src = np.empty(m, dtype=np.int32)
+        dst = np.empty(m, dtype=np.int32)
+        rc = _native().rmat_edges(scale, m, seed & 0xFFFFFFFFFFFFFFFF, t[0], t[1], t[2],
+                                  src.ctypes.data_as(ctypes.c_void_p), dst.ctypes.data_as(ctypes.c_void_p),
+                                  _host_threads())
+        if rc != 0:
+            raise RuntimeError(f"rmat_edges failed with {rc}")
+        return Graph(1 << scale, src, dst, False, f"rmat{scale}_ef{edge_factor}_s{seed}",
+                     {"scale": scale, "edge_factor": edge_factor})
     t1, t2, t3 = (np.uint64(t) for t in rmat_thresholds(a, b, c))
     per_edge = (scale + 1) // 2
     src = np.empty(m, dtype=np.int32)

@@ -70,3 +70,11 @@ def test_seed_sampling():
 def test_workload_er_shape():
     g, seeds = gen.workload_er(1)
     assert 9000 < g.n <= 10000 and seeds.size == 64 and np.unique(seeds).size == 64
+
+
+def test_native_rmat_matches_numpy():
+    """The C generator and the numpy one give the same edge list."""
+    for scale, ef, seed in [(10, 8, 3), (13, 16, 1), (14, 4, 99)]:
+        a = gen.rmat(scale, ef, seed, native=False, chunk=1 << 12)
+        b = gen.rmat(scale, ef, seed, native=True)
+        assert np.array_equal(a.src, b.src) and np.array_equal(a.dst, b.dst)
