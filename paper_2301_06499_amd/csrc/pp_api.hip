@@ -173,50 +173,98 @@ namespace {
 
 // rows[u] = sorted, distinct heads v of arcs u -> v in the propagation
 // direction (u ORs in v's signature), self-loops removed.
-void build_rows(int64_t n, int64_t m, const int32_t *a, const int32_t *b, bool undirected,
-                std::vector<int64_t> &rp, std::vector<int32_t> &col) {
-    std::vector<int64_t> cnt((size_t)n + 1, 0);
-    for (int64_t k = 0; k < m; ++k) {
-        if (a[k] == b[k]) continue;
-        cnt[(size_t)a[k] + 1]++;
-        if (undirected) cnt[(size_t)b[k] + 1]++;
+// Runs f(t) for t in [0, T) on T host threads.
+template <typename F> void on_threads(int T, F f) {
+    if (T <= 1) {
+        f(0);
+        return;
     }
-    for (int64_t u = 0; u < n; ++u) cnt[(size_t)u + 1] += cnt[(size_t)u];
-    std::vector<int32_t> tmp((size_t)cnt[(size_t)n]);
-    std::vector<int64_t> fill(cnt.begin(), cnt.end() - 1);
-    for (int64_t k = 0; k < m; ++k) {
-        if (a[k] == b[k]) continue;
-        tmp[(size_t)fill[(size_t)a[k]]++] = b[k];
-        if (undirected) tmp[(size_t)fill[(size_t)b[k]]++] = a[k];
-    }
-    std::vector<int64_t> uniq((size_t)n, 0);
-    parallel_for(n, [&](int64_t lo, int64_t hi) {
-        for (int64_t u = lo; u < hi; ++u) {
-            int32_t *p = tmp.data() + cnt[(size_t)u];
-            int32_t *q = tmp.data() + cnt[(size_t)u + 1];
-            std::sort(p, q);
-            uniq[(size_t)u] = std::unique(p, q) - p;
+    std::vector<std::thread> th;
+    for (int t = 0; t < T; ++t) th.emplace_back([=] { f(t); });
+    for (auto &x : th) x.join();
+}
+
+// Runs f(i) for i in [0, count) on every host thread, each taking the next
+// index from a shared counter (uneven items balance themselves).
+template <typename F> void on_items(int64_t count, F f) {
+    std::atomic<int64_t> next{0};
+    on_threads((int)hw_threads(), [&](int) {
+        for (int64_t i; (i = next.fetch_add(1)) < count;) f(i);
+    });
+}
+
+// CSR of the arcs that gen(lo, hi, emit) emits for input items [lo, hi)
+// (emit(row, column) per arc), rows sorted, repeated arcs merged.  Parallel
+// without atomics on the data: each thread counts its slice's arcs per
+// bucket of consecutive rows, the arcs are scattered bucket by bucket as
+// 64-bit keys (row, column), and the buckets (many more than threads, taken
+// from a shared counter, since degree-skewed graphs fill some far more than
+// others) are sorted and deduplicated one per thread at a time.
+template <typename Gen>
+void build_csr(int64_t n, int64_t items, Gen gen, std::vector<int64_t> &rp, std::vector<int32_t> &col) {
+    const int T = (int)hw_threads();
+    const int NB = (int)std::min<int64_t>(4096, std::max<int64_t>(1, n / 64));
+    const int64_t per = (n + NB - 1) / NB;   // rows per bucket
+    std::vector<int64_t> cnt((size_t)T * NB, 0);   // [thread][bucket]
+    on_threads(T, [&](int t) {
+        int64_t *c = cnt.data() + (size_t)t * NB;
+        gen(items * t / T, items * (t + 1) / T, [&](int64_t r, int32_t) { c[r / per]++; });
+    });
+    std::vector<int64_t> off((size_t)T * NB), bstart((size_t)NB + 1);
+    int64_t total = 0;
+    for (int bk = 0; bk < NB; ++bk) {
+        bstart[(size_t)bk] = total;
+        for (int t = 0; t < T; ++t) {
+            off[(size_t)t * NB + bk] = total;
+            total += cnt[(size_t)t * NB + bk];
         }
+    }
+    bstart[(size_t)NB] = total;
+    std::vector<uint64_t> keys((size_t)total);
+    on_threads(T, [&](int t) {
+        int64_t *pos = off.data() + (size_t)t * NB;
+        gen(items * t / T, items * (t + 1) / T,
+            [&](int64_t r, int32_t c) { keys[(size_t)pos[r / per]++] = ((uint64_t)r << 32) | (uint32_t)c; });
+    });
+    std::vector<int64_t> len((size_t)n, 0), uniq((size_t)NB, 0);
+    on_items(NB, [&](int64_t bk) {
+        uint64_t *p = keys.data() + bstart[(size_t)bk], *q = keys.data() + bstart[(size_t)bk + 1];
+        std::sort(p, q);
+        uint64_t *e = std::unique(p, q);
+        uniq[(size_t)bk] = e - p;
+        for (uint64_t *k = p; k < e; ++k) len[(size_t)(*k >> 32)]++;
     });
     rp.assign((size_t)n + 1, 0);
-    for (int64_t u = 0; u < n; ++u) rp[(size_t)u + 1] = rp[(size_t)u] + uniq[(size_t)u];
+    for (int64_t u = 0; u < n; ++u) rp[(size_t)u + 1] = rp[(size_t)u] + len[(size_t)u];
     col.resize((size_t)rp[(size_t)n]);
-    parallel_for(n, [&](int64_t lo, int64_t hi) {
-        for (int64_t u = lo; u < hi; ++u)
-            std::memcpy(col.data() + rp[(size_t)u], tmp.data() + cnt[(size_t)u], sizeof(int32_t) * (size_t)uniq[(size_t)u]);
+    on_items(NB, [&](int64_t bk) {
+        const int64_t first_row = std::min<int64_t>(bk * per, n);
+        const uint64_t *p = keys.data() + bstart[(size_t)bk];
+        int32_t *out = col.data() + rp[(size_t)first_row];
+        for (int64_t k = 0; k < uniq[(size_t)bk]; ++k) out[k] = (int32_t)(p[k] & 0xFFFFFFFFull);
     });
+}
+
+// Successor rows of the input arcs: u -> v for pair (src, dst) (reversed
+// with `transpose`, both directions with `undirected`), self-loops dropped.
+void build_rows(int64_t n, int64_t m, const int32_t *a, const int32_t *b, bool undirected,
+                std::vector<int64_t> &rp, std::vector<int32_t> &col) {
+    build_csr(n, m, [&](int64_t lo, int64_t hi, auto emit) {
+        for (int64_t k = lo; k < hi; ++k) {
+            if (a[k] == b[k]) continue;
+            emit(a[k], b[k]);
+            if (undirected) emit(b[k], a[k]);
+        }
+    }, rp, col);
 }
 
 // Transpose of a CSR: trow[v] = sorted {u : v in row u}.
 void transpose_rows(int64_t n, const std::vector<int64_t> &rp, const std::vector<int32_t> &col,
                     std::vector<int64_t> &trp, std::vector<int32_t> &tcol) {
-    trp.assign((size_t)n + 1, 0);
-    for (size_t k = 0; k < col.size(); ++k) trp[(size_t)col[k] + 1]++;
-    for (int64_t v = 0; v < n; ++v) trp[(size_t)v + 1] += trp[(size_t)v];
-    tcol.resize(col.size());
-    std::vector<int64_t> fill(trp.begin(), trp.end() - 1);
-    for (int64_t u = 0; u < n; ++u)
-        for (int64_t e = rp[(size_t)u]; e < rp[(size_t)u + 1]; ++e) tcol[(size_t)fill[(size_t)col[(size_t)e]]++] = (int32_t)u;
+    build_csr(n, n, [&](int64_t lo, int64_t hi, auto emit) {
+        for (int64_t u = lo; u < hi; ++u)
+            for (int64_t e = rp[(size_t)u]; e < rp[(size_t)u + 1]; ++e) emit(col[(size_t)e], (int32_t)u);
+    }, trp, tcol);
 }
 
 // Storage order of the nodes (hub-first grouping): within each graph of a
@@ -227,10 +275,10 @@ void transpose_rows(int64_t n, const std::vector<int64_t> &rp, const std::vector
 // such nodes (lattices) keep their order.  perm[x] is the stored id of input
 // node x.  Returns false when the order is the identity.
 bool hub_first_order(const std::vector<int64_t> &noff, int G, const std::vector<int64_t> &rp,
-                     const std::vector<int32_t> &col, std::vector<int32_t> &perm) {
+                     const std::vector<int64_t> &trp, std::vector<int32_t> &perm) {
     const int64_t n = (int64_t)rp.size() - 1;
     std::vector<int64_t> indeg((size_t)n, 0);
-    for (size_t k = 0; k < col.size(); ++k) indeg[(size_t)col[k]]++;
+    for (int64_t v = 0; v < n; ++v) indeg[(size_t)v] = trp[(size_t)v + 1] - trp[(size_t)v];
     perm.resize((size_t)n);
     bool moved = false;
     for (int g = 0; g < G; ++g) {
@@ -268,7 +316,9 @@ void relabel_rows(const std::vector<int32_t> &perm, std::vector<int64_t> &rp, st
     std::vector<int64_t> rp2((size_t)n + 1, 0);
     for (int64_t y = 0; y < n; ++y) rp2[(size_t)y + 1] = rp2[(size_t)y] + (rp[(size_t)inv[(size_t)y] + 1] - rp[(size_t)inv[(size_t)y]]);
     std::vector<int32_t> col2(col.size());
-    parallel_for(n, [&](int64_t lo, int64_t hi) {
+    constexpr int64_t CH = 1024;   // rows per work item (hub rows come first and are long)
+    on_items((n + CH - 1) / CH, [&](int64_t c) {
+        const int64_t lo = c * CH, hi = std::min(n, lo + CH);
         for (int64_t y = lo; y < hi; ++y) {
             const int64_t u = inv[(size_t)y];
             int32_t *out = col2.data() + rp2[(size_t)y];
@@ -474,9 +524,13 @@ extern "C" int pp_csr_build(int64_t n, int64_t m, const int32_t *src, const int3
     try {
         if (tr) build_rows(n, m, pd, ps, und, rp, col);
         else build_rows(n, m, ps, pd, und, rp, col);
-        if (!(flags & PP_KEEP_ORDER) && hub_first_order(noff, G, rp, col, perm)) relabel_rows(perm, rp, col);
-        else perm.clear();
         transpose_rows(n, rp, col, trp, tcol);
+        if (!(flags & PP_KEEP_ORDER) && hub_first_order(noff, G, rp, trp, perm)) {
+            relabel_rows(perm, rp, col);
+            relabel_rows(perm, trp, tcol);
+        } else {
+            perm.clear();
+        }
     } catch (const std::bad_alloc &) {
         return fail(PP_ENOMEM, "host memory for the adjacency build");
     }
