@@ -44,6 +44,10 @@ def workload(name: str):
         g, seeds = inputs.workload_rmat(20, 16, 256, 1)
         return g, seeds, {"workload": "rmat_scale20_ef16_s256", "generator": "R-MAT a,b,c,d=.57,.19,.19,.05, "
                           "self-loops and duplicates removed, all 2^20 nodes kept", "seeds": 256}
+    if name == "rmat26":
+        g, seeds = inputs.workload_rmat(26, 16, 512, 1)
+        return g, seeds, {"workload": "rmat_scale26_ef16_s512", "generator": "R-MAT a,b,c,d=.57,.19,.19,.05, "
+                          "self-loops and duplicates removed, all 2^26 nodes kept", "seeds": 512}
     if name == "er":
         g, seeds = inputs.workload_er(1)
         return g, seeds, {"workload": "er_n10000_m50000_lcc_s64", "seeds": 64}
@@ -223,6 +227,23 @@ def bench_grid(args, torch, pp):
     print(json.dumps(out), flush=True)
 
 
+def sampled_check(g, seeds, sig, k: int):
+    """Signature columns of k sampled seeds against the oracle's BFS, bit for bit.
+
+    Bit i of node u is set exactly when u reaches seed i (a finite distance);
+    the sample is every (s/k)-th seed.
+    """
+    import oracle
+    s = len(seeds)
+    idx = np.unique(np.linspace(0, s - 1, k).astype(np.int64))
+    want = oracle.propagate(g.n, g.src, g.dst, seeds[idx], g.undirected, dist=True)
+    for j, i in enumerate(idx):
+        bit = (sig[:, i >> 6] >> np.uint64(i & 63)) & np.uint64(1)
+        if not np.array_equal(bit.astype(bool), want["dist"][j] >= 0):
+            raise AssertionError(f"seed {i}: signature column differs from the oracle")
+    return {"seeds_checked": [int(i) for i in idx], "nodes": int(g.n), "result": "bit-exact"}
+
+
 def cpu_baseline(g, seeds, nominal_edge_words: float, budget_s: float):
     """The oracle (not tuned) on the host cores; a seed sample sized to the budget."""
     import oracle
@@ -257,6 +278,9 @@ def main():
     ap.add_argument("--grid-side", type=int, default=4096, help="side of the grid4096 workload")
     ap.add_argument("--persistent", action="store_true",
                     help="all rounds in one cooperative launch instead of launches per round")
+    ap.add_argument("--check-seeds", type=int, default=-1,
+                    help="after timing, compare the signature columns of this many sampled seeds with the "
+                         "oracle (default: 8 for rmat26, none otherwise)")
     ap.add_argument("--tune", action="store_true",
                     help="run options from the autotuner (measured before the timed steps, cached per workload)")
     ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work for cpu_baseline")
@@ -393,13 +417,23 @@ def main():
         "touched_edge_words_per_s": touched * args.steps / elapsed,
         "roofline": roof,
     }
+    check = args.check_seeds if args.check_seeds >= 0 else (8 if args.workload == "rmat26" else 0)
+    if check:
+        log(f"[bench] checking {check} sampled seeds against the oracle")
+        sig = pp.pp_get_signatures(run)
+        run.free()
+        run_t.free()
+        G.free()
+        out["sampled_check"] = sampled_check(g, seeds, sig, check)
+        del sig
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle")
         out["cpu_baseline"] = cpu_baseline(g, seeds, nominal, args.cpu_budget)
     print(json.dumps(out), flush=True)
-    run.free()
-    run_t.free()
-    G.free()
+    if not check:
+        run.free()
+        run_t.free()
+        G.free()
 
 
 if __name__ == "__main__":
