@@ -48,6 +48,10 @@ def workload(name: str):
         g, seeds = inputs.workload_rmat(26, 16, 512, 1)
         return g, seeds, {"workload": "rmat_scale26_ef16_s512", "generator": "R-MAT a,b,c,d=.57,.19,.19,.05, "
                           "self-loops and duplicates removed, all 2^26 nodes kept", "seeds": 512}
+    if name.startswith("rmat:"):   # rmat:SCALE:SEEDS, edge factor 16
+        scale, s = (int(x) for x in name.split(":")[1:3])
+        g, seeds = inputs.workload_rmat(scale, 16, s, 1)
+        return g, seeds, {"workload": f"rmat_scale{scale}_ef16_s{s}", "seeds": s}
     if name == "er":
         g, seeds = inputs.workload_er(1)
         return g, seeds, {"workload": "er_n10000_m50000_lcc_s64", "seeds": 64}
