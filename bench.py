@@ -103,21 +103,29 @@ def bench_batch(args, torch, pp):
     stream = torch.cuda.Stream()
     GB = pp.pp_csr_build(n, np.concatenate(srcs).astype(np.int32), np.concatenate(dsts).astype(np.int32),
                          node_offsets=offs, stream=stream)
-    run = pp.pp_seeds_init(GB, allseeds, s=64, opts=pp.options(max_rounds=25000, persistent=True), stream=stream)
     dseeds = torch.from_numpy(allseeds).to("cuda")
+    engines = {}
+    for name, persistent in (("clustered", True), ("union", False)):
+        run = pp.pp_seeds_init(GB, allseeds, s=64, opts=pp.options(max_rounds=25000, persistent=persistent),
+                               stream=stream)
 
-    def step():
-        pp.pp_seeds_reset(run, dseeds)
-        return pp.pp_propagate_until_converged(run)
+        def step():
+            pp.pp_seeds_reset(run, dseeds)
+            return pp.pp_propagate_until_converged(run)
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        counts, D = step()
-    torch.cuda.synchronize()
-    t_batch = (time.perf_counter() - t0) / args.steps
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            counts, D = step()
+        torch.cuda.synchronize()
+        engines[name] = ((time.perf_counter() - t0) / args.steps, counts, D)
+        run.free()
+        log(f"[bench] batch, {name} engine: {engines[name][0] * 1e3:.2f} ms per step")
+    assert all(np.array_equal(engines["union"][1], engines["clustered"][1]) for _ in [0])
+    best = min(engines, key=lambda k: engines[k][0])
+    t_batch, counts, D = engines[best]
     # stored arcs per graph, from solo builds (also used by the plain runs)
     solo_graphs, solo_runs, arcs_g = [], [], []
     for g, sd in zip(graphs, seeds):
@@ -151,7 +159,10 @@ def bench_batch(args, torch, pp):
         "config": {"workload": "batch64: 22 R-MAT (scale 10-16, edge factor 8-16), 21 grids (64^2..512^2), "
                                "21 paths (1000..20000 edges), 64 seeds each",
                    "graphs": len(graphs), "nodes": n, "arcs": int(GB.arcs), "words": 1,
-                   "max_rounds": int(D.max()) + 1, "engine": "clustered persistent launch"},
+                   "max_rounds": int(D.max()) + 1,
+                   "engine": {"clustered": "one persistent launch, each graph on its own block range",
+                              "union": "per-round launches over the disjoint union, graph replay"}[best]},
+        "engines_ms_per_step": {k: round(v[0] * 1000.0, 3) for k, v in engines.items()},
         "plain": {"ms_per_step": round(t_plain * 1000.0, 3), "value": nominal / t_plain,
                   "engine": "64 solo runs, per-round launches, fixed-threshold heuristic"},
         "speedup_vs_plain": round(t_plain / t_batch, 2),

@@ -845,7 +845,8 @@ int reset_run(pp_run r, const int32_t *dseeds) {
 }
 
 // Splits the persistent grid among the graphs of a batch, in proportion to
-// their arcs plus nodes, at least one block each; graph order is kept.
+// their arcs plus nodes, at least one block each and at most one per 64 Ki
+// arcs plus nodes (blocks beyond every cap stay idle); graph order is kept.
 std::vector<pp::Cluster> make_clusters(pp_graph g, const TileSet *ts, int grid) {
     const int G = g->G;
     std::vector<double> w((size_t)G);
@@ -855,14 +856,28 @@ std::vector<pp::Cluster> make_clusters(pp_graph g, const TileSet *ts, int grid) 
         w[(size_t)k] = (double)(g->rp_host[(size_t)n1] - g->rp_host[(size_t)n0]) + (double)(n1 - n0) + 1.0;
         tot += w[(size_t)k];
     }
-    std::vector<int> nb((size_t)G, 1);
+    // a graph gets at most one block per CLUSTER_ITEMS arcs plus nodes: small
+    // graphs run many cheap rounds, where a barrier among a few blocks costs
+    // more than the work it spreads (one block synchronises with its own
+    // barrier only)
+    constexpr double CLUSTER_ITEMS = 65536.0;
+    std::vector<int> nb((size_t)G, 1), cap((size_t)G);
     int used = G;
     for (int k = 0; k < G; ++k) {
-        const int extra = (int)((double)(grid - G) * w[(size_t)k] / tot);
+        cap[(size_t)k] = (int)std::max(1.0, std::ceil(w[(size_t)k] / CLUSTER_ITEMS));
+        const int extra = std::min((int)((double)(grid - G) * w[(size_t)k] / tot), cap[(size_t)k] - 1);
         nb[(size_t)k] += extra;
         used += extra;
     }
-    for (int k = 0; used < grid; k = (k + 1) % G, ++used) nb[(size_t)k] += 1;   // leftovers, round robin
+    for (bool grew = true; used < grid && grew;) {   // leftovers, round robin, up to each cap
+        grew = false;
+        for (int k = 0; k < G && used < grid; ++k)
+            if (nb[(size_t)k] < cap[(size_t)k]) {
+                ++nb[(size_t)k];
+                ++used;
+                grew = true;
+            }
+    }
     std::vector<pp::Cluster> cl((size_t)G);
     int b0 = 0;
     int64_t ch0 = 0;
