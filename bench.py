@@ -209,6 +209,11 @@ def bench_grid(args, torch, pp):
         S.timed_run(G, seeds, sch, params_, repeats=max(1, args.warmup))
         runs[name] = S.timed_run(G, seeds, sch, params_, repeats=reps)
         log(f"[bench] {name}: {runs[name][0]:.3f} ms")
+    # the fixed threshold at its best for this graph (autotuned push threshold and tile)
+    tuned, tuned_table = pp.pp_autotune(G, seeds, reps=2)
+    runs["heuristic_tuned"] = S.timed_run(G, seeds, pp.PP_SCHED_HEURISTIC, None, repeats=reps,
+                                          push_div=int(tuned.push_div), pull_k=int(tuned.pull_k))
+    log(f"[bench] heuristic with the tuned threshold {tuned.push_div}: {runs['heuristic_tuned'][0]:.3f} ms")
     (t_h, c_h, D_h, m_h), (t_l, c_l, D_l, m_l) = runs["heuristic"], runs["learned"]
     assert int(D_h[0]) == int(D_l[0]) and list(c_h[0]) == list(c_l[0]), "schedules changed the counts"
     rounds = int(D_l[0]) + 1
@@ -232,6 +237,9 @@ def bench_grid(args, torch, pp):
                     "training_samples": len(samples), "train_s": round(t_train, 3),
                     "final_loss": float(losses[-1])},
         "speedup_vs_heuristic": round(t_h / t_l, 4),
+        "heuristic_tuned": {"ms_per_step": round(runs["heuristic_tuned"][0], 4), "push_div": int(tuned.push_div),
+                            "pull_k": int(tuned.pull_k),
+                            "pulls": int((runs["heuristic_tuned"][3][1:rounds + 1] == pp.MODE_PULL).sum())},
         "held_out_table_ms": {"optimal": round(best_ms, 3),
                               "heuristic": round(S.policy_cost(held, S.heuristic_policy())[0], 3),
                               "learned": round(S.policy_cost(held, S.model_policy(params, held))[0], 3),

@@ -194,14 +194,14 @@ def policy_cost(t: CostTable, choose) -> tuple[float, np.ndarray]:
 
 
 def timed_run(graph: pp.Graph, seeds, scheduler: int, params=None, repeats: int = 3, push_div: int = 0,
-              stream=None):
+              stream=None, pull_k: int = 0):
     """Best wall time (ms) of a whole propagation with graph replay, the counts, D and the mode log.
 
     The library's calls return after the device work they ask for (the
     convergence check reads the control block back), so host clocks bracket
     the device time.
     """
-    opts = pp.options(scheduler=scheduler, push_div=push_div)
+    opts = pp.options(scheduler=scheduler, push_div=push_div, pull_k=pull_k)
     run = pp.pp_seeds_init(graph, seeds, opts=opts, stream=stream)
     try:
         if params is not None:
