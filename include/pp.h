@@ -300,6 +300,20 @@ int pp_mlp_loss_grad(const float *params, const float *x, const float *t, int64_
  * place; loss_log (host [steps] or NULL) receives the loss before each step. */
 int pp_mlp_train(float *params, const float *x, const float *t, int64_t n, int32_t steps, float lr, float *loss_log);
 
+/*
+ * pp_exact_counts -- the exact neighbourhood function: PROPAGATE-P with
+ * every node as a seed (s = n, the paper's ground-truth use of the method),
+ * run as ceil(n / group) seed groups of up to `group` (1..512) nodes each,
+ * in node order, their per-round counts summed: counts[r] = the number of
+ * ordered pairs (u, v) with d(u, v) = r (counts[0] = n), for r < cap_rounds
+ * (host array, zeroed first); *D (may be NULL) = the largest distance, the
+ * exact diameter of the reachable pairs.  One graph only.  opt (NULL:
+ * defaults) sets the engine and scheduler of the runs; per-seed counts are
+ * off.  PP_ERANGE if D >= cap_rounds (counts then hold the rounds that fit).
+ */
+int pp_exact_counts(pp_graph g, int32_t group, const pp_options *opt, int64_t *counts, int32_t cap_rounds,
+                    int32_t *D);
+
 /* One configuration tried by pp_autotune and its best time. */
 typedef struct {
     int32_t pull_k, push_div, rounds_per_sync, persistent;

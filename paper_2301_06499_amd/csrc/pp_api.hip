@@ -1484,3 +1484,47 @@ extern "C" int pp_autotune(pp_graph g, const int32_t *seeds, int32_t s, const pp
     if (tried == 0) return fail(PP_EDEVICE, "no candidate configuration could run");
     return PP_OK;
 }
+
+extern "C" int pp_exact_counts(pp_graph g, int32_t group, const pp_options *opt, int64_t *counts, int32_t cap_rounds,
+                               int32_t *D) {
+    if (!g || !counts) return fail(PP_EINVAL, "graph or counts is NULL");
+    if (g->G != 1) return fail(PP_EINVAL, "one graph only (got a batch of %d)", g->G);
+    if (group < 1 || group > 512) return fail(PP_EINVAL, "group = %d outside [1, 512]", group);
+    if (cap_rounds < 1) return fail(PP_EINVAL, "cap_rounds < 1");
+    const int64_t n = g->n;
+    pp_options o;
+    pp_options_default(&o);
+    if (opt) o = *opt;
+    o.seed_counts = 0;
+    std::memset(counts, 0, sizeof(int64_t) * (size_t)cap_rounds);
+    int32_t dmax = 0;
+    std::vector<int32_t> seeds((size_t)group);
+    std::vector<int64_t> c((size_t)cap_rounds);
+    pp_run run = nullptr;     // runs of `group` seeds, reset per group
+    int32_t run_s = 0;
+    int rc = PP_OK;
+    for (int64_t first = 0; first < n && rc == PP_OK; first += group) {
+        const int32_t s = (int32_t)std::min<int64_t>(group, n - first);
+        for (int32_t i = 0; i < s; ++i) seeds[(size_t)i] = (int32_t)(first + i);
+        if (run && run_s != s) {
+            pp_run_free(run);
+            run = nullptr;
+        }
+        if (!run) {
+            rc = pp_seeds_init(g, seeds.data(), s, &o, nullptr, &run);
+            run_s = s;
+        } else {
+            rc = pp_seeds_reset(run, seeds.data(), 0);
+        }
+        int32_t d = 0;
+        if (rc == PP_OK) rc = pp_propagate_until_converged(run, 0, c.data(), cap_rounds, &d);
+        if (rc == PP_OK) {
+            for (int32_t k = 0; k < cap_rounds; ++k) counts[k] += c[(size_t)k];
+            dmax = std::max(dmax, d);
+        }
+    }
+    if (run) pp_run_free(run);
+    if (rc) return rc;
+    if (D) *D = dmax;
+    return dmax >= cap_rounds ? fail(PP_ERANGE, "D = %d does not fit cap_rounds = %d", dmax, cap_rounds) : PP_OK;
+}

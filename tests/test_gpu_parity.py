@@ -313,3 +313,20 @@ def test_autotune_candidates_keep_results():
         pp.pp_seeds_init(G, seeds, opts=pp.options(pull_k=3))
     with pytest.raises(pp.PPError):
         pp.pp_seeds_init(G, seeds, opts=pp.options(pull_k=2, persistent=True))
+
+
+@pytest.mark.parametrize("case", range(4))
+def test_exact_neighbourhood_function(case):
+    """Every node a seed, in groups: the counts equal all-pairs distances (brute force)."""
+    g = [gen.erdos_renyi_gnm(300, 700, 2), gen.grid_with_shortcuts(20, 15, gen.Fraction(1, 10), 5, 1),
+         gen.rmat(9, 8, 4), gen.path_graph(130)][case]
+    group = [64, 100, 512, 7][case]
+    say("exact", g.name, "group", group)
+    want, dist = oracle.brute_force_counts(g.n, g.src, g.dst, np.arange(g.n), g.undirected)
+    G = pp.pp_csr_build(g.n, g.src, g.dst, undirected=g.undirected)
+    counts, D = pp.pp_exact_counts(G, group=group)
+    assert D == len(want) - 1 and list(counts) == list(want)
+    m = pp.pp_estimate_metrics(counts, g.n, g.n)
+    assert m["reachable_pairs"] == float(int((dist >= 0).sum()))
+    with pytest.raises(pp.PPError):
+        pp.pp_exact_counts(G, group=513)
