@@ -610,6 +610,7 @@ void free_run_dev(RunDev &d) {
     dev_free(d.phase_log);
     dev_free(d.feat_log);
     dev_free(d.tickets);
+    dev_free(d.post_part);
     dev_free(d.mlp);
 }
 
@@ -664,7 +665,7 @@ int alloc_run_dev(pp_graph g, RunDev &d, int s, int W, int cap, bool seed_counts
         (rc = dev_alloc(&d.ctrl, G)) || (rc = dev_alloc(&d.bar, G)) ||
         (rc = dev_alloc(&d.phase_log, (int64_t)cap * 3 * G)) ||
         (rc = dev_alloc(&d.feat_log, (int64_t)cap * pp::MLP_IN * G)) || (rc = dev_alloc(&d.mlp, pp::MLP_PARAMS)) ||
-        (rc = dev_alloc(&d.tickets, pp::TICKET_INTS)))
+        (rc = dev_alloc(&d.tickets, pp::TICKET_INTS)) || (rc = dev_alloc(&d.post_part, 3 * pp::POST_MAX)))
         return rc;
     d.sig[1] = d.sig[0] + n * W;
     d.f_ids[1] = d.f_ids[0] + n;

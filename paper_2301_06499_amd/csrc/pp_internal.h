@@ -95,6 +95,7 @@ struct Ctrl {
 constexpr int TICKET_GROUP = 32;
 constexpr int TICKET_STRIDE = 32;   // int32 per cache line
 constexpr int TICKET_INTS = (TICKET_GROUP + 1) * TICKET_STRIDE;
+constexpr int POST_MAX = 256;       // blocks of the closing launch at most
 
 // Learned cost model: an MLP 8 -> 32 -> 32 -> 2 (ReLU) predicting the log of a
 // round's duration under pull (output 0) and push (output 1).  Parameter
@@ -172,6 +173,7 @@ struct RunDev {
     int64_t *phase_log;   // [G][cap][3] device-clock stamps of the persistent loop
     float *feat_log;      // [G][cap][8] scheduler features of each round (row 0 unused)
     int32_t *tickets;     // [TICKET_INTS] the closing launch's ticket counters (zero between launches)
+    int64_t *post_part;   // [3][POST_MAX] the closing launch's per-block partials
     GridBar *bar;         // [G] barrier state per cluster
     Ctrl *ctrl;           // [G]: ctrl[0] for the per-round engine, one per graph when clustered
     // scheduler

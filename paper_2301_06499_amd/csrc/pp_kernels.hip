@@ -39,6 +39,8 @@ namespace pp {
 // Reads of the control block: atomic loads, so they are never served from
 // the scalar cache, which a persistent launch would leave stale.
 #define CTL(x) __hip_atomic_load(&(x), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+// Device-scope store of a value another block of the same launch reads.
+#define PUT(x, v) __hip_atomic_store(&(x), (v), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
 
 PP_DEV int lane_id() { return __lane_id(); }
 
@@ -425,7 +427,10 @@ __global__ void __launch_bounds__(BLOCK) k_seed_scatter(GraphDev g, RunDev R, co
 // for the next round.  Round 0 (init) also writes them into both signature
 // buffers; a push round has set them in Sig already.
 template <int W>
-PP_DEV void phase_push_commit(const GraphDev &g, const RunDev &R, int init, int bid, int nb) {
+// parts (the closing launch): the block's new-bit count and predecessor arcs
+// go to its slots of the per-block partials instead of the round's
+// counters, which the round's end then sums.
+PP_DEV void phase_push_commit(const GraphDev &g, const RunDev &R, int init, int bid, int nb, int64_t *parts = nullptr) {
     Ctrl *C = R.ctrl;
     const int r = init ? 0 : CTL(C->round);
     const int p = r & 1;
@@ -495,8 +500,14 @@ PP_DEV void phase_push_commit(const GraphDev &g, const RunDev &R, int init, int 
     const unsigned long long tp = block_sum<unsigned long long>(pop, s_red);
     const unsigned long long ta = block_sum<unsigned long long>((unsigned long long)arcs, s_red);
     if (threadIdx.x == 0) {
-        if (R.G == 1 && tp) atomicAdd((unsigned long long *)&R.counts[(int64_t)r * R.cstride], tp);
-        if (ta) atomicAdd((unsigned long long *)&C->f_arcs[p], ta);
+        if (parts) {
+            PUT(parts[0 * POST_MAX + bid], (int64_t)tp);
+            PUT(parts[1 * POST_MAX + bid], (int64_t)0);
+            PUT(parts[2 * POST_MAX + bid], (int64_t)ta);
+        } else {
+            if (R.G == 1 && tp) atomicAdd((unsigned long long *)&R.counts[(int64_t)r * R.cstride], tp);
+            if (ta) atomicAdd((unsigned long long *)&C->f_arcs[p], ta);
+        }
     }
     if (per_seed && R.G == 1) seed_flush<W>(R, r, sc);
 }
@@ -691,9 +702,16 @@ PP_DEV void phase_pull(const GraphDev &g, const RunDev &R, int bid, int nb) {
 // High-degree nodes of a pull round: the chunks left their ORed rows in the
 // accumulator.
 template <int W>
-PP_DEV void phase_pull_hubs(const GraphDev &g, const RunDev &R, int bid, int nb) {
+PP_DEV void phase_pull_hubs(const GraphDev &g, const RunDev &R, int bid, int nb, int64_t *parts = nullptr) {
     Ctrl *C = R.ctrl;
-    if (g.nhubs == 0) return;
+    if (g.nhubs == 0) {
+        if (parts && threadIdx.x == 0) {
+            PUT(parts[0 * POST_MAX + bid], (int64_t)0);
+            PUT(parts[1 * POST_MAX + bid], (int64_t)0);
+            PUT(parts[2 * POST_MAX + bid], (int64_t)0);
+        }
+        return;
+    }
     const int r = CTL(C->round);
     const int cur = CTL(C->cur);
     const uint64_t *sig = sel(R.sig, cur);
@@ -748,9 +766,15 @@ PP_DEV void phase_pull_hubs(const GraphDev &g, const RunDev &R, int bid, int nb)
     const unsigned long long tn = block_sum<unsigned long long>((unsigned long long)nodes, s_red);
     const unsigned long long ta = block_sum<unsigned long long>((unsigned long long)parcs, s_red);
     if (threadIdx.x == 0) {
-        if (tp) atomicAdd((unsigned long long *)&C->hub_cnt, tp);
-        if (tn) atomicAdd((unsigned long long *)&C->hub_nodes, tn);
-        if (ta) atomicAdd((unsigned long long *)&C->hub_arcs, ta);
+        if (parts) {
+            PUT(parts[0 * POST_MAX + bid], (int64_t)tp);
+            PUT(parts[1 * POST_MAX + bid], (int64_t)tn);
+            PUT(parts[2 * POST_MAX + bid], (int64_t)ta);
+        } else {
+            if (tp) atomicAdd((unsigned long long *)&C->hub_cnt, tp);
+            if (tn) atomicAdd((unsigned long long *)&C->hub_nodes, tn);
+            if (ta) atomicAdd((unsigned long long *)&C->hub_arcs, ta);
+        }
     }
     if (per_seed && R.G == 1) seed_flush<W>(R, r, sc);
 }
@@ -1010,38 +1034,69 @@ PP_DEV int32_t mlp_decide(const float *w, const float (&f)[MLP_IN], int32_t fall
     return o0 <= o1 ? MODE_PULL : MODE_PUSH;
 }
 
-// nparts: blocks of the pull that left per-block partials.
-PP_DEV void phase_round_end(const GraphDev &g, const RunDev &R, int init, int nparts) {
+// nparts: blocks of the pull that left per-block partials.  parts/npost:
+// the closing launch's per-block partials (new bits, hub nodes, arcs), or
+// NULL when its blocks added into the control block instead.
+PP_DEV void phase_round_end(const GraphDev &g, const RunDev &R, int init, int nparts, const int64_t *parts = nullptr,
+                            int npost = 0) {
     Ctrl *C = R.ctrl;
     const int r = init ? 0 : CTL(C->round);
     const int mode = init ? MODE_INIT : CTL(C->mode);
-    __shared__ long long s_red[BLOCK / 64];
+    __shared__ long long s_red4[4][BLOCK / 64];
     __shared__ int s_active;
     __shared__ int s_next;
-    long long fnodes = 0, farcs = 0, pulled = 0;
+    // every control-block value the end needs, loaded up front
+    const long long hub_cnt = CTL(C->hub_cnt), hub_nodes = CTL(C->hub_nodes), hub_arcs = CTL(C->hub_arcs);
+    const long long lst_count = CTL(C->f_count[r & 1]), lst_arcs = CTL(C->f_arcs[r & 1]);
+    const long long prev_arcs = CTL(C->f_arcs[(r - 1) & 1]);
+    const int64_t reached0 = CTL(C->reached), last = CTL(C->last_count);
+    // one reduction for the four sums: pull partials (pull rounds) and the
+    // closing launch's partials
+    long long v[4] = {0, 0, 0, 0};
     if (mode == MODE_PULL) {
-        long long c = 0, nn = 0, na = 0, np = 0;
         for (int b = threadIdx.x; b < nparts; b += BLOCK) {
-            c += R.blk_cnt[b];
-            nn += R.blk_nodes[b];
-            na += R.blk_arcs[b];
-            np += R.blk_pulled[b];
+            v[0] += R.blk_cnt[b];
+            v[1] += R.blk_nodes[b];
+            v[2] += R.blk_arcs[b];
+            v[3] += R.blk_pulled[b];
         }
-        c = block_sum<long long>(c, s_red);
-        fnodes = block_sum<long long>(nn, s_red) + CTL(C->hub_nodes);
-        farcs = block_sum<long long>(na, s_red) + CTL(C->hub_arcs);
-        pulled = block_sum<long long>(np, s_red);
-        if (R.G == 1 && threadIdx.x == 0) R.counts[(int64_t)r * R.cstride] = c + CTL(C->hub_cnt);
-    } else {
-        fnodes = CTL(C->f_count[r & 1]);
-        farcs = CTL(C->f_arcs[r & 1]);
+    }
+    for (int b = threadIdx.x; b < npost; b += BLOCK) {
+        v[0] += CTL(parts[0 * POST_MAX + b]);
+        v[1] += CTL(parts[1 * POST_MAX + b]);
+        v[2] += CTL(parts[2 * POST_MAX + b]);
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[k] = wave_sum(v[k]);
+    if (lane_id() == 0) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) s_red4[k][threadIdx.x >> 6] = v[k];
     }
     if (threadIdx.x == 0) s_active = 0;
     __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        v[k] = 0;
+#pragma unroll
+        for (int w = 0; w < BLOCK / 64; ++w) v[k] += s_red4[k][w];
+    }
+    long long fnodes = 0, farcs = 0, pulled = 0;
+    long long own = -1;   // this round's count of a single graph when known here
+    if (mode == MODE_PULL) {
+        fnodes = v[1] + hub_nodes;
+        farcs = v[2] + hub_arcs;
+        pulled = v[3];
+        if (R.G == 1) own = v[0] + hub_cnt;
+    } else {
+        fnodes = lst_count;
+        farcs = lst_arcs + v[2];
+        if (R.G == 1 && parts) own = v[0];
+    }
+    if (own >= 0 && threadIdx.x == 0) R.counts[(int64_t)r * R.cstride] = own;
     int act = 0;
     long long cnt = 0;
     for (int gi = threadIdx.x; gi < R.G; gi += BLOCK) {
-        const long long c = CTL(R.counts[(int64_t)r * R.cstride + gi]);
+        const long long c = own >= 0 ? own : CTL(R.counts[(int64_t)r * R.cstride + gi]);
         cnt += c;
         if (R.gconv[gi]) continue;
         if (c == 0) {
@@ -1052,9 +1107,9 @@ PP_DEV void phase_round_end(const GraphDev &g, const RunDev &R, int init, int np
         }
     }
     if (act) atomicAdd(&s_active, act);
-    cnt = block_sum<long long>(cnt, s_red);
-    const int64_t reached = CTL(C->reached) + (init ? 0 : cnt);
-    const int64_t last = CTL(C->last_count);
+    if (own >= 0) cnt = own;
+    else cnt = block_sum<long long>(cnt, s_red4[0]);
+    const int64_t reached = reached0 + (init ? 0 : cnt);
     float f[MLP_IN];
     sched_features(g, R, r + 1, mode, fnodes, farcs, cnt, reached, last, f);
     const int32_t fallback = schedule(g, R, r + 1, fnodes, farcs);
@@ -1065,7 +1120,8 @@ PP_DEV void phase_round_end(const GraphDev &g, const RunDev &R, int init, int np
     __syncthreads();
     if (threadIdx.x == 0) {
         R.mode_log[r] = mode;
-        R.arcs_log[r] = mode == MODE_PULL ? pulled : (mode == MODE_PUSH ? CTL(C->f_arcs[(r - 1) & 1]) : 0);
+        R.arcs_log[r] = mode == MODE_PULL ? pulled : (mode == MODE_PUSH ? prev_arcs : 0);
+        if (mode != MODE_PULL && parts) C->f_arcs[r & 1] = farcs;   // the list's arcs, summed here
         if (mode == MODE_PULL) C->cur ^= 1;
         C->prev_mode = mode;
         C->hub_cnt = 0;
@@ -1155,8 +1211,8 @@ PP_DEV bool last_block(int32_t *tickets, int bid, int nb) {
 template <int W> __global__ void __launch_bounds__(BLOCK) k_post(GraphDev g, RunDev R) {
     Ctrl *C = R.ctrl;
     if (CTL(C->converged)) return;   // set only by the last block, after every block has finished
-    if (CTL(C->mode) == MODE_PUSH) phase_push_commit<W>(g, R, 0, blockIdx.x, gridDim.x);
-    else phase_pull_hubs<W>(g, R, blockIdx.x, gridDim.x);
+    if (CTL(C->mode) == MODE_PUSH) phase_push_commit<W>(g, R, 0, blockIdx.x, gridDim.x, R.post_part);
+    else phase_pull_hubs<W>(g, R, blockIdx.x, gridDim.x, R.post_part);
     __shared__ int s_last;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __syncthreads();
@@ -1164,7 +1220,7 @@ template <int W> __global__ void __launch_bounds__(BLOCK) k_post(GraphDev g, Run
     __syncthreads();
     if (!s_last) return;
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-    phase_round_end(g, R, 0, g.pull_grid);
+    phase_round_end(g, R, 0, g.pull_grid, R.post_part, (int)gridDim.x);
 }
 
 // New cost-model weights for a run in progress: the direction of the round
@@ -1402,7 +1458,7 @@ static hipError_t round_impl(const GraphDev &g, const RunDev &R, hipStream_t st,
     }
     // the closing launch is light (the push's gained nodes, the hubs): one
     // block per compute unit keeps its same-address atomics few
-    hipLaunchKernelGGL(k_post<W>, dim3(lg < 256 ? lg : 256), dim3(BLOCK), 0, st, g, R);
+    hipLaunchKernelGGL(k_post<W>, dim3(lg < POST_MAX ? lg : POST_MAX), dim3(BLOCK), 0, st, g, R);
     return hipGetLastError();
 }
 
