@@ -205,7 +205,8 @@ def bench_grid(args, torch, pp):
     t_prep = time.perf_counter() - t_prep
     reps = max(1, args.steps)
     runs = {}
-    for name, sch, params_ in (("heuristic", pp.PP_SCHED_HEURISTIC, None), ("learned", pp.PP_SCHED_MLP, params)):
+    for name, sch, params_ in (("heuristic", pp.PP_SCHED_HEURISTIC, None), ("learned", pp.PP_SCHED_MLP, params),
+                               ("pull_only", pp.PP_SCHED_PULL, None), ("push_only", pp.PP_SCHED_PUSH, None)):
         S.timed_run(G, seeds, sch, params_, repeats=max(1, args.warmup))
         runs[name] = S.timed_run(G, seeds, sch, params_, repeats=reps)
         log(f"[bench] {name}: {runs[name][0]:.3f} ms")
@@ -215,7 +216,8 @@ def bench_grid(args, torch, pp):
                                           push_div=int(tuned.push_div), pull_k=int(tuned.pull_k))
     log(f"[bench] heuristic with the tuned threshold {tuned.push_div}: {runs['heuristic_tuned'][0]:.3f} ms")
     (t_h, c_h, D_h, m_h), (t_l, c_l, D_l, m_l) = runs["heuristic"], runs["learned"]
-    assert int(D_h[0]) == int(D_l[0]) and list(c_h[0]) == list(c_l[0]), "schedules changed the counts"
+    for name, (_, c_x, D_x, _) in runs.items():
+        assert int(D_x[0]) == int(D_l[0]) and list(c_x[0]) == list(c_l[0]), f"{name} changed the counts"
     rounds = int(D_l[0]) + 1
     W = 2
     nominal = float(G.arcs) * W * rounds
@@ -237,6 +239,8 @@ def bench_grid(args, torch, pp):
                     "training_samples": len(samples), "train_s": round(t_train, 3),
                     "final_loss": float(losses[-1])},
         "speedup_vs_heuristic": round(t_h / t_l, 4),
+        "pull_only_ms": round(runs["pull_only"][0], 4),
+        "push_only_ms": round(runs["push_only"][0], 4),
         "heuristic_tuned": {"ms_per_step": round(runs["heuristic_tuned"][0], 4), "push_div": int(tuned.push_div),
                             "pull_k": int(tuned.pull_k),
                             "pulls": int((runs["heuristic_tuned"][3][1:rounds + 1] == pp.MODE_PULL).sum())},
@@ -285,10 +289,35 @@ def cpu_baseline(g, seeds, nominal_edge_words: float, budget_s: float):
         t1 = time.perf_counter() - t0
         k = k2
     t_full = t1 * s / k
+    # one thread on a small sample, for the per-core figure
+    k1 = min(s, 8)
+    t0 = time.perf_counter()
+    oracle.propagate(g.n, g.src, g.dst, seeds[:k1], g.undirected, nthreads=1)
+    t_one = (time.perf_counter() - t0) * s / k1
     return {"value": nominal_edge_words / t_full, "unit": "edge-words/s", "cores": min(nth, k),
             "kind": "oracle",
             "sample": f"per-seed BFS over {k} of {s} seeds in {t1:.2f} s, scaled by {s}/{k} "
-                      f"to the full seed set ({t_full:.2f} s)"}
+                      f"to the full seed set ({t_full:.2f} s)",
+            "single_thread_value": nominal_edge_words / t_one,
+            "single_thread_sample": f"{k1} seeds on one thread, scaled by {s}/{k1}",
+            "host": host_info()}
+
+
+def host_info() -> dict:
+    """CPU model, usable cores and memory of the host the oracle ran on."""
+    info = {"nproc": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()}
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                info["cpu"] = line.split(":", 1)[1].strip()
+                break
+        for line in open("/proc/meminfo"):
+            if line.startswith("MemTotal"):
+                info["mem_gib"] = round(int(line.split()[1]) / 2**20, 1)
+                break
+    except OSError:
+        pass
+    return info
 
 
 def main():
@@ -304,6 +333,9 @@ def main():
     ap.add_argument("--check-seeds", type=int, default=-1,
                     help="after timing, compare the signature columns of this many sampled seeds with the "
                          "oracle (default: 8 for rmat26, none otherwise)")
+    ap.add_argument("--seed-groups", type=int, default=0,
+                    help="also time the same seeds as this many groups run one after another (the "
+                         "counts of the groups add up to the single run's; default: 2 for rmat26)")
     ap.add_argument("--tune", action="store_true",
                     help="run options from the autotuner (measured before the timed steps, cached per workload)")
     ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work for cpu_baseline")
@@ -371,13 +403,17 @@ def main():
         pp.pp_seeds_reset(r, dseeds)
         return pp.pp_propagate_until_converged(r)
 
-    # throughput: the timed steps
+    # throughput: the timed steps (each step ends with the counts on the
+    # host, so a host clock around it brackets the device work)
     for _ in range(args.warmup):
         step(run)
     torch.cuda.synchronize()
+    per_step = []
     t0 = time.perf_counter()
     for _ in range(args.steps):
+        ts = time.perf_counter()
         counts, D = step(run)
+        per_step.append(time.perf_counter() - ts)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     # the pull kernel: the same steps with HIP events around every pull launch
@@ -405,10 +441,10 @@ def main():
 
     # roofline of the dense pull kernel: algorithmic bytes per launch
     #   per arc gathered: 4 B column index + 8W B source row
-    #   per node: 8 B row offset + 8W B own row
+    #   per node: 8 B row offset (int64) + 8W B own row read + 8W B new row written
     pull_rounds = [r for r in range(1, rounds + 1) if modes[r] == pp.MODE_PULL]
     pull_ms = (ms_after - ms_before) / args.steps
-    bytes_pull = sum(float(arcs[r]) * (4 + 8 * W) + n * (8 + 8 * W) for r in pull_rounds)
+    bytes_pull = sum(float(arcs[r]) * (4 + 8 * W) + n * (8 + 16 * W) for r in pull_rounds)
     t_pull = sum(pull_ms[r] for r in pull_rounds) / 1000.0
     achieved = bytes_pull / t_pull / 1e9 if t_pull > 0 else 0.0
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -431,6 +467,8 @@ def main():
         "unit": "edge-words/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(ms_step, 4),
+        "ms_per_step_min": round(min(per_step) * 1000.0, 4),
+        "ms_per_step_median": round(float(np.median(per_step)) * 1000.0, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "u64", "data": "synthetic",
         "config": dict(cfg, nodes=n, arcs=m, words=W, rounds=rounds, diameter_lb=Dv,
@@ -440,6 +478,38 @@ def main():
         "touched_edge_words_per_s": touched * args.steps / elapsed,
         "roofline": roof,
     }
+    groups = args.seed_groups or (2 if args.workload == "rmat26" else 0)
+    if groups > 1 and s % groups == 0:
+        # seed groups: s/groups seeds per run, the runs one after another, counts summed
+        gs = s // groups
+        parts = [seeds[k * gs:(k + 1) * gs] for k in range(groups)]
+        runs_g = [pp.pp_seeds_init(G, part, opts=pp.options(scheduler=sched, max_rounds=4096), stream=stream)
+                  for part in parts]
+        dparts = [torch.from_numpy(part.astype(np.int32)).to("cuda") for part in parts]
+        for _ in range(args.warmup):
+            for rg, dp in zip(runs_g, dparts):
+                pp.pp_seeds_reset(rg, dp)
+                pp.pp_propagate_until_converged(rg)
+        torch.cuda.synchronize()
+        tg = time.perf_counter()
+        for _ in range(args.steps):
+            total = None
+            for rg, dp in zip(runs_g, dparts):
+                pp.pp_seeds_reset(rg, dp)
+                cg, _ = pp.pp_propagate_until_converged(rg)
+                c0 = cg[0]
+                if total is None:
+                    total = c0.copy()
+                else:
+                    L = max(len(total), len(c0))
+                    total = np.pad(total, (0, L - len(total))) + np.pad(c0, (0, L - len(c0)))
+        torch.cuda.synchronize()
+        tg = (time.perf_counter() - tg) / args.steps
+        assert list(np.trim_zeros(total, "b")) == list(np.trim_zeros(counts[0], "b")), "seed groups changed the counts"
+        out["seed_groups"] = {"groups": groups, "seeds_per_group": gs, "words": int(runs_g[0].words),
+                              "ms_per_step": round(tg * 1000.0, 4), "value": nominal / tg}
+        for rg in runs_g:
+            rg.free()
     check = args.check_seeds if args.check_seeds >= 0 else (8 if args.workload == "rmat26" else 0)
     if check:
         log(f"[bench] checking {check} sampled seeds against the oracle")
