@@ -449,8 +449,8 @@ def main():
     achieved = bytes_pull / t_pull / 1e9 if t_pull > 0 else 0.0
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": (measured_traffic("k_pull_rmat20_s256")
-                        if (args.workload == "rmat20" and not base.persistent and W == 4
+            "traffic": (measured_traffic({"rmat20": "k_pull_rmat20_s256", "rmat26": "k_pull_rmat26_s512"}[args.workload])
+                        if (args.workload in ("rmat20", "rmat26") and not base.persistent
                             and (base.pull_k or 4) == 4) else None),
             "kernel": f"k_batch<{W}> pull phase" if base.persistent else f"k_pull<{W}>",
             "timing": ("device clock between grid barriers" if base.persistent else
