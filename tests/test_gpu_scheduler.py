@@ -230,3 +230,24 @@ def test_trained_scheduler_keeps_results():
     ms, counts, D, modes = scheduler.timed_run(graph, seeds, pp.PP_SCHED_MLP, params, repeats=1)
     assert int(D[0]) == want["D"] and list(counts[0]) == list(want["counts"])
     assert math.isfinite(ms)
+
+
+def test_learned_schedule_gains_on_held_out_costs():
+    """The trained model's schedule against the fixed heuristic's, both priced
+    on the measured round costs of a held-out graph (deterministic given the
+    measurement): the model must not lose and must come close to the optimum."""
+    tables = []
+    for k in (2, 3, 1):
+        g = gen.grid_with_shortcuts(768, 768, gen.Fraction(1, 10), 60, 70 + k)
+        graph = pp.pp_csr_build(g.n, g.src, g.dst, undirected=True)
+        tables.append(scheduler.measure(graph, gen.sample_seeds(g.n, 128, k)))
+        graph.free()
+    train, held = tables[:2], tables[2]
+    params, losses = scheduler.train(scheduler.Samples.concat(scheduler.label(t) for t in train), steps=3000)
+    _, best, _ = scheduler.optimal_schedule(held)
+    heur, _ = scheduler.policy_cost(held, scheduler.heuristic_policy())
+    learned, plan = scheduler.policy_cost(held, scheduler.model_policy(params, held))
+    say("held-out costs ms: optimal %.3f heuristic %.3f learned %.3f" % (best, heur, learned))
+    assert best <= learned + 1e-9 and best <= heur + 1e-9
+    assert learned <= heur * 1.005
+    assert learned <= best * 1.03
