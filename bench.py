@@ -52,6 +52,10 @@ def workload(name: str):
         scale, s = (int(x) for x in name.split(":")[1:3])
         g, seeds = inputs.workload_rmat(scale, 16, s, 1)
         return g, seeds, {"workload": f"rmat_scale{scale}_ef16_s{s}", "seeds": s}
+    if name.startswith("grid:"):   # grid:SIDE, the lattice workload without the cost-model training
+        side = int(name.split(":")[1])
+        g, seeds = inputs.workload_grid_shortcuts(side, 128, 1)
+        return g, seeds, {"workload": f"grid{side}x{side}_del10pct_sc1000_lcc_s128", "seeds": 128}
     if name == "er":
         g, seeds = inputs.workload_er(1)
         return g, seeds, {"workload": "er_n10000_m50000_lcc_s64", "seeds": 64}

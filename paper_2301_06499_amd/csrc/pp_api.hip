@@ -142,6 +142,10 @@ struct pp_run_s {
     std::vector<int64_t> counts_host;       // [staged][G]
     std::vector<int32_t> D_host;            // [G]
     int staged = 0;
+    // The push accumulator is all zero between rounds (every round clears
+    // what it set), so a reset leaves it alone -- unless a launch failed
+    // part-way through a round, or it was never cleared.
+    bool acc_clean = false;
 };
 
 // count rows copied back per wait at most
@@ -676,14 +680,14 @@ int alloc_run_dev(pp_graph g, RunDev &d, int s, int W, int cap, bool seed_counts
     return PP_OK;
 }
 
-hipError_t clear_run_dev(pp_graph g, RunDev &d, hipStream_t st) {
+hipError_t clear_run_dev(pp_graph g, RunDev &d, hipStream_t st, bool with_acc) {
     const int64_t n = g->n;
     const int64_t G = d.G;
     const int64_t cap = d.cap;
     auto seg = [](void *p, int64_t bytes, uint32_t v) { return pp::FillSeg{(uint32_t *)p, bytes / 4, v}; };
     const pp::FillSeg segs[] = {
         seg(d.sig[0], 2 * 8 * n * d.W, 0u),      // both signature buffers (one allocation)
-        seg(d.acc, 8 * n * d.W, 0u),
+        seg(d.acc, with_acc ? 8 * n * d.W : 0, 0u),
         seg(d.stamp, 4 * n, 0xFFFFFFFFu),        // -1: never queued
         seg(d.counts, 8 * cap * G, 0u),
         seg(d.seed_counts, d.seed_counts ? 4 * cap * G * d.s : 0, 0u),
@@ -808,10 +812,16 @@ int pp::set_error(int code, const char *fmt, ...) {
 
 namespace {
 
+// A failed round launch may have stopped part-way through a round.
+hipError_t noted(pp_run r, hipError_t e) {
+    if (e != hipSuccess) r->acc_clean = false;
+    return e;
+}
+
 int launch_clusters(pp_run r, int max_round) {
     GraphDev gv = graph_view(r->g, run_tiles(r));
-    HIP_TRY(pp::launch_batch_persistent(gv, r->dev, r->dclusters, (int)r->clusters.size(), r->pgrid, max_round,
-                                        r->stream));
+    HIP_TRY(noted(r, pp::launch_batch_persistent(gv, r->dev, r->dclusters, (int)r->clusters.size(), r->pgrid,
+                                                 max_round, r->stream)));
     return PP_OK;
 }
 
@@ -821,8 +831,9 @@ int reset_run(pp_run r, const int32_t *dseeds) {
     pp_graph g = r->g;
     TileSet *ts = run_tiles(r);
     GraphDev gv = graph_view(g, ts);
-    hipError_t e = clear_run_dev(g, r->dev, r->stream);
+    hipError_t e = clear_run_dev(g, r->dev, r->stream, !r->acc_clean);
     if (e == hipSuccess) {
+        r->acc_clean = true;
         if (r->pgrid) e = pp::launch_seed_scatter_batch(gv, r->dev, dseeds, r->stream);
         else e = pp::launch_seed_init(gv, r->dev, dseeds, r->stream);
     }
@@ -1051,7 +1062,10 @@ int run_persistent(pp_run r, int max_round) {
     std::vector<pp::GridBar> bars((size_t)r->G);
     HIP_TRY(hipMemcpy(bars.data(), r->dev.bar, sizeof(pp::GridBar) * bars.size(), hipMemcpyDeviceToHost));
     for (const pp::GridBar &b : bars)
-        if (b.abort) return fail(PP_EDEVICE, "persistent round loop: a cluster barrier timed out");
+        if (b.abort) {
+            r->acc_clean = false;
+            return fail(PP_EDEVICE, "persistent round loop: a cluster barrier timed out");
+        }
     if (r->timing) {
         const int last = std::min(r->host_ctrl.converged ? r->host_ctrl.round : r->host_ctrl.round - 1, r->cap - 1);
         if (last >= before) {
@@ -1086,7 +1100,7 @@ extern "C" int pp_propagate_round(pp_run r, int64_t *new_bits, int32_t *all_conv
     } else {
         GraphDev gv = graph_view(r->g, run_tiles(r));
         hipEvent_t e0 = r->timing ? r->ev[0] : nullptr, e1 = r->timing ? r->ev[1] : nullptr;
-        HIP_TRY(pp::launch_round(gv, r->dev, r->stream, e0, e1));
+        HIP_TRY(noted(r, pp::launch_round(gv, r->dev, r->stream, e0, e1)));
         if ((rc = sync_state(r, rr + 1))) return rc;
         if (r->timing) {
             float ms = 0.0f;
@@ -1115,7 +1129,7 @@ int launch_batch(pp_run r, int k) {
     GraphDev gv = graph_view(r->g, run_tiles(r));
     if (!r->opt.use_graph || (r->timing && !r->graph_events)) {
         for (int i = 0; i < k; ++i)
-            HIP_TRY(pp::launch_round(gv, r->dev, r->stream, slot_event(r, i, 0), slot_event(r, i, 1)));
+            HIP_TRY(noted(r, pp::launch_round(gv, r->dev, r->stream, slot_event(r, i, 0), slot_event(r, i, 1))));
         return PP_OK;
     }
     auto it = r->graphs.find(k);
@@ -1141,7 +1155,7 @@ int launch_batch(pp_run r, int k) {
         r->graphs[k] = exec;
         it = r->graphs.find(k);
     }
-    HIP_TRY(hipGraphLaunch(it->second, r->stream));
+    HIP_TRY(noted(r, hipGraphLaunch(it->second, r->stream)));
     return PP_OK;
 }
 
@@ -1366,12 +1380,16 @@ extern "C" int pp_run_restore(pp_run r, pp_run from) {
     if (!e) e = cp(b.ctrl, a.ctrl, sizeof(Ctrl) * G);
     if (!e) e = cp(b.bar, a.bar, sizeof(pp::GridBar) * G);
     if (!e) e = hipStreamSynchronize(st);
-    if (e) return fail(PP_EDEVICE, "restore: %s", hipGetErrorString(e));
+    if (e) {
+        r->acc_clean = false;
+        return fail(PP_EDEVICE, "restore: %s", hipGetErrorString(e));
+    }
     r->host_ctrl = from->host_ctrl;
     r->cur = from->cur;
     r->staged = from->staged;
     r->counts_host = from->counts_host;
     r->D_host = from->D_host;
+    r->acc_clean = from->acc_clean;
     return PP_OK;
 }
 
@@ -1421,7 +1439,7 @@ extern "C" int pp_time_round(pp_run r, int32_t mode, float *features, float *ms)
     // done, never the result
     HIP_TRY(hipMemcpyAsync(&r->dev.ctrl[0].mode, &mode, sizeof(int32_t), hipMemcpyHostToDevice, r->stream));
     HIP_TRY(hipEventRecord(r->tev[0], r->stream));
-    HIP_TRY(pp::launch_round(gv, r->dev, r->stream));
+    HIP_TRY(noted(r, pp::launch_round(gv, r->dev, r->stream)));
     HIP_TRY(hipEventRecord(r->tev[1], r->stream));
     HIP_TRY(hipEventSynchronize(r->tev[1]));
     HIP_TRY(hipEventElapsedTime(ms, r->tev[0], r->tev[1]));

@@ -31,7 +31,6 @@ struct Chunk {
 
 constexpr int BLOCK = 256;       // threads per block of every bulk kernel
 constexpr int TILE_NODES = 64;   // node budget of a pull tile (one wave)
-constexpr int PUSH_SLOTS = 4;    // predecessor slots per frontier entry in a push
 constexpr int PUSH_LIGHT = 16;   // entries with more predecessors go through chunks
 constexpr int PUSH_CHUNK_MIN = 32;   // smallest chunk (W = 8)
 #ifndef PP_PULL_GRID_MAX
@@ -48,9 +47,6 @@ constexpr int PULL_GRID_MAX = PP_PULL_GRID_MAX;
 #ifndef PP_PULL_WAVES
 #define PP_PULL_WAVES 4   // occupancy the pull kernel is compiled for (W <= 4)
 #endif
-#ifndef PP_STREAM_NT
-#define PP_STREAM_NT 0
-#endif
 
 // A pull tile is the work of one wave, per signature width W (words) and
 // arcs per lane K (KK, or the default when KK = 0): the tile's arc budget
@@ -66,6 +62,13 @@ template <int W, int KK = 0> struct PullShape {
     static constexpr int KG = K * L;
 };
 
+// Sizes of a frontier list, in one 8-byte word so that a block reserves both
+// with one atomic (entries in the low half).
+struct alignas(8) ListCounts {
+    int32_t nodes;    // entries
+    int32_t chunks;   // push chunks of its long predecessor lists
+};
+
 // Device control block: the round counter and everything the per-round
 // kernels hand to each other.  Frontier list p holds the nodes that changed
 // in a round of parity p.
@@ -78,8 +81,7 @@ struct Ctrl {
     int32_t active;       // graphs not yet converged
     int32_t overflow;     // the round log is full
     int32_t bad_seed;     // a seed id outside its graph was seen (nothing written for it)
-    int32_t f_count[2];   // entries in frontier list p
-    int32_t ch_count[2];  // push chunks of frontier list p
+    ListCounts lst[2];    // entries and push chunks of frontier list p
     int64_t f_arcs[2];    // predecessor arcs of frontier list p (push work)
     int64_t hub_cnt;      // new bits found by the hub kernel this round
     int64_t hub_nodes;    // hubs that changed this round
@@ -189,7 +191,6 @@ struct RunDev {
 int set_error(int code, const char *fmt, ...);
 
 // Launchers (pp_kernels.hip).  All enqueue on `st` and return the launch status.
-hipError_t launch_fill_u64(uint64_t *p, uint64_t v, int64_t count, hipStream_t st);
 hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t count, hipStream_t st);
 // Re-takes the pending direction of each of the first nctrl control blocks
 // with the run's current cost-model weights (PP_SCHED_MLP runs only).

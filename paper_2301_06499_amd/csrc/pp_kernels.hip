@@ -61,28 +61,10 @@ PP_DEV uint64_t mix64(uint64_t z) {
     return z ^ (z >> 31);
 }
 
-// Loads and stores of data read or written once per round (arc lists, the
-// node's own row, the new row): optionally marked non-temporal so they do not
-// displace the gathered successor rows from the caches.
 // Buffer k & 1 of a pair by arithmetic on both pointers rather than a
 // run-time index into the pair (which would keep a struct copy of the run in
 // scratch memory).  Both members of every pair live in one allocation.
 template <typename T> PP_DEV T *sel(T *const (&a)[2], int k) { return a[0] + (ptrdiff_t)(k & 1) * (a[1] - a[0]); }
-
-template <typename T> PP_DEV T stream_ld(const T *p) {
-#if PP_STREAM_NT
-    return __builtin_nontemporal_load(p);
-#else
-    return *p;
-#endif
-}
-template <typename T> PP_DEV void stream_st(T *p, T v) {
-#if PP_STREAM_NT
-    __builtin_nontemporal_store(v, p);
-#else
-    *p = v;
-#endif
-}
 
 template <typename T> PP_DEV T wave_sum(T v) {
 #pragma unroll
@@ -282,11 +264,6 @@ struct BlockQueue {
 
 // ---------------------------------------------------------------- fills
 
-__global__ void k_fill_u64(uint64_t *p, uint64_t v, int64_t count) {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
-         i += (int64_t)gridDim.x * blockDim.x)
-        p[i] = v;
-}
 
 __global__ void k_fill_i32(int32_t *p, int32_t v, int64_t count) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
@@ -299,11 +276,6 @@ static int fill_grid(int64_t count) {
     return (int)(b < 1 ? 1 : (b > 4096 ? 4096 : b));
 }
 
-hipError_t launch_fill_u64(uint64_t *p, uint64_t v, int64_t count, hipStream_t st) {
-    if (count <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_fill_u64, dim3(fill_grid(count)), dim3(BLOCK), 0, st, p, v, count);
-    return hipGetLastError();
-}
 
 hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t count, hipStream_t st) {
     if (count <= 0) return hipSuccess;
@@ -415,7 +387,7 @@ __global__ void __launch_bounds__(BLOCK) k_seed_scatter(GraphDev g, RunDev R, co
         if (!ok) atomicOr(&R.ctrl->bad_seed, 1);
         if (ok) atomicOr((unsigned long long *)&R.acc[(int64_t)x * W + (i >> 6)], 1ull << (i & 63));
         const bool want = ok && atomicMax(&R.stamp[x], 0) < 0;
-        const int pos = wave_append(&R.ctrl->f_count[0], want);
+        const int pos = wave_append(&R.ctrl->lst[0].nodes, want);
         if (want) R.f_ids[0][pos] = x;
     }
 }
@@ -434,7 +406,7 @@ PP_DEV void phase_push_commit(const GraphDev &g, const RunDev &R, int init, int 
     Ctrl *C = R.ctrl;
     const int r = init ? 0 : CTL(C->round);
     const int p = r & 1;
-    const int32_t cnt = CTL(C->f_count[p]);
+    const int32_t cnt = CTL(C->lst[p].nodes);
     const int64_t items = (int64_t)cnt * W;
     const int32_t *ids = sel(R.f_ids, p);
     uint64_t *dl = sel(R.f_delta, p);
@@ -487,7 +459,7 @@ PP_DEV void phase_push_commit(const GraphDev &g, const RunDev &R, int init, int 
         int total = 0;
         const int before = block_scan(nchk, s_scan, total);
         if (total) {
-            if (threadIdx.x == 0) s_cbase = atomicAdd(&C->ch_count[p], total);
+            if (threadIdx.x == 0) s_cbase = atomicAdd(&C->lst[p].chunks, total);
             __syncthreads();
             write_chunks(chunks + s_cbase, before, nchk, e, total, PushShape<W>::CHUNK, s_pre, s_ent);
         }
@@ -523,15 +495,15 @@ PP_DEV void stage_tile(const GraphDev &g, const Tile &T, int ln, int32_t (&cv)[K
 #pragma unroll
     for (int j = 0; j < K; ++j) {
         const int i = ln + j * 64;
-        cv[j] = i < ne ? stream_ld(g.col + T.e0 + i) : 0;
+        cv[j] = i < ne ? g.col[T.e0 + i] : 0;
     }
     rv0 = 0;
     rv1 = 0;
     if (T.hub >= 0) {
         rv0 = ln == 0 ? 0 : ne;
     } else {
-        if (ln <= nn) rv0 = (int)(stream_ld(g.rp + T.u0 + ln) - T.e0);
-        if (ln == 0 && nn == NODES) rv1 = (int)(stream_ld(g.rp + T.u0 + NODES) - T.e0);
+        if (ln <= nn) rv0 = (int)(g.rp[T.u0 + ln] - T.e0);
+        if (ln == 0 && nn == NODES) rv1 = (int)(g.rp[T.u0 + NODES] - T.e0);
     }
 }
 
@@ -597,7 +569,7 @@ PP_DEV void phase_pull(const GraphDev &g, const RunDev &R, int bid, int nb) {
 #pragma unroll
         for (int j = 0; j < W; ++j) {
             const int idx = ln + j * 64;
-            own[j] = (!hub && idx < nn * W) ? stream_ld(sig + (int64_t)T.u0 * W + idx) : 0;
+            own[j] = (!hub && idx < nn * W) ? sig[(int64_t)T.u0 * W + idx] : 0;
         }
 
         // gather: a group of L lanes shares arcs [a, a + KG); each lane loads
@@ -661,7 +633,7 @@ PP_DEV void phase_pull(const GraphDev &g, const RunDev &R, int bid, int nb) {
                 if (valid) {
                     const uint64_t av = acc_l[idx];
                     nw2 = av & ~own[j];
-                    stream_st(nxt + (int64_t)T.u0 * W + idx, own[j] | av);
+                    nxt[(int64_t)T.u0 * W + idx] = own[j] | av;
                 }
                 tpop += (uint64_t)__popcll(nw2);
                 const uint64_t bal = __ballot(nw2 != 0);
@@ -784,14 +756,16 @@ PP_DEV void phase_pull_hubs(const GraphDev &g, const RunDev &R, int bid, int nb,
 // After a pull round the frontier is not listed; this lists the nodes that
 // changed in round r-1 (the pull stamped them with r-1) with their new bits
 // (Sig_{r-1} and Sig_{r-2} are the two buffers), into list (r-1)&1.  Each
-// block owns a contiguous node range, one thread per node: a first pass
-// counts its entries and push chunks from the stamps alone, one atomic per
-// block reserves their slots, a second pass writes them in node order (rows
-// read for the changed nodes only) and stops once the block's entries are
-// written.
+// block owns a contiguous node range, one thread per node.  A first pass
+// reads the stamps, counts the block's entries, arcs and push chunks, and
+// collects the changed nodes in LDS; one atomic per block reserves their
+// slots; a second pass writes the entries (rows read for the changed nodes
+// only).  A block whose changed nodes overflow the LDS list rescans its
+// range instead.
 template <int W>
 PP_DEV void phase_frontier(const GraphDev &g, const RunDev &R, int bid, int nb) {
     Ctrl *C = R.ctrl;
+    constexpr int CAP = 2048;   // LDS list capacity per block
     const int r = CTL(C->round);
     const int p = (r - 1) & 1;
     const int cur = CTL(C->cur);
@@ -803,12 +777,17 @@ PP_DEV void phase_frontier(const GraphDev &g, const RunDev &R, int bid, int nb) 
     const int64_t u_end = u_begin + per < g.n ? u_begin + per : g.n;
     __shared__ int s_scan[BLOCK / 64];
     __shared__ unsigned long long s_red[BLOCK / 64];
-    __shared__ int s_nbase, s_cbase;
+    __shared__ int s_nbase, s_cbase, s_len;
     __shared__ int s_pre[BLOCK];
     __shared__ int32_t s_ent[BLOCK];
+    __shared__ int32_t s_list[CAP];
+    __shared__ int32_t s_deg[CAP];
+    if (threadIdx.x == 0) s_len = 0;
+    __syncthreads();
 
     int nodes = 0, nchunks = 0;
     int64_t arcs = 0;
+    const int ln = lane_id();
     constexpr int U = 4;   // nodes per thread whose loads are in flight together
     for (int64_t u0 = u_begin + threadIdx.x; u0 < u_end; u0 += (int64_t)U * BLOCK) {
         bool ch[U];
@@ -830,22 +809,64 @@ PP_DEV void phase_frontier(const GraphDev &g, const RunDev &R, int bid, int nb) 
             nodes += ch[k] ? 1 : 0;
             arcs += deg;
             nchunks += chunks_for<W>(deg);
+            // append to the block's LDS list: one LDS atomic per wave
+            const uint64_t m = __ballot(ch[k]);
+            if (m) {
+                const int leader = __ffsll((long long)m) - 1;
+                int base = 0;
+                if (ln == leader) base = atomicAdd(&s_len, (int)__popcll(m));
+                base = __shfl(base, leader);
+                const int pos = base + (int)__popcll(m & ((1ull << ln) - 1ull));
+                if (ch[k] && pos < CAP) {
+                    s_list[pos] = (int32_t)(u0 + (int64_t)k * BLOCK);
+                    s_deg[pos] = (int32_t)deg;
+                }
+            }
         }
     }
     const int tn = block_sum<int>(nodes, s_scan);
     const int tc = block_sum<int>(nchunks, s_scan);
     const unsigned long long ta = block_sum<unsigned long long>((unsigned long long)arcs, s_red);
-    if (threadIdx.x == 0) {
-        s_nbase = tn ? atomicAdd(&C->f_count[p], tn) : 0;
-        s_cbase = tc ? atomicAdd(&C->ch_count[p], tc) : 0;
-        if (ta) atomicAdd((unsigned long long *)&C->f_arcs[p], ta);
+    // the list's arcs are the pull's changed nodes' arcs, which the round's
+    // end of that pull has recorded already
+    (void)ta;
+    if (threadIdx.x == 0 && (tn | tc)) {
+        const unsigned long long old = atomicAdd(reinterpret_cast<unsigned long long *>(&C->lst[p]),
+                                                 (unsigned long long)tn | ((unsigned long long)tc << 32));
+        s_nbase = (int)(uint32_t)old;
+        s_cbase = (int)(old >> 32);
     }
     __syncthreads();
     if (tn == 0) return;   // same for the whole block
     int32_t *ids = sel(R.f_ids, p);
     uint64_t *dl = sel(R.f_delta, p);
     Chunk *chunks = sel(R.chunks, p);
-    int done = 0, crun = s_cbase;
+    int crun = s_cbase;
+    if (tn <= CAP) {
+        // the listed nodes only (in the order the waves appended them)
+        for (int i0 = 0; i0 < tn; i0 += BLOCK) {   // block-uniform
+            const int i = i0 + threadIdx.x;
+            const bool valid = i < tn;
+            const int64_t u = valid ? s_list[i] : 0;
+            const int nchk = valid ? chunks_for<W>(s_deg[i]) : 0;
+            const int pos = s_nbase + i;
+            int it_chunks = 0;
+            const int cfirst = crun + block_scan(nchk, s_scan, it_chunks);
+            if (valid) {
+                uint64_t a[W], b[W];
+                load_row<W>(now + u * W, a);
+                load_row<W>(old + u * W, b);
+#pragma unroll
+                for (int w = 0; w < W; ++w) a[w] &= ~b[w];
+                ids[pos] = (int32_t)u;
+                store_row<W>(dl + (int64_t)pos * W, a);
+            }
+            if (it_chunks) write_chunks(chunks + crun, cfirst - crun, nchk, pos, it_chunks, PushShape<W>::CHUNK, s_pre, s_ent);
+            crun += it_chunks;
+        }
+        return;
+    }
+    int done = 0;
     for (int64_t ub = u_begin; ub < u_end && done < tn; ub += BLOCK) {   // block-uniform
         const int64_t u = ub + threadIdx.x;
         const bool changed = u < u_end && R.stamp[u] == r - 1;
@@ -869,24 +890,36 @@ PP_DEV void phase_frontier(const GraphDev &g, const RunDev &R, int bid, int nb) 
     }
 }
 
-// Pushes the new bits d of one frontier entry to up to IT predecessors per
+// Pushes new bits d[it] of frontier entries to up to IT predecessors per
 // lane (the W lanes of a slot share the predecessor and hold its words).  All
-// predecessor ids are loaded, then all atomic ORs issued, before any result is
-// used; a bit is new when the atomic that set it saw it clear.  Predecessors
+// predecessor ids are loaded, then all rows read, then the atomic ORs of the
+// bits not seen set issued, before any result is used; a bit is new when the
+// atomic that set it saw it clear.  Predecessors
 // that gained a bit are queued once per round (stamp).
 template <int W, int IT>
 PP_DEV void push_slots(const RunDev &R, uint64_t *sig, int r, const int64_t (&k)[IT], const bool (&kv)[IT],
-                       const int32_t *tcol, int w, uint64_t d, BlockQueue &bq, Ctrl *C, int pn) {
+                       const int32_t *tcol, int w, const uint64_t (&d)[IT], BlockQueue &bq, Ctrl *C, int pn) {
     int32_t u[IT];
 #pragma unroll
     for (int it = 0; it < IT; ++it) u[it] = kv[it] ? tcol[k[it]] : 0;
+    // a plain read first: bits only ever get set, so a bit seen set (even in
+    // a stale copy) needs no atomic, and most pushes of a late round bring
+    // nothing new
+    uint64_t seen[IT];
+#pragma unroll
+    for (int it = 0; it < IT; ++it)
+        seen[it] = (kv[it] && d[it]) ? __hip_atomic_load(&sig[(int64_t)u[it] * W + w], __ATOMIC_RELAXED,
+                                                         __HIP_MEMORY_SCOPE_WORKGROUP)
+                                     : ~0ull;
     uint64_t nb[IT];
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
         nb[it] = 0;
-        if (kv[it] && d) {
-            const uint64_t oldv = atomicOr((unsigned long long *)&sig[(int64_t)u[it] * W + w], (unsigned long long)d);
-            nb[it] = d & ~oldv;
+        const uint64_t need = d[it] & ~seen[it];
+        if (kv[it] && need) {
+            const uint64_t oldv =
+                atomicOr((unsigned long long *)&sig[(int64_t)u[it] * W + w], (unsigned long long)need);
+            nb[it] = need & ~oldv;
         }
     }
     const int ln = lane_id();
@@ -900,7 +933,7 @@ PP_DEV void push_slots(const RunDev &R, uint64_t *sig, int r, const int64_t (&k)
         want[it] = any && w == 0 && atomicMax(&R.stamp[u[it]], r) < r;
     }
 #pragma unroll
-    for (int it = 0; it < IT; ++it) bq.push(want[it], u[it], &C->f_count[pn], sel(R.f_ids, pn));
+    for (int it = 0; it < IT; ++it) bq.push(want[it], u[it], &C->lst[pn].nodes, sel(R.f_ids, pn));
 }
 
 template <int W>
@@ -909,8 +942,8 @@ PP_DEV void phase_push(const GraphDev &g, const RunDev &R, int bid, int nb) {
     const int r = CTL(C->round);
     const int pp = (r - 1) & 1, pn = r & 1;
     uint64_t *sig = sel(R.sig, CTL(C->cur));
-    const int32_t cnt = CTL(C->f_count[pp]);
-    const int32_t nch = CTL(C->ch_count[pp]);
+    const int32_t cnt = CTL(C->lst[pp].nodes);
+    const int32_t nch = CTL(C->lst[pp].chunks);
     const int32_t *ids = sel(R.f_ids, pp);
     const uint64_t *dl = sel(R.f_delta, pp);
     const int ln = lane_id();
@@ -923,32 +956,50 @@ PP_DEV void phase_push(const GraphDev &g, const RunDev &R, int bid, int nb) {
     if (threadIdx.x == 0) s_qn = 0;
     __syncthreads();
 
-    // light entries: PUSH_SLOTS slots of W lanes each walk the whole list
+    // light entries (at most PUSH_LIGHT predecessors): a wave takes G = 64/W
+    // entries at a time, one per group of W lanes, and walks their arcs as
+    // one flat range (an exclusive scan of the entries' degrees), one arc per
+    // group per step, so short lists leave no lane idle; a group finds the
+    // entry of its arc by binary search over the scan held in the lanes
     {
-        constexpr int L = W * PUSH_SLOTS;
-        constexpr int GPW = 64 / L;
-        constexpr int IT = PUSH_LIGHT / PUSH_SLOTS;
-        const int grp = ln / L, slot = (ln % L) / W;
-        for (int64_t e0 = wave * GPW; e0 < cnt; e0 += nwaves * GPW) {   // wave-uniform
+        constexpr int G = 64 / W;
+        constexpr int IT = 4;
+        const int grp = ln / W;
+        for (int64_t e0 = wave * G; e0 < cnt; e0 += nwaves * G) {   // wave-uniform
             const int64_t e = e0 + grp;
-            bool ev = e < cnt;
-            int64_t b = 0, end = 0;
+            int64_t b = 0;
+            int deg = 0;
             uint64_t d = 0;
-            if (ev) {
+            if (e < cnt) {
                 const int32_t v = ids[e];
                 b = g.trp[v];
-                end = g.trp[v + 1];
-                ev = end - b <= PUSH_LIGHT;
+                const int64_t len = g.trp[v + 1] - b;
+                deg = len <= PUSH_LIGHT ? (int)len : 0;   // long lists go through chunks
                 d = dl[e * W + w];
             }
-            int64_t k[IT];
-            bool kv[IT];
+            const int contrib = w == 0 ? deg : 0;
+            const int incl = wave_inclusive_scan(contrib);
+            const int start = __shfl(incl - contrib, grp * W);   // the group's first flat arc
+            const int total = __shfl(incl, 63);
+            for (int a0 = 0; a0 < total; a0 += G * IT) {   // wave-uniform
+                int64_t k[IT];
+                bool kv[IT];
+                uint64_t dd[IT];
 #pragma unroll
-            for (int it = 0; it < IT; ++it) {
-                k[it] = b + slot + it * PUSH_SLOTS;
-                kv[it] = ev && k[it] < end;
+                for (int it = 0; it < IT; ++it) {
+                    const int a = a0 + it * G + grp;
+                    int lo = 0;   // the last group whose first flat arc is <= a
+#pragma unroll
+                    for (int step = G >> 1; step > 0; step >>= 1)   // lo + step stays below G
+                        if (__shfl(start, (lo + step) * W) <= a) lo += step;
+                    const int so = __shfl(start, lo * W);
+                    const int64_t bo = __shfl(b, lo * W);
+                    dd[it] = __shfl(d, lo * W + w);
+                    kv[it] = a < total;
+                    k[it] = bo + (a - so);
+                }
+                push_slots<W, IT>(R, sig, r, k, kv, g.tcol, w, dd, bq, C, pn);
             }
-            push_slots<W, IT>(R, sig, r, k, kv, g.tcol, w, d, bq, C, pn);
         }
     }
     // long lists: chunks of CHUNK arcs, one wave each
@@ -966,15 +1017,17 @@ PP_DEV void phase_push(const GraphDev &g, const RunDev &R, int bid, int nb) {
             const int64_t end = (b + CH < lim) ? b + CH : lim;
             int64_t k[IT];
             bool kv[IT];
+            uint64_t dd[IT];
 #pragma unroll
             for (int it = 0; it < IT; ++it) {
                 k[it] = b + slot + it * SL;
                 kv[it] = k[it] < end;
+                dd[it] = d;
             }
-            push_slots<W, IT>(R, sig, r, k, kv, g.tcol, w, d, bq, C, pn);
+            push_slots<W, IT>(R, sig, r, k, kv, g.tcol, w, dd, bq, C, pn);
         }
     }
-    bq.flush(&C->f_count[pn], sel(R.f_ids, pn), &s_qbase);
+    bq.flush(&C->lst[pn].nodes, sel(R.f_ids, pn), &s_qbase);
 }
 
 // ---------------------------------------------------------------- round end
@@ -1047,7 +1100,7 @@ PP_DEV void phase_round_end(const GraphDev &g, const RunDev &R, int init, int np
     __shared__ int s_next;
     // every control-block value the end needs, loaded up front
     const long long hub_cnt = CTL(C->hub_cnt), hub_nodes = CTL(C->hub_nodes), hub_arcs = CTL(C->hub_arcs);
-    const long long lst_count = CTL(C->f_count[r & 1]), lst_arcs = CTL(C->f_arcs[r & 1]);
+    const long long lst_count = CTL(C->lst[r & 1].nodes), lst_arcs = CTL(C->f_arcs[r & 1]);
     const long long prev_arcs = CTL(C->f_arcs[(r - 1) & 1]);
     const int64_t reached0 = CTL(C->reached), last = CTL(C->last_count);
     // one reduction for the four sums: pull partials (pull rounds) and the
@@ -1121,7 +1174,8 @@ PP_DEV void phase_round_end(const GraphDev &g, const RunDev &R, int init, int np
     if (threadIdx.x == 0) {
         R.mode_log[r] = mode;
         R.arcs_log[r] = mode == MODE_PULL ? pulled : (mode == MODE_PUSH ? prev_arcs : 0);
-        if (mode != MODE_PULL && parts) C->f_arcs[r & 1] = farcs;   // the list's arcs, summed here
+        // the arcs of the nodes changed in this round: a following push's work
+        if (mode == MODE_PULL || parts) C->f_arcs[r & 1] = farcs;
         if (mode == MODE_PULL) C->cur ^= 1;
         C->prev_mode = mode;
         C->hub_cnt = 0;
@@ -1143,8 +1197,8 @@ PP_DEV void phase_round_end(const GraphDev &g, const RunDev &R, int init, int np
             C->overflow = 1;
         } else {
             const int nr = r + 1, q = nr & 1;
-            C->f_count[q] = 0;
-            C->ch_count[q] = 0;
+            C->lst[q].nodes = 0;
+            C->lst[q].chunks = 0;
             C->f_arcs[q] = 0;
             C->mode = s_next;
             C->round = nr;
@@ -1165,10 +1219,6 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(W >=
 k_pull(GraphDev g, RunDev R) {
     if (R.ctrl->converged || R.ctrl->mode != MODE_PULL) return;
     phase_pull<W, KK>(g, R, blockIdx.x, gridDim.x);
-}
-template <int W> __global__ void __launch_bounds__(BLOCK) k_pull_hubs(GraphDev g, RunDev R) {
-    if (R.ctrl->converged || R.ctrl->mode != MODE_PULL) return;
-    phase_pull_hubs<W>(g, R, blockIdx.x, gridDim.x);
 }
 template <int W> __global__ void __launch_bounds__(BLOCK) k_frontier(GraphDev g, RunDev R) {
     if (R.ctrl->converged || R.ctrl->mode != MODE_PUSH || R.ctrl->prev_mode != MODE_PULL) return;
@@ -1411,7 +1461,7 @@ __global__ void __launch_bounds__(BLOCK) k_seed_scatter_batch(GraphDev g, RunDev
         if (!ok) continue;
         atomicOr((unsigned long long *)&R.acc[(int64_t)x * W + (i >> 6)], 1ull << (i & 63));
         if (atomicMax(&R.stamp[x], 0) < 0) {
-            const int pos = atomicAdd(&R.ctrl[gi].f_count[0], 1);
+            const int pos = atomicAdd(&R.ctrl[gi].lst[0].nodes, 1);
             R.f_ids[0][n0 + pos] = x;
         }
     }

@@ -330,3 +330,20 @@ def test_exact_neighbourhood_function(case):
     assert m["reachable_pairs"] == float(int((dist >= 0).sum()))
     with pytest.raises(pp.PPError):
         pp.pp_exact_counts(G, group=513)
+
+
+def test_grid4096_full_size():
+    """The 4096^2 grid with deletions and shortcuts, s = 128, at full size: per-round
+    counts, D and every signature against the oracle (all 128 BFS on the host),
+    with the heuristic and with a pseudo-random schedule."""
+    g, seeds = gen.workload_grid_shortcuts(4096, 128, 1)
+    say("grid4096 oracle", g.n)
+    want = oracle.propagate(g.n, g.src, g.dst, seeds, True, final_sig=True)
+    G = pp.pp_csr_build(g.n, g.src, g.dst, undirected=True)
+    for sched in (pp.PP_SCHED_HEURISTIC, pp.PP_SCHED_FUZZ):
+        say("grid4096 run", sched)
+        r = pp.pp_seeds_init(G, seeds, opts=pp.options(scheduler=sched, fuzz_seed=3, max_rounds=want["D"] + 4))
+        counts, D = pp.pp_propagate_until_converged(r)
+        assert int(D[0]) == want["D"] and list(counts[0]) == list(want["counts"])
+        assert np.array_equal(pp.pp_get_signatures(r), pad_words(want["final_sig"], r.words))
+        r.free()
