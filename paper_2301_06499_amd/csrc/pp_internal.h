@@ -97,7 +97,7 @@ struct Ctrl {
 constexpr int TICKET_GROUP = 32;
 constexpr int TICKET_STRIDE = 32;   // int32 per cache line
 constexpr int TICKET_INTS = (TICKET_GROUP + 1) * TICKET_STRIDE;
-constexpr int POST_MAX = 256;       // blocks of the closing launch at most
+constexpr int POST_MAX = 1024;      // blocks of the closing launch at most
 
 // Learned cost model: an MLP 8 -> 32 -> 32 -> 2 (ReLU) predicting the log of a
 // round's duration under pull (output 0) and push (output 1).  Parameter

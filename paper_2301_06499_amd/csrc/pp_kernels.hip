@@ -1,7 +1,7 @@
 // HIP kernels for PROPAGATE-P rounds on gfx950 (wave64).
 //
 // A round r (one pass of Algorithm 1's do-while body) is a fixed sequence of
-// four launches that hand work to each other through the device control
+// three launches that hand work to each other through the device control
 // block, so no host decision is needed between rounds and a batch of rounds
 // can be replayed as a captured graph.  Kernels of the direction not chosen
 // for the round return at once.
@@ -19,7 +19,8 @@
 // Sparse push (equal to the pull: only the bits a node gained in round r-1
 // can give new bits in round r, every older bit having reached its
 // predecessors already):
-//   k_frontier<W>    after a pull round, lists the nodes that changed in it.
+//   k_pull<W>        in a push round after a pull round: lists the nodes
+//                    that changed in the pull (same launch slot).
 //   k_push<W>        ORs those new bits into the predecessors' rows with
 //                    atomics; a bit is new when the atomic that sets it saw
 //                    it clear; nodes that gained bits are queued once.
@@ -206,19 +207,25 @@ template <int W> PP_DEV int chunks_for(int64_t deg) {
 }
 
 // Push chunk records of one block iteration, written by the whole block:
-// thread t owns nchk chunks of entry `entry` at slots [before, before + nchk)
-// of out (before: the block's exclusive scan of nchk; total: its sum).  Each
-// thread writes every BLOCK-th slot, finding the owner by binary search over
-// the block's scan, so one long list costs no thread more than total/BLOCK
-// stores.  All threads of the block call; ends with a barrier.
-PP_DEV void write_chunks(Chunk *out, int before, int nchk, int32_t entry, int total, int chunk, int *s_pre,
-                         int32_t *s_ent) {
-    s_pre[threadIdx.x] = before;
-    s_ent[threadIdx.x] = entry;
-    (void)nchk;
+// thread t owns nchk[k] chunks of entry entry[k] (k < U), at slots from
+// `before` on, in (thread, k) order (before: the block's exclusive scan of
+// the threads' sums; total: the block's sum).  Each thread writes every
+// BLOCK-th slot, finding the owner by binary search over the block's scan, so
+// one long list costs no thread more than total/BLOCK stores.  All threads of
+// the block call; s_pre and s_ent hold BLOCK * U ints; ends with a barrier.
+template <int U>
+PP_DEV void write_chunks(Chunk *out, int before, const int (&nchk)[U], const int32_t (&entry)[U], int total,
+                         int chunk, int *s_pre, int32_t *s_ent) {
+    int run = before;
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+        s_pre[threadIdx.x * U + k] = run;
+        s_ent[threadIdx.x * U + k] = entry[k];
+        run += nchk[k];
+    }
     __syncthreads();
     for (int c = threadIdx.x; c < total; c += BLOCK) {
-        int lo = 0, hi = BLOCK - 1;   // last thread whose first slot is <= c: it owns slot c
+        int lo = 0, hi = BLOCK * U - 1;   // the last (thread, k) whose first slot is <= c owns slot c
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
             if (s_pre[mid] <= c) lo = mid; else hi = mid - 1;
@@ -226,6 +233,12 @@ PP_DEV void write_chunks(Chunk *out, int before, int nchk, int32_t entry, int to
         out[c] = Chunk{s_ent[lo], (c - s_pre[lo]) * chunk};
     }
     __syncthreads();
+}
+PP_DEV void write_chunks(Chunk *out, int before, int nchk, int32_t entry, int total, int chunk, int *s_pre,
+                         int32_t *s_ent) {
+    const int n1[1] = {nchk};
+    const int32_t e1[1] = {entry};
+    write_chunks<1>(out, before, n1, e1, total, chunk, s_pre, s_ent);
 }
 
 // Lists nodes in a block-private LDS queue and moves the queue to the global
@@ -394,80 +407,112 @@ __global__ void __launch_bounds__(BLOCK) k_seed_scatter(GraphDev g, RunDev R, co
 
 // ---------------------------------------------------------------- list commit
 
+// The commit's items (entry, word) of list p: U per thread and pass, their
+// loads in flight together, taken U grid-widths apart so that a short list
+// still spreads over every block.
+template <int W, int U>
+PP_DEV void commit_items(const GraphDev &g, const RunDev &R, int init, int r, int p, int64_t items, int bid, int nb,
+                         uint64_t &pop, int64_t &arcs, uint32_t (&sc)[W]) {
+    Ctrl *C = R.ctrl;
+    const int32_t *ids = sel(R.f_ids, p);
+    uint64_t *dl = sel(R.f_delta, p);
+    Chunk *chunks = sel(R.chunks, p);
+    const int w = lane_id() & (W - 1);
+    const bool per_seed = R.seed_counts != nullptr;
+    __shared__ int s_scan[BLOCK / 64];
+    __shared__ int s_cbase;
+    __shared__ int s_pre[BLOCK * U];
+    __shared__ int32_t s_ent[BLOCK * U];
+    const int64_t width = (int64_t)nb * BLOCK;
+    for (int64_t bb = bid * (int64_t)BLOCK; bb < items; bb += width * U) {   // block-uniform
+        int64_t idx[U];
+        bool valid[U];
+        int32_t u[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            idx[k] = bb + (int64_t)k * width + threadIdx.x;   // word idx % W == w
+            valid[k] = idx[k] < items;
+            u[k] = valid[k] ? ids[idx[k] / W] : 0;
+        }
+        uint64_t d[U];
+        int64_t lo[U], hi[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            d[k] = valid[k] ? R.acc[(int64_t)u[k] * W + w] : 0;
+            const bool head = valid[k] && w == 0;
+            lo[k] = head ? g.trp[u[k]] : 0;
+            hi[k] = head ? g.trp[u[k] + 1] : 0;
+        }
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            if (!valid[k]) continue;
+            R.acc[(int64_t)u[k] * W + w] = 0;
+            dl[idx[k]] = d[k];
+            if (init) {
+                R.sig[0][(int64_t)u[k] * W + w] |= d[k];
+                R.sig[1][(int64_t)u[k] * W + w] |= d[k];
+            }
+        }
+        int nchk[U];
+        int32_t ent[U];
+        int tc = 0;
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            const int64_t deg = hi[k] - lo[k];
+            arcs += deg;
+            nchk[k] = chunks_for<W>(deg);
+            ent[k] = (int32_t)(idx[k] / W);
+            tc += nchk[k];
+        }
+        // push chunks of long predecessor lists: one reservation per block and pass
+        if (__syncthreads_or(tc > 0)) {
+            int total = 0;
+            const int before = block_scan(tc, s_scan, total);
+            if (threadIdx.x == 0) s_cbase = atomicAdd(&C->lst[p].chunks, total);
+            __syncthreads();
+            write_chunks<U>(chunks + s_cbase, before, nchk, ent, total, PushShape<W>::CHUNK, s_pre, s_ent);
+        }
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            const int pc = __popcll(d[k]);
+            int gi = 0;
+            if (R.G == 1) {
+                pop += (uint64_t)pc;
+            } else if (valid[k]) {
+                gi = g.node_graph[u[k]];
+                if (pc) atomicAdd((unsigned long long *)&R.counts[(int64_t)r * R.cstride + gi], (unsigned long long)pc);
+            }
+            if (per_seed) {
+                if (R.G == 1) seed_ballot<W>(d[k], sc);
+                else if (valid[k]) seed_bits(R, r, gi, w, d[k]);
+            }
+        }
+    }
+}
+
 // Collects the bits gathered in the accumulator for the entries of frontier
 // list r&1, writes them into the list, counts them, and reserves push chunks
 // for the next round.  Round 0 (init) also writes them into both signature
 // buffers; a push round has set them in Sig already.
-template <int W>
 // parts (the closing launch): the block's new-bit count and predecessor arcs
 // go to its slots of the per-block partials instead of the round's
 // counters, which the round's end then sums.
+template <int W>
 PP_DEV void phase_push_commit(const GraphDev &g, const RunDev &R, int init, int bid, int nb, int64_t *parts = nullptr) {
     Ctrl *C = R.ctrl;
     const int r = init ? 0 : CTL(C->round);
     const int p = r & 1;
     const int32_t cnt = CTL(C->lst[p].nodes);
     const int64_t items = (int64_t)cnt * W;
-    const int32_t *ids = sel(R.f_ids, p);
-    uint64_t *dl = sel(R.f_delta, p);
-    Chunk *chunks = sel(R.chunks, p);
-    const int ln = lane_id();
-    const int w = ln & (W - 1);
     const bool per_seed = R.seed_counts != nullptr;
-    __shared__ int s_scan[BLOCK / 64];
-    __shared__ int s_cbase;
-    __shared__ int s_pre[BLOCK];
-    __shared__ int32_t s_ent[BLOCK];
     uint64_t pop = 0;
     int64_t arcs = 0;
     uint32_t sc[W];
 #pragma unroll
     for (int k = 0; k < W; ++k) sc[k] = 0;
-    const int64_t stride = (int64_t)nb * BLOCK;
-    for (int64_t bb = bid * (int64_t)BLOCK; bb < items; bb += stride) {   // block-uniform
-        const int64_t idx = bb + threadIdx.x;
-        const bool valid = idx < items;
-        const int32_t e = (int32_t)(idx / W);
-        uint64_t d = 0;
-        int32_t u = 0;
-        int64_t deg = 0;
-        if (valid) {
-            u = ids[e];
-            uint64_t *ap = R.acc + (int64_t)u * W + w;
-            d = *ap;
-            *ap = 0;
-            dl[idx] = d;
-            if (init) {
-                R.sig[0][(int64_t)u * W + w] |= d;
-                R.sig[1][(int64_t)u * W + w] |= d;
-            }
-            if (w == 0) {
-                deg = g.trp[u + 1] - g.trp[u];
-                arcs += deg;
-            }
-        }
-        const int pc = __popcll(d);
-        int gi = 0;
-        if (R.G == 1) {
-            pop += (uint64_t)pc;
-        } else if (valid) {
-            gi = g.node_graph[u];
-            if (pc) atomicAdd((unsigned long long *)&R.counts[(int64_t)r * R.cstride + gi], (unsigned long long)pc);
-        }
-        // push chunks of long predecessor lists, one reservation per block
-        const int nchk = (valid && w == 0) ? chunks_for<W>(deg) : 0;
-        int total = 0;
-        const int before = block_scan(nchk, s_scan, total);
-        if (total) {
-            if (threadIdx.x == 0) s_cbase = atomicAdd(&C->lst[p].chunks, total);
-            __syncthreads();
-            write_chunks(chunks + s_cbase, before, nchk, e, total, PushShape<W>::CHUNK, s_pre, s_ent);
-        }
-        if (per_seed) {
-            if (R.G == 1) seed_ballot<W>(d, sc);
-            else if (valid) seed_bits(R, r, gi, w, d);
-        }
-    }
+    // long lists: four items per thread and pass
+    if (items > 2 * (int64_t)nb * BLOCK) commit_items<W, 4>(g, R, init, r, p, items, bid, nb, pop, arcs, sc);
+    else commit_items<W, 1>(g, R, init, r, p, items, bid, nb, pop, arcs, sc);
     __shared__ unsigned long long s_red[BLOCK / 64];
     const unsigned long long tp = block_sum<unsigned long long>(pop, s_red);
     const unsigned long long ta = block_sum<unsigned long long>((unsigned long long)arcs, s_red);
@@ -762,10 +807,9 @@ PP_DEV void phase_pull_hubs(const GraphDev &g, const RunDev &R, int bid, int nb,
 // slots; a second pass writes the entries (rows read for the changed nodes
 // only).  A block whose changed nodes overflow the LDS list rescans its
 // range instead.
-template <int W>
+template <int W, int CAP = 2048>   // CAP: LDS list capacity per block
 PP_DEV void phase_frontier(const GraphDev &g, const RunDev &R, int bid, int nb) {
     Ctrl *C = R.ctrl;
-    constexpr int CAP = 2048;   // LDS list capacity per block
     const int r = CTL(C->round);
     const int p = (r - 1) & 1;
     const int cur = CTL(C->cur);
@@ -1107,6 +1151,7 @@ PP_DEV void phase_round_end(const GraphDev &g, const RunDev &R, int init, int np
     // closing launch's partials
     long long v[4] = {0, 0, 0, 0};
     if (mode == MODE_PULL) {
+#pragma unroll 4
         for (int b = threadIdx.x; b < nparts; b += BLOCK) {
             v[0] += R.blk_cnt[b];
             v[1] += R.blk_nodes[b];
@@ -1114,10 +1159,14 @@ PP_DEV void phase_round_end(const GraphDev &g, const RunDev &R, int init, int np
             v[3] += R.blk_pulled[b];
         }
     }
-    for (int b = threadIdx.x; b < npost; b += BLOCK) {
-        v[0] += CTL(parts[0 * POST_MAX + b]);
-        v[1] += CTL(parts[1 * POST_MAX + b]);
-        v[2] += CTL(parts[2 * POST_MAX + b]);
+#pragma unroll
+    for (int j = 0; j < POST_MAX / BLOCK; ++j) {   // all loads issued before the sums
+        const int b = threadIdx.x + j * BLOCK;
+        if (b < npost) {
+            v[0] += CTL(parts[0 * POST_MAX + b]);
+            v[1] += CTL(parts[1 * POST_MAX + b]);
+            v[2] += CTL(parts[2 * POST_MAX + b]);
+        }
     }
 #pragma unroll
     for (int k = 0; k < 4; ++k) v[k] = wave_sum(v[k]);
@@ -1214,15 +1263,22 @@ template <int W> __global__ void __launch_bounds__(BLOCK) k_push_commit(GraphDev
     if (R.ctrl->converged || (!init && R.ctrl->mode != MODE_PUSH)) return;
     phase_push_commit<W>(g, R, init, blockIdx.x, gridDim.x);
 }
+// The pull, or in a push round that follows a pull the frontier listing (the
+// push's first phase, in the same launch slot so that a round takes three
+// launches).  The listing uses at most FRONTIER_BLOCKS blocks: each takes one
+// reservation atomic on a single address, and those serialise.
+constexpr int FRONTIER_BLOCKS = 1024;
 template <int W, int KK>
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(W >= 8 ? 2 : PP_PULL_WAVES)))
 k_pull(GraphDev g, RunDev R) {
-    if (R.ctrl->converged || R.ctrl->mode != MODE_PULL) return;
-    phase_pull<W, KK>(g, R, blockIdx.x, gridDim.x);
-}
-template <int W> __global__ void __launch_bounds__(BLOCK) k_frontier(GraphDev g, RunDev R) {
-    if (R.ctrl->converged || R.ctrl->mode != MODE_PUSH || R.ctrl->prev_mode != MODE_PULL) return;
-    phase_frontier<W>(g, R, blockIdx.x, gridDim.x);
+    const Ctrl *C = R.ctrl;
+    if (C->converged) return;
+    if (C->mode == MODE_PULL) {
+        phase_pull<W, KK>(g, R, blockIdx.x, gridDim.x);
+    } else if (C->prev_mode == MODE_PULL && blockIdx.x < FRONTIER_BLOCKS) {
+        const int nb = gridDim.x < FRONTIER_BLOCKS ? (int)gridDim.x : FRONTIER_BLOCKS;
+        phase_frontier<W, 1024>(g, R, blockIdx.x, nb);
+    }
 }
 template <int W> __global__ void __launch_bounds__(BLOCK) k_push(GraphDev g, RunDev R) {
     if (R.ctrl->converged || R.ctrl->mode != MODE_PUSH) return;
@@ -1477,10 +1533,18 @@ int pull_grid_for(int32_t ntiles) {
 
 // blocks of the frontier, push and closing launches (at most 1024, which the
 // closing launch's ticket covers)
-static_assert(TICKET_GROUP * TICKET_GROUP >= 1024, "ticket groups");
+static_assert(TICKET_GROUP * TICKET_GROUP >= 1024 && POST_MAX >= 1024, "ticket groups, partials");
 static int list_grid(const GraphDev &g) {
     const int64_t b = (g.n + BLOCK - 1) / BLOCK;
     return (int)(b < 64 ? 64 : (b > 1024 ? 1024 : b));
+}
+
+// blocks of the closing launch: a push round's commit lists up to n nodes,
+// but a launch of many blocks that mostly find nothing to do costs time in
+// every round; one block per 4096 nodes, 64 to POST_MAX
+static int post_grid(const GraphDev &g) {
+    const int64_t b = (g.n + 4095) / 4096;
+    return (int)(b < 64 ? 64 : (b > POST_MAX ? POST_MAX : b));
 }
 
 template <int W> static hipError_t seed_init_impl(const GraphDev &g, const RunDev &R, const int32_t *seeds, hipStream_t st) {
@@ -1493,9 +1557,6 @@ template <int W> static hipError_t seed_init_impl(const GraphDev &g, const RunDe
 
 template <int W>
 static hipError_t round_impl(const GraphDev &g, const RunDev &R, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
-    const int lg = list_grid(g);
-    hipLaunchKernelGGL(k_frontier<W>, dim3(lg), dim3(BLOCK), 0, st, g, R);
-    hipLaunchKernelGGL(k_push<W>, dim3(lg), dim3(BLOCK), 0, st, g, R);
     if (e0) {
         const hipError_t e = hipEventRecord(e0, st);
         if (e != hipSuccess) return e;
@@ -1506,9 +1567,8 @@ static hipError_t round_impl(const GraphDev &g, const RunDev &R, hipStream_t st,
         const hipError_t e = hipEventRecord(e1, st);
         if (e != hipSuccess) return e;
     }
-    // the closing launch is light (the push's gained nodes, the hubs): one
-    // block per compute unit keeps its same-address atomics few
-    hipLaunchKernelGGL(k_post<W>, dim3(lg < POST_MAX ? lg : POST_MAX), dim3(BLOCK), 0, st, g, R);
+    hipLaunchKernelGGL(k_push<W>, dim3(list_grid(g)), dim3(BLOCK), 0, st, g, R);
+    hipLaunchKernelGGL(k_post<W>, dim3(post_grid(g)), dim3(BLOCK), 0, st, g, R);
     return hipGetLastError();
 }
 
