@@ -120,7 +120,7 @@ struct pp_run_s {
     Ctrl host_ctrl{};
     std::map<int, hipGraphExec_t> graphs;   // captured batches by round count
     std::map<int, hipGraph_t> graph_defs;
-    int32_t *dseeds = nullptr;              // [G*s] staging for host seed lists
+    int32_t *dseeds = nullptr;              // [G*s] mapped device seeds for the clustered engine
     bool timing = false;
     bool graph_events = true;               // events recorded inside captured graphs work
     std::vector<hipEvent_t> ev;             // 2 per round slot of a batch
@@ -137,7 +137,11 @@ struct pp_run_s {
     Ctrl *h_ctrl = nullptr;
     int32_t *h_D = nullptr;
     int64_t *h_rows = nullptr;
-    int32_t *h_seeds = nullptr;             // host seed list on its way to dseeds
+    void *h_ctrl_dev = nullptr;             // the same three, as the device addresses them
+    int32_t *h_D_dev = nullptr;
+    int64_t *h_rows_dev = nullptr;
+    int32_t *h_seeds = nullptr;             // host seed list, read in place by the initialisation
+    int32_t *h_seeds_dev = nullptr;         // the same, as the device addresses it
     hipEvent_t seeds_sent = nullptr;        // its copy has been read
     std::vector<int64_t> counts_host;       // [staged][G]
     std::vector<int32_t> D_host;            // [G]
@@ -715,7 +719,8 @@ int alloc_staging(pp_run r) {
     const size_t G = (size_t)r->G;
     const size_t bytes = sizeof(Ctrl) * G + 8 * ((G + 1) / 2) + sizeof(int64_t) * STAGE_ROWS * G +
                          sizeof(int32_t) * G * (size_t)r->s;
-    if (hipHostMalloc(&r->pinned, bytes, hipHostMallocDefault) != hipSuccess) {
+    // coherent and mapped: the staging kernel stores into it directly
+    if (hipHostMalloc(&r->pinned, bytes, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
         r->pinned = nullptr;
         (void)hipGetLastError();
         return fail(PP_ENOMEM, "pinned host staging of %zu bytes", bytes);
@@ -724,6 +729,15 @@ int alloc_staging(pp_run r) {
     r->h_D = (int32_t *)(r->h_ctrl + G);
     r->h_rows = (int64_t *)((char *)r->h_D + 8 * ((G + 1) / 2));
     r->h_seeds = (int32_t *)(r->h_rows + STAGE_ROWS * G);
+    void *dev = nullptr;
+    if (hipHostGetDevicePointer(&dev, r->pinned, 0) != hipSuccess || !dev) {
+        (void)hipGetLastError();
+        return fail(PP_EDEVICE, "pinned host staging is not mapped for the device");
+    }
+    r->h_ctrl_dev = dev;
+    r->h_D_dev = (int32_t *)((char *)dev + ((char *)r->h_D - (char *)r->pinned));
+    r->h_rows_dev = (int64_t *)((char *)dev + ((char *)r->h_rows - (char *)r->pinned));
+    r->h_seeds_dev = (int32_t *)((char *)dev + ((char *)r->h_seeds - (char *)r->pinned));
     r->D_host.assign(G, 0);
     if (hipEventCreateWithFlags(&r->seeds_sent, hipEventDisableTiming) != hipSuccess) {
         r->seeds_sent = nullptr;
@@ -732,14 +746,18 @@ int alloc_staging(pp_run r) {
     return PP_OK;
 }
 
-// Input seed ids (already checked) -> stored ids in the pinned list, then
-// its copy to the device seed list, both ordered on the run's stream.
-int send_host_seeds(pp_run r, const int32_t *seeds) {
+int reset_run(pp_run r, const int32_t *seeds, const int32_t *map);
+
+// Host seeds (already checked): input ids -> stored ids in the pinned list
+// (once the initialisation that read the last list has run), then the
+// initialisation, which reads the list in place; the event marks when it has.
+int reset_with_host_seeds(pp_run r, const int32_t *seeds) {
     const int64_t total = (int64_t)r->G * r->s;
-    HIP_TRY(hipEventSynchronize(r->seeds_sent));   // the last list has been read
+    HIP_TRY(hipEventSynchronize(r->seeds_sent));
     const std::vector<int32_t> &perm = r->g->perm;
     for (int64_t j = 0; j < total; ++j) r->h_seeds[j] = perm.empty() ? seeds[j] : perm[(size_t)seeds[j]];
-    HIP_TRY(hipMemcpyAsync(r->dseeds, r->h_seeds, sizeof(int32_t) * (size_t)total, hipMemcpyHostToDevice, r->stream));
+    int rc = reset_run(r, r->h_seeds_dev, nullptr);
+    if (rc) return rc;
     HIP_TRY(hipEventRecord(r->seeds_sent, r->stream));
     return PP_OK;
 }
@@ -753,12 +771,9 @@ int send_host_seeds(pp_run r, const int32_t *seeds) {
 int sync_state(pp_run r, int upto) {
     const int nc = r->pgrid ? r->G : 1;
     const int G = r->G;
-    HIP_TRY(hipMemcpyAsync(r->h_ctrl, r->dev.ctrl, sizeof(Ctrl) * (size_t)nc, hipMemcpyDeviceToHost, r->stream));
-    HIP_TRY(hipMemcpyAsync(r->h_D, r->dev.D, sizeof(int32_t) * (size_t)G, hipMemcpyDeviceToHost, r->stream));
     const int rows = std::max(0, std::min({upto, r->cap, r->staged + STAGE_ROWS}) - r->staged);
-    if (rows > 0)
-        HIP_TRY(hipMemcpyAsync(r->h_rows, r->dev.counts + (int64_t)r->staged * G, sizeof(int64_t) * (size_t)rows * G,
-                               hipMemcpyDeviceToHost, r->stream));
+    HIP_TRY(pp::launch_stage(r->dev.ctrl, (int64_t)sizeof(Ctrl) * nc, r->dev.D, G, r->dev.counts + (int64_t)r->staged * G,
+                             (int64_t)rows * G, r->h_ctrl_dev, r->h_D_dev, r->h_rows_dev, r->stream));
     HIP_TRY(hipStreamSynchronize(r->stream));
     r->host_ctrl = r->h_ctrl[0];
     r->cur.assign((size_t)nc, 0);
@@ -826,16 +841,26 @@ int launch_clusters(pp_run r, int max_round) {
 }
 
 // Algorithm 1's initialisation on an allocated run: clear every buffer, place
-// the seed bits (device seeds), run the round-0 commit.  Synchronises.
-int reset_run(pp_run r, const int32_t *dseeds) {
+// the seed bits, run the round-0 commit.  seeds: device-readable input ids,
+// mapped to stored ids by map when it is given (ids outside [0, n) become
+// -1, which the seed placement reports).  The clustered engine synchronises;
+// the per-round engine does not wait.
+int reset_run(pp_run r, const int32_t *seeds, const int32_t *map) {
     pp_graph g = r->g;
     TileSet *ts = run_tiles(r);
     GraphDev gv = graph_view(g, ts);
     hipError_t e = clear_run_dev(g, r->dev, r->stream, !r->acc_clean);
     if (e == hipSuccess) {
         r->acc_clean = true;
-        if (r->pgrid) e = pp::launch_seed_scatter_batch(gv, r->dev, dseeds, r->stream);
-        else e = pp::launch_seed_init(gv, r->dev, dseeds, r->stream);
+        if (r->pgrid) {
+            if (map) {
+                e = pp::launch_map_ids(r->dseeds, seeds, map, (int64_t)r->G * r->s, g->n, r->stream);
+                seeds = r->dseeds;
+            }
+            if (e == hipSuccess) e = pp::launch_seed_scatter_batch(gv, r->dev, seeds, r->stream);
+        } else {
+            e = pp::launch_seed_init(gv, r->dev, seeds, map, r->stream);
+        }
     }
     if (e != hipSuccess) return fail(PP_EDEVICE, "seed initialisation: %s", hipGetErrorString(e));
     r->staged = 0;
@@ -1019,11 +1044,7 @@ extern "C" int pp_seeds_init(pp_graph g, const int32_t *seeds, int32_t s, const 
         free_run(r);
         return fail(PP_EDEVICE, "cost-model reset: %s", hipGetErrorString(e));
     }
-    if ((rc = alloc_staging(r)) != PP_OK || (rc = send_host_seeds(r, seeds)) != PP_OK) {
-        free_run(r);
-        return rc;
-    }
-    if ((rc = reset_run(r, r->dseeds)) != PP_OK) {
+    if ((rc = alloc_staging(r)) != PP_OK || (rc = reset_with_host_seeds(r, seeds)) != PP_OK) {
         free_run(r);
         return rc;
     }
@@ -1033,19 +1054,12 @@ extern "C" int pp_seeds_init(pp_graph g, const int32_t *seeds, int32_t s, const 
 
 extern "C" int pp_seeds_reset(pp_run r, const int32_t *seeds, int32_t seeds_on_device) {
     if (!r || !seeds) return fail(PP_EINVAL, "run or seeds is NULL");
-    const int64_t total = (int64_t)r->G * r->s;
     if (!seeds_on_device) {
         int rc = check_host_seeds(r->g, seeds, r->s);
         if (rc) return rc;
-        if ((rc = send_host_seeds(r, seeds))) return rc;
-        return reset_run(r, r->dseeds);
+        return reset_with_host_seeds(r, seeds);
     }
-    if (r->g->perm_d) {
-        // ids outside [0, n) become -1, which the seed placement reports
-        HIP_TRY(pp::launch_map_ids(r->dseeds, seeds, r->g->perm_d, total, r->g->n, r->stream));
-        return reset_run(r, r->dseeds);
-    }
-    return reset_run(r, seeds);
+    return reset_run(r, seeds, r->g->perm_d);
 }
 
 extern "C" void pp_run_free(pp_run r) { free_run(r); }

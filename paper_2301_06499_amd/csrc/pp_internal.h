@@ -91,6 +91,8 @@ struct Ctrl {
     float feat[8];        // scheduler features of the round about to run
 };
 
+static_assert(sizeof(Ctrl) % 4 == 0, "the control block is staged to the host as 32-bit words");
+
 // Counters of the closing launch's two-level ticket: TICKET_GROUP group
 // counters, each on its own 128-byte line, then the top counter (launches of
 // at most TICKET_GROUP^2 blocks).
@@ -207,9 +209,13 @@ hipError_t launch_fills(const FillSeg *segs, int nseg, hipStream_t st);
 hipError_t launch_map_ids(int32_t *out, const int32_t *in, const int32_t *perm, int64_t count, int64_t n,
                           hipStream_t st);
 // dst row x = src row perm[x], rows of W words.
+hipError_t launch_stage(const void *ctrl, int64_t ctrl_bytes, const int32_t *D, int64_t nD, const int64_t *rows,
+                        int64_t nrows, void *h_ctrl, int32_t *h_D, int64_t *h_rows, hipStream_t st);
 hipError_t launch_gather_rows(uint64_t *dst, const uint64_t *src, const int32_t *perm, int64_t n, int W,
                               hipStream_t st);
-hipError_t launch_seed_init(const GraphDev &g, const RunDev &r, const int32_t *seeds_dev, hipStream_t st);
+// seeds: device-readable ids; map (may be NULL): input id -> stored id.
+hipError_t launch_seed_init(const GraphDev &g, const RunDev &r, const int32_t *seeds, const int32_t *map,
+                            hipStream_t st);
 // One round; when e0/e1 are given they are recorded around the pull launch.
 hipError_t launch_round(const GraphDev &g, const RunDev &r, hipStream_t st, hipEvent_t e0 = nullptr,
                         hipEvent_t e1 = nullptr);

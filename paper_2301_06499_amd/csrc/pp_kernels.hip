@@ -377,6 +377,27 @@ __global__ void __launch_bounds__(BLOCK) k_gather_rows(uint64_t *dst, const uint
     }
 }
 
+// The host's view of a run in one launch: control blocks and D (as 32-bit
+// words) and a range of count rows, stored straight into pinned host memory
+// (coherent, mapped), which the host reads after waiting on the stream.
+__global__ void k_stage(const int32_t *ctrl, int64_t nctrl, const int32_t *D, int64_t nD, const int64_t *rows,
+                        int64_t nrows, int32_t *h_ctrl, int32_t *h_D, int64_t *h_rows) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nctrl + nD + nrows; i += stride) {
+        if (i < nctrl) h_ctrl[i] = ctrl[i];
+        else if (i < nctrl + nD) h_D[i - nctrl] = D[i - nctrl];
+        else h_rows[i - nctrl - nD] = rows[i - nctrl - nD];
+    }
+}
+
+hipError_t launch_stage(const void *ctrl, int64_t ctrl_bytes, const int32_t *D, int64_t nD, const int64_t *rows,
+                        int64_t nrows, void *h_ctrl, int32_t *h_D, int64_t *h_rows, hipStream_t st) {
+    const int64_t nctrl = ctrl_bytes / 4;
+    hipLaunchKernelGGL(k_stage, dim3(fill_grid(nctrl + nD + nrows)), dim3(BLOCK), 0, st, (const int32_t *)ctrl, nctrl,
+                       D, nD, rows, nrows, (int32_t *)h_ctrl, h_D, h_rows);
+    return hipGetLastError();
+}
+
 hipError_t launch_gather_rows(uint64_t *dst, const uint64_t *src, const int32_t *perm, int64_t n, int W,
                               hipStream_t st) {
     if (n <= 0) return hipSuccess;
@@ -390,12 +411,15 @@ hipError_t launch_gather_rows(uint64_t *dst, const uint64_t *src, const int32_t 
 // initialisation).  Bits are gathered in the accumulator first so that a node
 // holding several seeds is listed once; the round-0 commit writes them.  A
 // seed outside its graph's node range is skipped and flagged.
+// map (may be NULL): input id -> stored id for ids in [0, n), -1 otherwise.
 template <int W>
-__global__ void __launch_bounds__(BLOCK) k_seed_scatter(GraphDev g, RunDev R, const int32_t *seeds, int64_t total) {
-    for (int64_t j = blockIdx.x * (int64_t)BLOCK + threadIdx.x; j < total; j += (int64_t)gridDim.x * BLOCK) {
+PP_DEV void phase_seed_scatter(const GraphDev &g, const RunDev &R, const int32_t *seeds, const int32_t *map,
+                               int64_t total, int bid, int nb) {
+    for (int64_t j = bid * (int64_t)BLOCK + threadIdx.x; j < total; j += (int64_t)nb * BLOCK) {
         const int i = (int)(j % R.s);
         const int gi = (int)(j / R.s);
-        const int32_t x = seeds[j];
+        int32_t x = seeds[j];
+        if (map) x = (x >= 0 && x < g.n) ? map[x] : -1;
         const bool ok = x >= g.node_off[gi] && x < g.node_off[gi + 1];
         if (!ok) atomicOr(&R.ctrl->bad_seed, 1);
         if (ok) atomicOr((unsigned long long *)&R.acc[(int64_t)x * W + (i >> 6)], 1ull << (i & 63));
@@ -403,6 +427,11 @@ __global__ void __launch_bounds__(BLOCK) k_seed_scatter(GraphDev g, RunDev R, co
         const int pos = wave_append(&R.ctrl->lst[0].nodes, want);
         if (want) R.f_ids[0][pos] = x;
     }
+}
+template <int W>
+__global__ void __launch_bounds__(BLOCK) k_seed_scatter(GraphDev g, RunDev R, const int32_t *seeds,
+                                                        const int32_t *map, int64_t total) {
+    phase_seed_scatter<W>(g, R, seeds, map, total, blockIdx.x, gridDim.x);
 }
 
 // ---------------------------------------------------------------- list commit
@@ -1288,6 +1317,19 @@ __global__ void __launch_bounds__(BLOCK) k_round_end(GraphDev g, RunDev R, int i
     if (R.ctrl->converged) return;
     phase_round_end(g, R, init, g.pull_grid);
 }
+// Algorithm 1's initialisation for a short seed list in one block: the seed
+// bits, the round-0 commit and the round's end, one after the other (the
+// block's barriers order them; its global writes are visible to its own
+// threads after a barrier).
+template <int W>
+__global__ void __launch_bounds__(BLOCK) k_seed_init(GraphDev g, RunDev R, const int32_t *seeds, const int32_t *map,
+                                                     int64_t total) {
+    phase_seed_scatter<W>(g, R, seeds, map, total, 0, 1);
+    __syncthreads();
+    phase_push_commit<W>(g, R, 1, 0, 1);
+    __syncthreads();
+    phase_round_end(g, R, 1, g.pull_grid);
+}
 
 // Two-level ticket (one thread per block): true for the block that finishes
 // last.  Blocks count off in groups of TICKET_GROUP, each group on its own
@@ -1547,9 +1589,18 @@ static int post_grid(const GraphDev &g) {
     return (int)(b < 64 ? 64 : (b > POST_MAX ? POST_MAX : b));
 }
 
-template <int W> static hipError_t seed_init_impl(const GraphDev &g, const RunDev &R, const int32_t *seeds, hipStream_t st) {
+// seed lists up to this length initialise in one single-block launch
+constexpr int64_t SEED_INIT_ONE_BLOCK = 4096;
+
+template <int W>
+static hipError_t seed_init_impl(const GraphDev &g, const RunDev &R, const int32_t *seeds, const int32_t *map,
+                                 hipStream_t st) {
     const int64_t total = (int64_t)R.G * R.s;
-    hipLaunchKernelGGL(k_seed_scatter<W>, dim3(fill_grid(total)), dim3(BLOCK), 0, st, g, R, seeds, total);
+    if (total <= SEED_INIT_ONE_BLOCK) {
+        hipLaunchKernelGGL(k_seed_init<W>, dim3(1), dim3(BLOCK), 0, st, g, R, seeds, map, total);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL(k_seed_scatter<W>, dim3(fill_grid(total)), dim3(BLOCK), 0, st, g, R, seeds, map, total);
     hipLaunchKernelGGL(k_push_commit<W>, dim3(fill_grid(total * W)), dim3(BLOCK), 0, st, g, R, 1);
     hipLaunchKernelGGL(k_round_end, dim3(1), dim3(BLOCK), 0, st, g, R, 1);
     return hipGetLastError();
@@ -1572,12 +1623,13 @@ static hipError_t round_impl(const GraphDev &g, const RunDev &R, hipStream_t st,
     return hipGetLastError();
 }
 
-hipError_t launch_seed_init(const GraphDev &g, const RunDev &R, const int32_t *seeds, hipStream_t st) {
+hipError_t launch_seed_init(const GraphDev &g, const RunDev &R, const int32_t *seeds, const int32_t *map,
+                            hipStream_t st) {
     switch (R.W) {
-        case 1: return seed_init_impl<1>(g, R, seeds, st);
-        case 2: return seed_init_impl<2>(g, R, seeds, st);
-        case 4: return seed_init_impl<4>(g, R, seeds, st);
-        case 8: return seed_init_impl<8>(g, R, seeds, st);
+        case 1: return seed_init_impl<1>(g, R, seeds, map, st);
+        case 2: return seed_init_impl<2>(g, R, seeds, map, st);
+        case 4: return seed_init_impl<4>(g, R, seeds, map, st);
+        case 8: return seed_init_impl<8>(g, R, seeds, map, st);
         default: return hipErrorInvalidValue;
     }
 }
