@@ -31,7 +31,11 @@ struct Chunk {
 
 constexpr int BLOCK = 256;       // threads per block of every bulk kernel
 constexpr int TILE_NODES = 64;   // node budget of a pull tile (one wave)
+constexpr int PUSH_SLOTS = 4;    // predecessor slots per entry in a small push
 constexpr int PUSH_LIGHT = 16;   // entries with more predecessors go through chunks
+// frontier entries from which a push walks flattened arc ranges and reads
+// predecessor words before its atomics (below: latency-bound, direct slots)
+constexpr int PUSH_FILTER_MIN = 16384;
 constexpr int PUSH_CHUNK_MIN = 32;   // smallest chunk (W = 8)
 #ifndef PP_PULL_GRID_MAX
 #define PP_PULL_GRID_MAX 2048

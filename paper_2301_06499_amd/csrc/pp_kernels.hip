@@ -526,7 +526,9 @@ PP_DEV void commit_items(const GraphDev &g, const RunDev &R, int init, int r, in
 // parts (the closing launch): the block's new-bit count and predecessor arcs
 // go to its slots of the per-block partials instead of the round's
 // counters, which the round's end then sums.
-template <int W>
+// UMAX: at most this many items per thread and pass (1 keeps the LDS and
+// registers small, for the persistent kernel).
+template <int W, int UMAX = 4>
 PP_DEV void phase_push_commit(const GraphDev &g, const RunDev &R, int init, int bid, int nb, int64_t *parts = nullptr) {
     Ctrl *C = R.ctrl;
     const int r = init ? 0 : CTL(C->round);
@@ -540,7 +542,7 @@ PP_DEV void phase_push_commit(const GraphDev &g, const RunDev &R, int init, int 
 #pragma unroll
     for (int k = 0; k < W; ++k) sc[k] = 0;
     // long lists: four items per thread and pass
-    if (items > 2 * (int64_t)nb * BLOCK) commit_items<W, 4>(g, R, init, r, p, items, bid, nb, pop, arcs, sc);
+    if (UMAX >= 4 && items > 2 * (int64_t)nb * BLOCK) commit_items<W, 4>(g, R, init, r, p, items, bid, nb, pop, arcs, sc);
     else commit_items<W, 1>(g, R, init, r, p, items, bid, nb, pop, arcs, sc);
     __shared__ unsigned long long s_red[BLOCK / 64];
     const unsigned long long tp = block_sum<unsigned long long>(pop, s_red);
@@ -971,19 +973,20 @@ PP_DEV void phase_frontier(const GraphDev &g, const RunDev &R, int bid, int nb) 
 // that gained a bit are queued once per round (stamp).
 template <int W, int IT>
 PP_DEV void push_slots(const RunDev &R, uint64_t *sig, int r, const int64_t (&k)[IT], const bool (&kv)[IT],
-                       const int32_t *tcol, int w, const uint64_t (&d)[IT], BlockQueue &bq, Ctrl *C, int pn) {
+                       const int32_t *tcol, int w, const uint64_t (&d)[IT], BlockQueue &bq, Ctrl *C, int pn,
+                       bool filter) {
     int32_t u[IT];
 #pragma unroll
     for (int it = 0; it < IT; ++it) u[it] = kv[it] ? tcol[k[it]] : 0;
-    // a plain read first: bits only ever get set, so a bit seen set (even in
-    // a stale copy) needs no atomic, and most pushes of a late round bring
-    // nothing new
+    // filter: a plain read first -- bits only ever get set, so a bit seen set
+    // (even in a stale copy) needs no atomic, and most pushes of a late round
+    // bring nothing new; a small push, bound by latency, skips the read
     uint64_t seen[IT];
 #pragma unroll
     for (int it = 0; it < IT; ++it)
-        seen[it] = (kv[it] && d[it]) ? __hip_atomic_load(&sig[(int64_t)u[it] * W + w], __ATOMIC_RELAXED,
+        seen[it] = (filter && kv[it] && d[it]) ? __hip_atomic_load(&sig[(int64_t)u[it] * W + w], __ATOMIC_RELAXED,
                                                          __HIP_MEMORY_SCOPE_WORKGROUP)
-                                     : ~0ull;
+                                     : 0ull;
     uint64_t nb[IT];
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
@@ -1009,7 +1012,9 @@ PP_DEV void push_slots(const RunDev &R, uint64_t *sig, int r, const int64_t (&k)
     for (int it = 0; it < IT; ++it) bq.push(want[it], u[it], &C->lst[pn].nodes, sel(R.f_ids, pn));
 }
 
-template <int W>
+// FLAT: large frontiers take the flattened, read-first path (false keeps
+// only the direct path, with fewer registers, for the persistent kernel).
+template <int W, bool FLAT = true>
 PP_DEV void phase_push(const GraphDev &g, const RunDev &R, int bid, int nb) {
     Ctrl *C = R.ctrl;
     const int r = CTL(C->round);
@@ -1017,6 +1022,7 @@ PP_DEV void phase_push(const GraphDev &g, const RunDev &R, int bid, int nb) {
     uint64_t *sig = sel(R.sig, CTL(C->cur));
     const int32_t cnt = CTL(C->lst[pp].nodes);
     const int32_t nch = CTL(C->lst[pp].chunks);
+    const bool filter = FLAT && cnt >= PUSH_FILTER_MIN;
     const int32_t *ids = sel(R.f_ids, pp);
     const uint64_t *dl = sel(R.f_delta, pp);
     const int ln = lane_id();
@@ -1029,50 +1035,83 @@ PP_DEV void phase_push(const GraphDev &g, const RunDev &R, int bid, int nb) {
     if (threadIdx.x == 0) s_qn = 0;
     __syncthreads();
 
-    // light entries (at most PUSH_LIGHT predecessors): a wave takes G = 64/W
-    // entries at a time, one per group of W lanes, and walks their arcs as
-    // one flat range (an exclusive scan of the entries' degrees), one arc per
-    // group per step, so short lists leave no lane idle; a group finds the
-    // entry of its arc by binary search over the scan held in the lanes
-    {
-        constexpr int G = 64 / W;
-        constexpr int IT = 4;
-        const int grp = ln / W;
-        for (int64_t e0 = wave * G; e0 < cnt; e0 += nwaves * G) {   // wave-uniform
+    // light entries (at most PUSH_LIGHT predecessors)
+    if (FLAT && filter) {
+        // light entries (at most PUSH_LIGHT predecessors): a wave takes G = 64/W
+        // entries at a time, one per group of W lanes, and walks their arcs as
+        // one flat range (an exclusive scan of the entries' degrees), one arc per
+        // group per step, so short lists leave no lane idle; a group finds the
+        // entry of its arc by binary search over the scan held in the lanes
+        {
+            constexpr int G = 64 / W;
+            constexpr int IT = 4;
+            const int grp = ln / W;
+            for (int64_t e0 = wave * G; e0 < cnt; e0 += nwaves * G) {   // wave-uniform
+                const int64_t e = e0 + grp;
+                int64_t b = 0;
+                int deg = 0;
+                uint64_t d = 0;
+                if (e < cnt) {
+                    const int32_t v = ids[e];
+                    b = g.trp[v];
+                    const int64_t len = g.trp[v + 1] - b;
+                    deg = len <= PUSH_LIGHT ? (int)len : 0;   // long lists go through chunks
+                    d = dl[e * W + w];
+                }
+                const int contrib = w == 0 ? deg : 0;
+                const int incl = wave_inclusive_scan(contrib);
+                const int start = __shfl(incl - contrib, grp * W);   // the group's first flat arc
+                const int total = __shfl(incl, 63);
+                for (int a0 = 0; a0 < total; a0 += G * IT) {   // wave-uniform
+                    int64_t k[IT];
+                    bool kv[IT];
+                    uint64_t dd[IT];
+    #pragma unroll
+                    for (int it = 0; it < IT; ++it) {
+                        const int a = a0 + it * G + grp;
+                        int lo = 0;   // the last group whose first flat arc is <= a
+    #pragma unroll
+                        for (int step = G >> 1; step > 0; step >>= 1)   // lo + step stays below G
+                            if (__shfl(start, (lo + step) * W) <= a) lo += step;
+                        const int so = __shfl(start, lo * W);
+                        const int64_t bo = __shfl(b, lo * W);
+                        dd[it] = __shfl(d, lo * W + w);
+                        kv[it] = a < total;
+                        k[it] = bo + (a - so);
+                    }
+                    push_slots<W, IT>(R, sig, r, k, kv, g.tcol, w, dd, bq, C, pn, filter);
+                }
+            }
+        }
+    } else {
+        // a small frontier, bound by latency: PUSH_SLOTS slots of W lanes per
+        // entry walk its list directly (no scan, no search)
+        constexpr int L = W * PUSH_SLOTS;
+        constexpr int GPW = 64 / L;
+        constexpr int IT = PUSH_LIGHT / PUSH_SLOTS;
+        const int grp = ln / L, slot = (ln % L) / W;
+        for (int64_t e0 = wave * GPW; e0 < cnt; e0 += nwaves * GPW) {   // wave-uniform
             const int64_t e = e0 + grp;
-            int64_t b = 0;
-            int deg = 0;
+            bool ev = e < cnt;
+            int64_t b = 0, end = 0;
             uint64_t d = 0;
-            if (e < cnt) {
+            if (ev) {
                 const int32_t v = ids[e];
                 b = g.trp[v];
-                const int64_t len = g.trp[v + 1] - b;
-                deg = len <= PUSH_LIGHT ? (int)len : 0;   // long lists go through chunks
+                end = g.trp[v + 1];
+                ev = end - b <= PUSH_LIGHT;
                 d = dl[e * W + w];
             }
-            const int contrib = w == 0 ? deg : 0;
-            const int incl = wave_inclusive_scan(contrib);
-            const int start = __shfl(incl - contrib, grp * W);   // the group's first flat arc
-            const int total = __shfl(incl, 63);
-            for (int a0 = 0; a0 < total; a0 += G * IT) {   // wave-uniform
-                int64_t k[IT];
-                bool kv[IT];
-                uint64_t dd[IT];
+            int64_t k[IT];
+            bool kv[IT];
+            uint64_t dd[IT];
 #pragma unroll
-                for (int it = 0; it < IT; ++it) {
-                    const int a = a0 + it * G + grp;
-                    int lo = 0;   // the last group whose first flat arc is <= a
-#pragma unroll
-                    for (int step = G >> 1; step > 0; step >>= 1)   // lo + step stays below G
-                        if (__shfl(start, (lo + step) * W) <= a) lo += step;
-                    const int so = __shfl(start, lo * W);
-                    const int64_t bo = __shfl(b, lo * W);
-                    dd[it] = __shfl(d, lo * W + w);
-                    kv[it] = a < total;
-                    k[it] = bo + (a - so);
-                }
-                push_slots<W, IT>(R, sig, r, k, kv, g.tcol, w, dd, bq, C, pn);
+            for (int it = 0; it < IT; ++it) {
+                k[it] = b + slot + it * PUSH_SLOTS;
+                kv[it] = ev && k[it] < end;
+                dd[it] = d;
             }
+            push_slots<W, IT>(R, sig, r, k, kv, g.tcol, w, dd, bq, C, pn, false);
         }
     }
     // long lists: chunks of CHUNK arcs, one wave each
@@ -1097,7 +1136,7 @@ PP_DEV void phase_push(const GraphDev &g, const RunDev &R, int bid, int nb) {
                 kv[it] = k[it] < end;
                 dd[it] = d;
             }
-            push_slots<W, IT>(R, sig, r, k, kv, g.tcol, w, dd, bq, C, pn);
+            push_slots<W, IT>(R, sig, r, k, kv, g.tcol, w, dd, bq, C, pn, filter);
         }
     }
     bq.flush(&C->lst[pn].nodes, sel(R.f_ids, pn), &s_qbase);
@@ -1507,7 +1546,7 @@ __global__ void __launch_bounds__(BLOCK) k_batch(GraphDev g, RunDev R, const Clu
     GridBar *bar = rv.bar;
     const bool lead = bid == 0 && threadIdx.x == 0;
     if (CTL(C->round) == 0 && !CTL(C->converged)) {
-        phase_push_commit<W>(gv, rv, 1, bid, nb);
+        phase_push_commit<W, 1>(gv, rv, 1, bid, nb);
         if (!cluster_barrier(bar, bid, nb)) return;
         if (bid == 0) phase_round_end(gv, rv, 1, nb);
         if (!cluster_barrier(bar, bid, nb)) return;
@@ -1522,13 +1561,13 @@ __global__ void __launch_bounds__(BLOCK) k_batch(GraphDev g, RunDev R, const Clu
         if (lead && stamp) stamp[0] = (int64_t)wall_clock64();
         if (mode == MODE_PUSH) {
             if (prev == MODE_PULL) {
-                phase_frontier<W>(gv, rv, bid, nb);
+                phase_frontier<W, 256>(gv, rv, bid, nb);
                 if (!cluster_barrier(bar, bid, nb)) break;
             }
-            phase_push<W>(gv, rv, bid, nb);
+            phase_push<W, false>(gv, rv, bid, nb);
             if (!cluster_barrier(bar, bid, nb)) break;
             if (lead && stamp) stamp[1] = (int64_t)wall_clock64();
-            phase_push_commit<W>(gv, rv, 0, bid, nb);
+            phase_push_commit<W, 1>(gv, rv, 0, bid, nb);
             if (!cluster_barrier(bar, bid, nb)) break;
         } else {
             phase_pull<W>(gv, rv, bid, nb);
