@@ -20,6 +20,9 @@ Contents
                     small graphs.
 ``brute_force_counts``  all-pairs distances by repeated boolean matrix
                     products, for tiny graphs.
+``propagate_s``     (module ``oracle.propagate_s``) Algorithm 2, PROPAGATE-S:
+                    one seed at a time with one bit per node and the early
+                    break, pure Python, for small graphs.
 
 Parity pins for each function live in ``tests/test_oracle_*.py``.  The
 interpolated effective diameter has no printed worked value in the paper:
