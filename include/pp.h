@@ -314,6 +314,31 @@ int pp_mlp_train(float *params, const float *x, const float *t, int64_t n, int32
 int pp_exact_counts(pp_graph g, int32_t group, const pp_options *opt, int64_t *counts, int32_t cap_rounds,
                     int32_t *D);
 
+/*
+ * pp_propagate_s -- PROPAGATE-S (Algorithm 2): the seeds one at a time with
+ * one bit per node, each pass a synchronous bottom-up step in which a node
+ * not reached yet stops at its first reached successor (the early break).
+ * Same counts as PROPAGATE-P for the same seeds, in O(n) bits per seed
+ * instead of O(n s) for all of them.
+ *   seeds      host [s] input node ids, checked (PP_ERANGE if outside [0, n));
+ *              duplicates count once each, as seed bits do in PROPAGATE-P.
+ *   concurrent seeds in flight at once (0: min(s, 256)); device memory is
+ *              2 x concurrent x ceil(n/64) x 8 bytes of signatures plus
+ *              concurrent x cap_rounds x 8 bytes of counts, allocated here
+ *              and freed before return.
+ *   stream     hipStream_t or NULL (the graph's stream); synchronous.
+ *   counts     host [cap_rounds], zeroed first: counts[r] = pairs (u, x_i)
+ *              with d(u, x_i) = r, counts[0] = s.
+ *   D          host, the largest r with counts[r] > 0.
+ *   examined   host or NULL: arcs examined over all passes and seeds, each
+ *              node's walk counted up to and including its first hit (the
+ *              work the early break leaves).
+ * One graph only (PP_EINVAL for a batch).  PP_ENOTCONV if a seed still finds
+ * nodes at pass cap_rounds - 1 (counts then hold the passes that fit).
+ */
+int pp_propagate_s(pp_graph g, const int32_t *seeds, int32_t s, int32_t concurrent, void *stream, int64_t *counts,
+                   int32_t cap_rounds, int32_t *D, int64_t *examined);
+
 /* One configuration tried by pp_autotune and its best time. */
 typedef struct {
     int32_t pull_k, push_div, rounds_per_sync, persistent;

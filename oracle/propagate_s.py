@@ -28,8 +28,12 @@ from __future__ import annotations
 import numpy as np
 
 
-def successor_lists(n, src, dst, undirected, transpose=False):
-    """Arc lists of the propagation direction: u takes Sig(v) for an arc u -> v."""
+def successor_lists(n, src, dst, undirected, transpose=False, stored=False):
+    """Arc lists of the propagation direction: u takes Sig(v) for an arc u -> v.
+
+    stored: the arc set a graph library would store -- self-loops dropped,
+    duplicates merged, each list in increasing node order -- which fixes the
+    order the early break sees (the counts do not depend on it)."""
     succ = [[] for _ in range(int(n))]
     pairs = list(zip(np.asarray(src, dtype=np.int64).tolist(), np.asarray(dst, dtype=np.int64).tolist()))
     if undirected:
@@ -38,13 +42,15 @@ def successor_lists(n, src, dst, undirected, transpose=False):
         if transpose:
             u, v = v, u
         succ[u].append(v)
+    if stored:
+        succ = [sorted(set(v for v in lst if v != u)) for u, lst in enumerate(succ)]
     return succ
 
 
-def propagate_s(n, src, dst, seeds, undirected, transpose=False):
+def propagate_s(n, src, dst, seeds, undirected, transpose=False, stored=False):
     """(CountAll [D_LB + 1] int64, D_LB, arcs examined) by Algorithm 2, pure Python (small graphs only)."""
     n = int(n)
-    succ = successor_lists(n, src, dst, undirected, transpose)
+    succ = successor_lists(n, src, dst, undirected, transpose, stored)
     seeds = [int(x) for x in np.asarray(seeds).tolist()]
     count_all = [len(seeds)]
     d_lb = 0

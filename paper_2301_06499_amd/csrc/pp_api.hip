@@ -1561,3 +1561,90 @@ extern "C" int pp_exact_counts(pp_graph g, int32_t group, const pp_options *opt,
     if (D) *D = dmax;
     return dmax >= cap_rounds ? fail(PP_ERANGE, "D = %d does not fit cap_rounds = %d", dmax, cap_rounds) : PP_OK;
 }
+
+// PROPAGATE-S: batches of `concurrent` seeds, each run to its last seed's
+// first pass without a find; the host checks every 8 passes.
+extern "C" int pp_propagate_s(pp_graph g, const int32_t *seeds, int32_t s, int32_t concurrent, void *stream,
+                              int64_t *counts, int32_t cap_rounds, int32_t *D, int64_t *examined) {
+    if (!g || !seeds || !counts || !D) return fail(PP_EINVAL, "graph, seeds, counts or D is NULL");
+    if (g->G != 1) return fail(PP_EINVAL, "one graph only (got a batch of %d)", g->G);
+    if (s < 1) return fail(PP_EINVAL, "s < 1");
+    if (concurrent < 0) return fail(PP_EINVAL, "concurrent < 0");
+    if (cap_rounds < 1) return fail(PP_EINVAL, "cap_rounds < 1");
+    int rc = check_host_seeds(g, seeds, s);
+    if (rc) return rc;
+    // seeds in flight: one grid row each (at most 65535)
+    const int k = std::min({concurrent > 0 ? concurrent : 256, s, 65535});
+    const int64_t n = g->n, nw = (n + 63) / 64, cap = cap_rounds;
+    hipStream_t st = stream ? (hipStream_t)stream : g->stream;
+    pp::SeqDev S{};
+    S.k = k;
+    S.cap = cap_rounds;
+    S.nw = nw;
+    int32_t *dseeds = nullptr;
+    auto release = [&]() {
+        dev_free(S.bits);
+        dev_free(S.cnt);
+        dev_free(S.examined);
+        dev_free(S.done);
+        dev_free(S.dpass);
+        dev_free(S.active);
+        dev_free(dseeds);
+    };
+    if ((rc = dev_alloc(&S.bits, 2 * k * nw)) || (rc = dev_alloc(&S.cnt, k * cap)) ||
+        (rc = dev_alloc(&S.examined, k)) || (rc = dev_alloc(&S.done, k)) || (rc = dev_alloc(&S.dpass, k)) ||
+        (rc = dev_alloc(&S.active, 1)) || (rc = dev_alloc(&dseeds, k))) {
+        release();
+        return rc;
+    }
+    std::memset(counts, 0, sizeof(int64_t) * (size_t)cap);
+    counts[0] = s;
+    int32_t dmax = 0;
+    int64_t ex_total = 0;
+    bool overflow = false;
+    const GraphDev gv = graph_view(g, nullptr);
+    // about 16 Ki waves in all, at least one block per seed, at most one wave per word
+    const int64_t want = (16384 / 4 + k - 1) / k, most = (nw + 3) / 4;
+    const int bps = (int)std::max<int64_t>(1, std::min(want, most));
+    std::vector<int32_t> hs((size_t)k), hd((size_t)k), hdone((size_t)k);
+    std::vector<int64_t> hc((size_t)(k * cap)), hx((size_t)k);
+    hipError_t e = hipSuccess;
+    for (int first = 0; first < s && e == hipSuccess; first += k) {
+        const int kk = std::min(k, s - first);
+        for (int i = 0; i < kk; ++i) {
+            const int32_t x = seeds[first + i];
+            hs[(size_t)i] = g->perm.empty() ? x : g->perm[(size_t)x];
+        }
+        e = hipMemcpyAsync(dseeds, hs.data(), sizeof(int32_t) * (size_t)kk, hipMemcpyHostToDevice, st);
+        const pp::FillSeg segs[] = {{(uint32_t *)S.bits, 2 * k * nw, 0u}, {(uint32_t *)S.cnt, 2 * k * cap, 0u}};
+        if (e == hipSuccess) e = pp::launch_fills(segs, 2, st);
+        if (e == hipSuccess) e = pp::launch_seq_seeds(S, dseeds, kk, st);
+        for (int r = 1; r < cap_rounds && e == hipSuccess; ++r) {
+            e = pp::launch_seq_pass(gv, S, r, bps, st);
+            if (e == hipSuccess && (r % 8 == 0 || r == cap_rounds - 1)) {
+                int32_t act = 0;
+                e = hipMemcpyAsync(&act, S.active, sizeof(int32_t), hipMemcpyDeviceToHost, st);
+                if (e == hipSuccess) e = hipStreamSynchronize(st);
+                if (act == 0) break;
+            }
+        }
+        if (e == hipSuccess) e = hipMemcpyAsync(hc.data(), S.cnt, sizeof(int64_t) * (size_t)(kk * cap), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(hx.data(), S.examined, sizeof(int64_t) * (size_t)kk, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(hd.data(), S.dpass, sizeof(int32_t) * (size_t)kk, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(hdone.data(), S.done, sizeof(int32_t) * (size_t)kk, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) break;
+        for (int j = 0; j < kk; ++j) {
+            for (int64_t r = 1; r < cap; ++r) counts[r] += hc[(size_t)(j * cap + r)];
+            dmax = std::max(dmax, hd[(size_t)j]);
+            ex_total += hx[(size_t)j];
+            overflow |= hdone[(size_t)j] == 2;
+        }
+    }
+    release();
+    if (e != hipSuccess) return fail(PP_EDEVICE, "PROPAGATE-S: %s", hipGetErrorString(e));
+    *D = dmax;
+    if (examined) *examined = ex_total;
+    if (overflow) return fail(PP_ENOTCONV, "a seed still found nodes at pass %d", cap_rounds - 1);
+    return PP_OK;
+}

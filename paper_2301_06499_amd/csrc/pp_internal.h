@@ -213,6 +213,21 @@ hipError_t launch_fills(const FillSeg *segs, int nseg, hipStream_t st);
 hipError_t launch_map_ids(int32_t *out, const int32_t *in, const int32_t *perm, int64_t count, int64_t n,
                           hipStream_t st);
 // dst row x = src row perm[x], rows of W words.
+// PROPAGATE-S state for k seeds side by side (see pp_seq.hip).
+struct SeqDev {
+    uint64_t *bits;       // [2][k][nw] signatures, one bit per node
+    int64_t *cnt;         // [k][cap] nodes found at each pass
+    int64_t *examined;    // [k] arcs examined
+    int32_t *done;        // [k] 0 running, 1 done, 2 stopped at the end of the log
+    int32_t *dpass;       // [k] last pass that found a node
+    int32_t *active;      // [1] seeds still running
+    int32_t k, cap;
+    int64_t nw;           // 64-bit words per signature
+};
+hipError_t launch_seq_seeds(const SeqDev &S, const int32_t *seeds, int kk, hipStream_t st);
+// Pass r and its per-seed end.
+hipError_t launch_seq_pass(const GraphDev &g, const SeqDev &S, int r, int blocks_per_seed, hipStream_t st);
+
 hipError_t launch_stage(const void *ctrl, int64_t ctrl_bytes, const int32_t *D, int64_t nD, const int64_t *rows,
                         int64_t nrows, void *h_ctrl, int32_t *h_D, int64_t *h_rows, hipStream_t st);
 hipError_t launch_gather_rows(uint64_t *dst, const uint64_t *src, const int32_t *perm, int64_t n, int W,

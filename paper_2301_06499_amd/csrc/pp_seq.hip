@@ -1,0 +1,174 @@
+// PROPAGATE-S (Algorithm 2) on gfx950 (wave64): the seeds one at a time with
+// one bit per node, k seeds side by side.
+//
+// Each of the k seeds in flight owns a pair of n-bit signatures (node u is
+// bit u & 63 of word u >> 6).  Pass r reads buffer (r-1) & 1 and writes
+// buffer r & 1 in full, so the update is synchronous.  A wave takes a word of
+// 64 nodes of one seed, one node per lane: a node not reached yet walks its
+// successor list and stops at the first successor already reached (the
+// algorithm's early break); one ballot gives the word's new bits.  A lane
+// walks a short list itself, four arcs per step; a list longer than
+// SEQ_LIGHT is walked by the whole wave, 64 arcs per step, up to the first
+// step with a hit.  Each pass counts, per seed, the nodes it found and the
+// arcs it examined (up to and including the first hit of each node); a seed
+// is done at its first pass that finds nothing.
+#include "pp_internal.h"
+
+namespace pp {
+
+#define PS_DEV __device__ __forceinline__
+
+constexpr int SEQ_LIGHT = 32;   // longer successor lists are walked by the whole wave
+
+namespace {
+
+PS_DEV int lane() { return __lane_id(); }
+
+PS_DEV bool reached(const uint64_t *sig, int32_t v) { return (sig[v >> 6] >> (v & 63)) & 1ull; }
+
+PS_DEV uint64_t *buffer(const SeqDev &S, int b, int j) {
+    return S.bits + ((int64_t)(b & 1) * S.k + j) * S.nw;
+}
+
+template <typename T> PS_DEV T block_total(T v, T *scratch) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    __syncthreads();
+    if (lane() == 0) scratch[threadIdx.x >> 6] = v;
+    __syncthreads();
+    T t = 0;
+#pragma unroll
+    for (int w = 0; w < BLOCK / 64; ++w) t += scratch[w];
+    return t;
+}
+
+}  // namespace
+
+// Seed j of the batch (kk of them) starts with its own bit; slots kk..k-1
+// are idle.  Buffer 0 of every slot was cleared before.
+__global__ void __launch_bounds__(BLOCK) k_seq_seeds(SeqDev S, const int32_t *seeds, int kk) {
+    for (int j = blockIdx.x * BLOCK + threadIdx.x; j < S.k; j += gridDim.x * BLOCK) {
+        S.done[j] = j < kk ? 0 : 1;
+        S.dpass[j] = 0;
+        S.examined[j] = 0;
+        if (j < kk) {
+            const int32_t x = seeds[j];
+            buffer(S, 0, j)[x >> 6] |= 1ull << (x & 63);
+        }
+        if (j == 0) S.active[0] = kk;
+    }
+}
+
+// Pass r of every seed still running (grid: blocks per seed x k).
+__global__ void __launch_bounds__(BLOCK) k_seq_pass(GraphDev g, SeqDev S, int r) {
+    const int j = blockIdx.y;
+    if (S.done[j]) return;   // the same for the whole block
+    const uint64_t *cur = buffer(S, r - 1, j);
+    uint64_t *nxt = buffer(S, r, j);
+    const int ln = lane();
+    const int64_t wave = (int64_t)blockIdx.x * (BLOCK / 64) + (threadIdx.x >> 6);
+    const int64_t nwaves = (int64_t)gridDim.x * (BLOCK / 64);
+    int64_t found = 0, exam = 0;
+    for (int64_t wd = wave; wd < S.nw; wd += nwaves) {   // wave-uniform
+        const uint64_t word = cur[wd];
+        const int64_t u = wd * 64 + ln;
+        const bool open = u < g.n && !((word >> ln) & 1ull);
+        int64_t b = 0, e = 0;
+        if (open) {
+            b = g.rp[u];
+            e = g.rp[u + 1];
+        }
+        bool hit = false;
+        if (open && e - b <= SEQ_LIGHT) {
+            // the lane's own list, four arcs in flight per step
+            for (int64_t a = b; a < e && !hit; a += 4) {
+                int32_t v[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) v[q] = a + q < e ? g.col[a + q] : -1;
+                bool t[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) t[q] = v[q] >= 0 && reached(cur, v[q]);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    if (!hit && v[q] >= 0) {
+                        ++exam;
+                        hit = t[q];
+                    }
+                }
+            }
+        }
+        // long lists, one node at a time across the wave
+        uint64_t heavy = __ballot(open && e - b > SEQ_LIGHT);
+        while (heavy) {   // wave-uniform
+            const int h = __ffsll((long long)heavy) - 1;
+            heavy &= heavy - 1;
+            const int64_t hb = __shfl(b, h), he = __shfl(e, h);
+            bool hh = false;
+            int64_t hx = 0;
+            for (int64_t a0 = hb; a0 < he; a0 += 64) {   // wave-uniform
+                const int64_t a = a0 + ln;
+                const bool t = a < he && reached(cur, g.col[a]);
+                const uint64_t m = __ballot(t);
+                if (m) {
+                    hh = true;
+                    hx += __ffsll((long long)m);   // the arcs up to the first hit
+                    break;
+                }
+                hx += he - a0 < 64 ? he - a0 : 64;
+            }
+            if (ln == h) {
+                hit = hh;
+                exam += hx;
+            }
+        }
+        const uint64_t nb = __ballot(hit);
+        if (ln == 0) {
+            nxt[wd] = word | nb;
+            found += __popcll(nb);
+        }
+    }
+    __shared__ long long s_red[BLOCK / 64];
+    const long long tf = block_total<long long>(found, s_red);
+    const long long te = block_total<long long>(exam, s_red);
+    if (threadIdx.x == 0) {
+        if (tf) atomicAdd((unsigned long long *)&S.cnt[(int64_t)j * S.cap + r], (unsigned long long)tf);
+        if (te) atomicAdd((unsigned long long *)&S.examined[j], (unsigned long long)te);
+    }
+}
+
+// After pass r: a seed whose pass found nothing is done; otherwise r is its
+// last pass so far with a find.  A seed still running at the last pass the
+// log holds is stopped and counted as not converged.
+__global__ void __launch_bounds__(BLOCK) k_seq_end(SeqDev S, int r) {
+    for (int j = blockIdx.x * BLOCK + threadIdx.x; j < S.k; j += gridDim.x * BLOCK) {
+        if (S.done[j]) continue;
+        if (S.cnt[(int64_t)j * S.cap + r] == 0) {
+            S.done[j] = 1;
+            atomicSub(S.active, 1);
+        } else {
+            S.dpass[j] = r;
+            if (r + 1 >= S.cap) {
+                S.done[j] = 2;
+                atomicSub(S.active, 1);
+            }
+        }
+    }
+}
+
+static int small_grid(int64_t items) {
+    const int64_t b = (items + BLOCK - 1) / BLOCK;
+    return (int)(b < 1 ? 1 : (b > 1024 ? 1024 : b));
+}
+
+hipError_t launch_seq_seeds(const SeqDev &S, const int32_t *seeds, int kk, hipStream_t st) {
+    hipLaunchKernelGGL(k_seq_seeds, dim3(small_grid(S.k)), dim3(BLOCK), 0, st, S, seeds, kk);
+    return hipGetLastError();
+}
+
+hipError_t launch_seq_pass(const GraphDev &g, const SeqDev &S, int r, int blocks_per_seed, hipStream_t st) {
+    hipLaunchKernelGGL(k_seq_pass, dim3(blocks_per_seed, S.k), dim3(BLOCK), 0, st, g, S, r);
+    hipLaunchKernelGGL(k_seq_end, dim3(small_grid(S.k)), dim3(BLOCK), 0, st, S, r);
+    return hipGetLastError();
+}
+
+}  // namespace pp

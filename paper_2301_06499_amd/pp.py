@@ -58,7 +58,8 @@ EXPORTS = ["pp_options_default", "pp_csr_build", "pp_graph_arcs", "pp_graph_node
            "pp_get_signatures", "pp_get_seed_counts", "pp_run_round", "pp_run_words", "pp_get_round_log",
            "pp_run_snapshot", "pp_run_restore", "pp_run_free", "pp_graph_free", "pp_last_error",
            "pp_seeds_reset", "pp_get_kernel_times", "pp_run_set_mlp", "pp_get_round_features",
-           "pp_time_round", "pp_mlp_forward", "pp_mlp_loss_grad", "pp_mlp_train", "pp_autotune", "pp_exact_counts"]
+           "pp_time_round", "pp_mlp_forward", "pp_mlp_loss_grad", "pp_mlp_train", "pp_autotune", "pp_exact_counts",
+           "pp_propagate_s"]
 
 MLP_IN, MLP_HID, MLP_OUT = 8, 32, 2
 MLP_PARAMS = MLP_HID * MLP_IN + MLP_HID + MLP_HID * MLP_HID + MLP_HID + MLP_OUT * MLP_HID + MLP_OUT   # 1410
@@ -100,6 +101,7 @@ def lib():
         "pp_mlp_train": (ctypes.c_int, [P, P, P, I64, I32, ctypes.c_float, P]),
         "pp_autotune": (ctypes.c_int, [P, P, I32, P, I32, P, P, I32, P]),
         "pp_exact_counts": (ctypes.c_int, [P, I32, P, P, I32, P]),
+        "pp_propagate_s": (ctypes.c_int, [P, P, I32, I32, P, P, I32, P, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -428,6 +430,18 @@ def pp_exact_counts(graph: Graph, group: int = 512, opts: Options | None = None,
     _check(lib().pp_exact_counts(graph.handle, int(group), ctypes.byref(opts) if opts is not None else None,
                                  _np_ptr(c), cap, ctypes.byref(D)))
     return c[:D.value + 1].copy(), int(D.value)
+
+
+def pp_propagate_s(graph: Graph, seeds, concurrent: int = 0, cap_rounds: int | None = None, stream=None):
+    """PROPAGATE-S (Algorithm 2); host seeds; returns (counts c[0..D] int64, D, arcs examined)."""
+    a = np.ascontiguousarray(seeds, dtype=np.int32).reshape(-1)
+    cap = int(cap_rounds) if cap_rounds else graph.nodes + 1
+    c = np.zeros(cap, dtype=np.int64)
+    D = ctypes.c_int32(0)
+    ex = ctypes.c_int64(0)
+    _check(lib().pp_propagate_s(graph.handle, _np_ptr(a), int(a.shape[0]), int(concurrent), _stream_ptr(stream),
+                                _np_ptr(c), cap, ctypes.byref(D), ctypes.byref(ex)))
+    return c[:D.value + 1].copy(), int(D.value), int(ex.value)
 
 
 def propagate(n, src, dst, seeds, undirected=False, transpose=False, opts=None, stream=None):

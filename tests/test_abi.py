@@ -55,6 +55,7 @@ def test_validation_before_device_work():
     assert L.pp_propagate_round(None, None, None) == pp.PP_EINVAL
     assert L.pp_propagate_until_converged(None, 0, None, 0, None) == pp.PP_EINVAL
     assert L.pp_get_signatures(None, None, 0) == pp.PP_EINVAL
+    assert L.pp_propagate_s(None, None, 1, 0, None, None, 1, None, None) == pp.PP_EINVAL
     assert "NULL" in L.pp_last_error().decode()
 
 

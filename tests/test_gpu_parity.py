@@ -11,6 +11,7 @@ import numpy as np
 import pytest
 
 import oracle
+import oracle.propagate_s
 from paper_2301_06499_amd import inputs as gen
 from paper_2301_06499_amd import pp
 
@@ -330,6 +331,75 @@ def test_exact_neighbourhood_function(case):
     assert m["reachable_pairs"] == float(int((dist >= 0).sum()))
     with pytest.raises(pp.PPError):
         pp.pp_exact_counts(G, group=513)
+
+
+# ------------------------------------------------------------ PROPAGATE-S
+
+S_CASES = [("er", lambda: gen.erdos_renyi_gnm(400, 1200, 5), 64),
+           ("rmat", lambda: gen.rmat(12, 8, 6), 100),
+           ("grid", lambda: gen.grid_with_shortcuts(40, 30, gen.Fraction(1, 10), 20, 2), 77),
+           ("path", lambda: gen.path_graph(300), 5),
+           ("dpath", lambda: gen.path_graph(120, directed=True), 9),
+           ("star", lambda: gen.star_graph(2000), 33)]
+
+
+@pytest.mark.parametrize("case", range(len(S_CASES)))
+@pytest.mark.parametrize("concurrent", [0, 1, 7])
+@pytest.mark.parametrize("keep_order", [False, True])
+def test_propagate_s_counts(case, concurrent, keep_order):
+    """Algorithm 2 on the device: the same per-round counts and D as the BFS oracle, for every
+    number of seeds in flight (batches with a ragged last one) and both storage orders."""
+    name, make, s = S_CASES[case]
+    g = make()
+    seeds = gen.sample_seeds(g.n, s, 13 + case)
+    seeds[1] = seeds[0]   # a duplicate seed counts twice
+    say("propagate_s", name, "n", g.n, "s", s, "concurrent", concurrent, "keep_order", keep_order)
+    want = oracle.propagate(g.n, g.src, g.dst, seeds, g.undirected)
+    G = pp.pp_csr_build(g.n, g.src, g.dst, undirected=g.undirected, keep_order=keep_order)
+    counts, D, examined = pp.pp_propagate_s(G, seeds, concurrent=concurrent)
+    assert D == want["D"] and list(counts) == list(want["counts"])
+    assert 0 < examined <= (D + 1) * s * G.arcs
+
+
+@pytest.mark.parametrize("case", range(4))
+def test_propagate_s_literal_algorithm(case):
+    """Small graphs against the literal Algorithm 2 oracle, early-break work included: with the
+    stored order kept, every node walks the same sorted list and stops at the same arc."""
+    rng = np.random.default_rng(40 + case)
+    n = [40, 60, 25, 50][case]
+    src = rng.integers(0, n, 3 * n).astype(np.int32)
+    dst = rng.integers(0, n, 3 * n).astype(np.int32)
+    undirected, transpose = [(False, False), (True, False), (False, True), (True, True)][case]
+    seeds = rng.integers(0, n, 6).astype(np.int32)
+    say("propagate_s literal", case)
+    want, Dw, ex = oracle.propagate_s.propagate_s(n, src, dst, seeds, undirected, transpose, stored=True)
+    G = pp.pp_csr_build(n, src, dst, undirected=undirected, transpose=transpose, keep_order=True)
+    for conc in (0, 2):
+        counts, D, examined = pp.pp_propagate_s(G, seeds, concurrent=conc)
+        assert D == Dw and list(counts) == list(want) and examined == ex
+
+
+def test_propagate_s_long_lists_and_errors():
+    """Nodes with more successors than one lane walks (the wave-wide walk), the log's end,
+    bad seeds and batches."""
+    hub = gen.star_graph(5000)   # undirected: the centre's list is 4999 long
+    seeds = np.array([3, 0, 4998, 17], np.int32)
+    want = oracle.propagate(hub.n, hub.src, hub.dst, seeds, hub.undirected)
+    G = pp.pp_csr_build(hub.n, hub.src, hub.dst, undirected=True)
+    counts, D, _ = pp.pp_propagate_s(G, seeds)
+    assert D == want["D"] and list(counts) == list(want["counts"])
+    P = gen.path_graph(64)
+    GP = pp.pp_csr_build(P.n, P.src, P.dst, undirected=True)
+    with pytest.raises(pp.PPError) as e:
+        pp.pp_propagate_s(GP, np.array([0], np.int32), cap_rounds=10)
+    assert e.value.code == pp.PP_ENOTCONV
+    with pytest.raises(pp.PPError) as e:
+        pp.pp_propagate_s(GP, np.array([64], np.int32))
+    assert e.value.code == pp.PP_ERANGE
+    B = pp.pp_csr_build(4, np.array([0, 2], np.int32), np.array([1, 3], np.int32), node_offsets=[0, 2, 4])
+    with pytest.raises(pp.PPError) as e:
+        pp.pp_propagate_s(B, np.array([0], np.int32))
+    assert e.value.code == pp.PP_EINVAL
 
 
 def test_grid4096_full_size():

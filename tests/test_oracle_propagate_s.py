@@ -60,3 +60,16 @@ def test_early_break_stops_at_the_first_hit():
 def test_empty_graph():
     counts, D, examined = propagate_s(5, [], [], [0, 3, 3], undirected=True)
     assert counts.tolist() == [3] and D == 0 and examined == 0
+
+
+def test_stored_arc_set_keeps_the_counts():
+    # merging duplicates, dropping self-loops and sorting the lists changes
+    # only which arcs the early break examines
+    rng = np.random.default_rng(11)
+    for _ in range(5):
+        n = int(rng.integers(2, 25))
+        src, dst = _random_graph(rng, n, 3 * n)
+        seeds = rng.integers(0, n, 4)
+        a, Da, _ = propagate_s(n, src, dst, seeds, False)
+        b, Db, _ = propagate_s(n, src, dst, seeds, False, stored=True)
+        assert a.tolist() == b.tolist() and Da == Db
