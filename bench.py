@@ -275,6 +275,66 @@ def sampled_check(g, seeds, sig, k: int):
     return {"seeds_checked": [int(i) for i in idx], "nodes": int(g.n), "result": "bit-exact"}
 
 
+def calibration_copy(args, torch):
+    """A plain device copy of known size, for scaling the traffic counters."""
+    if not args.copy_calibration:
+        return
+    nb = args.copy_calibration << 20
+    a = torch.empty(nb // 4, dtype=torch.int32, device="cuda").fill_(1)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    log(f"[bench] calibration copy of {nb} bytes read + {nb} bytes written")
+    del a, b
+
+
+def bench_propagate_s(args, torch, pp, g, seeds, cfg):
+    """PROPAGATE-S (Algorithm 2) on the same workload: time per propagation of all seeds,
+    with the same nominal accounting as PROPAGATE-P, and its counts against the oracle."""
+    import oracle
+    stream = torch.cuda.Stream()
+    G = pp.pp_csr_build(g.n, g.src, g.dst, undirected=g.undirected, stream=stream)
+    torch.cuda.synchronize()
+    calibration_copy(args, torch)
+    s = len(seeds)
+    for _ in range(args.warmup):
+        pp.pp_propagate_s(G, seeds, concurrent=args.concurrent, stream=stream)
+    times = []
+    for _ in range(args.steps):
+        t0 = time.perf_counter()
+        counts, D, examined = pp.pp_propagate_s(G, seeds, concurrent=args.concurrent, stream=stream)
+        times.append(time.perf_counter() - t0)
+    t = sum(times) / len(times)
+    want = oracle.propagate(g.n, g.src, g.dst, seeds, g.undirected)
+    exact = want["D"] == D and list(want["counts"]) == list(counts)
+    rounds = D + 1
+    nominal = float(G.arcs) * (s / 64.0) * rounds
+    nw = (g.n + 63) // 64
+    # per examined arc its 4-byte successor id and the 8-byte signature word
+    # holding the successor's bit; per pass and seed every word read and written
+    bytes_total = examined * 12.0 + rounds * s * nw * 16.0
+    achieved = bytes_total / t / 1e9
+    out = {"metric": "edge-words OR'd/sec (edges x s/64 per round), PROPAGATE-S", "value": nominal / t,
+           "unit": "edge-words/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": round(t * 1000.0, 4), "ms_per_step_min": round(min(times) * 1000.0, 4),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+           "config": dict(cfg, method="PROPAGATE-S (Algorithm 2)", nodes=int(G.nodes), arcs=int(G.arcs), rounds=rounds,
+                          concurrent=args.concurrent or min(s, 256)),
+           "arcs_examined": int(examined),
+           "arcs_examined_per_s": examined / t,
+           "full_scan_arcs": int(G.arcs) * rounds * s,
+           "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": 8000.0, "unit": "GB/s",
+                        "frac": round(achieved / 8000.0, 4), "traffic": None, "kernel": "k_seq_pass",
+                        "bytes_per_step": bytes_total,
+                        "timing": "host clock around the synchronous call (every pass launch and check included)"},
+           "check": {"against": "oracle per-seed BFS, every seed", "result": "bit-exact" if exact else "MISMATCH"}}
+    print(json.dumps(out), flush=True)
+    G.free()
+    if not exact:
+        raise SystemExit("PROPAGATE-S counts differ from the oracle")
+
+
 def cpu_baseline(g, seeds, nominal_edge_words: float, budget_s: float):
     """The oracle (not tuned) on the host cores; a seed sample sized to the budget."""
     import oracle
@@ -344,6 +404,10 @@ def main():
                     help="run options from the autotuner (measured before the timed steps, cached per workload)")
     ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--method", default="p", choices=["p", "s"],
+                    help="p: PROPAGATE-P (the default, the headline line); s: PROPAGATE-S, one bit per node "
+                         "and seed, its own JSON line")
+    ap.add_argument("--concurrent", type=int, default=0, help="PROPAGATE-S: seeds in flight (0: min(s, 256))")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device-to-device with a plain torch copy, so that a "
                          "hardware-counter run has a kernel of known traffic to scale against")
@@ -369,6 +433,8 @@ def main():
     t0 = time.perf_counter()
     g, seeds, cfg = workload(args.workload)
     log(f"[bench] generated {cfg['workload']} in {time.perf_counter() - t0:.1f} s")
+    if args.method == "s":
+        return bench_propagate_s(args, torch, pp, g, seeds, cfg)
     stream = torch.cuda.Stream()                       # default priority
     t0 = time.perf_counter()
     G = pp.pp_csr_build(g.n, g.src, g.dst, undirected=g.undirected, stream=stream)
@@ -392,15 +458,7 @@ def main():
     opts_t.time_kernels = 1
     run_t = pp.pp_seeds_init(G, seeds, opts=opts_t, stream=stream)
     W = run.words
-    if args.copy_calibration:
-        nb = args.copy_calibration << 20
-        a = torch.empty(nb // 4, dtype=torch.int32, device="cuda").fill_(1)
-        b = torch.empty_like(a)
-        torch.cuda.synchronize()
-        b.copy_(a)
-        torch.cuda.synchronize()
-        log(f"[bench] calibration copy of {nb} bytes read + {nb} bytes written")
-        del a, b
+    calibration_copy(args, torch)
     s = len(seeds)
 
     def step(r):

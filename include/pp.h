@@ -322,10 +322,11 @@ int pp_exact_counts(pp_graph g, int32_t group, const pp_options *opt, int64_t *c
  * instead of O(n s) for all of them.
  *   seeds      host [s] input node ids, checked (PP_ERANGE if outside [0, n));
  *              duplicates count once each, as seed bits do in PROPAGATE-P.
- *   concurrent seeds in flight at once (0: min(s, 256)); device memory is
- *              2 x concurrent x ceil(n/64) x 8 bytes of signatures plus
- *              concurrent x cap_rounds x 8 bytes of counts, allocated here
- *              and freed before return.
+ *   concurrent seeds in flight at once (0: min(s, 256), at most 65535);
+ *              device memory is 2 x concurrent x ceil(n/64) x 8 bytes of
+ *              signatures plus cap_rounds x 8 bytes of counts, allocated
+ *              here and freed before return (the graph keeps a list of its
+ *              nodes with long successor lists from the first call on).
  *   stream     hipStream_t or NULL (the graph's stream); synchronous.
  *   counts     host [cap_rounds], zeroed first: counts[r] = pairs (u, x_i)
  *              with d(u, x_i) = r, counts[0] = s.

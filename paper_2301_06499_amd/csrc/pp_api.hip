@@ -108,6 +108,8 @@ struct pp_graph_s {
     std::map<int, TileSet> tiles;   // by pull arc budget
     std::vector<int32_t> perm;      // stored id of each input node (empty: identity)
     int32_t *perm_d = nullptr;      // the same on the device
+    int32_t *seq_heavy = nullptr;   // PROPAGATE-S: nodes with long successor lists (built on first use)
+    int64_t nseq_heavy = -1;
 };
 
 struct pp_run_s {
@@ -439,6 +441,7 @@ void free_graph(pp_graph g) {
     dev_free(g->node_graph);
     dev_free(g->node_off);
     dev_free(g->perm_d);
+    dev_free(g->seq_heavy);
     for (auto &kv : g->tiles) {
         dev_free(kv.second.tiles);
         dev_free(kv.second.hub_node);
@@ -1582,16 +1585,32 @@ extern "C" int pp_propagate_s(pp_graph g, const int32_t *seeds, int32_t s, int32
     S.cap = cap_rounds;
     S.nw = nw;
     int32_t *dseeds = nullptr;
+    if (g->nseq_heavy < 0) {
+        // nodes whose successor lists go to the wave-per-node launch, kept with the graph
+        std::vector<int32_t> hv;
+        for (int64_t u = 0; u < n; ++u)
+            if (g->rp_host[(size_t)u + 1] - g->rp_host[(size_t)u] > pp::SEQ_LIGHT) hv.push_back((int32_t)u);
+        if ((rc = dev_alloc(&g->seq_heavy, (int64_t)hv.size()))) return rc;
+        if (!hv.empty() && hipMemcpy(g->seq_heavy, hv.data(), sizeof(int32_t) * hv.size(), hipMemcpyHostToDevice) !=
+                               hipSuccess) {
+            dev_free(g->seq_heavy);
+            return fail(PP_EDEVICE, "PROPAGATE-S: heavy-node list upload");
+        }
+        g->nseq_heavy = (int64_t)hv.size();
+    }
+    const int32_t *heavy = g->seq_heavy;
+    const int64_t nheavy = g->nseq_heavy;
     auto release = [&]() {
         dev_free(S.bits);
-        dev_free(S.cnt);
+        dev_free(S.pass_cnt);
+        dev_free(S.sum_cnt);
         dev_free(S.examined);
         dev_free(S.done);
         dev_free(S.dpass);
         dev_free(S.active);
         dev_free(dseeds);
     };
-    if ((rc = dev_alloc(&S.bits, 2 * k * nw)) || (rc = dev_alloc(&S.cnt, k * cap)) ||
+    if ((rc = dev_alloc(&S.bits, 2 * k * nw)) || (rc = dev_alloc(&S.pass_cnt, k)) || (rc = dev_alloc(&S.sum_cnt, cap)) ||
         (rc = dev_alloc(&S.examined, k)) || (rc = dev_alloc(&S.done, k)) || (rc = dev_alloc(&S.dpass, k)) ||
         (rc = dev_alloc(&S.active, 1)) || (rc = dev_alloc(&dseeds, k))) {
         release();
@@ -1606,8 +1625,9 @@ extern "C" int pp_propagate_s(pp_graph g, const int32_t *seeds, int32_t s, int32
     // about 16 Ki waves in all, at least one block per seed, at most one wave per word
     const int64_t want = (16384 / 4 + k - 1) / k, most = (nw + 3) / 4;
     const int bps = (int)std::max<int64_t>(1, std::min(want, most));
+    const int bph = (int)std::max<int64_t>(1, std::min(want, (nheavy + 3) / 4));
     std::vector<int32_t> hs((size_t)k), hd((size_t)k), hdone((size_t)k);
-    std::vector<int64_t> hc((size_t)(k * cap)), hx((size_t)k);
+    std::vector<int64_t> hc, hx((size_t)k);
     hipError_t e = hipSuccess;
     for (int first = 0; first < s && e == hipSuccess; first += k) {
         const int kk = std::min(k, s - first);
@@ -1616,11 +1636,13 @@ extern "C" int pp_propagate_s(pp_graph g, const int32_t *seeds, int32_t s, int32
             hs[(size_t)i] = g->perm.empty() ? x : g->perm[(size_t)x];
         }
         e = hipMemcpyAsync(dseeds, hs.data(), sizeof(int32_t) * (size_t)kk, hipMemcpyHostToDevice, st);
-        const pp::FillSeg segs[] = {{(uint32_t *)S.bits, 2 * k * nw, 0u}, {(uint32_t *)S.cnt, 2 * k * cap, 0u}};
+        int last = 0;   // passes launched
+        const pp::FillSeg segs[] = {{(uint32_t *)S.bits, 2 * k * nw, 0u}, {(uint32_t *)S.sum_cnt, 2 * cap, 0u}};
         if (e == hipSuccess) e = pp::launch_fills(segs, 2, st);
         if (e == hipSuccess) e = pp::launch_seq_seeds(S, dseeds, kk, st);
         for (int r = 1; r < cap_rounds && e == hipSuccess; ++r) {
-            e = pp::launch_seq_pass(gv, S, r, bps, st);
+            last = r;
+            e = pp::launch_seq_pass(gv, S, heavy, nheavy, r, bps, bph, st);
             if (e == hipSuccess && (r % 8 == 0 || r == cap_rounds - 1)) {
                 int32_t act = 0;
                 e = hipMemcpyAsync(&act, S.active, sizeof(int32_t), hipMemcpyDeviceToHost, st);
@@ -1628,14 +1650,15 @@ extern "C" int pp_propagate_s(pp_graph g, const int32_t *seeds, int32_t s, int32
                 if (act == 0) break;
             }
         }
-        if (e == hipSuccess) e = hipMemcpyAsync(hc.data(), S.cnt, sizeof(int64_t) * (size_t)(kk * cap), hipMemcpyDeviceToHost, st);
+        hc.assign((size_t)last + 1, 0);
+        if (e == hipSuccess) e = hipMemcpyAsync(hc.data(), S.sum_cnt, sizeof(int64_t) * hc.size(), hipMemcpyDeviceToHost, st);
         if (e == hipSuccess) e = hipMemcpyAsync(hx.data(), S.examined, sizeof(int64_t) * (size_t)kk, hipMemcpyDeviceToHost, st);
         if (e == hipSuccess) e = hipMemcpyAsync(hd.data(), S.dpass, sizeof(int32_t) * (size_t)kk, hipMemcpyDeviceToHost, st);
         if (e == hipSuccess) e = hipMemcpyAsync(hdone.data(), S.done, sizeof(int32_t) * (size_t)kk, hipMemcpyDeviceToHost, st);
         if (e == hipSuccess) e = hipStreamSynchronize(st);
         if (e != hipSuccess) break;
+        for (int r = 1; r <= last; ++r) counts[r] += hc[(size_t)r];
         for (int j = 0; j < kk; ++j) {
-            for (int64_t r = 1; r < cap; ++r) counts[r] += hc[(size_t)(j * cap + r)];
             dmax = std::max(dmax, hd[(size_t)j]);
             ex_total += hx[(size_t)j];
             overflow |= hdone[(size_t)j] == 2;

@@ -216,7 +216,8 @@ hipError_t launch_map_ids(int32_t *out, const int32_t *in, const int32_t *perm, 
 // PROPAGATE-S state for k seeds side by side (see pp_seq.hip).
 struct SeqDev {
     uint64_t *bits;       // [2][k][nw] signatures, one bit per node
-    int64_t *cnt;         // [k][cap] nodes found at each pass
+    int64_t *pass_cnt;    // [k] nodes found by the current pass (cleared by its end)
+    int64_t *sum_cnt;     // [cap] nodes found at each pass, summed over the seeds
     int64_t *examined;    // [k] arcs examined
     int32_t *done;        // [k] 0 running, 1 done, 2 stopped at the end of the log
     int32_t *dpass;       // [k] last pass that found a node
@@ -225,8 +226,11 @@ struct SeqDev {
     int64_t nw;           // 64-bit words per signature
 };
 hipError_t launch_seq_seeds(const SeqDev &S, const int32_t *seeds, int kk, hipStream_t st);
-// Pass r and its per-seed end.
-hipError_t launch_seq_pass(const GraphDev &g, const SeqDev &S, int r, int blocks_per_seed, hipStream_t st);
+// Nodes with more successors than this go to the wave-per-node launch.
+constexpr int SEQ_LIGHT = 32;
+// Pass r (short lists, then heavy[0..nheavy)) and its per-seed end.
+hipError_t launch_seq_pass(const GraphDev &g, const SeqDev &S, const int32_t *heavy, int64_t nheavy, int r,
+                           int blocks_per_seed, int heavy_blocks_per_seed, hipStream_t st);
 
 hipError_t launch_stage(const void *ctrl, int64_t ctrl_bytes, const int32_t *D, int64_t nD, const int64_t *rows,
                         int64_t nrows, void *h_ctrl, int32_t *h_D, int64_t *h_rows, hipStream_t st);

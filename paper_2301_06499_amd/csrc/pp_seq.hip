@@ -7,18 +7,18 @@
 // 64 nodes of one seed, one node per lane: a node not reached yet walks its
 // successor list and stops at the first successor already reached (the
 // algorithm's early break); one ballot gives the word's new bits.  A lane
-// walks a short list itself, four arcs per step; a list longer than
-// SEQ_LIGHT is walked by the whole wave, 64 arcs per step, up to the first
-// step with a hit.  Each pass counts, per seed, the nodes it found and the
-// arcs it examined (up to and including the first hit of each node); a seed
-// is done at its first pass that finds nothing.
+// walks a short list itself, four arcs per step.  Nodes with more than
+// SEQ_LIGHT successors (listed once per graph) are left to a second launch
+// in which each wave takes one such node and walks its list 256 arcs per
+// step up to the first step with a hit, so a hub costs one wave, not the
+// word that holds it.  Each pass counts, per seed, the nodes it found and
+// the arcs it examined (up to and including the first hit of each node); a
+// seed is done at its first pass that finds nothing.
 #include "pp_internal.h"
 
 namespace pp {
 
 #define PS_DEV __device__ __forceinline__
-
-constexpr int SEQ_LIGHT = 32;   // longer successor lists are walked by the whole wave
 
 namespace {
 
@@ -51,6 +51,7 @@ __global__ void __launch_bounds__(BLOCK) k_seq_seeds(SeqDev S, const int32_t *se
         S.done[j] = j < kk ? 0 : 1;
         S.dpass[j] = 0;
         S.examined[j] = 0;
+        S.pass_cnt[j] = 0;
         if (j < kk) {
             const int32_t x = seeds[j];
             buffer(S, 0, j)[x >> 6] |= 1ull << (x & 63);
@@ -59,7 +60,8 @@ __global__ void __launch_bounds__(BLOCK) k_seq_seeds(SeqDev S, const int32_t *se
     }
 }
 
-// Pass r of every seed still running (grid: blocks per seed x k).
+// Pass r, nodes with short lists, of every seed still running (grid: blocks
+// per seed x k).  Writes every word of the next signature.
 __global__ void __launch_bounds__(BLOCK) k_seq_pass(GraphDev g, SeqDev S, int r) {
     const int j = blockIdx.y;
     if (S.done[j]) return;   // the same for the whole block
@@ -79,7 +81,7 @@ __global__ void __launch_bounds__(BLOCK) k_seq_pass(GraphDev g, SeqDev S, int r)
             e = g.rp[u + 1];
         }
         bool hit = false;
-        if (open && e - b <= SEQ_LIGHT) {
+        if (open && e - b <= SEQ_LIGHT) {   // longer lists: k_seq_heavy
             // the lane's own list, four arcs in flight per step
             for (int64_t a = b; a < e && !hit; a += 4) {
                 int32_t v[4];
@@ -97,30 +99,6 @@ __global__ void __launch_bounds__(BLOCK) k_seq_pass(GraphDev g, SeqDev S, int r)
                 }
             }
         }
-        // long lists, one node at a time across the wave
-        uint64_t heavy = __ballot(open && e - b > SEQ_LIGHT);
-        while (heavy) {   // wave-uniform
-            const int h = __ffsll((long long)heavy) - 1;
-            heavy &= heavy - 1;
-            const int64_t hb = __shfl(b, h), he = __shfl(e, h);
-            bool hh = false;
-            int64_t hx = 0;
-            for (int64_t a0 = hb; a0 < he; a0 += 64) {   // wave-uniform
-                const int64_t a = a0 + ln;
-                const bool t = a < he && reached(cur, g.col[a]);
-                const uint64_t m = __ballot(t);
-                if (m) {
-                    hh = true;
-                    hx += __ffsll((long long)m);   // the arcs up to the first hit
-                    break;
-                }
-                hx += he - a0 < 64 ? he - a0 : 64;
-            }
-            if (ln == h) {
-                hit = hh;
-                exam += hx;
-            }
-        }
         const uint64_t nb = __ballot(hit);
         if (ln == 0) {
             nxt[wd] = word | nb;
@@ -131,7 +109,61 @@ __global__ void __launch_bounds__(BLOCK) k_seq_pass(GraphDev g, SeqDev S, int r)
     const long long tf = block_total<long long>(found, s_red);
     const long long te = block_total<long long>(exam, s_red);
     if (threadIdx.x == 0) {
-        if (tf) atomicAdd((unsigned long long *)&S.cnt[(int64_t)j * S.cap + r], (unsigned long long)tf);
+        if (tf) atomicAdd((unsigned long long *)&S.pass_cnt[j], (unsigned long long)tf);
+        if (te) atomicAdd((unsigned long long *)&S.examined[j], (unsigned long long)te);
+    }
+}
+
+// Pass r, nodes with long lists (heavy[0..nheavy), stored ids): one wave per
+// node, four arcs per lane and step in arc order; a hit sets the node's bit in
+// the next signature (written by k_seq_pass before, in stream order).
+__global__ void __launch_bounds__(BLOCK) k_seq_heavy(GraphDev g, SeqDev S, const int32_t *heavy, int64_t nheavy,
+                                                    int r) {
+    const int j = blockIdx.y;
+    if (S.done[j]) return;   // the same for the whole block
+    const uint64_t *cur = buffer(S, r - 1, j);
+    uint64_t *nxt = buffer(S, r, j);
+    const int ln = lane();
+    const int64_t wave = (int64_t)blockIdx.x * (BLOCK / 64) + (threadIdx.x >> 6);
+    const int64_t nwaves = (int64_t)gridDim.x * (BLOCK / 64);
+    int64_t found = 0, exam = 0;
+    for (int64_t h = wave; h < nheavy; h += nwaves) {   // wave-uniform
+        const int32_t u = heavy[h];
+        if (reached(cur, u)) continue;
+        const int64_t b = g.rp[u], e = g.rp[u + 1];
+        bool hit = false;
+        for (int64_t a0 = b; a0 < e && !hit; a0 += 256) {   // wave-uniform
+            bool t[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int64_t a = a0 + q * 64 + ln;
+                t[q] = a < e && reached(cur, g.col[a]);
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const uint64_t m = __ballot(t[q]);
+                if (!hit) {
+                    if (m) {
+                        hit = true;
+                        exam += q * 64 + __ffsll((long long)m);   // up to the first hit, in arc order
+                    } else {
+                        const int64_t left = e - (a0 + q * 64);
+                        exam += left <= 0 ? 0 : (left < 64 ? left : 64);
+                    }
+                }
+            }
+        }
+        if (hit) {
+            ++found;
+            if (ln == 0) atomicOr((unsigned long long *)&nxt[u >> 6], 1ull << (u & 63));
+        }
+    }
+    if (ln != 0) found = exam = 0;   // every lane holds the wave's figures: count them once
+    __shared__ long long s_red[BLOCK / 64];
+    const long long tf = block_total<long long>(found, s_red);
+    const long long te = block_total<long long>(exam, s_red);
+    if (threadIdx.x == 0) {
+        if (tf) atomicAdd((unsigned long long *)&S.pass_cnt[j], (unsigned long long)tf);
         if (te) atomicAdd((unsigned long long *)&S.examined[j], (unsigned long long)te);
     }
 }
@@ -139,10 +171,15 @@ __global__ void __launch_bounds__(BLOCK) k_seq_pass(GraphDev g, SeqDev S, int r)
 // After pass r: a seed whose pass found nothing is done; otherwise r is its
 // last pass so far with a find.  A seed still running at the last pass the
 // log holds is stopped and counted as not converged.
+// The pass's finds are summed into sum_cnt[r].
 __global__ void __launch_bounds__(BLOCK) k_seq_end(SeqDev S, int r) {
+    long long sum = 0;
     for (int j = blockIdx.x * BLOCK + threadIdx.x; j < S.k; j += gridDim.x * BLOCK) {
         if (S.done[j]) continue;
-        if (S.cnt[(int64_t)j * S.cap + r] == 0) {
+        const int64_t c = S.pass_cnt[j];
+        S.pass_cnt[j] = 0;
+        sum += c;
+        if (c == 0) {
             S.done[j] = 1;
             atomicSub(S.active, 1);
         } else {
@@ -153,6 +190,9 @@ __global__ void __launch_bounds__(BLOCK) k_seq_end(SeqDev S, int r) {
             }
         }
     }
+    __shared__ long long s_red[BLOCK / 64];
+    const long long t = block_total<long long>(sum, s_red);
+    if (threadIdx.x == 0 && t) atomicAdd((unsigned long long *)&S.sum_cnt[r], (unsigned long long)t);
 }
 
 static int small_grid(int64_t items) {
@@ -165,8 +205,11 @@ hipError_t launch_seq_seeds(const SeqDev &S, const int32_t *seeds, int kk, hipSt
     return hipGetLastError();
 }
 
-hipError_t launch_seq_pass(const GraphDev &g, const SeqDev &S, int r, int blocks_per_seed, hipStream_t st) {
+hipError_t launch_seq_pass(const GraphDev &g, const SeqDev &S, const int32_t *heavy, int64_t nheavy, int r,
+                           int blocks_per_seed, int heavy_blocks_per_seed, hipStream_t st) {
     hipLaunchKernelGGL(k_seq_pass, dim3(blocks_per_seed, S.k), dim3(BLOCK), 0, st, g, S, r);
+    if (nheavy > 0)
+        hipLaunchKernelGGL(k_seq_heavy, dim3(heavy_blocks_per_seed, S.k), dim3(BLOCK), 0, st, g, S, heavy, nheavy, r);
     hipLaunchKernelGGL(k_seq_end, dim3(small_grid(S.k)), dim3(BLOCK), 0, st, S, r);
     return hipGetLastError();
 }

@@ -380,14 +380,21 @@ def test_propagate_s_literal_algorithm(case):
 
 
 def test_propagate_s_long_lists_and_errors():
-    """Nodes with more successors than one lane walks (the wave-wide walk), the log's end,
-    bad seeds and batches."""
+    """Nodes with more successors than one lane walks (the wave-per-node launch), the log's
+    end, bad seeds and batches."""
     hub = gen.star_graph(5000)   # undirected: the centre's list is 4999 long
     seeds = np.array([3, 0, 4998, 17], np.int32)
     want = oracle.propagate(hub.n, hub.src, hub.dst, seeds, hub.undirected)
     G = pp.pp_csr_build(hub.n, hub.src, hub.dst, undirected=True)
     counts, D, _ = pp.pp_propagate_s(G, seeds)
     assert D == want["D"] and list(counts) == list(want["counts"])
+    # the early break inside a long list: the centre stops at the arc to the seed
+    # leaf (arc 300 of its sorted list), exactly as the literal algorithm does
+    GK = pp.pp_csr_build(hub.n, hub.src, hub.dst, undirected=True, keep_order=True)
+    one = np.array([300], np.int32)
+    wc, wD, wex = oracle.propagate_s.propagate_s(hub.n, hub.src, hub.dst, one, True, stored=True)
+    counts, D, examined = pp.pp_propagate_s(GK, one)
+    assert D == wD and list(counts) == list(wc) and examined == wex == 300 + 2 * 4998
     P = gen.path_graph(64)
     GP = pp.pp_csr_build(P.n, P.src, P.dst, undirected=True)
     with pytest.raises(pp.PPError) as e:
