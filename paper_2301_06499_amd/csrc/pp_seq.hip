@@ -9,9 +9,9 @@
 // algorithm's early break); one ballot gives the word's new bits.  A lane
 // walks a short list itself, four arcs per step.  Nodes with more than
 // SEQ_LIGHT successors (listed once per graph) are left to a second launch
-// in which each wave takes one such node and walks its list 256 arcs per
-// step up to the first step with a hit, so a hub costs one wave, not the
-// word that holds it.  Each pass counts, per seed, the nodes it found and
+// in which a group of 16 lanes takes one such node and walks its list 64
+// arcs per step up to the first step with a hit, so a hub costs one group,
+// not the word that holds it.  Each pass counts, per seed, the nodes it found and
 // the arcs it examined (up to and including the first hit of each node); a
 // seed is done at its first pass that finds nothing.
 #include "pp_internal.h"
@@ -114,51 +114,69 @@ __global__ void __launch_bounds__(BLOCK) k_seq_pass(GraphDev g, SeqDev S, int r)
     }
 }
 
-// Pass r, nodes with long lists (heavy[0..nheavy), stored ids): one wave per
-// node, four arcs per lane and step in arc order; a hit sets the node's bit in
-// the next signature (written by k_seq_pass before, in stream order).
+// Pass r, nodes with long lists (heavy[0..nheavy), stored ids): a group of
+// 16 lanes per node, four nodes per wave, each lane four arcs per step (64
+// arcs per node and step, in arc order); a hit sets the node's bit in the
+// next signature (written by k_seq_pass before, in stream order).
 __global__ void __launch_bounds__(BLOCK) k_seq_heavy(GraphDev g, SeqDev S, const int32_t *heavy, int64_t nheavy,
                                                     int r) {
+    constexpr int GL = 16;                 // lanes per node
+    constexpr int GW = 64 / GL;            // nodes per wave
     const int j = blockIdx.y;
     if (S.done[j]) return;   // the same for the whole block
     const uint64_t *cur = buffer(S, r - 1, j);
     uint64_t *nxt = buffer(S, r, j);
     const int ln = lane();
+    const int grp = ln / GL, sub = ln % GL;
+    const uint64_t gmask = ((1ull << GL) - 1) << (grp * GL);
     const int64_t wave = (int64_t)blockIdx.x * (BLOCK / 64) + (threadIdx.x >> 6);
     const int64_t nwaves = (int64_t)gridDim.x * (BLOCK / 64);
     int64_t found = 0, exam = 0;
-    for (int64_t h = wave; h < nheavy; h += nwaves) {   // wave-uniform
-        const int32_t u = heavy[h];
-        if (reached(cur, u)) continue;
-        const int64_t b = g.rp[u], e = g.rp[u + 1];
-        bool hit = false;
-        for (int64_t a0 = b; a0 < e && !hit; a0 += 256) {   // wave-uniform
+    for (int64_t h0 = wave * GW; h0 < nheavy; h0 += nwaves * GW) {   // wave-uniform
+        const int64_t h = h0 + grp;
+        int32_t u = 0;
+        bool open = false;
+        int64_t b = 0, e = 0;
+        if (h < nheavy) {
+            u = heavy[h];
+            open = !reached(cur, u);
+            if (open) {
+                b = g.rp[u];
+                e = g.rp[u + 1];
+            }
+        }
+        bool hit = false;     // the same in every lane of a group
+        int64_t ex = 0;
+        for (int64_t a0 = b; __ballot(open && !hit && a0 < e); a0 += 4 * GL) {   // wave-uniform condition
+            const bool go = open && !hit && a0 < e;
             bool t[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const int64_t a = a0 + q * 64 + ln;
-                t[q] = a < e && reached(cur, g.col[a]);
+                const int64_t a = a0 + q * GL + sub;
+                t[q] = go && a < e && reached(cur, g.col[a]);
             }
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const uint64_t m = __ballot(t[q]);
-                if (!hit) {
+                const uint64_t m = (__ballot(t[q]) & gmask) >> (grp * GL);
+                if (go && !hit) {
                     if (m) {
                         hit = true;
-                        exam += q * 64 + __ffsll((long long)m);   // up to the first hit, in arc order
+                        ex += __ffsll((long long)m);   // this chunk's arcs up to the first hit, in arc order
                     } else {
-                        const int64_t left = e - (a0 + q * 64);
-                        exam += left <= 0 ? 0 : (left < 64 ? left : 64);
+                        const int64_t left = e - (a0 + q * GL);
+                        ex += left <= 0 ? 0 : (left < GL ? left : GL);
                     }
                 }
             }
         }
-        if (hit) {
-            ++found;
-            if (ln == 0) atomicOr((unsigned long long *)&nxt[u >> 6], 1ull << (u & 63));
+        if (sub == 0) {   // one lane per group counts and sets the bit
+            exam += ex;
+            if (hit) {
+                ++found;
+                atomicOr((unsigned long long *)&nxt[u >> 6], 1ull << (u & 63));
+            }
         }
     }
-    if (ln != 0) found = exam = 0;   // every lane holds the wave's figures: count them once
     __shared__ long long s_red[BLOCK / 64];
     const long long tf = block_total<long long>(found, s_red);
     const long long te = block_total<long long>(exam, s_red);

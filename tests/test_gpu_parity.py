@@ -389,12 +389,14 @@ def test_propagate_s_long_lists_and_errors():
     counts, D, _ = pp.pp_propagate_s(G, seeds)
     assert D == want["D"] and list(counts) == list(want["counts"])
     # the early break inside a long list: the centre stops at the arc to the seed
-    # leaf (arc 300 of its sorted list), exactly as the literal algorithm does
+    # leaf (arc x of its sorted list), exactly as the literal algorithm does;
+    # hits at several offsets within a step of the wave-wide walk
     GK = pp.pp_csr_build(hub.n, hub.src, hub.dst, undirected=True, keep_order=True)
-    one = np.array([300], np.int32)
-    wc, wD, wex = oracle.propagate_s.propagate_s(hub.n, hub.src, hub.dst, one, True, stored=True)
-    counts, D, examined = pp.pp_propagate_s(GK, one)
-    assert D == wD and list(counts) == list(wc) and examined == wex == 300 + 2 * 4998
+    for x in (1, 16, 17, 63, 64, 65, 300, 4999):
+        one = np.array([x], np.int32)
+        wc, wD, wex = oracle.propagate_s.propagate_s(hub.n, hub.src, hub.dst, one, True, stored=True)
+        counts, D, examined = pp.pp_propagate_s(GK, one)
+        assert D == wD and list(counts) == list(wc) and examined == wex == x + 2 * 4998, x
     P = gen.path_graph(64)
     GP = pp.pp_csr_build(P.n, P.src, P.dst, undirected=True)
     with pytest.raises(pp.PPError) as e:
