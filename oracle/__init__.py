@@ -20,6 +20,9 @@ Contents
                     small graphs.
 ``brute_force_counts``  all-pairs distances by repeated boolean matrix
                     products, for tiny graphs.
+``progressive``     (module ``oracle.progressive``) seed groups added until a
+                    Hoeffding half-width of the average distance meets a
+                    target (Section 4 error bounds).
 ``propagate_s``     (module ``oracle.propagate_s``) Algorithm 2, PROPAGATE-S:
                     one seed at a time with one bit per node and the early
                     break, pure Python, for small graphs.
