@@ -275,6 +275,50 @@ def sampled_check(g, seeds, sig, k: int):
     return {"seeds_checked": [int(i) for i in idx], "nodes": int(g.n), "result": "bit-exact"}
 
 
+def bench_progressive(args, torch, pp, g, seeds, cfg):
+    """Progressive sampling on the workload's graph: seed groups of the workload's s from a
+    pool of 16 s distinct seeds until the average distance's Hoeffding half-width (the
+    sample's D and alpha) meets --target; the run checked against the oracle's."""
+    from paper_2301_06499_amd import inputs
+    import oracle.progressive as prog
+    s = len(seeds)
+    pool = inputs.sample_seeds(g.n, min(g.n, 16 * s), 7)
+    G = pp.pp_csr_build(g.n, g.src, g.dst, undirected=g.undirected)
+    group = min(s, 512)
+    for _ in range(args.warmup):
+        pp.pp_progressive_sample(G, pool, group, args.target, args.delta)
+    times = []
+    for _ in range(args.steps):
+        t0 = time.perf_counter()
+        got = pp.pp_progressive_sample(G, pool, group, args.target, args.delta)
+        times.append(time.perf_counter() - t0)
+    t = sum(times) / len(times)
+    t0 = time.perf_counter()
+    want = prog.progressive(g.n, g.src, g.dst, pool, group, args.target, args.delta, g.undirected)
+    t_oracle = time.perf_counter() - t0
+    exact = list(want["counts"]) == list(got["counts"]) and all(
+        want[k] == got[k] for k in ("seeds", "groups", "met", "D", "alpha", "eps", "bound"))
+    m = pp.pp_estimate_metrics(got["counts"], g.n, got["seeds"])
+    rounds = int(got["D"]) + 1
+    nominal = float(G.arcs) * (got["seeds"] / 64.0) * rounds
+    out = {"metric": "edge-words OR'd/sec (edges x s/64 per round), progressive sampling", "value": nominal / t,
+           "unit": "edge-words/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": round(t * 1000.0, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "u64", "data": "synthetic",
+           "config": dict(cfg, method="progressive sampling, Hoeffding stop", group=group, pool=len(pool),
+                          target=args.target, delta=args.delta),
+           "stop": {k: (bool(v) if k == "met" else v) for k, v in got.items() if k != "counts"},
+           "estimates": {k: m[k] for k in ("avg_dist", "eff_diam", "diameter", "alpha", "reachable_pairs")},
+           "roofline": None,
+           "cpu_baseline": {"value": nominal / t_oracle, "unit": "edge-words/s", "cores": __import__("oracle").default_threads(),
+                            "kind": "oracle", "sample": f"the whole run ({got['seeds']} seeds) by per-seed BFS in {t_oracle:.2f} s"},
+           "check": {"against": "the oracle's progressive run (same pool)", "result": "bit-exact" if exact else "MISMATCH"}}
+    print(json.dumps(out), flush=True)
+    G.free()
+    if not exact:
+        raise SystemExit("progressive sampling differs from the oracle")
+
+
 def calibration_copy(args, torch):
     """A plain device copy of known size, for scaling the traffic counters."""
     if not args.copy_calibration:
@@ -404,9 +448,12 @@ def main():
                     help="run options from the autotuner (measured before the timed steps, cached per workload)")
     ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--method", default="p", choices=["p", "s"],
+    ap.add_argument("--method", default="p", choices=["p", "s", "progressive"],
                     help="p: PROPAGATE-P (the default, the headline line); s: PROPAGATE-S, one bit per node "
-                         "and seed, its own JSON line")
+                         "and seed; progressive: seed groups until the average distance's Hoeffding half-width "
+                         "meets --target (each its own JSON line)")
+    ap.add_argument("--target", type=float, default=1.0, help="progressive: half-width target (hops)")
+    ap.add_argument("--delta", type=float, default=0.05, help="progressive: 1 - confidence")
     ap.add_argument("--concurrent", type=int, default=0, help="PROPAGATE-S: seeds in flight (0: min(s, 256))")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device-to-device with a plain torch copy, so that a "
@@ -435,6 +482,8 @@ def main():
     log(f"[bench] generated {cfg['workload']} in {time.perf_counter() - t0:.1f} s")
     if args.method == "s":
         return bench_propagate_s(args, torch, pp, g, seeds, cfg)
+    if args.method == "progressive":
+        return bench_progressive(args, torch, pp, g, seeds, cfg)
     stream = torch.cuda.Stream()                       # default priority
     t0 = time.perf_counter()
     G = pp.pp_csr_build(g.n, g.src, g.dst, undirected=g.undirected, stream=stream)

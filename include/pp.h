@@ -315,6 +315,34 @@ int pp_exact_counts(pp_graph g, int32_t group, const pp_options *opt, int64_t *c
                     int32_t *D);
 
 /*
+ * pp_progressive_sample -- progressive sampling with a Hoeffding stopping
+ * rule (Section 4, error bounds).  Seeds are taken from pool (host [pool_len]
+ * input ids, checked), in order, `group` (1..512) at a time; after each
+ * group the per-round counts of all seeds so far are summed, and with
+ * eps = sqrt(ln(2 / delta) / (2 s)) the run stops at the first group after
+ * which eps x D / alpha <= target, where D and alpha = (T - s) / (s (n - 1))
+ * are the sample's (the average distance's half-width at confidence
+ * 1 - delta, with the sample's values for the unknown Delta and alpha; 0
+ * when D = 0), or when the pool runs out.  0 < delta < 1, target >= 0.
+ * counts (host [cap_rounds], zeroed first) receives the summed counts
+ * c[0..D] of the seeds used; out the figures below.  opt (NULL: defaults)
+ * sets the engine and scheduler of the runs.  One graph only.  PP_ERANGE if
+ * D >= cap_rounds.
+ */
+typedef struct {
+    int32_t seeds;          /* seeds used */
+    int32_t groups;         /* groups run */
+    int32_t met;            /* 1: the bound met the target; 0: the pool ran out first */
+    int32_t D;              /* D of the sample */
+    double alpha;           /* the sample's connectivity rate */
+    double eps;             /* sqrt(ln(2 / delta) / (2 seeds)) */
+    double bound;           /* eps x D / alpha (0 when D = 0) */
+} pp_progress;
+int pp_progressive_sample(pp_graph g, const int32_t *pool, int32_t pool_len, int32_t group, double target,
+                          double delta, const pp_options *opt, int64_t *counts, int32_t cap_rounds,
+                          pp_progress *out);
+
+/*
  * pp_propagate_s -- PROPAGATE-S (Algorithm 2): the seeds one at a time with
  * one bit per node, each pass a synchronous bottom-up step in which a node
  * not reached yet stops at its first reached successor (the early break).

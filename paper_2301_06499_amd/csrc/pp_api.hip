@@ -1565,6 +1565,68 @@ extern "C" int pp_exact_counts(pp_graph g, int32_t group, const pp_options *opt,
     return dmax >= cap_rounds ? fail(PP_ERANGE, "D = %d does not fit cap_rounds = %d", dmax, cap_rounds) : PP_OK;
 }
 
+// Progressive sampling: groups of seeds from the pool until the average
+// distance's Hoeffding half-width (sample D and alpha) meets the target.
+extern "C" int pp_progressive_sample(pp_graph g, const int32_t *pool, int32_t pool_len, int32_t group, double target,
+                                     double delta, const pp_options *opt, int64_t *counts, int32_t cap_rounds,
+                                     pp_progress *out) {
+    if (!g || !pool || !counts || !out) return fail(PP_EINVAL, "graph, pool, counts or out is NULL");
+    if (g->G != 1) return fail(PP_EINVAL, "one graph only (got a batch of %d)", g->G);
+    if (pool_len < 1) return fail(PP_EINVAL, "pool_len < 1");
+    if (group < 1 || group > 512) return fail(PP_EINVAL, "group = %d outside [1, 512]", group);
+    if (!(delta > 0.0 && delta < 1.0)) return fail(PP_EINVAL, "delta outside (0, 1)");
+    if (!(target >= 0.0)) return fail(PP_EINVAL, "target < 0");
+    if (cap_rounds < 1) return fail(PP_EINVAL, "cap_rounds < 1");
+    int rc = check_host_seeds(g, pool, pool_len);
+    if (rc) return rc;
+    pp_options o;
+    pp_options_default(&o);
+    if (opt) o = *opt;
+    o.seed_counts = 0;
+    std::memset(counts, 0, sizeof(int64_t) * (size_t)cap_rounds);
+    std::memset(out, 0, sizeof(*out));
+    std::vector<int64_t> c((size_t)cap_rounds);
+    pp_run run = nullptr;
+    int32_t run_s = 0, used = 0, dmax = 0;
+    while (used < pool_len) {
+        const int32_t s = std::min(group, pool_len - used);
+        if (run && run_s != s) {
+            pp_run_free(run);
+            run = nullptr;
+        }
+        if (!run) {
+            rc = pp_seeds_init(g, pool + used, s, &o, nullptr, &run);
+            run_s = s;
+        } else {
+            rc = pp_seeds_reset(run, pool + used, 0);
+        }
+        int32_t d = 0;
+        if (rc == PP_OK) rc = pp_propagate_until_converged(run, 0, c.data(), cap_rounds, &d);
+        if (rc) break;
+        for (int32_t k = 0; k < cap_rounds; ++k) counts[k] += c[(size_t)k];
+        dmax = std::max(dmax, d);
+        used += s;
+        out->groups += 1;
+        if (dmax >= cap_rounds) break;
+        pp_metrics m;
+        if ((rc = pp_estimate_metrics(counts, dmax + 1, g->n, used, 9, 10, &m))) break;
+        const double eps = std::sqrt(std::log(2.0 / delta) / (2.0 * (double)used));
+        const double bound = dmax == 0 ? 0.0 : (m.alpha > 0.0 ? eps * (double)dmax / m.alpha : INFINITY);
+        out->seeds = used;
+        out->D = dmax;
+        out->alpha = m.alpha;
+        out->eps = eps;
+        out->bound = bound;
+        if (bound <= target) {
+            out->met = 1;
+            break;
+        }
+    }
+    if (run) pp_run_free(run);
+    if (rc) return rc;
+    return dmax >= cap_rounds ? fail(PP_ERANGE, "D = %d does not fit cap_rounds = %d", dmax, cap_rounds) : PP_OK;
+}
+
 // PROPAGATE-S: batches of `concurrent` seeds, each run to its last seed's
 // first pass without a find; the host checks every 8 passes.
 extern "C" int pp_propagate_s(pp_graph g, const int32_t *seeds, int32_t s, int32_t concurrent, void *stream,

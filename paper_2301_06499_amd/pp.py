@@ -43,6 +43,11 @@ class TuneEntry(ctypes.Structure):
                 ("persistent", ctypes.c_int32), ("ms", ctypes.c_float)]
 
 
+class Progress(ctypes.Structure):
+    _fields_ = [("seeds", ctypes.c_int32), ("groups", ctypes.c_int32), ("met", ctypes.c_int32), ("D", ctypes.c_int32),
+                ("alpha", ctypes.c_double), ("eps", ctypes.c_double), ("bound", ctypes.c_double)]
+
+
 class Metrics(ctypes.Structure):
     _fields_ = [("diameter", ctypes.c_int32), ("rounds_executed", ctypes.c_int32), ("R_final", ctypes.c_int64),
                 ("eff_diam", ctypes.c_double), ("eff_diam_interp", ctypes.c_double), ("avg_dist", ctypes.c_double),
@@ -59,7 +64,7 @@ EXPORTS = ["pp_options_default", "pp_csr_build", "pp_graph_arcs", "pp_graph_node
            "pp_run_snapshot", "pp_run_restore", "pp_run_free", "pp_graph_free", "pp_last_error",
            "pp_seeds_reset", "pp_get_kernel_times", "pp_run_set_mlp", "pp_get_round_features",
            "pp_time_round", "pp_mlp_forward", "pp_mlp_loss_grad", "pp_mlp_train", "pp_autotune", "pp_exact_counts",
-           "pp_propagate_s"]
+           "pp_propagate_s", "pp_progressive_sample"]
 
 MLP_IN, MLP_HID, MLP_OUT = 8, 32, 2
 MLP_PARAMS = MLP_HID * MLP_IN + MLP_HID + MLP_HID * MLP_HID + MLP_HID + MLP_OUT * MLP_HID + MLP_OUT   # 1410
@@ -102,6 +107,7 @@ def lib():
         "pp_autotune": (ctypes.c_int, [P, P, I32, P, I32, P, P, I32, P]),
         "pp_exact_counts": (ctypes.c_int, [P, I32, P, P, I32, P]),
         "pp_propagate_s": (ctypes.c_int, [P, P, I32, I32, P, P, I32, P, P]),
+        "pp_progressive_sample": (ctypes.c_int, [P, P, I32, I32, ctypes.c_double, ctypes.c_double, P, P, I32, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -430,6 +436,22 @@ def pp_exact_counts(graph: Graph, group: int = 512, opts: Options | None = None,
     _check(lib().pp_exact_counts(graph.handle, int(group), ctypes.byref(opts) if opts is not None else None,
                                  _np_ptr(c), cap, ctypes.byref(D)))
     return c[:D.value + 1].copy(), int(D.value)
+
+
+def pp_progressive_sample(graph: Graph, pool, group: int, target: float, delta: float, opts: Options | None = None,
+                          cap_rounds: int | None = None):
+    """Progressive sampling; returns a dict: counts c[0..D] of the seeds used, and the Progress figures."""
+    a = np.ascontiguousarray(pool, dtype=np.int32).reshape(-1)
+    cap = int(cap_rounds) if cap_rounds else graph.nodes + 1
+    c = np.zeros(cap, dtype=np.int64)
+    out = Progress()
+    _check(lib().pp_progressive_sample(graph.handle, _np_ptr(a), int(a.shape[0]), int(group), float(target),
+                                       float(delta), ctypes.byref(opts) if opts is not None else None,
+                                       _np_ptr(c), cap, ctypes.byref(out)))
+    res = {k: getattr(out, k) for k, _ in Progress._fields_}
+    res["met"] = bool(res["met"])
+    res["counts"] = c[:out.D + 1].copy()
+    return res
 
 
 def pp_propagate_s(graph: Graph, seeds, concurrent: int = 0, cap_rounds: int | None = None, stream=None):

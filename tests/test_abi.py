@@ -30,6 +30,7 @@ def test_every_declared_symbol_is_exported():
 
 def test_struct_layouts_match_header():
     assert ctypes.sizeof(pp.Options) == 48
+    assert ctypes.sizeof(pp.Progress) == 4 * 4 + 3 * 8
     assert ctypes.sizeof(pp.Metrics) == 4 + 4 + 8 + 6 * 8
 
 
@@ -56,6 +57,7 @@ def test_validation_before_device_work():
     assert L.pp_propagate_until_converged(None, 0, None, 0, None) == pp.PP_EINVAL
     assert L.pp_get_signatures(None, None, 0) == pp.PP_EINVAL
     assert L.pp_propagate_s(None, None, 1, 0, None, None, 1, None, None) == pp.PP_EINVAL
+    assert L.pp_progressive_sample(None, None, 1, 1, 1.0, 0.05, None, None, 1, None) == pp.PP_EINVAL
     assert "NULL" in L.pp_last_error().decode()
 
 

@@ -411,6 +411,30 @@ def test_propagate_s_long_lists_and_errors():
     assert e.value.code == pp.PP_EINVAL
 
 
+# ------------------------------------------------------------ progressive sampling
+
+@pytest.mark.parametrize("case", range(4))
+def test_progressive_sample(case):
+    """Seed groups until the Hoeffding half-width meets the target: the same groups, the
+    same summed counts and the same float64 figures as the oracle (exact integers, one
+    rounding each, the same libm), including a run whose pool runs out."""
+    import oracle.progressive as prog
+    g, group, target, delta = [(gen.erdos_renyi_gnm(2000, 6000, 3), 64, 0.5, 0.05),
+                               (gen.rmat(12, 8, 9), 100, 1.2, 0.1),
+                               (gen.cycle_graph(301), 17, 25.0, 0.05),
+                               (gen.grid_with_shortcuts(30, 30, gen.Fraction(1, 10), 10, 4), 32, 0.01, 0.05)][case]
+    rng = np.random.default_rng(70 + case)
+    pool = rng.integers(0, g.n, 600).astype(np.int32)
+    say("progressive", g.name, "group", group, "target", target)
+    want = prog.progressive(g.n, g.src, g.dst, pool, group, target, delta, g.undirected)
+    G = pp.pp_csr_build(g.n, g.src, g.dst, undirected=g.undirected)
+    got = pp.pp_progressive_sample(G, pool, group, target, delta)
+    assert list(got["counts"]) == list(want["counts"])
+    for k in ("seeds", "groups", "met", "D", "alpha", "eps", "bound"):
+        assert got[k] == want[k], k
+    assert got["met"] == (case != 3) and got["groups"] > 1
+
+
 def test_grid4096_full_size():
     """The 4096^2 grid with deletions and shortcuts, s = 128, at full size: per-round
     counts, D and every signature against the oracle (all 128 BFS on the host),
