@@ -11,7 +11,10 @@
  * does), and counts the newly set bits c[r] = sum_u popcount(Sig_r(u) XOR
  * Sig_{r-1}(u)) -- the number of (node, seed) pairs at distance exactly r.
  * The loop stops at the first round that sets no bit.  The metrics of the
- * paper's Section 3 are then estimated from c[0..D].
+ * paper's Section 3 are then estimated from c[0..D].  The library also runs
+ * PROPAGATE-S (Algorithm 2: the seeds one at a time, one bit per node),
+ * the exact neighbourhood function (every node a seed) and progressive
+ * sampling with a Hoeffding stopping rule (Section 4, error bounds).
  *
  * Conventions shared by every entry point
  *   - Every function returns a pp_status (0 = success, < 0 = error); none
@@ -228,7 +231,8 @@ int pp_get_round_log(pp_run r, int32_t *mode, int64_t *arcs, int32_t cap);
  * pull launches (HIP events on the run's stream), summed over every
  * propagation since the run was created (pp_seeds_reset keeps the sums, so
  * a caller differences two reads around repeated runs).  A launch in a push
- * round returns at once and is still timed.  With opt.persistent the value
+ * round returns at once (or, after a pull round, lists the push's frontier)
+ * and is still timed.  With opt.persistent the value
  * is the main phase of round r (pull, or push for a push round) measured by
  * the device clock between the grid barriers around it.  Host array of cap
  * entries. */
