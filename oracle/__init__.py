@@ -20,6 +20,8 @@ Contents
                     small graphs.
 ``brute_force_counts``  all-pairs distances by repeated boolean matrix
                     products, for tiny graphs.
+``node_stats``      (module ``oracle.node_stats``) per-node reach counts and
+                    distance sums to the seeds, from the BFS distances.
 ``progressive``     (module ``oracle.progressive``) seed groups added until a
                     Hoeffding half-width of the average distance meets a
                     target (Section 4 error bounds).
