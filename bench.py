@@ -453,6 +453,9 @@ def main():
                          "and seed; progressive: seed groups until the average distance's Hoeffding half-width "
                          "meets --target (each its own JSON line)")
     ap.add_argument("--target", type=float, default=1.0, help="progressive: half-width target (hops)")
+    ap.add_argument("--node-stats", action="store_true",
+                    help="also keep the per-node reach and distance sums (one extra pass per round), "
+                         "checked against the oracle after timing")
     ap.add_argument("--delta", type=float, default=0.05, help="progressive: 1 - confidence")
     ap.add_argument("--concurrent", type=int, default=0, help="PROPAGATE-S: seeds in flight (0: min(s, 256))")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -490,7 +493,7 @@ def main():
     log(f"[bench] csr_build {time.perf_counter() - t0:.1f} s: n={G.nodes} arcs={G.arcs}")
     dseeds = torch.from_numpy(seeds.astype(np.int32)).to("cuda")
     torch.cuda.synchronize()
-    base = pp.options(scheduler=sched, max_rounds=4096, persistent=args.persistent)
+    base = pp.options(scheduler=sched, max_rounds=4096, persistent=args.persistent, node_stats=args.node_stats)
     tuned = None
     if args.tune:
         from paper_2301_06499_amd import autotune
@@ -621,6 +624,14 @@ def main():
                               "ms_per_step": round(tg * 1000.0, 4), "value": nominal / tg}
         for rg in runs_g:
             rg.free()
+    if args.node_stats:
+        import oracle.node_stats as ons
+        gr, gd = pp.pp_get_node_stats(run)
+        wr, wd = ons.node_stats(g.n, g.src, g.dst, seeds, g.undirected)
+        out["config"]["node_stats"] = True
+        out["node_stats_check"] = {"against": "oracle per-seed BFS distances, every node",
+                                   "result": "bit-exact" if np.array_equal(gr, wr) and np.array_equal(gd, wd)
+                                   else "MISMATCH"}
     check = args.check_seeds if args.check_seeds >= 0 else (8 if args.workload == "rmat26" else 0)
     if check:
         log(f"[bench] checking {check} sampled seeds against the oracle")

@@ -98,7 +98,8 @@ typedef struct {
                                    tile (64 K arcs) and so the high-degree threshold
                                    (longer lists are split into tile-sized chunks).
                                    The persistent engine uses 4. */
-    int32_t pad;                /* zero */
+    int32_t node_stats;         /* 1: per-node reach and distance sums (pp_get_node_stats);
+                                   the per-round engine only */
 } pp_options;
 
 /* Metrics estimated from c[0..D] (paper Section 3 and Algorithm 1's closing
@@ -237,6 +238,21 @@ int pp_get_round_log(pp_run r, int32_t *mode, int64_t *arcs, int32_t cap);
  * the device clock between the grid barriers around it.  Host array of cap
  * entries. */
 int pp_get_kernel_times(pp_run r, float *pull_ms, int32_t cap);
+
+/*
+ * pp_get_node_stats -- per-node outputs for centrality estimates (needs
+ * opt.node_stats): for every node u (host arrays [n], by input node id)
+ *   reached[u]  = the seeds u reaches within the rounds run so far (seed bits
+ *                 set in Sig(u); a repeated seed counts once per bit),
+ *   dist_sum[u] = the sum of d(u, x_i) over those seeds.
+ * The paper leaves per-node centralities to future work and defines none:
+ * these are the plain per-node quantities the propagation determines, from
+ * which a caller forms sampled closeness or similar estimates.  The run
+ * keeps, per node, the sum of popcount(Sig(u)) over its states (after the
+ * initialisation and after every round run), one extra pass per round.
+ * Synchronises.  PP_ESTATE if the run was created without node_stats.
+ */
+int pp_get_node_stats(pp_run r, int32_t *reached, int64_t *dist_sum);
 
 /* Copy of a run's whole state (signatures, frontier, logs) / restore from a
  * copy of the same graph and s.  A restored run continues bit-identically. */

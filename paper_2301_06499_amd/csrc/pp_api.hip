@@ -623,6 +623,7 @@ void free_run_dev(RunDev &d) {
     dev_free(d.tickets);
     dev_free(d.post_part);
     dev_free(d.mlp);
+    dev_free(d.node_acc);
 }
 
 void drop_graphs(pp_run r) {
@@ -707,6 +708,7 @@ hipError_t clear_run_dev(pp_graph g, RunDev &d, hipStream_t st, bool with_acc) {
         seg(d.feat_log, 4 * cap * pp::MLP_IN * G, 0u),
         seg(d.ctrl, (int64_t)sizeof(Ctrl) * G, 0u),
         seg(d.tickets, 4 * pp::TICKET_INTS, 0u),
+        seg(d.node_acc, d.node_acc ? 8 * n : 0, 0u),
     };
     return pp::launch_fills(segs, (int)(sizeof(segs) / sizeof(segs[0])), st);
 }
@@ -966,6 +968,8 @@ extern "C" int pp_seeds_init(pp_graph g, const int32_t *seeds, int32_t s, const 
     if (o.pull_k == 0) o.pull_k = 4;
     if (o.pull_k != 2 && o.pull_k != 4) return fail(PP_EINVAL, "pull_k = %d: 2 or 4 arcs per lane", o.pull_k);
     if (o.persistent && o.pull_k != 4) return fail(PP_EINVAL, "the persistent engine pulls with 4 arcs per lane");
+    if (o.node_stats && o.persistent) return fail(PP_EINVAL, "per-node statistics need the per-round engine");
+    if (o.node_stats != 0 && o.node_stats != 1) return fail(PP_EINVAL, "node_stats must be 0 or 1");
     if (o.scheduler < PP_SCHED_HEURISTIC || o.scheduler > PP_SCHED_MLP) return fail(PP_EINVAL, "unknown scheduler %d", o.scheduler);
     if (o.max_rounds < 0 || o.rounds_per_sync < 0) return fail(PP_EINVAL, "negative max_rounds / rounds_per_sync");
     const int G = g->G;
@@ -1018,6 +1022,7 @@ extern "C" int pp_seeds_init(pp_graph g, const int32_t *seeds, int32_t s, const 
     if (rc == PP_OK)
         rc = alloc_run_dev(g, r->dev, s, W, (int)cap, o.seed_counts != 0, std::max(pp::pull_grid_for(ts->ntiles), r->pgrid));
     if (rc == PP_OK) rc = dev_alloc(&r->dseeds, (int64_t)G * s);
+    if (rc == PP_OK && o.node_stats) rc = dev_alloc(&r->dev.node_acc, g->n);
     if (rc == PP_OK && r->pgrid) {
         r->clusters = make_clusters(g, ts, r->pgrid);
         rc = dev_alloc(&r->dclusters, (int64_t)r->clusters.size());
@@ -1394,6 +1399,7 @@ extern "C" int pp_run_restore(pp_run r, pp_run from) {
     if (!e) e = cp(b.feat_log, a.feat_log, sizeof(float) * pp::MLP_IN * cap * G);
     if (!e) e = cp(b.mlp, a.mlp, sizeof(float) * pp::MLP_PARAMS);
     if (!e) e = cp(b.tickets, a.tickets, sizeof(int32_t) * pp::TICKET_INTS);
+    if (!e && b.node_acc && a.node_acc) e = cp(b.node_acc, a.node_acc, sizeof(int64_t) * n);
     if (!e) e = cp(b.ctrl, a.ctrl, sizeof(Ctrl) * G);
     if (!e) e = cp(b.bar, a.bar, sizeof(pp::GridBar) * G);
     if (!e) e = hipStreamSynchronize(st);
@@ -1407,6 +1413,40 @@ extern "C" int pp_run_restore(pp_run r, pp_run from) {
     r->counts_host = from->counts_host;
     r->D_host = from->D_host;
     r->acc_clean = from->acc_clean;
+    return PP_OK;
+}
+
+extern "C" int pp_get_node_stats(pp_run r, int32_t *reached, int64_t *dist_sum) {
+    if (!r || !reached || !dist_sum) return fail(PP_EINVAL, "run, reached or dist_sum is NULL");
+    if (!r->dev.node_acc) return fail(PP_ESTATE, "run created without node_stats");
+    int rc = sync_ctrl(r);
+    if (rc) return rc;
+    // states accumulated: the initialisation and every round run
+    const int64_t K = (int64_t)r->host_ctrl.round + (r->host_ctrl.converged ? 1 : 0);
+    const int64_t n = r->g->n;
+    int32_t *dr = nullptr;
+    int64_t *dd = nullptr;
+    if ((rc = dev_alloc(&dr, n)) || (rc = dev_alloc(&dd, n))) {
+        dev_free(dr);
+        return rc;
+    }
+    std::vector<int32_t> hr((size_t)n);
+    std::vector<int64_t> hd((size_t)n);
+    // the per-round engine (node_stats excludes the clustered one) keeps Sig in one buffer
+    hipError_t e = pp::launch_node_stats(r->dev.sig[r->host_ctrl.cur & 1], r->dev.node_acc, n, r->W, K, dr, dd,
+                                         r->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(hr.data(), dr, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToHost, r->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(hd.data(), dd, sizeof(int64_t) * (size_t)n, hipMemcpyDeviceToHost, r->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(r->stream);
+    dev_free(dr);
+    dev_free(dd);
+    if (e != hipSuccess) return fail(PP_EDEVICE, "node statistics: %s", hipGetErrorString(e));
+    const std::vector<int32_t> &perm = r->g->perm;
+    for (int64_t u = 0; u < n; ++u) {
+        const size_t x = perm.empty() ? (size_t)u : (size_t)perm[(size_t)u];
+        reached[u] = hr[x];
+        dist_sum[u] = hd[x];
+    }
     return PP_OK;
 }
 

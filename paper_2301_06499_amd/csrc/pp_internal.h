@@ -93,6 +93,8 @@ struct Ctrl {
     int64_t reached;      // new bits of every round so far (R[r] - s)
     int64_t last_count;   // new bits of the last round
     float feat[8];        // scheduler features of the round about to run
+    int32_t acc_pending;  // a round (or the initialisation) ran since the last per-node accumulation
+    int32_t pad_ctrl;
 };
 
 static_assert(sizeof(Ctrl) % 4 == 0, "the control block is staged to the host as 32-bit words");
@@ -191,6 +193,7 @@ struct RunDev {
     int32_t pad2;
     uint64_t fuzz_seed;
     float *mlp;           // [MLP_PARAMS] cost-model weights (NaN: not set, heuristic decides)
+    int64_t *node_acc;    // [n] per-node sums of popcount(Sig_r(u)) over the states so far, or NULL
 };
 
 // Records the message returned by pp_last_error and returns `code`.
@@ -231,6 +234,11 @@ constexpr int SEQ_LIGHT = 32;
 // Pass r (short lists, then heavy[0..nheavy)) and its per-seed end.
 hipError_t launch_seq_pass(const GraphDev &g, const SeqDev &S, const int32_t *heavy, int64_t nheavy, int r,
                            int blocks_per_seed, int heavy_blocks_per_seed, hipStream_t st);
+
+// Per-node statistics: reached[u] = popcount of u's row of sig, dist_sum[u]
+// = K reached[u] - acc[u] (K states accumulated).
+hipError_t launch_node_stats(const uint64_t *sig, const int64_t *acc, int64_t n, int W, int64_t K, int32_t *reached,
+                             int64_t *dist_sum, hipStream_t st);
 
 hipError_t launch_stage(const void *ctrl, int64_t ctrl_bytes, const int32_t *D, int64_t nD, const int64_t *rows,
                         int64_t nrows, void *h_ctrl, int32_t *h_D, int64_t *h_rows, hipStream_t st);

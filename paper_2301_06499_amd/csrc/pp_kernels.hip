@@ -1289,6 +1289,7 @@ PP_DEV void phase_round_end(const GraphDev &g, const RunDev &R, int init, int np
     }
     __syncthreads();
     if (threadIdx.x == 0) {
+        C->acc_pending = 1;   // a state for the per-node sums
         R.mode_log[r] = mode;
         R.arcs_log[r] = mode == MODE_PULL ? pulled : (mode == MODE_PUSH ? prev_arcs : 0);
         // the arcs of the nodes changed in this round: a following push's work
@@ -1397,7 +1398,10 @@ PP_DEV bool last_block(int32_t *tickets, int bid, int nb) {
 // release waits for them without writing back the caches).
 template <int W> __global__ void __launch_bounds__(BLOCK) k_post(GraphDev g, RunDev R) {
     Ctrl *C = R.ctrl;
-    if (CTL(C->converged)) return;   // set only by the last block, after every block has finished
+    if (CTL(C->converged)) {   // set only by the last block, after every block has finished
+        if (blockIdx.x == 0 && threadIdx.x == 0) PUT(C->acc_pending, 0);   // no round ran in this slot
+        return;
+    }
     if (CTL(C->mode) == MODE_PUSH) phase_push_commit<W>(g, R, 0, blockIdx.x, gridDim.x, R.post_part);
     else phase_pull_hubs<W>(g, R, blockIdx.x, gridDim.x, R.post_part);
     __shared__ int s_last;
@@ -1408,6 +1412,39 @@ template <int W> __global__ void __launch_bounds__(BLOCK) k_post(GraphDev g, Run
     if (!s_last) return;
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
     phase_round_end(g, R, 0, g.pull_grid, R.post_part, (int)gridDim.x);
+}
+
+// Per-node sums for reach and distance statistics: after the initialisation
+// and after every round that ran, each node adds the popcount of its current
+// signature.  A seed bit that u gains at round d stays, so over the states
+// 0..E it is counted E - d + 1 times, and sum_i d(u, x_i) = (E + 1) reached(u)
+// - sum (see k_node_stats).
+template <int W> __global__ void __launch_bounds__(BLOCK) k_node_acc(GraphDev g, RunDev R) {
+    Ctrl *C = R.ctrl;
+    if (!CTL(C->acc_pending)) return;
+    const uint64_t *sig = sel(R.sig, CTL(C->cur));
+    for (int64_t u = blockIdx.x * (int64_t)BLOCK + threadIdx.x; u < g.n; u += (int64_t)gridDim.x * BLOCK) {
+        int c = 0;
+#pragma unroll
+        for (int w = 0; w < W; ++w) c += __popcll(sig[u * W + w]);
+        if (c) R.node_acc[u] += c;
+    }
+}
+
+__global__ void __launch_bounds__(BLOCK) k_node_stats(const uint64_t *sig, const int64_t *acc, int64_t n, int W,
+                                                      int64_t K, int32_t *reached, int64_t *dist_sum) {
+    for (int64_t u = blockIdx.x * (int64_t)BLOCK + threadIdx.x; u < n; u += (int64_t)gridDim.x * BLOCK) {
+        int c = 0;
+        for (int w = 0; w < W; ++w) c += __popcll(sig[u * W + w]);
+        reached[u] = c;
+        dist_sum[u] = K * (int64_t)c - acc[u];
+    }
+}
+
+hipError_t launch_node_stats(const uint64_t *sig, const int64_t *acc, int64_t n, int W, int64_t K, int32_t *reached,
+                             int64_t *dist_sum, hipStream_t st) {
+    hipLaunchKernelGGL(k_node_stats, dim3(fill_grid(n)), dim3(BLOCK), 0, st, sig, acc, n, W, K, reached, dist_sum);
+    return hipGetLastError();
 }
 
 // New cost-model weights for a run in progress: the direction of the round
@@ -1637,11 +1674,13 @@ static hipError_t seed_init_impl(const GraphDev &g, const RunDev &R, const int32
     const int64_t total = (int64_t)R.G * R.s;
     if (total <= SEED_INIT_ONE_BLOCK) {
         hipLaunchKernelGGL(k_seed_init<W>, dim3(1), dim3(BLOCK), 0, st, g, R, seeds, map, total);
+        if (R.node_acc) hipLaunchKernelGGL(k_node_acc<W>, dim3(list_grid(g)), dim3(BLOCK), 0, st, g, R);
         return hipGetLastError();
     }
     hipLaunchKernelGGL(k_seed_scatter<W>, dim3(fill_grid(total)), dim3(BLOCK), 0, st, g, R, seeds, map, total);
     hipLaunchKernelGGL(k_push_commit<W>, dim3(fill_grid(total * W)), dim3(BLOCK), 0, st, g, R, 1);
     hipLaunchKernelGGL(k_round_end, dim3(1), dim3(BLOCK), 0, st, g, R, 1);
+    if (R.node_acc) hipLaunchKernelGGL(k_node_acc<W>, dim3(list_grid(g)), dim3(BLOCK), 0, st, g, R);
     return hipGetLastError();
 }
 
@@ -1659,6 +1698,7 @@ static hipError_t round_impl(const GraphDev &g, const RunDev &R, hipStream_t st,
     }
     hipLaunchKernelGGL(k_push<W>, dim3(list_grid(g)), dim3(BLOCK), 0, st, g, R);
     hipLaunchKernelGGL(k_post<W>, dim3(post_grid(g)), dim3(BLOCK), 0, st, g, R);
+    if (R.node_acc) hipLaunchKernelGGL(k_node_acc<W>, dim3(list_grid(g)), dim3(BLOCK), 0, st, g, R);
     return hipGetLastError();
 }
 

@@ -35,7 +35,7 @@ class Options(ctypes.Structure):
     _fields_ = [("scheduler", ctypes.c_int32), ("seed_counts", ctypes.c_int32), ("max_rounds", ctypes.c_int32),
                 ("rounds_per_sync", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("push_div", ctypes.c_int32),
                 ("fuzz_seed", ctypes.c_uint64), ("time_kernels", ctypes.c_int32), ("persistent", ctypes.c_int32),
-                ("pull_k", ctypes.c_int32), ("pad", ctypes.c_int32)]
+                ("pull_k", ctypes.c_int32), ("node_stats", ctypes.c_int32)]
 
 
 class TuneEntry(ctypes.Structure):
@@ -64,7 +64,7 @@ EXPORTS = ["pp_options_default", "pp_csr_build", "pp_graph_arcs", "pp_graph_node
            "pp_run_snapshot", "pp_run_restore", "pp_run_free", "pp_graph_free", "pp_last_error",
            "pp_seeds_reset", "pp_get_kernel_times", "pp_run_set_mlp", "pp_get_round_features",
            "pp_time_round", "pp_mlp_forward", "pp_mlp_loss_grad", "pp_mlp_train", "pp_autotune", "pp_exact_counts",
-           "pp_propagate_s", "pp_progressive_sample"]
+           "pp_propagate_s", "pp_progressive_sample", "pp_get_node_stats"]
 
 MLP_IN, MLP_HID, MLP_OUT = 8, 32, 2
 MLP_PARAMS = MLP_HID * MLP_IN + MLP_HID + MLP_HID * MLP_HID + MLP_HID + MLP_OUT * MLP_HID + MLP_OUT   # 1410
@@ -108,6 +108,7 @@ def lib():
         "pp_exact_counts": (ctypes.c_int, [P, I32, P, P, I32, P]),
         "pp_propagate_s": (ctypes.c_int, [P, P, I32, I32, P, P, I32, P, P]),
         "pp_progressive_sample": (ctypes.c_int, [P, P, I32, I32, ctypes.c_double, ctypes.c_double, P, P, I32, P]),
+        "pp_get_node_stats": (ctypes.c_int, [P, P, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -139,7 +140,8 @@ def _is_device(a) -> bool:
 
 
 def options(scheduler=PP_SCHED_HEURISTIC, seed_counts=False, max_rounds=0, rounds_per_sync=0,
-            use_graph=True, push_div=0, fuzz_seed=0, time_kernels=False, persistent=False, pull_k=0) -> Options:
+            use_graph=True, push_div=0, fuzz_seed=0, time_kernels=False, persistent=False, pull_k=0,
+            node_stats=False) -> Options:
     o = Options()
     lib().pp_options_default(ctypes.byref(o))
     o.scheduler = scheduler
@@ -153,6 +155,7 @@ def options(scheduler=PP_SCHED_HEURISTIC, seed_counts=False, max_rounds=0, round
     o.time_kernels = int(bool(time_kernels))
     o.persistent = int(bool(persistent))
     o.pull_k = int(pull_k)
+    o.node_stats = int(bool(node_stats))
     return o
 
 
@@ -323,6 +326,15 @@ def pp_get_signatures(run: Run, out=None):
     a = np.zeros((n, W), dtype=np.uint64)
     _check(lib().pp_get_signatures(run.handle, _np_ptr(a), 0))
     return a
+
+
+def pp_get_node_stats(run: Run):
+    """Per-node (reached int32 [n], dist_sum int64 [n]) by input node id (needs options(node_stats=True))."""
+    n = run.graph.nodes
+    reached = np.zeros(n, dtype=np.int32)
+    dist_sum = np.zeros(n, dtype=np.int64)
+    _check(lib().pp_get_node_stats(run.handle, _np_ptr(reached), _np_ptr(dist_sum)))
+    return reached, dist_sum
 
 
 def pp_get_seed_counts(run: Run, cap_rounds: int):

@@ -58,6 +58,7 @@ def test_validation_before_device_work():
     assert L.pp_get_signatures(None, None, 0) == pp.PP_EINVAL
     assert L.pp_propagate_s(None, None, 1, 0, None, None, 1, None, None) == pp.PP_EINVAL
     assert L.pp_progressive_sample(None, None, 1, 1, 1.0, 0.05, None, None, 1, None) == pp.PP_EINVAL
+    assert L.pp_get_node_stats(None, None, None) == pp.PP_EINVAL
     assert "NULL" in L.pp_last_error().decode()
 
 

@@ -411,6 +411,60 @@ def test_propagate_s_long_lists_and_errors():
     assert e.value.code == pp.PP_EINVAL
 
 
+# ------------------------------------------------------------ per-node statistics
+
+NS_CASES = [("er", lambda: gen.erdos_renyi_gnm(500, 1500, 8), 70),
+            ("rmat", lambda: gen.rmat(11, 8, 3), 130),
+            ("grid", lambda: gen.grid_with_shortcuts(25, 20, gen.Fraction(1, 10), 8, 6), 64),
+            ("dpath", lambda: gen.path_graph(90, directed=True), 10)]
+
+
+@pytest.mark.parametrize("case", range(len(NS_CASES)))
+@pytest.mark.parametrize("sched", SCHEDS)
+@pytest.mark.parametrize("keep_order", [False, True])
+def test_node_stats(case, sched, keep_order):
+    """Per-node reach counts and distance sums after convergence and after each of the
+    first rounds, against the oracle's BFS distances, for every direction policy."""
+    import oracle.node_stats as ons
+    name, make, s = NS_CASES[case]
+    g = make()
+    seeds = gen.sample_seeds(g.n, s, 21 + case)
+    seeds[2] = seeds[1]
+    say("node_stats", name, "sched", sched, "keep_order", keep_order)
+    want = oracle.propagate(g.n, g.src, g.dst, seeds, g.undirected)
+    G = pp.pp_csr_build(g.n, g.src, g.dst, undirected=g.undirected, keep_order=keep_order)
+    r = pp.pp_seeds_init(G, seeds, opts=pp.options(scheduler=sched, fuzz_seed=case, node_stats=True,
+                                                    max_rounds=want["D"] + 4))
+    for k in range(0, 4):
+        if k:
+            pp.pp_propagate_round(r)
+        wr, wd = ons.node_stats(g.n, g.src, g.dst, seeds, g.undirected, rounds=k)
+        gr, gd = pp.pp_get_node_stats(r)
+        assert np.array_equal(gr, wr) and np.array_equal(gd, wd), k
+    pp.pp_propagate_until_converged(r)
+    wr, wd = ons.node_stats(g.n, g.src, g.dst, seeds, g.undirected)
+    gr, gd = pp.pp_get_node_stats(r)
+    assert np.array_equal(gr, wr) and np.array_equal(gd, wd)
+    # a reset starts the sums again; extra no-op replays after convergence add nothing
+    pp.pp_seeds_reset(r, seeds)
+    pp.pp_propagate_until_converged(r)
+    pp.pp_propagate_round(r)
+    gr, gd = pp.pp_get_node_stats(r)
+    assert np.array_equal(gr, wr) and np.array_equal(gd, wd)
+
+
+def test_node_stats_errors():
+    g = gen.path_graph(20)
+    G = pp.pp_csr_build(g.n, g.src, g.dst, undirected=True)
+    r = pp.pp_seeds_init(G, np.array([0, 5], np.int32))
+    with pytest.raises(pp.PPError) as e:
+        pp.pp_get_node_stats(r)
+    assert e.value.code == pp.PP_ESTATE
+    with pytest.raises(pp.PPError) as e:
+        pp.pp_seeds_init(G, np.array([0, 5], np.int32), opts=pp.options(node_stats=True, persistent=True))
+    assert e.value.code == pp.PP_EINVAL
+
+
 # ------------------------------------------------------------ progressive sampling
 
 @pytest.mark.parametrize("case", range(4))
