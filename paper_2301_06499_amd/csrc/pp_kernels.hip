@@ -648,6 +648,40 @@ PP_DEV void phase_pull(const GraphDev &g, const RunDev &R, int bid, int nb) {
             own[j] = (!hub && idx < nn * W) ? sig[(int64_t)T.u0 * W + idx] : 0;
         }
 
+        // a tile whose lists are all short (one- and two-word rows, at most
+        // NPL successors): one lane per node walks its own list, so load j
+        // of the wave takes the j-th successor of 64 consecutive nodes
+        // (neighbouring rows on a lattice: few cache lines per load)
+        constexpr int NPL = 6;
+        int dmax = 0;
+        if constexpr (W <= 2) {
+            if (!hub) {
+                int d = ln < nn ? rp_l[ln + 1] - rp_l[ln] : 0;
+#pragma unroll
+                for (int o = 32; o > 0; o >>= 1) d = max(d, __shfl_xor(d, o));
+                dmax = d;
+            }
+        }
+        if (W <= 2 && !hub && dmax <= NPL) {
+            const int b0 = ln < nn ? rp_l[ln] : 0;
+            const int d = ln < nn ? rp_l[ln + 1] - b0 : 0;
+            uint64_t rows[NPL][W];
+#pragma unroll
+            for (int j = 0; j < NPL; ++j) {
+#pragma unroll
+                for (int w = 0; w < W; ++w) rows[j][w] = 0;
+                if (j < d) load_row<W>(sig + (int64_t)col_l[b0 + j] * W, rows[j]);
+            }
+            if (ln < nn) {
+#pragma unroll
+                for (int w = 0; w < W; ++w) {
+                    uint64_t a = 0;
+#pragma unroll
+                    for (int j = 0; j < NPL; ++j) a |= rows[j][w];
+                    acc_l[ln * W + w] = a;
+                }
+            }
+        } else {
         // gather: a group of L lanes shares arcs [a, a + KG); each lane loads
         // and ORs its P-word slice of every source row (one 16-byte load per
         // lane, so the group's loads of one row fall in one cache line and
@@ -692,6 +726,7 @@ PP_DEV void phase_pull(const GraphDev &g, const RunDev &R, int bid, int nb) {
                 }
             }
             flush_lds<P>(acc_l + i * W + sub * P, acc);
+        }
         }
         if (ln == 0) pulled += ne;
 
