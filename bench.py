@@ -498,8 +498,7 @@ def main():
     if args.tune:
         from paper_2301_06499_amd import autotune
         t0 = time.perf_counter()
-        base, tuned = autotune.tune(G, seeds, base=base, reps=3, name=cfg["workload"],
-                                    cache_path=os.path.join(ROOT, "gpurun_out", "pp_tune.json"))
+        base, tuned = autotune.tune(G, seeds, base=base, reps=3, name=cfg["workload"])
         tuned = {k: v for k, v in tuned.items() if k != "candidates"} | {"tune_s": round(time.perf_counter() - t0, 2)}
         log(f"[bench] tuned options {tuned}")
     # two runs of the same workload: the throughput is timed without kernel
