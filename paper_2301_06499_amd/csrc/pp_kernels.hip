@@ -1517,7 +1517,7 @@ hipError_t launch_redecide(const RunDev &R, int nctrl, hipStream_t st) {
 PP_DEV bool cluster_barrier(GridBar *b, int bid, int nb) {
     __shared__ int s_abort;
     __syncthreads();
-    if (nb == 1) return CTL(b->abort) == 0;
+    if (nb == 1) return true;   // one block: nothing to wait for, and no one to time out
     if (threadIdx.x == 0) {
         const uint32_t ng = nb < 8 ? (uint32_t)nb : 8u;
         const uint32_t grp = (uint32_t)bid % ng;
@@ -1614,21 +1614,35 @@ __global__ void __launch_bounds__(BLOCK) k_batch(GraphDev g, RunDev R, const Clu
     GraphDev gv;
     RunDev rv;
     cluster_view(g, R, cl, gv, rv);
+    // A cluster of one block keeps its control block in LDS for the launch:
+    // every read of it in a round is then an LDS access instead of a trip to
+    // the L2, and no other block reads it before the launch ends.
+    __shared__ Ctrl s_ctrl;
+    Ctrl *const gctrl = rv.ctrl;
+    const bool local = nb == 1;
+    constexpr int CTRL_WORDS = (int)(sizeof(Ctrl) / 4);
+    if (local) {
+        for (int i = threadIdx.x; i < CTRL_WORDS; i += BLOCK)
+            reinterpret_cast<int32_t *>(&s_ctrl)[i] = reinterpret_cast<const int32_t *>(gctrl)[i];
+        __syncthreads();
+        rv.ctrl = &s_ctrl;
+    }
     Ctrl *C = rv.ctrl;
     GridBar *bar = rv.bar;
     const bool lead = bid == 0 && threadIdx.x == 0;
+    bool ok = true;
     if (CTL(C->round) == 0 && !CTL(C->converged)) {
         phase_push_commit<W, 1>(gv, rv, 1, bid, nb);
-        if (!cluster_barrier(bar, bid, nb)) return;
-        if (bid == 0) phase_round_end(gv, rv, 1, nb);
-        if (!cluster_barrier(bar, bid, nb)) return;
+        ok = cluster_barrier(bar, bid, nb);
+        if (ok && bid == 0) phase_round_end(gv, rv, 1, nb);
+        if (ok) ok = cluster_barrier(bar, bid, nb);
     }
-    for (;;) {
+    while (ok) {
         const int conv = CTL(C->converged);
         const int r = CTL(C->round);
         const int mode = CTL(C->mode);
         const int prev = CTL(C->prev_mode);
-        if (conv || r > max_round || CTL(bar->abort)) break;
+        if (conv || r > max_round || (!local && CTL(bar->abort))) break;
         int64_t *stamp = r < rv.cap ? rv.phase_log + (int64_t)r * 3 : nullptr;
         if (lead && stamp) stamp[0] = (int64_t)wall_clock64();
         if (mode == MODE_PUSH) {
@@ -1653,6 +1667,11 @@ __global__ void __launch_bounds__(BLOCK) k_batch(GraphDev g, RunDev R, const Clu
         if (bid == 0) phase_round_end(gv, rv, 0, nb);
         if (lead && stamp) stamp[2] = (int64_t)wall_clock64();
         if (!cluster_barrier(bar, bid, nb)) break;
+    }
+    if (local) {   // the control block back for the host and the next launch
+        __syncthreads();
+        for (int i = threadIdx.x; i < CTRL_WORDS; i += BLOCK)
+            reinterpret_cast<int32_t *>(gctrl)[i] = reinterpret_cast<const int32_t *>(&s_ctrl)[i];
     }
 }
 
