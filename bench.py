@@ -62,6 +62,11 @@ def workload(name: str):
     raise SystemExit(f"unknown workload {name}")
 
 
+# workloads whose dense pull launches have counter figures under profiles/
+TRAFFIC_PROFILES = {"rmat20": "k_pull_rmat20_s256", "rmat26": "k_pull_rmat26_s512",
+                    "grid:4096": "k_pull_grid4096_s128"}
+
+
 def measured_traffic(profile: str):
     """HBM bytes per launch from the committed counter summary, if the kernel is unchanged.
 
@@ -456,6 +461,8 @@ def main():
     ap.add_argument("--node-stats", action="store_true",
                     help="also keep the per-node reach and distance sums (one extra pass per round), "
                          "checked against the oracle after timing")
+    ap.add_argument("--sparse-pull", type=int, default=0, choices=[0, 1, 2],
+                    help="sparse rounds: 0 push, 1 sparse pull, 2 either per round (pseudo-random)")
     ap.add_argument("--delta", type=float, default=0.05, help="progressive: 1 - confidence")
     ap.add_argument("--concurrent", type=int, default=0, help="PROPAGATE-S: seeds in flight (0: min(s, 256))")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -493,7 +500,8 @@ def main():
     log(f"[bench] csr_build {time.perf_counter() - t0:.1f} s: n={G.nodes} arcs={G.arcs}")
     dseeds = torch.from_numpy(seeds.astype(np.int32)).to("cuda")
     torch.cuda.synchronize()
-    base = pp.options(scheduler=sched, max_rounds=4096, persistent=args.persistent, node_stats=args.node_stats)
+    base = pp.options(scheduler=sched, max_rounds=4096, persistent=args.persistent, node_stats=args.node_stats,
+                      sparse_pull=args.sparse_pull)
     tuned = None
     if args.tune:
         from paper_2301_06499_amd import autotune
@@ -562,8 +570,8 @@ def main():
     achieved = bytes_pull / t_pull / 1e9 if t_pull > 0 else 0.0
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": (measured_traffic({"rmat20": "k_pull_rmat20_s256", "rmat26": "k_pull_rmat26_s512"}[args.workload])
-                        if (args.workload in ("rmat20", "rmat26") and not base.persistent
+            "traffic": (measured_traffic(TRAFFIC_PROFILES[args.workload])
+                        if (args.workload in TRAFFIC_PROFILES and not base.persistent
                             and (base.pull_k or 4) == 4) else None),
             "kernel": f"k_batch<{W}> pull phase" if base.persistent else f"k_pull<{W}>",
             "timing": ("device clock between grid barriers" if base.persistent else
@@ -587,7 +595,9 @@ def main():
         "config": dict(cfg, nodes=n, arcs=m, words=W, rounds=rounds, diameter_lb=Dv,
                        scheduler=args.scheduler, engine="persistent" if base.persistent else "rounds",
                        pull_k=int(base.pull_k) or 4, push_div=int(base.push_div) or 8, tuned=tuned,
-                       modes="".join("P" if modes[r] == pp.MODE_PULL else "S" for r in range(1, rounds + 1))),
+                       sparse_pull=int(base.sparse_pull),
+                       modes="".join({pp.MODE_PULL: "P", pp.MODE_PUSH: "S", pp.MODE_SPULL: "Q"}.get(int(modes[r]), "?")
+                                     for r in range(1, rounds + 1))),
         "touched_edge_words_per_s": touched * args.steps / elapsed,
         "roofline": roof,
     }

@@ -100,6 +100,14 @@ typedef struct {
                                    The persistent engine uses 4. */
     int32_t node_stats;         /* 1: per-node reach and distance sums (pp_get_node_stats);
                                    the per-round engine only */
+    int32_t sparse_pull;        /* how a round the scheduler makes sparse runs: 0 a push
+                                   (atomic OR of the changed nodes' new bits into their
+                                   predecessors); 1 a sparse pull (each predecessor that
+                                   can gain a bit ORs its whole successor list, as in
+                                   Algorithm 1's inner loop, restricted to those nodes);
+                                   2 either, by a pseudo-random bit per round from
+                                   fuzz_seed (testing).  Same bits every way.  The
+                                   per-round engine only */
 } pp_options;
 
 /* Metrics estimated from c[0..D] (paper Section 3 and Algorithm 1's closing
@@ -224,8 +232,10 @@ int32_t pp_run_round(pp_run r);
 int32_t pp_run_words(pp_run r);
 
 /* Per-round record of the last pp_propagate_* call: for each round r <= the
- * current round, mode[r] (0 pull, 1 push) and arcs[r] (arcs the round
- * touched).  Host arrays of cap entries; either may be NULL. */
+ * current round, mode[r] (PP_MODE_PULL, PP_MODE_PUSH or PP_MODE_SPARSE_PULL;
+ * 2 for round 0, the initialisation) and arcs[r] (arcs the round touched: all
+ * arcs for a pull, the changed nodes' predecessor arcs for a sparse round).
+ * Host arrays of cap entries; either may be NULL. */
 int pp_get_round_log(pp_run r, int32_t *mode, int64_t *arcs, int32_t cap);
 
 /* With opt.time_kernels: pull_ms[r] = total duration in ms of round r's
@@ -296,14 +306,16 @@ int pp_run_set_mlp(pp_run r, const float *params);
 int pp_get_round_features(pp_run r, float *feat, int32_t cap);
 
 /* Training samples for the cost model.  Runs the next round of a run on the
- * per-round engine in the given direction (PP_MODE_PULL or PP_MODE_PUSH)
+ * per-round engine in the given direction (PP_MODE_PULL, PP_MODE_PUSH or
+ * PP_MODE_SPARSE_PULL; PP_MODE_PUSH stands for the run's sparse direction,
+ * i.e. a sparse pull when the run was created with sparse_pull = 1)
  * instead of the scheduler's, and stores its duration in milliseconds in
  * *ms (HIP events around the whole round, every launch of the round
  * included).  features (host [8] or NULL) receives the round's features.
  * With pp_run_snapshot / pp_run_restore a caller times a round both ways,
  * and after either kind of previous round.  PP_ESTATE if the run has
  * converged or is persistent; PP_ENOTCONV if its round log is full. */
-enum { PP_MODE_PULL = 0, PP_MODE_PUSH = 1 };
+enum { PP_MODE_PULL = 0, PP_MODE_PUSH = 1, PP_MODE_SPARSE_PULL = 3 };
 int pp_time_round(pp_run r, int32_t mode, float *features, float *ms);
 
 /* The cost model on the device, for training and its tests.  All arrays
@@ -390,7 +402,7 @@ int pp_propagate_s(pp_graph g, const int32_t *seeds, int32_t s, int32_t concurre
 
 /* One configuration tried by pp_autotune and its best time. */
 typedef struct {
-    int32_t pull_k, push_div, rounds_per_sync, persistent;
+    int32_t pull_k, push_div, rounds_per_sync, persistent, sparse_pull;
     float ms;                   /* least wall time of a reset plus a propagation to convergence */
 } pp_tune_entry;
 
@@ -398,7 +410,8 @@ typedef struct {
  * pp_autotune -- picks run options for a graph by measurement.  Candidates:
  * the pull tile (2 or 4 arcs per lane, which also sets the length above
  * which a list is split into tile-sized chunks) times the push threshold
- * (push_div 4, 8, 16, 32) on the per-round engine, and the persistent
+ * (push_div 4, 8, 16, 32) on the per-round engine, the same thresholds with
+ * sparse pulls for the sparse rounds (4 arcs per lane), and the persistent
  * engine.  Each is run once to warm up (graph capture), then `reps` times
  * (>= 1) from pp_seeds_reset to convergence; the least wall time counts.
  *   seeds, s    a representative seed list (host, as for pp_seeds_init).

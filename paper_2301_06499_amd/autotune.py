@@ -2,7 +2,8 @@
 
 ``pp_autotune`` (the library) times every candidate configuration -- pull
 tile shape (arcs per lane, which also sets the high-degree split length),
-push threshold, per-round or persistent engine -- and returns the fastest.
+push threshold, push or sparse pull for sparse rounds, per-round or
+persistent engine -- and returns the fastest.
 This module keys the result by the workload (nodes, stored arcs, graphs,
 seeds, and a caller-chosen name) and keeps it in a JSON file so a workload
 is tuned once per machine.
@@ -14,7 +15,7 @@ import os
 
 from . import pp
 
-TUNED_FIELDS = ("pull_k", "push_div", "rounds_per_sync", "persistent")
+TUNED_FIELDS = ("pull_k", "push_div", "rounds_per_sync", "persistent", "sparse_pull")
 
 
 def default_cache_path() -> str:
@@ -46,7 +47,8 @@ def apply(opts: pp.Options, tuned: dict) -> pp.Options:
     """A copy of opts with the tuned fields set."""
     out = pp.Options.from_buffer_copy(opts)
     for k in TUNED_FIELDS:
-        setattr(out, k, int(tuned[k]))
+        if k in tuned:   # a record written before a field existed leaves it as given
+            setattr(out, k, int(tuned[k]))
     return out
 
 

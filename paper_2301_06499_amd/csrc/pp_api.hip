@@ -970,6 +970,8 @@ extern "C" int pp_seeds_init(pp_graph g, const int32_t *seeds, int32_t s, const 
     if (o.persistent && o.pull_k != 4) return fail(PP_EINVAL, "the persistent engine pulls with 4 arcs per lane");
     if (o.node_stats && o.persistent) return fail(PP_EINVAL, "per-node statistics need the per-round engine");
     if (o.node_stats != 0 && o.node_stats != 1) return fail(PP_EINVAL, "node_stats must be 0 or 1");
+    if (o.sparse_pull < 0 || o.sparse_pull > 2) return fail(PP_EINVAL, "sparse_pull = %d: 0, 1 or 2", o.sparse_pull);
+    if (o.sparse_pull && o.persistent) return fail(PP_EINVAL, "sparse pulls need the per-round engine");
     if (o.scheduler < PP_SCHED_HEURISTIC || o.scheduler > PP_SCHED_MLP) return fail(PP_EINVAL, "unknown scheduler %d", o.scheduler);
     if (o.max_rounds < 0 || o.rounds_per_sync < 0) return fail(PP_EINVAL, "negative max_rounds / rounds_per_sync");
     const int G = g->G;
@@ -1045,6 +1047,7 @@ extern "C" int pp_seeds_init(pp_graph g, const int32_t *seeds, int32_t s, const 
     }
     r->dev.sched = o.scheduler;
     r->dev.push_div = o.push_div;
+    r->dev.sparse_pull = o.sparse_pull;
     r->dev.fuzz_seed = o.fuzz_seed;
     // cost-model weights start as NaN: the heuristic decides until they are set
     hipError_t e = pp::launch_fill_i32((int32_t *)r->dev.mlp, kNaNBits, pp::MLP_PARAMS, r->stream);
@@ -1358,6 +1361,7 @@ extern "C" int pp_run_snapshot(pp_run r, pp_run *copy) {
     c->dev.sched = r->dev.sched;
     c->dev.push_div = r->dev.push_div;
     c->dev.pull_k = r->dev.pull_k;
+    c->dev.sparse_pull = r->dev.sparse_pull;
     c->dev.fuzz_seed = r->dev.fuzz_seed;
     rc = pp_run_restore(c, r);
     if (rc) {
@@ -1481,7 +1485,9 @@ extern "C" int pp_get_round_features(pp_run r, float *feat, int32_t cap) {
 
 extern "C" int pp_time_round(pp_run r, int32_t mode, float *features, float *ms) {
     if (!r || !ms) return fail(PP_EINVAL, "run or ms is NULL");
-    if (mode != pp::MODE_PULL && mode != pp::MODE_PUSH) return fail(PP_EINVAL, "mode %d is neither pull (0) nor push (1)", mode);
+    if (mode != pp::MODE_PULL && mode != pp::MODE_PUSH && mode != pp::MODE_SPULL)
+        return fail(PP_EINVAL, "mode %d is none of pull (0), push (1), sparse pull (3)", mode);
+    if (mode == pp::MODE_PUSH && r->dev.sparse_pull == 1) mode = pp::MODE_SPULL;   // the run's sparse direction
     if (r->pgrid) return fail(PP_ESTATE, "timing of single rounds needs the per-round engine");
     int rc = sync_ctrl(r);
     if (rc) return rc;
@@ -1496,7 +1502,9 @@ extern "C" int pp_time_round(pp_run r, int32_t mode, float *features, float *ms)
     // done, never the result
     HIP_TRY(hipMemcpyAsync(&r->dev.ctrl[0].mode, &mode, sizeof(int32_t), hipMemcpyHostToDevice, r->stream));
     HIP_TRY(hipEventRecord(r->tev[0], r->stream));
-    HIP_TRY(noted(r, pp::launch_round(gv, r->dev, r->stream)));
+    // the sparse kernel of the forced direction (a pull round launches the run's own)
+    const int kinds = mode == pp::MODE_PUSH ? pp::SPARSE_PUSH : (mode == pp::MODE_SPULL ? pp::SPARSE_PULL : pp::SPARSE_BY_RUN);
+    HIP_TRY(noted(r, pp::launch_round(gv, r->dev, r->stream, nullptr, nullptr, kinds)));
     HIP_TRY(hipEventRecord(r->tev[1], r->stream));
     HIP_TRY(hipEventSynchronize(r->tev[1]));
     HIP_TRY(hipEventElapsedTime(ms, r->tev[0], r->tev[1]));
@@ -1515,7 +1523,8 @@ extern "C" int pp_autotune(pp_graph g, const int32_t *seeds, int32_t s, const pp
     if (base) o0 = *base;
     o0.time_kernels = 0;
     // candidates: tile shape (arcs per lane, hence the high-degree threshold)
-    // x push threshold on the per-round engine, then the persistent engine
+    // x push threshold on the per-round engine, the thresholds again with
+    // sparse pulls, then the persistent engine
     std::vector<pp_options> cands;
     for (int k : {4, 2})
         for (int d : {8, 4, 16, 32}) {
@@ -1523,13 +1532,23 @@ extern "C" int pp_autotune(pp_graph g, const int32_t *seeds, int32_t s, const pp
             o.persistent = 0;
             o.pull_k = k;
             o.push_div = d;
+            o.sparse_pull = 0;
             cands.push_back(o);
         }
+    for (int d : {8, 4, 16, 32}) {
+        pp_options o = o0;
+        o.persistent = 0;
+        o.pull_k = 4;
+        o.push_div = d;
+        o.sparse_pull = 1;
+        cands.push_back(o);
+    }
     {
         pp_options o = o0;
         o.persistent = 1;
         o.pull_k = 4;
         o.push_div = 8;
+        o.sparse_pull = 0;
         cands.push_back(o);
     }
     float best_ms = INFINITY;
@@ -1549,7 +1568,7 @@ extern "C" int pp_autotune(pp_graph g, const int32_t *seeds, int32_t s, const pp
         pp_run_free(r);
         if (err != PP_OK) return err;
         if (tried < cap)
-            table[tried] = pp_tune_entry{o.pull_k, o.push_div, o.rounds_per_sync, o.persistent, ms};
+            table[tried] = pp_tune_entry{o.pull_k, o.push_div, o.rounds_per_sync, o.persistent, o.sparse_pull, ms};
         ++tried;
         if (ms < best_ms) {
             best_ms = ms;

@@ -8,8 +8,11 @@
 
 namespace pp {
 
-// Round directions.  INIT marks the seed initialisation (round 0).
-enum Mode : int32_t { MODE_PULL = 0, MODE_PUSH = 1, MODE_INIT = 2 };
+// Round directions.  INIT marks the seed initialisation (round 0).  A sparse
+// round runs either as a push (atomic ORs of the changed nodes' new bits into
+// their predecessors) or as a sparse pull (the predecessors that can gain a
+// bit gather their whole successor lists); both give the same bits.
+enum Mode : int32_t { MODE_PULL = 0, MODE_PUSH = 1, MODE_INIT = 2, MODE_SPULL = 3 };
 
 // A pull work unit: a run of consecutive nodes [u0, u1) whose successor
 // lists occupy arcs [e0, e1) (at most the tile's arc budget), or one chunk of
@@ -37,6 +40,9 @@ constexpr int PUSH_LIGHT = 16;   // entries with more predecessors go through ch
 // predecessor words before its atomics (below: latency-bound, direct slots)
 constexpr int PUSH_FILTER_MIN = 16384;
 constexpr int PUSH_CHUNK_MIN = 32;   // smallest chunk (W = 8)
+// sparse pull: a candidate with at most this many successors gathers them
+// itself; a longer list takes the new bits by atomic OR instead
+constexpr int SPULL_LIGHT = 16;
 #ifndef PP_PULL_GRID_MAX
 #define PP_PULL_GRID_MAX 2048
 #endif
@@ -190,7 +196,7 @@ struct RunDev {
     int32_t sched;
     int32_t push_div;
     int32_t pull_k;       // arcs per lane of the pull (the tile set was built for it)
-    int32_t pad2;
+    int32_t sparse_pull;  // sparse rounds: 0 push, 1 sparse pull, 2 either (pseudo-random per round)
     uint64_t fuzz_seed;
     float *mlp;           // [MLP_PARAMS] cost-model weights (NaN: not set, heuristic decides)
     int64_t *node_acc;    // [n] per-node sums of popcount(Sig_r(u)) over the states so far, or NULL
@@ -247,9 +253,12 @@ hipError_t launch_gather_rows(uint64_t *dst, const uint64_t *src, const int32_t 
 // seeds: device-readable ids; map (may be NULL): input id -> stored id.
 hipError_t launch_seed_init(const GraphDev &g, const RunDev &r, const int32_t *seeds, const int32_t *map,
                             hipStream_t st);
+// Sparse-round kernels a round launches: the push's, the sparse pull's, or
+// both (SPARSE_BY_RUN: as the run's sparse_pull option asks).
+enum SparseKinds : int { SPARSE_BY_RUN = 0, SPARSE_PUSH = 1, SPARSE_PULL = 2, SPARSE_BOTH = 3 };
 // One round; when e0/e1 are given they are recorded around the pull launch.
 hipError_t launch_round(const GraphDev &g, const RunDev &r, hipStream_t st, hipEvent_t e0 = nullptr,
-                        hipEvent_t e1 = nullptr);
+                        hipEvent_t e1 = nullptr, int kinds = SPARSE_BY_RUN);
 // Rounds up to max_round of every graph in one cooperative launch of `grid`
 // blocks split into clusters (device array), initialising graphs at round 0.
 hipError_t launch_batch_persistent(const GraphDev &g, const RunDev &r, const Cluster *clusters, int nclusters,

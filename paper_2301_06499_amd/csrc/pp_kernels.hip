@@ -440,9 +440,10 @@ __global__ void __launch_bounds__(BLOCK) k_seed_scatter(GraphDev g, RunDev R, co
 // loads in flight together, taken U grid-widths apart so that a short list
 // still spreads over every block.
 template <int W, int U>
-PP_DEV void commit_items(const GraphDev &g, const RunDev &R, int init, int r, int p, int64_t items, int bid, int nb,
-                         uint64_t &pop, int64_t &arcs, uint32_t (&sc)[W]) {
+PP_DEV void commit_items(const GraphDev &g, const RunDev &R, int init, bool apply, int r, int p, int64_t items, int bid,
+                         int nb, uint64_t &pop, int64_t &arcs, uint32_t (&sc)[W]) {
     Ctrl *C = R.ctrl;
+    uint64_t *sg = sel(R.sig, CTL(C->cur));
     const int32_t *ids = sel(R.f_ids, p);
     uint64_t *dl = sel(R.f_delta, p);
     Chunk *chunks = sel(R.chunks, p);
@@ -480,6 +481,8 @@ PP_DEV void commit_items(const GraphDev &g, const RunDev &R, int init, int r, in
             if (init) {
                 R.sig[0][(int64_t)u[k] * W + w] |= d[k];
                 R.sig[1][(int64_t)u[k] * W + w] |= d[k];
+            } else if (apply) {   // a sparse pull left the row as it was
+                sg[(int64_t)u[k] * W + w] |= d[k];
             }
         }
         int nchk[U];
@@ -522,14 +525,16 @@ PP_DEV void commit_items(const GraphDev &g, const RunDev &R, int init, int r, in
 // Collects the bits gathered in the accumulator for the entries of frontier
 // list r&1, writes them into the list, counts them, and reserves push chunks
 // for the next round.  Round 0 (init) also writes them into both signature
-// buffers; a push round has set them in Sig already.
+// buffers; a push round has set them in Sig already; after a sparse pull
+// (apply) they are set in Sig here.
 // parts (the closing launch): the block's new-bit count and predecessor arcs
 // go to its slots of the per-block partials instead of the round's
 // counters, which the round's end then sums.
 // UMAX: at most this many items per thread and pass (1 keeps the LDS and
 // registers small, for the persistent kernel).
 template <int W, int UMAX = 4>
-PP_DEV void phase_push_commit(const GraphDev &g, const RunDev &R, int init, int bid, int nb, int64_t *parts = nullptr) {
+PP_DEV void phase_push_commit(const GraphDev &g, const RunDev &R, int init, int bid, int nb, int64_t *parts = nullptr,
+                              bool apply = false) {
     Ctrl *C = R.ctrl;
     const int r = init ? 0 : CTL(C->round);
     const int p = r & 1;
@@ -542,8 +547,10 @@ PP_DEV void phase_push_commit(const GraphDev &g, const RunDev &R, int init, int 
 #pragma unroll
     for (int k = 0; k < W; ++k) sc[k] = 0;
     // long lists: four items per thread and pass
-    if (UMAX >= 4 && items > 2 * (int64_t)nb * BLOCK) commit_items<W, 4>(g, R, init, r, p, items, bid, nb, pop, arcs, sc);
-    else commit_items<W, 1>(g, R, init, r, p, items, bid, nb, pop, arcs, sc);
+    if (UMAX >= 4 && items > 2 * (int64_t)nb * BLOCK)
+        commit_items<W, 4>(g, R, init, apply, r, p, items, bid, nb, pop, arcs, sc);
+    else
+        commit_items<W, 1>(g, R, init, apply, r, p, items, bid, nb, pop, arcs, sc);
     __shared__ unsigned long long s_red[BLOCK / 64];
     const unsigned long long tp = block_sum<unsigned long long>(pop, s_red);
     const unsigned long long ta = block_sum<unsigned long long>((unsigned long long)arcs, s_red);
@@ -1047,9 +1054,71 @@ PP_DEV void push_slots(const RunDev &R, uint64_t *sig, int r, const int64_t (&k)
     for (int it = 0; it < IT; ++it) bq.push(want[it], u[it], &C->lst[pn].nodes, sel(R.f_ids, pn));
 }
 
+// Sparse pull over up to IT (frontier entry, predecessor u) pairs per slot of
+// W lanes (lane w holds word w of the entry's new bits d).  No signature is
+// written in this phase, so u gains a bit in this round exactly when some
+// entry's new bits are not all in u's row; such a u is claimed once per round
+// (stamp).  A u with at most SPULL_LIGHT successors is then gathered whole by
+// the claiming slot (every successor's row, as in a pull) and the bits its
+// row lacks go to the accumulator; a u with a longer list instead takes each
+// entry's missing bits by atomic OR into the accumulator.  Either way u is
+// queued once, and the commit sets the accumulated bits in its row.
+template <int W, int IT>
+PP_DEV void spull_slots(const GraphDev &g, const RunDev &R, const uint64_t *sig, int r, const int64_t (&k)[IT],
+                        const bool (&kv)[IT], int w, const uint64_t (&d)[IT], BlockQueue &bq, Ctrl *C, int pn) {
+    int32_t u[IT];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) u[it] = kv[it] ? g.tcol[k[it]] : 0;
+    uint64_t own[IT];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) own[it] = kv[it] ? sig[(int64_t)u[it] * W + w] : 0ull;
+    const int ln = lane_id();
+    const int gb = ln & ~(W - 1);
+    bool any[IT];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        const uint64_t bal = __ballot(kv[it] && (d[it] & ~own[it]) != 0);
+        any[it] = ((bal >> gb) & WordMask<W>::row) != 0;
+    }
+    int64_t b[IT], e[IT];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        b[it] = any[it] ? g.rp[u[it]] : 0;
+        e[it] = any[it] ? g.rp[u[it] + 1] : 0;
+    }
+    bool claim[IT];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        const uint64_t need = d[it] & ~own[it];
+        if (any[it] && e[it] - b[it] > SPULL_LIGHT && need)
+            atomicOr((unsigned long long *)&R.acc[(int64_t)u[it] * W + w], (unsigned long long)need);
+        const bool c = any[it] && w == 0 && atomicMax(&R.stamp[u[it]], r) < r;
+        claim[it] = ((__ballot(c) >> gb) & 1ull) != 0;   // the slot's first lane holds the claim
+    }
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        if (claim[it] && e[it] - b[it] <= SPULL_LIGHT) {
+            uint64_t a = 0;
+            for (int64_t j = b[it]; j < e[it]; j += 4) {
+                int32_t v4[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) v4[q] = j + q < e[it] ? g.col[j + q] : -1;
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    if (v4[q] >= 0) a |= sig[(int64_t)v4[q] * W + w];
+            }
+            R.acc[(int64_t)u[it] * W + w] = a & ~own[it];
+        }
+    }
+#pragma unroll
+    for (int it = 0; it < IT; ++it) bq.push(claim[it] && w == 0, u[it], &C->lst[pn].nodes, sel(R.f_ids, pn));
+}
+
 // FLAT: large frontiers take the flattened, read-first path (false keeps
 // only the direct path, with fewer registers, for the persistent kernel).
-template <int W, bool FLAT = true>
+// SPARSE: the same walk over the frontier's predecessor arcs as a sparse
+// pull (spull_slots) instead of a push.
+template <int W, bool FLAT = true, bool SPARSE = false>
 PP_DEV void phase_push(const GraphDev &g, const RunDev &R, int bid, int nb) {
     Ctrl *C = R.ctrl;
     const int r = CTL(C->round);
@@ -1114,7 +1183,8 @@ PP_DEV void phase_push(const GraphDev &g, const RunDev &R, int bid, int nb) {
                         kv[it] = a < total;
                         k[it] = bo + (a - so);
                     }
-                    push_slots<W, IT>(R, sig, r, k, kv, g.tcol, w, dd, bq, C, pn, filter);
+                    if constexpr (SPARSE) spull_slots<W, IT>(g, R, sig, r, k, kv, w, dd, bq, C, pn);
+                    else push_slots<W, IT>(R, sig, r, k, kv, g.tcol, w, dd, bq, C, pn, filter);
                 }
             }
         }
@@ -1146,7 +1216,8 @@ PP_DEV void phase_push(const GraphDev &g, const RunDev &R, int bid, int nb) {
                 kv[it] = ev && k[it] < end;
                 dd[it] = d;
             }
-            push_slots<W, IT>(R, sig, r, k, kv, g.tcol, w, dd, bq, C, pn, false);
+            if constexpr (SPARSE) spull_slots<W, IT>(g, R, sig, r, k, kv, w, dd, bq, C, pn);
+            else push_slots<W, IT>(R, sig, r, k, kv, g.tcol, w, dd, bq, C, pn, false);
         }
     }
     // long lists: chunks of CHUNK arcs, one wave each
@@ -1171,7 +1242,8 @@ PP_DEV void phase_push(const GraphDev &g, const RunDev &R, int bid, int nb) {
                 kv[it] = k[it] < end;
                 dd[it] = d;
             }
-            push_slots<W, IT>(R, sig, r, k, kv, g.tcol, w, dd, bq, C, pn, filter);
+            if constexpr (SPARSE) spull_slots<W, IT>(g, R, sig, r, k, kv, w, dd, bq, C, pn);
+            else push_slots<W, IT>(R, sig, r, k, kv, g.tcol, w, dd, bq, C, pn, filter);
         }
     }
     bq.flush(&C->lst[pn].nodes, sel(R.f_ids, pn), &s_qbase);
@@ -1189,6 +1261,15 @@ PP_DEV int32_t schedule(const GraphDev &g, const RunDev &R, int32_t r, int64_t f
             (void)fnodes;
             return (farcs * (int64_t)R.push_div < g.m) ? MODE_PUSH : MODE_PULL;
     }
+}
+
+// The sparse direction of round r: a push, or a sparse pull when the run asks
+// for it (sparse_pull 1), or either by a pseudo-random bit per round
+// (sparse_pull 2, for testing: the bits do not depend on it).
+PP_DEV int32_t sparse_dir(const RunDev &R, int32_t r, int32_t d) {
+    if (d != MODE_PUSH || R.sparse_pull == 0) return d;
+    if (R.sparse_pull == 1) return MODE_SPULL;
+    return (mix64(~R.fuzz_seed + (uint64_t)r * 0xD1B54A32D192ED03ull) >> 63) ? MODE_SPULL : MODE_PUSH;
 }
 
 // The eight frontier features of the round after `r` (each roughly in [0, 1]):
@@ -1326,7 +1407,7 @@ PP_DEV void phase_round_end(const GraphDev &g, const RunDev &R, int init, int np
     if (threadIdx.x == 0) {
         C->acc_pending = 1;   // a state for the per-node sums
         R.mode_log[r] = mode;
-        R.arcs_log[r] = mode == MODE_PULL ? pulled : (mode == MODE_PUSH ? prev_arcs : 0);
+        R.arcs_log[r] = mode == MODE_PULL ? pulled : (mode == MODE_INIT ? 0 : prev_arcs);
         // the arcs of the nodes changed in this round: a following push's work
         if (mode == MODE_PULL || parts) C->f_arcs[r & 1] = farcs;
         if (mode == MODE_PULL) C->cur ^= 1;
@@ -1353,7 +1434,7 @@ PP_DEV void phase_round_end(const GraphDev &g, const RunDev &R, int init, int np
             C->lst[q].nodes = 0;
             C->lst[q].chunks = 0;
             C->f_arcs[q] = 0;
-            C->mode = s_next;
+            C->mode = sparse_dir(R, nr, s_next);
             C->round = nr;
         }
     }
@@ -1387,6 +1468,12 @@ k_pull(GraphDev g, RunDev R) {
 template <int W> __global__ void __launch_bounds__(BLOCK) k_push(GraphDev g, RunDev R) {
     if (R.ctrl->converged || R.ctrl->mode != MODE_PUSH) return;
     phase_push<W>(g, R, blockIdx.x, gridDim.x);
+}
+// The sparse pull's kernel, apart from the push's so that a run that never
+// takes it keeps the push kernel's smaller register and LDS footprint.
+template <int W> __global__ void __launch_bounds__(BLOCK) k_spull(GraphDev g, RunDev R) {
+    if (R.ctrl->converged || R.ctrl->mode != MODE_SPULL) return;
+    phase_push<W, true, true>(g, R, blockIdx.x, gridDim.x);
 }
 __global__ void __launch_bounds__(BLOCK) k_round_end(GraphDev g, RunDev R, int init) {
     if (R.ctrl->converged) return;
@@ -1437,8 +1524,9 @@ template <int W> __global__ void __launch_bounds__(BLOCK) k_post(GraphDev g, Run
         if (blockIdx.x == 0 && threadIdx.x == 0) PUT(C->acc_pending, 0);   // no round ran in this slot
         return;
     }
-    if (CTL(C->mode) == MODE_PUSH) phase_push_commit<W>(g, R, 0, blockIdx.x, gridDim.x, R.post_part);
-    else phase_pull_hubs<W>(g, R, blockIdx.x, gridDim.x, R.post_part);
+    const int32_t mode = CTL(C->mode);
+    if (mode == MODE_PULL) phase_pull_hubs<W>(g, R, blockIdx.x, gridDim.x, R.post_part);
+    else phase_push_commit<W>(g, R, 0, blockIdx.x, gridDim.x, R.post_part, mode == MODE_SPULL);
     __shared__ int s_last;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __syncthreads();
@@ -1489,12 +1577,12 @@ __global__ void __launch_bounds__(64) k_redecide(RunDev R, int nctrl) {
     Ctrl *C = R.ctrl + blockIdx.x;
     if ((int)blockIdx.x >= nctrl || R.sched != PP_SCHED_MLP) return;
     const int32_t mode = CTL(C->mode);
-    if (CTL(C->round) < 1 || CTL(C->converged) || (mode != MODE_PULL && mode != MODE_PUSH)) return;
+    if (CTL(C->round) < 1 || CTL(C->converged) || mode == MODE_INIT) return;
     float f[MLP_IN];
 #pragma unroll
     for (int i = 0; i < MLP_IN; ++i) f[i] = C->feat[i];
-    const int32_t d = mlp_decide(R.mlp, f, mode);
-    if (threadIdx.x == 0) C->mode = d;
+    const int32_t d = mlp_decide(R.mlp, f, mode == MODE_PULL ? MODE_PULL : MODE_PUSH);
+    if (threadIdx.x == 0) C->mode = sparse_dir(R, CTL(C->round), d);
 }
 
 hipError_t launch_redecide(const RunDev &R, int nctrl, hipStream_t st) {
@@ -1739,7 +1827,9 @@ static hipError_t seed_init_impl(const GraphDev &g, const RunDev &R, const int32
 }
 
 template <int W>
-static hipError_t round_impl(const GraphDev &g, const RunDev &R, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+static hipError_t round_impl(const GraphDev &g, const RunDev &R, hipStream_t st, hipEvent_t e0, hipEvent_t e1,
+                             int kinds) {
+    if (kinds == SPARSE_BY_RUN) kinds = R.sparse_pull == 0 ? SPARSE_PUSH : (R.sparse_pull == 1 ? SPARSE_PULL : SPARSE_BOTH);
     if (e0) {
         const hipError_t e = hipEventRecord(e0, st);
         if (e != hipSuccess) return e;
@@ -1750,7 +1840,8 @@ static hipError_t round_impl(const GraphDev &g, const RunDev &R, hipStream_t st,
         const hipError_t e = hipEventRecord(e1, st);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(k_push<W>, dim3(list_grid(g)), dim3(BLOCK), 0, st, g, R);
+    if (kinds & SPARSE_PUSH) hipLaunchKernelGGL(k_push<W>, dim3(list_grid(g)), dim3(BLOCK), 0, st, g, R);
+    if (kinds & SPARSE_PULL) hipLaunchKernelGGL(k_spull<W>, dim3(list_grid(g)), dim3(BLOCK), 0, st, g, R);
     hipLaunchKernelGGL(k_post<W>, dim3(post_grid(g)), dim3(BLOCK), 0, st, g, R);
     if (R.node_acc) hipLaunchKernelGGL(k_node_acc<W>, dim3(list_grid(g)), dim3(BLOCK), 0, st, g, R);
     return hipGetLastError();
@@ -1767,12 +1858,12 @@ hipError_t launch_seed_init(const GraphDev &g, const RunDev &R, const int32_t *s
     }
 }
 
-hipError_t launch_round(const GraphDev &g, const RunDev &R, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+hipError_t launch_round(const GraphDev &g, const RunDev &R, hipStream_t st, hipEvent_t e0, hipEvent_t e1, int kinds) {
     switch (R.W) {
-        case 1: return round_impl<1>(g, R, st, e0, e1);
-        case 2: return round_impl<2>(g, R, st, e0, e1);
-        case 4: return round_impl<4>(g, R, st, e0, e1);
-        case 8: return round_impl<8>(g, R, st, e0, e1);
+        case 1: return round_impl<1>(g, R, st, e0, e1, kinds);
+        case 2: return round_impl<2>(g, R, st, e0, e1, kinds);
+        case 4: return round_impl<4>(g, R, st, e0, e1, kinds);
+        case 8: return round_impl<8>(g, R, st, e0, e1, kinds);
         default: return hipErrorInvalidValue;
     }
 }

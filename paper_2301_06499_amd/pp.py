@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_PKG, "libpp.so")
 PP_OK, PP_EINVAL, PP_ERANGE, PP_ENOMEM, PP_EDEVICE, PP_ENOTCONV, PP_ESTATE = 0, -1, -2, -3, -4, -5, -6
 PP_UNDIRECTED, PP_INPUT_ON_DEVICE, PP_TRANSPOSE, PP_KEEP_ORDER = 1, 2, 4, 8
 PP_SCHED_HEURISTIC, PP_SCHED_PULL, PP_SCHED_PUSH, PP_SCHED_FUZZ, PP_SCHED_MLP = 0, 1, 2, 3, 4
-MODE_PULL, MODE_PUSH, MODE_INIT = 0, 1, 2      # entries of the per-round mode log
+MODE_PULL, MODE_PUSH, MODE_INIT, MODE_SPULL = 0, 1, 2, 3   # entries of the per-round mode log
 _NAMES = {0: "PP_OK", -1: "PP_EINVAL", -2: "PP_ERANGE", -3: "PP_ENOMEM", -4: "PP_EDEVICE",
           -5: "PP_ENOTCONV", -6: "PP_ESTATE"}
 
@@ -35,12 +35,12 @@ class Options(ctypes.Structure):
     _fields_ = [("scheduler", ctypes.c_int32), ("seed_counts", ctypes.c_int32), ("max_rounds", ctypes.c_int32),
                 ("rounds_per_sync", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("push_div", ctypes.c_int32),
                 ("fuzz_seed", ctypes.c_uint64), ("time_kernels", ctypes.c_int32), ("persistent", ctypes.c_int32),
-                ("pull_k", ctypes.c_int32), ("node_stats", ctypes.c_int32)]
+                ("pull_k", ctypes.c_int32), ("node_stats", ctypes.c_int32), ("sparse_pull", ctypes.c_int32)]
 
 
 class TuneEntry(ctypes.Structure):
     _fields_ = [("pull_k", ctypes.c_int32), ("push_div", ctypes.c_int32), ("rounds_per_sync", ctypes.c_int32),
-                ("persistent", ctypes.c_int32), ("ms", ctypes.c_float)]
+                ("persistent", ctypes.c_int32), ("sparse_pull", ctypes.c_int32), ("ms", ctypes.c_float)]
 
 
 class Progress(ctypes.Structure):
@@ -141,7 +141,7 @@ def _is_device(a) -> bool:
 
 def options(scheduler=PP_SCHED_HEURISTIC, seed_counts=False, max_rounds=0, rounds_per_sync=0,
             use_graph=True, push_div=0, fuzz_seed=0, time_kernels=False, persistent=False, pull_k=0,
-            node_stats=False) -> Options:
+            node_stats=False, sparse_pull=0) -> Options:
     o = Options()
     lib().pp_options_default(ctypes.byref(o))
     o.scheduler = scheduler
@@ -156,6 +156,7 @@ def options(scheduler=PP_SCHED_HEURISTIC, seed_counts=False, max_rounds=0, round
     o.persistent = int(bool(persistent))
     o.pull_k = int(pull_k)
     o.node_stats = int(bool(node_stats))
+    o.sparse_pull = int(sparse_pull)
     return o
 
 
@@ -383,7 +384,10 @@ def pp_get_round_features(run: Run, cap: int):
 
 
 def pp_time_round(run: Run, mode: int):
-    """Runs the next round in direction `mode` (MODE_PULL / MODE_PUSH); returns (features [8], ms)."""
+    """Runs the next round in direction `mode` (MODE_PULL / MODE_PUSH / MODE_SPULL); returns (features [8], ms).
+
+    MODE_PUSH stands for the run's sparse direction (a sparse pull when the run
+    was created with sparse_pull=1)."""
     f = np.zeros(MLP_IN, dtype=np.float32)
     ms = ctypes.c_float(0.0)
     _check(lib().pp_time_round(run.handle, int(mode), _np_ptr(f), ctypes.byref(ms)))

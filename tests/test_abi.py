@@ -29,9 +29,40 @@ def test_every_declared_symbol_is_exported():
 
 
 def test_struct_layouts_match_header():
-    assert ctypes.sizeof(pp.Options) == 48
+    assert ctypes.sizeof(pp.Options) == 56
+    assert ctypes.sizeof(pp.TuneEntry) == 6 * 4
     assert ctypes.sizeof(pp.Progress) == 4 * 4 + 3 * 8
     assert ctypes.sizeof(pp.Metrics) == 4 + 4 + 8 + 6 * 8
+
+
+def test_struct_offsets_match_a_c_compiler(tmp_path):
+    """Every field of the binding's structures sits where a C compiler puts it."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = {"pp_options": pp.Options, "pp_tune_entry": pp.TuneEntry, "pp_progress": pp.Progress,
+               "pp_metrics": pp.Metrics}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "pp.h"', "int main(void) {"]
+    for cname, cls in structs.items():
+        lines.append(f'printf("{cname} sizeof %zu\\n", sizeof({cname}));')
+        for f, _ in cls._fields_:
+            lines.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    include = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    subprocess.check_call([cc, "-I", include, str(src), "-o", str(exe)])
+    got = {}
+    for line in subprocess.check_output([str(exe)], text=True).splitlines():
+        cname, f, v = line.split()
+        got[(cname, f)] = int(v)
+    for cname, cls in structs.items():
+        assert got[(cname, "sizeof")] == ctypes.sizeof(cls), cname
+        for f, _ in cls._fields_:
+            assert got[(cname, f)] == getattr(cls, f).offset, (cname, f)
 
 
 def test_validation_before_device_work():

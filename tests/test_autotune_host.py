@@ -48,3 +48,15 @@ def test_unreadable_cache_is_ignored(tmp_path, monkeypatch):
 def test_autotune_argument_errors():
     L = pp.lib()
     assert L.pp_autotune(None, None, 1, None, 1, None, None, 0, None) == pp.PP_EINVAL
+
+
+def test_sparse_pull_is_tuned_and_old_records_still_apply(tmp_path):
+    """A record carries the sparse direction; one written before that field existed
+    leaves the caller's value as it was."""
+    base = pp.options(sparse_pull=2, max_rounds=50)
+    o = autotune.apply(base, {"pull_k": 4, "push_div": 16, "rounds_per_sync": 0, "persistent": 0, "sparse_pull": 1})
+    assert (o.sparse_pull, o.push_div, o.max_rounds) == (1, 16, 50)
+    old = {"pull_k": 2, "push_div": 8, "rounds_per_sync": 0, "persistent": 0}
+    o = autotune.apply(base, old)
+    assert (o.sparse_pull, o.pull_k) == (2, 2)
+    assert "sparse_pull" in autotune.TUNED_FIELDS

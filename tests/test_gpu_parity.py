@@ -36,7 +36,7 @@ def pad_words(sig, W):
 
 def check_run(n, src, dst, seeds, undirected, transpose=False, sched=pp.PP_SCHED_HEURISTIC,
               fuzz_seed=0, use_graph=True, want=None, max_rounds=0, persistent=False, keep_order=False,
-              pull_k=0):
+              pull_k=0, sparse_pull=0):
     s = len(seeds)
     if want is None:
         want = oracle.propagate(n, src, dst, seeds, undirected, transpose=transpose,
@@ -44,7 +44,7 @@ def check_run(n, src, dst, seeds, undirected, transpose=False, sched=pp.PP_SCHED
     g = pp.pp_csr_build(n, src, dst, undirected=undirected, transpose=transpose, keep_order=keep_order)
     cap = max_rounds or want["D"] + 4
     opts = pp.options(scheduler=sched, seed_counts=True, max_rounds=cap, fuzz_seed=fuzz_seed,
-                      use_graph=use_graph, persistent=persistent, pull_k=pull_k)
+                      use_graph=use_graph, persistent=persistent, pull_k=pull_k, sparse_pull=sparse_pull)
     r = pp.pp_seeds_init(g, seeds, opts=opts)
     counts, D = pp.pp_propagate_until_converged(r)
     assert int(D[0]) == want["D"]
@@ -296,16 +296,19 @@ def test_autotune_candidates_keep_results():
     want = oracle.propagate(g.n, g.src, g.dst, seeds, False, final_sig=True)
     G = pp.pp_csr_build(g.n, g.src, g.dst)
     best, table = pp.pp_autotune(G, seeds, reps=2)
-    assert len(table) == 9
-    assert {(t["pull_k"], t["push_div"]) for t in table if not t["persistent"]} == \
+    assert len(table) == 13
+    assert {(t["pull_k"], t["push_div"]) for t in table if not t["persistent"] and not t["sparse_pull"]} == \
         {(k, d) for k in (2, 4) for d in (4, 8, 16, 32)}
+    assert {(t["pull_k"], t["push_div"]) for t in table if t["sparse_pull"]} == {(4, d) for d in (4, 8, 16, 32)}
+    assert sum(1 for t in table if t["persistent"]) == 1
     assert all(np.isfinite(t["ms"]) and t["ms"] > 0 for t in table)
     best_ms = min(t["ms"] for t in table)
     assert any(t["ms"] == best_ms and t["pull_k"] == best.pull_k and t["push_div"] == best.push_div
-               and t["persistent"] == best.persistent for t in table)
+               and t["persistent"] == best.persistent and t["sparse_pull"] == best.sparse_pull for t in table)
     for k in (2, 4):
-        for pers in ((False, True) if k == 4 else (False,)):
-            opts = pp.options(pull_k=k, persistent=pers, push_div=best.push_div, max_rounds=want["D"] + 4)
+        for pers, sparse in (((False, 0), (True, 0), (False, 1)) if k == 4 else ((False, 0),)):
+            opts = pp.options(pull_k=k, persistent=pers, push_div=best.push_div, max_rounds=want["D"] + 4,
+                              sparse_pull=sparse)
             r = pp.pp_seeds_init(G, seeds, opts=opts)
             c, D = pp.pp_propagate_until_converged(r)
             assert int(D[0]) == want["D"] and list(c[0]) == list(want["counts"])
@@ -492,15 +495,147 @@ def test_progressive_sample(case):
 def test_grid4096_full_size():
     """The 4096^2 grid with deletions and shortcuts, s = 128, at full size: per-round
     counts, D and every signature against the oracle (all 128 BFS on the host),
-    with the heuristic and with a pseudo-random schedule."""
+    with the heuristic and with a pseudo-random schedule, sparse rounds as pushes,
+    as sparse pulls, or either."""
     g, seeds = gen.workload_grid_shortcuts(4096, 128, 1)
     say("grid4096 oracle", g.n)
     want = oracle.propagate(g.n, g.src, g.dst, seeds, True, final_sig=True)
     G = pp.pp_csr_build(g.n, g.src, g.dst, undirected=True)
-    for sched in (pp.PP_SCHED_HEURISTIC, pp.PP_SCHED_FUZZ):
-        say("grid4096 run", sched)
-        r = pp.pp_seeds_init(G, seeds, opts=pp.options(scheduler=sched, fuzz_seed=3, max_rounds=want["D"] + 4))
+    for sched, sparse in ((pp.PP_SCHED_HEURISTIC, 0), (pp.PP_SCHED_FUZZ, 0), (pp.PP_SCHED_HEURISTIC, 1),
+                          (pp.PP_SCHED_FUZZ, 2)):
+        say("grid4096 run", sched, "sparse_pull", sparse)
+        r = pp.pp_seeds_init(G, seeds, opts=pp.options(scheduler=sched, fuzz_seed=3, max_rounds=want["D"] + 4,
+                                                        sparse_pull=sparse))
         counts, D = pp.pp_propagate_until_converged(r)
         assert int(D[0]) == want["D"] and list(counts[0]) == list(want["counts"])
         assert np.array_equal(pp.pp_get_signatures(r), pad_words(want["final_sig"], r.words))
         r.free()
+
+
+# ------------------------------------------------------------ sparse pull
+
+SPARSE_SCHEDS = [pp.PP_SCHED_PUSH, pp.PP_SCHED_HEURISTIC, pp.PP_SCHED_FUZZ]
+
+
+@pytest.mark.parametrize("gi", range(len(CLOSED)))
+@pytest.mark.parametrize("sched", SPARSE_SCHEDS)
+@pytest.mark.parametrize("sparse", [1, 2])
+def test_sparse_pull_closed_forms(gi, sched, sparse):
+    """Sparse rounds as sparse pulls (1) or mixed with pushes (2): the star and the
+    complete graph take the long-list path, the lattices and paths the gather."""
+    g = CLOSED[gi]
+    s = min(g.n, 512)
+    seeds = gen.sample_seeds(g.n, s, 3 + gi)
+    say("sparse closed", g.name, "s", s, "sched", sched, "sparse_pull", sparse)
+    r, _, counts = check_run(g.n, g.src, g.dst, seeds, g.undirected, sched=sched, fuzz_seed=gi,
+                             sparse_pull=sparse)
+    modes, _ = pp.pp_get_round_log(r, len(counts) + 1)
+    if sched == pp.PP_SCHED_PUSH and sparse == 1:
+        assert all(int(m) == pp.MODE_SPULL for m in modes[1:len(counts) + 1])
+
+
+@pytest.mark.parametrize("trial", range(16))
+def test_sparse_pull_random_graphs(trial):
+    """Random multigraphs at every signature width, sparse rounds as sparse pulls."""
+    rng = np.random.default_rng(900 + trial)
+    s = [1, 64, 65, 128, 200, 256, 300, 512][trial % 8]
+    n = int(rng.integers(max(2, s // 4), 3000))
+    m = int(rng.integers(0, 8 * n))
+    src = rng.integers(0, n, m).astype(np.int32)
+    dst = rng.integers(0, n, m).astype(np.int32)
+    und = bool(trial % 3 == 0)
+    tr = bool(trial % 4 == 1)
+    seeds = rng.integers(0, n, s).astype(np.int32)
+    sched = SPARSE_SCHEDS[trial % 3]
+    sparse = 1 + trial % 2
+    say("sparse random", trial, "n", n, "m", m, "s", s, "sched", sched, "sparse_pull", sparse)
+    check_run(n, src, dst, seeds, und, transpose=tr, sched=sched, fuzz_seed=trial, sparse_pull=sparse,
+              pull_k=2 if trial % 5 == 0 else 0)
+
+
+@pytest.mark.parametrize("sched", SPARSE_SCHEDS)
+@pytest.mark.parametrize("keep_order", [False, True])
+def test_sparse_pull_rmat_with_hubs(sched, keep_order):
+    """R-MAT scale 14 (lists far longer than the gather limit), sparse pulls."""
+    g = gen.rmat(14, 16, 77)
+    seeds = gen.sample_seeds(g.n, 256, 8)
+    say("sparse rmat14", sched, "keep_order", keep_order)
+    check_run(g.n, g.src, g.dst, seeds, False, sched=sched, fuzz_seed=5, keep_order=keep_order, sparse_pull=1)
+
+
+@pytest.mark.parametrize("sparse", [1, 2])
+def test_sparse_pull_round_by_round(sparse):
+    """The ER workload one round at a time: the signatures after every round."""
+    g, seeds = gen.workload_er(1)
+    want = oracle.propagate(g.n, g.src, g.dst, seeds, True, sig_rounds=list(range(0, 16)),
+                            seed_counts=True, final_sig=True)
+    say("sparse er rounds", sparse, "D", want["D"])
+    G = pp.pp_csr_build(g.n, g.src, g.dst, undirected=True)
+    r = pp.pp_seeds_init(G, seeds, opts=pp.options(scheduler=pp.PP_SCHED_FUZZ, seed_counts=True, max_rounds=64,
+                                                    fuzz_seed=9, sparse_pull=sparse))
+    got = [len(seeds)]
+    for k in range(1, want["D"] + 2):
+        nb, conv = pp.pp_propagate_round(r)
+        got.append(int(nb[0]))
+        assert np.array_equal(pp.pp_get_signatures(r), want["sigs"][min(k, 15)]), k
+        assert conv == (k == want["D"] + 1)
+    assert got[:-1] == list(want["counts"]) and got[-1] == 0
+    modes, arcs = pp.pp_get_round_log(r, want["D"] + 2)
+    assert set(int(m) for m in modes[1:want["D"] + 2]) <= {pp.MODE_PULL, pp.MODE_PUSH, pp.MODE_SPULL}
+    if sparse == 1:
+        assert pp.MODE_PUSH not in [int(m) for m in modes[1:want["D"] + 2]]
+
+
+@pytest.mark.parametrize("case", range(len(NS_CASES)))
+def test_sparse_pull_node_stats(case):
+    """Per-node sums with sparse pulls, against the oracle's BFS distances."""
+    import oracle.node_stats as ons
+    name, make, s = NS_CASES[case]
+    g = make()
+    seeds = gen.sample_seeds(g.n, s, 21 + case)
+    say("sparse node_stats", name)
+    G = pp.pp_csr_build(g.n, g.src, g.dst, undirected=g.undirected)
+    r = pp.pp_seeds_init(G, seeds, opts=pp.options(scheduler=pp.PP_SCHED_PUSH, node_stats=True, sparse_pull=1,
+                                                    max_rounds=g.n + 2))
+    pp.pp_propagate_until_converged(r)
+    wr, wd = ons.node_stats(g.n, g.src, g.dst, seeds, g.undirected)
+    gr, gd = pp.pp_get_node_stats(r)
+    assert np.array_equal(gr, wr) and np.array_equal(gd, wd)
+
+
+def test_sparse_pull_forced_rounds_snapshot_and_errors():
+    """pp_time_round in each direction, from snapshots: the same bits every way; the
+    mode log records the sparse pulls; bad options are rejected."""
+    g, seeds = gen.workload_er(2)
+    want = oracle.propagate(g.n, g.src, g.dst, seeds, True, final_sig=True)
+    G = pp.pp_csr_build(g.n, g.src, g.dst, undirected=True)
+    r = pp.pp_seeds_init(G, seeds, opts=pp.options(max_rounds=64, sparse_pull=1))
+    pp.pp_propagate_round(r)
+    snap = pp.pp_run_snapshot(r)
+    results = []
+    for mode in (pp.MODE_PULL, pp.MODE_PUSH, pp.MODE_SPULL):
+        pp.pp_run_restore(r, snap)
+        pp.pp_time_round(r, mode)
+        modes, _ = pp.pp_get_round_log(r, 4)
+        assert int(modes[2]) == (pp.MODE_PULL if mode == pp.MODE_PULL else pp.MODE_SPULL), mode
+        c, _ = pp.pp_propagate_until_converged(r)
+        results.append((list(c[0]), pp.pp_get_signatures(r)))
+    for c, sig in results:
+        assert c == list(want["counts"])
+        assert np.array_equal(sig, pad_words(want["final_sig"], sig.shape[1]))
+    # a push run forced into a sparse pull, and back
+    r2 = pp.pp_seeds_init(G, seeds, opts=pp.options(max_rounds=64))
+    pp.pp_propagate_round(r2)
+    pp.pp_time_round(r2, pp.MODE_SPULL)
+    pp.pp_time_round(r2, pp.MODE_PUSH)
+    modes, _ = pp.pp_get_round_log(r2, 4)
+    assert [int(m) for m in modes[2:4]] == [pp.MODE_SPULL, pp.MODE_PUSH]
+    c, _ = pp.pp_propagate_until_converged(r2)
+    assert list(c[0]) == list(want["counts"])
+    for bad in (dict(sparse_pull=3), dict(sparse_pull=-1), dict(sparse_pull=1, persistent=True)):
+        with pytest.raises(pp.PPError) as e:
+            pp.pp_seeds_init(G, seeds, opts=pp.options(**bad))
+        assert e.value.code == pp.PP_EINVAL, bad
+    with pytest.raises(pp.PPError) as e:
+        pp.pp_time_round(r2, 2)
+    assert e.value.code == pp.PP_EINVAL
