@@ -1069,45 +1069,56 @@ PP_DEV void spull_slots(const GraphDev &g, const RunDev &R, const uint64_t *sig,
     int32_t u[IT];
 #pragma unroll
     for (int it = 0; it < IT; ++it) u[it] = kv[it] ? g.tcol[k[it]] : 0;
+    // the row and the list bounds of every slot's predecessor, in one batch
     uint64_t own[IT];
-#pragma unroll
-    for (int it = 0; it < IT; ++it) own[it] = kv[it] ? sig[(int64_t)u[it] * W + w] : 0ull;
-    const int ln = lane_id();
-    const int gb = ln & ~(W - 1);
-    bool any[IT];
-#pragma unroll
-    for (int it = 0; it < IT; ++it) {
-        const uint64_t bal = __ballot(kv[it] && (d[it] & ~own[it]) != 0);
-        any[it] = ((bal >> gb) & WordMask<W>::row) != 0;
-    }
     int64_t b[IT], e[IT];
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
-        b[it] = any[it] ? g.rp[u[it]] : 0;
-        e[it] = any[it] ? g.rp[u[it] + 1] : 0;
+        own[it] = kv[it] ? sig[(int64_t)u[it] * W + w] : 0ull;
+        b[it] = kv[it] ? g.rp[u[it]] : 0;
+        e[it] = kv[it] ? g.rp[u[it] + 1] : 0;
     }
-    bool claim[IT];
+    const int ln = lane_id();
+    const int gb = ln & ~(W - 1);
+    bool claim[IT], light[IT];
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
-        const uint64_t need = d[it] & ~own[it];
-        if (any[it] && e[it] - b[it] > SPULL_LIGHT && need)
-            atomicOr((unsigned long long *)&R.acc[(int64_t)u[it] * W + w], (unsigned long long)need);
-        const bool c = any[it] && w == 0 && atomicMax(&R.stamp[u[it]], r) < r;
+        const uint64_t need = kv[it] ? d[it] & ~own[it] : 0ull;
+        const bool any = ((__ballot(need != 0) >> gb) & WordMask<W>::row) != 0;
+        light[it] = e[it] - b[it] <= SPULL_LIGHT;
+        if (!light[it] && need) atomicOr((unsigned long long *)&R.acc[(int64_t)u[it] * W + w], (unsigned long long)need);
+        const bool c = any && w == 0 && atomicMax(&R.stamp[u[it]], r) < r;
         claim[it] = ((__ballot(c) >> gb) & 1ull) != 0;   // the slot's first lane holds the claim
     }
+    // claimed short lists: the first four successors of every slot in one
+    // batch of loads, then the rest of the longer ones
+    uint64_t a[IT];
+    int32_t v4[IT][4];
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
-        if (claim[it] && e[it] - b[it] <= SPULL_LIGHT) {
-            uint64_t a = 0;
-            for (int64_t j = b[it]; j < e[it]; j += 4) {
-                int32_t v4[4];
+        const bool go = claim[it] && light[it];
 #pragma unroll
-                for (int q = 0; q < 4; ++q) v4[q] = j + q < e[it] ? g.col[j + q] : -1;
+        for (int q = 0; q < 4; ++q) v4[it][q] = go && b[it] + q < e[it] ? g.col[b[it] + q] : -1;
+    }
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        a[it] = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (v4[it][q] >= 0) a[it] |= sig[(int64_t)v4[it][q] * W + w];
+    }
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        if (claim[it] && light[it]) {
+            for (int64_t j = b[it] + 4; j < e[it]; j += 4) {
+                int32_t vv[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) vv[q] = j + q < e[it] ? g.col[j + q] : -1;
 #pragma unroll
                 for (int q = 0; q < 4; ++q)
-                    if (v4[q] >= 0) a |= sig[(int64_t)v4[q] * W + w];
+                    if (vv[q] >= 0) a[it] |= sig[(int64_t)vv[q] * W + w];
             }
-            R.acc[(int64_t)u[it] * W + w] = a & ~own[it];
+            R.acc[(int64_t)u[it] * W + w] = a[it] & ~own[it];
         }
     }
 #pragma unroll
