@@ -1810,6 +1810,19 @@ static int list_grid(const GraphDev &g) {
     return (int)(b < 64 ? 64 : (b > 1024 ? 1024 : b));
 }
 
+// blocks of the push and sparse-pull launches: as many as the list launches,
+// and on graphs of more than 2^27 arcs one per 2^17 arcs up to 8192, since a
+// push there can walk a hundred million arcs at once (R-MAT scale 26: 76.3 ->
+// 67.6 ms per propagation from 1024 to 8192 blocks).  A launch that finds
+// little or nothing to do costs more the more blocks it has, which is why
+// smaller graphs keep the list launches' 1024 (R-MAT scale 20 lost 7% at
+// 2048, the 4096^2 grid 9%).
+static int push_grid(const GraphDev &g) {
+    const int lg = list_grid(g);
+    const int64_t by_arcs = g.m >> 17;
+    return by_arcs > lg ? (int)(by_arcs < 8192 ? by_arcs : 8192) : lg;
+}
+
 // blocks of the closing launch: a push round's commit lists up to n nodes,
 // but a launch of many blocks that mostly find nothing to do costs time in
 // every round; one block per 4096 nodes, 64 to POST_MAX
@@ -1851,8 +1864,8 @@ static hipError_t round_impl(const GraphDev &g, const RunDev &R, hipStream_t st,
         const hipError_t e = hipEventRecord(e1, st);
         if (e != hipSuccess) return e;
     }
-    if (kinds & SPARSE_PUSH) hipLaunchKernelGGL(k_push<W>, dim3(list_grid(g)), dim3(BLOCK), 0, st, g, R);
-    if (kinds & SPARSE_PULL) hipLaunchKernelGGL(k_spull<W>, dim3(list_grid(g)), dim3(BLOCK), 0, st, g, R);
+    if (kinds & SPARSE_PUSH) hipLaunchKernelGGL(k_push<W>, dim3(push_grid(g)), dim3(BLOCK), 0, st, g, R);
+    if (kinds & SPARSE_PULL) hipLaunchKernelGGL(k_spull<W>, dim3(push_grid(g)), dim3(BLOCK), 0, st, g, R);
     hipLaunchKernelGGL(k_post<W>, dim3(post_grid(g)), dim3(BLOCK), 0, st, g, R);
     if (R.node_acc) hipLaunchKernelGGL(k_node_acc<W>, dim3(list_grid(g)), dim3(BLOCK), 0, st, g, R);
     return hipGetLastError();
