@@ -461,6 +461,8 @@ def main():
     ap.add_argument("--node-stats", action="store_true",
                     help="also keep the per-node reach and distance sums (one extra pass per round), "
                          "checked against the oracle after timing")
+    ap.add_argument("--push-div", type=int, default=0,
+                    help="heuristic: push while frontier arcs x push_div < arcs (0: the library's default)")
     ap.add_argument("--sparse-pull", type=int, default=0, choices=[0, 1, 2],
                     help="sparse rounds: 0 push, 1 sparse pull, 2 either per round (pseudo-random)")
     ap.add_argument("--delta", type=float, default=0.05, help="progressive: 1 - confidence")
@@ -501,7 +503,7 @@ def main():
     dseeds = torch.from_numpy(seeds.astype(np.int32)).to("cuda")
     torch.cuda.synchronize()
     base = pp.options(scheduler=sched, max_rounds=4096, persistent=args.persistent, node_stats=args.node_stats,
-                      sparse_pull=args.sparse_pull)
+                      sparse_pull=args.sparse_pull, push_div=args.push_div)
     tuned = None
     if args.tune:
         from paper_2301_06499_amd import autotune
