@@ -288,6 +288,40 @@ def test_rmat20_full_size_sampled_seeds():
     say("rmat20 D", Dg, "counts", list(counts[0]))
 
 
+def test_rmat26_full_size_sampled_seeds():
+    """R-MAT scale 26, s = 512 (eight-word rows), in the benchmark's launch configuration,
+    whose pushes run at their widest (one block per 2^17 arcs, 8192 blocks).
+
+    Per-round totals come from the GPU only; the oracle checks 8 sampled seeds one by
+    one (per-seed counts and the seeds' signature bit columns over all 2^26 nodes), and
+    the totals are checked against the per-seed counts' sums.
+    """
+    g, seeds = gen.workload_rmat(26, 16, 512, 1)
+    say("rmat26 build", g.n)
+    G = pp.pp_csr_build(g.n, g.src, g.dst)
+    r = pp.pp_seeds_init(G, seeds, opts=pp.options(seed_counts=True, max_rounds=256))
+    counts, D = pp.pp_propagate_until_converged(r)
+    Dg = int(D[0])
+    modes, _ = pp.pp_get_round_log(r, Dg + 2)
+    say("rmat26 D", Dg, "modes", list(modes[1:Dg + 2]))
+    assert pp.MODE_PUSH in [int(m) for m in modes[1:Dg + 2]] and pp.MODE_PULL in [int(m) for m in modes[1:Dg + 2]]
+    sc = pp.pp_get_seed_counts(r, Dg + 1)[0]
+    assert np.array_equal(sc.sum(axis=1).astype(np.int64), counts[0])
+    sig = pp.pp_get_signatures(r)
+    r.free()
+    G.free()
+    pick = np.unique(np.linspace(0, 511, 8).astype(np.int64))
+    say("rmat26 oracle", list(pick))
+    want = oracle.propagate(g.n, g.src, g.dst, seeds[pick], False, seed_counts=True, dist=True)
+    for j, i in enumerate(pick):
+        col = want["seed_counts"][:, j]
+        L = max(len(col), Dg + 1)
+        assert np.array_equal(np.pad(sc[:, i], (0, L - Dg - 1)), np.pad(col, (0, L - len(col)))), i
+        bits = (sig[:, i >> 6] >> np.uint64(i & 63)) & np.uint64(1)
+        assert np.array_equal(bits.astype(bool), want["dist"][j] >= 0), i
+    say("rmat26 ok", list(counts[0]))
+
+
 def test_autotune_candidates_keep_results():
     """Every autotuner candidate runs the same propagation; the tuned options reproduce it."""
     g = gen.rmat(13, 16, 21)
