@@ -1802,9 +1802,8 @@ int pull_grid_for(int32_t ntiles) {
     return b < 1 ? 1 : (b < PULL_GRID_MAX ? b : PULL_GRID_MAX);
 }
 
-// blocks of the frontier, push and closing launches (at most 1024, which the
-// closing launch's ticket covers)
-static_assert(TICKET_GROUP * TICKET_GROUP >= 1024 && POST_MAX >= 1024, "ticket groups, partials");
+// blocks of the per-node launches (node sums), and the push launch's least
+// width: one per 256 nodes, 64 to 1024
 static int list_grid(const GraphDev &g) {
     const int64_t b = (g.n + BLOCK - 1) / BLOCK;
     return (int)(b < 64 ? 64 : (b > 1024 ? 1024 : b));
@@ -1823,6 +1822,7 @@ static int push_grid(const GraphDev &g) {
     return by_arcs > lg ? (int)(by_arcs < 8192 ? by_arcs : 8192) : lg;
 }
 
+static_assert(TICKET_GROUP * TICKET_GROUP >= POST_MAX, "the closing launch's ticket covers its blocks");
 // blocks of the closing launch: a push round's commit lists up to n nodes,
 // but a launch of many blocks that mostly find nothing to do costs time in
 // every round; one block per 4096 nodes, 64 to POST_MAX
