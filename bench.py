@@ -461,6 +461,8 @@ def main():
     ap.add_argument("--node-stats", action="store_true",
                     help="also keep the per-node reach and distance sums (one extra pass per round), "
                          "checked against the oracle after timing")
+    ap.add_argument("--torch-allocator", action="store_true",
+                    help="the library's device memory from PyTorch's caching allocator (pp_set_allocator)")
     ap.add_argument("--push-div", type=int, default=0,
                     help="heuristic: push while frontier arcs x push_div < arcs (0: the library's default)")
     ap.add_argument("--sparse-pull", type=int, default=0, choices=[0, 1, 2],
@@ -483,6 +485,8 @@ def main():
     if not torch.cuda.is_available():
         raise SystemExit("no GPU visible")
     torch.cuda.set_device(0)
+    if args.torch_allocator:
+        pp.use_torch_allocator(torch)
     sched = {"heuristic": pp.PP_SCHED_HEURISTIC, "pull": pp.PP_SCHED_PULL, "push": pp.PP_SCHED_PUSH}[args.scheduler]
     if args.workload == "batch64":
         return bench_batch(args, torch, pp)

@@ -132,6 +132,30 @@ typedef struct {
 void pp_options_default(pp_options *opt);
 
 /*
+ * pp_set_allocator -- device memory from the caller (for instance a caching
+ * allocator that owns the process's GPU memory) for every block the library
+ * allocates from now on: graphs, runs, snapshots and the temporaries of
+ * single calls.
+ *   alloc(bytes, stream, ctx)   returns device memory of at least `bytes`
+ *               bytes, 256-byte aligned, or NULL (the calling entry point
+ *               then returns PP_ENOMEM).  stream is the hipStream_t of the
+ *               graph, run or call being served (NULL: the legacy default
+ *               stream, also for calls that take no stream).
+ *   release(ptr, stream, ctx)   takes a block back, with the stream it was
+ *               allocated for; the library first waits for the device to
+ *               finish with it, as hipFree does.
+ *   ctx         passed to both unchanged.
+ * A block always goes back to the allocator that gave it, also after a later
+ * call changes or clears the allocator, so both functions must stay callable
+ * until every graph and run made under them is freed.  alloc = release = NULL
+ * restores hipMalloc / hipFree.  The setting is process-wide: change it while
+ * no other thread is inside the library.  Pinned host staging still comes from
+ * hipHostMalloc.  PP_EINVAL if exactly one of alloc and release is NULL.
+ */
+int pp_set_allocator(void *(*alloc)(size_t bytes, void *stream, void *ctx),
+                     void (*release)(void *ptr, void *stream, void *ctx), void *ctx);
+
+/*
  * pp_csr_build -- the graph G = (V, E) of Algorithm 1's input.
  *   n, m        nodes and input pairs (m >= 0, 1 <= n < 2^31).
  *   src, dst    m node ids each: pair k is the arc src[k] -> dst[k] (both

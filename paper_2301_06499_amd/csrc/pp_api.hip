@@ -10,7 +10,9 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
+#include <unordered_map>
 #include <string>
 #include <chrono>
 #include <thread>
@@ -46,21 +48,32 @@ int fail(int code, const char *fmt, ...) {
         if (e_ != hipSuccess) return fail(PP_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
     } while (0)
 
+// The caller's device allocator (pp_set_allocator), and every block it gave
+// the library with the allocator and stream it came from, so that a block
+// goes back where it came from even after the allocator is changed.
+struct Allocator {
+    void *(*alloc)(size_t, void *, void *);
+    void (*release)(void *, void *, void *);
+    void *ctx;
+};
+struct OwnedBlock {
+    Allocator from;
+    void *stream;
+};
+std::mutex g_alloc_mu;
+Allocator g_alloc{nullptr, nullptr, nullptr};
+std::unordered_map<void *, OwnedBlock> g_owned;
+thread_local void *t_alloc_stream = nullptr;
+
 template <typename T> int dev_alloc(T **p, int64_t count) {
-    *p = nullptr;
     if (count <= 0) count = 1;
-    hipError_t e = hipMalloc((void **)p, sizeof(T) * (size_t)count);
-    if (e != hipSuccess) {
-        *p = nullptr;
-        (void)hipGetLastError();
-        return fail(PP_ENOMEM, "hipMalloc of %lld bytes failed: %s", (long long)(sizeof(T) * count),
-                    hipGetErrorString(e));
-    }
+    *p = (T *)pp::dev_malloc(sizeof(T) * (size_t)count);
+    if (!*p) return fail(PP_ENOMEM, "device allocation of %lld bytes failed", (long long)(sizeof(T) * count));
     return PP_OK;
 }
 
 template <typename T> void dev_free(T *&p) {
-    if (p) (void)hipFree((void *)p);
+    pp::dev_release((void *)p);
     p = nullptr;
 }
 
@@ -473,6 +486,7 @@ GraphDev graph_view(pp_graph g, const TileSet *ts) {
 extern "C" int pp_csr_build(int64_t n, int64_t m, const int32_t *src, const int32_t *dst, uint32_t flags,
                             const int64_t *node_offsets, int32_t num_graphs, void *stream, pp_graph *out) {
     if (!out) return fail(PP_EINVAL, "out is NULL");
+    pp::AllocStream as(stream);
     if (n < 1 || n > INT32_MAX - 1) return fail(PP_EINVAL, "n = %lld outside [1, 2^31-2]", (long long)n);
     if (m < 0) return fail(PP_EINVAL, "m < 0");
     if (m > 0 && (!src || !dst)) return fail(PP_EINVAL, "src/dst NULL with m > 0");
@@ -820,6 +834,60 @@ int ensure_staged(pp_run r, int upto) {
 
 }  // namespace
 
+void *pp::dev_malloc(size_t bytes) {
+    Allocator a;
+    {
+        std::lock_guard<std::mutex> lk(g_alloc_mu);
+        a = g_alloc;
+    }
+    if (!a.alloc) {
+        void *p = nullptr;
+        if (hipMalloc(&p, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        return p;
+    }
+    void *p = a.alloc(bytes, t_alloc_stream, a.ctx);
+    if (p) {
+        std::lock_guard<std::mutex> lk(g_alloc_mu);
+        g_owned[p] = OwnedBlock{a, t_alloc_stream};
+    }
+    return p;
+}
+
+void pp::dev_release(void *p) {
+    if (!p) return;
+    OwnedBlock o{};
+    bool owned = false;
+    {
+        std::lock_guard<std::mutex> lk(g_alloc_mu);
+        auto it = g_owned.find(p);
+        if (it != g_owned.end()) {
+            o = it->second;
+            g_owned.erase(it);
+            owned = true;
+        }
+    }
+    if (!owned) {
+        (void)hipFree(p);
+        return;
+    }
+    (void)hipDeviceSynchronize();   // what hipFree waits for: no kernel still uses the block
+    o.from.release(p, o.stream, o.from.ctx);
+}
+
+pp::AllocStream::AllocStream(void *stream) : prev(t_alloc_stream) { t_alloc_stream = stream; }
+pp::AllocStream::~AllocStream() { t_alloc_stream = prev; }
+
+extern "C" int pp_set_allocator(void *(*alloc)(size_t, void *, void *), void (*release)(void *, void *, void *),
+                                void *ctx) {
+    if ((alloc == nullptr) != (release == nullptr)) return fail(PP_EINVAL, "alloc and release: both or neither");
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    g_alloc = Allocator{alloc, release, alloc ? ctx : nullptr};
+    return PP_OK;
+}
+
 int pp::set_error(int code, const char *fmt, ...) {
     char buf[512];
     va_list ap;
@@ -959,6 +1027,7 @@ int check_host_seeds(pp_graph g, const int32_t *seeds, int s) {
 extern "C" int pp_seeds_init(pp_graph g, const int32_t *seeds, int32_t s, const pp_options *opt, void *stream,
                              pp_run *out) {
     if (!g || !out) return fail(PP_EINVAL, "graph or out is NULL");
+    pp::AllocStream as(stream);
     if (s < 1 || s > 512) return fail(PP_EINVAL, "s = %d outside [1, 512]", s);
     if (!seeds) return fail(PP_EINVAL, "seeds is NULL");
     pp_options o;
@@ -1326,6 +1395,7 @@ extern "C" int pp_get_round_log(pp_run r, int32_t *mode, int64_t *arcs, int32_t 
 
 extern "C" int pp_run_snapshot(pp_run r, pp_run *copy) {
     if (!r || !copy) return fail(PP_EINVAL, "run or copy is NULL");
+    pp::AllocStream as(r->stream);
     pp_run c = new (std::nothrow) pp_run_s();
     if (!c) return fail(PP_ENOMEM, "run handle");
     c->g = r->g;
@@ -1691,6 +1761,7 @@ extern "C" int pp_progressive_sample(pp_graph g, const int32_t *pool, int32_t po
 extern "C" int pp_propagate_s(pp_graph g, const int32_t *seeds, int32_t s, int32_t concurrent, void *stream,
                               int64_t *counts, int32_t cap_rounds, int32_t *D, int64_t *examined) {
     if (!g || !seeds || !counts || !D) return fail(PP_EINVAL, "graph, seeds, counts or D is NULL");
+    pp::AllocStream as(stream);
     if (g->G != 1) return fail(PP_EINVAL, "one graph only (got a batch of %d)", g->G);
     if (s < 1) return fail(PP_EINVAL, "s < 1");
     if (concurrent < 0) return fail(PP_EINVAL, "concurrent < 0");

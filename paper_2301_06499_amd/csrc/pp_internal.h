@@ -205,6 +205,20 @@ struct RunDev {
 // Records the message returned by pp_last_error and returns `code`.
 int set_error(int code, const char *fmt, ...);
 
+// Device memory for everything the library allocates: through the caller's
+// allocator when one is set (pp_set_allocator), else hipMalloc / hipFree.
+// dev_malloc returns nullptr on failure; dev_release returns a block to the
+// allocator that gave it, after the device has finished with it.
+void *dev_malloc(size_t bytes);
+void dev_release(void *p);
+// The stream handed to the caller's allocator for this thread's allocations
+// while the guard lives (the stream of the graph or run being built).
+struct AllocStream {
+    void *prev;
+    explicit AllocStream(void *stream);
+    ~AllocStream();
+};
+
 // Launchers (pp_kernels.hip).  All enqueue on `st` and return the launch status.
 hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t count, hipStream_t st);
 // Re-takes the pending direction of each of the first nctrl control blocks

@@ -171,18 +171,14 @@ struct MlpBufs {
           *D2 = nullptr, *DO = nullptr, *L = nullptr, *G = nullptr, *M = nullptr, *V = nullptr, *loss = nullptr;
     hipStream_t st = nullptr;
     ~MlpBufs() {
-        for (float *p : {P, X, T, Y, H1, H2, D1, D2, DO, L, G, M, V, loss})
-            if (p) (void)hipFree(p);
+        for (float *p : {P, X, T, Y, H1, H2, D1, D2, DO, L, G, M, V, loss}) dev_release(p);
         if (st) (void)hipStreamDestroy(st);
     }
 };
 
 int alloc_f(float **p, int64_t count) {
-    if (hipMalloc((void **)p, sizeof(float) * (size_t)(count > 0 ? count : 1)) != hipSuccess) {
-        *p = nullptr;
-        (void)hipGetLastError();
-        return set_error(PP_ENOMEM, "cost-model buffer of %lld floats", (long long)count);
-    }
+    *p = (float *)dev_malloc(sizeof(float) * (size_t)(count > 0 ? count : 1));
+    if (!*p) return set_error(PP_ENOMEM, "cost-model buffer of %lld floats", (long long)count);
     return PP_OK;
 }
 

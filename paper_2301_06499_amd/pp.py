@@ -64,7 +64,7 @@ EXPORTS = ["pp_options_default", "pp_csr_build", "pp_graph_arcs", "pp_graph_node
            "pp_run_snapshot", "pp_run_restore", "pp_run_free", "pp_graph_free", "pp_last_error",
            "pp_seeds_reset", "pp_get_kernel_times", "pp_run_set_mlp", "pp_get_round_features",
            "pp_time_round", "pp_mlp_forward", "pp_mlp_loss_grad", "pp_mlp_train", "pp_autotune", "pp_exact_counts",
-           "pp_propagate_s", "pp_progressive_sample", "pp_get_node_stats"]
+           "pp_propagate_s", "pp_progressive_sample", "pp_get_node_stats", "pp_set_allocator"]
 
 MLP_IN, MLP_HID, MLP_OUT = 8, 32, 2
 MLP_PARAMS = MLP_HID * MLP_IN + MLP_HID + MLP_HID * MLP_HID + MLP_HID + MLP_OUT * MLP_HID + MLP_OUT   # 1410
@@ -109,6 +109,7 @@ def lib():
         "pp_propagate_s": (ctypes.c_int, [P, P, I32, I32, P, P, I32, P, P]),
         "pp_progressive_sample": (ctypes.c_int, [P, P, I32, I32, ctypes.c_double, ctypes.c_double, P, P, I32, P]),
         "pp_get_node_stats": (ctypes.c_int, [P, P, P]),
+        "pp_set_allocator": (ctypes.c_int, [P, P, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -336,6 +337,36 @@ def pp_get_node_stats(run: Run):
     dist_sum = np.zeros(n, dtype=np.int64)
     _check(lib().pp_get_node_stats(run.handle, _np_ptr(reached), _np_ptr(dist_sum)))
     return reached, dist_sum
+
+
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+_RELEASE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
+_allocators = []   # every callback pair ever set: blocks go back to the pair that gave them
+
+
+def pp_set_allocator(alloc=None, release=None):
+    """Device memory for the library from the caller.
+
+    alloc(nbytes, stream) returns a device pointer (int; 0 when out of memory),
+    release(ptr, stream) takes it back; stream is the raw hipStream_t as an int
+    (0: the legacy default stream).  Both None: hipMalloc / hipFree again.
+    """
+    if alloc is None and release is None:
+        _check(lib().pp_set_allocator(None, None, None))
+        return
+    if alloc is None or release is None:
+        raise PPError(PP_EINVAL, "alloc and release: both or neither")
+    a = _ALLOC_FN(lambda n, st, ctx: alloc(int(n), st or 0) or None)
+    r = _RELEASE_FN(lambda p, st, ctx: release(p, st or 0))
+    _allocators.append((a, r))
+    _check(lib().pp_set_allocator(ctypes.cast(a, ctypes.c_void_p), ctypes.cast(r, ctypes.c_void_p), None))
+
+
+def use_torch_allocator(torch):
+    """Route the library's device memory through PyTorch's caching allocator."""
+    dev = torch.cuda.current_device()
+    pp_set_allocator(lambda n, st: torch.cuda.caching_allocator_alloc(n, dev, st),
+                     lambda p, st: torch.cuda.caching_allocator_delete(p))
 
 
 def pp_get_seed_counts(run: Run, cap_rounds: int):

@@ -88,6 +88,11 @@ def test_validation_before_device_work():
     assert L.pp_propagate_until_converged(None, 0, None, 0, None) == pp.PP_EINVAL
     assert L.pp_get_signatures(None, None, 0) == pp.PP_EINVAL
     assert L.pp_propagate_s(None, None, 1, 0, None, None, 1, None, None) == pp.PP_EINVAL
+    fn = pp._ALLOC_FN(lambda n, st, ctx: None)
+    assert L.pp_set_allocator(ctypes.cast(fn, ctypes.c_void_p), None, None) == pp.PP_EINVAL
+    assert L.pp_set_allocator(None, None, None) == pp.PP_OK
+    with pytest.raises(pp.PPError):
+        pp.pp_set_allocator(lambda n, st: 0, None)
     assert L.pp_progressive_sample(None, None, 1, 1, 1.0, 0.05, None, None, 1, None) == pp.PP_EINVAL
     assert L.pp_get_node_stats(None, None, None) == pp.PP_EINVAL
     assert "NULL" in L.pp_last_error().decode()
