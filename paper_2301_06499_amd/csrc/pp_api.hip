@@ -462,7 +462,9 @@ void free_graph(pp_graph g) {
     delete g;
 }
 
-GraphDev graph_view(pp_graph g, const TileSet *ts) {
+// W: the run's row width (sets the pull launch's width; 0 for a view without
+// pull tiles)
+GraphDev graph_view(pp_graph g, const TileSet *ts, int W) {
     GraphDev d{};
     d.n = g->n;
     d.m = g->m;
@@ -477,7 +479,7 @@ GraphDev graph_view(pp_graph g, const TileSet *ts) {
     d.node_graph = g->node_graph;
     d.node_off = g->node_off;
     d.G = g->G;
-    d.pull_grid = pp::pull_grid_for(d.ntiles);
+    d.pull_grid = pp::pull_grid_for(d.ntiles, W);
     return d;
 }
 
@@ -907,7 +909,7 @@ hipError_t noted(pp_run r, hipError_t e) {
 }
 
 int launch_clusters(pp_run r, int max_round) {
-    GraphDev gv = graph_view(r->g, run_tiles(r));
+    GraphDev gv = graph_view(r->g, run_tiles(r), r->W);
     HIP_TRY(noted(r, pp::launch_batch_persistent(gv, r->dev, r->dclusters, (int)r->clusters.size(), r->pgrid,
                                                  max_round, r->stream)));
     return PP_OK;
@@ -921,7 +923,7 @@ int launch_clusters(pp_run r, int max_round) {
 int reset_run(pp_run r, const int32_t *seeds, const int32_t *map) {
     pp_graph g = r->g;
     TileSet *ts = run_tiles(r);
-    GraphDev gv = graph_view(g, ts);
+    GraphDev gv = graph_view(g, ts, r->W);
     hipError_t e = clear_run_dev(g, r->dev, r->stream, !r->acc_clean);
     if (e == hipSuccess) {
         r->acc_clean = true;
@@ -1091,7 +1093,7 @@ extern "C" int pp_seeds_init(pp_graph g, const int32_t *seeds, int32_t s, const 
     TileSet *ts = nullptr;
     rc = ensure_tiles(g, W, r->dev.pull_k, &ts);
     if (rc == PP_OK)
-        rc = alloc_run_dev(g, r->dev, s, W, (int)cap, o.seed_counts != 0, std::max(pp::pull_grid_for(ts->ntiles), r->pgrid));
+        rc = alloc_run_dev(g, r->dev, s, W, (int)cap, o.seed_counts != 0, std::max(pp::pull_grid_for(ts->ntiles, W), r->pgrid));
     if (rc == PP_OK) rc = dev_alloc(&r->dseeds, (int64_t)G * s);
     if (rc == PP_OK && o.node_stats) rc = dev_alloc(&r->dev.node_acc, g->n);
     if (rc == PP_OK && r->pgrid) {
@@ -1192,7 +1194,7 @@ extern "C" int pp_propagate_round(pp_run r, int64_t *new_bits, int32_t *all_conv
     if (r->pgrid) {
         if ((rc = run_persistent(r, rr))) return rc;
     } else {
-        GraphDev gv = graph_view(r->g, run_tiles(r));
+        GraphDev gv = graph_view(r->g, run_tiles(r), r->W);
         hipEvent_t e0 = r->timing ? r->ev[0] : nullptr, e1 = r->timing ? r->ev[1] : nullptr;
         HIP_TRY(noted(r, pp::launch_round(gv, r->dev, r->stream, e0, e1)));
         if ((rc = sync_state(r, rr + 1))) return rc;
@@ -1220,7 +1222,7 @@ namespace {
 hipEvent_t slot_event(pp_run r, int i, int which) { return r->timing ? r->ev[(size_t)(2 * i + which)] : nullptr; }
 
 int launch_batch(pp_run r, int k) {
-    GraphDev gv = graph_view(r->g, run_tiles(r));
+    GraphDev gv = graph_view(r->g, run_tiles(r), r->W);
     if (!r->opt.use_graph || (r->timing && !r->graph_events)) {
         for (int i = 0; i < k; ++i)
             HIP_TRY(noted(r, pp::launch_round(gv, r->dev, r->stream, slot_event(r, i, 0), slot_event(r, i, 1))));
@@ -1422,7 +1424,7 @@ extern "C" int pp_run_snapshot(pp_run r, pp_run *copy) {
         }
     }
     int rc = alloc_run_dev(r->g, c->dev, r->s, r->W, r->cap, r->dev.seed_counts != nullptr,
-                           std::max(pp::pull_grid_for(ts->ntiles), r->pgrid));
+                           std::max(pp::pull_grid_for(ts->ntiles, r->W), r->pgrid));
     if (!rc) rc = alloc_staging(c);
     if (rc) {
         free_run(c);
@@ -1567,7 +1569,7 @@ extern "C" int pp_time_round(pp_run r, int32_t mode, float *features, float *ms)
         for (int i = 0; i < pp::MLP_IN; ++i) features[i] = r->host_ctrl.feat[i];
     for (auto &e : r->tev)
         if (!e) HIP_TRY(hipEventCreate(&e));
-    GraphDev gv = graph_view(r->g, run_tiles(r));
+    GraphDev gv = graph_view(r->g, run_tiles(r), r->W);
     // every direction is valid in every round: forcing one changes the work
     // done, never the result
     HIP_TRY(hipMemcpyAsync(&r->dev.ctrl[0].mode, &mode, sizeof(int32_t), hipMemcpyHostToDevice, r->stream));
@@ -1813,7 +1815,7 @@ extern "C" int pp_propagate_s(pp_graph g, const int32_t *seeds, int32_t s, int32
     int32_t dmax = 0;
     int64_t ex_total = 0;
     bool overflow = false;
-    const GraphDev gv = graph_view(g, nullptr);
+    const GraphDev gv = graph_view(g, nullptr, 0);
     // about 16 Ki waves in all, at least one block per seed, at most one wave per word
     const int64_t want = (16384 / 4 + k - 1) / k, most = (nw + 3) / 4;
     const int bps = (int)std::max<int64_t>(1, std::min(want, most));

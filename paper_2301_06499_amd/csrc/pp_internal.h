@@ -281,6 +281,6 @@ hipError_t launch_batch_persistent(const GraphDev &g, const RunDev &r, const Clu
 hipError_t launch_seed_scatter_batch(const GraphDev &g, const RunDev &r, const int32_t *seeds, hipStream_t st);
 // Largest co-resident grid for the persistent loop at width W.
 int persistent_grid(int W);
-int pull_grid_for(int32_t ntiles);
+int pull_grid_for(int32_t ntiles, int W);
 
 }  // namespace pp

@@ -1796,10 +1796,18 @@ __global__ void __launch_bounds__(BLOCK) k_seed_scatter_batch(GraphDev g, RunDev
 
 // ---------------------------------------------------------------- launchers
 
-// blocks of a pull launch: one wave per tile, four waves per block
-int pull_grid_for(int32_t ntiles) {
+// blocks of a pull launch: one wave per tile, four waves per block, up to a
+// cap measured per row width.  The dispatcher starts blocks in order, so many
+// short-lived blocks keep the blocks in flight on neighbouring tiles and
+// balance themselves; each block also costs its start and its partial sums.
+// One- and two-word rows: 1024 (4096^2 grid 138.4 ms per propagation, 140.3
+// at 2048); four words: 2048 (R-MAT 20 0.709 ms; 0.723 at 1024, 0.734 at
+// 4096); eight words: 2048 below 2^20 tiles, else 32768 (R-MAT 26, s = 512:
+// a dense pull 19.2 ms at 2048, 18.0 at 8192, 17.4 at 32768).
+int pull_grid_for(int32_t ntiles, int W) {
     const int b = (ntiles + BLOCK / 64 - 1) / (BLOCK / 64);
-    return b < 1 ? 1 : (b < PULL_GRID_MAX ? b : PULL_GRID_MAX);
+    const int cap = W <= 2 ? PULL_GRID_MAX / 2 : (W >= 8 && ntiles >= (1 << 20) ? 16 * PULL_GRID_MAX : PULL_GRID_MAX);
+    return b < 1 ? 1 : (b < cap ? b : cap);
 }
 
 // blocks of the per-node launches (node sums), and the push launch's least
