@@ -1801,12 +1801,13 @@ __global__ void __launch_bounds__(BLOCK) k_seed_scatter_batch(GraphDev g, RunDev
 // short-lived blocks keep the blocks in flight on neighbouring tiles and
 // balance themselves; each block also costs its start and its partial sums.
 // One- and two-word rows: 1024 (4096^2 grid 138.4 ms per propagation, 140.3
-// at 2048); four words: 2048 (R-MAT 20 0.709 ms; 0.723 at 1024, 0.734 at
-// 4096); eight words: 2048 below 2^20 tiles, else 32768 (R-MAT 26, s = 512:
-// a dense pull 19.2 ms at 2048, 18.0 at 8192, 17.4 at 32768).
+// at 2048); four and eight words: 2048 below 2^20 tiles (R-MAT 20, four
+// words: 0.709 ms; 0.723 at 1024, 0.734 at 4096), else 32768 (R-MAT 26: with
+// s = 512 a dense pull takes 19.2 ms at 2048, 18.0 at 8192, 17.4 at 32768;
+// two groups of 256 seeds take 105.1 ms at 2048, 102.2 at 32768).
 int pull_grid_for(int32_t ntiles, int W) {
     const int b = (ntiles + BLOCK / 64 - 1) / (BLOCK / 64);
-    const int cap = W <= 2 ? PULL_GRID_MAX / 2 : (W >= 8 && ntiles >= (1 << 20) ? 16 * PULL_GRID_MAX : PULL_GRID_MAX);
+    const int cap = W <= 2 ? PULL_GRID_MAX / 2 : (ntiles >= (1 << 20) ? 16 * PULL_GRID_MAX : PULL_GRID_MAX);
     return b < 1 ? 1 : (b < cap ? b : cap);
 }
 
