@@ -68,7 +68,9 @@ thread_local void *t_alloc_stream = nullptr;
 template <typename T> int dev_alloc(T **p, int64_t count) {
     if (count <= 0) count = 1;
     *p = (T *)pp::dev_malloc(sizeof(T) * (size_t)count);
-    if (!*p) return fail(PP_ENOMEM, "device allocation of %lld bytes failed", (long long)(sizeof(T) * count));
+    if (!*p)
+        return fail(PP_ENOMEM, "device allocation of %lld bytes failed (or the caller's allocator gave a block "
+                               "that is not 256-byte aligned)", (long long)(sizeof(T) * count));
     return PP_OK;
 }
 
@@ -851,6 +853,10 @@ void *pp::dev_malloc(size_t bytes) {
         return p;
     }
     void *p = a.alloc(bytes, t_alloc_stream, a.ctx);
+    if (p && (reinterpret_cast<uintptr_t>(p) & 255u) != 0) {   // the kernels' vector accesses need the alignment
+        a.release(p, t_alloc_stream, a.ctx);
+        return nullptr;
+    }
     if (p) {
         std::lock_guard<std::mutex> lk(g_alloc_mu);
         g_owned[p] = OwnedBlock{a, t_alloc_stream};

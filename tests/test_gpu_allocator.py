@@ -79,6 +79,16 @@ def test_failed_allocation_is_reported():
         assert e.value.code == pp.PP_ENOMEM
     finally:
         pp.pp_set_allocator(None, None)
+    # a block off the 256-byte alignment is handed back and reported
+    a = CountingAllocator()
+    pp.pp_set_allocator(lambda n, st: a.alloc(n + 256, st) + 64, lambda p, st: a.release(p - 64, st))
+    try:
+        with pytest.raises(pp.PPError) as e:
+            pp.pp_seeds_init(G, np.array([0, 50], np.int32))
+        assert e.value.code == pp.PP_ENOMEM and "aligned" in str(e.value)
+    finally:
+        pp.pp_set_allocator(None, None)
+    assert a.live == {} and a.allocs >= 1
     r = pp.pp_seeds_init(G, np.array([0, 50], np.int32))
     c, D = pp.pp_propagate_until_converged(r)
     assert int(D[0]) == 99   # node 99 lies 99 hops from seed 0
