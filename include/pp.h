@@ -34,7 +34,9 @@
  *   - Arguments are validated before any device work; a failed validation
  *     leaves the handles unchanged.
  *   - Handles are not thread-safe: use one thread per handle at a time.
- *   - Device memory is owned by the handles and released by the *_free calls.
+ *   - Device memory is owned by the handles and released by the *_free calls;
+ *     it comes from hipMalloc, or from the caller's allocator when one is set
+ *     (pp_set_allocator).
  */
 #ifndef PP_H
 #define PP_H
@@ -138,9 +140,10 @@ void pp_options_default(pp_options *opt);
  * single calls.
  *   alloc(bytes, stream, ctx)   returns device memory of at least `bytes`
  *               bytes, 256-byte aligned, or NULL (the calling entry point
- *               then returns PP_ENOMEM).  stream is the hipStream_t of the
- *               graph, run or call being served (NULL: the legacy default
- *               stream, also for calls that take no stream).
+ *               then returns PP_ENOMEM; so does a block off that alignment,
+ *               which is handed back first).  stream is the hipStream_t the
+ *               caller gave the entry point that allocates (NULL when it gave
+ *               none, and for entry points that take no stream).
  *   release(ptr, stream, ctx)   takes a block back, with the stream it was
  *               allocated for; the library first waits for the device to
  *               finish with it, as hipFree does.
