@@ -9,7 +9,7 @@
 // algorithm's early break); one ballot gives the word's new bits.  A lane
 // walks a short list itself, four arcs per step.  Nodes with more than
 // SEQ_LIGHT successors (listed once per graph) are left to a second launch
-// in which a group of 16 lanes takes one such node and walks its list 64
+// in which a group of 32 lanes takes one such node and walks its list 128
 // arcs per step up to the first step with a hit, so a hub costs one group,
 // not the word that holds it.  Each pass counts, per seed, the nodes it found and
 // the arcs it examined (up to and including the first hit of each node); a
@@ -115,12 +115,14 @@ __global__ void __launch_bounds__(BLOCK) k_seq_pass(GraphDev g, SeqDev S, int r)
 }
 
 // Pass r, nodes with long lists (heavy[0..nheavy), stored ids): a group of
-// 16 lanes per node, four nodes per wave, each lane four arcs per step (64
+// 32 lanes per node, two nodes per wave, each lane four arcs per step (128
 // arcs per node and step, in arc order); a hit sets the node's bit in the
-// next signature (written by k_seq_pass before, in stream order).
+// next signature (written by k_seq_pass before, in stream order).  R-MAT 20,
+// 256 seeds: 25.3 ms per propagation with 32 lanes, 27.4 with 16, 34.1 with
+// 8, 27.5 with 64.
 __global__ void __launch_bounds__(BLOCK) k_seq_heavy(GraphDev g, SeqDev S, const int32_t *heavy, int64_t nheavy,
                                                     int r) {
-    constexpr int GL = 16;                 // lanes per node
+    constexpr int GL = 32;                 // lanes per node
     constexpr int GW = 64 / GL;            // nodes per wave
     const int j = blockIdx.y;
     if (S.done[j]) return;   // the same for the whole block
@@ -128,7 +130,7 @@ __global__ void __launch_bounds__(BLOCK) k_seq_heavy(GraphDev g, SeqDev S, const
     uint64_t *nxt = buffer(S, r, j);
     const int ln = lane();
     const int grp = ln / GL, sub = ln % GL;
-    const uint64_t gmask = ((1ull << GL) - 1) << (grp * GL);
+    const uint64_t gmask = GL == 64 ? ~0ull : (((1ull << (GL & 63)) - 1) << (grp * GL));
     const int64_t wave = (int64_t)blockIdx.x * (BLOCK / 64) + (threadIdx.x >> 6);
     const int64_t nwaves = (int64_t)gridDim.x * (BLOCK / 64);
     int64_t found = 0, exam = 0;
