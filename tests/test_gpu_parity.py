@@ -243,13 +243,17 @@ def test_batched_union_matches_solo_runs():
         seeds.append(sd + offs[-1])
         offs.append(offs[-1] + g.n)
     n = offs[-1]
-    for sched, persistent in [(sc_, p_) for sc_ in SCHEDS for p_ in (False, True)]:
-        say("batch", sched, "persistent", persistent)
+    # every direction policy on both engines, and sparse rounds as sparse pulls
+    # (or mixed with pushes) on the per-round engine
+    cases = [(sc_, p_, 0) for sc_ in SCHEDS for p_ in (False, True)] + \
+            [(sc_, False, sp) for sc_ in (pp.PP_SCHED_PUSH, pp.PP_SCHED_HEURISTIC, pp.PP_SCHED_FUZZ) for sp in (1, 2)]
+    for sched, persistent, sparse in cases:
+        say("batch", sched, "persistent", persistent, "sparse_pull", sparse)
         G = pp.pp_csr_build(n, np.concatenate(srcs).astype(np.int32), np.concatenate(dsts).astype(np.int32),
                             node_offsets=offs)
         r = pp.pp_seeds_init(G, np.concatenate(seeds), s=s,
                              opts=pp.options(scheduler=sched, seed_counts=True, max_rounds=400, fuzz_seed=1,
-                                             persistent=persistent))
+                                             persistent=persistent, sparse_pull=sparse))
         counts, D = pp.pp_propagate_until_converged(r)
         sc = pp.pp_get_seed_counts(r, 400)
         for k, w in enumerate(wants):
