@@ -645,6 +645,17 @@ PP_DEV void phase_pull(const GraphDev &g, const RunDev &R, int bid, int nb) {
         }
         if (tn < g.ntiles) stage_tile<K, NODES>(g, Tn, ln, cv, rv0, rv1);
         if (skip) {
+            // a graph of the batch that has converged gathers nothing, but its
+            // rows still go to the other buffer: its last round may have been a
+            // push, which set bits in this buffer only, and the pull is about
+            // to make the other one current
+            if (!hub) {
+#pragma unroll
+                for (int j = 0; j < W; ++j) {
+                    const int idx = ln + j * 64;
+                    if (idx < nn * W) nxt[(int64_t)T.u0 * W + idx] = sig[(int64_t)T.u0 * W + idx];
+                }
+            }
             T = Tn;
             continue;
         }

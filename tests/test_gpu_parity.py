@@ -234,7 +234,7 @@ def test_batched_union_matches_solo_runs():
         sd = gen.sample_seeds(g.n, min(s, g.n), 20 + k)
         if len(sd) < s:
             sd = np.resize(sd, s)
-        wants.append(oracle.propagate(g.n, g.src, g.dst, sd, g.undirected, seed_counts=True))
+        wants.append(oracle.propagate(g.n, g.src, g.dst, sd, g.undirected, seed_counts=True, final_sig=True))
         src, dst = g.src.astype(np.int64), g.dst.astype(np.int64)
         if g.undirected:
             src, dst = np.concatenate([src, dst]), np.concatenate([dst, src])
@@ -256,11 +256,14 @@ def test_batched_union_matches_solo_runs():
                                              persistent=persistent, sparse_pull=sparse))
         counts, D = pp.pp_propagate_until_converged(r)
         sc = pp.pp_get_seed_counts(r, 400)
+        sig = pp.pp_get_signatures(r)
         for k, w in enumerate(wants):
             assert int(D[k]) == w["D"], k
             assert list(counts[k][:w["D"] + 1]) == list(w["counts"]), k
             assert not counts[k][w["D"] + 1:].any()
             assert np.array_equal(sc[k][:w["D"] + 1], w["seed_counts"]), k
+            # every graph's final signatures, also of graphs that converged long before the last
+            assert np.array_equal(sig[offs[k]:offs[k + 1]], pad_words(w["final_sig"], r.words)), k
 
 
 # ------------------------------------------------------------ full size
