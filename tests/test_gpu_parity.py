@@ -497,6 +497,36 @@ def test_node_stats(case, sched, keep_order):
     assert np.array_equal(gr, wr) and np.array_equal(gd, wd)
 
 
+@pytest.mark.parametrize("sched", [pp.PP_SCHED_FUZZ, pp.PP_SCHED_HEURISTIC])
+def test_node_stats_batched_union(sched):
+    """Per-node sums on a batch of graphs that converge at different rounds, each
+    graph's slice against the oracle's BFS distances of that graph alone."""
+    import oracle.node_stats as ons
+    graphs = [gen.path_graph(120), gen.rmat(10, 8, 4), gen.grid_graph(9, 7), gen.cycle_graph(31, directed=True)]
+    s = 16
+    offs, srcs, dsts, seeds, wants = [0], [], [], [], []
+    for k, g in enumerate(graphs):
+        sd = gen.sample_seeds(g.n, s, 40 + k)
+        wants.append(ons.node_stats(g.n, g.src, g.dst, sd, g.undirected))
+        src, dst = g.src.astype(np.int64), g.dst.astype(np.int64)
+        if g.undirected:
+            src, dst = np.concatenate([src, dst]), np.concatenate([dst, src])
+        srcs.append(src + offs[-1])
+        dsts.append(dst + offs[-1])
+        seeds.append(sd + offs[-1])
+        offs.append(offs[-1] + g.n)
+    say("node_stats batch", sched)
+    G = pp.pp_csr_build(offs[-1], np.concatenate(srcs).astype(np.int32), np.concatenate(dsts).astype(np.int32),
+                        node_offsets=offs)
+    r = pp.pp_seeds_init(G, np.concatenate(seeds).astype(np.int32), s=s,
+                         opts=pp.options(scheduler=sched, fuzz_seed=7, node_stats=True, max_rounds=300))
+    pp.pp_propagate_until_converged(r)
+    gr, gd = pp.pp_get_node_stats(r)
+    for k, (wr, wd) in enumerate(wants):
+        assert np.array_equal(gr[offs[k]:offs[k + 1]], wr), k
+        assert np.array_equal(gd[offs[k]:offs[k + 1]], wd), k
+
+
 def test_node_stats_errors():
     g = gen.path_graph(20)
     G = pp.pp_csr_build(g.n, g.src, g.dst, undirected=True)
