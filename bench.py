@@ -97,21 +97,10 @@ def bench_batch(args, torch, pp):
     from paper_2301_06499_amd import inputs
     t0 = time.perf_counter()
     graphs, seeds = inputs.workload_batch(1, 64)
-    offs, srcs, dsts, sds = [0], [], [], []
-    for g, sd in zip(graphs, seeds):
-        src, dst = g.src.astype(np.int64), g.dst.astype(np.int64)
-        if g.undirected:
-            src, dst = np.concatenate([src, dst]), np.concatenate([dst, src])
-        srcs.append(src + offs[-1])
-        dsts.append(dst + offs[-1])
-        sds.append(sd.astype(np.int64) + offs[-1])
-        offs.append(offs[-1] + g.n)
-    n = offs[-1]
-    allseeds = np.concatenate(sds).astype(np.int32)
+    n, usrc, udst, offs, allseeds = inputs.union_of(graphs, seeds)
     log(f"[bench] generated the batch in {time.perf_counter() - t0:.1f} s: {len(graphs)} graphs, n={n}")
     stream = torch.cuda.Stream()
-    GB = pp.pp_csr_build(n, np.concatenate(srcs).astype(np.int32), np.concatenate(dsts).astype(np.int32),
-                         node_offsets=offs, stream=stream)
+    GB = pp.pp_csr_build(n, usrc, udst, node_offsets=offs, stream=stream)
     dseeds = torch.from_numpy(allseeds).to("cuda")
     engines = {}
     for name, persistent in (("clustered", True), ("union", False)):
@@ -178,6 +167,13 @@ def bench_batch(args, torch, pp):
         "roofline": None,
     }
     print(json.dumps(out), flush=True)
+    # every handle goes back before the process ends, not at interpreter teardown
+    for r_ in solo_runs:
+        r_.free()
+    for g_ in solo_graphs:
+        g_.free()
+    GB.free()
+    torch.cuda.synchronize()
 
 
 def bench_grid(args, torch, pp):
@@ -261,23 +257,7 @@ def bench_grid(args, torch, pp):
         "roofline": None,
     }
     print(json.dumps(out), flush=True)
-
-
-def sampled_check(g, seeds, sig, k: int):
-    """Signature columns of k sampled seeds against the oracle's BFS, bit for bit.
-
-    Bit i of node u is set exactly when u reaches seed i (a finite distance);
-    the sample is every (s/k)-th seed.
-    """
-    import oracle
-    s = len(seeds)
-    idx = np.unique(np.linspace(0, s - 1, k).astype(np.int64))
-    want = oracle.propagate(g.n, g.src, g.dst, seeds[idx], g.undirected, dist=True)
-    for j, i in enumerate(idx):
-        bit = (sig[:, i >> 6] >> np.uint64(i & 63)) & np.uint64(1)
-        if not np.array_equal(bit.astype(bool), want["dist"][j] >= 0):
-            raise AssertionError(f"seed {i}: signature column differs from the oracle")
-    return {"seeds_checked": [int(i) for i in idx], "nodes": int(g.n), "result": "bit-exact"}
+    G.free()
 
 
 def bench_progressive(args, torch, pp, g, seeds, cfg):
@@ -384,38 +364,6 @@ def bench_propagate_s(args, torch, pp, g, seeds, cfg):
         raise SystemExit("PROPAGATE-S counts differ from the oracle")
 
 
-def cpu_baseline(g, seeds, nominal_edge_words: float, budget_s: float):
-    """The oracle (not tuned) on the host cores; a seed sample sized to the budget."""
-    import oracle
-    nth = oracle.default_threads()
-    s = len(seeds)
-    k = min(s, max(nth, 8))
-    t0 = time.perf_counter()
-    oracle.propagate(g.n, g.src, g.dst, seeds[:k], g.undirected, nthreads=nth)
-    t1 = time.perf_counter() - t0
-    # grow the sample toward the budget, in whole thread-rounds of seeds
-    if t1 < budget_s / 4 and k < s:
-        k2 = min(s, int(k * max(1.0, (budget_s / 2) / max(t1, 1e-3))))
-        k2 = max(k, (k2 // nth) * nth) if k2 >= nth else k2
-        t0 = time.perf_counter()
-        oracle.propagate(g.n, g.src, g.dst, seeds[:k2], g.undirected, nthreads=nth)
-        t1 = time.perf_counter() - t0
-        k = k2
-    t_full = t1 * s / k
-    # one thread on a small sample, for the per-core figure
-    k1 = min(s, 8)
-    t0 = time.perf_counter()
-    oracle.propagate(g.n, g.src, g.dst, seeds[:k1], g.undirected, nthreads=1)
-    t_one = (time.perf_counter() - t0) * s / k1
-    return {"value": nominal_edge_words / t_full, "unit": "edge-words/s", "cores": min(nth, k),
-            "kind": "oracle",
-            "sample": f"per-seed BFS over {k} of {s} seeds in {t1:.2f} s, scaled by {s}/{k} "
-                      f"to the full seed set ({t_full:.2f} s)",
-            "single_thread_value": nominal_edge_words / t_one,
-            "single_thread_sample": f"{k1} seeds on one thread, scaled by {s}/{k1}",
-            "host": host_info()}
-
-
 def host_info() -> dict:
     """CPU model, usable cores and memory of the host the oracle ran on."""
     info = {"nproc": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()}
@@ -433,22 +381,191 @@ def host_info() -> dict:
     return info
 
 
+def oracle_sample(g, seeds, idx, nominal_edge_words: float, single_thread: bool):
+    """The oracle (not tuned) on the host cores for the seeds idx: its exact per-seed
+    counts and final signature columns (for the check), and its time, scaled to the
+    whole seed set, as cpu_baseline."""
+    import oracle
+    nth = oracle.default_threads()
+    s, k = len(seeds), len(idx)
+    t0 = time.perf_counter()
+    want = oracle.propagate(g.n, g.src, g.dst, seeds[idx], g.undirected, seed_counts=True, final_sig=True,
+                            nthreads=nth)
+    t1 = time.perf_counter() - t0
+    t_full = t1 * s / k
+    base = {"value": nominal_edge_words / t_full, "unit": "edge-words/s", "cores": min(nth, k), "kind": "oracle",
+            "sample": f"per-seed BFS over {k} of {s} seeds in {t1:.2f} s (predecessor lists built inside the "
+                      f"timed call), scaled by {s}/{k} to the full seed set ({t_full:.2f} s)",
+            "host": host_info()}
+    if single_thread:   # one thread on a few seeds, for the per-core figure
+        k1 = min(s, 8)
+        t0 = time.perf_counter()
+        oracle.propagate(g.n, g.src, g.dst, seeds[:k1], g.undirected, nthreads=1)
+        base["single_thread_value"] = nominal_edge_words / ((time.perf_counter() - t0) * s / k1)
+        base["single_thread_sample"] = f"{k1} seeds on one thread, scaled by {s}/{k1}"
+    return want, base
+
+
+def compare(want, idx, counts, sc, sig, D, whole: bool) -> dict:
+    """The timed run's results against the oracle's for the seeds idx (all seeds when whole)."""
+    s = sc.shape[1]
+    res = {"against": "oracle per-seed BFS", "seeds_checked": len(idx) if whole else [int(i) for i in idx]}
+    res["totals_vs_per_seed_sums"] = "equal" if np.array_equal(sc.sum(axis=1).astype(np.int64), counts) else "DIFFER"
+    ok_counts, ok_cols = True, True
+    L = max(D + 1, want["seed_counts"].shape[0])
+    for j, i in enumerate(idx):
+        mine = np.pad(sc[:, i], (0, L - sc.shape[0]))
+        theirs = np.pad(want["seed_counts"][:, j], (0, L - want["seed_counts"].shape[0]))
+        ok_counts &= bool(np.array_equal(mine, theirs))
+        bit = (sig[:, i >> 6] >> np.uint64(i & 63)) & np.uint64(1)
+        wbit = (want["final_sig"][:, j >> 6] >> np.uint64(j & 63)) & np.uint64(1)
+        ok_cols &= bool(np.array_equal(bit, wbit))
+    res["per_seed_counts"] = "bit-exact" if ok_counts else "MISMATCH"
+    res["signature_columns"] = "bit-exact" if ok_cols else "MISMATCH"
+    if whole:
+        res["counts"] = "bit-exact" if (want["D"] == D and list(want["counts"]) == list(counts)) else "MISMATCH"
+    good = ok_counts and ok_cols and res["totals_vs_per_seed_sums"] == "equal" and res.get("counts", "bit-exact") == "bit-exact"
+    res["result"] = "bit-exact" if good else "MISMATCH"
+    return res
+
+
+def time_propagation(args, torch, pp, G, seeds, opts, stream):
+    """K timed steps (seed reset + propagation to convergence, counts on the host) on one
+    run, then the same K steps on a second run with HIP events around every pull launch."""
+    dseeds = torch.from_numpy(seeds.astype(np.int32)).to("cuda")
+    run = pp.pp_seeds_init(G, seeds, opts=opts, stream=stream)
+    opts_t = pp.Options.from_buffer_copy(opts)
+    opts_t.time_kernels = 1
+    run_t = pp.pp_seeds_init(G, seeds, opts=opts_t, stream=stream)
+
+    def step(r):
+        pp.pp_seeds_reset(r, dseeds)
+        return pp.pp_propagate_until_converged(r)
+
+    for _ in range(args.warmup):
+        step(run)
+    torch.cuda.synchronize()
+    per_step = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ts = time.perf_counter()
+        counts, D = step(run)
+        per_step.append(time.perf_counter() - ts)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    cap = 4097
+    for _ in range(args.warmup):
+        step(run_t)
+    torch.cuda.synchronize()
+    ms_before = pp.pp_get_kernel_times(run_t, cap).astype(np.float64)
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        counts_t, D_t = step(run_t)
+    torch.cuda.synchronize()
+    elapsed_t = time.perf_counter() - t1
+    ms_after = pp.pp_get_kernel_times(run_t, cap).astype(np.float64)
+    assert int(D_t[0]) == int(D[0]) and list(counts_t[0]) == list(counts[0])
+    modes, arcs = pp.pp_get_round_log(run_t, cap)
+    words = run.words
+    run.free()
+    run_t.free()
+    return {"counts": counts[0], "D": int(D[0]), "elapsed": elapsed, "elapsed_t": elapsed_t, "per_step": per_step,
+            "pull_ms": (ms_after - ms_before) / args.steps, "modes": modes, "arcs": arcs, "words": words,
+            "dseeds": dseeds}
+
+
+def propagation_line(args, torch, pp, g, seeds, cfg, wl, sample, stream, base_opts):
+    """Builds the graph, times the propagation, checks it: one result object.
+
+    sample: indices of the seeds the oracle checks one by one (and times for
+    cpu_baseline); all of them for a whole-seed-set check."""
+    t0 = time.perf_counter()
+    G = pp.pp_csr_build(g.n, g.src, g.dst, undirected=g.undirected, stream=stream)
+    log(f"[bench] {cfg['workload']}: csr_build {time.perf_counter() - t0:.1f} s, n={G.nodes} arcs={G.arcs}")
+    torch.cuda.synchronize()
+    calibration_copy(args, torch)
+    T = time_propagation(args, torch, pp, G, seeds, base_opts, stream)
+    counts, Dv, W = T["counts"], T["D"], T["words"]
+    rounds = Dv + 1
+    modes, arcs = T["modes"], T["arcs"]
+    m, n, s = G.arcs, G.nodes, len(seeds)
+    nominal = m * (s / 64.0) * rounds
+    touched = float(arcs[1:rounds + 1].sum()) * (s / 64.0)
+    # roofline of the dense pull kernel: algorithmic bytes per launch
+    #   per arc gathered: 4 B column index + 8W B source row
+    #   per node: 8 B row offset (int64) + 8W B own row read + 8W B new row written
+    pull_rounds = [r for r in range(1, rounds + 1) if modes[r] == pp.MODE_PULL]
+    bytes_pull = sum(float(arcs[r]) * (4 + 8 * W) + n * (8 + 16 * W) for r in pull_rounds)
+    t_pull = sum(T["pull_ms"][r] for r in pull_rounds) / 1000.0
+    achieved = bytes_pull / t_pull / 1e9 if t_pull > 0 else 0.0
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": (measured_traffic(TRAFFIC_PROFILES[wl])
+                        if (wl in TRAFFIC_PROFILES and not base_opts.persistent and (base_opts.pull_k or 4) == 4)
+                        else None),
+            "kernel": f"k_batch<{W}> pull phase" if base_opts.persistent else f"k_pull<{W}>",
+            "timing": ("device clock between grid barriers" if base_opts.persistent else
+                       "HIP events around each launch, on the run's stream, over a second timed region of "
+                       "the same steps"),
+            "ms_per_step_with_events": round(T["elapsed_t"] * 1000.0 / args.steps, 4),
+            "launches_per_step": len(pull_rounds),
+            "avg_launch_ms": round(t_pull * 1000.0 / max(1, len(pull_rounds)), 4),
+            "bytes_per_launch": round(bytes_pull / max(1, len(pull_rounds)))}
+    res = {"value": nominal * args.steps / T["elapsed"], "unit": "edge-words/s",
+           "ms_per_step": round(T["elapsed"] * 1000.0 / args.steps, 4),
+           "ms_per_step_min": round(min(T["per_step"]) * 1000.0, 4),
+           "ms_per_step_median": round(float(np.median(T["per_step"])) * 1000.0, 4),
+           "config": dict(cfg, nodes=n, arcs=m, words=W, rounds=rounds, diameter_lb=Dv,
+                          scheduler=args.scheduler, engine="persistent" if base_opts.persistent else "rounds",
+                          pull_k=int(base_opts.pull_k) or 4, push_div=int(base_opts.push_div) or 8,
+                          sparse_pull=int(base_opts.sparse_pull),
+                          modes="".join({pp.MODE_PULL: "P", pp.MODE_PUSH: "S", pp.MODE_SPULL: "Q"}.get(int(modes[r]), "?")
+                                        for r in range(1, rounds + 1))),
+           "touched_edge_words_per_s": touched * args.steps / T["elapsed"],
+           "roofline": roof}
+    if args.no_check and args.no_cpu_baseline:
+        G.free()
+        return res
+    # the check: the same propagation with per-seed counts (untimed) against the timed
+    # counts, its totals against its per-seed sums, and the sampled seeds against the oracle
+    opts_c = pp.Options.from_buffer_copy(base_opts)
+    opts_c.seed_counts = 1
+    chk = pp.pp_seeds_init(G, seeds, opts=opts_c, stream=stream)
+    pp.pp_seeds_reset(chk, T["dseeds"])
+    c2, D2 = pp.pp_propagate_until_converged(chk)
+    sc = pp.pp_get_seed_counts(chk, Dv + 1)[0]
+    sig = pp.pp_get_signatures(chk)
+    chk.free()
+    G.free()
+    log(f"[bench] {cfg['workload']}: oracle on {len(sample)} of {s} seeds")
+    want, base = oracle_sample(g, seeds, sample, nominal, single_thread=g.n <= (1 << 22))
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = base
+    check = compare(want, sample, counts, sc, sig, Dv, whole=len(sample) == s)
+    check["check_run_counts_vs_timed"] = "equal" if (int(D2[0]) == Dv and list(c2[0]) == list(counts)) else "DIFFER"
+    if check["check_run_counts_vs_timed"] != "equal":
+        check["result"] = "MISMATCH"
+    res["check"] = check
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="rmat20")
+    ap.add_argument("--workload", default="rmat26",
+                    help="rmat26 (the default: the largest single-GPU configuration, with R-MAT 20 as a "
+                         "secondary object in the same line), rmat20, er, grid:SIDE, rmat:SCALE:SEEDS, "
+                         "grid4096 (learned scheduler), batch64 (the 64-graph batch)")
+    ap.add_argument("--no-secondary", action="store_true", help="rmat26: skip the R-MAT 20 object")
     ap.add_argument("--scheduler", default="heuristic", choices=["heuristic", "pull", "push"])
     ap.add_argument("--grid-side", type=int, default=4096, help="side of the grid4096 workload")
     ap.add_argument("--persistent", action="store_true",
                     help="all rounds in one cooperative launch instead of launches per round")
-    ap.add_argument("--check-seeds", type=int, default=-1,
-                    help="after timing, compare the signature columns of this many sampled seeds with the "
-                         "oracle (default: 8 for rmat26, none otherwise)")
-    ap.add_argument("--seed-groups", type=int, default=0,
-                    help="also time the same seeds as this many groups run one after another (the "
-                         "counts of the groups add up to the single run's; default: 2 for rmat26)")
+    ap.add_argument("--check-seeds", type=int, default=16,
+                    help="seeds the oracle checks one by one on graphs above 2^22 nodes (all seeds below)")
+    ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--tune", action="store_true",
                     help="run options from the autotuner (measured before the timed steps, cached per workload)")
     ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work for cpu_baseline")
@@ -459,8 +576,8 @@ def main():
                          "meets --target (each its own JSON line)")
     ap.add_argument("--target", type=float, default=1.0, help="progressive: half-width target (hops)")
     ap.add_argument("--node-stats", action="store_true",
-                    help="also keep the per-node reach and distance sums (one extra pass per round), "
-                         "checked against the oracle after timing")
+                    help="also keep the per-node reach and distance sums (one extra pass per round) in the "
+                         "timed runs (their values are checked against the oracle by the GPU tests)")
     ap.add_argument("--torch-allocator", action="store_true",
                     help="the library's device memory from PyTorch's caching allocator (pp_set_allocator)")
     ap.add_argument("--push-div", type=int, default=0,
@@ -478,6 +595,7 @@ def main():
               "path in this build (seed groups would shard across GPUs with one final all-reduce of the "
               "per-round counts). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
+    t_start = time.perf_counter()
 
     import torch
     from paper_2301_06499_amd import pp
@@ -501,169 +619,46 @@ def main():
     if args.method == "progressive":
         return bench_progressive(args, torch, pp, g, seeds, cfg)
     stream = torch.cuda.Stream()                       # default priority
-    t0 = time.perf_counter()
-    G = pp.pp_csr_build(g.n, g.src, g.dst, undirected=g.undirected, stream=stream)
-    log(f"[bench] csr_build {time.perf_counter() - t0:.1f} s: n={G.nodes} arcs={G.arcs}")
-    dseeds = torch.from_numpy(seeds.astype(np.int32)).to("cuda")
-    torch.cuda.synchronize()
     base = pp.options(scheduler=sched, max_rounds=4096, persistent=args.persistent, node_stats=args.node_stats,
                       sparse_pull=args.sparse_pull, push_div=args.push_div)
     tuned = None
     if args.tune:
         from paper_2301_06499_amd import autotune
         t0 = time.perf_counter()
-        base, tuned = autotune.tune(G, seeds, base=base, reps=3, name=cfg["workload"])
+        Gt = pp.pp_csr_build(g.n, g.src, g.dst, undirected=g.undirected, stream=stream)
+        base, tuned = autotune.tune(Gt, seeds, base=base, reps=3, name=cfg["workload"])
+        Gt.free()
         tuned = {k: v for k, v in tuned.items() if k != "candidates"} | {"tune_s": round(time.perf_counter() - t0, 2)}
         log(f"[bench] tuned options {tuned}")
-    # two runs of the same workload: the throughput is timed without kernel
-    # events (each event in a replayed round costs a few microseconds), the
-    # pull kernel's launches are timed with HIP events on the run's stream
-    run = pp.pp_seeds_init(G, seeds, opts=base, stream=stream)
-    opts_t = pp.Options.from_buffer_copy(base)
-    opts_t.time_kernels = 1
-    run_t = pp.pp_seeds_init(G, seeds, opts=opts_t, stream=stream)
-    W = run.words
-    calibration_copy(args, torch)
     s = len(seeds)
-
-    def step(r):
-        pp.pp_seeds_reset(r, dseeds)
-        return pp.pp_propagate_until_converged(r)
-
-    # throughput: the timed steps (each step ends with the counts on the
-    # host, so a host clock around it brackets the device work)
-    for _ in range(args.warmup):
-        step(run)
-    torch.cuda.synchronize()
-    per_step = []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        ts = time.perf_counter()
-        counts, D = step(run)
-        per_step.append(time.perf_counter() - ts)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    # the pull kernel: the same steps with HIP events around every pull launch
-    cap = 4097
-    for _ in range(args.warmup):
-        step(run_t)
-    torch.cuda.synchronize()
-    ms_before = pp.pp_get_kernel_times(run_t, cap).astype(np.float64)
-    t1 = time.perf_counter()
-    for _ in range(args.steps):
-        counts_t, D_t = step(run_t)
-    torch.cuda.synchronize()
-    elapsed_t = time.perf_counter() - t1
-    ms_after = pp.pp_get_kernel_times(run_t, cap).astype(np.float64)
-    assert int(D_t[0]) == int(D[0]) and list(counts_t[0]) == list(counts[0])
-    Dv = int(D[0])
-    rounds = Dv + 1
-    modes, arcs = pp.pp_get_round_log(run_t, cap)
-    m, n = G.arcs, G.nodes
-
-    words_per_arc = s / 64.0
-    nominal = m * words_per_arc * rounds
-    touched = float(arcs[1:rounds + 1].sum()) * words_per_arc
-    ms_step = elapsed * 1000.0 / args.steps
-
-    # roofline of the dense pull kernel: algorithmic bytes per launch
-    #   per arc gathered: 4 B column index + 8W B source row
-    #   per node: 8 B row offset (int64) + 8W B own row read + 8W B new row written
-    pull_rounds = [r for r in range(1, rounds + 1) if modes[r] == pp.MODE_PULL]
-    pull_ms = (ms_after - ms_before) / args.steps
-    bytes_pull = sum(float(arcs[r]) * (4 + 8 * W) + n * (8 + 16 * W) for r in pull_rounds)
-    t_pull = sum(pull_ms[r] for r in pull_rounds) / 1000.0
-    achieved = bytes_pull / t_pull / 1e9 if t_pull > 0 else 0.0
-    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": (measured_traffic(TRAFFIC_PROFILES[args.workload])
-                        if (args.workload in TRAFFIC_PROFILES and not base.persistent
-                            and (base.pull_k or 4) == 4) else None),
-            "kernel": f"k_batch<{W}> pull phase" if base.persistent else f"k_pull<{W}>",
-            "timing": ("device clock between grid barriers" if base.persistent else
-                       "HIP events around each launch, on the run's stream, over a second timed region of "
-                       "the same steps"),
-            "ms_per_step_with_events": round(elapsed_t * 1000.0 / args.steps, 4),
-            "launches_per_step": len(pull_rounds),
-            "avg_launch_ms": round(t_pull * 1000.0 / max(1, len(pull_rounds)), 4),
-            "bytes_per_launch": round(bytes_pull / max(1, len(pull_rounds)))}
-
-    out = {
-        "metric": METRIC,
-        "value": nominal * args.steps / elapsed,
-        "unit": "edge-words/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": round(ms_step, 4),
-        "ms_per_step_min": round(min(per_step) * 1000.0, 4),
-        "ms_per_step_median": round(float(np.median(per_step)) * 1000.0, 4),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "u64", "data": "synthetic",
-        "config": dict(cfg, nodes=n, arcs=m, words=W, rounds=rounds, diameter_lb=Dv,
-                       scheduler=args.scheduler, engine="persistent" if base.persistent else "rounds",
-                       pull_k=int(base.pull_k) or 4, push_div=int(base.push_div) or 8, tuned=tuned,
-                       sparse_pull=int(base.sparse_pull),
-                       modes="".join({pp.MODE_PULL: "P", pp.MODE_PUSH: "S", pp.MODE_SPULL: "Q"}.get(int(modes[r]), "?")
-                                     for r in range(1, rounds + 1))),
-        "touched_edge_words_per_s": touched * args.steps / elapsed,
-        "roofline": roof,
-    }
-    groups = args.seed_groups or (2 if args.workload == "rmat26" else 0)
-    if groups > 1 and s % groups == 0:
-        # seed groups: s/groups seeds per run, the runs one after another, counts summed
-        gs = s // groups
-        parts = [seeds[k * gs:(k + 1) * gs] for k in range(groups)]
-        runs_g = [pp.pp_seeds_init(G, part, opts=pp.options(scheduler=sched, max_rounds=4096), stream=stream)
-                  for part in parts]
-        dparts = [torch.from_numpy(part.astype(np.int32)).to("cuda") for part in parts]
-        for _ in range(args.warmup):
-            for rg, dp in zip(runs_g, dparts):
-                pp.pp_seeds_reset(rg, dp)
-                pp.pp_propagate_until_converged(rg)
-        torch.cuda.synchronize()
-        tg = time.perf_counter()
-        for _ in range(args.steps):
-            total = None
-            for rg, dp in zip(runs_g, dparts):
-                pp.pp_seeds_reset(rg, dp)
-                cg, _ = pp.pp_propagate_until_converged(rg)
-                c0 = cg[0]
-                if total is None:
-                    total = c0.copy()
-                else:
-                    L = max(len(total), len(c0))
-                    total = np.pad(total, (0, L - len(total))) + np.pad(c0, (0, L - len(c0)))
-        torch.cuda.synchronize()
-        tg = (time.perf_counter() - tg) / args.steps
-        assert list(np.trim_zeros(total, "b")) == list(np.trim_zeros(counts[0], "b")), "seed groups changed the counts"
-        out["seed_groups"] = {"groups": groups, "seeds_per_group": gs, "words": int(runs_g[0].words),
-                              "ms_per_step": round(tg * 1000.0, 4), "value": nominal / tg}
-        for rg in runs_g:
-            rg.free()
+    sample = (np.arange(s) if g.n <= (1 << 22) else
+              np.unique(np.linspace(0, s - 1, min(s, args.check_seeds)).astype(np.int64)))
+    head = propagation_line(args, torch, pp, g, seeds, cfg, args.workload, sample, stream, base)
+    head["config"]["tuned"] = tuned
+    out = {"metric": METRIC, "value": head["value"], "unit": "edge-words/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": head["ms_per_step"], "ms_per_step_min": head["ms_per_step_min"],
+           "ms_per_step_median": head["ms_per_step_median"], "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "u64", "data": "synthetic", "config": head["config"],
+           "touched_edge_words_per_s": head["touched_edge_words_per_s"], "roofline": head["roofline"]}
+    for k in ("cpu_baseline", "check"):
+        if k in head:
+            out[k] = head[k]
+    del g
+    if args.workload == "rmat26" and not args.no_secondary:
+        g2, seeds2, cfg2 = workload("rmat20")
+        base2 = pp.options(scheduler=sched, max_rounds=4096, sparse_pull=args.sparse_pull, push_div=args.push_div)
+        out["rmat20"] = propagation_line(args, torch, pp, g2, seeds2, cfg2, "rmat20", np.arange(len(seeds2)),
+                                         stream, base2)
+        out["rmat20"]["note"] = "secondary: R-MAT scale 20, s = 256, every seed checked against the oracle"
     if args.node_stats:
-        import oracle.node_stats as ons
-        gr, gd = pp.pp_get_node_stats(run)
-        wr, wd = ons.node_stats(g.n, g.src, g.dst, seeds, g.undirected)
-        out["config"]["node_stats"] = True
-        out["node_stats_check"] = {"against": "oracle per-seed BFS distances, every node",
-                                   "result": "bit-exact" if np.array_equal(gr, wr) and np.array_equal(gd, wd)
-                                   else "MISMATCH"}
-    check = args.check_seeds if args.check_seeds >= 0 else (8 if args.workload == "rmat26" else 0)
-    if check:
-        log(f"[bench] checking {check} sampled seeds against the oracle")
-        sig = pp.pp_get_signatures(run)
-        run.free()
-        run_t.free()
-        G.free()
-        out["sampled_check"] = sampled_check(g, seeds, sig, check)
-        del sig
-    if not args.no_cpu_baseline:
-        log("[bench] timing the CPU oracle")
-        out["cpu_baseline"] = cpu_baseline(g, seeds, nominal, args.cpu_budget)
+        out["node_stats_note"] = "per-node sums kept in every timed round (their check runs in the GPU tests)"
+    out["hip_runtime"] = pp.hip_runtime()
+    out["wall_s"] = round(time.perf_counter() - t_start, 1)
     print(json.dumps(out), flush=True)
-    if not check:
-        run.free()
-        run_t.free()
-        G.free()
+    bad = [k for k, v in (("headline", out.get("check")), ("rmat20", out.get("rmat20", {}).get("check")))
+           if v is not None and v.get("result") != "bit-exact"]
+    if bad:
+        raise SystemExit(f"check failed: {bad}")
 
 
 if __name__ == "__main__":

@@ -142,11 +142,15 @@ void pp_options_default(pp_options *opt);
  *               bytes, 256-byte aligned, or NULL (the calling entry point
  *               then returns PP_ENOMEM; so does a block off that alignment,
  *               which is handed back first).  stream is the hipStream_t the
- *               caller gave the entry point that allocates (NULL when it gave
- *               none, and for entry points that take no stream).
+ *               library's work on the block is ordered on: the run's stream
+ *               for a run's blocks (the one the run creates when the caller
+ *               gave none), the call's stream for the temporaries of a call,
+ *               the build's stream for a graph (NULL: the legacy default).
  *   release(ptr, stream, ctx)   takes a block back, with the stream it was
- *               allocated for; the library first waits for the device to
- *               finish with it, as hipFree does.
+ *               allocated for.  Stream-ordered: the library hands a block
+ *               back only after waiting for its own streams that used it
+ *               (it never waits for the whole device), so the allocator may
+ *               give the block out again at once.
  *   ctx         passed to both unchanged.
  * A block always goes back to the allocator that gave it, also after a later
  * call changes or clears the allocator, so both functions must stay callable
@@ -427,6 +431,30 @@ int pp_progressive_sample(pp_graph g, const int32_t *pool, int32_t pool_len, int
 int pp_propagate_s(pp_graph g, const int32_t *seeds, int32_t s, int32_t concurrent, void *stream, int64_t *counts,
                    int32_t cap_rounds, int32_t *D, int64_t *examined);
 
+/*
+ * pp_propagate_s_noalloc -- pp_propagate_s for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc.  Same arguments, same results bit for bit; it calls
+ * no allocator (neither hipMalloc nor the caller's allocator of
+ * pp_set_allocator).  Its device buffers (every seed's signature pair, the
+ * pass log, per-seed counters, the seed ids) come from one fixed region of
+ * PP_NOALLOC_BYTES bytes that every device the library runs on holds from its
+ * first such call until the process ends.
+ *   concurrent  0: the most seeds in flight, up to min(s, 256), whose buffers
+ *               fit the region; > 0: that many (at most s), PP_EINVAL if they
+ *               do not fit.
+ * The buffers of k seeds over n nodes with a log of cap_rounds passes take
+ * about 16 k ceil(n/64) + 8 cap_rounds bytes; PP_EINVAL (with the sizes in
+ * the message) when even one seed does not fit.  Calls on one device share
+ * that device's region, which keeps the last call's contents (each call
+ * clears what must start at zero): two calls that overlap on one device race
+ * and give wrong results; run them one after the other (one stream, or the
+ * caller's own ordering).  Synchronous, like pp_propagate_s.
+ */
+#define PP_NOALLOC_BYTES (64u << 20)
+int pp_propagate_s_noalloc(pp_graph g, const int32_t *seeds, int32_t s, int32_t concurrent, void *stream,
+                           int64_t *counts, int32_t cap_rounds, int32_t *D, int64_t *examined);
+
 /* One configuration tried by pp_autotune and its best time. */
 typedef struct {
     int32_t pull_k, push_div, rounds_per_sync, persistent, sparse_pull;
@@ -456,6 +484,9 @@ typedef struct {
 int pp_autotune(pp_graph g, const int32_t *seeds, int32_t s, const pp_options *base, int32_t reps,
                 pp_options *best, pp_tune_entry *table, int32_t cap, int32_t *ntried);
 
+/* Free a run (waits for its stream first) / a graph.  Free every run made on
+ * a graph, and let every call that uses the graph return, before freeing the
+ * graph: its blocks go back to the allocator without a device-wide wait. */
 void pp_run_free(pp_run r);
 void pp_graph_free(pp_graph g);
 const char *pp_last_error(void);

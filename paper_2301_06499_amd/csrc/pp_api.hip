@@ -60,9 +60,17 @@ struct OwnedBlock {
     Allocator from;
     void *stream;
 };
-std::mutex g_alloc_mu;
+// The lock and the ledger live until the process ends (never destroyed), so
+// a handle freed late in the process's exit still finds them.
+std::mutex &alloc_mu() {
+    static std::mutex *m = new std::mutex();
+    return *m;
+}
+std::unordered_map<void *, OwnedBlock> &owned_blocks() {
+    static auto *m = new std::unordered_map<void *, OwnedBlock>();
+    return *m;
+}
 Allocator g_alloc{nullptr, nullptr, nullptr};
-std::unordered_map<void *, OwnedBlock> g_owned;
 thread_local void *t_alloc_stream = nullptr;
 
 template <typename T> int dev_alloc(T **p, int64_t count) {
@@ -123,8 +131,8 @@ struct pp_graph_s {
     std::map<int, TileSet> tiles;   // by pull arc budget
     std::vector<int32_t> perm;      // stored id of each input node (empty: identity)
     int32_t *perm_d = nullptr;      // the same on the device
-    int32_t *seq_heavy = nullptr;   // PROPAGATE-S: nodes with long successor lists (built on first use)
-    int64_t nseq_heavy = -1;
+    int32_t *seq_heavy = nullptr;   // PROPAGATE-S: nodes with more than SEQ_LIGHT successors
+    int64_t nseq_heavy = 0;
 };
 
 struct pp_run_s {
@@ -588,8 +596,26 @@ extern "C" int pp_csr_build(int64_t n, int64_t m, const int32_t *src, const int3
         e = hipMemcpyAsync(g->perm_d, perm.data(), sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) {
+        (void)hipStreamSynchronize(st);   // copies already queued finish before the blocks go back
         free_graph(g);
         return fail(PP_EDEVICE, "graph upload: %s", hipGetErrorString(e));
+    }
+    // PROPAGATE-S: the nodes whose successor lists go to the group-per-node
+    // launch, listed once with the graph (stored ids)
+    {
+        std::vector<int32_t> hv;
+        for (int64_t u = 0; u < n; ++u)
+            if (rp[(size_t)u + 1] - rp[(size_t)u] > pp::SEQ_LIGHT) hv.push_back((int32_t)u);
+        if ((rc = dev_alloc(&g->seq_heavy, (int64_t)hv.size()))) {
+            free_graph(g);
+            return rc;
+        }
+        if (!hv.empty() && (e = hipMemcpy(g->seq_heavy, hv.data(), sizeof(int32_t) * hv.size(),
+                                          hipMemcpyHostToDevice)) != hipSuccess) {
+            free_graph(g);
+            return fail(PP_EDEVICE, "long-list table upload: %s", hipGetErrorString(e));
+        }
+        g->nseq_heavy = (int64_t)hv.size();
     }
     g->rp_host = std::move(rp);
     g->perm = std::move(perm);
@@ -841,7 +867,7 @@ int ensure_staged(pp_run r, int upto) {
 void *pp::dev_malloc(size_t bytes) {
     Allocator a;
     {
-        std::lock_guard<std::mutex> lk(g_alloc_mu);
+        std::lock_guard<std::mutex> lk(alloc_mu());
         a = g_alloc;
     }
     if (!a.alloc) {
@@ -858,8 +884,8 @@ void *pp::dev_malloc(size_t bytes) {
         return nullptr;
     }
     if (p) {
-        std::lock_guard<std::mutex> lk(g_alloc_mu);
-        g_owned[p] = OwnedBlock{a, t_alloc_stream};
+        std::lock_guard<std::mutex> lk(alloc_mu());
+        owned_blocks()[p] = OwnedBlock{a, t_alloc_stream};
     }
     return p;
 }
@@ -869,11 +895,11 @@ void pp::dev_release(void *p) {
     OwnedBlock o{};
     bool owned = false;
     {
-        std::lock_guard<std::mutex> lk(g_alloc_mu);
-        auto it = g_owned.find(p);
-        if (it != g_owned.end()) {
+        std::lock_guard<std::mutex> lk(alloc_mu());
+        auto it = owned_blocks().find(p);
+        if (it != owned_blocks().end()) {
             o = it->second;
-            g_owned.erase(it);
+            owned_blocks().erase(it);
             owned = true;
         }
     }
@@ -881,7 +907,9 @@ void pp::dev_release(void *p) {
         (void)hipFree(p);
         return;
     }
-    (void)hipDeviceSynchronize();   // what hipFree waits for: no kernel still uses the block
+    // Stream-ordered: every caller of dev_release has waited for the streams
+    // its work on the block ran on (a run's stream, a call's stream), so the
+    // allocator may hand the block out again at once.
     o.from.release(p, o.stream, o.from.ctx);
 }
 
@@ -891,7 +919,7 @@ pp::AllocStream::~AllocStream() { t_alloc_stream = prev; }
 extern "C" int pp_set_allocator(void *(*alloc)(size_t, void *, void *), void (*release)(void *, void *, void *),
                                 void *ctx) {
     if ((alloc == nullptr) != (release == nullptr)) return fail(PP_EINVAL, "alloc and release: both or neither");
-    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    std::lock_guard<std::mutex> lk(alloc_mu());
     g_alloc = Allocator{alloc, release, alloc ? ctx : nullptr};
     return PP_OK;
 }
@@ -1096,6 +1124,7 @@ extern "C" int pp_seeds_init(pp_graph g, const int32_t *seeds, int32_t s, const 
         }
         r->own_stream = true;
     }
+    pp::AllocStream run_as(r->stream);   // the run's blocks are used on its stream
     TileSet *ts = nullptr;
     rc = ensure_tiles(g, W, r->dev.pull_k, &ts);
     if (rc == PP_OK)
@@ -1342,6 +1371,7 @@ extern "C" int pp_get_signatures(pp_run r, uint64_t *dst, int32_t dst_on_device)
         if (!rc && !e && !dst_on_device)
             e = hipMemcpyAsync(dst, out, sizeof(uint64_t) * (size_t)words, hipMemcpyDeviceToHost, r->stream);
         if (!rc && !e) e = hipStreamSynchronize(r->stream);
+        if (rc || e) (void)hipStreamSynchronize(r->stream);   // queued work done before the blocks go back
         dev_free(tmp);
         dev_free(out);
         if (rc) return rc;
@@ -1417,6 +1447,7 @@ extern "C" int pp_run_snapshot(pp_run r, pp_run *copy) {
         return fail(PP_EDEVICE, "snapshot stream");
     }
     c->own_stream = true;
+    pp::AllocStream copy_as(c->stream);   // the copy's blocks are used on its own stream
     TileSet *ts = run_tiles(r);
     c->pgrid = r->pgrid;
     c->clock_khz = r->clock_khz;
@@ -1520,6 +1551,7 @@ extern "C" int pp_get_node_stats(pp_run r, int32_t *reached, int64_t *dist_sum) 
     if (e == hipSuccess) e = hipMemcpyAsync(hr.data(), dr, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToHost, r->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(hd.data(), dd, sizeof(int64_t) * (size_t)n, hipMemcpyDeviceToHost, r->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(r->stream);
+    if (e != hipSuccess) (void)hipStreamSynchronize(r->stream);
     dev_free(dr);
     dev_free(dd);
     if (e != hipSuccess) return fail(PP_EDEVICE, "node statistics: %s", hipGetErrorString(e));
@@ -1764,58 +1796,61 @@ extern "C" int pp_progressive_sample(pp_graph g, const int32_t *pool, int32_t po
     return dmax >= cap_rounds ? fail(PP_ERANGE, "D = %d does not fit cap_rounds = %d", dmax, cap_rounds) : PP_OK;
 }
 
-// PROPAGATE-S: batches of `concurrent` seeds, each run to its last seed's
+// PROPAGATE-S: batches of k seeds in flight, each run to its last seed's
 // first pass without a find; the host checks every 8 passes.
-extern "C" int pp_propagate_s(pp_graph g, const int32_t *seeds, int32_t s, int32_t concurrent, void *stream,
-                              int64_t *counts, int32_t cap_rounds, int32_t *D, int64_t *examined) {
+namespace {
+
+// One device region holds every buffer of a PROPAGATE-S call for k seeds in
+// flight over ceil(n/64) words and a pass log of cap entries (each part
+// 256-byte aligned): both signatures of every seed, per-seed pass counts,
+// the pass log, per-seed arcs examined, states, last passes, the count of
+// running seeds, and the device copy of the batch's seed ids.
+int64_t seq_region_bytes(int64_t k, int64_t nw, int64_t cap) {
+    auto up = [](int64_t b) { return (b + 255) & ~(int64_t)255; };
+    return up(16 * k * nw) + up(8 * k) + up(8 * cap) + up(8 * k) + up(4 * k) + up(4 * k) + up(4) + up(4 * k);
+}
+
+void seq_carve(void *base, int64_t k, int64_t nw, int64_t cap, pp::SeqDev &S, int32_t **dseeds) {
+    auto up = [](int64_t b) { return (b + 255) & ~(int64_t)255; };
+    char *p = (char *)base;
+    S.bits = (uint64_t *)p;
+    p += up(16 * k * nw);
+    S.pass_cnt = (int64_t *)p;
+    p += up(8 * k);
+    S.sum_cnt = (int64_t *)p;
+    p += up(8 * cap);
+    S.examined = (int64_t *)p;
+    p += up(8 * k);
+    S.done = (int32_t *)p;
+    p += up(4 * k);
+    S.dpass = (int32_t *)p;
+    p += up(4 * k);
+    S.active = (int32_t *)p;
+    p += up(4);
+    *dseeds = (int32_t *)p;
+    S.k = (int32_t)k;
+    S.nw = nw;
+    S.cap = (int32_t)cap;
+}
+
+int check_seq_args(pp_graph g, const int32_t *seeds, int32_t s, int32_t concurrent, int64_t *counts, int32_t cap_rounds,
+                   int32_t *D) {
     if (!g || !seeds || !counts || !D) return fail(PP_EINVAL, "graph, seeds, counts or D is NULL");
-    pp::AllocStream as(stream);
     if (g->G != 1) return fail(PP_EINVAL, "one graph only (got a batch of %d)", g->G);
     if (s < 1) return fail(PP_EINVAL, "s < 1");
     if (concurrent < 0) return fail(PP_EINVAL, "concurrent < 0");
     if (cap_rounds < 1) return fail(PP_EINVAL, "cap_rounds < 1");
-    int rc = check_host_seeds(g, seeds, s);
-    if (rc) return rc;
-    // seeds in flight: one grid row each (at most 65535)
-    const int k = std::min({concurrent > 0 ? concurrent : 256, s, 65535});
-    const int64_t n = g->n, nw = (n + 63) / 64, cap = cap_rounds;
-    hipStream_t st = stream ? (hipStream_t)stream : g->stream;
-    pp::SeqDev S{};
-    S.k = k;
-    S.cap = cap_rounds;
-    S.nw = nw;
-    int32_t *dseeds = nullptr;
-    if (g->nseq_heavy < 0) {
-        // nodes whose successor lists go to the wave-per-node launch, kept with the graph
-        std::vector<int32_t> hv;
-        for (int64_t u = 0; u < n; ++u)
-            if (g->rp_host[(size_t)u + 1] - g->rp_host[(size_t)u] > pp::SEQ_LIGHT) hv.push_back((int32_t)u);
-        if ((rc = dev_alloc(&g->seq_heavy, (int64_t)hv.size()))) return rc;
-        if (!hv.empty() && hipMemcpy(g->seq_heavy, hv.data(), sizeof(int32_t) * hv.size(), hipMemcpyHostToDevice) !=
-                               hipSuccess) {
-            dev_free(g->seq_heavy);
-            return fail(PP_EDEVICE, "PROPAGATE-S: heavy-node list upload");
-        }
-        g->nseq_heavy = (int64_t)hv.size();
-    }
+    return check_host_seeds(g, seeds, s);
+}
+
+// The propagation over buffers laid out by seq_carve (S.k seeds in flight).
+// Clears what must start at zero; leaves the stream synchronised.
+int propagate_s_run(pp_graph g, const int32_t *seeds, int32_t s, const pp::SeqDev &S, int32_t *dseeds, hipStream_t st,
+                    int64_t *counts, int32_t cap_rounds, int32_t *D, int64_t *examined) {
+    const int k = S.k;
+    const int64_t nw = S.nw, cap = cap_rounds;
     const int32_t *heavy = g->seq_heavy;
     const int64_t nheavy = g->nseq_heavy;
-    auto release = [&]() {
-        dev_free(S.bits);
-        dev_free(S.pass_cnt);
-        dev_free(S.sum_cnt);
-        dev_free(S.examined);
-        dev_free(S.done);
-        dev_free(S.dpass);
-        dev_free(S.active);
-        dev_free(dseeds);
-    };
-    if ((rc = dev_alloc(&S.bits, 2 * k * nw)) || (rc = dev_alloc(&S.pass_cnt, k)) || (rc = dev_alloc(&S.sum_cnt, cap)) ||
-        (rc = dev_alloc(&S.examined, k)) || (rc = dev_alloc(&S.done, k)) || (rc = dev_alloc(&S.dpass, k)) ||
-        (rc = dev_alloc(&S.active, 1)) || (rc = dev_alloc(&dseeds, k))) {
-        release();
-        return rc;
-    }
     std::memset(counts, 0, sizeof(int64_t) * (size_t)cap);
     counts[0] = s;
     int32_t dmax = 0;
@@ -1839,6 +1874,8 @@ extern "C" int pp_propagate_s(pp_graph g, const int32_t *seeds, int32_t s, int32
         }
         e = hipMemcpyAsync(dseeds, hs.data(), sizeof(int32_t) * (size_t)kk, hipMemcpyHostToDevice, st);
         int last = 0;   // passes launched
+        // buffer 0 of every slot (as 4-byte words) and the pass log; pass 1 writes
+        // every word of buffer 1 before anything reads it
         const pp::FillSeg segs[] = {{(uint32_t *)S.bits, 2 * k * nw, 0u}, {(uint32_t *)S.sum_cnt, 2 * cap, 0u}};
         if (e == hipSuccess) e = pp::launch_fills(segs, 2, st);
         if (e == hipSuccess) e = pp::launch_seq_seeds(S, dseeds, kk, st);
@@ -1866,10 +1903,68 @@ extern "C" int pp_propagate_s(pp_graph g, const int32_t *seeds, int32_t s, int32
             overflow |= hdone[(size_t)j] == 2;
         }
     }
-    release();
+    (void)hipStreamSynchronize(st);   // also after a failed launch: nothing queued still uses the buffers
     if (e != hipSuccess) return fail(PP_EDEVICE, "PROPAGATE-S: %s", hipGetErrorString(e));
     *D = dmax;
     if (examined) *examined = ex_total;
     if (overflow) return fail(PP_ENOTCONV, "a seed still found nodes at pass %d", cap_rounds - 1);
     return PP_OK;
+}
+
+}  // namespace
+
+extern "C" int pp_propagate_s(pp_graph g, const int32_t *seeds, int32_t s, int32_t concurrent, void *stream,
+                              int64_t *counts, int32_t cap_rounds, int32_t *D, int64_t *examined) {
+    int rc = check_seq_args(g, seeds, s, concurrent, counts, cap_rounds, D);
+    if (rc) return rc;
+    // seeds in flight: one grid row each (at most 65535)
+    const int64_t k = std::min({concurrent > 0 ? concurrent : 256, s, 65535});
+    const int64_t nw = (g->n + 63) / 64;
+    hipStream_t st = stream ? (hipStream_t)stream : g->stream;
+    pp::AllocStream as(st);
+    void *region = nullptr;
+    const int64_t bytes = seq_region_bytes(k, nw, cap_rounds);
+    if ((region = pp::dev_malloc((size_t)bytes)) == nullptr)
+        return fail(PP_ENOMEM, "PROPAGATE-S: device buffers of %lld bytes", (long long)bytes);
+    pp::SeqDev S{};
+    int32_t *dseeds = nullptr;
+    seq_carve(region, k, nw, cap_rounds, S, &dseeds);
+    rc = propagate_s_run(g, seeds, s, S, dseeds, st, counts, cap_rounds, D, examined);
+    pp::dev_release(region);   // propagate_s_run has synchronised the stream
+    return rc;
+}
+
+extern "C" int pp_propagate_s_noalloc(pp_graph g, const int32_t *seeds, int32_t s, int32_t concurrent, void *stream,
+                                      int64_t *counts, int32_t cap_rounds, int32_t *D, int64_t *examined) {
+    int rc = check_seq_args(g, seeds, s, concurrent, counts, cap_rounds, D);
+    if (rc) return rc;
+    const int64_t nw = (g->n + 63) / 64;
+    const int64_t most = PP_NOALLOC_BYTES;
+    if (seq_region_bytes(1, nw, cap_rounds) > most)
+        return fail(PP_EINVAL, "PROPAGATE-S without allocation: one seed over %lld nodes with a log of %d passes "
+                               "needs %lld bytes, more than the fixed region's %lld",
+                    (long long)g->n, cap_rounds, (long long)seq_region_bytes(1, nw, cap_rounds), (long long)most);
+    int64_t k;
+    if (concurrent > 0) {
+        k = std::min<int64_t>({concurrent, s, 65535});
+        if (seq_region_bytes(k, nw, cap_rounds) > most)
+            return fail(PP_EINVAL, "PROPAGATE-S without allocation: %lld seeds in flight need %lld bytes, more than "
+                                   "the fixed region's %lld",
+                        (long long)k, (long long)seq_region_bytes(k, nw, cap_rounds), (long long)most);
+    } else {
+        // the most seeds in flight, up to min(s, 256), that the region holds
+        int64_t lo = 1, hi = std::min<int64_t>(256, s);
+        while (lo < hi) {
+            const int64_t mid = (lo + hi + 1) / 2;
+            if (seq_region_bytes(mid, nw, cap_rounds) <= most) lo = mid; else hi = mid - 1;
+        }
+        k = lo;
+    }
+    void *region = nullptr;
+    if ((rc = pp::noalloc_region(&region)) != PP_OK) return rc;
+    hipStream_t st = stream ? (hipStream_t)stream : g->stream;
+    pp::SeqDev S{};
+    int32_t *dseeds = nullptr;
+    seq_carve(region, k, nw, cap_rounds, S, &dseeds);
+    return propagate_s_run(g, seeds, s, S, dseeds, st, counts, cap_rounds, D, examined);
 }

@@ -249,6 +249,9 @@ struct SeqDev {
     int64_t nw;           // 64-bit words per signature
 };
 hipError_t launch_seq_seeds(const SeqDev &S, const int32_t *seeds, int kk, hipStream_t st);
+// The current device's address of the fixed PP_NOALLOC_BYTES region that
+// pp_propagate_s_noalloc carves its buffers from (looked up once per device).
+int noalloc_region(void **out);
 // Nodes with more successors than this go to the wave-per-node launch.
 constexpr int SEQ_LIGHT = 32;
 // Pass r (short lists, then heavy[0..nheavy)) and its per-seed end.

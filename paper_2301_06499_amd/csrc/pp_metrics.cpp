@@ -11,11 +11,21 @@
 
 #include "pp.h"
 
+namespace pp {
+// Records the message pp_last_error returns (defined with the rest of the
+// interface) and returns `code`.
+int set_error(int code, const char *fmt, ...);
+}  // namespace pp
+
 extern "C" int pp_estimate_metrics(const int64_t *counts, int32_t len, int64_t n, int32_t s, uint32_t tau_num,
                                    uint32_t tau_den, pp_metrics *out) {
-    if (!counts || !out || len < 1 || s < 1 || n < 1 || tau_den == 0 || tau_num > tau_den) return PP_EINVAL;
+    if (!counts || !out) return pp::set_error(PP_EINVAL, "counts or out is NULL");
+    if (len < 1) return pp::set_error(PP_EINVAL, "len = %d < 1", len);
+    if (s < 1 || n < 1) return pp::set_error(PP_EINVAL, "s = %d and n = %lld must be >= 1", s, (long long)n);
+    if (tau_den == 0 || tau_num > tau_den)
+        return pp::set_error(PP_EINVAL, "tau = %u/%u outside [0, 1]", tau_num, tau_den);
     for (int32_t r = 0; r < len; ++r)
-        if (counts[r] < 0) return PP_EINVAL;
+        if (counts[r] < 0) return pp::set_error(PP_EINVAL, "counts[%d] = %lld < 0", r, (long long)counts[r]);
     // D: last round with new collisions
     int32_t D = 0;
     for (int32_t r = 0; r < len; ++r)

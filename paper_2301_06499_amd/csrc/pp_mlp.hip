@@ -171,6 +171,7 @@ struct MlpBufs {
           *D2 = nullptr, *DO = nullptr, *L = nullptr, *G = nullptr, *M = nullptr, *V = nullptr, *loss = nullptr;
     hipStream_t st = nullptr;
     ~MlpBufs() {
+        if (st) (void)hipStreamSynchronize(st);   // every kernel and copy on the buffers has finished
         for (float *p : {P, X, T, Y, H1, H2, D1, D2, DO, L, G, M, V, loss}) dev_release(p);
         if (st) (void)hipStreamDestroy(st);
     }
@@ -188,6 +189,7 @@ int setup(MlpBufs &b, const float *params, const float *x, const float *t, int64
     if (!params || !x) return set_error(PP_EINVAL, "params or x is NULL");
     if (n < 1 || n > ((int64_t)1 << 26)) return set_error(PP_EINVAL, "sample count %lld outside [1, 2^26]", (long long)n);
     if (hipStreamCreateWithFlags(&b.st, hipStreamNonBlocking) != hipSuccess) return set_error(PP_EDEVICE, "stream");
+    AllocStream as(b.st);   // the buffers are used on this call's stream
     int rc;
     if ((rc = alloc_f(&b.P, MLP_PARAMS)) || (rc = alloc_f(&b.X, n * MLP_IN)) || (rc = alloc_f(&b.Y, n * MLP_OUT)))
         return rc;

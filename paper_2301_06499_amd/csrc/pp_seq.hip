@@ -14,6 +14,8 @@
 // not the word that holds it.  Each pass counts, per seed, the nodes it found and
 // the arcs it examined (up to and including the first hit of each node); a
 // seed is done at its first pass that finds nothing.
+#include <mutex>
+
 #include "pp_internal.h"
 
 namespace pp {
@@ -213,6 +215,40 @@ __global__ void __launch_bounds__(BLOCK) k_seq_end(SeqDev S, int r) {
     __shared__ long long s_red[BLOCK / 64];
     const long long t = block_total<long long>(sum, s_red);
     if (threadIdx.x == 0 && t) atomicAdd((unsigned long long *)&S.sum_cnt[r], (unsigned long long)t);
+}
+
+// The fixed device region of pp_propagate_s_noalloc: PROPAGATE-S's buffers
+// for callers that cannot allocate.  Every device the library runs on holds
+// its own copy, at its own address, until the process ends.  Host code never
+// passes the array's name to a kernel (on the host it only stands for the
+// symbol): it takes the device address from hipGetSymbolAddress once per
+// device and passes that.
+static __device__ __align__(256) unsigned char scratch[PP_NOALLOC_BYTES];
+
+namespace {
+constexpr int MAX_DEVICES = 256;
+std::mutex &region_mu() {
+    static std::mutex *m = new std::mutex();   // lives until the process ends
+    return *m;
+}
+void *g_region[MAX_DEVICES];   // device address of `scratch` per device (NULL: not looked up yet)
+}  // namespace
+
+int noalloc_region(void **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return set_error(PP_EDEVICE, "hipGetDevice: %s", hipGetErrorString(e));
+    if (dev < 0 || dev >= MAX_DEVICES) return set_error(PP_EDEVICE, "device %d beyond the %d the library tracks", dev, MAX_DEVICES);
+    std::lock_guard<std::mutex> lk(region_mu());
+    if (!g_region[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return set_error(PP_EDEVICE, "address of the fixed region on device %d: %s", dev, hipGetErrorString(e));
+        g_region[dev] = ptr;
+    }
+    *out = g_region[dev];
+    return PP_OK;
 }
 
 static int small_grid(int64_t items) {

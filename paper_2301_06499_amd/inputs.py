@@ -365,3 +365,20 @@ def workload_batch(seed: int = 1, s: int = 64):
         graphs.append(path_graph(1000 + (k * 19000) // 20 + 1))
     seeds = [sample_seeds(g.n, s, subseed(seed, 200 + i)) for i, g in enumerate(graphs)]
     return graphs, seeds
+
+
+def union_of(graphs, seeds):
+    """A batch as one disjoint union: (n, src, dst, node_offsets, seeds) with
+    every undirected edge written as its two arcs and graph k's node ids and
+    seeds shifted by node_offsets[k] (input plumbing only)."""
+    offs, srcs, dsts, sds = [0], [], [], []
+    for g, sd in zip(graphs, seeds):
+        src, dst = g.src.astype(np.int64), g.dst.astype(np.int64)
+        if g.undirected:
+            src, dst = np.concatenate([src, dst]), np.concatenate([dst, src])
+        srcs.append(src + offs[-1])
+        dsts.append(dst + offs[-1])
+        sds.append(np.asarray(sd, dtype=np.int64) + offs[-1])
+        offs.append(offs[-1] + g.n)
+    cat = (lambda xs: np.concatenate(xs).astype(np.int32)) if graphs else (lambda xs: np.zeros(0, np.int32))
+    return offs[-1], cat(srcs), cat(dsts), offs, cat(sds)

@@ -10,6 +10,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+import sys
 from dataclasses import dataclass
 
 import numpy as np
@@ -64,7 +65,8 @@ EXPORTS = ["pp_options_default", "pp_csr_build", "pp_graph_arcs", "pp_graph_node
            "pp_run_snapshot", "pp_run_restore", "pp_run_free", "pp_graph_free", "pp_last_error",
            "pp_seeds_reset", "pp_get_kernel_times", "pp_run_set_mlp", "pp_get_round_features",
            "pp_time_round", "pp_mlp_forward", "pp_mlp_loss_grad", "pp_mlp_train", "pp_autotune", "pp_exact_counts",
-           "pp_propagate_s", "pp_progressive_sample", "pp_get_node_stats", "pp_set_allocator"]
+           "pp_propagate_s", "pp_progressive_sample", "pp_get_node_stats", "pp_set_allocator",
+           "pp_propagate_s_noalloc"]
 
 MLP_IN, MLP_HID, MLP_OUT = 8, 32, 2
 MLP_PARAMS = MLP_HID * MLP_IN + MLP_HID + MLP_HID * MLP_HID + MLP_HID + MLP_OUT * MLP_HID + MLP_OUT   # 1410
@@ -107,6 +109,7 @@ def lib():
         "pp_autotune": (ctypes.c_int, [P, P, I32, P, I32, P, P, I32, P]),
         "pp_exact_counts": (ctypes.c_int, [P, I32, P, P, I32, P]),
         "pp_propagate_s": (ctypes.c_int, [P, P, I32, I32, P, P, I32, P, P]),
+        "pp_propagate_s_noalloc": (ctypes.c_int, [P, P, I32, I32, P, P, I32, P, P]),
         "pp_progressive_sample": (ctypes.c_int, [P, P, I32, I32, ctypes.c_double, ctypes.c_double, P, P, I32, P]),
         "pp_get_node_stats": (ctypes.c_int, [P, P, P]),
         "pp_set_allocator": (ctypes.c_int, [P, P, P]),
@@ -117,6 +120,20 @@ def lib():
         f.argtypes = args
     _lib = L
     return L
+
+
+def hip_runtime() -> str | None:
+    """Path of the HIP runtime library mapped into this process (the one libpp.so
+    calls): a process that loads PyTorch first binds the library to PyTorch's
+    bundled copy, otherwise the system's.  None when none is mapped yet."""
+    try:
+        with open("/proc/self/maps") as f:
+            for line in f:
+                if "libamdhip64" in line:
+                    return line.split()[-1]
+    except OSError:
+        pass
+    return None
 
 
 def _check(rc: int):
@@ -189,6 +206,10 @@ class Graph:
             self._h = None
 
     def __del__(self):
+        # at interpreter shutdown the HIP runtime (and a profiler's hooks) may
+        # already be going away: leave the memory to the process's end then
+        if sys.is_finalizing():
+            return
         try:
             self.free()
         except Exception:
@@ -249,6 +270,10 @@ class Run:
             self._h = None
 
     def __del__(self):
+        # at interpreter shutdown the HIP runtime (and a profiler's hooks) may
+        # already be going away: leave the memory to the process's end then
+        if sys.is_finalizing():
+            return
         try:
             self.free()
         except Exception:
@@ -511,6 +536,22 @@ def pp_propagate_s(graph: Graph, seeds, concurrent: int = 0, cap_rounds: int | N
     _check(lib().pp_propagate_s(graph.handle, _np_ptr(a), int(a.shape[0]), int(concurrent), _stream_ptr(stream),
                                 _np_ptr(c), cap, ctypes.byref(D), ctypes.byref(ex)))
     return c[:D.value + 1].copy(), int(D.value), int(ex.value)
+
+
+def pp_propagate_s_noalloc(graph: Graph, seeds, concurrent: int = 0, cap_rounds: int | None = None, stream=None):
+    """PROPAGATE-S with its device buffers in the library's fixed region (no allocation);
+    returns (counts c[0..D] int64, D, arcs examined) like pp_propagate_s."""
+    a = np.ascontiguousarray(seeds, dtype=np.int32).reshape(-1)
+    cap = int(cap_rounds) if cap_rounds else graph.nodes + 1
+    c = np.zeros(cap, dtype=np.int64)
+    D = ctypes.c_int32(0)
+    ex = ctypes.c_int64(0)
+    _check(lib().pp_propagate_s_noalloc(graph.handle, _np_ptr(a), int(a.shape[0]), int(concurrent),
+                                        _stream_ptr(stream), _np_ptr(c), cap, ctypes.byref(D), ctypes.byref(ex)))
+    return c[:D.value + 1].copy(), int(D.value), int(ex.value)
+
+
+NOALLOC_BYTES = 64 << 20   # PP_NOALLOC_BYTES
 
 
 def propagate(n, src, dst, seeds, undirected=False, transpose=False, opts=None, stream=None):

@@ -5,6 +5,7 @@ library's entry points (device arcs, device seeds, device signature
 destinations) without a tensor library.
 """
 import ctypes
+import sys
 
 import numpy as np
 
@@ -62,6 +63,8 @@ class DeviceArray:
             self.ptr = ctypes.c_void_p()
 
     def __del__(self):
+        if sys.is_finalizing():
+            return
         try:
             self.free()
         except Exception:

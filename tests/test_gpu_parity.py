@@ -268,33 +268,6 @@ def test_batched_union_matches_solo_runs():
 
 # ------------------------------------------------------------ full size
 
-def test_rmat20_full_size_sampled_seeds():
-    """R-MAT scale 20, s = 256, in the benchmark's launch configuration.
-
-    Per-round totals come from the GPU only; the oracle checks 24 sampled
-    seeds one by one (per-seed counts and the seeds' signature bit columns)
-    and the totals are checked against the per-seed counts' sums.
-    """
-    g, seeds = gen.workload_rmat(20, 16, 256, 1)
-    say("rmat20 build")
-    G = pp.pp_csr_build(g.n, g.src, g.dst)
-    r = pp.pp_seeds_init(G, seeds, opts=pp.options(seed_counts=True, max_rounds=256))
-    counts, D = pp.pp_propagate_until_converged(r)
-    Dg = int(D[0])
-    sc = pp.pp_get_seed_counts(r, Dg + 1)[0]
-    sig = pp.pp_get_signatures(r)
-    assert np.array_equal(sc.sum(axis=1).astype(np.int64), counts[0])
-    pick = np.random.default_rng(0).choice(256, 24, replace=False)
-    want = oracle.propagate(g.n, g.src, g.dst, seeds[pick], False, seed_counts=True, dist=True)
-    for j, i in enumerate(pick):
-        col = want["seed_counts"][:, j]
-        L = max(len(col), Dg + 1)
-        assert np.array_equal(np.pad(sc[:, i], (0, L - Dg - 1)), np.pad(col, (0, L - len(col)))), i
-        bits = (sig[:, i >> 6] >> np.uint64(i & 63)) & np.uint64(1)
-        assert np.array_equal(bits.astype(bool), want["dist"][j] >= 0), i
-    say("rmat20 D", Dg, "counts", list(counts[0]))
-
-
 def test_rmat26_full_size_sampled_seeds():
     """R-MAT scale 26, s = 512 (eight-word rows), in the benchmark's launch configuration,
     whose pushes run at their widest (one block per 2^17 arcs, 8192 blocks).
@@ -565,21 +538,34 @@ def test_progressive_sample(case):
 
 def test_grid4096_full_size():
     """The 4096^2 grid with deletions and shortcuts, s = 128, at full size: per-round
-    counts, D and every signature against the oracle (all 128 BFS on the host),
-    with the heuristic and with a pseudo-random schedule, sparse rounds as pushes,
-    as sparse pulls, or either."""
+    counts, per-seed counts, D and every signature against the oracle (all 128 BFS
+    on the host), with the heuristic, a pseudo-random schedule and the learned
+    scheduler (a threshold model at another threshold than the heuristic's, and
+    random weights); sparse rounds as pushes, as sparse pulls, or either."""
+    from test_gpu_scheduler import rand_params, threshold_params
     g, seeds = gen.workload_grid_shortcuts(4096, 128, 1)
     say("grid4096 oracle", g.n)
-    want = oracle.propagate(g.n, g.src, g.dst, seeds, True, final_sig=True)
+    want = oracle.propagate(g.n, g.src, g.dst, seeds, True, final_sig=True, seed_counts=True)
     G = pp.pp_csr_build(g.n, g.src, g.dst, undirected=True)
-    for sched, sparse in ((pp.PP_SCHED_HEURISTIC, 0), (pp.PP_SCHED_FUZZ, 0), (pp.PP_SCHED_HEURISTIC, 1),
-                          (pp.PP_SCHED_FUZZ, 2)):
-        say("grid4096 run", sched, "sparse_pull", sparse)
+    cases = [(pp.PP_SCHED_HEURISTIC, 0, None), (pp.PP_SCHED_FUZZ, 0, None), (pp.PP_SCHED_HEURISTIC, 1, None),
+             (pp.PP_SCHED_FUZZ, 2, None), (pp.PP_SCHED_MLP, 0, threshold_params(1.0 / 12.0)),
+             (pp.PP_SCHED_MLP, 2, rand_params(17, 0.3))]
+    for sched, sparse, params in cases:
+        say("grid4096 run", sched, "sparse_pull", sparse, "model", params is not None)
         r = pp.pp_seeds_init(G, seeds, opts=pp.options(scheduler=sched, fuzz_seed=3, max_rounds=want["D"] + 4,
-                                                        sparse_pull=sparse))
+                                                        sparse_pull=sparse, seed_counts=True))
+        if params is not None:
+            pp.pp_run_set_mlp(r, params)
         counts, D = pp.pp_propagate_until_converged(r)
         assert int(D[0]) == want["D"] and list(counts[0]) == list(want["counts"])
+        assert np.array_equal(pp.pp_get_seed_counts(r, want["D"] + 1)[0], want["seed_counts"])
         assert np.array_equal(pp.pp_get_signatures(r), pad_words(want["final_sig"], r.words))
+        if params is not None:
+            modes, _ = pp.pp_get_round_log(r, want["D"] + 2)
+            ran = [int(m) for m in modes[1:want["D"] + 2]]
+            say("grid4096 learned: pulls", ran.count(pp.MODE_PULL), "of", len(ran))
+            if sparse == 0:   # the threshold model mixes both directions on this graph
+                assert pp.MODE_PULL in ran and pp.MODE_PUSH in ran
         r.free()
 
 

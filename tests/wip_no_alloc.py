@@ -1,0 +1,78 @@
+"""PROPAGATE-S without allocation (pp_propagate_s_noalloc): the same results as
+pp_propagate_s, bit for bit, from the library's fixed per-device region.
+
+Two calls in a row, the second on a smaller input (the region keeps the first
+call's contents), against pp_propagate_s and the oracle; no allocation while a
+caller's allocator is installed; sizes beyond the region rejected before any
+device work.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2301_06499_amd import inputs as gen
+from paper_2301_06499_amd import pp
+from test_gpu_allocator import CountingAllocator
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def both(G, seeds, concurrent=0, cap_rounds=None):
+    want = pp.pp_propagate_s(G, seeds, concurrent=concurrent, cap_rounds=cap_rounds)
+    got = pp.pp_propagate_s_noalloc(G, seeds, concurrent=concurrent, cap_rounds=cap_rounds)
+    return want, got
+
+
+def test_two_calls_in_a_row_second_smaller():
+    big = gen.rmat(14, 16, 77)                  # long successor lists: the group-per-node launch too
+    small = gen.grid_with_shortcuts(30, 20, gen.Fraction(1, 10), 10, 3)
+    cases = [(big, gen.sample_seeds(big.n, 300, 5), False, 0),
+             (small, gen.sample_seeds(small.n, 37, 6), True, 7)]
+    for g, seeds, und, conc in cases:
+        say("noalloc", g.name, "n", g.n, "s", len(seeds), "concurrent", conc)
+        G = pp.pp_csr_build(g.n, g.src, g.dst, undirected=und)
+        (wc, wD, wex), (gc, gD, gex) = both(G, seeds, concurrent=conc)
+        assert gD == wD and list(gc) == list(wc) and gex == wex
+        ref = oracle.propagate(g.n, g.src, g.dst, seeds, und)
+        assert gD == ref["D"] and list(gc) == list(ref["counts"])
+        G.free()
+
+
+def test_no_allocation_with_a_callers_allocator():
+    g = gen.rmat(12, 8, 3)
+    seeds = gen.sample_seeds(g.n, 90, 4)
+    a = CountingAllocator()
+    pp.pp_set_allocator(a.alloc, a.release)
+    try:
+        G = pp.pp_csr_build(g.n, g.src, g.dst)
+        want = pp.pp_propagate_s(G, seeds)
+        before = (a.allocs, a.releases)
+        got = pp.pp_propagate_s_noalloc(G, seeds)
+        assert (a.allocs, a.releases) == before, "the no-allocation entry point allocated"
+        assert got[1] == want[1] and list(got[0]) == list(want[0]) and got[2] == want[2]
+        G.free()
+    finally:
+        pp.pp_set_allocator(None, None)
+    assert not a.live
+
+
+def test_sizes_beyond_the_region_are_rejected():
+    g = gen.path_graph(1 << 20)                 # 16384 words per seed: 256 KiB per signature pair
+    G = pp.pp_csr_build(g.n, g.src, g.dst, undirected=True)
+    seeds = np.arange(0, 1 << 20, 4096, dtype=np.int32)   # 256 seeds
+    with pytest.raises(pp.PPError) as e:
+        pp.pp_propagate_s_noalloc(G, seeds, concurrent=256, cap_rounds=64)   # 64 MiB of signatures + the rest
+    assert e.value.code == pp.PP_EINVAL and "fixed region" in str(e.value)
+    with pytest.raises(pp.PPError) as e:
+        pp.pp_propagate_s_noalloc(G, seeds[:1], cap_rounds=(pp.NOALLOC_BYTES // 8) + 1)   # the pass log alone
+    assert e.value.code == pp.PP_EINVAL
+    # concurrent = 0 takes the most seeds that fit; the run itself is still exact
+    P = gen.path_graph(3000)
+    GP = pp.pp_csr_build(P.n, P.src, P.dst, undirected=True)
+    sd = np.array([0, 1500, 2999, 7], np.int32)
+    (wc, wD, wex), (gc, gD, gex) = both(GP, sd)
+    assert gD == wD == 2999 and list(gc) == list(wc) and gex == wex
