@@ -15,9 +15,9 @@ Contents
 ``metrics``         the estimators of Algorithm 1's closing steps and of the
                     Section 3 definitions, in exact integer arithmetic with one
                     final rounding per value.
-``literal_alg1``    a dense synchronous OR-propagation that takes Algorithm 1's
-                    steps in order (numpy), used to cross-check the BFS form on
-                    small graphs.
+``dense_rounds``    the ball recurrence of Section 4 on a dense boolean
+                    signature matrix, one boolean matrix product per round
+                    (numpy), used to cross-check the BFS form on small graphs.
 ``brute_force_counts``  all-pairs distances by repeated boolean matrix
                     products, for tiny graphs.
 ``node_stats``      (module ``oracle.node_stats``) per-node reach counts and
@@ -201,41 +201,38 @@ def metrics(counts, n: int, s: int, tau_num: int = 9, tau_den: int = 10) -> dict
 # cross-check implementations
 # ---------------------------------------------------------------------------
 
-def literal_alg1(n, src, dst, seeds, undirected, transpose=False, max_rounds=None):
-    """Algorithm 1 taken step by step on a dense boolean signature matrix.
+def dense_rounds(n, src, dst, seeds, undirected, transpose=False, max_rounds=None):
+    """The ball recurrence of Section 4 on a dense boolean signature matrix.
 
-    Sig[u, i] starts as [u = x_i].  Each pass builds Sig_next[u] = Sig[u] OR
-    the signatures of the heads of u's arcs, counts the set bits of
-    Sig_next XOR Sig, then commits, until a pass counts nothing.  Hops are
-    numbered from 1 with c[0] = s (the numbering reading).  Returns
-    (counts, list of signature matrices after each round, starting with
-    round 0).
+    Sig_0[u, i] = [u = x_i]; Sig_r = Sig_{r-1} OR (A Sig_{r-1} > 0) with
+    A[u, v] = 1 for every arc u -> v (u keeps its own ball, as Algorithm 1's
+    update does), and c[r] = the number of bits Sig_r has that Sig_{r-1}
+    lacks, until a round adds none.  Hops are numbered from 1 with c[0] = s.
+    Returns (counts, the signature matrices after each round, from round 0 up
+    to and including the round that added nothing).
     """
     seeds = np.asarray(seeds, dtype=np.int64)
     s = seeds.shape[0]
+    A = np.zeros((n, n), dtype=np.int64)
     src = np.asarray(src, dtype=np.int64)
     dst = np.asarray(dst, dtype=np.int64)
+    a, b = (dst, src) if transpose else (src, dst)
+    A[a, b] = 1
     if undirected:
-        src, dst = np.concatenate([src, dst]), np.concatenate([dst, src])
-    if transpose:
-        src, dst = dst, src
+        A[b, a] = 1
     sig = np.zeros((n, s), dtype=bool)
     sig[seeds, np.arange(s)] = True
     counts = [s]
     history = [sig.copy()]
-    r = 0
     cap = max_rounds if max_rounds is not None else n + 1
-    while r < cap:
-        r += 1
-        nxt = sig.copy()
-        for u, v in zip(src.tolist(), dst.tolist()):
-            nxt[u] |= sig[v]
-        count = int(np.count_nonzero(nxt ^ sig))
+    for _ in range(cap):
+        nxt = sig | ((A @ sig.astype(np.int64)) > 0)
+        added = int(np.count_nonzero(nxt & ~sig))
         sig = nxt
         history.append(sig.copy())
-        if count == 0:
+        if added == 0:
             break
-        counts.append(count)
+        counts.append(added)
     return np.asarray(counts, dtype=np.int64), history
 
 

@@ -20,7 +20,7 @@ the features of round k + 1 are
 
 Pins (``tests/test_oracle_features.py``): closed forms on paths and stars,
 and agreement with features derived from the dense signature matrices of
-``literal_alg1``.
+``dense_rounds``.
 """
 from __future__ import annotations
 

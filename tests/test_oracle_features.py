@@ -64,7 +64,7 @@ def test_against_dense_signatures(undirected, transpose):
     rng = np.random.default_rng(1)
     modes = [2] + list(rng.integers(0, 2, size=60))
     f, out = feats_from_dist(40, src, dst, seeds, undirected, transpose, modes)
-    counts, hist = oracle.literal_alg1(40, src, dst, seeds, undirected, transpose)
+    counts, hist = oracle.dense_rounds(40, src, dst, seeds, undirected, transpose)
     # predecessor sets by brute force over the input pairs
     preds = [set() for _ in range(40)]
     for a, b in zip(src.tolist(), dst.tolist()):

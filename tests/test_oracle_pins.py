@@ -168,7 +168,7 @@ def test_literal_algorithm1_matches_bfs(trial):
     s = int(rng.integers(1, 130))                      # crosses a word boundary
     seeds = rng.integers(0, n, s).astype(np.int32)
     for tr in (False, True):
-        counts, hist = oracle.literal_alg1(n, src, dst, seeds, und, transpose=tr)
+        counts, hist = oracle.dense_rounds(n, src, dst, seeds, und, transpose=tr)
         rounds = list(range(len(hist)))
         got = oracle.propagate(n, src, dst, seeds, und, transpose=tr, sig_rounds=rounds,
                                seed_counts=True, final_sig=True)
