@@ -250,9 +250,9 @@ def bench_grid(args, torch, pp):
                             "pull_k": int(tuned.pull_k),
                             "pulls": int((runs["heuristic_tuned"][3][1:rounds + 1] == pp.MODE_PULL).sum())},
         "held_out_table_ms": {"optimal": round(best_ms, 3),
-                              "heuristic": round(S.policy_cost(held, S.heuristic_policy())[0], 3),
+                              "heuristic": round(S.policy_cost(held, S.heuristic_policy(8, held.n))[0], 3),
                               "learned": round(S.policy_cost(held, S.model_policy(params, held))[0], 3),
-                              "all_pull": round(S.policy_cost(held, lambda r, f: pp.MODE_PULL)[0], 3)},
+                              "all_pull": round(S.policy_cost(held, lambda r, f: S.A_PULL)[0], 3)},
         "prep_s": round(t_prep, 1),
         "roofline": None,
     }
@@ -465,17 +465,61 @@ def time_propagation(args, torch, pp, G, seeds, opts, stream):
     elapsed_t = time.perf_counter() - t1
     ms_after = pp.pp_get_kernel_times(run_t, cap).astype(np.float64)
     assert int(D_t[0]) == int(D[0]) and list(counts_t[0]) == list(counts[0])
-    modes, arcs = pp.pp_get_round_log(run_t, cap)
-    words = run.words
+    logs = [pp.pp_get_group_log(run_t, j, cap) for j in range(run.groups)]   # (modes, arcs) per seed group
+    out = {"counts": counts[0], "D": int(D[0]), "elapsed": elapsed, "elapsed_t": elapsed_t, "per_step": per_step,
+           "pull_ms": (ms_after - ms_before) / args.steps, "logs": logs, "words": run.words,
+           "group_words": run.group_words, "groups": run.groups, "dseeds": dseeds}
     run.free()
     run_t.free()
-    return {"counts": counts[0], "D": int(D[0]), "elapsed": elapsed, "elapsed_t": elapsed_t, "per_step": per_step,
-            "pull_ms": (ms_after - ms_before) / args.steps, "modes": modes, "arcs": arcs, "words": words,
-            "dseeds": dseeds}
+    return out
 
 
-def propagation_line(args, torch, pp, g, seeds, cfg, wl, sample, stream, base_opts):
-    """Builds the graph, times the propagation, checks it: one result object.
+def step_figures(args, pp, T, m, n, s, wl, opts):
+    """Throughput, roofline of the dense pull launches and the round record of one timed run.
+
+    Each round's pull launch covers every seed group; its algorithmic bytes are
+    those of the groups that pulled in that round (group logs), per group
+      per arc gathered: 4 B column index + 8Wg B source row
+      per node: 8 B row offset (int64) + 8Wg B own row read + 8Wg B new row written."""
+    rounds = T["D"] + 1
+    Wg = T["group_words"]
+    nominal = m * (s / 64.0) * rounds
+    touched = sum(float(a[1:rounds + 1].sum()) * Wg for _, a in T["logs"])
+    pull_rounds, bytes_pull = [], 0.0
+    for r in range(1, rounds + 1):
+        pulled = [float(a[r]) for md, a in T["logs"] if md[r] == pp.MODE_PULL]
+        if pulled:
+            pull_rounds.append(r)
+            bytes_pull += sum(x * (4 + 8 * Wg) + n * (8 + 16 * Wg) for x in pulled)
+    t_pull = sum(T["pull_ms"][r] for r in pull_rounds) / 1000.0
+    achieved = bytes_pull / t_pull / 1e9 if t_pull > 0 else 0.0
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": (measured_traffic(TRAFFIC_PROFILES[wl]) if (wl in TRAFFIC_PROFILES and T["groups"] == 1 and
+                                                                  not opts.persistent and (opts.pull_k or 4) == 4)
+                        else None),
+            "kernel": f"k_batch<{Wg}> pull phase" if opts.persistent else f"k_pull<{Wg}>",
+            "timing": ("device clock between grid barriers" if opts.persistent else
+                       "HIP events around each launch, on the run's stream, over a second timed region of "
+                       "the same steps"),
+            "ms_per_step_with_events": round(T["elapsed_t"] * 1000.0 / args.steps, 4),
+            "launches_per_step": len(pull_rounds),
+            "avg_launch_ms": round(t_pull * 1000.0 / max(1, len(pull_rounds)), 4),
+            "bytes_per_launch": round(bytes_pull / max(1, len(pull_rounds)))}
+    code = {pp.MODE_PULL: "P", pp.MODE_PUSH: "S", pp.MODE_PUSH_FLAT: "F", pp.MODE_SPULL: "Q"}
+    modes = ["".join(code.get(int(md[r]), "-") for r in range(1, rounds + 1)) for md, _ in T["logs"]]
+    return {"value": nominal * args.steps / T["elapsed"], "unit": "edge-words/s",
+            "ms_per_step": round(T["elapsed"] * 1000.0 / args.steps, 4),
+            "ms_per_step_min": round(min(T["per_step"]) * 1000.0, 4),
+            "ms_per_step_median": round(float(np.median(T["per_step"])) * 1000.0, 4),
+            "touched_edge_words_per_s": touched * args.steps / T["elapsed"], "roofline": roof,
+            "run": {"words": T["words"], "seed_groups": T["groups"], "group_words": Wg, "rounds": rounds,
+                    "modes": modes[0] if len(modes) == 1 else modes}}
+
+
+def propagation_line(args, torch, pp, g, seeds, cfg, wl, sample, stream, base_opts, plain_opts=None):
+    """Builds the graph, times the propagation (and the plain form beside it when
+    plain_opts is given), checks it: one result object.
 
     sample: indices of the seeds the oracle checks one by one (and times for
     cpu_baseline); all of them for a whole-seed-set check."""
@@ -484,45 +528,26 @@ def propagation_line(args, torch, pp, g, seeds, cfg, wl, sample, stream, base_op
     log(f"[bench] {cfg['workload']}: csr_build {time.perf_counter() - t0:.1f} s, n={G.nodes} arcs={G.arcs}")
     torch.cuda.synchronize()
     calibration_copy(args, torch)
-    T = time_propagation(args, torch, pp, G, seeds, base_opts, stream)
-    counts, Dv, W = T["counts"], T["D"], T["words"]
-    rounds = Dv + 1
-    modes, arcs = T["modes"], T["arcs"]
     m, n, s = G.arcs, G.nodes, len(seeds)
-    nominal = m * (s / 64.0) * rounds
-    touched = float(arcs[1:rounds + 1].sum()) * (s / 64.0)
-    # roofline of the dense pull kernel: algorithmic bytes per launch
-    #   per arc gathered: 4 B column index + 8W B source row
-    #   per node: 8 B row offset (int64) + 8W B own row read + 8W B new row written
-    pull_rounds = [r for r in range(1, rounds + 1) if modes[r] == pp.MODE_PULL]
-    bytes_pull = sum(float(arcs[r]) * (4 + 8 * W) + n * (8 + 16 * W) for r in pull_rounds)
-    t_pull = sum(T["pull_ms"][r] for r in pull_rounds) / 1000.0
-    achieved = bytes_pull / t_pull / 1e9 if t_pull > 0 else 0.0
-    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": (measured_traffic(TRAFFIC_PROFILES[wl])
-                        if (wl in TRAFFIC_PROFILES and not base_opts.persistent and (base_opts.pull_k or 4) == 4)
-                        else None),
-            "kernel": f"k_batch<{W}> pull phase" if base_opts.persistent else f"k_pull<{W}>",
-            "timing": ("device clock between grid barriers" if base_opts.persistent else
-                       "HIP events around each launch, on the run's stream, over a second timed region of "
-                       "the same steps"),
-            "ms_per_step_with_events": round(T["elapsed_t"] * 1000.0 / args.steps, 4),
-            "launches_per_step": len(pull_rounds),
-            "avg_launch_ms": round(t_pull * 1000.0 / max(1, len(pull_rounds)), 4),
-            "bytes_per_launch": round(bytes_pull / max(1, len(pull_rounds)))}
-    res = {"value": nominal * args.steps / T["elapsed"], "unit": "edge-words/s",
-           "ms_per_step": round(T["elapsed"] * 1000.0 / args.steps, 4),
-           "ms_per_step_min": round(min(T["per_step"]) * 1000.0, 4),
-           "ms_per_step_median": round(float(np.median(T["per_step"])) * 1000.0, 4),
-           "config": dict(cfg, nodes=n, arcs=m, words=W, rounds=rounds, diameter_lb=Dv,
-                          scheduler=args.scheduler, engine="persistent" if base_opts.persistent else "rounds",
-                          pull_k=int(base_opts.pull_k) or 4, push_div=int(base_opts.push_div) or 8,
-                          sparse_pull=int(base_opts.sparse_pull),
-                          modes="".join({pp.MODE_PULL: "P", pp.MODE_PUSH: "S", pp.MODE_SPULL: "Q"}.get(int(modes[r]), "?")
-                                        for r in range(1, rounds + 1))),
-           "touched_edge_words_per_s": touched * args.steps / T["elapsed"],
-           "roofline": roof}
+    T = time_propagation(args, torch, pp, G, seeds, base_opts, stream)
+    counts, Dv = T["counts"], T["D"]
+    res = step_figures(args, pp, T, m, n, s, wl, base_opts)
+    res["config"] = dict(cfg, nodes=n, arcs=m, words=T["words"], rounds=Dv + 1, diameter_lb=Dv,
+                         scheduler=args.scheduler, engine="persistent" if base_opts.persistent else "rounds",
+                         pull_k=int(base_opts.pull_k) or 4, push_div=int(base_opts.push_div) or 8,
+                         sparse_pull=int(base_opts.sparse_pull), seed_groups=T["groups"],
+                         group_words=T["group_words"],
+                         seed_order="by reach" if (base_opts.seed_order or base_opts.seed_groups == pp.PP_GROUPS_BY_REACH)
+                         else "as given")
+    log(f"[bench] {cfg['workload']}: {res['ms_per_step']} ms per step, {T['groups']} seed group(s)")
+    if plain_opts is not None:
+        P = time_propagation(args, torch, pp, G, seeds, plain_opts, stream)
+        if P["D"] != Dv or list(P["counts"]) != list(counts):
+            raise SystemExit("the plain form's counts differ from the seed groups'")
+        res["plain"] = step_figures(args, pp, P, m, n, s, wl, plain_opts)
+        res["plain"]["note"] = "the same graph and seeds as one group of s seeds, same scheduler"
+        res["speedup_vs_plain"] = round(P["elapsed"] / T["elapsed"], 4)
+        log(f"[bench] {cfg['workload']}: plain {res['plain']['ms_per_step']} ms per step")
     if args.no_check and args.no_cpu_baseline:
         G.free()
         return res
@@ -538,6 +563,7 @@ def propagation_line(args, torch, pp, g, seeds, cfg, wl, sample, stream, base_op
     chk.free()
     G.free()
     log(f"[bench] {cfg['workload']}: oracle on {len(sample)} of {s} seeds")
+    nominal = m * (s / 64.0) * (Dv + 1)
     want, base = oracle_sample(g, seeds, sample, nominal, single_thread=g.n <= (1 << 22))
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = base
@@ -559,6 +585,10 @@ def main():
                          "secondary object in the same line), rmat20, er, grid:SIDE, rmat:SCALE:SEEDS, "
                          "grid4096 (learned scheduler), batch64 (the 64-graph batch)")
     ap.add_argument("--no-secondary", action="store_true", help="rmat26: skip the R-MAT 20 object")
+    ap.add_argument("--groups", default="reach",
+                    help="seed groups of the timed run: 'reach' (the default: groups sized so that the seeds "
+                         "with a predecessor fill whole groups first), 'plain' (one group), or a number; "
+                         "with more than one group the plain form is timed beside it")
     ap.add_argument("--scheduler", default="heuristic", choices=["heuristic", "pull", "push"])
     ap.add_argument("--grid-side", type=int, default=4096, help="side of the grid4096 workload")
     ap.add_argument("--persistent", action="store_true",
@@ -619,8 +649,15 @@ def main():
     if args.method == "progressive":
         return bench_progressive(args, torch, pp, g, seeds, cfg)
     stream = torch.cuda.Stream()                       # default priority
-    base = pp.options(scheduler=sched, max_rounds=4096, persistent=args.persistent, node_stats=args.node_stats,
-                      sparse_pull=args.sparse_pull, push_div=args.push_div)
+    def make_opts(groups):
+        sg = {"reach": pp.PP_GROUPS_BY_REACH, "plain": 0}.get(groups, None)
+        sg = int(groups) if sg is None else sg
+        return pp.options(scheduler=sched, max_rounds=4096, persistent=args.persistent, node_stats=args.node_stats,
+                          sparse_pull=args.sparse_pull, push_div=args.push_div, seed_groups=sg)
+
+    grouped = args.groups != "plain" and not args.persistent and not args.node_stats
+    base = make_opts(args.groups if grouped else "plain")
+    plain = make_opts("plain") if grouped else None
     tuned = None
     if args.tune:
         from paper_2301_06499_amd import autotune
@@ -633,22 +670,22 @@ def main():
     s = len(seeds)
     sample = (np.arange(s) if g.n <= (1 << 22) else
               np.unique(np.linspace(0, s - 1, min(s, args.check_seeds)).astype(np.int64)))
-    head = propagation_line(args, torch, pp, g, seeds, cfg, args.workload, sample, stream, base)
+    head = propagation_line(args, torch, pp, g, seeds, cfg, args.workload, sample, stream, base, plain)
     head["config"]["tuned"] = tuned
     out = {"metric": METRIC, "value": head["value"], "unit": "edge-words/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": head["ms_per_step"], "ms_per_step_min": head["ms_per_step_min"],
            "ms_per_step_median": head["ms_per_step_median"], "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "u64", "data": "synthetic", "config": head["config"],
-           "touched_edge_words_per_s": head["touched_edge_words_per_s"], "roofline": head["roofline"]}
-    for k in ("cpu_baseline", "check"):
+           "touched_edge_words_per_s": head["touched_edge_words_per_s"], "roofline": head["roofline"],
+           "run": head["run"]}
+    for k in ("plain", "speedup_vs_plain", "cpu_baseline", "check"):
         if k in head:
             out[k] = head[k]
     del g
     if args.workload == "rmat26" and not args.no_secondary:
         g2, seeds2, cfg2 = workload("rmat20")
-        base2 = pp.options(scheduler=sched, max_rounds=4096, sparse_pull=args.sparse_pull, push_div=args.push_div)
         out["rmat20"] = propagation_line(args, torch, pp, g2, seeds2, cfg2, "rmat20", np.arange(len(seeds2)),
-                                         stream, base2)
+                                         stream, base, plain)
         out["rmat20"]["note"] = "secondary: R-MAT scale 20, s = 256, every seed checked against the oracle"
     if args.node_stats:
         out["node_stats_note"] = "per-node sums kept in every timed round (their check runs in the GPU tests)"

@@ -79,7 +79,8 @@ enum {
     PP_SCHED_PULL = 1,       /* every round a dense pull over all arcs */
     PP_SCHED_PUSH = 2,       /* every round a push from the changed nodes */
     PP_SCHED_FUZZ = 3,       /* pseudo-random choice per round (testing: outputs must not change) */
-    PP_SCHED_MLP = 4         /* learned cost model, heuristic fallback */
+    PP_SCHED_MLP = 4,        /* learned cost model, heuristic fallback */
+    PP_SCHED_PLAN = 5        /* a given action per round (pp_run_set_plan), heuristic elsewhere */
 };
 
 /* Options of a run.  Zero-initialise and set what you need; pp_options_default
@@ -110,7 +111,28 @@ typedef struct {
                                    2 either, by a pseudo-random bit per round from
                                    fuzz_seed (testing).  Same bits every way.  The
                                    per-round engine only */
+    int32_t seed_groups;        /* seed groups of the run (the per-round engine): the seeds
+                                   of each graph are split, in order, into groups of
+                                   sg = ceil(s / seed_groups) (the last may hold fewer);
+                                   each group is propagated with rows of its own width
+                                   (the smallest power of two >= ceil(sg / 64) words, at
+                                   most 8), its own direction per round, counts and
+                                   convergence, all groups in the same launches.  Outputs
+                                   are the same as one group's, in the caller's bit order.
+                                   0: ceil(s / 512) groups (one when s <= 512);
+                                   PP_GROUPS_BY_REACH: seed_order 1 and groups sized so
+                                   that the initialisation's seeds with a predecessor fill
+                                   whole groups first (a group of seeds with none
+                                   converges after one round) */
+    int32_t seed_order;         /* order of the seeds across the groups: 0 as given;
+                                   1 (PP_ORDER_BY_REACH) the seeds whose node has a
+                                   predecessor first -- a seed without one reaches no
+                                   other node -- each part in the caller's order.
+                                   Applied at every initialisation and reset */
 } pp_options;
+
+#define PP_GROUPS_BY_REACH (-1)
+#define PP_ORDER_BY_REACH 1
 
 /* Metrics estimated from c[0..D] (paper Section 3 and Algorithm 1's closing
  * steps).  T = c[0] + ... + c[D] counts (node, seed) pairs within reach,
@@ -195,7 +217,8 @@ int32_t pp_graph_count(pp_graph g);
  *   seeds       host array of num_graphs * s node ids: seeds[g*s + i] is
  *               seed i of graph g and must lie in graph g's node range.
  *               Repeated seeds are allowed (each owns its own bit).
- *   s           1 <= s <= 512 seeds per graph (W = ceil(s/64) <= 8 words).
+ *   s           1 <= s <= 4096 seeds per graph; more than 512 need at least
+ *               ceil(s / 512) seed groups (opt.seed_groups), which is the default.
  *   opt         NULL for defaults.
  *   stream      hipStream_t for all of the run's device work (NULL: the run
  *               creates its own non-blocking stream).
@@ -258,16 +281,25 @@ int pp_get_signatures(pp_run r, uint64_t *dst, int32_t dst_on_device);
  * dst[(g*cap_rounds + r)*s + i] = c_{g,i}[r]. */
 int pp_get_seed_counts(pp_run r, uint32_t *dst, int32_t cap_rounds);
 
-/* Rounds run so far (the next round's index) and the number of words W. */
+/* Rounds run so far (the next round's index) and the number of words W of
+ * the signature rows the run reports (pp_get_signatures; W = the smallest
+ * power of two >= ceil(s / 64)). */
 int32_t pp_run_round(pp_run r);
 int32_t pp_run_words(pp_run r);
+/* Seed groups of the run and the row width of one group in words. */
+int32_t pp_run_groups(pp_run r);
+int32_t pp_run_group_words(pp_run r);
 
 /* Per-round record of the last pp_propagate_* call: for each round r <= the
- * current round, mode[r] (PP_MODE_PULL, PP_MODE_PUSH or PP_MODE_SPARSE_PULL;
- * 2 for round 0, the initialisation) and arcs[r] (arcs the round touched: all
+ * current round, mode[r] (PP_MODE_PULL, PP_MODE_PUSH, PP_MODE_PUSH_FLAT or
+ * PP_MODE_SPARSE_PULL; 2 for round 0, the initialisation) and arcs[r] (arcs the round touched: all
  * arcs for a pull, the changed nodes' predecessor arcs for a sparse round).
  * Host arrays of cap entries; either may be NULL. */
 int pp_get_round_log(pp_run r, int32_t *mode, int64_t *arcs, int32_t cap);
+/* The same record for one seed group of a run (pp_get_round_log: group 0's
+ * modes, arcs summed over the groups).  PP_EINVAL for a group outside
+ * [0, pp_run_groups). */
+int pp_get_group_log(pp_run r, int32_t group, int32_t *mode, int64_t *arcs, int32_t cap);
 
 /* With opt.time_kernels: pull_ms[r] = total duration in ms of round r's
  * pull launches (HIP events on the run's stream), summed over every
@@ -301,13 +333,13 @@ int pp_run_snapshot(pp_run r, pp_run *copy);
 int pp_run_restore(pp_run r, pp_run from);
 
 /*
- * Learned direction scheduler.  Every round of PROPAGATE-P (Algorithm 1)
- * computes the same Sig_r whether it pulls (each node ORs its successors'
- * signatures) or pushes (each changed node ORs its delta into its
- * predecessors); the direction only changes the cost.  PP_SCHED_MLP picks,
- * before each round, the direction with the smaller predicted cost of a
- * cost model evaluated on the device from eight features of the last round
- * (all normalised to about [0, 1]):
+ * Learned scheduler.  Every round of PROPAGATE-P (Algorithm 1) computes the
+ * same Sig_r whether it pulls (each node ORs its successors' signatures) or
+ * pushes (each changed node ORs its delta into its predecessors), and however
+ * a push spreads the frontier's arcs over the lanes; these choices only
+ * change the cost.  PP_SCHED_MLP picks, before each round, the action with
+ * the smallest predicted cost of a cost model evaluated on the device from
+ * eight features of the last round (all normalised to about [0, 1]):
  *   f0 nodes changed / n            f1 their predecessor arcs / stored arcs
  *   f2 pairs reached past the seeds / (n s)
  *   f3 new pairs of the round / (n s)
@@ -315,14 +347,26 @@ int pp_run_restore(pp_run r, pp_run from);
  *   f5 log2(index of the next round + 1) / 16
  *   f6 log2(f1's arcs / max(f0's nodes, 1) + 1) / 16
  *   f7 1 if the last round pulled, else 0
- * The model is a fully connected network 8 -> 32 -> 32 -> 2, ReLU on both
- * hidden layers, outputs y0 (pull) and y1 (push) in log-milliseconds; pull
- * is taken when y0 <= y1.  Weights are PP_MLP_PARAMS floats in the order
- * W1[32][8], b1[32], W2[32][32], b2[32], W3[2][32], b3[2] (row = output
- * unit).  A non-finite output, or weights never set, falls back to the
- * heuristic.  The scheduler never changes a result bit, only the work.
+ * The model is a fully connected network 8 -> 32 -> 32 -> 4, ReLU on both
+ * hidden layers, outputs in log-milliseconds of the round's effective cost
+ * under each action:
+ *   y0 dense pull (every node gathers its successors' rows)
+ *   y1 push over direct slots: a few lanes per frontier entry walk its
+ *      predecessor list (lean for small frontiers)
+ *   y2 push over flattened arc ranges: the frontier's arcs laid out as one
+ *      range per wave, each predecessor word read before its atomic (for
+ *      large frontiers)
+ *   y3 sparse pull (the predecessors that can gain a bit gather their lists)
+ * and takes the allowed action with the least output (the first on a tie):
+ * the pushes unless the run's sparse_pull is 1, the sparse pull when it is 1
+ * or 2 (the persistent engine's pushes always use direct slots).  Weights are
+ * PP_MLP_PARAMS floats in the order W1[32][8], b1[32], W2[32][32], b2[32],
+ * W3[4][32], b3[4] (row = output unit).  A non-finite output of an allowed
+ * action, or weights never set, falls back to the heuristic (direction by
+ * frontier arcs, tiling by frontier size: flattened from 16384 entries).
+ * The scheduler never changes a result bit, only the work.
  */
-#define PP_MLP_PARAMS 1410
+#define PP_MLP_PARAMS 1476
 
 /* Sets the run's cost-model weights (host array of PP_MLP_PARAMS floats,
  * copied) or clears them (NULL: the heuristic decides).  Used only when the
@@ -332,21 +376,35 @@ int pp_run_restore(pp_run r, pp_run from);
  * across pp_seeds_reset.  Synchronises. */
 int pp_run_set_mlp(pp_run r, const float *params);
 
+/* The actions of PP_SCHED_PLAN: plan[r] (host, len entries) for round r, an
+ * action index of the cost model (0 dense pull, 1 push over direct slots, 2
+ * push over flattened ranges, 3 sparse pull; an action the run does not
+ * allow, or -1, leaves the round to the heuristic, as do rounds >= len).
+ * Kept across resets.  Used to measure fixed schedules.  Synchronises. */
+int pp_run_set_plan(pp_run r, const int32_t *plan, int32_t len);
+
+/* Device-clock duration of each round of the run's last propagation (the
+ * per-round engine; seed group 0): ms[r] (host, cap entries) from the start
+ * of round r's first launch to the end of its closing launch, 0 for rounds
+ * not run.  Synchronises. */
+int pp_get_round_times(pp_run r, float *ms, int32_t cap);
+
 /* Scheduler features of every round: feat[r][8] (host, cap rows) holds the
  * features computed at the end of round r-1 for round r; row 0 is zero. */
 int pp_get_round_features(pp_run r, float *feat, int32_t cap);
 
 /* Training samples for the cost model.  Runs the next round of a run on the
- * per-round engine in the given direction (PP_MODE_PULL, PP_MODE_PUSH or
- * PP_MODE_SPARSE_PULL; PP_MODE_PUSH stands for the run's sparse direction,
- * i.e. a sparse pull when the run was created with sparse_pull = 1)
+ * per-round engine with the given action (PP_MODE_PULL, PP_MODE_PUSH (direct
+ * slots), PP_MODE_PUSH_FLAT (flattened arc ranges) or PP_MODE_SPARSE_PULL;
+ * PP_MODE_PUSH stands for the run's sparse direction, i.e. a sparse pull
+ * when the run was created with sparse_pull = 1)
  * instead of the scheduler's, and stores its duration in milliseconds in
  * *ms (HIP events around the whole round, every launch of the round
  * included).  features (host [8] or NULL) receives the round's features.
  * With pp_run_snapshot / pp_run_restore a caller times a round both ways,
  * and after either kind of previous round.  PP_ESTATE if the run has
  * converged or is persistent; PP_ENOTCONV if its round log is full. */
-enum { PP_MODE_PULL = 0, PP_MODE_PUSH = 1, PP_MODE_SPARSE_PULL = 3 };
+enum { PP_MODE_PULL = 0, PP_MODE_PUSH = 1, PP_MODE_SPARSE_PULL = 3, PP_MODE_PUSH_FLAT = 4 };
 int pp_time_round(pp_run r, int32_t mode, float *features, float *ms);
 
 /* The cost model on the device, for training and its tests.  All arrays

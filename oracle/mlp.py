@@ -4,9 +4,10 @@ TEST INFRASTRUCTURE ONLY (see the package header): it checks the device
 model's forward pass, gradient and Adam steps.
 
 The model is a fully connected network with eight inputs, two hidden layers
-of 32 ReLU units and two linear outputs (predicted log-times of a pull round
-and of a push round).  Parameters come as one flat vector in the order
-W1[32][8], b1[32], W2[32][32], b2[32], W3[2][32], b3[2] (each weight matrix
+of 32 ReLU units and four linear outputs (predicted log-costs of a round run
+as a dense pull, a push over direct slots, a push over flattened arc ranges
+and a sparse pull).  Parameters come as one flat vector in the order
+W1[32][8], b1[32], W2[32][32], b2[32], W3[4][32], b3[4] (each weight matrix
 stored row = output unit).  The loss over n samples is the mean squared
 error 1/(2n) sum_n sum_k (y_nk - t_nk)^2; gradients follow the chain rule
 layer by layer; Adam is the update of Kingma and Ba (ICLR 2015, Algorithm 1)
@@ -21,10 +22,10 @@ from __future__ import annotations
 
 import numpy as np
 
-IN, HID, OUT = 8, 32, 2
+IN, HID, OUT = 8, 32, 4
 SHAPES = [("W1", (HID, IN)), ("b1", (HID,)), ("W2", (HID, HID)), ("b2", (HID,)), ("W3", (OUT, HID)),
           ("b3", (OUT,))]
-PARAMS = sum(int(np.prod(s)) for _, s in SHAPES)   # 1410
+PARAMS = sum(int(np.prod(s)) for _, s in SHAPES)   # 1476
 
 
 def unpack(p):
@@ -45,7 +46,7 @@ def pack(parts) -> np.ndarray:
 
 
 def forward(p, x, keep=False):
-    """Outputs y [n][2] for inputs x [n][8]; with keep, also the hidden activations."""
+    """Outputs y [n][4] for inputs x [n][8]; with keep, also the hidden activations."""
     w = unpack(p)
     x = np.asarray(x, dtype=np.float64)
     a1 = x @ w["W1"].T + w["b1"]
@@ -100,7 +101,8 @@ def adam(p, x, t, steps: int, lr: float, beta1=0.9, beta2=0.999, eps=1e-8):
     return p, np.array(losses)
 
 
-def decide(p, f) -> int:
-    """Direction the model picks for features f: 0 (pull) when y0 <= y1, else 1."""
+def decide(p, f, allowed=(0, 1, 2)) -> int:
+    """The action the model picks for features f: the allowed output with the
+    least value, the first of equal ones."""
     y = forward(p, np.asarray(f, dtype=np.float64).reshape(1, IN))[0]
-    return 0 if y[0] <= y[1] else 1
+    return min(allowed, key=lambda a: (y[a], a))

@@ -131,13 +131,19 @@ struct pp_graph_s {
     std::map<int, TileSet> tiles;   // by pull arc budget
     std::vector<int32_t> perm;      // stored id of each input node (empty: identity)
     int32_t *perm_d = nullptr;      // the same on the device
+    std::vector<uint64_t> pred_bits;  // bit u (stored id): node u has a predecessor
     int32_t *seq_heavy = nullptr;   // PROPAGATE-S: nodes with more than SEQ_LIGHT successors
     int64_t nseq_heavy = 0;
 };
 
 struct pp_run_s {
     pp_graph g = nullptr;
-    int32_t s = 0, W = 0, cap = 0, G = 1;
+    int32_t s = 0, W = 0, cap = 0, G = 1;   // s: seeds per graph; W: row words of one seed group
+    int32_t k = 1, sg = 0, Wout = 0;        // seed groups, seeds per group, row words reported
+    bool grouped = false;                   // groups or a seed order: internal seed list and positions
+    int32_t *iseeds = nullptr;              // [G*s] stored ids in internal order
+    int32_t *dpos = nullptr;                // [G*s] internal position of each caller seed
+    int32_t *dcur = nullptr;                // [k] current signature buffer of each group
     pp_options opt{};
     hipStream_t stream = nullptr;
     bool own_stream = false;
@@ -168,8 +174,8 @@ struct pp_run_s {
     int32_t *h_seeds = nullptr;             // host seed list, read in place by the initialisation
     int32_t *h_seeds_dev = nullptr;         // the same, as the device addresses it
     hipEvent_t seeds_sent = nullptr;        // its copy has been read
-    std::vector<int64_t> counts_host;       // [staged][G]
-    std::vector<int32_t> D_host;            // [G]
+    std::vector<int64_t> counts_host;       // [staged][k][G] as the device logs them
+    std::vector<int32_t> D_host;            // [k][G]
     int staged = 0;
     // The push accumulator is all zero between rounds (every round clears
     // what it set), so a reset leaves it alone -- unless a launch failed
@@ -617,6 +623,10 @@ extern "C" int pp_csr_build(int64_t n, int64_t m, const int32_t *src, const int3
         }
         g->nseq_heavy = (int64_t)hv.size();
     }
+    // which nodes have a predecessor (a seed there can pass its bit on)
+    g->pred_bits.assign((size_t)((n + 63) / 64), 0ull);
+    for (int64_t u = 0; u < n; ++u)
+        if (trp[(size_t)u + 1] > trp[(size_t)u]) g->pred_bits[(size_t)(u >> 6)] |= 1ull << (u & 63);
     g->rp_host = std::move(rp);
     g->perm = std::move(perm);
     *out = g;
@@ -667,6 +677,7 @@ void free_run_dev(RunDev &d) {
     dev_free(d.tickets);
     dev_free(d.post_part);
     dev_free(d.mlp);
+    dev_free(d.plan);
     dev_free(d.node_acc);
 }
 
@@ -684,6 +695,9 @@ void free_run(pp_run r) {
     free_run_dev(r->dev);
     dev_free(r->dseeds);
     dev_free(r->dclusters);
+    dev_free(r->iseeds);
+    dev_free(r->dpos);
+    dev_free(r->dcur);
     for (hipEvent_t e : r->ev) (void)hipEventDestroy(e);
     for (hipEvent_t e : r->tev)
         if (e) (void)hipEventDestroy(e);
@@ -697,61 +711,75 @@ void free_run(pp_run r) {
 // region of its own for each graph of a batch
 int64_t chunk_capacity(pp_graph g) { return g->n + g->m / pp::PUSH_CHUNK_MIN + 2 * (int64_t)g->G + 2; }
 
-// Allocates every device buffer of a run with the sizes fixed by (g, s, cap).
-int alloc_run_dev(pp_graph g, RunDev &d, int s, int W, int cap, bool seed_counts, int pull_grid) {
+// Allocates every device buffer of a run with the sizes fixed by (g, seeds,
+// groups, cap): one copy of each per-group array for every seed group, the
+// groups one after another (group_view in the kernels), counts and per-seed
+// counts as rows of [groups][graphs] per round.
+int alloc_run_dev(pp_graph g, RunDev &d, int s_all, int k, int sg, int W, int cap, bool seed_counts, int pull_grid) {
     const int64_t n = g->n;
     const int G = g->G;
+    const int64_t KG = (int64_t)k * G;
     int rc;
-    d.s = s;
+    d.s = sg;
+    d.sg = sg;
+    d.s_last = s_all - (k - 1) * sg;
+    d.s_all = s_all;
+    d.ngroups = k;
     d.W = W;
     d.cap = cap;
     d.G = G;
-    d.cstride = G;
-    d.sstride = G * s;
+    d.cstride = (int32_t)KG;
+    d.sstride = (int32_t)(KG * sg);
+    d.nn = n;
+    d.pgrid = pull_grid;
     // the double buffers come in pairs, each pair one allocation (the kernels
     // pick a member by pointer arithmetic)
     const int64_t cc = chunk_capacity(g);
-    if ((rc = dev_alloc(&d.sig[0], 2 * n * W)) || (rc = dev_alloc(&d.acc, n * W)) || (rc = dev_alloc(&d.stamp, n)) ||
-        (rc = dev_alloc(&d.f_ids[0], 2 * n)) || (rc = dev_alloc(&d.f_delta[0], 2 * n * W)) ||
-        (rc = dev_alloc(&d.chunks[0], 2 * cc)) ||
-        (rc = dev_alloc(&d.blk_cnt, pull_grid)) || (rc = dev_alloc(&d.blk_nodes, pull_grid)) ||
-        (rc = dev_alloc(&d.blk_arcs, pull_grid)) || (rc = dev_alloc(&d.blk_pulled, pull_grid)) ||
-        (rc = dev_alloc(&d.counts, (int64_t)cap * G)) || (rc = dev_alloc(&d.D, G)) || (rc = dev_alloc(&d.gconv, G)) ||
-        (rc = dev_alloc(&d.mode_log, (int64_t)cap * G)) || (rc = dev_alloc(&d.arcs_log, (int64_t)cap * G)) ||
-        (rc = dev_alloc(&d.ctrl, G)) || (rc = dev_alloc(&d.bar, G)) ||
-        (rc = dev_alloc(&d.phase_log, (int64_t)cap * 3 * G)) ||
-        (rc = dev_alloc(&d.feat_log, (int64_t)cap * pp::MLP_IN * G)) || (rc = dev_alloc(&d.mlp, pp::MLP_PARAMS)) ||
-        (rc = dev_alloc(&d.tickets, pp::TICKET_INTS)) || (rc = dev_alloc(&d.post_part, 3 * pp::POST_MAX)))
+    d.cc = cc;
+    if ((rc = dev_alloc(&d.sig[0], 2 * k * n * W)) || (rc = dev_alloc(&d.acc, k * n * W)) ||
+        (rc = dev_alloc(&d.stamp, k * n)) || (rc = dev_alloc(&d.f_ids[0], 2 * k * n)) ||
+        (rc = dev_alloc(&d.f_delta[0], 2 * k * n * W)) || (rc = dev_alloc(&d.chunks[0], 2 * k * cc)) ||
+        (rc = dev_alloc(&d.blk_cnt, (int64_t)k * pull_grid)) || (rc = dev_alloc(&d.blk_nodes, (int64_t)k * pull_grid)) ||
+        (rc = dev_alloc(&d.blk_arcs, (int64_t)k * pull_grid)) || (rc = dev_alloc(&d.blk_pulled, (int64_t)k * pull_grid)) ||
+        (rc = dev_alloc(&d.counts, (int64_t)cap * KG)) || (rc = dev_alloc(&d.D, KG)) || (rc = dev_alloc(&d.gconv, KG)) ||
+        (rc = dev_alloc(&d.mode_log, (int64_t)cap * KG)) || (rc = dev_alloc(&d.arcs_log, (int64_t)cap * KG)) ||
+        (rc = dev_alloc(&d.ctrl, KG)) || (rc = dev_alloc(&d.bar, KG)) ||
+        (rc = dev_alloc(&d.phase_log, (int64_t)cap * 3 * KG)) ||
+        (rc = dev_alloc(&d.feat_log, (int64_t)cap * pp::MLP_IN * KG)) || (rc = dev_alloc(&d.mlp, pp::MLP_PARAMS)) ||
+        (rc = dev_alloc(&d.plan, cap)) ||
+        (rc = dev_alloc(&d.tickets, (int64_t)k * pp::TICKET_INTS)) ||
+        (rc = dev_alloc(&d.post_part, (int64_t)k * 3 * pp::POST_MAX)))
         return rc;
     d.sig[1] = d.sig[0] + n * W;
     d.f_ids[1] = d.f_ids[0] + n;
     d.f_delta[1] = d.f_delta[0] + n * W;
     d.chunks[1] = d.chunks[0] + cc;
-    if (seed_counts && (rc = dev_alloc(&d.seed_counts, (int64_t)cap * G * s))) return rc;
+    if (seed_counts && (rc = dev_alloc(&d.seed_counts, (int64_t)cap * KG * sg))) return rc;
     if (!seed_counts) d.seed_counts = nullptr;
     return PP_OK;
 }
 
 hipError_t clear_run_dev(pp_graph g, RunDev &d, hipStream_t st, bool with_acc) {
     const int64_t n = g->n;
-    const int64_t G = d.G;
+    const int64_t k = d.ngroups;
+    const int64_t KG = k * d.G;
     const int64_t cap = d.cap;
     auto seg = [](void *p, int64_t bytes, uint32_t v) { return pp::FillSeg{(uint32_t *)p, bytes / 4, v}; };
     const pp::FillSeg segs[] = {
-        seg(d.sig[0], 2 * 8 * n * d.W, 0u),      // both signature buffers (one allocation)
-        seg(d.acc, with_acc ? 8 * n * d.W : 0, 0u),
-        seg(d.stamp, 4 * n, 0xFFFFFFFFu),        // -1: never queued
-        seg(d.counts, 8 * cap * G, 0u),
-        seg(d.seed_counts, d.seed_counts ? 4 * cap * G * d.s : 0, 0u),
-        seg(d.D, 4 * G, 0u),
-        seg(d.gconv, 4 * G, 0u),
-        seg(d.mode_log, 4 * cap * G, 0xFFFFFFFFu),
-        seg(d.arcs_log, 8 * cap * G, 0u),
-        seg(d.bar, (int64_t)sizeof(pp::GridBar) * G, 0u),
-        seg(d.phase_log, 8 * cap * 3 * G, 0u),
-        seg(d.feat_log, 4 * cap * pp::MLP_IN * G, 0u),
-        seg(d.ctrl, (int64_t)sizeof(Ctrl) * G, 0u),
-        seg(d.tickets, 4 * pp::TICKET_INTS, 0u),
+        seg(d.sig[0], 2 * 8 * k * n * d.W, 0u),  // both signature buffers of every group (one allocation)
+        seg(d.acc, with_acc ? 8 * k * n * d.W : 0, 0u),
+        seg(d.stamp, 4 * k * n, 0xFFFFFFFFu),    // -1: never queued
+        seg(d.counts, 8 * cap * KG, 0u),
+        seg(d.seed_counts, d.seed_counts ? 4 * cap * KG * d.sg : 0, 0u),
+        seg(d.D, 4 * KG, 0u),
+        seg(d.gconv, 4 * KG, 0u),
+        seg(d.mode_log, 4 * cap * KG, 0xFFFFFFFFu),
+        seg(d.arcs_log, 8 * cap * KG, 0u),
+        seg(d.bar, (int64_t)sizeof(pp::GridBar) * KG, 0u),
+        seg(d.phase_log, 8 * cap * 3 * KG, 0u),
+        seg(d.feat_log, 4 * cap * pp::MLP_IN * KG, 0u),
+        seg(d.ctrl, (int64_t)sizeof(Ctrl) * KG, 0u),
+        seg(d.tickets, 4 * pp::TICKET_INTS * k, 0u),
         seg(d.node_acc, d.node_acc ? 8 * n : 0, 0u),
     };
     return pp::launch_fills(segs, (int)(sizeof(segs) / sizeof(segs[0])), st);
@@ -765,9 +793,10 @@ TileSet *run_tiles(pp_run r) { return &r->g->tiles[pull_edges(r->W, r->dev.pull_
 // Pinned host staging of a run: G control blocks, G values of D,
 // STAGE_ROWS rows of G counts and a seed list of G s ids.
 int alloc_staging(pp_run r) {
-    const size_t G = (size_t)r->G;
-    const size_t bytes = sizeof(Ctrl) * G + 8 * ((G + 1) / 2) + sizeof(int64_t) * STAGE_ROWS * G +
-                         sizeof(int32_t) * G * (size_t)r->s;
+    const size_t KG = (size_t)r->k * (size_t)r->G;   // control blocks, D values and counts per row
+    const size_t G = KG;
+    const size_t bytes = sizeof(Ctrl) * KG + 8 * ((KG + 1) / 2) + sizeof(int64_t) * STAGE_ROWS * KG +
+                         sizeof(int32_t) * (size_t)r->G * (size_t)r->s;
     // coherent and mapped: the staging kernel stores into it directly
     if (hipHostMalloc(&r->pinned, bytes, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
         r->pinned = nullptr;
@@ -777,7 +806,7 @@ int alloc_staging(pp_run r) {
     r->h_ctrl = (Ctrl *)r->pinned;
     r->h_D = (int32_t *)(r->h_ctrl + G);
     r->h_rows = (int64_t *)((char *)r->h_D + 8 * ((G + 1) / 2));
-    r->h_seeds = (int32_t *)(r->h_rows + STAGE_ROWS * G);
+    r->h_seeds = (int32_t *)(r->h_rows + STAGE_ROWS * KG);
     void *dev = nullptr;
     if (hipHostGetDevicePointer(&dev, r->pinned, 0) != hipSuccess || !dev) {
         (void)hipGetLastError();
@@ -787,7 +816,7 @@ int alloc_staging(pp_run r) {
     r->h_D_dev = (int32_t *)((char *)dev + ((char *)r->h_D - (char *)r->pinned));
     r->h_rows_dev = (int64_t *)((char *)dev + ((char *)r->h_rows - (char *)r->pinned));
     r->h_seeds_dev = (int32_t *)((char *)dev + ((char *)r->h_seeds - (char *)r->pinned));
-    r->D_host.assign(G, 0);
+    r->D_host.assign(KG, 0);
     if (hipEventCreateWithFlags(&r->seeds_sent, hipEventDisableTiming) != hipSuccess) {
         r->seeds_sent = nullptr;
         return fail(PP_EDEVICE, "event creation");
@@ -818,26 +847,32 @@ int reset_with_host_seeds(pp_run r, const int32_t *seeds) {
 // seed outside its graph (device seed lists are checked by the device) is
 // reported here.
 int sync_state(pp_run r, int upto) {
-    const int nc = r->pgrid ? r->G : 1;
+    // control blocks staged: one per graph (clustered engine), one per seed
+    // group (the per-round engine: group j's at j * G), one otherwise
     const int G = r->G;
+    const int KG = r->k * G;
+    const int nstage = r->pgrid ? G : (r->k > 1 ? KG : 1);
     const int rows = std::max(0, std::min({upto, r->cap, r->staged + STAGE_ROWS}) - r->staged);
-    HIP_TRY(pp::launch_stage(r->dev.ctrl, (int64_t)sizeof(Ctrl) * nc, r->dev.D, G, r->dev.counts + (int64_t)r->staged * G,
-                             (int64_t)rows * G, r->h_ctrl_dev, r->h_D_dev, r->h_rows_dev, r->stream));
+    HIP_TRY(pp::launch_stage(r->dev.ctrl, (int64_t)sizeof(Ctrl) * nstage, r->dev.D, KG,
+                             r->dev.counts + (int64_t)r->staged * KG, (int64_t)rows * KG, r->h_ctrl_dev, r->h_D_dev,
+                             r->h_rows_dev, r->stream));
     HIP_TRY(hipStreamSynchronize(r->stream));
+    const int nc = r->pgrid ? G : r->k;          // live control blocks
+    const int cstep = r->pgrid ? 1 : G;
     r->host_ctrl = r->h_ctrl[0];
     r->cur.assign((size_t)nc, 0);
-    for (int k = 0; k < nc; ++k) {
-        const Ctrl &c = r->h_ctrl[k];
-        r->cur[(size_t)k] = c.cur & 1;
-        if (k == 0) continue;
+    for (int j = 0; j < nc; ++j) {
+        const Ctrl &c = r->h_ctrl[(size_t)j * cstep];
+        r->cur[(size_t)j] = c.cur & 1;
+        if (j == 0) continue;
         r->host_ctrl.round = std::max(r->host_ctrl.round, c.round);
         r->host_ctrl.converged = r->host_ctrl.converged && c.converged;
         r->host_ctrl.overflow |= c.overflow;
         r->host_ctrl.bad_seed |= c.bad_seed;
     }
-    r->D_host.assign(r->h_D, r->h_D + G);
+    r->D_host.assign(r->h_D, r->h_D + KG);
     if (rows > 0) {
-        r->counts_host.insert(r->counts_host.end(), r->h_rows, r->h_rows + (size_t)rows * G);
+        r->counts_host.insert(r->counts_host.end(), r->h_rows, r->h_rows + (size_t)rows * KG);
         r->staged += rows;
     }
     if (r->host_ctrl.bad_seed) return fail(PP_ERANGE, "a seed id lies outside its graph's node range");
@@ -852,7 +887,7 @@ int ensure_staged(pp_run r, int upto) {
     upto = std::min(upto, r->cap);
     if (r->staged >= upto) return PP_OK;
     if (upto - r->staged <= STAGE_ROWS) return sync_state(r, upto);
-    const size_t G = (size_t)r->G;
+    const size_t G = (size_t)r->k * (size_t)r->G;   // values per round row
     const size_t have = r->counts_host.size();
     r->counts_host.resize((size_t)upto * G);
     HIP_TRY(hipMemcpyAsync(r->counts_host.data() + have, r->dev.counts + have, sizeof(int64_t) * ((size_t)upto * G - have),
@@ -860,6 +895,21 @@ int ensure_staged(pp_run r, int upto) {
     HIP_TRY(hipStreamSynchronize(r->stream));
     r->staged = upto;
     return PP_OK;
+}
+
+// c_g[row] of graph gi, summed over the seed groups (rows already staged).
+int64_t staged_count(pp_run r, int row, int gi) {
+    int64_t c = 0;
+    const size_t base = (size_t)row * r->k * r->G;
+    for (int j = 0; j < r->k; ++j) c += r->counts_host[base + (size_t)j * r->G + gi];
+    return c;
+}
+
+// D of graph gi: the largest over its seed groups.
+int32_t staged_D(pp_run r, int gi) {
+    int32_t d = 0;
+    for (int j = 0; j < r->k; ++j) d = std::max(d, r->D_host[(size_t)j * r->G + gi]);
+    return d;
 }
 
 }  // namespace
@@ -961,7 +1011,12 @@ int reset_run(pp_run r, const int32_t *seeds, const int32_t *map) {
     hipError_t e = clear_run_dev(g, r->dev, r->stream, !r->acc_clean);
     if (e == hipSuccess) {
         r->acc_clean = true;
-        if (r->pgrid) {
+        if (r->grouped) {
+            // the seed list in internal order (stored ids), then the groups' seed bits
+            e = pp::launch_seed_order(gv, seeds, map, r->G, r->s, r->opt.seed_order == PP_ORDER_BY_REACH, r->iseeds,
+                                      r->dpos, r->stream);
+            if (e == hipSuccess) e = pp::launch_seed_init(gv, r->dev, r->iseeds, nullptr, r->stream);
+        } else if (r->pgrid) {
             if (map) {
                 e = pp::launch_map_ids(r->dseeds, seeds, map, (int64_t)r->G * r->s, g->n, r->stream);
                 seeds = r->dseeds;
@@ -974,7 +1029,7 @@ int reset_run(pp_run r, const int32_t *seeds, const int32_t *map) {
     if (e != hipSuccess) return fail(PP_EDEVICE, "seed initialisation: %s", hipGetErrorString(e));
     r->staged = 0;
     r->counts_host.clear();
-    r->D_host.assign((size_t)r->G, 0);
+    r->D_host.assign((size_t)r->k * r->G, 0);
     if (r->pgrid) {
         int rc = launch_clusters(r, 0);   // round 0 of every graph only
         if (rc) return rc;
@@ -986,7 +1041,7 @@ int reset_run(pp_run r, const int32_t *seeds, const int32_t *map) {
     // reported by the next call that waits.
     r->host_ctrl = Ctrl{};
     r->host_ctrl.round = 1;
-    r->cur.assign(1, 0);
+    r->cur.assign((size_t)r->k, 0);
     return PP_OK;
 }
 
@@ -1064,7 +1119,7 @@ extern "C" int pp_seeds_init(pp_graph g, const int32_t *seeds, int32_t s, const 
                              pp_run *out) {
     if (!g || !out) return fail(PP_EINVAL, "graph or out is NULL");
     pp::AllocStream as(stream);
-    if (s < 1 || s > 512) return fail(PP_EINVAL, "s = %d outside [1, 512]", s);
+    if (s < 1 || s > 4096) return fail(PP_EINVAL, "s = %d outside [1, 4096]", s);
     if (!seeds) return fail(PP_EINVAL, "seeds is NULL");
     pp_options o;
     pp_options_default(&o);
@@ -1077,22 +1132,54 @@ extern "C" int pp_seeds_init(pp_graph g, const int32_t *seeds, int32_t s, const 
     if (o.node_stats != 0 && o.node_stats != 1) return fail(PP_EINVAL, "node_stats must be 0 or 1");
     if (o.sparse_pull < 0 || o.sparse_pull > 2) return fail(PP_EINVAL, "sparse_pull = %d: 0, 1 or 2", o.sparse_pull);
     if (o.sparse_pull && o.persistent) return fail(PP_EINVAL, "sparse pulls need the per-round engine");
-    if (o.scheduler < PP_SCHED_HEURISTIC || o.scheduler > PP_SCHED_MLP) return fail(PP_EINVAL, "unknown scheduler %d", o.scheduler);
+    if (o.scheduler < PP_SCHED_HEURISTIC || o.scheduler > PP_SCHED_PLAN) return fail(PP_EINVAL, "unknown scheduler %d", o.scheduler);
     if (o.max_rounds < 0 || o.rounds_per_sync < 0) return fail(PP_EINVAL, "negative max_rounds / rounds_per_sync");
+    if (o.seed_order != 0 && o.seed_order != PP_ORDER_BY_REACH) return fail(PP_EINVAL, "seed_order = %d: 0 or 1", o.seed_order);
+    if (o.seed_groups < PP_GROUPS_BY_REACH || o.seed_groups > 64)
+        return fail(PP_EINVAL, "seed_groups = %d outside [-1, 64]", o.seed_groups);
     const int G = g->G;
     int rc = check_host_seeds(g, seeds, s);
     if (rc) return rc;
+    // seed groups: k groups of sg seeds (the last may hold fewer), rows of W words each
+    if (o.seed_groups == PP_GROUPS_BY_REACH) o.seed_order = PP_ORDER_BY_REACH;
+    int k = o.seed_groups > 0 ? o.seed_groups : (s + 511) / 512;
+    if (o.seed_groups == PP_GROUPS_BY_REACH) {
+        // one group wide enough for the seeds with a predecessor (the most of any graph)
+        int live = 1;
+        for (int gi = 0; gi < G; ++gi) {
+            int c = 0;
+            for (int i = 0; i < s; ++i) {
+                const int32_t x = seeds[(int64_t)gi * s + i];
+                const size_t u = g->perm.empty() ? (size_t)x : (size_t)g->perm[(size_t)x];
+                c += (int)((g->pred_bits[u >> 6] >> (u & 63)) & 1ull);
+            }
+            live = std::max(live, c);
+        }
+        const int sg0 = std::min(512, 64 * words_for(live));
+        k = (s + sg0 - 1) / sg0;
+    }
+    const int sg = (s + k - 1) / k;
+    if (sg > 512) return fail(PP_EINVAL, "%d seeds in %d groups: more than 512 per group", s, k);
+    if ((int64_t)(k - 1) * sg >= s) return fail(PP_EINVAL, "%d seeds do not fill %d groups of %d", s, k, sg);
+    if (k > 1 && o.persistent) return fail(PP_EINVAL, "seed groups need the per-round engine");
+    if (k > 1 && o.node_stats) return fail(PP_EINVAL, "per-node statistics need a single seed group");
+    if (o.seed_order && o.persistent) return fail(PP_EINVAL, "a seed order needs the per-round engine");
     int64_t cap = o.max_rounds > 0 ? (int64_t)o.max_rounds + 1 : std::min<int64_t>(g->n + 1, 1 << 20);
     if (cap < 2) cap = 2;
-    if (o.seed_counts && cap * G * (int64_t)s * 4 > (int64_t)1 << 31)
-        return fail(PP_EINVAL, "per-seed count log of %lld bytes: lower max_rounds", (long long)(cap * G * (int64_t)s * 4));
-    const int W = words_for(s);
+    if (o.seed_counts && cap * G * (int64_t)k * sg * 4 > (int64_t)1 << 31)
+        return fail(PP_EINVAL, "per-seed count log of %lld bytes: lower max_rounds",
+                    (long long)(cap * G * (int64_t)k * sg * 4));
+    const int W = words_for(sg);
 
     pp_run r = new (std::nothrow) pp_run_s();
     if (!r) return fail(PP_ENOMEM, "run handle");
     r->g = g;
     r->s = s;
     r->W = W;
+    r->k = k;
+    r->sg = sg;
+    r->Wout = words_for(s);
+    r->grouped = k > 1 || o.seed_order != 0;
     r->cap = (int32_t)cap;
     r->G = G;
     r->opt = o;
@@ -1109,7 +1196,9 @@ extern "C" int pp_seeds_init(pp_graph g, const int32_t *seeds, int32_t s, const 
             delete r;
             return fail(PP_EINVAL, "%d graphs but only %d co-resident blocks: use the per-round engine", G, p);
         }
-        int dev = 0, khz = 0;
+    }
+    {
+        int dev = 0, khz = 0;   // the device clock of the per-round stamps
         if (hipGetDevice(&dev) == hipSuccess &&
             hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) == hipSuccess && khz > 0)
             r->clock_khz = khz;
@@ -1128,8 +1217,11 @@ extern "C" int pp_seeds_init(pp_graph g, const int32_t *seeds, int32_t s, const 
     TileSet *ts = nullptr;
     rc = ensure_tiles(g, W, r->dev.pull_k, &ts);
     if (rc == PP_OK)
-        rc = alloc_run_dev(g, r->dev, s, W, (int)cap, o.seed_counts != 0, std::max(pp::pull_grid_for(ts->ntiles, W), r->pgrid));
+        rc = alloc_run_dev(g, r->dev, s, k, sg, W, (int)cap, o.seed_counts != 0,
+                           std::max(pp::pull_grid_for(ts->ntiles, W), r->pgrid));
     if (rc == PP_OK) rc = dev_alloc(&r->dseeds, (int64_t)G * s);
+    if (rc == PP_OK && r->grouped && ((rc = dev_alloc(&r->iseeds, (int64_t)G * s)) == PP_OK))
+        if ((rc = dev_alloc(&r->dpos, (int64_t)G * s)) == PP_OK) rc = dev_alloc(&r->dcur, k);
     if (rc == PP_OK && o.node_stats) rc = dev_alloc(&r->dev.node_acc, g->n);
     if (rc == PP_OK && r->pgrid) {
         r->clusters = make_clusters(g, ts, r->pgrid);
@@ -1157,6 +1249,7 @@ extern "C" int pp_seeds_init(pp_graph g, const int32_t *seeds, int32_t s, const 
     r->dev.fuzz_seed = o.fuzz_seed;
     // cost-model weights start as NaN: the heuristic decides until they are set
     hipError_t e = pp::launch_fill_i32((int32_t *)r->dev.mlp, kNaNBits, pp::MLP_PARAMS, r->stream);
+    if (e == hipSuccess) e = pp::launch_fill_i32(r->dev.plan, -1, cap, r->stream);   // no plan: the heuristic
     if (e != hipSuccess) {
         free_run(r);
         return fail(PP_EDEVICE, "cost-model reset: %s", hipGetErrorString(e));
@@ -1214,7 +1307,9 @@ int run_persistent(pp_run r, int max_round) {
 
 }  // namespace
 extern "C" int32_t pp_run_round(pp_run r) { return r ? r->host_ctrl.round : -1; }
-extern "C" int32_t pp_run_words(pp_run r) { return r ? r->W : -1; }
+extern "C" int32_t pp_run_words(pp_run r) { return r ? r->Wout : -1; }
+extern "C" int32_t pp_run_groups(pp_run r) { return r ? r->k : -1; }
+extern "C" int32_t pp_run_group_words(pp_run r) { return r ? r->W : -1; }
 
 extern "C" int pp_propagate_round(pp_run r, int64_t *new_bits, int32_t *all_converged) {
     if (!r) return fail(PP_EINVAL, "run is NULL");
@@ -1242,7 +1337,7 @@ extern "C" int pp_propagate_round(pp_run r, int64_t *new_bits, int32_t *all_conv
     if (new_bits) {
         if (rr < r->cap) {
             if ((rc = ensure_staged(r, rr + 1))) return rc;
-            std::memcpy(new_bits, r->counts_host.data() + (size_t)rr * G, sizeof(int64_t) * (size_t)G);
+            for (int gi = 0; gi < G; ++gi) new_bits[gi] = staged_count(r, rr, gi);
         } else {
             std::memset(new_bits, 0, sizeof(int64_t) * (size_t)G);
         }
@@ -1345,10 +1440,10 @@ extern "C" int pp_propagate_until_converged(pp_run r, int32_t max_rounds, int64_
         if (rc) return rc;
         std::memset(counts, 0, sizeof(int64_t) * (size_t)G * cap_rounds);
         for (int g = 0; g < G; ++g)
-            for (int k = 0; k <= last && k < cap_rounds; ++k)
-                counts[(int64_t)g * cap_rounds + k] = r->counts_host[(size_t)k * G + g];
+            for (int k = 0; k <= last && k < cap_rounds; ++k) counts[(int64_t)g * cap_rounds + k] = staged_count(r, k, g);
     }
-    if (D) std::memcpy(D, r->D_host.data(), sizeof(int32_t) * (size_t)G);
+    if (D)
+        for (int g = 0; g < G; ++g) D[g] = staged_D(r, g);
     if (!r->host_ctrl.converged || r->host_ctrl.overflow) return fail(PP_ENOTCONV, "stopped after %d rounds without convergence", r->host_ctrl.round);
     return PP_OK;
 }
@@ -1359,6 +1454,37 @@ int copy_signatures(pp_run r, uint64_t *dst, hipMemcpyKind kind);
 
 extern "C" int pp_get_signatures(pp_run r, uint64_t *dst, int32_t dst_on_device) {
     if (!r || !dst) return fail(PP_EINVAL, "run or dst is NULL");
+    if (r->grouped) {
+        // the groups' rows in the caller's bit order (stored node order), then by input id
+        int rc = sync_ctrl(r);   // each group's current buffer
+        if (rc) return rc;
+        const int64_t n = r->g->n, words = n * r->Wout;
+        std::vector<int32_t> cur(r->cur.begin(), r->cur.end());
+        uint64_t *tmp = nullptr, *out = nullptr;
+        const bool direct = dst_on_device && !r->g->perm_d;
+        if (!direct) rc = dev_alloc(&tmp, words);
+        if (!rc && !dst_on_device && r->g->perm_d) rc = dev_alloc(&out, words);
+        hipError_t e = hipSuccess;
+        if (!rc) e = hipMemcpyAsync(r->dcur, cur.data(), sizeof(int32_t) * cur.size(), hipMemcpyHostToDevice, r->stream);
+        uint64_t *rows = direct ? dst : tmp;
+        if (!rc && !e)
+            e = pp::launch_sig_regroup(r->dev.sig[0], n, r->W, r->Wout, r->s, r->sg, r->dcur, r->dpos, r->g->node_graph,
+                                       rows, r->stream);
+        if (!rc && !e && r->g->perm_d) {
+            uint64_t *by_id = dst_on_device ? dst : out;
+            e = pp::launch_gather_rows(by_id, rows, r->g->perm_d, n, r->Wout, r->stream);
+            rows = by_id;
+        }
+        if (!rc && !e && !dst_on_device)
+            e = hipMemcpyAsync(dst, rows, sizeof(uint64_t) * (size_t)words, hipMemcpyDeviceToHost, r->stream);
+        if (!rc && !e) e = hipStreamSynchronize(r->stream);
+        if (rc || e) (void)hipStreamSynchronize(r->stream);   // queued work done before the blocks go back
+        dev_free(tmp);
+        dev_free(out);
+        if (rc) return rc;
+        if (e) return fail(PP_EDEVICE, "signature regroup: %s", hipGetErrorString(e));
+        return PP_OK;
+    }
     if (r->g->perm_d) {
         // stored order -> input order: assemble the rows, then gather them by id
         const int64_t words = r->g->n * r->W;
@@ -1409,15 +1535,41 @@ extern "C" int pp_get_seed_counts(pp_run r, uint32_t *dst, int32_t cap_rounds) {
     if (!r || !dst) return fail(PP_EINVAL, "run or dst is NULL");
     if (!r->dev.seed_counts) return fail(PP_ESTATE, "run was created without seed_counts");
     if (cap_rounds < 1) return fail(PP_EINVAL, "cap_rounds < 1");
-    const int G = r->G, s = r->s;
+    const int G = r->G, s = r->s, k = r->k, sg = r->sg;
     const int rows = std::min(cap_rounds, r->cap);
-    std::vector<uint32_t> buf((size_t)rows * G * s);
+    // device layout [round][group][graph][sg]; the caller's seed i of graph g is
+    // internal position pos[g s + i]: group pos / sg, column pos % sg
+    std::vector<uint32_t> buf((size_t)rows * k * G * sg);
+    std::vector<int32_t> pos((size_t)G * s);
     HIP_TRY(hipMemcpyAsync(buf.data(), r->dev.seed_counts, sizeof(uint32_t) * buf.size(), hipMemcpyDeviceToHost, r->stream));
+    if (r->grouped)
+        HIP_TRY(hipMemcpyAsync(pos.data(), r->dpos, sizeof(int32_t) * pos.size(), hipMemcpyDeviceToHost, r->stream));
     HIP_TRY(hipStreamSynchronize(r->stream));
+    if (!r->grouped)
+        for (size_t j = 0; j < pos.size(); ++j) pos[j] = (int32_t)(j % (size_t)s);
     std::memset(dst, 0, sizeof(uint32_t) * (size_t)G * cap_rounds * s);
     for (int g = 0; g < G; ++g)
-        for (int k = 0; k < rows; ++k)
-            std::memcpy(dst + ((int64_t)g * cap_rounds + k) * s, buf.data() + ((size_t)k * G + g) * s, sizeof(uint32_t) * s);
+        for (int q = 0; q < rows; ++q) {
+            uint32_t *o = dst + ((int64_t)g * cap_rounds + q) * s;
+            for (int i = 0; i < s; ++i) {
+                const int p = pos[(size_t)g * s + i], grp = p / sg;
+                o[i] = buf[(((size_t)q * k + grp) * G + g) * sg + (p - grp * sg)];
+            }
+        }
+    return PP_OK;
+}
+
+extern "C" int pp_get_group_log(pp_run r, int32_t group, int32_t *mode, int64_t *arcs, int32_t cap) {
+    if (!r) return fail(PP_EINVAL, "run is NULL");
+    if (group < 0 || group >= r->k) return fail(PP_EINVAL, "group %d outside [0, %d)", group, r->k);
+    const int rows = std::min(cap, r->cap);
+    if (rows < 1) return fail(PP_EINVAL, "cap < 1");
+    const int64_t off = (int64_t)group * r->G * r->cap;   // group j's logs (row 0 of its graphs)
+    if (mode)
+        HIP_TRY(hipMemcpyAsync(mode, r->dev.mode_log + off, sizeof(int32_t) * rows, hipMemcpyDeviceToHost, r->stream));
+    if (arcs)
+        HIP_TRY(hipMemcpyAsync(arcs, r->dev.arcs_log + off, sizeof(int64_t) * rows, hipMemcpyDeviceToHost, r->stream));
+    HIP_TRY(hipStreamSynchronize(r->stream));
     return PP_OK;
 }
 
@@ -1425,9 +1577,13 @@ extern "C" int pp_get_round_log(pp_run r, int32_t *mode, int64_t *arcs, int32_t 
     if (!r) return fail(PP_EINVAL, "run is NULL");
     const int rows = std::min(cap, r->cap);
     if (rows < 1) return fail(PP_EINVAL, "cap < 1");
-    if (mode) HIP_TRY(hipMemcpyAsync(mode, r->dev.mode_log, sizeof(int32_t) * rows, hipMemcpyDeviceToHost, r->stream));
-    if (arcs) HIP_TRY(hipMemcpyAsync(arcs, r->dev.arcs_log, sizeof(int64_t) * rows, hipMemcpyDeviceToHost, r->stream));
-    HIP_TRY(hipStreamSynchronize(r->stream));
+    int rc = pp_get_group_log(r, 0, mode, arcs, cap);
+    if (rc || !arcs) return rc;
+    std::vector<int64_t> more((size_t)rows);
+    for (int j = 1; j < r->k; ++j) {
+        if ((rc = pp_get_group_log(r, j, nullptr, more.data(), cap))) return rc;
+        for (int q = 0; q < rows; ++q) arcs[q] += more[(size_t)q];
+    }
     return PP_OK;
 }
 
@@ -1439,6 +1595,10 @@ extern "C" int pp_run_snapshot(pp_run r, pp_run *copy) {
     c->g = r->g;
     c->s = r->s;
     c->W = r->W;
+    c->k = r->k;
+    c->sg = r->sg;
+    c->Wout = r->Wout;
+    c->grouped = r->grouped;
     c->cap = r->cap;
     c->G = r->G;
     c->opt = r->opt;
@@ -1460,8 +1620,11 @@ extern "C" int pp_run_snapshot(pp_run r, pp_run *copy) {
             return fail(PP_ENOMEM, "snapshot clusters");
         }
     }
-    int rc = alloc_run_dev(r->g, c->dev, r->s, r->W, r->cap, r->dev.seed_counts != nullptr,
+    int rc = alloc_run_dev(r->g, c->dev, r->s, r->k, r->sg, r->W, r->cap, r->dev.seed_counts != nullptr,
                            std::max(pp::pull_grid_for(ts->ntiles, r->W), r->pgrid));
+    if (!rc && c->grouped && (rc = dev_alloc(&c->iseeds, (int64_t)c->G * c->s)) == PP_OK &&
+        (rc = dev_alloc(&c->dpos, (int64_t)c->G * c->s)) == PP_OK)
+        rc = dev_alloc(&c->dcur, c->k);
     if (!rc) rc = alloc_staging(c);
     if (rc) {
         free_run(c);
@@ -1483,38 +1646,39 @@ extern "C" int pp_run_snapshot(pp_run r, pp_run *copy) {
 
 extern "C" int pp_run_restore(pp_run r, pp_run from) {
     if (!r || !from) return fail(PP_EINVAL, "run is NULL");
-    if (r->g != from->g || r->s != from->s || r->cap != from->cap ||
-        (r->dev.seed_counts == nullptr) != (from->dev.seed_counts == nullptr))
-        return fail(PP_EINVAL, "runs differ in graph, s, max_rounds or seed_counts");
+    if (r->g != from->g || r->s != from->s || r->cap != from->cap || r->k != from->k ||
+        r->grouped != from->grouped || (r->dev.seed_counts == nullptr) != (from->dev.seed_counts == nullptr))
+        return fail(PP_EINVAL, "runs differ in graph, s, seed groups, max_rounds or seed_counts");
     if (r == from) return PP_OK;
     if (from->stream != r->stream) HIP_TRY(hipStreamSynchronize(from->stream));
-    const int64_t n = r->g->n, W = r->W, G = r->G, cap = r->cap;
+    const int64_t n = r->g->n, W = r->W, k = r->k, KG = (int64_t)r->k * r->G, cap = r->cap;
     hipStream_t st = r->stream;
     auto cp = [&](void *d, const void *s, size_t bytes) { return hipMemcpyAsync(d, s, bytes, hipMemcpyDeviceToDevice, st); };
     const RunDev &a = from->dev;
     RunDev &b = r->dev;
-    hipError_t e = cp(b.sig[0], a.sig[0], 8 * n * W);
-    if (!e) e = cp(b.sig[1], a.sig[1], 8 * n * W);
-    if (!e) e = cp(b.acc, a.acc, 8 * n * W);
-    if (!e) e = cp(b.stamp, a.stamp, 4 * n);
-    for (int k = 0; k < 2 && !e; ++k) {
-        e = cp(b.f_ids[k], a.f_ids[k], 4 * n);
-        if (!e) e = cp(b.f_delta[k], a.f_delta[k], 8 * n * W);
-        if (!e) e = cp(b.chunks[k], a.chunks[k], sizeof(Chunk) * chunk_capacity(r->g));
-    }
-    if (!e) e = cp(b.counts, a.counts, 8 * cap * G);
-    if (!e && b.seed_counts) e = cp(b.seed_counts, a.seed_counts, 4 * cap * G * r->s);
-    if (!e) e = cp(b.D, a.D, 4 * G);
-    if (!e) e = cp(b.gconv, a.gconv, 4 * G);
-    if (!e) e = cp(b.mode_log, a.mode_log, 4 * cap * G);
-    if (!e) e = cp(b.arcs_log, a.arcs_log, 8 * cap * G);
-    if (!e) e = cp(b.phase_log, a.phase_log, 8 * cap * 3 * G);
-    if (!e) e = cp(b.feat_log, a.feat_log, sizeof(float) * pp::MLP_IN * cap * G);
+    // every group's arrays, each one allocation (pairs included)
+    hipError_t e = cp(b.sig[0], a.sig[0], 8 * 2 * k * n * W);
+    if (!e) e = cp(b.acc, a.acc, 8 * k * n * W);
+    if (!e) e = cp(b.stamp, a.stamp, 4 * k * n);
+    if (!e) e = cp(b.f_ids[0], a.f_ids[0], 4 * 2 * k * n);
+    if (!e) e = cp(b.f_delta[0], a.f_delta[0], 8 * 2 * k * n * W);
+    if (!e) e = cp(b.chunks[0], a.chunks[0], sizeof(Chunk) * 2 * k * chunk_capacity(r->g));
+    if (!e) e = cp(b.counts, a.counts, 8 * cap * KG);
+    if (!e && b.seed_counts) e = cp(b.seed_counts, a.seed_counts, 4 * cap * KG * r->sg);
+    if (!e) e = cp(b.D, a.D, 4 * KG);
+    if (!e) e = cp(b.gconv, a.gconv, 4 * KG);
+    if (!e) e = cp(b.mode_log, a.mode_log, 4 * cap * KG);
+    if (!e) e = cp(b.arcs_log, a.arcs_log, 8 * cap * KG);
+    if (!e) e = cp(b.phase_log, a.phase_log, 8 * cap * 3 * KG);
+    if (!e) e = cp(b.feat_log, a.feat_log, sizeof(float) * pp::MLP_IN * cap * KG);
     if (!e) e = cp(b.mlp, a.mlp, sizeof(float) * pp::MLP_PARAMS);
-    if (!e) e = cp(b.tickets, a.tickets, sizeof(int32_t) * pp::TICKET_INTS);
+    if (!e) e = cp(b.plan, a.plan, sizeof(int32_t) * cap);
+    if (!e) e = cp(b.tickets, a.tickets, sizeof(int32_t) * pp::TICKET_INTS * k);
     if (!e && b.node_acc && a.node_acc) e = cp(b.node_acc, a.node_acc, sizeof(int64_t) * n);
-    if (!e) e = cp(b.ctrl, a.ctrl, sizeof(Ctrl) * G);
-    if (!e) e = cp(b.bar, a.bar, sizeof(pp::GridBar) * G);
+    if (!e) e = cp(b.ctrl, a.ctrl, sizeof(Ctrl) * KG);
+    if (!e) e = cp(b.bar, a.bar, sizeof(pp::GridBar) * KG);
+    if (!e && r->grouped) e = cp(r->iseeds, from->iseeds, sizeof(int32_t) * (size_t)r->G * r->s);
+    if (!e && r->grouped) e = cp(r->dpos, from->dpos, sizeof(int32_t) * (size_t)r->G * r->s);
     if (!e) e = hipStreamSynchronize(st);
     if (e) {
         r->acc_clean = false;
@@ -1579,7 +1743,8 @@ extern "C" int pp_run_set_mlp(pp_run r, const float *params) {
         HIP_TRY(pp::launch_fill_i32((int32_t *)r->dev.mlp, kNaNBits, pp::MLP_PARAMS, r->stream));
     }
     // the next round's direction was taken with the old weights
-    if (params) HIP_TRY(pp::launch_redecide(r->dev, r->G, r->stream));
+    // live control blocks: one per graph (clustered engine), one per seed group otherwise
+    if (params) HIP_TRY(pp::launch_redecide(r->dev, r->pgrid ? r->G : r->k, r->pgrid ? 1 : r->G, r->stream));
     HIP_TRY(hipStreamSynchronize(r->stream));
     return sync_ctrl(r);
 }
@@ -1593,10 +1758,35 @@ extern "C" int pp_get_round_features(pp_run r, float *feat, int32_t cap) {
     return PP_OK;
 }
 
+extern "C" int pp_run_set_plan(pp_run r, const int32_t *plan, int32_t len) {
+    if (!r) return fail(PP_EINVAL, "run is NULL");
+    if (len < 0 || (len > 0 && !plan)) return fail(PP_EINVAL, "plan is NULL with len > 0");
+    const int n = std::min(len, r->cap);
+    HIP_TRY(pp::launch_fill_i32(r->dev.plan, -1, r->cap, r->stream));
+    if (n > 0) HIP_TRY(hipMemcpyAsync(r->dev.plan, plan, sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice, r->stream));
+    HIP_TRY(hipStreamSynchronize(r->stream));
+    return PP_OK;
+}
+
+extern "C" int pp_get_round_times(pp_run r, float *ms, int32_t cap) {
+    if (!r || !ms) return fail(PP_EINVAL, "run or ms is NULL");
+    if (cap < 1) return fail(PP_EINVAL, "cap < 1");
+    if (r->pgrid) return fail(PP_ESTATE, "round times are kept by the per-round engine");
+    const int rows = std::min(cap, r->cap);
+    std::vector<int64_t> st((size_t)rows * 3);
+    HIP_TRY(hipMemcpyAsync(st.data(), r->dev.phase_log, sizeof(int64_t) * st.size(), hipMemcpyDeviceToHost, r->stream));
+    HIP_TRY(hipStreamSynchronize(r->stream));
+    for (int q = 0; q < cap; ++q) {
+        const int64_t a = q < rows ? st[(size_t)q * 3] : 0, b = q < rows ? st[(size_t)q * 3 + 2] : 0;
+        ms[q] = (q >= 1 && a > 0 && b > a) ? (float)((double)(b - a) / r->clock_khz) : 0.0f;
+    }
+    return PP_OK;
+}
+
 extern "C" int pp_time_round(pp_run r, int32_t mode, float *features, float *ms) {
     if (!r || !ms) return fail(PP_EINVAL, "run or ms is NULL");
-    if (mode != pp::MODE_PULL && mode != pp::MODE_PUSH && mode != pp::MODE_SPULL)
-        return fail(PP_EINVAL, "mode %d is none of pull (0), push (1), sparse pull (3)", mode);
+    if (mode != pp::MODE_PULL && mode != pp::MODE_PUSH && mode != pp::MODE_SPULL && mode != pp::MODE_PUSH_FLAT)
+        return fail(PP_EINVAL, "mode %d is none of pull (0), push (1), sparse pull (3), flattened push (4)", mode);
     if (mode == pp::MODE_PUSH && r->dev.sparse_pull == 1) mode = pp::MODE_SPULL;   // the run's sparse direction
     if (r->pgrid) return fail(PP_ESTATE, "timing of single rounds needs the per-round engine");
     int rc = sync_ctrl(r);
@@ -1610,10 +1800,24 @@ extern "C" int pp_time_round(pp_run r, int32_t mode, float *features, float *ms)
     GraphDev gv = graph_view(r->g, run_tiles(r), r->W);
     // every direction is valid in every round: forcing one changes the work
     // done, never the result
-    HIP_TRY(hipMemcpyAsync(&r->dev.ctrl[0].mode, &mode, sizeof(int32_t), hipMemcpyHostToDevice, r->stream));
+    // every seed group's control block: the direction, and the frontier's
+    // tiling (bit 0; a sparse pull keeps the fixed threshold's, bit 1)
+    std::vector<int32_t> fw((size_t)r->k * 2);
+    for (int j = 0; j < r->k; ++j) {
+        const int32_t hf = (r->h_ctrl[(size_t)j * (r->k > 1 ? r->G : 1)].flat >> 1) & 1;
+        const int32_t b0 = mode == pp::MODE_PUSH_FLAT ? 1 : (mode == pp::MODE_PUSH ? 0 : hf);
+        fw[(size_t)2 * j] = mode == pp::MODE_PUSH_FLAT ? pp::MODE_PUSH : mode;
+        fw[(size_t)2 * j + 1] = b0 | (hf << 1);
+        HIP_TRY(hipMemcpyAsync(&r->dev.ctrl[(size_t)j * r->G].mode, &fw[(size_t)2 * j], sizeof(int32_t),
+                               hipMemcpyHostToDevice, r->stream));
+        HIP_TRY(hipMemcpyAsync(&r->dev.ctrl[(size_t)j * r->G].flat, &fw[(size_t)2 * j + 1], sizeof(int32_t),
+                               hipMemcpyHostToDevice, r->stream));
+    }
     HIP_TRY(hipEventRecord(r->tev[0], r->stream));
     // the sparse kernel of the forced direction (a pull round launches the run's own)
-    const int kinds = mode == pp::MODE_PUSH ? pp::SPARSE_PUSH : (mode == pp::MODE_SPULL ? pp::SPARSE_PULL : pp::SPARSE_BY_RUN);
+    const int kinds = (mode == pp::MODE_PUSH || mode == pp::MODE_PUSH_FLAT)
+                          ? pp::SPARSE_PUSH
+                          : (mode == pp::MODE_SPULL ? pp::SPARSE_PULL : pp::SPARSE_BY_RUN);
     HIP_TRY(noted(r, pp::launch_round(gv, r->dev, r->stream, nullptr, nullptr, kinds)));
     HIP_TRY(hipEventRecord(r->tev[1], r->stream));
     HIP_TRY(hipEventSynchronize(r->tev[1]));

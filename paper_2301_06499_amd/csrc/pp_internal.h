@@ -12,7 +12,10 @@ namespace pp {
 // round runs either as a push (atomic ORs of the changed nodes' new bits into
 // their predecessors) or as a sparse pull (the predecessors that can gain a
 // bit gather their whole successor lists); both give the same bits.
-enum Mode : int32_t { MODE_PULL = 0, MODE_PUSH = 1, MODE_INIT = 2, MODE_SPULL = 3 };
+// MODE_PUSH_FLAT is a push that walks its frontier as flattened arc ranges
+// (the mode logs record it; the control block keeps MODE_PUSH and sets
+// bit 0 of `flat`).
+enum Mode : int32_t { MODE_PULL = 0, MODE_PUSH = 1, MODE_INIT = 2, MODE_SPULL = 3, MODE_PUSH_FLAT = 4 };
 
 // A pull work unit: a run of consecutive nodes [u0, u1) whose successor
 // lists occupy arcs [e0, e1) (at most the tile's arc budget), or one chunk of
@@ -100,7 +103,9 @@ struct Ctrl {
     int64_t last_count;   // new bits of the last round
     float feat[8];        // scheduler features of the round about to run
     int32_t acc_pending;  // a round (or the initialisation) ran since the last per-node accumulation
-    int32_t pad_ctrl;
+    int32_t flat;         // bit 0: the sparse round about to run walks its frontier as flattened
+                          // arc ranges (read before atomics) rather than direct slots per entry;
+                          // bit 1: the fixed threshold's choice (frontier >= PUSH_FILTER_MIN)
 };
 
 static_assert(sizeof(Ctrl) % 4 == 0, "the control block is staged to the host as 32-bit words");
@@ -113,17 +118,19 @@ constexpr int TICKET_STRIDE = 32;   // int32 per cache line
 constexpr int TICKET_INTS = (TICKET_GROUP + 1) * TICKET_STRIDE;
 constexpr int POST_MAX = 1024;      // blocks of the closing launch at most
 
-// Learned cost model: an MLP 8 -> 32 -> 32 -> 2 (ReLU) predicting the log of a
-// round's duration under pull (output 0) and push (output 1).  Parameter
-// layout (floats): W1[32][8], b1[32], W2[32][32], b2[32], W3[2][32], b3[2].
-constexpr int MLP_IN = 8, MLP_HID = 32, MLP_OUT = 2;
+// Learned cost model: an MLP 8 -> 32 -> 32 -> 4 (ReLU) predicting the log of a
+// round's effective cost under each action: 0 dense pull, 1 push over direct
+// slots per frontier entry, 2 push over flattened arc ranges, 3 sparse pull.
+// Parameter layout (floats): W1[32][8], b1[32], W2[32][32], b2[32], W3[4][32],
+// b3[4].
+constexpr int MLP_IN = 8, MLP_HID = 32, MLP_OUT = 4;
 constexpr int MLP_W1 = 0;
 constexpr int MLP_B1 = MLP_W1 + MLP_HID * MLP_IN;
 constexpr int MLP_W2 = MLP_B1 + MLP_HID;
 constexpr int MLP_B2 = MLP_W2 + MLP_HID * MLP_HID;
 constexpr int MLP_W3 = MLP_B2 + MLP_HID;
 constexpr int MLP_B3 = MLP_W3 + MLP_OUT * MLP_HID;
-constexpr int MLP_PARAMS = MLP_B3 + MLP_OUT;   // 1410
+constexpr int MLP_PARAMS = MLP_B3 + MLP_OUT;   // 1476
 static_assert(MLP_PARAMS == PP_MLP_PARAMS, "cost-model layout");
 
 // State of the grid barrier of the persistent round loop (zero at start).
@@ -166,10 +173,23 @@ struct GraphDev {
     int32_t pull_grid;           // blocks of the pull launch (= per-block partial slots)
 };
 
+// A run's device state.  Its seeds may be split into seed groups, each with
+// its own signature rows (W words), frontier, counters and control block:
+// every per-group array holds the groups one after another, and the kernels
+// of a launch take group blockIdx.y (group_view).  The fields below describe
+// group 0 until a kernel takes its group's view.
 struct RunDev {
-    int32_t s, W, cap, G;
-    int32_t cstride;      // distance between rounds in counts (graphs of the run)
-    int32_t sstride;      // distance between rounds in seed_counts (graphs * s)
+    int32_t s, W, cap, G; // seeds of the group, words per row, round-log capacity, graphs
+    int32_t cstride;      // distance between rounds in counts (groups * graphs)
+    int32_t sstride;      // distance between rounds in seed_counts (groups * graphs * sg)
+    int32_t ngroups;      // seed groups
+    int32_t sg;           // seeds per group (the last one may hold fewer: s_last)
+    int32_t s_last;       // seeds of the last group
+    int32_t s_all;        // seeds per graph (distance between graphs in a seed list)
+    int64_t nn;           // nodes of the graph (size of the per-node arrays of one group)
+    int64_t cc;           // push-chunk slots per frontier list of one group
+    int32_t pgrid;        // per-block partial slots of one group
+    int32_t pad_run;
     uint64_t *sig[2];     // [n][W] each: Sig_{r-1} in sig[cur], the pull writes the other
     uint64_t *acc;        // [n][W] push / hub accumulator, zero between rounds
     int32_t *stamp;       // [n] last round the node was queued
@@ -180,13 +200,14 @@ struct RunDev {
     int64_t *blk_nodes;   // [pull_grid] changed nodes
     int64_t *blk_arcs;    // [pull_grid] predecessor arcs of changed nodes
     int64_t *blk_pulled;  // [pull_grid] arcs gathered
-    int64_t *counts;      // [cap][G]
-    uint32_t *seed_counts;// [cap][G][s] or NULL
+    int64_t *counts;      // [cap][groups][G]
+    uint32_t *seed_counts;// [cap][groups][G][sg] or NULL
     int32_t *D;           // [G]
     int32_t *gconv;       // [G]
     int32_t *mode_log;    // [G][cap] (row 0 when the graphs run as one union)
     int64_t *arcs_log;    // [G][cap]
-    int64_t *phase_log;   // [G][cap][3] device-clock stamps of the persistent loop
+    int64_t *phase_log;   // [G][cap][3] device-clock stamps of each round: start, after the main
+                          // phase (persistent loop), end
     float *feat_log;      // [G][cap][8] scheduler features of each round (row 0 unused)
     int32_t *tickets;     // [TICKET_INTS] the closing launch's ticket counters (zero between launches)
     int64_t *post_part;   // [3][POST_MAX] the closing launch's per-block partials
@@ -199,6 +220,7 @@ struct RunDev {
     int32_t sparse_pull;  // sparse rounds: 0 push, 1 sparse pull, 2 either (pseudo-random per round)
     uint64_t fuzz_seed;
     float *mlp;           // [MLP_PARAMS] cost-model weights (NaN: not set, heuristic decides)
+    int32_t *plan;        // [cap] action of each round for PP_SCHED_PLAN (-1: the heuristic's)
     int64_t *node_acc;    // [n] per-node sums of popcount(Sig_r(u)) over the states so far, or NULL
 };
 
@@ -221,9 +243,9 @@ struct AllocStream {
 
 // Launchers (pp_kernels.hip).  All enqueue on `st` and return the launch status.
 hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t count, hipStream_t st);
-// Re-takes the pending direction of each of the first nctrl control blocks
+// Re-takes the pending direction of nctrl control blocks, `stride` apart,
 // with the run's current cost-model weights (PP_SCHED_MLP runs only).
-hipError_t launch_redecide(const RunDev &r, int nctrl, hipStream_t st);
+hipError_t launch_redecide(const RunDev &r, int nctrl, int stride, hipStream_t st);
 // A fill of n 4-byte words at p (16-byte aligned) with the value v.
 struct FillSeg {
     uint32_t *p;
@@ -267,6 +289,14 @@ hipError_t launch_stage(const void *ctrl, int64_t ctrl_bytes, const int32_t *D, 
                         int64_t nrows, void *h_ctrl, int32_t *h_D, int64_t *h_rows, hipStream_t st);
 hipError_t launch_gather_rows(uint64_t *dst, const uint64_t *src, const int32_t *perm, int64_t n, int W,
                               hipStream_t st);
+// The internal seed list of a run with seed groups or a seed order (one block
+// per graph): out = the stored ids in internal order, pos[i] = the internal
+// position of the caller's seed i (see k_seed_order).
+hipError_t launch_seed_order(const GraphDev &g, const int32_t *seeds, const int32_t *map, int G, int s_all,
+                             int by_reach, int32_t *out, int32_t *pos, hipStream_t st);
+// Rows of a grouped run's signatures in the caller's bit order (stored node order).
+hipError_t launch_sig_regroup(const uint64_t *sig, int64_t n, int Wg, int Wout, int s_all, int sg, const int32_t *cur,
+                              const int32_t *pos, const int32_t *node_graph, uint64_t *out, hipStream_t st);
 // seeds: device-readable ids; map (may be NULL): input id -> stored id.
 hipError_t launch_seed_init(const GraphDev &g, const RunDev &r, const int32_t *seeds, const int32_t *map,
                             hipStream_t st);

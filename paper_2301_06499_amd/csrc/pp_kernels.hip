@@ -62,6 +62,43 @@ PP_DEV uint64_t mix64(uint64_t z) {
     return z ^ (z >> 31);
 }
 
+// Group grp's view of a run: its signature pair, accumulator, stamps,
+// frontier lists, partial slots, counters, logs and control block (each
+// per-group array holds the groups one after another; counts and per-seed
+// counts interleave the groups within each round's row).
+PP_DEV RunDev group_view(const RunDev &R0, int grp) {
+    RunDev R = R0;
+    const int64_t n = R0.nn, W = R0.W, G = R0.G, cap = R0.cap;
+    R.s = grp == R0.ngroups - 1 ? R0.s_last : R0.sg;
+    R.sig[0] = R0.sig[0] + grp * 2 * n * W;
+    R.sig[1] = R.sig[0] + n * W;
+    R.acc = R0.acc + grp * n * W;
+    R.stamp = R0.stamp + grp * n;
+    R.f_ids[0] = R0.f_ids[0] + grp * 2 * n;
+    R.f_ids[1] = R.f_ids[0] + n;
+    R.f_delta[0] = R0.f_delta[0] + grp * 2 * n * W;
+    R.f_delta[1] = R.f_delta[0] + n * W;
+    R.chunks[0] = R0.chunks[0] + grp * 2 * R0.cc;
+    R.chunks[1] = R.chunks[0] + R0.cc;
+    R.blk_cnt = R0.blk_cnt + (int64_t)grp * R0.pgrid;
+    R.blk_nodes = R0.blk_nodes + (int64_t)grp * R0.pgrid;
+    R.blk_arcs = R0.blk_arcs + (int64_t)grp * R0.pgrid;
+    R.blk_pulled = R0.blk_pulled + (int64_t)grp * R0.pgrid;
+    R.counts = R0.counts + grp * G;
+    R.seed_counts = R0.seed_counts ? R0.seed_counts + grp * G * R0.sg : nullptr;
+    R.D = R0.D + grp * G;
+    R.gconv = R0.gconv + grp * G;
+    R.mode_log = R0.mode_log + grp * G * cap;
+    R.arcs_log = R0.arcs_log + grp * G * cap;
+    R.phase_log = R0.phase_log + grp * G * cap * 3;
+    R.feat_log = R0.feat_log + grp * G * cap * MLP_IN;
+    R.tickets = R0.tickets + (int64_t)grp * TICKET_INTS;
+    R.post_part = R0.post_part + (int64_t)grp * 3 * POST_MAX;
+    R.bar = R0.bar + grp * G;
+    R.ctrl = R0.ctrl + grp * G;
+    return R;
+}
+
 // Buffer k & 1 of a pair by arithmetic on both pointers rather than a
 // run-time index into the pair (which would keep a struct copy of the run in
 // scratch memory).  Both members of every pair live in one allocation.
@@ -176,7 +213,7 @@ PP_DEV void seed_bits(const RunDev &R, int r, int gi, int w, uint64_t d) {
     while (d) {
         const int bit = __ffsll((long long)d) - 1;
         d &= d - 1;
-        atomicAdd(&R.seed_counts[(int64_t)r * R.sstride + (int64_t)gi * R.s + w * 64 + bit], 1u);
+        atomicAdd(&R.seed_counts[(int64_t)r * R.sstride + (int64_t)gi * R.sg + w * 64 + bit], 1u);
     }
 }
 
@@ -407,18 +444,106 @@ hipError_t launch_gather_rows(uint64_t *dst, const uint64_t *src, const int32_t 
 
 // ---------------------------------------------------------------- seeds
 
+// The internal seed list of a run with seed groups or a seed order, one block
+// per graph: the caller's ids (mapped to stored ids by `map` when given; ids
+// outside [0, n) become -1, which the seed placement reports) in internal
+// order, out[gi * s_all + q], and pos[gi * s_all + i] = q, the internal
+// position of the caller's seed i.  With by_reach, the seeds whose node has a
+// predecessor come first and the rest after them, each part in the caller's
+// order (a seed without a predecessor can set no bit but its own); otherwise
+// q = i.  Group j holds internal positions [j sg, (j + 1) sg).
+__global__ void __launch_bounds__(BLOCK) k_seed_order(GraphDev g, const int32_t *seeds, const int32_t *map,
+                                                      int s_all, int by_reach, int32_t *out, int32_t *pos) {
+    __shared__ int s_scan[BLOCK / 64];
+    const int64_t base = (int64_t)blockIdx.x * s_all;
+    auto stored = [&](int i) -> int32_t {
+        int32_t x = seeds[base + i];
+        if (map) x = (x >= 0 && x < g.n) ? map[x] : -1;
+        return x;
+    };
+    // a seed the placement will reject keeps its place among the first part
+    auto live = [&](int32_t x) -> bool { return !by_reach || x < 0 || x >= g.n || g.trp[x + 1] > g.trp[x]; };
+    int nlive = 0;
+    for (int i0 = 0; i0 < s_all; i0 += BLOCK) {   // block-uniform
+        const int i = i0 + threadIdx.x;
+        int t = 0;
+        (void)block_scan(i < s_all && live(stored(i)) ? 1 : 0, s_scan, t);
+        nlive += t;
+    }
+    int done_live = 0, done_dead = 0;
+    for (int i0 = 0; i0 < s_all; i0 += BLOCK) {   // block-uniform
+        const int i = i0 + threadIdx.x;
+        const bool valid = i < s_all;
+        const int32_t x = valid ? stored(i) : 0;
+        const bool lv = valid && live(x);
+        int tl = 0, td = 0;
+        const int rl = block_scan(lv ? 1 : 0, s_scan, tl);
+        const int rd = block_scan(valid && !lv ? 1 : 0, s_scan, td);
+        if (valid) {
+            const int q = lv ? done_live + rl : nlive + done_dead + rd;
+            out[base + q] = x;
+            pos[base + i] = q;
+        }
+        done_live += tl;
+        done_dead += td;
+    }
+}
+
+// Signature rows in the caller's bit order from the rows of a run's seed
+// groups: word j of row u holds the caller's seeds 64 j .. 64 j + 63 of u's
+// graph; seed i sits at internal position q = pos[gi * s_all + i], bit q % sg
+// of group q / sg's row (group grp's current buffer is cur[grp]; each group
+// holds a pair of [n][Wg] buffers, the groups one after another).  Rows in
+// stored order.
+__global__ void __launch_bounds__(BLOCK) k_sig_regroup(const uint64_t *sig, int64_t n, int Wg, int Wout, int s_all,
+                                                       int sg, const int32_t *cur, const int32_t *pos,
+                                                       const int32_t *node_graph, uint64_t *out) {
+    const int64_t total = n * Wout;
+    for (int64_t t = blockIdx.x * (int64_t)BLOCK + threadIdx.x; t < total; t += (int64_t)gridDim.x * BLOCK) {
+        const int64_t u = t / Wout;
+        const int j = (int)(t - u * Wout);
+        const int64_t gb = (node_graph ? (int64_t)node_graph[u] : 0) * s_all;
+        uint64_t word = 0;
+        for (int b = 0; b < 64; ++b) {
+            const int i = j * 64 + b;
+            if (i >= s_all) break;
+            const int q = pos[gb + i];
+            const int grp = q / sg, p = q - grp * sg;
+            const uint64_t *row = sig + ((int64_t)grp * 2 + cur[grp]) * n * Wg + u * Wg;
+            word |= ((row[p >> 6] >> (p & 63)) & 1ull) << b;
+        }
+        out[t] = word;
+    }
+}
+
+hipError_t launch_seed_order(const GraphDev &g, const int32_t *seeds, const int32_t *map, int G, int s_all,
+                             int by_reach, int32_t *out, int32_t *pos, hipStream_t st) {
+    hipLaunchKernelGGL(k_seed_order, dim3(G), dim3(BLOCK), 0, st, g, seeds, map, s_all, by_reach, out, pos);
+    return hipGetLastError();
+}
+
+hipError_t launch_sig_regroup(const uint64_t *sig, int64_t n, int Wg, int Wout, int s_all, int sg, const int32_t *cur,
+                              const int32_t *pos, const int32_t *node_graph, uint64_t *out, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_sig_regroup, dim3(fill_grid(n * Wout)), dim3(BLOCK), 0, st, sig, n, Wg, Wout, s_all, sg, cur,
+                       pos, node_graph, out);
+    return hipGetLastError();
+}
+
 // Seed bit i of graph g goes to node seeds[g*s + i] (Algorithm 1's
 // initialisation).  Bits are gathered in the accumulator first so that a node
 // holding several seeds is listed once; the round-0 commit writes them.  A
 // seed outside its graph's node range is skipped and flagged.
 // map (may be NULL): input id -> stored id for ids in [0, n), -1 otherwise.
+// seeds: the group's first seed of graph 0 (graph gi's at gi * s_all).
 template <int W>
 PP_DEV void phase_seed_scatter(const GraphDev &g, const RunDev &R, const int32_t *seeds, const int32_t *map,
-                               int64_t total, int bid, int nb) {
+                               int bid, int nb) {
+    const int64_t total = (int64_t)R.G * R.s;
     for (int64_t j = bid * (int64_t)BLOCK + threadIdx.x; j < total; j += (int64_t)nb * BLOCK) {
         const int i = (int)(j % R.s);
         const int gi = (int)(j / R.s);
-        int32_t x = seeds[j];
+        int32_t x = seeds[(int64_t)gi * R.s_all + i];
         if (map) x = (x >= 0 && x < g.n) ? map[x] : -1;
         const bool ok = x >= g.node_off[gi] && x < g.node_off[gi + 1];
         if (!ok) atomicOr(&R.ctrl->bad_seed, 1);
@@ -429,9 +554,10 @@ PP_DEV void phase_seed_scatter(const GraphDev &g, const RunDev &R, const int32_t
     }
 }
 template <int W>
-__global__ void __launch_bounds__(BLOCK) k_seed_scatter(GraphDev g, RunDev R, const int32_t *seeds,
-                                                        const int32_t *map, int64_t total) {
-    phase_seed_scatter<W>(g, R, seeds, map, total, blockIdx.x, gridDim.x);
+__global__ void __launch_bounds__(BLOCK) k_seed_scatter(GraphDev g, RunDev R0, const int32_t *seeds,
+                                                        const int32_t *map) {
+    const RunDev R = group_view(R0, blockIdx.y);
+    phase_seed_scatter<W>(g, R, seeds + (int64_t)blockIdx.y * R0.sg, map, blockIdx.x, gridDim.x);
 }
 
 // ---------------------------------------------------------------- list commit
@@ -1148,7 +1274,7 @@ PP_DEV void phase_push(const GraphDev &g, const RunDev &R, int bid, int nb) {
     uint64_t *sig = sel(R.sig, CTL(C->cur));
     const int32_t cnt = CTL(C->lst[pp].nodes);
     const int32_t nch = CTL(C->lst[pp].chunks);
-    const bool filter = FLAT && cnt >= PUSH_FILTER_MIN;
+    const bool filter = FLAT && (CTL(C->flat) & 1);   // the round's tiling of the frontier's arcs
     const int32_t *ids = sel(R.f_ids, pp);
     const uint64_t *dl = sel(R.f_delta, pp);
     const int ln = lane_id();
@@ -1315,11 +1441,99 @@ PP_DEV void sched_features(const GraphDev &g, const RunDev &R, int r, int mode, 
     f[7] = mode == MODE_PULL ? 1.0f : 0.0f;
 }
 
-// MLP inference by one wave: lane j < 32 computes hidden unit j of each layer;
-// the hidden values move between lanes by shuffles.  Returns the direction
-// with the smaller predicted time, or `fallback` if a prediction is not
-// finite.  The whole wave must call.
-PP_DEV int32_t mlp_decide(const float *w, const float (&f)[MLP_IN], int32_t fallback) {
+// The cost model's actions a run may take: dense pull always; the pushes
+// unless sparse rounds must be sparse pulls; the sparse pull when the run
+// launches its kernel (the per-round engine with sparse_pull 1 or 2).
+PP_DEV uint32_t allowed_actions(const RunDev &R, bool direct_only) {
+    uint32_t a = 1u;
+    if (R.sparse_pull != 1) a |= direct_only ? 2u : 6u;
+    if (R.sparse_pull != 0 && !direct_only) a |= 8u;
+    return a;
+}
+
+// MLP inference for the closing launch of a round, where it lies on the path
+// from one round to the next: every weight is loaded ahead into the threads
+// that use it (the loads overlap the round's sums), layer 1 takes the whole
+// block of BLOCK = 256 threads (thread t: hidden unit t / 8, input t % 8, a
+// reduction over 8 lanes) and hands over through LDS with one barrier, and
+// one wave takes layers 2 and 3 without further barriers: lane j sums half of
+// hidden unit j % 32's inputs (j < 32 the first 16, else the last 16, read as
+// LDS broadcasts) and the halves meet by one shuffle; then lane j takes
+// output j / 16 over hidden units 2 (j % 16) and 2 (j % 16) + 1 (shuffled in)
+// and 16 lanes reduce each output.
+static_assert(BLOCK == 256 && MLP_IN == 8 && MLP_HID == 32 && MLP_OUT == 4, "block inference layout");
+struct MlpThread {
+    float w1, b1;       // layer 1: unit t / 8, input t % 8
+    float w2[16], b2;   // wave 0, lane j: unit j % 32, inputs 16 (j / 32) .. + 15
+    float w3[2], b3;    // wave 0, lane j: output j / 16, hidden units 2 (j % 16), + 1
+};
+
+PP_DEV void mlp_load_block(const float *w, MlpThread &m) {
+    const int t = threadIdx.x;
+    m.w1 = w[MLP_W1 + (t >> 3) * MLP_IN + (t & 7)];
+    m.b1 = w[MLP_B1 + (t >> 3)];
+    if (t < 64) {
+        const int jj = t & 31, h0 = 16 * (t >> 5);
+#pragma unroll
+        for (int u = 0; u < 16; ++u) m.w2[u] = w[MLP_W2 + jj * MLP_HID + h0 + u];
+        m.b2 = w[MLP_B2 + jj];
+        const int k = t >> 4, i0 = 2 * (t & 15);
+        m.w3[0] = w[MLP_W3 + k * MLP_HID + i0];
+        m.w3[1] = w[MLP_W3 + k * MLP_HID + i0 + 1];
+        m.b3 = w[MLP_B3 + k];
+    }
+}
+
+// Every thread of the block calls; returns the action (as mlp_decide) in every thread.
+PP_DEV int32_t mlp_eval_block(const MlpThread &m, const float (&f)[MLP_IN], uint32_t allow) {
+    __shared__ float s_h1[MLP_HID];
+    __shared__ int32_t s_act;
+    const int t = threadIdx.x, q = t & 7;
+    float fq = f[0];
+#pragma unroll
+    for (int i = 1; i < MLP_IN; ++i) fq = q == i ? f[i] : fq;   // input q, without indexing a register array
+    float p = m.w1 * fq;
+    p += __shfl_xor(p, 1);
+    p += __shfl_xor(p, 2);
+    p += __shfl_xor(p, 4);
+    if (q == 0) s_h1[t >> 3] = fmaxf(p + m.b1, 0.0f);
+    __syncthreads();
+    if (t < 64) {
+        const int h0 = 16 * (t >> 5);
+        float h = 0.0f;
+#pragma unroll
+        for (int u = 0; u < 16; ++u) h += m.w2[u] * s_h1[h0 + u];
+        h += __shfl_xor(h, 32);
+        const float h2 = fmaxf(h + m.b2, 0.0f);   // lanes j and j + 32 hold hidden unit j % 32
+        const int i0 = 2 * (t & 15);
+        float o = m.w3[0] * __shfl(h2, i0) + m.w3[1] * __shfl(h2, i0 + 1);
+#pragma unroll
+        for (int d = 1; d < 16; d <<= 1) o += __shfl_xor(o, d);
+        o += m.b3;   // lanes 16 k .. 16 k + 15 hold output k
+        int32_t best = -1;
+        float bo = 0.0f;
+#pragma unroll
+        for (int a = 0; a < MLP_OUT; ++a) {
+            const float oa = __shfl(o, 16 * a);
+            if (!((allow >> a) & 1u) || best == -2) continue;
+            if (!__builtin_isfinite(oa)) {
+                best = -2;
+                continue;
+            }
+            if (best < 0 || oa < bo) {
+                best = a;
+                bo = oa;
+            }
+        }
+        if (t == 0) s_act = best < 0 ? -1 : best;
+    }
+    __syncthreads();
+    return s_act;
+}
+
+// The same inference with the weights read where they are used (few
+// registers: for the kernels that keep their footprint small).
+PP_DEV int32_t mlp_decide(const float *w, const float (&f)[MLP_IN], uint32_t allow) {
     const int j = lane_id();
     const int jj = j & (MLP_HID - 1);
     float h1 = w[MLP_B1 + jj];
@@ -1329,26 +1543,69 @@ PP_DEV int32_t mlp_decide(const float *w, const float (&f)[MLP_IN], int32_t fall
     float h2 = w[MLP_B2 + jj];
     for (int i = 0; i < MLP_HID; ++i) h2 += w[MLP_W2 + jj * MLP_HID + i] * __shfl(h1, i);
     h2 = h2 > 0.0f ? h2 : 0.0f;
-    const int k = j & 1;
+    const int k = j & (MLP_OUT - 1);
     float o = w[MLP_B3 + k];
     for (int i = 0; i < MLP_HID; ++i) o += w[MLP_W3 + k * MLP_HID + i] * __shfl(h2, i);
-    const float o0 = __shfl(o, 0), o1 = __shfl(o, 1);
-    if (!__builtin_isfinite(o0) || !__builtin_isfinite(o1)) return fallback;
-    return o0 <= o1 ? MODE_PULL : MODE_PUSH;
+    int32_t best = -1;
+    float bo = 0.0f;
+    for (int a = 0; a < MLP_OUT; ++a) {
+        const float oa = __shfl(o, a);
+        if (!((allow >> a) & 1u)) continue;
+        if (!__builtin_isfinite(oa)) return -1;
+        if (best < 0 || oa < bo) {
+            best = a;
+            bo = oa;
+        }
+    }
+    return best;
+}
+
+// The direction and frontier tiling of the next round from a cost-model
+// action (>= 0), else from the fixed rule: `fallback` (pull or push, turned
+// into a sparse pull as the run's option asks) with the threshold's tiling.
+// Returns the mode; *flat receives the control block's tiling bits.
+PP_DEV int32_t take_action(const RunDev &R, int32_t round, int32_t action, int32_t fallback, bool heur_flat,
+                           bool direct_only, int32_t *flat) {
+    const int32_t hf = heur_flat && !direct_only ? 1 : 0;
+    int32_t mode;
+    int32_t f = hf;
+    switch (action) {
+        case 0: mode = MODE_PULL; break;
+        case 1: mode = MODE_PUSH; f = 0; break;
+        case 2: mode = MODE_PUSH; f = direct_only ? 0 : 1; break;
+        case 3: mode = MODE_SPULL; break;
+        default: mode = sparse_dir(R, round, fallback); break;
+    }
+    *flat = f | (hf << 1);
+    return mode;
 }
 
 // nparts: blocks of the pull that left per-block partials.  parts/npost:
 // the closing launch's per-block partials (new bits, hub nodes, arcs), or
-// NULL when its blocks added into the control block instead.
+// NULL when its blocks added into the control block instead.  direct_only:
+// the caller's pushes walk direct slots only (the persistent loop).
+// INFER: how the cost model (a run under PP_SCHED_MLP) is evaluated:
+// INFER_WAVE by one wave, weights read where used (few registers: the
+// initialisation, the persistent loop); INFER_BLOCK by the whole block,
+// weights loaded before the sums (the per-round engine's closing launch);
+// INFER_NONE for callers whose run does not use the model.
+enum { INFER_WAVE = 0, INFER_BLOCK = 1, INFER_NONE = 2 };
+template <int INFER = INFER_WAVE>
 PP_DEV void phase_round_end(const GraphDev &g, const RunDev &R, int init, int nparts, const int64_t *parts = nullptr,
-                            int npost = 0) {
+                            int npost = 0, bool direct_only = false) {
     Ctrl *C = R.ctrl;
     const int r = init ? 0 : CTL(C->round);
     const int mode = init ? MODE_INIT : CTL(C->mode);
     __shared__ long long s_red4[4][BLOCK / 64];
     __shared__ int s_active;
     __shared__ int s_next;
-    // every control-block value the end needs, loaded up front
+    // every control-block value the end needs, loaded up front, and the
+    // scheduler's inputs: the cost model's weights (first wave) or the plan's
+    // next action
+    const bool use_mlp = R.sched == PP_SCHED_MLP;
+    MlpThread mw;
+    if (INFER == INFER_BLOCK && use_mlp) mlp_load_block(R.mlp, mw);
+    const int32_t planned = (R.sched == PP_SCHED_PLAN && r + 1 < R.cap) ? R.plan[r + 1] : -1;
     const long long hub_cnt = CTL(C->hub_cnt), hub_nodes = CTL(C->hub_nodes), hub_arcs = CTL(C->hub_arcs);
     const long long lst_count = CTL(C->lst[r & 1].nodes), lst_arcs = CTL(C->f_arcs[r & 1]);
     const long long prev_arcs = CTL(C->f_arcs[(r - 1) & 1]);
@@ -1421,14 +1678,21 @@ PP_DEV void phase_round_end(const GraphDev &g, const RunDev &R, int init, int np
     float f[MLP_IN];
     sched_features(g, R, r + 1, mode, fnodes, farcs, cnt, reached, last, f);
     const int32_t fallback = schedule(g, R, r + 1, fnodes, farcs);
-    if (threadIdx.x < 64) {
-        const int32_t d = R.sched == PP_SCHED_MLP ? mlp_decide(R.mlp, f, fallback) : fallback;
-        if (threadIdx.x == 0) s_next = d;
+    const uint32_t allow = allowed_actions(R, direct_only);
+    if (INFER == INFER_BLOCK && use_mlp) {
+        const int32_t a = mlp_eval_block(mw, f, allow);   // the whole block
+        if (threadIdx.x == 0) s_next = a;
+    } else if (threadIdx.x < 64) {
+        int32_t a = (INFER == INFER_WAVE && use_mlp) ? mlp_decide(R.mlp, f, allow) : -1;
+        if (R.sched == PP_SCHED_PLAN)   // a given plan (outside its actions: the heuristic)
+            a = (planned >= 0 && planned < MLP_OUT && ((allow >> planned) & 1u)) ? planned : -1;
+        if (threadIdx.x == 0) s_next = a;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
+        if (r < R.cap) R.phase_log[(int64_t)r * 3 + 2] = (int64_t)wall_clock64();   // the round's end
         C->acc_pending = 1;   // a state for the per-node sums
-        R.mode_log[r] = mode;
+        R.mode_log[r] = (mode == MODE_PUSH && !direct_only && (CTL(C->flat) & 1)) ? MODE_PUSH_FLAT : mode;
         R.arcs_log[r] = mode == MODE_PULL ? pulled : (mode == MODE_INIT ? 0 : prev_arcs);
         // the arcs of the nodes changed in this round: a following push's work
         if (mode == MODE_PULL || parts) C->f_arcs[r & 1] = farcs;
@@ -1456,7 +1720,9 @@ PP_DEV void phase_round_end(const GraphDev &g, const RunDev &R, int init, int np
             C->lst[q].nodes = 0;
             C->lst[q].chunks = 0;
             C->f_arcs[q] = 0;
-            C->mode = sparse_dir(R, nr, s_next);
+            int32_t fl = 0;
+            C->mode = take_action(R, nr, s_next, fallback, fnodes >= PUSH_FILTER_MIN, direct_only, &fl);
+            C->flat = fl;
             C->round = nr;
         }
     }
@@ -1466,7 +1732,8 @@ PP_DEV void phase_round_end(const GraphDev &g, const RunDev &R, int init, int np
 // ---------------------------------------------------------------- kernels
 
 // One launch per phase; a phase whose direction is not the round's returns.
-template <int W> __global__ void __launch_bounds__(BLOCK) k_push_commit(GraphDev g, RunDev R, int init) {
+template <int W> __global__ void __launch_bounds__(BLOCK) k_push_commit(GraphDev g, RunDev R0, int init) {
+    const RunDev R = group_view(R0, blockIdx.y);
     if (R.ctrl->converged || (!init && R.ctrl->mode != MODE_PUSH)) return;
     phase_push_commit<W>(g, R, init, blockIdx.x, gridDim.x);
 }
@@ -1477,9 +1744,14 @@ template <int W> __global__ void __launch_bounds__(BLOCK) k_push_commit(GraphDev
 constexpr int FRONTIER_BLOCKS = 1024;
 template <int W, int KK>
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(W >= 8 ? 2 : PP_PULL_WAVES)))
-k_pull(GraphDev g, RunDev R) {
+k_pull(GraphDev g, RunDev R0) {
+    const RunDev R = group_view(R0, blockIdx.y);
     const Ctrl *C = R.ctrl;
     if (C->converged) return;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {   // the round's start: its first launch's first block
+        const int r = C->round;
+        if (r < R.cap) R.phase_log[(int64_t)r * 3] = (int64_t)wall_clock64();
+    }
     if (C->mode == MODE_PULL) {
         phase_pull<W, KK>(g, R, blockIdx.x, gridDim.x);
     } else if (C->prev_mode == MODE_PULL && blockIdx.x < FRONTIER_BLOCKS) {
@@ -1487,17 +1759,20 @@ k_pull(GraphDev g, RunDev R) {
         phase_frontier<W, 1024>(g, R, blockIdx.x, nb);
     }
 }
-template <int W> __global__ void __launch_bounds__(BLOCK) k_push(GraphDev g, RunDev R) {
+template <int W> __global__ void __launch_bounds__(BLOCK) k_push(GraphDev g, RunDev R0) {
+    const RunDev R = group_view(R0, blockIdx.y);
     if (R.ctrl->converged || R.ctrl->mode != MODE_PUSH) return;
     phase_push<W>(g, R, blockIdx.x, gridDim.x);
 }
 // The sparse pull's kernel, apart from the push's so that a run that never
 // takes it keeps the push kernel's smaller register and LDS footprint.
-template <int W> __global__ void __launch_bounds__(BLOCK) k_spull(GraphDev g, RunDev R) {
+template <int W> __global__ void __launch_bounds__(BLOCK) k_spull(GraphDev g, RunDev R0) {
+    const RunDev R = group_view(R0, blockIdx.y);
     if (R.ctrl->converged || R.ctrl->mode != MODE_SPULL) return;
     phase_push<W, true, true>(g, R, blockIdx.x, gridDim.x);
 }
-__global__ void __launch_bounds__(BLOCK) k_round_end(GraphDev g, RunDev R, int init) {
+__global__ void __launch_bounds__(BLOCK) k_round_end(GraphDev g, RunDev R0, int init) {
+    const RunDev R = group_view(R0, blockIdx.y);
     if (R.ctrl->converged) return;
     phase_round_end(g, R, init, g.pull_grid);
 }
@@ -1506,9 +1781,9 @@ __global__ void __launch_bounds__(BLOCK) k_round_end(GraphDev g, RunDev R, int i
 // block's barriers order them; its global writes are visible to its own
 // threads after a barrier).
 template <int W>
-__global__ void __launch_bounds__(BLOCK) k_seed_init(GraphDev g, RunDev R, const int32_t *seeds, const int32_t *map,
-                                                     int64_t total) {
-    phase_seed_scatter<W>(g, R, seeds, map, total, 0, 1);
+__global__ void __launch_bounds__(BLOCK) k_seed_init(GraphDev g, RunDev R0, const int32_t *seeds, const int32_t *map) {
+    const RunDev R = group_view(R0, blockIdx.y);
+    phase_seed_scatter<W>(g, R, seeds + (int64_t)blockIdx.y * R0.sg, map, 0, 1);
     __syncthreads();
     phase_push_commit<W>(g, R, 1, 0, 1);
     __syncthreads();
@@ -1540,7 +1815,8 @@ PP_DEV bool last_block(int32_t *tickets, int bid, int nb) {
 // hub totals) and is read back with atomic loads; a block takes its ticket
 // only after its own memory operations have completed (a workgroup-scope
 // release waits for them without writing back the caches).
-template <int W> __global__ void __launch_bounds__(BLOCK) k_post(GraphDev g, RunDev R) {
+template <int W, bool MLP> __global__ void __launch_bounds__(BLOCK) k_post(GraphDev g, RunDev R0) {
+    const RunDev R = group_view(R0, blockIdx.y);
     Ctrl *C = R.ctrl;
     if (CTL(C->converged)) {   // set only by the last block, after every block has finished
         if (blockIdx.x == 0 && threadIdx.x == 0) PUT(C->acc_pending, 0);   // no round ran in this slot
@@ -1556,7 +1832,7 @@ template <int W> __global__ void __launch_bounds__(BLOCK) k_post(GraphDev g, Run
     __syncthreads();
     if (!s_last) return;
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-    phase_round_end(g, R, 0, g.pull_grid, R.post_part, (int)gridDim.x);
+    phase_round_end<MLP ? INFER_BLOCK : INFER_NONE>(g, R, 0, g.pull_grid, R.post_part, (int)gridDim.x);
 }
 
 // Per-node sums for reach and distance statistics: after the initialisation
@@ -1564,7 +1840,8 @@ template <int W> __global__ void __launch_bounds__(BLOCK) k_post(GraphDev g, Run
 // signature.  A seed bit that u gains at round d stays, so over the states
 // 0..E it is counted E - d + 1 times, and sum_i d(u, x_i) = (E + 1) reached(u)
 // - sum (see k_node_stats).
-template <int W> __global__ void __launch_bounds__(BLOCK) k_node_acc(GraphDev g, RunDev R) {
+template <int W> __global__ void __launch_bounds__(BLOCK) k_node_acc(GraphDev g, RunDev R0) {
+    const RunDev R = group_view(R0, blockIdx.y);
     Ctrl *C = R.ctrl;
     if (!CTL(C->acc_pending)) return;
     const uint64_t *sig = sel(R.sig, CTL(C->cur));
@@ -1595,21 +1872,25 @@ hipError_t launch_node_stats(const uint64_t *sig, const int64_t *acc, int64_t n,
 // New cost-model weights for a run in progress: the direction of the round
 // about to run was taken at the end of the last one, so take it again from
 // the features saved in each live control block (one wave per block).
-__global__ void __launch_bounds__(64) k_redecide(RunDev R, int nctrl) {
-    Ctrl *C = R.ctrl + blockIdx.x;
+__global__ void __launch_bounds__(64) k_redecide(RunDev R, int nctrl, int stride) {
+    Ctrl *C = R.ctrl + (int64_t)blockIdx.x * stride;
     if ((int)blockIdx.x >= nctrl || R.sched != PP_SCHED_MLP) return;
     const int32_t mode = CTL(C->mode);
     if (CTL(C->round) < 1 || CTL(C->converged) || mode == MODE_INIT) return;
     float f[MLP_IN];
 #pragma unroll
     for (int i = 0; i < MLP_IN; ++i) f[i] = C->feat[i];
-    const int32_t d = mlp_decide(R.mlp, f, mode == MODE_PULL ? MODE_PULL : MODE_PUSH);
-    if (threadIdx.x == 0) C->mode = sparse_dir(R, CTL(C->round), d);
+    const int32_t a = mlp_decide(R.mlp, f, allowed_actions(R, false));
+    if (threadIdx.x == 0 && a >= 0) {
+        int32_t fl = 0;
+        C->mode = take_action(R, CTL(C->round), a, MODE_PUSH, (CTL(C->flat) >> 1) & 1, false, &fl);
+        C->flat = fl;
+    }
 }
 
-hipError_t launch_redecide(const RunDev &R, int nctrl, hipStream_t st) {
+hipError_t launch_redecide(const RunDev &R, int nctrl, int stride, hipStream_t st) {
     if (nctrl <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_redecide, dim3(nctrl), dim3(64), 0, st, R, nctrl);
+    hipLaunchKernelGGL(k_redecide, dim3(nctrl), dim3(64), 0, st, R, nctrl, stride);
     return hipGetLastError();
 }
 
@@ -1681,7 +1962,7 @@ PP_DEV void cluster_view(const GraphDev &g, const RunDev &R, const Cluster &cl, 
     rv.ctrl = R.ctrl + cl.g;
     rv.bar = R.bar + cl.g;
     rv.counts = R.counts + cl.g;
-    rv.seed_counts = R.seed_counts ? R.seed_counts + (int64_t)cl.g * R.s : nullptr;
+    rv.seed_counts = R.seed_counts ? R.seed_counts + (int64_t)cl.g * R.sg : nullptr;
     rv.D = R.D + cl.g;
     rv.gconv = R.gconv + cl.g;
     rv.mode_log = R.mode_log + (int64_t)cl.g * R.cap;
@@ -1744,7 +2025,7 @@ __global__ void __launch_bounds__(BLOCK) k_batch(GraphDev g, RunDev R, const Clu
     if (CTL(C->round) == 0 && !CTL(C->converged)) {
         phase_push_commit<W, 1>(gv, rv, 1, bid, nb);
         ok = cluster_barrier(bar, bid, nb);
-        if (ok && bid == 0) phase_round_end(gv, rv, 1, nb);
+        if (ok && bid == 0) phase_round_end(gv, rv, 1, nb, nullptr, 0, true);
         if (ok) ok = cluster_barrier(bar, bid, nb);
     }
     while (ok) {
@@ -1774,7 +2055,7 @@ __global__ void __launch_bounds__(BLOCK) k_batch(GraphDev g, RunDev R, const Clu
                 if (!cluster_barrier(bar, bid, nb)) break;
             }
         }
-        if (bid == 0) phase_round_end(gv, rv, 0, nb);
+        if (bid == 0) phase_round_end(gv, rv, 0, nb, nullptr, 0, true);
         if (lead && stamp) stamp[2] = (int64_t)wall_clock64();
         if (!cluster_barrier(bar, bid, nb)) break;
     }
@@ -1857,16 +2138,17 @@ constexpr int64_t SEED_INIT_ONE_BLOCK = 4096;
 template <int W>
 static hipError_t seed_init_impl(const GraphDev &g, const RunDev &R, const int32_t *seeds, const int32_t *map,
                                  hipStream_t st) {
-    const int64_t total = (int64_t)R.G * R.s;
+    const int64_t total = (int64_t)R.G * R.sg;   // seeds of the largest group
+    const unsigned ng = (unsigned)R.ngroups;
     if (total <= SEED_INIT_ONE_BLOCK) {
-        hipLaunchKernelGGL(k_seed_init<W>, dim3(1), dim3(BLOCK), 0, st, g, R, seeds, map, total);
-        if (R.node_acc) hipLaunchKernelGGL(k_node_acc<W>, dim3(list_grid(g)), dim3(BLOCK), 0, st, g, R);
+        hipLaunchKernelGGL(k_seed_init<W>, dim3(1, ng), dim3(BLOCK), 0, st, g, R, seeds, map);
+        if (R.node_acc) hipLaunchKernelGGL(k_node_acc<W>, dim3(list_grid(g), ng), dim3(BLOCK), 0, st, g, R);
         return hipGetLastError();
     }
-    hipLaunchKernelGGL(k_seed_scatter<W>, dim3(fill_grid(total)), dim3(BLOCK), 0, st, g, R, seeds, map, total);
-    hipLaunchKernelGGL(k_push_commit<W>, dim3(fill_grid(total * W)), dim3(BLOCK), 0, st, g, R, 1);
-    hipLaunchKernelGGL(k_round_end, dim3(1), dim3(BLOCK), 0, st, g, R, 1);
-    if (R.node_acc) hipLaunchKernelGGL(k_node_acc<W>, dim3(list_grid(g)), dim3(BLOCK), 0, st, g, R);
+    hipLaunchKernelGGL(k_seed_scatter<W>, dim3(fill_grid(total), ng), dim3(BLOCK), 0, st, g, R, seeds, map);
+    hipLaunchKernelGGL(k_push_commit<W>, dim3(fill_grid(total * W), ng), dim3(BLOCK), 0, st, g, R, 1);
+    hipLaunchKernelGGL(k_round_end, dim3(1, ng), dim3(BLOCK), 0, st, g, R, 1);
+    if (R.node_acc) hipLaunchKernelGGL(k_node_acc<W>, dim3(list_grid(g), ng), dim3(BLOCK), 0, st, g, R);
     return hipGetLastError();
 }
 
@@ -1878,16 +2160,18 @@ static hipError_t round_impl(const GraphDev &g, const RunDev &R, hipStream_t st,
         const hipError_t e = hipEventRecord(e0, st);
         if (e != hipSuccess) return e;
     }
-    if (R.pull_k == 2) hipLaunchKernelGGL((k_pull<W, 2>), dim3(g.pull_grid), dim3(BLOCK), 0, st, g, R);
-    else hipLaunchKernelGGL((k_pull<W, 0>), dim3(g.pull_grid), dim3(BLOCK), 0, st, g, R);
+    const unsigned ng = (unsigned)R.ngroups;   // every launch covers every seed group (blockIdx.y)
+    if (R.pull_k == 2) hipLaunchKernelGGL((k_pull<W, 2>), dim3(g.pull_grid, ng), dim3(BLOCK), 0, st, g, R);
+    else hipLaunchKernelGGL((k_pull<W, 0>), dim3(g.pull_grid, ng), dim3(BLOCK), 0, st, g, R);
     if (e1) {
         const hipError_t e = hipEventRecord(e1, st);
         if (e != hipSuccess) return e;
     }
-    if (kinds & SPARSE_PUSH) hipLaunchKernelGGL(k_push<W>, dim3(push_grid(g)), dim3(BLOCK), 0, st, g, R);
-    if (kinds & SPARSE_PULL) hipLaunchKernelGGL(k_spull<W>, dim3(push_grid(g)), dim3(BLOCK), 0, st, g, R);
-    hipLaunchKernelGGL(k_post<W>, dim3(post_grid(g)), dim3(BLOCK), 0, st, g, R);
-    if (R.node_acc) hipLaunchKernelGGL(k_node_acc<W>, dim3(list_grid(g)), dim3(BLOCK), 0, st, g, R);
+    if (kinds & SPARSE_PUSH) hipLaunchKernelGGL(k_push<W>, dim3(push_grid(g), ng), dim3(BLOCK), 0, st, g, R);
+    if (kinds & SPARSE_PULL) hipLaunchKernelGGL(k_spull<W>, dim3(push_grid(g), ng), dim3(BLOCK), 0, st, g, R);
+    if (R.sched == PP_SCHED_MLP) hipLaunchKernelGGL((k_post<W, true>), dim3(post_grid(g), ng), dim3(BLOCK), 0, st, g, R);
+    else hipLaunchKernelGGL((k_post<W, false>), dim3(post_grid(g), ng), dim3(BLOCK), 0, st, g, R);
+    if (R.node_acc) hipLaunchKernelGGL(k_node_acc<W>, dim3(list_grid(g), ng), dim3(BLOCK), 0, st, g, R);
     return hipGetLastError();
 }
 

@@ -20,8 +20,9 @@ LIB_PATH = os.path.join(_PKG, "libpp.so")
 
 PP_OK, PP_EINVAL, PP_ERANGE, PP_ENOMEM, PP_EDEVICE, PP_ENOTCONV, PP_ESTATE = 0, -1, -2, -3, -4, -5, -6
 PP_UNDIRECTED, PP_INPUT_ON_DEVICE, PP_TRANSPOSE, PP_KEEP_ORDER = 1, 2, 4, 8
-PP_SCHED_HEURISTIC, PP_SCHED_PULL, PP_SCHED_PUSH, PP_SCHED_FUZZ, PP_SCHED_MLP = 0, 1, 2, 3, 4
-MODE_PULL, MODE_PUSH, MODE_INIT, MODE_SPULL = 0, 1, 2, 3   # entries of the per-round mode log
+PP_SCHED_HEURISTIC, PP_SCHED_PULL, PP_SCHED_PUSH, PP_SCHED_FUZZ, PP_SCHED_MLP, PP_SCHED_PLAN = 0, 1, 2, 3, 4, 5
+PP_GROUPS_BY_REACH, PP_ORDER_BY_REACH = -1, 1
+MODE_PULL, MODE_PUSH, MODE_INIT, MODE_SPULL, MODE_PUSH_FLAT = 0, 1, 2, 3, 4   # entries of the per-round mode log
 _NAMES = {0: "PP_OK", -1: "PP_EINVAL", -2: "PP_ERANGE", -3: "PP_ENOMEM", -4: "PP_EDEVICE",
           -5: "PP_ENOTCONV", -6: "PP_ESTATE"}
 
@@ -36,7 +37,8 @@ class Options(ctypes.Structure):
     _fields_ = [("scheduler", ctypes.c_int32), ("seed_counts", ctypes.c_int32), ("max_rounds", ctypes.c_int32),
                 ("rounds_per_sync", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("push_div", ctypes.c_int32),
                 ("fuzz_seed", ctypes.c_uint64), ("time_kernels", ctypes.c_int32), ("persistent", ctypes.c_int32),
-                ("pull_k", ctypes.c_int32), ("node_stats", ctypes.c_int32), ("sparse_pull", ctypes.c_int32)]
+                ("pull_k", ctypes.c_int32), ("node_stats", ctypes.c_int32), ("sparse_pull", ctypes.c_int32),
+                ("seed_groups", ctypes.c_int32), ("seed_order", ctypes.c_int32)]
 
 
 class TuneEntry(ctypes.Structure):
@@ -66,10 +68,11 @@ EXPORTS = ["pp_options_default", "pp_csr_build", "pp_graph_arcs", "pp_graph_node
            "pp_seeds_reset", "pp_get_kernel_times", "pp_run_set_mlp", "pp_get_round_features",
            "pp_time_round", "pp_mlp_forward", "pp_mlp_loss_grad", "pp_mlp_train", "pp_autotune", "pp_exact_counts",
            "pp_propagate_s", "pp_progressive_sample", "pp_get_node_stats", "pp_set_allocator",
-           "pp_propagate_s_noalloc"]
+           "pp_propagate_s_noalloc", "pp_run_groups", "pp_run_group_words", "pp_get_group_log",
+           "pp_run_set_plan", "pp_get_round_times"]
 
-MLP_IN, MLP_HID, MLP_OUT = 8, 32, 2
-MLP_PARAMS = MLP_HID * MLP_IN + MLP_HID + MLP_HID * MLP_HID + MLP_HID + MLP_OUT * MLP_HID + MLP_OUT   # 1410
+MLP_IN, MLP_HID, MLP_OUT = 8, 32, 4
+MLP_PARAMS = MLP_HID * MLP_IN + MLP_HID + MLP_HID * MLP_HID + MLP_HID + MLP_OUT * MLP_HID + MLP_OUT   # 1476
 
 _lib = None
 
@@ -94,6 +97,10 @@ def lib():
         "pp_get_signatures": (ctypes.c_int, [P, P, I32]),
         "pp_get_seed_counts": (ctypes.c_int, [P, P, I32]),
         "pp_run_round": (I32, [P]), "pp_run_words": (I32, [P]),
+        "pp_run_groups": (I32, [P]), "pp_run_group_words": (I32, [P]),
+        "pp_get_group_log": (ctypes.c_int, [P, I32, P, P, I32]),
+        "pp_run_set_plan": (ctypes.c_int, [P, P, I32]),
+        "pp_get_round_times": (ctypes.c_int, [P, P, I32]),
         "pp_get_round_log": (ctypes.c_int, [P, P, P, I32]),
         "pp_run_snapshot": (ctypes.c_int, [P, P]), "pp_run_restore": (ctypes.c_int, [P, P]),
         "pp_run_free": (None, [P]), "pp_graph_free": (None, [P]),
@@ -159,7 +166,7 @@ def _is_device(a) -> bool:
 
 def options(scheduler=PP_SCHED_HEURISTIC, seed_counts=False, max_rounds=0, rounds_per_sync=0,
             use_graph=True, push_div=0, fuzz_seed=0, time_kernels=False, persistent=False, pull_k=0,
-            node_stats=False, sparse_pull=0) -> Options:
+            node_stats=False, sparse_pull=0, seed_groups=0, seed_order=0) -> Options:
     o = Options()
     lib().pp_options_default(ctypes.byref(o))
     o.scheduler = scheduler
@@ -175,6 +182,8 @@ def options(scheduler=PP_SCHED_HEURISTIC, seed_counts=False, max_rounds=0, round
     o.pull_k = int(pull_k)
     o.node_stats = int(bool(node_stats))
     o.sparse_pull = int(sparse_pull)
+    o.seed_groups = int(seed_groups)
+    o.seed_order = int(seed_order)
     return o
 
 
@@ -263,6 +272,14 @@ class Run:
     @property
     def words(self) -> int:
         return int(lib().pp_run_words(self._h))
+
+    @property
+    def groups(self) -> int:
+        return int(lib().pp_run_groups(self._h))
+
+    @property
+    def group_words(self) -> int:
+        return int(lib().pp_run_group_words(self._h))
 
     def free(self):
         if self._h:
@@ -408,6 +425,14 @@ def pp_get_round_log(run: Run, cap: int):
     return mode, arcs
 
 
+def pp_get_group_log(run: Run, group: int, cap: int):
+    """(mode [cap], arcs [cap]) of one seed group of the run."""
+    mode = np.zeros(cap, dtype=np.int32)
+    arcs = np.zeros(cap, dtype=np.int64)
+    _check(lib().pp_get_group_log(run.handle, int(group), _np_ptr(mode), _np_ptr(arcs), int(cap)))
+    return mode, arcs
+
+
 def pp_run_snapshot(run: Run) -> Run:
     h = ctypes.c_void_p()
     _check(lib().pp_run_snapshot(run.handle, ctypes.byref(h)))
@@ -426,11 +451,24 @@ def _f32(a, shape=None):
 
 
 def pp_run_set_mlp(run: Run, params):
-    """Cost-model weights of a PP_SCHED_MLP run ([1410] float32), or None to clear them."""
+    """Cost-model weights of a PP_SCHED_MLP run ([MLP_PARAMS] float32), or None to clear them."""
     if params is None:
         _check(lib().pp_run_set_mlp(run.handle, None))
     else:
         _check(lib().pp_run_set_mlp(run.handle, _np_ptr(_f32(params, (MLP_PARAMS,)))))
+
+
+def pp_run_set_plan(run: Run, plan):
+    """Actions of a PP_SCHED_PLAN run (cost-model action indices per round; -1: the heuristic)."""
+    a = np.ascontiguousarray(plan, dtype=np.int32).reshape(-1)
+    _check(lib().pp_run_set_plan(run.handle, _np_ptr(a) if a.size else None, int(a.size)))
+
+
+def pp_get_round_times(run: Run, cap: int):
+    """Device-clock ms of each round of the last propagation (0 for rounds not run)."""
+    a = np.zeros(cap, dtype=np.float32)
+    _check(lib().pp_get_round_times(run.handle, _np_ptr(a), int(cap)))
+    return a
 
 
 def pp_get_round_features(run: Run, cap: int):
@@ -440,7 +478,8 @@ def pp_get_round_features(run: Run, cap: int):
 
 
 def pp_time_round(run: Run, mode: int):
-    """Runs the next round in direction `mode` (MODE_PULL / MODE_PUSH / MODE_SPULL); returns (features [8], ms).
+    """Runs the next round with action `mode` (MODE_PULL / MODE_PUSH (direct slots) / MODE_PUSH_FLAT /
+    MODE_SPULL); returns (features [8], ms).
 
     MODE_PUSH stands for the run's sparse direction (a sparse pull when the run
     was created with sparse_pull=1)."""
@@ -465,7 +504,7 @@ def pp_mlp_loss_grad(params, x, t):
     t = _f32(t)
     n = int(x.shape[0])
     if t.shape != (n, MLP_OUT) or x.shape != (n, MLP_IN):
-        raise ValueError("x must be [n][8] and t [n][2]")
+        raise ValueError("x must be [n][8] and t [n][4]")
     g = np.zeros(MLP_PARAMS, dtype=np.float32)
     loss = ctypes.c_float(0.0)
     _check(lib().pp_mlp_loss_grad(_np_ptr(p), _np_ptr(x), _np_ptr(t), n, _np_ptr(g), ctypes.byref(loss)))
@@ -479,7 +518,7 @@ def pp_mlp_train(params, x, t, steps: int, lr: float):
     t = _f32(t)
     n = int(x.shape[0])
     if t.shape != (n, MLP_OUT) or x.shape != (n, MLP_IN):
-        raise ValueError("x must be [n][8] and t [n][2]")
+        raise ValueError("x must be [n][8] and t [n][4]")
     log = np.zeros(max(int(steps), 1), dtype=np.float32)
     _check(lib().pp_mlp_train(_np_ptr(p), _np_ptr(x), _np_ptr(t), n, int(steps), float(lr), _np_ptr(log)))
     return p, log[:int(steps)]

@@ -29,7 +29,7 @@ def test_every_declared_symbol_is_exported():
 
 
 def test_struct_layouts_match_header():
-    assert ctypes.sizeof(pp.Options) == 56
+    assert ctypes.sizeof(pp.Options) == 64
     assert ctypes.sizeof(pp.TuneEntry) == 6 * 4
     assert ctypes.sizeof(pp.Progress) == 4 * 4 + 3 * 8
     assert ctypes.sizeof(pp.Metrics) == 4 + 4 + 8 + 6 * 8
@@ -126,13 +126,13 @@ def test_metrics_argument_errors():
 
 def test_cost_model_layout_and_argument_errors():
     text = open(os.path.join(ROOT, "include", "pp.h")).read()
-    assert int(re.search(r"#define PP_MLP_PARAMS (\d+)", text).group(1)) == pp.MLP_PARAMS == 1410
+    assert int(re.search(r"#define PP_MLP_PARAMS (\d+)", text).group(1)) == pp.MLP_PARAMS == 1476
     L = pp.lib()
     ptr = lambda a: a.ctypes.data_as(ctypes.c_void_p)
     p = np.zeros(pp.MLP_PARAMS, np.float32)
     x = np.zeros((4, 8), np.float32)
-    t = np.zeros((4, 2), np.float32)
-    y = np.zeros((4, 2), np.float32)
+    t = np.zeros((4, pp.MLP_OUT), np.float32)
+    y = np.zeros((4, pp.MLP_OUT), np.float32)
     assert L.pp_run_set_mlp(None, None) == pp.PP_EINVAL
     assert L.pp_time_round(None, 0, None, None) == pp.PP_EINVAL
     assert L.pp_get_round_features(None, None, 1) == pp.PP_EINVAL
