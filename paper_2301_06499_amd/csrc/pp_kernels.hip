@@ -1790,20 +1790,28 @@ __global__ void __launch_bounds__(BLOCK) k_seed_init(GraphDev g, RunDev R0, cons
     phase_round_end(g, R, 1, g.pull_grid);
 }
 
-// Two-level ticket (one thread per block): true for the block that finishes
-// last.  Blocks count off in groups of TICKET_GROUP, each group on its own
-// cache line, and the last block of each group counts off at the top, so no
-// address takes more than TICKET_GROUP atomics.  Whoever completes a counter
-// resets it for the next launch.
+// Two-level ticket (one thread per block, after a block barrier): true for
+// the block that finishes last.  Blocks count off in groups of TICKET_GROUP,
+// each group on its own cache line, and the last block of each group counts
+// off at the top, so no address takes more than TICKET_GROUP atomics.  Every
+// count is an agent-scope release, so what the block (and, at the top, the
+// group it closed) wrote is visible before the count that reports it, and the
+// block that completes a counter takes an agent-scope acquire before it reads
+// the others' writes.  A workgroup-scope release is not enough: on CDNA it
+// does not wait for the block's outstanding global stores, which may then
+// reach memory after a later block has already read them.  Whoever completes
+// a counter resets it for the next launch.
 PP_DEV bool last_block(int32_t *tickets, int bid, int nb) {
     const int ngroups = (nb + TICKET_GROUP - 1) / TICKET_GROUP;
     const int gi = bid / TICKET_GROUP;
     const int gsize = nb - gi * TICKET_GROUP < TICKET_GROUP ? nb - gi * TICKET_GROUP : TICKET_GROUP;
     int32_t *gc = tickets + gi * TICKET_STRIDE;
-    if (__hip_atomic_fetch_add(gc, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != gsize - 1) return false;
+    if (__hip_atomic_fetch_add(gc, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT) != gsize - 1) return false;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     __hip_atomic_store(gc, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     int32_t *top = tickets + TICKET_GROUP * TICKET_STRIDE;
-    if (__hip_atomic_fetch_add(top, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != ngroups - 1) return false;
+    if (__hip_atomic_fetch_add(top, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT) != ngroups - 1) return false;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     __hip_atomic_store(top, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     return true;
 }
@@ -1811,10 +1819,9 @@ PP_DEV bool last_block(int32_t *tickets, int bid, int nb) {
 // The closing launch of a round: the list commit of a push round or the
 // high-degree nodes of a pull round, then the round's end, run by the last
 // block to finish.  Everything the round's end reads from the other blocks
-// of this launch was written by device-scope atomics (counts, list sizes,
-// hub totals) and is read back with atomic loads; a block takes its ticket
-// only after its own memory operations have completed (a workgroup-scope
-// release waits for them without writing back the caches).
+// of this launch was written by device-scope atomics (per-block partials,
+// counts, hub totals) and is read back with atomic loads; the block barrier
+// and the ticket's release and acquire order those writes before the reads.
 template <int W, bool MLP> __global__ void __launch_bounds__(BLOCK) k_post(GraphDev g, RunDev R0) {
     const RunDev R = group_view(R0, blockIdx.y);
     Ctrl *C = R.ctrl;
@@ -1826,12 +1833,10 @@ template <int W, bool MLP> __global__ void __launch_bounds__(BLOCK) k_post(Graph
     if (mode == MODE_PULL) phase_pull_hubs<W>(g, R, blockIdx.x, gridDim.x, R.post_part);
     else phase_push_commit<W>(g, R, 0, blockIdx.x, gridDim.x, R.post_part, mode == MODE_SPULL);
     __shared__ int s_last;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __syncthreads();
     if (threadIdx.x == 0) s_last = last_block(R.tickets, (int)blockIdx.x, (int)gridDim.x);
     __syncthreads();
     if (!s_last) return;
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
     phase_round_end<MLP ? INFER_BLOCK : INFER_NONE>(g, R, 0, g.pull_grid, R.post_part, (int)gridDim.x);
 }
 
