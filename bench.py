@@ -62,23 +62,28 @@ def workload(name: str):
     raise SystemExit(f"unknown workload {name}")
 
 
-# workloads whose dense pull launches have counter figures under profiles/
-TRAFFIC_PROFILES = {"rmat20": "k_pull_rmat20_s256", "rmat26": "k_pull_rmat26_s512",
-                    "grid:4096": "k_pull_grid4096_s128"}
+# workloads whose dense pull launches have counter figures under profiles/ (one seed
+# group, and seed groups by reach)
+TRAFFIC_PROFILES = {("rmat20", False): "k_pull_rmat20_s256", ("rmat20", True): "k_pull_rmat20_s256_groups",
+                    ("rmat26", False): "k_pull_rmat26_s512", ("rmat26", True): "k_pull_rmat26_s512_groups",
+                    ("grid:4096", False): "k_pull_grid4096_s128", ("grid:4096", True): "k_pull_grid4096_s128"}
 
 
-def measured_traffic(profile: str):
+def measured_traffic(profile: str, kernel: str):
     """HBM bytes per launch from the committed counter summary, if the kernel is unchanged.
 
     profiles/<profile>_traffic.json holds FETCH_SIZE + WRITE_SIZE per launch
-    (scaled by a copy of known size) and the hash of the kernel sources the
-    counters were taken on; a different hash means the figure is stale.
+    (scaled by a copy of known size), the kernel it covers and the hash of the
+    kernel sources the counters were taken on; another kernel or hash means the
+    figure does not apply.
     """
     import hashlib
     path = os.path.join(ROOT, "profiles", profile + "_traffic.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
+    if rec.get("kernel") != kernel:
+        return None
     csrc = os.path.join(ROOT, "paper_2301_06499_amd", "csrc")
     src = b"".join(open(os.path.join(csrc, f), "rb").read() for f in ("pp_kernels.hip", "pp_internal.h"))
     if hashlib.sha256(src).hexdigest() != rec.get("source_sha256"):
@@ -119,11 +124,20 @@ def bench_batch(args, torch, pp):
             counts, D = step()
         torch.cuda.synchronize()
         engines[name] = ((time.perf_counter() - t0) / args.steps, counts, D)
+        if args.round_log and not persistent:
+            rounds = int(D.max()) + 2
+            write_round_log(args.round_log, pp, run, GB, counts.sum(axis=0), int(D.max()),
+                            [pp.pp_get_group_log(run, 0, rounds + 1)])
         run.free()
         log(f"[bench] batch, {name} engine: {engines[name][0] * 1e3:.2f} ms per step")
     assert all(np.array_equal(engines["union"][1], engines["clustered"][1]) for _ in [0])
     best = min(engines, key=lambda k: engines[k][0])
     t_batch, counts, D = engines[best]
+    if args.no_plain:   # the batched engines only (for profiling them)
+        print(json.dumps({"engines_ms_per_step": {k: round(v[0] * 1000.0, 3) for k, v in engines.items()},
+                          "note": "batched engines only (--no-plain)"}), flush=True)
+        GB.free()
+        return
     # stored arcs per graph, from solo builds (also used by the plain runs)
     solo_graphs, solo_runs, arcs_g = [], [], []
     for g, sd in zip(graphs, seeds):
@@ -429,6 +443,23 @@ def compare(want, idx, counts, sc, sig, D, whole: bool) -> dict:
     return res
 
 
+def write_round_log(path, pp, run, G, counts, D, logs):
+    """Per-round figures of seed group 0 for per-kernel byte models: the direction of
+    each round, the frontier it walked (entries and arcs, from the scheduler's features
+    computed at the end of the round before) and the bits it added."""
+    rounds = D + 2
+    feat = pp.pp_get_round_features(run, rounds + 1)
+    n, m = G.nodes, G.arcs
+    modes, arcs = logs[0]
+    rec = {"n": n, "m": m, "words": run.words, "group_words": run.group_words, "groups": run.groups, "D": D,
+           "rounds": [{"r": r, "mode": int(modes[r]), "arcs": int(arcs[r]),
+                       "entries": int(round(float(feat[r][0]) * n)), "entry_arcs": int(round(float(feat[r][1]) * m)),
+                       "count": int(counts[r]) if r < len(counts) else 0} for r in range(1, rounds)]}
+    os.makedirs(os.path.dirname(os.path.abspath(path)), exist_ok=True)
+    with open(path, "a") as f:
+        f.write(json.dumps(rec) + "\n")
+
+
 def time_propagation(args, torch, pp, G, seeds, opts, stream):
     """K timed steps (seed reset + propagation to convergence, counts on the host) on one
     run, then the same K steps on a second run with HIP events around every pull launch."""
@@ -466,6 +497,8 @@ def time_propagation(args, torch, pp, G, seeds, opts, stream):
     ms_after = pp.pp_get_kernel_times(run_t, cap).astype(np.float64)
     assert int(D_t[0]) == int(D[0]) and list(counts_t[0]) == list(counts[0])
     logs = [pp.pp_get_group_log(run_t, j, cap) for j in range(run.groups)]   # (modes, arcs) per seed group
+    if args.round_log:
+        write_round_log(args.round_log, pp, run_t, G, counts[0], int(D[0]), logs)
     out = {"counts": counts[0], "D": int(D[0]), "elapsed": elapsed, "elapsed_t": elapsed_t, "per_step": per_step,
            "pull_ms": (ms_after - ms_before) / args.steps, "logs": logs, "words": run.words,
            "group_words": run.group_words, "groups": run.groups, "dseeds": dseeds}
@@ -483,6 +516,7 @@ def step_figures(args, pp, T, m, n, s, wl, opts):
       per node: 8 B row offset (int64) + 8Wg B own row read + 8Wg B new row written."""
     rounds = T["D"] + 1
     Wg = T["group_words"]
+    by_reach = bool(opts.seed_groups == pp.PP_GROUPS_BY_REACH)
     nominal = m * (s / 64.0) * rounds
     touched = sum(float(a[1:rounds + 1].sum()) * Wg for _, a in T["logs"])
     pull_rounds, bytes_pull = [], 0.0
@@ -495,8 +529,9 @@ def step_figures(args, pp, T, m, n, s, wl, opts):
     achieved = bytes_pull / t_pull / 1e9 if t_pull > 0 else 0.0
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": (measured_traffic(TRAFFIC_PROFILES[wl]) if (wl in TRAFFIC_PROFILES and T["groups"] == 1 and
-                                                                  not opts.persistent and (opts.pull_k or 4) == 4)
+            "traffic": (measured_traffic(TRAFFIC_PROFILES[(wl, by_reach)], f"k_pull<{Wg}, 0>")
+                        if ((wl, by_reach) in TRAFFIC_PROFILES and not opts.persistent and (opts.pull_k or 4) == 4 and
+                            args.sparse_pull == 0 and args.push_div == 0 and args.scheduler == "heuristic")
                         else None),
             "kernel": f"k_batch<{Wg}> pull phase" if opts.persistent else f"k_pull<{Wg}>",
             "timing": ("device clock between grid barriers" if opts.persistent else
@@ -616,6 +651,11 @@ def main():
                     help="sparse rounds: 0 push, 1 sparse pull, 2 either per round (pseudo-random)")
     ap.add_argument("--delta", type=float, default=0.05, help="progressive: 1 - confidence")
     ap.add_argument("--concurrent", type=int, default=0, help="PROPAGATE-S: seeds in flight (0: min(s, 256))")
+    ap.add_argument("--no-plain", action="store_true",
+                    help="batch64: time the two batched engines only, without the 64 solo runs")
+    ap.add_argument("--round-log", default="", metavar="PATH",
+                    help="append each timed propagation's per-round figures (direction, frontier entries "
+                         "and arcs, new bits; seed group 0) as one JSON line to PATH")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device-to-device with a plain torch copy, so that a "
                          "hardware-counter run has a kernel of known traffic to scale against")

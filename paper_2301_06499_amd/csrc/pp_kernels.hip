@@ -1790,6 +1790,16 @@ __global__ void __launch_bounds__(BLOCK) k_seed_init(GraphDev g, RunDev R0, cons
     phase_round_end(g, R, 1, g.pull_grid);
 }
 
+// Blocks of a closing launch of nb blocks that items (words to commit or
+// combine) keep busy: POST_ITEMS per thread, at least one block.  Blocks
+// without items would only add ticket latency, and more than one item per
+// thread adds serial passes of dependent loads; one item measured best.
+constexpr int POST_ITEMS = 1;
+PP_DEV int post_blocks(int64_t items, int nb) {
+    const int64_t b = (items + (int64_t)BLOCK * POST_ITEMS - 1) / ((int64_t)BLOCK * POST_ITEMS);
+    return b < 1 ? 1 : (b < nb ? (int)b : nb);
+}
+
 // Two-level ticket (one thread per block, after a block barrier): true for
 // the block that finishes last.  Blocks count off in groups of TICKET_GROUP,
 // each group on its own cache line, and the last block of each group counts
@@ -1830,14 +1840,20 @@ template <int W, bool MLP> __global__ void __launch_bounds__(BLOCK) k_post(Graph
         return;
     }
     const int32_t mode = CTL(C->mode);
-    if (mode == MODE_PULL) phase_pull_hubs<W>(g, R, blockIdx.x, gridDim.x, R.post_part);
-    else phase_push_commit<W>(g, R, 0, blockIdx.x, gridDim.x, R.post_part, mode == MODE_SPULL);
+    // the blocks this round's items need (every block reads the same count):
+    // the rest leave at once and take no ticket, so a small round's end does
+    // not wait for the whole grid to count off
+    const int64_t items = mode == MODE_PULL ? (int64_t)g.nhubs * W : (int64_t)CTL(C->lst[CTL(C->round) & 1].nodes) * W;
+    const int nb = post_blocks(items, (int)gridDim.x);
+    if ((int)blockIdx.x >= nb) return;
+    if (mode == MODE_PULL) phase_pull_hubs<W>(g, R, blockIdx.x, nb, R.post_part);
+    else phase_push_commit<W>(g, R, 0, blockIdx.x, nb, R.post_part, mode == MODE_SPULL);
     __shared__ int s_last;
     __syncthreads();
-    if (threadIdx.x == 0) s_last = last_block(R.tickets, (int)blockIdx.x, (int)gridDim.x);
+    if (threadIdx.x == 0) s_last = last_block(R.tickets, (int)blockIdx.x, nb);
     __syncthreads();
     if (!s_last) return;
-    phase_round_end<MLP ? INFER_BLOCK : INFER_NONE>(g, R, 0, g.pull_grid, R.post_part, (int)gridDim.x);
+    phase_round_end<MLP ? INFER_BLOCK : INFER_NONE>(g, R, 0, g.pull_grid, R.post_part, nb);
 }
 
 // Per-node sums for reach and distance statistics: after the initialisation

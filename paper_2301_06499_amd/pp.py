@@ -214,10 +214,11 @@ class Graph:
             lib().pp_graph_free(self._h)
             self._h = None
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
         # at interpreter shutdown the HIP runtime (and a profiler's hooks) may
         # already be going away: leave the memory to the process's end then
-        if sys.is_finalizing():
+        # (the check is bound here: the module's globals may be gone by then)
+        if _finalizing():
             return
         try:
             self.free()
@@ -286,10 +287,11 @@ class Run:
             lib().pp_run_free(self._h)
             self._h = None
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
         # at interpreter shutdown the HIP runtime (and a profiler's hooks) may
         # already be going away: leave the memory to the process's end then
-        if sys.is_finalizing():
+        # (the check is bound here: the module's globals may be gone by then)
+        if _finalizing():
             return
         try:
             self.free()

@@ -62,8 +62,8 @@ class DeviceArray:
             hip().hipFree(self.ptr)
             self.ptr = ctypes.c_void_p()
 
-    def __del__(self):
-        if sys.is_finalizing():
+    def __del__(self, _finalizing=sys.is_finalizing):
+        if _finalizing():   # bound at definition: the module's globals may be gone at exit
             return
         try:
             self.free()
