@@ -106,6 +106,8 @@ def bench_batch(args, torch, pp):
     log(f"[bench] generated the batch in {time.perf_counter() - t0:.1f} s: {len(graphs)} graphs, n={n}")
     stream = torch.cuda.Stream()
     GB = pp.pp_csr_build(n, usrc, udst, node_offsets=offs, stream=stream)
+    torch.cuda.synchronize()
+    calibration_copy(args, torch)
     dseeds = torch.from_numpy(allseeds).to("cuda")
     engines = {}
     for name, persistent in (("clustered", True), ("union", False)):
@@ -460,14 +462,18 @@ def write_round_log(path, pp, run, G, counts, D, logs):
         f.write(json.dumps(rec) + "\n")
 
 
-def time_propagation(args, torch, pp, G, seeds, opts, stream):
+def time_propagation(args, torch, pp, G, seeds, opts, stream, params=None):
     """K timed steps (seed reset + propagation to convergence, counts on the host) on one
-    run, then the same K steps on a second run with HIP events around every pull launch."""
+    run, then the same K steps on a second run with HIP events around every pull launch.
+    params: the cost model's weights, for runs with the learned scheduler."""
     dseeds = torch.from_numpy(seeds.astype(np.int32)).to("cuda")
     run = pp.pp_seeds_init(G, seeds, opts=opts, stream=stream)
     opts_t = pp.Options.from_buffer_copy(opts)
     opts_t.time_kernels = 1
     run_t = pp.pp_seeds_init(G, seeds, opts=opts_t, stream=stream)
+    if params is not None:
+        pp.pp_run_set_mlp(run, params)
+        pp.pp_run_set_mlp(run_t, params)
 
     def step(r):
         pp.pp_seeds_reset(r, dseeds)
@@ -552,7 +558,49 @@ def step_figures(args, pp, T, m, n, s, wl, opts):
                     "modes": modes[0] if len(modes) == 1 else modes}}
 
 
-def propagation_line(args, torch, pp, g, seeds, cfg, wl, sample, stream, base_opts, plain_opts=None):
+def learned_object(args, torch, pp, G, g, seeds, base_opts, stream, T, res):
+    """The same propagation with the learned scheduler: the cost model trained on the
+    round costs of another seed sample of the same graph (every allowed action after
+    both kinds of round, replayed on the ordinary path), then timed on the run's seeds.
+    Also the training table's costs of the fixed rule, the model and the optimal plan."""
+    from paper_2301_06499_amd import inputs, scheduler
+    t0 = time.perf_counter()
+    train_seeds = inputs.sample_seeds(g.n, len(seeds), 7)
+    table = scheduler.measure_replay(G, train_seeds, opts=base_opts, repeats=2, stream=stream)
+    params, loss = scheduler.train(scheduler.label(table), steps=3000)
+    _, opt_ms, opt_plan = scheduler.optimal_schedule(table)
+    heur_ms, heur_plan = scheduler.policy_cost(table, scheduler.heuristic_policy(8, G.nodes))
+    model_ms, model_plan = scheduler.policy_cost(table, scheduler.model_policy(params, table))
+    train_s = time.perf_counter() - t0
+    opts = pp.Options.from_buffer_copy(base_opts)
+    opts.scheduler = pp.PP_SCHED_MLP
+    L = time_propagation(args, torch, pp, G, seeds, opts, stream, params=params)
+    if L["D"] != T["D"] or list(L["counts"]) != list(T["counts"]):
+        raise SystemExit("the learned scheduler's counts differ from the heuristic's")
+    ms = L["elapsed"] * 1000.0 / args.steps
+    code = "PSFQ"
+    out = {"ms_per_step": round(ms, 4), "ms_per_step_median": round(float(np.median(L["per_step"])) * 1000.0, 4),
+           "vs_heuristic_same_groups": round(res["ms_per_step"] / ms, 4),
+           "modes": ["".join({pp.MODE_PULL: "P", pp.MODE_PUSH: "S", pp.MODE_PUSH_FLAT: "F",
+                              pp.MODE_SPULL: "Q"}.get(int(md[r]), "-") for r in range(1, L["D"] + 2))
+                     for md, _ in L["logs"]],
+           "counts": "equal to the heuristic's",
+           "training": {"seeds": "another uniform sample of the same size (sampler seed 7)",
+                        "rounds": len(table), "samples": 2 * len(table) - 1, "final_loss": round(float(loss[-1]), 5),
+                        "seconds": round(train_s, 1),
+                        "table_ms": {"heuristic": round(heur_ms, 3), "model": round(model_ms, 3),
+                                     "optimal": round(opt_ms, 3)},
+                        "plans": {"heuristic": "".join(code[a] for a in heur_plan),
+                                  "model": "".join(code[a] for a in model_plan),
+                                  "optimal": "".join(code[a] for a in opt_plan)}}}
+    if "plain" in res:
+        out["vs_plain"] = round(res["plain"]["ms_per_step"] / ms, 4)
+    log(f"[bench] learned scheduler: {out['ms_per_step']} ms per step (heuristic {res['ms_per_step']})")
+    return out
+
+
+def propagation_line(args, torch, pp, g, seeds, cfg, wl, sample, stream, base_opts, plain_opts=None,
+                     learned=False):
     """Builds the graph, times the propagation (and the plain form beside it when
     plain_opts is given), checks it: one result object.
 
@@ -583,6 +631,8 @@ def propagation_line(args, torch, pp, g, seeds, cfg, wl, sample, stream, base_op
         res["plain"]["note"] = "the same graph and seeds as one group of s seeds, same scheduler"
         res["speedup_vs_plain"] = round(P["elapsed"] / T["elapsed"], 4)
         log(f"[bench] {cfg['workload']}: plain {res['plain']['ms_per_step']} ms per step")
+    if learned:
+        res["learned"] = learned_object(args, torch, pp, G, g, seeds, base_opts, stream, T, res)
     if args.no_check and args.no_cpu_baseline:
         G.free()
         return res
@@ -651,6 +701,9 @@ def main():
                     help="sparse rounds: 0 push, 1 sparse pull, 2 either per round (pseudo-random)")
     ap.add_argument("--delta", type=float, default=0.05, help="progressive: 1 - confidence")
     ap.add_argument("--concurrent", type=int, default=0, help="PROPAGATE-S: seeds in flight (0: min(s, 256))")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="rmat26: skip the learned-scheduler run (cost model trained on another seed sample's "
+                         "replayed round costs)")
     ap.add_argument("--no-plain", action="store_true",
                     help="batch64: time the two batched engines only, without the 64 solo runs")
     ap.add_argument("--round-log", default="", metavar="PATH",
@@ -710,7 +763,9 @@ def main():
     s = len(seeds)
     sample = (np.arange(s) if g.n <= (1 << 22) else
               np.unique(np.linspace(0, s - 1, min(s, args.check_seeds)).astype(np.int64)))
-    head = propagation_line(args, torch, pp, g, seeds, cfg, args.workload, sample, stream, base, plain)
+    head = propagation_line(args, torch, pp, g, seeds, cfg, args.workload, sample, stream, base, plain,
+                            learned=(args.workload == "rmat26" and not args.no_learned and sched == pp.PP_SCHED_HEURISTIC
+                                     and not args.persistent and not args.node_stats))
     head["config"]["tuned"] = tuned
     out = {"metric": METRIC, "value": head["value"], "unit": "edge-words/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": head["ms_per_step"], "ms_per_step_min": head["ms_per_step_min"],
@@ -718,7 +773,7 @@ def main():
            "vs_baseline": None, "dtype": "u64", "data": "synthetic", "config": head["config"],
            "touched_edge_words_per_s": head["touched_edge_words_per_s"], "roofline": head["roofline"],
            "run": head["run"]}
-    for k in ("plain", "speedup_vs_plain", "cpu_baseline", "check"):
+    for k in ("plain", "speedup_vs_plain", "learned", "cpu_baseline", "check"):
         if k in head:
             out[k] = head[k]
     del g

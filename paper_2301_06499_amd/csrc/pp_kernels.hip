@@ -1800,28 +1800,31 @@ PP_DEV int post_blocks(int64_t items, int nb) {
     return b < 1 ? 1 : (b < nb ? (int)b : nb);
 }
 
-// Two-level ticket (one thread per block, after a block barrier): true for
-// the block that finishes last.  Blocks count off in groups of TICKET_GROUP,
-// each group on its own cache line, and the last block of each group counts
-// off at the top, so no address takes more than TICKET_GROUP atomics.  Every
-// count is an agent-scope release, so what the block (and, at the top, the
-// group it closed) wrote is visible before the count that reports it, and the
-// block that completes a counter takes an agent-scope acquire before it reads
-// the others' writes.  A workgroup-scope release is not enough: on CDNA it
-// does not wait for the block's outstanding global stores, which may then
-// reach memory after a later block has already read them.  Whoever completes
-// a counter resets it for the next launch.
+// Waits until every global memory operation this thread issued has been
+// performed (s_waitcnt with vmcnt 0; expcnt 7 and lgkmcnt 15 leave the other
+// counters alone), with compiler fences so that no memory access moves
+// across it.
+PP_DEV void wait_global_ops() {
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0x0F70);
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+// Two-level ticket (one thread per block, after every thread of the block
+// has waited for its global operations and a block barrier): true for the
+// block that finishes last.  Blocks count off in groups of TICKET_GROUP, each
+// group on its own cache line, and the last block of each group counts off
+// at the top, so no address takes more than TICKET_GROUP atomics.  Whoever
+// completes a counter resets it for the next launch.
 PP_DEV bool last_block(int32_t *tickets, int bid, int nb) {
     const int ngroups = (nb + TICKET_GROUP - 1) / TICKET_GROUP;
     const int gi = bid / TICKET_GROUP;
     const int gsize = nb - gi * TICKET_GROUP < TICKET_GROUP ? nb - gi * TICKET_GROUP : TICKET_GROUP;
     int32_t *gc = tickets + gi * TICKET_STRIDE;
-    if (__hip_atomic_fetch_add(gc, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT) != gsize - 1) return false;
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (__hip_atomic_fetch_add(gc, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != gsize - 1) return false;
     __hip_atomic_store(gc, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     int32_t *top = tickets + TICKET_GROUP * TICKET_STRIDE;
-    if (__hip_atomic_fetch_add(top, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT) != ngroups - 1) return false;
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (__hip_atomic_fetch_add(top, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != ngroups - 1) return false;
     __hip_atomic_store(top, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     return true;
 }
@@ -1830,8 +1833,15 @@ PP_DEV bool last_block(int32_t *tickets, int bid, int nb) {
 // high-degree nodes of a pull round, then the round's end, run by the last
 // block to finish.  Everything the round's end reads from the other blocks
 // of this launch was written by device-scope atomics (per-block partials,
-// counts, hub totals) and is read back with atomic loads; the block barrier
-// and the ticket's release and acquire order those writes before the reads.
+// counts, hub totals), which are coherent across the XCDs' L2 caches once
+// performed, and is read back with device-scope atomic loads.  So each thread
+// waits for its own global operations to be performed before the block
+// counts off; the block barrier alone would not wait for them (a workgroup
+// release emits no such wait on CDNA), and the last block could read a
+// partial of the previous round.  An agent-scope release would also write
+// back every dirty L2 line, which this launch's plain writes (rows, deltas,
+// lists) need only at the launch boundary: up to 12 us per round on large
+// commits.
 template <int W, bool MLP> __global__ void __launch_bounds__(BLOCK) k_post(GraphDev g, RunDev R0) {
     const RunDev R = group_view(R0, blockIdx.y);
     Ctrl *C = R.ctrl;
@@ -1849,6 +1859,7 @@ template <int W, bool MLP> __global__ void __launch_bounds__(BLOCK) k_post(Graph
     if (mode == MODE_PULL) phase_pull_hubs<W>(g, R, blockIdx.x, nb, R.post_part);
     else phase_push_commit<W>(g, R, 0, blockIdx.x, nb, R.post_part, mode == MODE_SPULL);
     __shared__ int s_last;
+    wait_global_ops();
     __syncthreads();
     if (threadIdx.x == 0) s_last = last_block(R.tickets, (int)blockIdx.x, nb);
     __syncthreads();
