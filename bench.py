@@ -196,12 +196,14 @@ def bench_grid(args, torch, pp):
     """Large-diameter grid with the learned direction scheduler vs the fixed heuristic.
 
     The cost model is trained on this method's own round timings: every round
-    of two training graphs (same family, other generator seeds) is timed in
-    both directions after both kinds of previous round, the best schedule of
-    each is solved exactly, and the model is fitted to the resulting per-round
-    direction costs by the library's device training kernels.  The held-out
-    graph (generator seed 1) is then run to convergence with the heuristic and
-    with the model; both give the same counts (checked here).
+    of two training graphs (same family, other generator seeds) is priced under
+    every action after both kinds of previous round by replaying fixed plans on
+    the ordinary path, the best schedule of each is solved exactly, and the
+    model is fitted to the resulting per-round action costs by the library's
+    device training kernels.  The held-out graph (generator seed 1) is then run
+    to convergence with the heuristic, the model, the heuristic at its
+    autotuned threshold and the optimal plan of its own measured costs; all
+    give the same counts (checked here).
     """
     from paper_2301_06499_amd import inputs
     from paper_2301_06499_amd import scheduler as S
@@ -211,9 +213,9 @@ def bench_grid(args, torch, pp):
     for gs in (2, 3):
         g, sd = inputs.workload_grid_shortcuts(side, 128, gs)
         Gt = pp.pp_csr_build(g.n, g.src, g.dst, undirected=True)
-        tables.append(S.measure(Gt, sd))
+        tables.append(S.measure_replay(Gt, sd, repeats=2))
         Gt.free()
-        log(f"[bench] timed {len(tables[-1])} rounds of training graph {gs} both ways")
+        log(f"[bench] priced {len(tables[-1])} rounds of training graph {gs} under every action")
     samples = S.Samples.concat(S.label(t) for t in tables)
     t0 = time.perf_counter()
     params, losses = S.train(samples, steps=4000)
@@ -221,8 +223,8 @@ def bench_grid(args, torch, pp):
     log(f"[bench] trained on {len(samples)} samples in {t_train:.2f} s, loss {losses[0]:.3f} -> {losses[-1]:.5f}")
     g, seeds = inputs.workload_grid_shortcuts(side, 128, 1)
     G = pp.pp_csr_build(g.n, g.src, g.dst, undirected=True)
-    held = S.measure(G, seeds)
-    _, best_ms, _ = S.optimal_schedule(held)
+    held = S.measure_replay(G, seeds, repeats=2)
+    _, best_ms, best_plan = S.optimal_schedule(held)
     t_prep = time.perf_counter() - t_prep
     reps = max(1, args.steps)
     runs = {}
@@ -236,6 +238,9 @@ def bench_grid(args, torch, pp):
     runs["heuristic_tuned"] = S.timed_run(G, seeds, pp.PP_SCHED_HEURISTIC, None, repeats=reps,
                                           push_div=int(tuned.push_div), pull_k=int(tuned.pull_k))
     log(f"[bench] heuristic with the tuned threshold {tuned.push_div}: {runs['heuristic_tuned'][0]:.3f} ms")
+    t_opt, c_opt, D_opt = S.replay_plan(G, seeds, best_plan, repeats=reps)
+    runs["optimal_plan"] = (t_opt, c_opt, D_opt, None)
+    log(f"[bench] the held-out table's optimal plan replayed: {t_opt:.3f} ms")
     (t_h, c_h, D_h, m_h), (t_l, c_l, D_l, m_l) = runs["heuristic"], runs["learned"]
     for name, (_, c_x, D_x, _) in runs.items():
         assert int(D_x[0]) == int(D_l[0]) and list(c_x[0]) == list(c_l[0]), f"{name} changed the counts"
@@ -251,7 +256,8 @@ def bench_grid(args, torch, pp):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "u64", "data": "synthetic",
         "config": {"workload": f"grid{side}x{side}_del10pct_sc1000_lcc_s128", "nodes": G.nodes, "arcs": G.arcs,
-                   "words": W, "rounds": rounds, "scheduler": "learned (MLP 8-32-32-2), heuristic fallback",
+                   "words": W, "rounds": rounds, "scheduler": "learned (MLP 8-32-32-4: dense pull, push over direct slots, push over "
+                                "flattened ranges, sparse pull), heuristic fallback",
                    "timing": "best of steps, whole propagation with graph replay, host clock around "
                              "synchronous library calls"},
         "heuristic": {"ms_per_step": round(t_h, 4), "value": nominal / (t_h / 1000.0),
@@ -265,6 +271,7 @@ def bench_grid(args, torch, pp):
         "heuristic_tuned": {"ms_per_step": round(runs["heuristic_tuned"][0], 4), "push_div": int(tuned.push_div),
                             "pull_k": int(tuned.pull_k),
                             "pulls": int((runs["heuristic_tuned"][3][1:rounds + 1] == pp.MODE_PULL).sum())},
+        "optimal_plan_replayed_ms": round(t_opt, 4),
         "held_out_table_ms": {"optimal": round(best_ms, 3),
                               "heuristic": round(S.policy_cost(held, S.heuristic_policy(8, held.n))[0], 3),
                               "learned": round(S.policy_cost(held, S.model_policy(params, held))[0], 3),
