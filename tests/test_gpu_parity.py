@@ -269,38 +269,47 @@ def test_batched_union_matches_solo_runs():
 # ------------------------------------------------------------ full size
 
 def test_rmat26_full_size_sampled_seeds():
-    """R-MAT scale 26, s = 512 (eight-word rows), in the benchmark's launch configuration,
-    whose pushes run at their widest (one block per 2^17 arcs, 8192 blocks).
+    """R-MAT scale 26, s = 512, in the benchmark's launch configurations: one group of
+    eight-word rows, whose pushes run at their widest (one block per 2^17 arcs, 8192
+    blocks), and seed groups by reach (two groups of four-word rows, the benchmark's
+    headline form).
 
-    Per-round totals come from the GPU only; the oracle checks 8 sampled seeds one by
-    one (per-seed counts and the seeds' signature bit columns over all 2^26 nodes), and
-    the totals are checked against the per-seed counts' sums.
+    Per-round totals come from the GPU only (the two forms must agree); the oracle
+    checks 8 sampled seeds one by one (per-seed counts and the seeds' signature bit
+    columns over all 2^26 nodes) in both forms, and the totals are checked against
+    the per-seed counts' sums.
     """
     g, seeds = gen.workload_rmat(26, 16, 512, 1)
     say("rmat26 build", g.n)
     G = pp.pp_csr_build(g.n, g.src, g.dst)
-    r = pp.pp_seeds_init(G, seeds, opts=pp.options(seed_counts=True, max_rounds=256))
-    counts, D = pp.pp_propagate_until_converged(r)
-    Dg = int(D[0])
-    modes, _ = pp.pp_get_round_log(r, Dg + 2)
-    say("rmat26 D", Dg, "modes", list(modes[1:Dg + 2]))
-    ran = [int(m) for m in modes[1:Dg + 2]]
-    assert (pp.MODE_PUSH in ran or pp.MODE_PUSH_FLAT in ran) and pp.MODE_PULL in ran
-    sc = pp.pp_get_seed_counts(r, Dg + 1)[0]
-    assert np.array_equal(sc.sum(axis=1).astype(np.int64), counts[0])
-    sig = pp.pp_get_signatures(r)
-    r.free()
+    runs = {}
+    for name, groups in (("one group", 0), ("groups by reach", pp.PP_GROUPS_BY_REACH)):
+        r = pp.pp_seeds_init(G, seeds, opts=pp.options(seed_counts=True, max_rounds=256, seed_groups=groups))
+        counts, D = pp.pp_propagate_until_converged(r)
+        Dg = int(D[0])
+        modes, _ = pp.pp_get_round_log(r, Dg + 2)
+        say("rmat26", name, "groups", r.groups, "D", Dg, "modes", list(modes[1:Dg + 2]))
+        ran = [int(m) for m in modes[1:Dg + 2]]
+        assert (pp.MODE_PUSH in ran or pp.MODE_PUSH_FLAT in ran) and pp.MODE_PULL in ran
+        assert r.groups == (1 if groups == 0 else 2)
+        sc = pp.pp_get_seed_counts(r, Dg + 1)[0]
+        assert np.array_equal(sc.sum(axis=1).astype(np.int64), counts[0])
+        runs[name] = (counts[0].copy(), Dg, sc, pp.pp_get_signatures(r))
+        r.free()
     G.free()
+    (c1, D1, _, _), (c2, D2, _, _) = runs["one group"], runs["groups by reach"]
+    assert D1 == D2 and list(c1) == list(c2)
     pick = np.unique(np.linspace(0, 511, 8).astype(np.int64))
     say("rmat26 oracle", list(pick))
     want = oracle.propagate(g.n, g.src, g.dst, seeds[pick], False, seed_counts=True, dist=True)
-    for j, i in enumerate(pick):
-        col = want["seed_counts"][:, j]
-        L = max(len(col), Dg + 1)
-        assert np.array_equal(np.pad(sc[:, i], (0, L - Dg - 1)), np.pad(col, (0, L - len(col)))), i
-        bits = (sig[:, i >> 6] >> np.uint64(i & 63)) & np.uint64(1)
-        assert np.array_equal(bits.astype(bool), want["dist"][j] >= 0), i
-    say("rmat26 ok", list(counts[0]))
+    for name, (counts, Dg, sc, sig) in runs.items():
+        for j, i in enumerate(pick):
+            col = want["seed_counts"][:, j]
+            L = max(len(col), Dg + 1)
+            assert np.array_equal(np.pad(sc[:, i], (0, L - Dg - 1)), np.pad(col, (0, L - len(col)))), (name, i)
+            bits = (sig[:, i >> 6] >> np.uint64(i & 63)) & np.uint64(1)
+            assert np.array_equal(bits.astype(bool), want["dist"][j] >= 0), (name, i)
+    say("rmat26 ok", list(c1))
 
 
 def test_autotune_candidates_keep_results():
