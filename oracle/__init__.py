@@ -30,8 +30,11 @@ Contents
                     break, pure Python, for small graphs.
 
 Parity pins for each function live in ``tests/test_oracle_*.py``.  The
-interpolated effective diameter has no printed worked value in the paper:
-parity unpinned beyond self-consistency and monotonicity.
+paper's own algorithm returns the integer effective diameter; the
+interpolated form (linear between hops) is a reading of the fractional values
+its tables print, with no worked value to check against; its arithmetic is
+pinned against numpy.interp, which inverts the piecewise-linear cumulative
+pair count independently.
 """
 from __future__ import annotations
 

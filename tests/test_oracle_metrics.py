@@ -78,6 +78,32 @@ def test_effective_diameter_exact_threshold():
     assert m["eff_diam"] == 1.0 == m["diameter"]
 
 
+@pytest.mark.parametrize("case", range(6))
+def test_interpolated_eff_diam_is_the_inverse_of_the_cumulative_count(case):
+    """The interpolated effective diameter is the hop at which the piecewise-linear
+    cumulative pair count R (hops 0..D, linear between hops) reaches tau R[D]: the
+    library routine numpy.interp inverts it independently of the oracle's exact
+    integer arithmetic.  R is strictly increasing up to D (a pair at distance d puts
+    pairs at every shorter distance on its path), as numpy.interp needs."""
+    g, seeds = [
+        (gen.erdos_renyi_gnm(300, 700, 3), gen.sample_seeds(300, 40, 1)),
+        (gen.rmat(10, 8, 4), gen.sample_seeds(1024, 64, 2)),
+        (gen.grid_graph(20, 13), gen.sample_seeds(260, 30, 3)),
+        (gen.path_graph(77), gen.sample_seeds(77, 77, 4)),
+        (gen.cycle_graph(40, directed=True), gen.sample_seeds(40, 9, 5)),
+        (gen.star_graph(50), gen.sample_seeds(50, 12, 6))][case]
+    g_n = g.n
+    out = oracle.propagate(g_n, g.src, g.dst, seeds, g.undirected)
+    counts = out["counts"]
+    R = np.cumsum(counts)
+    assert np.all(np.diff(R) > 0)
+    hops = np.arange(len(R), dtype=np.float64)
+    for num, den in [(9, 10), (1, 2), (99, 100), (1, 3), (1, 1)]:
+        m = oracle.metrics(counts, g_n, len(seeds), num, den)
+        want = float(np.interp(num / den * float(R[-1]), R.astype(np.float64), hops))
+        assert m["eff_diam_interp"] == pytest.approx(want, rel=1e-12, abs=1e-12), (num, den)
+
+
 def test_interpolated_eff_diam_monotone_in_tau():
     g, seeds = gen.workload_er(seed=2)
     out = oracle.propagate(g.n, g.src, g.dst, seeds, True)
