@@ -64,9 +64,23 @@ def workload(name: str):
 
 # workloads whose dense pull launches have counter figures under profiles/ (one seed
 # group, and seed groups by reach)
-TRAFFIC_PROFILES = {("rmat20", False): "k_pull_rmat20_s256", ("rmat20", True): "k_pull_rmat20_s256_groups",
-                    ("rmat26", False): "k_pull_rmat26_s512", ("rmat26", True): "k_pull_rmat26_s512_groups",
-                    ("grid:4096", False): "k_pull_grid4096_s128", ("grid:4096", True): "k_pull_grid4096_s128"}
+TRAFFIC_PROFILES = {("rmat20", False): ["k_pull_rmat20_s256"], ("rmat20", True): ["k_pull_rmat20_s256_groups"],
+                    ("rmat26", False): ["k_pull_rmat26_s512"], ("rmat26", True): ["k_pull_rmat26_s512_groups"],
+                    ("grid:4096", False): ["k_pull_grid4096_s128"], ("grid:4096", True): ["k_pull_grid4096_s128"]}
+
+
+def pull_kernel(W: int, pull_k: int) -> str:
+    """The dense pull kernel's name for rows of W words and pull_k arcs per lane."""
+    return f"k_pull<{W}, {2 if pull_k == 2 else 0}>"
+
+
+def traffic_for(profiles, kernel: str):
+    """The first of the workload's counter summaries that covers this kernel, if any."""
+    for p in profiles:
+        t = measured_traffic(p, kernel)
+        if t is not None:
+            return t
+    return None
 
 
 def measured_traffic(profile: str, kernel: str):
@@ -542,11 +556,11 @@ def step_figures(args, pp, T, m, n, s, wl, opts):
     achieved = bytes_pull / t_pull / 1e9 if t_pull > 0 else 0.0
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": (measured_traffic(TRAFFIC_PROFILES[(wl, by_reach)], f"k_pull<{Wg}, 0>")
-                        if ((wl, by_reach) in TRAFFIC_PROFILES and not opts.persistent and (opts.pull_k or 4) == 4 and
+            "traffic": (traffic_for(TRAFFIC_PROFILES[(wl, by_reach)], pull_kernel(Wg, opts.pull_k))
+                        if ((wl, by_reach) in TRAFFIC_PROFILES and not opts.persistent and
                             args.sparse_pull == 0 and args.push_div == 0 and args.scheduler == "heuristic")
                         else None),
-            "kernel": f"k_batch<{Wg}> pull phase" if opts.persistent else f"k_pull<{Wg}>",
+            "kernel": f"k_batch<{Wg}> pull phase" if opts.persistent else pull_kernel(Wg, opts.pull_k),
             "timing": ("device clock between grid barriers" if opts.persistent else
                        "HIP events around each launch, on the run's stream, over a second timed region of "
                        "the same steps"),
@@ -636,6 +650,7 @@ def propagation_line(args, torch, pp, g, seeds, cfg, wl, sample, stream, base_op
             raise SystemExit("the plain form's counts differ from the seed groups'")
         res["plain"] = step_figures(args, pp, P, m, n, s, wl, plain_opts)
         res["plain"]["note"] = "the same graph and seeds as one group of s seeds, same scheduler"
+        res["plain"]["pull_k"] = int(plain_opts.pull_k) or 4
         res["speedup_vs_plain"] = round(P["elapsed"] / T["elapsed"], 4)
         log(f"[bench] {cfg['workload']}: plain {res['plain']['ms_per_step']} ms per step")
     if learned:
@@ -700,8 +715,13 @@ def main():
     ap.add_argument("--node-stats", action="store_true",
                     help="also keep the per-node reach and distance sums (one extra pass per round) in the "
                          "timed runs (their values are checked against the oracle by the GPU tests)")
-    ap.add_argument("--torch-allocator", action="store_true",
-                    help="the library's device memory from PyTorch's caching allocator (pp_set_allocator)")
+    ap.add_argument("--hip-malloc", action="store_true",
+                    help="the library's own hipMalloc / hipFree for its device memory instead of PyTorch's caching "
+                         "allocator (the default here, through pp_set_allocator): releasing gigabytes with hipFree "
+                         "slows the GPU work of the next seconds by a few percent, which would reach every form "
+                         "timed after the first")
+    ap.add_argument("--pull-k", type=int, default=0, choices=[0, 2, 4],
+                    help="arcs per lane of the dense pull's tiles (0: the library's default, 4)")
     ap.add_argument("--push-div", type=int, default=0,
                     help="heuristic: push while frontier arcs x push_div < arcs (0: the library's default)")
     ap.add_argument("--sparse-pull", type=int, default=0, choices=[0, 1, 2],
@@ -733,7 +753,7 @@ def main():
     if not torch.cuda.is_available():
         raise SystemExit("no GPU visible")
     torch.cuda.set_device(0)
-    if args.torch_allocator:
+    if not args.hip_malloc:
         pp.use_torch_allocator(torch)
     sched = {"heuristic": pp.PP_SCHED_HEURISTIC, "pull": pp.PP_SCHED_PULL, "push": pp.PP_SCHED_PUSH}[args.scheduler]
     if args.workload == "batch64":
@@ -753,7 +773,7 @@ def main():
         sg = {"reach": pp.PP_GROUPS_BY_REACH, "plain": 0}.get(groups, None)
         sg = int(groups) if sg is None else sg
         return pp.options(scheduler=sched, max_rounds=4096, persistent=args.persistent, node_stats=args.node_stats,
-                          sparse_pull=args.sparse_pull, push_div=args.push_div, seed_groups=sg)
+                          sparse_pull=args.sparse_pull, push_div=args.push_div, seed_groups=sg, pull_k=args.pull_k)
 
     grouped = args.groups != "plain" and not args.persistent and not args.node_stats
     base = make_opts(args.groups if grouped else "plain")
@@ -792,6 +812,7 @@ def main():
     if args.node_stats:
         out["node_stats_note"] = "per-node sums kept in every timed round (their check runs in the GPU tests)"
     out["hip_runtime"] = pp.hip_runtime()
+    out["allocator"] = "hipMalloc (the library's own)" if args.hip_malloc else "PyTorch's caching allocator (pp_set_allocator)"
     out["wall_s"] = round(time.perf_counter() - t_start, 1)
     print(json.dumps(out), flush=True)
     bad = [k for k, v in (("headline", out.get("check")), ("rmat20", out.get("rmat20", {}).get("check")))
