@@ -537,7 +537,10 @@ typedef struct {
  *               0); *ntried (may be NULL) receives how many were tried.
  * A candidate whose run cannot be created (the persistent engine with more
  * graphs than co-resident blocks) is skipped.  Outputs never depend on the
- * options, only the time does.  Allocates and frees a run per candidate.
+ * options, only the time does.  Allocates and frees a run per candidate,
+ * and one untimed run first: releasing gigabytes of device memory slows
+ * the next seconds of GPU work by a few percent, so every candidate is
+ * timed after a release, the first one included.
  */
 int pp_autotune(pp_graph g, const int32_t *seeds, int32_t s, const pp_options *base, int32_t reps,
                 pp_options *best, pp_tune_entry *table, int32_t cap, int32_t *ntried);
