@@ -67,11 +67,17 @@ enum {
     PP_INPUT_ON_DEVICE = 2,  /* src/dst point to device memory */
     PP_TRANSPOSE = 4,        /* propagate along reversed arcs: bit i reaches u when
                                 x_i can reach u (instead of u reaching x_i) */
-    PP_KEEP_ORDER = 8        /* store the nodes in input order (by default the nodes
+    PP_KEEP_ORDER = 8,       /* store the nodes in input order (by default the nodes
                                 with the most predecessors are stored first, which
                                 only changes the layout: every result is reported
                                 by input node id) */
+    PP_BUILD_ON_HOST = 16,   /* sort the arcs on host threads (the default below
+                                PP_DEVICE_BUILD_MIN input pairs) */
+    PP_BUILD_ON_DEVICE = 32  /* sort the arcs on the device (the default from
+                                PP_DEVICE_BUILD_MIN input pairs on); both builds
+                                give the same arrays */
 };
+#define PP_DEVICE_BUILD_MIN (1 << 20)
 
 /* per-round direction policy */
 enum {
@@ -190,7 +196,8 @@ int pp_set_allocator(void *(*alloc)(size_t bytes, void *stream, void *ctx),
  *   src, dst    m node ids each: pair k is the arc src[k] -> dst[k] (both
  *               directions with PP_UNDIRECTED).  Host memory unless
  *               PP_INPUT_ON_DEVICE; the caller keeps ownership.
- *   flags       PP_UNDIRECTED | PP_INPUT_ON_DEVICE | PP_TRANSPOSE | PP_KEEP_ORDER.
+ *   flags       PP_UNDIRECTED | PP_INPUT_ON_DEVICE | PP_TRANSPOSE | PP_KEEP_ORDER,
+ *               and at most one of PP_BUILD_ON_HOST, PP_BUILD_ON_DEVICE.
  *   node_offsets, num_graphs
  *               a batch of num_graphs disjoint graphs: graph g owns node ids
  *               [node_offsets[g], node_offsets[g+1]) (host array of
@@ -200,7 +207,10 @@ int pp_set_allocator(void *(*alloc)(size_t bytes, void *stream, void *ctx),
  *               is PP_ERANGE.
  *   stream      hipStream_t the build is ordered on (NULL: legacy default).
  * Self-loops and repeated arcs are removed (they cannot change a bit); the
- * stored arc count is pp_graph_arcs().  Errors: PP_EINVAL, PP_ERANGE,
+ * stored arc count is pp_graph_arcs().  The device build radix-sorts packed
+ * (row, column) keys on `stream` and needs about 24 bytes per input pair
+ * (48 with PP_UNDIRECTED) of device memory while it runs; device-resident
+ * input then never goes through the host.  Errors: PP_EINVAL, PP_ERANGE,
  * PP_ENOMEM, PP_EDEVICE; *out is written only on success.
  */
 int pp_csr_build(int64_t n, int64_t m, const int32_t *src, const int32_t *dst, uint32_t flags,
@@ -208,6 +218,14 @@ int pp_csr_build(int64_t n, int64_t m, const int32_t *src, const int32_t *dst, u
 
 /* Stored arcs (after dedup, both directions for undirected input) and nodes. */
 int64_t pp_graph_arcs(pp_graph g);
+/*
+ * pp_graph_get_csr -- the stored adjacency, for inspection: rp [n+1] (int64
+ * offsets) and col [m] of the successor rows, trp [n+1] and tcol [m] of the
+ * predecessor rows, all in storage order, and perm [n] (the stored id of
+ * each input node; the identity when the order was kept).  Host arrays, each
+ * may be NULL; m = pp_graph_arcs(g).  Synchronous.
+ */
+int pp_graph_get_csr(pp_graph g, int64_t *rp, int32_t *col, int64_t *trp, int32_t *tcol, int32_t *perm);
 int64_t pp_graph_nodes(pp_graph g);
 int32_t pp_graph_count(pp_graph g);
 

@@ -20,7 +20,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libpp.so")
 OBJDIR = os.path.join(PKG, "_build")
 
-SOURCES = ["pp_kernels.hip", "pp_api.hip", "pp_mlp.hip", "pp_seq.hip", "pp_metrics.cpp"]
+SOURCES = ["pp_kernels.hip", "pp_api.hip", "pp_build.hip", "pp_mlp.hip", "pp_seq.hip", "pp_metrics.cpp"]
 ARCH = "gfx950"
 
 

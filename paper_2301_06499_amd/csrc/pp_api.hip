@@ -16,6 +16,7 @@
 #include <string>
 #include <chrono>
 #include <thread>
+#include <utility>
 #include <vector>
 
 #include "pp_internal.h"
@@ -508,8 +509,11 @@ extern "C" int pp_csr_build(int64_t n, int64_t m, const int32_t *src, const int3
     if (n < 1 || n > INT32_MAX - 1) return fail(PP_EINVAL, "n = %lld outside [1, 2^31-2]", (long long)n);
     if (m < 0) return fail(PP_EINVAL, "m < 0");
     if (m > 0 && (!src || !dst)) return fail(PP_EINVAL, "src/dst NULL with m > 0");
-    if (flags & ~(uint32_t)(PP_UNDIRECTED | PP_INPUT_ON_DEVICE | PP_TRANSPOSE | PP_KEEP_ORDER))
+    if (flags & ~(uint32_t)(PP_UNDIRECTED | PP_INPUT_ON_DEVICE | PP_TRANSPOSE | PP_KEEP_ORDER | PP_BUILD_ON_HOST |
+                            PP_BUILD_ON_DEVICE))
         return fail(PP_EINVAL, "unknown flag bits");
+    if ((flags & PP_BUILD_ON_HOST) && (flags & PP_BUILD_ON_DEVICE))
+        return fail(PP_EINVAL, "PP_BUILD_ON_HOST and PP_BUILD_ON_DEVICE together");
     const int G = (num_graphs <= 1 && !node_offsets) ? 1 : num_graphs;
     if (G < 1) return fail(PP_EINVAL, "num_graphs < 1");
     std::vector<int64_t> noff((size_t)G + 1);
@@ -524,28 +528,17 @@ extern "C" int pp_csr_build(int64_t n, int64_t m, const int32_t *src, const int3
     }
     const bool und = flags & PP_UNDIRECTED;
     const bool tr = flags & PP_TRANSPOSE;
+    const bool on_device = (flags & PP_BUILD_ON_DEVICE) || (!(flags & PP_BUILD_ON_HOST) && m >= PP_DEVICE_BUILD_MIN);
     hipStream_t st = (hipStream_t)stream;
-
-    // input arcs on the host
-    std::vector<int32_t> hs, hd;
-    const int32_t *ps = src, *pd = dst;
-    if ((flags & PP_INPUT_ON_DEVICE) && m > 0) {
-        hs.resize((size_t)m);
-        hd.resize((size_t)m);
-        HIP_TRY(hipMemcpyAsync(hs.data(), src, sizeof(int32_t) * (size_t)m, hipMemcpyDeviceToHost, st));
-        HIP_TRY(hipMemcpyAsync(hd.data(), dst, sizeof(int32_t) * (size_t)m, hipMemcpyDeviceToHost, st));
-        HIP_TRY(hipStreamSynchronize(st));
-        ps = hs.data();
-        pd = hd.data();
-    }
-    // validation
     std::vector<int32_t> ng;
     if (G > 1) {
         ng.resize((size_t)n);
         for (int g = 0; g < G; ++g)
             for (int64_t u = noff[(size_t)g]; u < noff[(size_t)g + 1]; ++u) ng[(size_t)u] = g;
     }
-    {
+    // arcs outside [0, n) or across graphs: host arrays are checked here,
+    // before any device work; device arrays on the device, or after their copy
+    auto check_host_arcs = [&](const int32_t *ps, const int32_t *pd) -> int64_t {
         std::atomic<int64_t> bad{-1};
         parallel_for(m, [&](int64_t lo, int64_t hi) {
             for (int64_t k = lo; k < hi; ++k) {
@@ -556,55 +549,182 @@ extern "C" int pp_csr_build(int64_t n, int64_t m, const int32_t *src, const int3
                 }
             }
         });
-        if (bad.load() >= 0) {
-            const int64_t k = bad.load();
-            return fail(PP_ERANGE, "arc %lld (%d -> %d) outside [0, n) or across graphs", (long long)k, ps[k], pd[k]);
-        }
-    }
-    // propagation rows: u ORs in v for arc u -> v (or v -> u transposed)
-    std::vector<int64_t> rp, trp;
-    std::vector<int32_t> col, tcol, perm;
-    try {
-        if (tr) build_rows(n, m, pd, ps, und, rp, col);
-        else build_rows(n, m, ps, pd, und, rp, col);
-        transpose_rows(n, rp, col, trp, tcol);
-        if (!(flags & PP_KEEP_ORDER) && hub_first_order(noff, G, rp, trp, perm)) {
-            relabel_rows(perm, rp, col);
-            relabel_rows(perm, trp, tcol);
-        } else {
-            perm.clear();
-        }
-    } catch (const std::bad_alloc &) {
-        return fail(PP_ENOMEM, "host memory for the adjacency build");
+        return bad.load();
+    };
+    if (!(flags & PP_INPUT_ON_DEVICE) && m > 0) {
+        const int64_t k = check_host_arcs(src, dst);
+        if (k >= 0)
+            return fail(PP_ERANGE, "arc %lld (%d -> %d) outside [0, n) or across graphs", (long long)k, src[k], dst[k]);
     }
     pp_graph g = new (std::nothrow) pp_graph_s();
     if (!g) return fail(PP_ENOMEM, "graph handle");
     g->n = n;
-    g->m = (int64_t)col.size();
     g->G = G;
     g->flags = flags;
     g->stream = st;
     g->node_offsets = noff;
     int rc;
-    if ((rc = dev_alloc(&g->rp, n + 1)) || (rc = dev_alloc(&g->trp, n + 1)) || (rc = dev_alloc(&g->col, g->m)) ||
-        (rc = dev_alloc(&g->tcol, g->m)) || (G > 1 && (rc = dev_alloc(&g->node_graph, n))) ||
-        (rc = dev_alloc(&g->node_off, (int64_t)G + 1)) || (!perm.empty() && (rc = dev_alloc(&g->perm_d, n)))) {
+    if ((G > 1 && (rc = dev_alloc(&g->node_graph, n))) || (rc = dev_alloc(&g->node_off, (int64_t)G + 1))) {
         free_graph(g);
         return rc;
     }
-    hipError_t e = hipMemcpyAsync(g->rp, rp.data(), sizeof(int64_t) * (size_t)(n + 1), hipMemcpyHostToDevice, st);
-    if (e == hipSuccess) e = hipMemcpyAsync(g->trp, trp.data(), sizeof(int64_t) * (size_t)(n + 1), hipMemcpyHostToDevice, st);
-    if (e == hipSuccess && g->m) e = hipMemcpyAsync(g->col, col.data(), sizeof(int32_t) * (size_t)g->m, hipMemcpyHostToDevice, st);
-    if (e == hipSuccess && g->m) e = hipMemcpyAsync(g->tcol, tcol.data(), sizeof(int32_t) * (size_t)g->m, hipMemcpyHostToDevice, st);
-    if (e == hipSuccess && G > 1) e = hipMemcpyAsync(g->node_graph, ng.data(), sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice, st);
+    hipError_t e = hipSuccess;
+    if (G > 1) e = hipMemcpyAsync(g->node_graph, ng.data(), sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipMemcpyAsync(g->node_off, noff.data(), sizeof(int64_t) * (size_t)(G + 1), hipMemcpyHostToDevice, st);
-    if (e == hipSuccess && !perm.empty())
-        e = hipMemcpyAsync(g->perm_d, perm.data(), sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice, st);
-    if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) {
-        (void)hipStreamSynchronize(st);   // copies already queued finish before the blocks go back
+        (void)hipStreamSynchronize(st);
         free_graph(g);
         return fail(PP_EDEVICE, "graph upload: %s", hipGetErrorString(e));
+    }
+    // the storage order: hub-first unless the caller keeps the input order
+    auto order = [&](const std::vector<int64_t> &rp_, const std::vector<int64_t> &trp_, std::vector<int32_t> &perm_) {
+        return !(flags & PP_KEEP_ORDER) && hub_first_order(noff, G, rp_, trp_, perm_);
+    };
+    // propagation rows: u ORs in v for arc u -> v (or v -> u transposed)
+    std::vector<int64_t> rp, trp;
+    std::vector<int32_t> perm;
+    if (on_device) {
+        // the arcs on the device: the caller's, or a copy of the host arrays
+        int32_t *da = nullptr, *db = nullptr;
+        const int32_t *a = src, *b = dst;
+        auto drop_input = [&]() {
+            dev_free(da);
+            dev_free(db);
+        };
+        if (!(flags & PP_INPUT_ON_DEVICE) && m > 0) {
+            if ((rc = dev_alloc(&da, m)) || (rc = dev_alloc(&db, m))) {
+                drop_input();
+                free_graph(g);
+                return rc;
+            }
+            e = hipMemcpyAsync(da, src, sizeof(int32_t) * (size_t)m, hipMemcpyHostToDevice, st);
+            if (e == hipSuccess) e = hipMemcpyAsync(db, dst, sizeof(int32_t) * (size_t)m, hipMemcpyHostToDevice, st);
+            if (e != hipSuccess) {
+                (void)hipStreamSynchronize(st);
+                drop_input();
+                free_graph(g);
+                return fail(PP_EDEVICE, "arc upload: %s", hipGetErrorString(e));
+            }
+            a = da;
+            b = db;
+        }
+        int64_t bad = -1;
+        if ((flags & PP_INPUT_ON_DEVICE) && (rc = pp::device_check_arcs(a, b, m, n, g->node_graph, &bad, st))) {
+            drop_input();
+            free_graph(g);
+            return rc;
+        }
+        if (bad >= 0) {
+            int32_t ends[2] = {0, 0};
+            if (hipMemcpy(&ends[0], a + bad, sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess ||
+                hipMemcpy(&ends[1], b + bad, sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess)
+                (void)hipGetLastError();
+            drop_input();
+            free_graph(g);
+            return fail(PP_ERANGE, "arc %lld (%d -> %d) outside [0, n) or across graphs", (long long)bad, ends[0], ends[1]);
+        }
+        pp::DevRows rows, trows;
+        if (tr) std::swap(a, b);
+        rc = pp::device_build(n, m, a, b, und, order, rows, trows, perm, st);
+        drop_input();   // device_build has synchronised the stream
+        g->rp = rows.rp;
+        g->col = rows.col;
+        g->trp = trows.rp;
+        g->tcol = trows.col;
+        g->m = rows.m;
+        if (rc) {
+            free_graph(g);
+            return rc;
+        }
+        // host copies of the offsets (tiles, the long-list table, predecessor bits)
+        try {
+            rp.resize((size_t)n + 1);
+            trp.resize((size_t)n + 1);
+        } catch (const std::bad_alloc &) {
+            free_graph(g);
+            return fail(PP_ENOMEM, "host memory for the offsets");
+        }
+        e = hipMemcpyAsync(rp.data(), g->rp, sizeof(int64_t) * (size_t)(n + 1), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(trp.data(), g->trp, sizeof(int64_t) * (size_t)(n + 1), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) {
+            (void)hipStreamSynchronize(st);
+            free_graph(g);
+            return fail(PP_EDEVICE, "offset download: %s", hipGetErrorString(e));
+        }
+    } else {
+        // input arcs on the host
+        std::vector<int32_t> hs, hd, col, tcol;
+        const int32_t *ps = src, *pd = dst;
+        if ((flags & PP_INPUT_ON_DEVICE) && m > 0) {
+            try {
+                hs.resize((size_t)m);
+                hd.resize((size_t)m);
+            } catch (const std::bad_alloc &) {
+                free_graph(g);
+                return fail(PP_ENOMEM, "host memory for the arcs");
+            }
+            e = hipMemcpyAsync(hs.data(), src, sizeof(int32_t) * (size_t)m, hipMemcpyDeviceToHost, st);
+            if (e == hipSuccess) e = hipMemcpyAsync(hd.data(), dst, sizeof(int32_t) * (size_t)m, hipMemcpyDeviceToHost, st);
+            if (e == hipSuccess) e = hipStreamSynchronize(st);
+            if (e != hipSuccess) {
+                (void)hipStreamSynchronize(st);
+                free_graph(g);
+                return fail(PP_EDEVICE, "arc download: %s", hipGetErrorString(e));
+            }
+            ps = hs.data();
+            pd = hd.data();
+        }
+        if ((flags & PP_INPUT_ON_DEVICE) && m > 0) {
+            const int64_t k = check_host_arcs(ps, pd);
+            if (k >= 0) {
+                free_graph(g);
+                return fail(PP_ERANGE, "arc %lld (%d -> %d) outside [0, n) or across graphs", (long long)k, ps[k], pd[k]);
+            }
+        }
+        try {
+            if (tr) build_rows(n, m, pd, ps, und, rp, col);
+            else build_rows(n, m, ps, pd, und, rp, col);
+            transpose_rows(n, rp, col, trp, tcol);
+            if (order(rp, trp, perm)) {
+                relabel_rows(perm, rp, col);
+                relabel_rows(perm, trp, tcol);
+            } else {
+                perm.clear();
+            }
+        } catch (const std::bad_alloc &) {
+            free_graph(g);
+            return fail(PP_ENOMEM, "host memory for the adjacency build");
+        }
+        g->m = (int64_t)col.size();
+        if ((rc = dev_alloc(&g->rp, n + 1)) || (rc = dev_alloc(&g->trp, n + 1)) || (rc = dev_alloc(&g->col, g->m)) ||
+            (rc = dev_alloc(&g->tcol, g->m))) {
+            free_graph(g);
+            return rc;
+        }
+        e = hipMemcpyAsync(g->rp, rp.data(), sizeof(int64_t) * (size_t)(n + 1), hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(g->trp, trp.data(), sizeof(int64_t) * (size_t)(n + 1), hipMemcpyHostToDevice, st);
+        if (e == hipSuccess && g->m) e = hipMemcpyAsync(g->col, col.data(), sizeof(int32_t) * (size_t)g->m, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess && g->m) e = hipMemcpyAsync(g->tcol, tcol.data(), sizeof(int32_t) * (size_t)g->m, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) {
+            (void)hipStreamSynchronize(st);
+            free_graph(g);
+            return fail(PP_EDEVICE, "graph upload: %s", hipGetErrorString(e));
+        }
+    }
+    if (!perm.empty()) {
+        if ((rc = dev_alloc(&g->perm_d, n))) {
+            free_graph(g);
+            return rc;
+        }
+        e = hipMemcpyAsync(g->perm_d, perm.data(), sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) {
+            (void)hipStreamSynchronize(st);
+            free_graph(g);
+            return fail(PP_EDEVICE, "order upload: %s", hipGetErrorString(e));
+        }
     }
     // PROPAGATE-S: the nodes whose successor lists go to the group-per-node
     // launch, listed once with the graph (stored ids)
@@ -634,6 +754,20 @@ extern "C" int pp_csr_build(int64_t n, int64_t m, const int32_t *src, const int3
 }
 
 extern "C" void pp_graph_free(pp_graph g) { free_graph(g); }
+
+extern "C" int pp_graph_get_csr(pp_graph g, int64_t *rp, int32_t *col, int64_t *trp, int32_t *tcol, int32_t *perm) {
+    if (!g) return fail(PP_EINVAL, "graph is NULL");
+    const size_t n = (size_t)g->n, m = (size_t)g->m;
+    hipError_t e = hipSuccess;
+    if (rp) e = hipMemcpy(rp, g->rp, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToHost);
+    if (e == hipSuccess && col && m) e = hipMemcpy(col, g->col, sizeof(int32_t) * m, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && trp) e = hipMemcpy(trp, g->trp, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToHost);
+    if (e == hipSuccess && tcol && m) e = hipMemcpy(tcol, g->tcol, sizeof(int32_t) * m, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return fail(PP_EDEVICE, "adjacency download: %s", hipGetErrorString(e));
+    if (perm)
+        for (size_t x = 0; x < n; ++x) perm[x] = g->perm.empty() ? (int32_t)x : g->perm[x];
+    return PP_OK;
+}
 
 // --------------------------------------------------------------------------
 // runs

@@ -20,6 +20,8 @@ LIB_PATH = os.path.join(_PKG, "libpp.so")
 
 PP_OK, PP_EINVAL, PP_ERANGE, PP_ENOMEM, PP_EDEVICE, PP_ENOTCONV, PP_ESTATE = 0, -1, -2, -3, -4, -5, -6
 PP_UNDIRECTED, PP_INPUT_ON_DEVICE, PP_TRANSPOSE, PP_KEEP_ORDER = 1, 2, 4, 8
+PP_BUILD_ON_HOST, PP_BUILD_ON_DEVICE = 16, 32
+DEVICE_BUILD_MIN = 1 << 20
 PP_SCHED_HEURISTIC, PP_SCHED_PULL, PP_SCHED_PUSH, PP_SCHED_FUZZ, PP_SCHED_MLP, PP_SCHED_PLAN = 0, 1, 2, 3, 4, 5
 PP_GROUPS_BY_REACH, PP_ORDER_BY_REACH = -1, 1
 MODE_PULL, MODE_PUSH, MODE_INIT, MODE_SPULL, MODE_PUSH_FLAT = 0, 1, 2, 3, 4   # entries of the per-round mode log
@@ -62,6 +64,7 @@ class Metrics(ctypes.Structure):
 
 
 EXPORTS = ["pp_options_default", "pp_csr_build", "pp_graph_arcs", "pp_graph_nodes", "pp_graph_count",
+           "pp_graph_get_csr",
            "pp_seeds_init", "pp_propagate_round", "pp_propagate_until_converged", "pp_estimate_metrics",
            "pp_get_signatures", "pp_get_seed_counts", "pp_run_round", "pp_run_words", "pp_get_round_log",
            "pp_run_snapshot", "pp_run_restore", "pp_run_free", "pp_graph_free", "pp_last_error",
@@ -90,6 +93,7 @@ def lib():
         "pp_options_default": (None, [P]),
         "pp_csr_build": (ctypes.c_int, [I64, I64, P, P, U32, P, I32, P, P]),
         "pp_graph_arcs": (I64, [P]), "pp_graph_nodes": (I64, [P]), "pp_graph_count": (I32, [P]),
+        "pp_graph_get_csr": (ctypes.c_int, [P, P, P, P, P, P]),
         "pp_seeds_init": (ctypes.c_int, [P, P, I32, P, P, P]),
         "pp_propagate_round": (ctypes.c_int, [P, P, P]),
         "pp_propagate_until_converged": (ctypes.c_int, [P, I32, P, I32, P]),
@@ -227,10 +231,14 @@ class Graph:
 
 
 def pp_csr_build(n, src, dst, undirected=False, transpose=False, node_offsets=None, stream=None,
-                 keep_order=False) -> Graph:
-    """Build the device graph from m arcs src[k] -> dst[k] (numpy int32 or device tensors)."""
+                 keep_order=False, build="auto") -> Graph:
+    """Build the device graph from m arcs src[k] -> dst[k] (numpy int32 or device tensors).
+    build: "auto" (the library's choice by size), "host" or "device"."""
+    if build not in ("auto", "host", "device"):
+        raise ValueError("build must be 'auto', 'host' or 'device'")
     flags = ((PP_UNDIRECTED if undirected else 0) | (PP_TRANSPOSE if transpose else 0) |
-             (PP_KEEP_ORDER if keep_order else 0))
+             (PP_KEEP_ORDER if keep_order else 0) |
+             {"auto": 0, "host": PP_BUILD_ON_HOST, "device": PP_BUILD_ON_DEVICE}[build])
     keep = []
     if _is_device(src):
         flags |= PP_INPUT_ON_DEVICE
@@ -251,6 +259,19 @@ def pp_csr_build(n, src, dst, undirected=False, transpose=False, node_offsets=No
     h = ctypes.c_void_p()
     _check(lib().pp_csr_build(int(n), m, ps, pd, flags, po, G, _stream_ptr(stream), ctypes.byref(h)))
     return Graph(h)
+
+
+def pp_graph_get_csr(graph: Graph):
+    """(rp, col, trp, tcol, perm) of the stored adjacency, host copies (storage order)."""
+    n, m = graph.nodes, graph.arcs
+    rp = np.zeros(n + 1, np.int64)
+    col = np.zeros(max(m, 1), np.int32)
+    trp = np.zeros(n + 1, np.int64)
+    tcol = np.zeros(max(m, 1), np.int32)
+    perm = np.zeros(n, np.int32)
+    _check(lib().pp_graph_get_csr(graph.handle, _np_ptr(rp), _np_ptr(col), _np_ptr(trp), _np_ptr(tcol),
+                                  _np_ptr(perm)))
+    return rp, col[:m], trp, tcol[:m], perm
 
 
 class Run:
