@@ -20,6 +20,7 @@
 #include <vector>
 
 #include "pp_internal.h"
+#include "pp_build.h"
 
 using pp::Chunk;
 using pp::Ctrl;

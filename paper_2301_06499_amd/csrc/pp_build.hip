@@ -13,6 +13,7 @@
 // halves swapped.
 // The result is identical, array for array, to the host build.
 #include "pp_internal.h"
+#include "pp_build.h"
 
 #include <rocprim/device/device_radix_sort.hpp>
 #include <rocprim/device/device_scan.hpp>
