@@ -113,6 +113,7 @@ struct TileSet {
     int32_t ntiles = 0;
     int32_t *hub_node = nullptr;   // node of each high-degree entry
     int32_t nhubs = 0;
+    bool short_lists = false;      // no hubs and no node above PULL_NPL successors
     std::vector<int32_t> gtile;    // [G+1] first tile of each graph
     std::vector<int32_t> ghub;     // [G+1] first hub of each graph
 };
@@ -449,6 +450,9 @@ int ensure_tiles(pp_graph g, int W, int K, TileSet **out) {
     }
     ts.ntiles = (int32_t)tiles.size();
     ts.nhubs = (int32_t)hubs.size();
+    int64_t dmax = 0;
+    for (int64_t u = 0; u < g->n; ++u) dmax = std::max(dmax, g->rp_host[u + 1] - g->rp_host[u]);
+    ts.short_lists = hubs.empty() && dmax <= pp::PULL_NPL;
     hipError_t e = hipSuccess;
     if (!tiles.empty()) e = hipMemcpy(ts.tiles, tiles.data(), sizeof(Tile) * tiles.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess && !hubs.empty())
@@ -498,6 +502,7 @@ GraphDev graph_view(pp_graph g, const TileSet *ts, int W) {
     d.node_off = g->node_off;
     d.G = g->G;
     d.pull_grid = pp::pull_grid_for(d.ntiles, W);
+    d.short_lists = ts && ts->short_lists ? 1 : 0;
     return d;
 }
 

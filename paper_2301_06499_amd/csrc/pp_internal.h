@@ -60,6 +60,9 @@ constexpr int PULL_GRID_MAX = PP_PULL_GRID_MAX;
 #ifndef PP_PULL_WAVES
 #define PP_PULL_WAVES 4   // occupancy the pull kernel is compiled for (W <= 4)
 #endif
+#ifndef PP_PULL_SHORT_WAVES
+#define PP_PULL_SHORT_WAVES 5   // the same for its short-list form (W <= 2)
+#endif
 
 // A pull tile is the work of one wave, per signature width W (words) and
 // arcs per lane K (KK, or the default when KK = 0): the tile's arc budget
@@ -171,7 +174,14 @@ struct GraphDev {
     const int64_t *node_off;     // [G+1] node range of each graph
     int32_t G;
     int32_t pull_grid;           // blocks of the pull launch (= per-block partial slots)
+    int32_t short_lists;         // no high-degree chunks and every node at most PULL_NPL
+                                 // successors: the pull launches its short-list form
+    int32_t pad_graph;
 };
+
+// A pull tile whose nodes have at most PULL_NPL successors each gathers with
+// one lane per node (rows of one or two words).
+constexpr int PULL_NPL = 6;
 
 // A run's device state.  Its seeds may be split into seed groups, each with
 // its own signature rows (W words), frontier, counters and control block:

@@ -716,7 +716,10 @@ PP_DEV void stage_tile(const GraphDev &g, const Tile &T, int ln, int32_t (&cv)[K
     }
 }
 
-template <int W, int KK = 0>
+// SHORT: every tile of the graph takes the one-lane-per-node gather (rows of
+// one or two words, no high-degree chunks): the general gather is not
+// compiled in, which leaves the kernel fewer registers and more waves.
+template <int W, int KK = 0, bool SHORT = false>
 PP_DEV void phase_pull(const GraphDev &g, const RunDev &R, int bid, int nb) {
     Ctrl *C = R.ctrl;
     using PS = PullShape<W, KK>;
@@ -796,9 +799,9 @@ PP_DEV void phase_pull(const GraphDev &g, const RunDev &R, int bid, int nb) {
         // NPL successors): one lane per node walks its own list, so load j
         // of the wave takes the j-th successor of 64 consecutive nodes
         // (neighbouring rows on a lattice: few cache lines per load)
-        constexpr int NPL = 6;
+        constexpr int NPL = PULL_NPL;
         int dmax = 0;
-        if constexpr (W <= 2) {
+        if constexpr (W <= 2 && !SHORT) {
             if (!hub) {
                 int d = ln < nn ? rp_l[ln + 1] - rp_l[ln] : 0;
 #pragma unroll
@@ -806,7 +809,7 @@ PP_DEV void phase_pull(const GraphDev &g, const RunDev &R, int bid, int nb) {
                 dmax = d;
             }
         }
-        if (W <= 2 && !hub && dmax <= NPL) {
+        if (SHORT || (W <= 2 && !hub && dmax <= NPL)) {
             const int b0 = ln < nn ? rp_l[ln] : 0;
             const int d = ln < nn ? rp_l[ln + 1] - b0 : 0;
             uint64_t rows[NPL][W];
@@ -825,7 +828,7 @@ PP_DEV void phase_pull(const GraphDev &g, const RunDev &R, int bid, int nb) {
                     acc_l[ln * W + w] = a;
                 }
             }
-        } else {
+        } else if constexpr (!SHORT) {
         // gather: a group of L lanes shares arcs [a, a + KG); each lane loads
         // and ORs its P-word slice of every source row (one 16-byte load per
         // lane, so the group's loads of one row fall in one cache line and
@@ -1759,6 +1762,25 @@ k_pull(GraphDev g, RunDev R0) {
         phase_frontier<W, 1024>(g, R, blockIdx.x, nb);
     }
 }
+// The pull of a graph whose lists are all short (one- and two-word rows):
+// the same phases as k_pull with only the one-lane-per-node gather compiled.
+template <int W>
+__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(PP_PULL_SHORT_WAVES)))
+k_pull_short(GraphDev g, RunDev R0) {
+    const RunDev R = group_view(R0, blockIdx.y);
+    const Ctrl *C = R.ctrl;
+    if (C->converged) return;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {   // the round's start: its first launch's first block
+        const int r = C->round;
+        if (r < R.cap) R.phase_log[(int64_t)r * 3] = (int64_t)wall_clock64();
+    }
+    if (C->mode == MODE_PULL) {
+        phase_pull<W, 0, true>(g, R, blockIdx.x, gridDim.x);
+    } else if (C->prev_mode == MODE_PULL && blockIdx.x < FRONTIER_BLOCKS) {
+        const int nb = gridDim.x < FRONTIER_BLOCKS ? (int)gridDim.x : FRONTIER_BLOCKS;
+        phase_frontier<W, 1024>(g, R, blockIdx.x, nb);
+    }
+}
 template <int W> __global__ void __launch_bounds__(BLOCK) k_push(GraphDev g, RunDev R0) {
     const RunDev R = group_view(R0, blockIdx.y);
     if (R.ctrl->converged || R.ctrl->mode != MODE_PUSH) return;
@@ -2193,8 +2215,18 @@ static hipError_t round_impl(const GraphDev &g, const RunDev &R, hipStream_t st,
         if (e != hipSuccess) return e;
     }
     const unsigned ng = (unsigned)R.ngroups;   // every launch covers every seed group (blockIdx.y)
-    if (R.pull_k == 2) hipLaunchKernelGGL((k_pull<W, 2>), dim3(g.pull_grid, ng), dim3(BLOCK), 0, st, g, R);
-    else hipLaunchKernelGGL((k_pull<W, 0>), dim3(g.pull_grid, ng), dim3(BLOCK), 0, st, g, R);
+    if constexpr (W <= 2) {
+        if (g.short_lists && R.pull_k != 2) {
+            hipLaunchKernelGGL(k_pull_short<W>, dim3(g.pull_grid, ng), dim3(BLOCK), 0, st, g, R);
+        } else if (R.pull_k == 2) {
+            hipLaunchKernelGGL((k_pull<W, 2>), dim3(g.pull_grid, ng), dim3(BLOCK), 0, st, g, R);
+        } else {
+            hipLaunchKernelGGL((k_pull<W, 0>), dim3(g.pull_grid, ng), dim3(BLOCK), 0, st, g, R);
+        }
+    } else {
+        if (R.pull_k == 2) hipLaunchKernelGGL((k_pull<W, 2>), dim3(g.pull_grid, ng), dim3(BLOCK), 0, st, g, R);
+        else hipLaunchKernelGGL((k_pull<W, 0>), dim3(g.pull_grid, ng), dim3(BLOCK), 0, st, g, R);
+    }
     if (e1) {
         const hipError_t e = hipEventRecord(e1, st);
         if (e != hipSuccess) return e;

@@ -266,6 +266,76 @@ def test_batched_union_matches_solo_runs():
             assert np.array_equal(sig[offs[k]:offs[k + 1]], pad_words(w["final_sig"], r.words)), k
 
 
+# ------------------------------------------------------------ short lists
+
+PULL_NPL = 6   # the pull's one-lane-per-node limit (successors per node)
+
+
+def capped_degree_graph(n, dmax, seed):
+    """A directed graph with out-degree at most dmax, a quarter of the nodes at
+    exactly dmax (distinct successors, no self-loops)."""
+    rng = np.random.default_rng(seed)
+    deg = rng.integers(0, dmax + 1, n)
+    deg[rng.random(n) < 0.25] = dmax
+    src, dst = [], []
+    for u in range(n):
+        off = 1 + rng.choice(n - 1, int(deg[u]), replace=False)
+        src.append(np.full(len(off), u))
+        dst.append((u + off) % n)
+    return np.concatenate(src).astype(np.int32), np.concatenate(dst).astype(np.int32)
+
+
+@pytest.mark.parametrize("dmax", [1, PULL_NPL, PULL_NPL + 1])
+@pytest.mark.parametrize("s", [40, 64, 100, 128])
+def test_short_list_pull(dmax, s):
+    """Graphs whose every node has at most PULL_NPL successors and no high-degree
+    chunk take the pull's short-list form at one- and two-word rows; one more
+    successor on some node takes the general form.  Both against the oracle, with
+    every round a pull and with the heuristic's mix."""
+    n = 2500
+    src, dst = capped_degree_graph(n, dmax, 900 + dmax)
+    seeds = gen.sample_seeds(n, s, 31 + s)
+    want = oracle.propagate(n, src, dst, seeds, False, seed_counts=True, final_sig=True)
+    for sched in (pp.PP_SCHED_PULL, pp.PP_SCHED_HEURISTIC):
+        say("short lists dmax", dmax, "s", s, "sched", sched)
+        check_run(n, src, dst, seeds, False, sched=sched, want=want)
+
+
+def test_short_list_pull_batch():
+    """A batch of lattices, paths and cycles (every list short) whose members
+    converge at different rounds: the pull's short-list form copies the rows of
+    a converged member and gathers for the others."""
+    graphs = [gen.grid_graph(30, 20), gen.path_graph(400), gen.cycle_graph(9, directed=True),
+              gen.grid_graph(5, 5), gen.path_graph(1), gen.cycle_graph(150)]
+    s = 100
+    offs, srcs, dsts, seeds, wants = [0], [], [], [], []
+    for k, g in enumerate(graphs):
+        sd = np.resize(gen.sample_seeds(g.n, min(s, g.n), 60 + k), s)
+        wants.append(oracle.propagate(g.n, g.src, g.dst, sd, g.undirected, seed_counts=True, final_sig=True))
+        src, dst = g.src.astype(np.int64), g.dst.astype(np.int64)
+        if g.undirected:
+            src, dst = np.concatenate([src, dst]), np.concatenate([dst, src])
+        srcs.append(src + offs[-1])
+        dsts.append(dst + offs[-1])
+        seeds.append(sd + offs[-1])
+        offs.append(offs[-1] + g.n)
+    G = pp.pp_csr_build(offs[-1], np.concatenate(srcs).astype(np.int32), np.concatenate(dsts).astype(np.int32),
+                        node_offsets=offs)
+    for sched, persistent in ((pp.PP_SCHED_PULL, False), (pp.PP_SCHED_HEURISTIC, False), (pp.PP_SCHED_PULL, True)):
+        say("short-list batch", sched, "persistent", persistent)
+        r = pp.pp_seeds_init(G, np.concatenate(seeds), s=s,
+                             opts=pp.options(scheduler=sched, seed_counts=True, max_rounds=600, persistent=persistent))
+        counts, D = pp.pp_propagate_until_converged(r)
+        sc = pp.pp_get_seed_counts(r, 600)
+        sig = pp.pp_get_signatures(r)
+        for k, w in enumerate(wants):
+            assert int(D[k]) == w["D"], k
+            assert list(counts[k][:w["D"] + 1]) == list(w["counts"]), k
+            assert np.array_equal(sc[k][:w["D"] + 1], w["seed_counts"]), k
+            assert np.array_equal(sig[offs[k]:offs[k + 1]], pad_words(w["final_sig"], r.words)), k
+        r.free()
+
+
 # ------------------------------------------------------------ full size
 
 def test_rmat26_full_size_sampled_seeds():
