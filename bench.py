@@ -69,9 +69,23 @@ TRAFFIC_PROFILES = {("rmat20", False): ["k_pull_rmat20_s256"], ("rmat20", True):
                     ("grid:4096", False): ["k_pull_grid4096_s128"], ("grid:4096", True): ["k_pull_grid4096_s128"]}
 
 
-def pull_kernel(W: int, pull_k: int) -> str:
-    """The dense pull kernel's name for rows of W words and pull_k arcs per lane."""
+PULL_NPL = 6   # successors per node up to which the pull gathers one node per lane
+
+
+def pull_kernel(W: int, pull_k: int, short: bool = False) -> str:
+    """The dense pull kernel's name for rows of W words and pull_k arcs per lane;
+    short: every stored node has at most PULL_NPL successors (the short-list
+    form, launched for rows of one or two words at the default pull_k)."""
+    if short and W <= 2 and pull_k != 2:
+        return f"k_pull_short<{W}>"
     return f"k_pull<{W}, {2 if pull_k == 2 else 0}>"
+
+
+def short_lists(pp, G) -> bool:
+    """Whether no stored node of G has more than PULL_NPL successors."""
+    rp = np.zeros(G.nodes + 1, np.int64)
+    pp._check(pp.lib().pp_graph_get_csr(G.handle, pp._np_ptr(rp), None, None, None, None))
+    return G.nodes == 0 or int(np.diff(rp).max()) <= PULL_NPL
 
 
 def traffic_for(profiles, kernel: str):
@@ -528,7 +542,8 @@ def time_propagation(args, torch, pp, G, seeds, opts, stream, params=None):
         write_round_log(args.round_log, pp, run_t, G, counts[0], int(D[0]), logs)
     out = {"counts": counts[0], "D": int(D[0]), "elapsed": elapsed, "elapsed_t": elapsed_t, "per_step": per_step,
            "pull_ms": (ms_after - ms_before) / args.steps, "logs": logs, "words": run.words,
-           "group_words": run.group_words, "groups": run.groups, "dseeds": dseeds}
+           "group_words": run.group_words, "groups": run.groups, "dseeds": dseeds,
+           "short": run.group_words <= 2 and short_lists(pp, G)}
     run.free()
     run_t.free()
     return out
@@ -556,11 +571,11 @@ def step_figures(args, pp, T, m, n, s, wl, opts):
     achieved = bytes_pull / t_pull / 1e9 if t_pull > 0 else 0.0
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": (traffic_for(TRAFFIC_PROFILES[(wl, by_reach)], pull_kernel(Wg, opts.pull_k))
+            "traffic": (traffic_for(TRAFFIC_PROFILES[(wl, by_reach)], pull_kernel(Wg, opts.pull_k, T["short"]))
                         if ((wl, by_reach) in TRAFFIC_PROFILES and not opts.persistent and
                             args.sparse_pull == 0 and args.push_div == 0 and args.scheduler == "heuristic")
                         else None),
-            "kernel": f"k_batch<{Wg}> pull phase" if opts.persistent else pull_kernel(Wg, opts.pull_k),
+            "kernel": f"k_batch<{Wg}> pull phase" if opts.persistent else pull_kernel(Wg, opts.pull_k, T["short"]),
             "timing": ("device clock between grid barriers" if opts.persistent else
                        "HIP events around each launch, on the run's stream, over a second timed region of "
                        "the same steps"),

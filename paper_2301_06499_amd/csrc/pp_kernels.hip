@@ -208,12 +208,57 @@ template <int W> PP_DEV void seed_flush(const RunDev &R, int r, const uint32_t (
     }
 }
 
-// Per-seed counts of one word for a graph of a batch (one atomic per set bit).
-PP_DEV void seed_bits(const RunDev &R, int r, int gi, int w, uint64_t d) {
-    while (d) {
-        const int bit = __ffsll((long long)d) - 1;
-        d &= d - 1;
-        atomicAdd(&R.seed_counts[(int64_t)r * R.sstride + (int64_t)gi * R.sg + w * 64 + bit], 1u);
+// Counts of a batch of graphs, combined over the wave before the atomics: the
+// lanes of a wave mostly hold nodes of one graph (a list's entries and a
+// tile's nodes are in node order, and each graph is a node range), and every
+// lane adding into its graph's counter on its own would queue thousands of
+// same-address atomics per round on a few cache lines.  Every lane of the
+// wave calls; key: the lane's graph (any value where v = 0).
+PP_DEV void wave_add_keyed(unsigned long long *base, int key, unsigned long long v) {
+    const int ln = lane_id();
+    uint64_t todo = __ballot(v != 0);
+    while (todo) {   // wave-uniform: one pass per graph present
+        const int lead = __builtin_ctzll(todo);
+        const int k = __shfl(key, lead);
+        const bool mine = ((todo >> ln) & 1ull) && key == k;
+        const unsigned long long t = wave_sum(mine ? v : 0ull);
+        if (ln == lead) atomicAdd(base + k, t);
+        todo &= ~__ballot(mine);
+    }
+}
+
+// Per-seed counts of a batch: lane ln holds word ln % W of a row of graph
+// gi, d its new bits; the lanes of one graph are counted per seed bit by
+// ballot and each seed with new bits takes one atomic.  Every lane of the
+// wave calls.
+template <int W> PP_DEV void seed_bits_keyed(const RunDev &R, int r, int gi, uint64_t d, bool valid) {
+    const int ln = lane_id();
+    uint64_t todo = __ballot(valid && d != 0);
+    while (todo) {   // wave-uniform
+        const int k = __shfl(gi, __builtin_ctzll(todo));
+        const bool mine = valid && gi == k;
+        const uint64_t dm = mine ? d : 0ull;
+        uint64_t any = dm;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) any |= __shfl_xor(any, o);
+        uint32_t c[W];
+#pragma unroll
+        for (int w = 0; w < W; ++w) c[w] = 0;
+        while (any) {   // the seed bits set in any lane of the graph
+            const int b = __builtin_ctzll(any);
+            any &= any - 1;
+            const uint64_t m = __ballot((int)((dm >> b) & 1ull));
+#pragma unroll
+            for (int w = 0; w < W; ++w) {
+                const uint32_t cw = (uint32_t)__popcll(m & (WordMask<W>::rep << w));
+                if (ln == b) c[w] = cw;
+            }
+        }
+        const int64_t base = (int64_t)r * R.sstride + (int64_t)k * R.sg;
+#pragma unroll
+        for (int w = 0; w < W; ++w)
+            if (c[w]) atomicAdd(&R.seed_counts[base + w * 64 + ln], c[w]);
+        todo &= ~__ballot(mine && d != 0);
     }
 }
 
@@ -633,16 +678,13 @@ PP_DEV void commit_items(const GraphDev &g, const RunDev &R, int init, bool appl
 #pragma unroll
         for (int k = 0; k < U; ++k) {
             const int pc = __popcll(d[k]);
-            int gi = 0;
             if (R.G == 1) {
                 pop += (uint64_t)pc;
-            } else if (valid[k]) {
-                gi = g.node_graph[u[k]];
-                if (pc) atomicAdd((unsigned long long *)&R.counts[(int64_t)r * R.cstride + gi], (unsigned long long)pc);
-            }
-            if (per_seed) {
-                if (R.G == 1) seed_ballot<W>(d[k], sc);
-                else if (valid[k]) seed_bits(R, r, gi, w, d[k]);
+                if (per_seed) seed_ballot<W>(d[k], sc);
+            } else {
+                const int gi = valid[k] ? g.node_graph[u[k]] : 0;
+                wave_add_keyed((unsigned long long *)&R.counts[(int64_t)r * R.cstride], gi, (unsigned long long)pc);
+                if (per_seed) seed_bits_keyed<W>(R, r, gi, d[k], valid[k]);
             }
         }
     }
@@ -904,7 +946,7 @@ PP_DEV void phase_pull(const GraphDev &g, const RunDev &R, int bid, int nb) {
                 }
                 if (per_seed) {
                     if (R.G == 1) seed_ballot<W>(nw2, sc);
-                    else if (valid) seed_bits(R, r, T.graph, idx & (W - 1), nw2);
+                    else seed_bits_keyed<W>(R, r, T.graph, nw2, valid);
                 }
             }
             if (R.G == 1) {
@@ -979,16 +1021,13 @@ PP_DEV void phase_pull_hubs(const GraphDev &g, const RunDev &R, int bid, int nb,
             R.stamp[u] = r;
         }
         const int pc = __popcll(nw);
-        int gi = 0;
         if (R.G == 1) {
             pop += (uint64_t)pc;
-        } else if (valid) {
-            gi = g.node_graph[u];
-            if (pc) atomicAdd((unsigned long long *)&R.counts[(int64_t)r * R.cstride + gi], (unsigned long long)pc);
-        }
-        if (per_seed) {
-            if (R.G == 1) seed_ballot<W>(nw, sc);
-            else if (valid) seed_bits(R, r, gi, w, nw);
+            if (per_seed) seed_ballot<W>(nw, sc);
+        } else {
+            const int gi = valid ? g.node_graph[u] : 0;
+            wave_add_keyed((unsigned long long *)&R.counts[(int64_t)r * R.cstride], gi, (unsigned long long)pc);
+            if (per_seed) seed_bits_keyed<W>(R, r, gi, nw, valid);
         }
     }
     __shared__ unsigned long long s_red[BLOCK / 64];
