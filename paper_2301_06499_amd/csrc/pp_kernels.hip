@@ -699,10 +699,11 @@ PP_DEV void commit_items(const GraphDev &g, const RunDev &R, int init, bool appl
 // go to its slots of the per-block partials instead of the round's
 // counters, which the round's end then sums.
 // UMAX: at most this many items per thread and pass (1 keeps the LDS and
-// registers small, for the persistent kernel).
+// registers small, for the persistent kernel).  pstride: distance between
+// the three partials' arrays (a one-block cluster keeps its three in LDS).
 template <int W, int UMAX = 4>
 PP_DEV void phase_push_commit(const GraphDev &g, const RunDev &R, int init, int bid, int nb, int64_t *parts = nullptr,
-                              bool apply = false) {
+                              bool apply = false, int pstride = POST_MAX) {
     Ctrl *C = R.ctrl;
     const int r = init ? 0 : CTL(C->round);
     const int p = r & 1;
@@ -724,9 +725,9 @@ PP_DEV void phase_push_commit(const GraphDev &g, const RunDev &R, int init, int 
     const unsigned long long ta = block_sum<unsigned long long>((unsigned long long)arcs, s_red);
     if (threadIdx.x == 0) {
         if (parts) {
-            PUT(parts[0 * POST_MAX + bid], (int64_t)tp);
-            PUT(parts[1 * POST_MAX + bid], (int64_t)0);
-            PUT(parts[2 * POST_MAX + bid], (int64_t)ta);
+            PUT(parts[0 * pstride + bid], (int64_t)tp);
+            PUT(parts[1 * pstride + bid], (int64_t)0);
+            PUT(parts[2 * pstride + bid], (int64_t)ta);
         } else {
             if (R.G == 1 && tp) atomicAdd((unsigned long long *)&R.counts[(int64_t)r * R.cstride], tp);
             if (ta) atomicAdd((unsigned long long *)&C->f_arcs[p], ta);
@@ -1634,7 +1635,7 @@ PP_DEV int32_t take_action(const RunDev &R, int32_t round, int32_t action, int32
 enum { INFER_WAVE = 0, INFER_BLOCK = 1, INFER_NONE = 2 };
 template <int INFER = INFER_WAVE>
 PP_DEV void phase_round_end(const GraphDev &g, const RunDev &R, int init, int nparts, const int64_t *parts = nullptr,
-                            int npost = 0, bool direct_only = false) {
+                            int npost = 0, bool direct_only = false, int pstride = POST_MAX) {
     Ctrl *C = R.ctrl;
     const int r = init ? 0 : CTL(C->round);
     const int mode = init ? MODE_INIT : CTL(C->mode);
@@ -1668,9 +1669,9 @@ PP_DEV void phase_round_end(const GraphDev &g, const RunDev &R, int init, int np
     for (int j = 0; j < POST_MAX / BLOCK; ++j) {   // all loads issued before the sums
         const int b = threadIdx.x + j * BLOCK;
         if (b < npost) {
-            v[0] += CTL(parts[0 * POST_MAX + b]);
-            v[1] += CTL(parts[1 * POST_MAX + b]);
-            v[2] += CTL(parts[2 * POST_MAX + b]);
+            v[0] += CTL(parts[0 * pstride + b]);
+            v[1] += CTL(parts[1 * pstride + b]);
+            v[2] += CTL(parts[2 * pstride + b]);
         }
     }
 #pragma unroll
@@ -1705,7 +1706,9 @@ PP_DEV void phase_round_end(const GraphDev &g, const RunDev &R, int init, int np
     for (int gi = threadIdx.x; gi < R.G; gi += BLOCK) {
         const long long c = own >= 0 ? own : CTL(R.counts[(int64_t)r * R.cstride + gi]);
         cnt += c;
-        if (R.gconv[gi]) continue;
+        // a single graph whose round ends here has not converged (its
+        // rounds stop with it), so its flag need not be read
+        if (own < 0 && R.gconv[gi]) continue;
         if (c == 0) {
             R.gconv[gi] = 1;
         } else {
@@ -2114,6 +2117,10 @@ __global__ void __launch_bounds__(BLOCK) k_batch(GraphDev g, RunDev R, const Clu
     Ctrl *C = rv.ctrl;
     GridBar *bar = rv.bar;
     const bool lead = bid == 0 && threadIdx.x == 0;
+    // a one-block cluster's commit hands its new-bit count and arcs to the
+    // round's end through LDS, not through the graph's counter in memory
+    __shared__ int64_t s_parts[3];
+    int64_t *const lparts = local ? s_parts : nullptr;
     bool ok = true;
     if (CTL(C->round) == 0 && !CTL(C->converged)) {
         phase_push_commit<W, 1>(gv, rv, 1, bid, nb);
@@ -2137,7 +2144,7 @@ __global__ void __launch_bounds__(BLOCK) k_batch(GraphDev g, RunDev R, const Clu
             phase_push<W, false>(gv, rv, bid, nb);
             if (!cluster_barrier(bar, bid, nb)) break;
             if (lead && stamp) stamp[1] = (int64_t)wall_clock64();
-            phase_push_commit<W, 1>(gv, rv, 0, bid, nb);
+            phase_push_commit<W, 1>(gv, rv, 0, bid, nb, lparts, false, 1);
             if (!cluster_barrier(bar, bid, nb)) break;
         } else {
             phase_pull<W>(gv, rv, bid, nb);
@@ -2148,7 +2155,8 @@ __global__ void __launch_bounds__(BLOCK) k_batch(GraphDev g, RunDev R, const Clu
                 if (!cluster_barrier(bar, bid, nb)) break;
             }
         }
-        if (bid == 0) phase_round_end(gv, rv, 0, nb, nullptr, 0, true);
+        const bool lp = local && mode == MODE_PUSH;
+        if (bid == 0) phase_round_end(gv, rv, 0, nb, lp ? lparts : nullptr, lp ? 1 : 0, true, 1);
         if (lead && stamp) stamp[2] = (int64_t)wall_clock64();
         if (!cluster_barrier(bar, bid, nb)) break;
     }
