@@ -114,6 +114,7 @@ struct TileSet {
     int32_t *hub_node = nullptr;   // node of each high-degree entry
     int32_t nhubs = 0;
     bool short_lists = false;      // no hubs and no node above PULL_NPL successors
+    int64_t dead = 0;              // nodes without successors
     std::vector<int32_t> gtile;    // [G+1] first tile of each graph
     std::vector<int32_t> ghub;     // [G+1] first hub of each graph
 };
@@ -451,7 +452,11 @@ int ensure_tiles(pp_graph g, int W, int K, TileSet **out) {
     ts.ntiles = (int32_t)tiles.size();
     ts.nhubs = (int32_t)hubs.size();
     int64_t dmax = 0;
-    for (int64_t u = 0; u < g->n; ++u) dmax = std::max(dmax, g->rp_host[u + 1] - g->rp_host[u]);
+    for (int64_t u = 0; u < g->n; ++u) {
+        const int64_t d = g->rp_host[u + 1] - g->rp_host[u];
+        dmax = std::max(dmax, d);
+        ts.dead += d == 0;
+    }
     ts.short_lists = hubs.empty() && dmax <= pp::PULL_NPL;
     hipError_t e = hipSuccess;
     if (!tiles.empty()) e = hipMemcpy(ts.tiles, tiles.data(), sizeof(Tile) * tiles.size(), hipMemcpyHostToDevice);
@@ -503,6 +508,11 @@ GraphDev graph_view(pp_graph g, const TileSet *ts, int W) {
     d.G = g->G;
     d.pull_grid = pp::pull_grid_for(d.ntiles, W);
     d.short_lists = ts && ts->short_lists ? 1 : 0;
+    // rows of nodes without successors are skipped by the pull when there are
+    // many (a quarter of the nodes or more) and the two signature buffers
+    // exceed the 256 MB last-level cache: the copy would go to HBM; a graph
+    // whose rows stay in the cache loses more to the test than it saves
+    d.skip_dead = ts && ts->dead * 4 >= g->n && 16.0 * W * (double)g->n > 256.0 * 1048576.0 ? 1 : 0;
     return d;
 }
 

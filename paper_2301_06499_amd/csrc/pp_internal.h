@@ -176,7 +176,8 @@ struct GraphDev {
     int32_t pull_grid;           // blocks of the pull launch (= per-block partial slots)
     int32_t short_lists;         // no high-degree chunks and every node at most PULL_NPL
                                  // successors: the pull launches its short-list form
-    int32_t pad_graph;
+    int32_t skip_dead;           // the pull leaves the rows of nodes without successors
+                                 // alone (many such nodes, rows beyond the caches)
 };
 
 // A pull tile whose nodes have at most PULL_NPL successors each gathers with

@@ -762,7 +762,8 @@ PP_DEV void stage_tile(const GraphDev &g, const Tile &T, int ln, int32_t (&cv)[K
 // SHORT: every tile of the graph takes the one-lane-per-node gather (rows of
 // one or two words, no high-degree chunks): the general gather is not
 // compiled in, which leaves the kernel fewer registers and more waves.
-template <int W, int KK = 0, bool SHORT = false>
+// DEAD: the rows of nodes without successors are left alone (see below).
+template <int W, int KK = 0, bool SHORT = false, bool DEAD = false>
 PP_DEV void phase_pull(const GraphDev &g, const RunDev &R, int bid, int nb) {
     Ctrl *C = R.ctrl;
     using PS = PullShape<W, KK>;
@@ -831,11 +832,19 @@ PP_DEV void phase_pull(const GraphDev &g, const RunDev &R, int bid, int nb) {
             T = Tn;
             continue;
         }
+        // A node without successors keeps its row for good, and the row is the
+        // same in both buffers (the initialisation writes the seed bits into
+        // both): with DEAD it is neither read nor written here (rowmask bit i:
+        // the tile's node i has successors).  On a large R-MAT graph most
+        // nodes have none.
+        uint64_t rowmask = 0;
+        if constexpr (DEAD) rowmask = hub ? 0ull : __ballot(ln < nn && rp_l[ln + 1] > rp_l[ln]);
         uint64_t own[W];
 #pragma unroll
         for (int j = 0; j < W; ++j) {
-            const int idx = ln + j * 64;
-            own[j] = (!hub && idx < nn * W) ? sig[(int64_t)T.u0 * W + idx] : 0;
+            const int idx = ln + j * 64;   // word idx % W of node idx / W (< 64)
+            const bool rw = DEAD ? ((rowmask >> (idx / W)) & 1ull) != 0 : (!hub && idx < nn * W);
+            own[j] = rw ? sig[(int64_t)T.u0 * W + idx] : 0;
         }
 
         // a tile whose lists are all short (one- and two-word rows, at most
@@ -931,7 +940,7 @@ PP_DEV void phase_pull(const GraphDev &g, const RunDev &R, int bid, int nb) {
                 const bool valid = idx < nn * W;
                 uint64_t nw2 = 0;
                 const int32_t u = T.u0 + idx / W;
-                if (valid) {
+                if (DEAD ? ((rowmask >> (idx / W)) & 1ull) != 0 : valid) {
                     const uint64_t av = acc_l[idx];
                     nw2 = av & ~own[j];
                     nxt[(int64_t)T.u0 * W + idx] = own[j] | av;
@@ -1787,7 +1796,7 @@ template <int W> __global__ void __launch_bounds__(BLOCK) k_push_commit(GraphDev
 // launches).  The listing uses at most FRONTIER_BLOCKS blocks: each takes one
 // reservation atomic on a single address, and those serialise.
 constexpr int FRONTIER_BLOCKS = 1024;
-template <int W, int KK>
+template <int W, int KK, bool DEAD = false>
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(W >= 8 ? 2 : PP_PULL_WAVES)))
 k_pull(GraphDev g, RunDev R0) {
     const RunDev R = group_view(R0, blockIdx.y);
@@ -1798,7 +1807,7 @@ k_pull(GraphDev g, RunDev R0) {
         if (r < R.cap) R.phase_log[(int64_t)r * 3] = (int64_t)wall_clock64();
     }
     if (C->mode == MODE_PULL) {
-        phase_pull<W, KK>(g, R, blockIdx.x, gridDim.x);
+        phase_pull<W, KK, false, DEAD>(g, R, blockIdx.x, gridDim.x);
     } else if (C->prev_mode == MODE_PULL && blockIdx.x < FRONTIER_BLOCKS) {
         const int nb = gridDim.x < FRONTIER_BLOCKS ? (int)gridDim.x : FRONTIER_BLOCKS;
         phase_frontier<W, 1024>(g, R, blockIdx.x, nb);
@@ -2262,17 +2271,18 @@ static hipError_t round_impl(const GraphDev &g, const RunDev &R, hipStream_t st,
         if (e != hipSuccess) return e;
     }
     const unsigned ng = (unsigned)R.ngroups;   // every launch covers every seed group (blockIdx.y)
-    if constexpr (W <= 2) {
-        if (g.short_lists && R.pull_k != 2) {
-            hipLaunchKernelGGL(k_pull_short<W>, dim3(g.pull_grid, ng), dim3(BLOCK), 0, st, g, R);
-        } else if (R.pull_k == 2) {
-            hipLaunchKernelGGL((k_pull<W, 2>), dim3(g.pull_grid, ng), dim3(BLOCK), 0, st, g, R);
-        } else {
-            hipLaunchKernelGGL((k_pull<W, 0>), dim3(g.pull_grid, ng), dim3(BLOCK), 0, st, g, R);
-        }
+    // the pull's form for this graph: short lists only, rows of nodes without
+    // successors left alone, or the general one
+    bool short_form = false;
+    if constexpr (W <= 2) short_form = g.short_lists && R.pull_k != 2;
+    if (short_form) {
+        if constexpr (W <= 2) hipLaunchKernelGGL(k_pull_short<W>, dim3(g.pull_grid, ng), dim3(BLOCK), 0, st, g, R);
+    } else if (R.pull_k == 2) {
+        hipLaunchKernelGGL((k_pull<W, 2>), dim3(g.pull_grid, ng), dim3(BLOCK), 0, st, g, R);
+    } else if (g.skip_dead) {
+        hipLaunchKernelGGL((k_pull<W, 0, true>), dim3(g.pull_grid, ng), dim3(BLOCK), 0, st, g, R);
     } else {
-        if (R.pull_k == 2) hipLaunchKernelGGL((k_pull<W, 2>), dim3(g.pull_grid, ng), dim3(BLOCK), 0, st, g, R);
-        else hipLaunchKernelGGL((k_pull<W, 0>), dim3(g.pull_grid, ng), dim3(BLOCK), 0, st, g, R);
+        hipLaunchKernelGGL((k_pull<W, 0>), dim3(g.pull_grid, ng), dim3(BLOCK), 0, st, g, R);
     }
     if (e1) {
         const hipError_t e = hipEventRecord(e1, st);
