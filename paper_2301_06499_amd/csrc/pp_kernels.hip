@@ -1472,6 +1472,27 @@ PP_DEV int32_t sparse_dir(const RunDev &R, int32_t r, int32_t d) {
     return (mix64(~R.fuzz_seed + (uint64_t)r * 0xD1B54A32D192ED03ull) >> 63) ? MODE_SPULL : MODE_PUSH;
 }
 
+// log2(x) for x >= 1, to about 1e-15 relative: x = m 2^e with m in
+// [sqrt(1/2), sqrt(2)) (frexp, then one halving of the range), and
+// ln m = 2 artanh(t) = 2 (t + t^3/3 + t^5/5 + ...) with t = (m - 1)/(m + 1),
+// |t| <= 0.1716, summed to t^17/17 (the next term is below 1e-16 of the sum).
+// It stands in for the library's double log2, whose long dependent chain sat
+// on every round's path through the round's end (about 0.5 us per round of a
+// one-block cluster), for features that are then rounded to float.
+PP_DEV double log2_series(double x) {
+    int e = 0;
+    double m = frexp(x, &e);   // m in [0.5, 1)
+    if (m < 0.70710678118654752440) {
+        m *= 2.0;
+        e -= 1;
+    }
+    const double t = (m - 1.0) / (m + 1.0), t2 = t * t;
+    double p = 1.0 / 17.0;
+#pragma unroll
+    for (int k = 15; k >= 1; k -= 2) p = p * t2 + 1.0 / (double)k;
+    return (double)e + 2.0 * t * p * 1.44269504088896340736;   // 1 / ln 2
+}
+
 // The eight frontier features of the round after `r` (each roughly in [0, 1]):
 // changed nodes / n, their predecessor arcs / m, reached (node, seed) pairs /
 // (n s), new bits of round r / (n s), growth of the new-bit count (ratio to
@@ -1488,8 +1509,8 @@ PP_DEV void sched_features(const GraphDev &g, const RunDev &R, int r, int mode, 
     f[3] = (float)((double)cnt / pairs);
     const double grow = (double)cnt / (double)(last > 0 ? last : 1);
     f[4] = (float)((grow < 4.0 ? grow : 4.0) / 4.0);
-    f[5] = (float)(log2((double)r + 1.0) / 16.0);
-    f[6] = (float)(log2((double)farcs / (double)(fnodes > 0 ? fnodes : 1) + 1.0) / 16.0);
+    f[5] = (float)(log2_series((double)r + 1.0) / 16.0);
+    f[6] = (float)(log2_series((double)farcs / (double)(fnodes > 0 ? fnodes : 1) + 1.0) / 16.0);
     f[7] = mode == MODE_PULL ? 1.0f : 0.0f;
 }
 
