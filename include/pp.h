@@ -67,10 +67,12 @@ enum {
     PP_INPUT_ON_DEVICE = 2,  /* src/dst point to device memory */
     PP_TRANSPOSE = 4,        /* propagate along reversed arcs: bit i reaches u when
                                 x_i can reach u (instead of u reaching x_i) */
-    PP_KEEP_ORDER = 8,       /* store the nodes in input order (by default the nodes
-                                with the most predecessors are stored first, which
-                                only changes the layout: every result is reported
-                                by input node id) */
+    PP_KEEP_ORDER = 8,       /* store the nodes in input order (by default, per
+                                graph, the nodes with the most predecessors are
+                                stored first, or, in a graph without such nodes,
+                                the nodes are numbered in breadth-first order;
+                                either only changes the layout: every result is
+                                reported by input node id) */
     PP_BUILD_ON_HOST = 16,   /* sort the arcs on host threads (the default below
                                 PP_DEVICE_BUILD_MIN input pairs) */
     PP_BUILD_ON_DEVICE = 32  /* sort the arcs on the device (the default from

@@ -21,12 +21,13 @@ int device_check_arcs(const int32_t *a, const int32_t *b, int64_t m, int64_t n, 
                       int64_t *first_bad, hipStream_t st);
 // The rows of arcs a[k] -> b[k] (device; and b -> a when undirected), without
 // self-loops and duplicates, each sorted, and their transpose.  order(rp, trp,
-// perm) gets the host offsets of both by input id and may fill perm (the
-// stored id of each input node) and return true; the rows are then stored in
-// that order (perm is cleared when it returns false).
-int device_build(int64_t n, int64_t m, const int32_t *a, const int32_t *b, bool undirected,
-                 const std::function<bool(const std::vector<int64_t> &, const std::vector<int64_t> &,
-                                          std::vector<int32_t> &)> &order,
+// col, perm) gets the host offsets of both by input id, and col() the host
+// successor ids (by input id, fetched from the device on its first call), and
+// may fill perm (the stored id of each input node) and return true; the rows
+// are then stored in that order (perm is cleared when it returns false).
+using OrderFn = std::function<bool(const std::vector<int64_t> &, const std::vector<int64_t> &,
+                                   const std::function<const int32_t *()> &, std::vector<int32_t> &)>;
+int device_build(int64_t n, int64_t m, const int32_t *a, const int32_t *b, bool undirected, const OrderFn &order,
                  DevRows &rows, DevRows &trows, std::vector<int32_t> &perm, hipStream_t st);
 
 }  // namespace pp

@@ -182,9 +182,7 @@ int device_check_arcs(const int32_t *a, const int32_t *b, int64_t m, int64_t n, 
     return PP_OK;
 }
 
-int device_build(int64_t n, int64_t m, const int32_t *a, const int32_t *b, bool undirected,
-                 const std::function<bool(const std::vector<int64_t> &, const std::vector<int64_t> &,
-                                          std::vector<int32_t> &)> &order,
+int device_build(int64_t n, int64_t m, const int32_t *a, const int32_t *b, bool undirected, const OrderFn &order,
                  DevRows &rows, DevRows &trows, std::vector<int32_t> &perm, hipStream_t st) {
     const int shift = bits_for(n);
     const int bits = 2 * shift;
@@ -243,7 +241,18 @@ int device_build(int64_t n, int64_t m, const int32_t *a, const int32_t *b, bool 
         BUILD_TRY(hipMemcpyAsync(deg_h.data(), indeg.p, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToHost, st));
         BUILD_TRY(hipStreamSynchronize(st));
         for (int64_t v = 0; v < n; ++v) trp_h[(size_t)v + 1] = trp_h[(size_t)v] + deg_h[(size_t)v];
-        const bool moved = order(rp_h, trp_h, perm);
+        std::vector<int32_t> col_h;
+        hipError_t col_err = hipSuccess;
+        const std::function<const int32_t *()> col = [&]() -> const int32_t * {
+            if (col_h.empty() && count > 0) {
+                col_h.resize((size_t)count);
+                col_err = hipMemcpyAsync(col_h.data(), col0.p, sizeof(int32_t) * (size_t)count, hipMemcpyDeviceToHost, st);
+                if (col_err == hipSuccess) col_err = hipStreamSynchronize(st);
+            }
+            return col_h.data();
+        };
+        const bool moved = order(rp_h, trp_h, col, perm);
+        BUILD_TRY(col_err);
         if (!moved) {
             perm.clear();
             rows.rp = rp0.release();
