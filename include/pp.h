@@ -75,9 +75,14 @@ enum {
                                 reported by input node id) */
     PP_BUILD_ON_HOST = 16,   /* sort the arcs on host threads (the default below
                                 PP_DEVICE_BUILD_MIN input pairs) */
-    PP_BUILD_ON_DEVICE = 32  /* sort the arcs on the device (the default from
+    PP_BUILD_ON_DEVICE = 32, /* sort the arcs on the device (the default from
                                 PP_DEVICE_BUILD_MIN input pairs on); both builds
                                 give the same arrays */
+    PP_HUBS_ONLY = 64        /* store the high-degree nodes first but leave the
+                                others in input order, without the breadth-first
+                                numbering: a faster build of a large graph (one
+                                host search over every arc) for one that is
+                                propagated a few times only */
 };
 #define PP_DEVICE_BUILD_MIN (1 << 20)
 

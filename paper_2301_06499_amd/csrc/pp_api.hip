@@ -324,13 +324,15 @@ void transpose_rows(int64_t n, const std::vector<int64_t> &rp, const std::vector
 //   successors in the pull, a frontier's predecessors in a push (on a
 //   lattice they lie along rings).  Against input order for the rest: the
 //   4096^2 lattice 135.5 -> 124.8 ms per propagation, R-MAT scale 26 with
-//   512 seeds 54.4 -> 53.3 ms with seed groups.
+//   512 seeds 53.5 -> 52.3 ms with seed groups.  The searches run on one
+//   host thread (R-MAT 26: about 7 s of the build); searches = false
+//   (PP_HUBS_ONLY) leaves the rest in input order.
 bool storage_order(const std::vector<int64_t> &noff, int G, const std::vector<int64_t> &rp,
-                   const std::vector<int64_t> &trp, const std::function<const int32_t *()> &col_of,
+                   const std::vector<int64_t> &trp, const std::function<const int32_t *()> &col_of, bool searches,
                    std::vector<int32_t> &perm) {
     const int64_t n = (int64_t)rp.size() - 1;
     perm.resize((size_t)n);
-    const int32_t *col = n > 0 && rp[(size_t)n] > 0 ? col_of() : nullptr;
+    const int32_t *col = searches && n > 0 && rp[(size_t)n] > 0 ? col_of() : nullptr;
     bool moved = false;
     for (int g = 0; g < G; ++g) {
         const int64_t a = noff[(size_t)g], b = noff[(size_t)g + 1];
@@ -369,13 +371,14 @@ bool storage_order(const std::vector<int64_t> &noff, int G, const std::vector<in
                 }
             }
         };
-        for (int32_t x : hot) search(x);
+        if (searches && col)
+            for (int32_t x : hot) search(x);
         for (int64_t x = a; x < b; ++x) {
             if (seen[(size_t)(x - a)]) continue;
             seen[(size_t)(x - a)] = 1;
             moved |= pos != x;
             perm[(size_t)x] = (int32_t)pos++;
-            search((int32_t)x);
+            if (searches && col) search((int32_t)x);
         }
     }
     return moved;
@@ -557,7 +560,7 @@ extern "C" int pp_csr_build(int64_t n, int64_t m, const int32_t *src, const int3
     if (m < 0) return fail(PP_EINVAL, "m < 0");
     if (m > 0 && (!src || !dst)) return fail(PP_EINVAL, "src/dst NULL with m > 0");
     if (flags & ~(uint32_t)(PP_UNDIRECTED | PP_INPUT_ON_DEVICE | PP_TRANSPOSE | PP_KEEP_ORDER | PP_BUILD_ON_HOST |
-                            PP_BUILD_ON_DEVICE))
+                            PP_BUILD_ON_DEVICE | PP_HUBS_ONLY))
         return fail(PP_EINVAL, "unknown flag bits");
     if ((flags & PP_BUILD_ON_HOST) && (flags & PP_BUILD_ON_DEVICE))
         return fail(PP_EINVAL, "PP_BUILD_ON_HOST and PP_BUILD_ON_DEVICE together");
@@ -627,7 +630,7 @@ extern "C" int pp_csr_build(int64_t n, int64_t m, const int32_t *src, const int3
     // caller keeps the input order
     auto order = [&](const std::vector<int64_t> &rp_, const std::vector<int64_t> &trp_,
                      const std::function<const int32_t *()> &col_, std::vector<int32_t> &perm_) {
-        return !(flags & PP_KEEP_ORDER) && storage_order(noff, G, rp_, trp_, col_, perm_);
+        return !(flags & PP_KEEP_ORDER) && storage_order(noff, G, rp_, trp_, col_, !(flags & PP_HUBS_ONLY), perm_);
     };
     // propagation rows: u ORs in v for arc u -> v (or v -> u transposed)
     std::vector<int64_t> rp, trp;

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_PKG, "libpp.so")
 
 PP_OK, PP_EINVAL, PP_ERANGE, PP_ENOMEM, PP_EDEVICE, PP_ENOTCONV, PP_ESTATE = 0, -1, -2, -3, -4, -5, -6
 PP_UNDIRECTED, PP_INPUT_ON_DEVICE, PP_TRANSPOSE, PP_KEEP_ORDER = 1, 2, 4, 8
-PP_BUILD_ON_HOST, PP_BUILD_ON_DEVICE = 16, 32
+PP_BUILD_ON_HOST, PP_BUILD_ON_DEVICE, PP_HUBS_ONLY = 16, 32, 64
 DEVICE_BUILD_MIN = 1 << 20
 PP_SCHED_HEURISTIC, PP_SCHED_PULL, PP_SCHED_PUSH, PP_SCHED_FUZZ, PP_SCHED_MLP, PP_SCHED_PLAN = 0, 1, 2, 3, 4, 5
 PP_GROUPS_BY_REACH, PP_ORDER_BY_REACH = -1, 1
@@ -231,13 +231,15 @@ class Graph:
 
 
 def pp_csr_build(n, src, dst, undirected=False, transpose=False, node_offsets=None, stream=None,
-                 keep_order=False, build="auto") -> Graph:
+                 keep_order=False, build="auto", hubs_only=False) -> Graph:
     """Build the device graph from m arcs src[k] -> dst[k] (numpy int32 or device tensors).
-    build: "auto" (the library's choice by size), "host" or "device"."""
+    build: "auto" (the library's choice by size), "host" or "device".
+    hubs_only: the high-degree nodes first, the others in input order (no
+    breadth-first numbering; a faster build)."""
     if build not in ("auto", "host", "device"):
         raise ValueError("build must be 'auto', 'host' or 'device'")
     flags = ((PP_UNDIRECTED if undirected else 0) | (PP_TRANSPOSE if transpose else 0) |
-             (PP_KEEP_ORDER if keep_order else 0) |
+             (PP_KEEP_ORDER if keep_order else 0) | (PP_HUBS_ONLY if hubs_only else 0) |
              {"auto": 0, "host": PP_BUILD_ON_HOST, "device": PP_BUILD_ON_DEVICE}[build])
     keep = []
     if _is_device(src):

@@ -53,6 +53,10 @@ CASES = [
     ("random multigraph transposed", lambda: (3000,) + multigraph(3, 3000, 20000), {"transpose": True}),
     ("random multigraph in input order", lambda: (3000,) + multigraph(4, 3000, 20000), {"keep_order": True}),
     ("rmat with hubs", lambda: (lambda g: (g.n, g.src, g.dst))(gen.rmat(14, 16, 77)), {}),
+    ("rmat with hubs, the rest in input order", lambda: (lambda g: (g.n, g.src, g.dst))(gen.rmat(14, 16, 77)),
+     {"hubs_only": True}),
+    ("grid, input order (no hubs)", lambda: (lambda g: (g.n, g.src, g.dst))(gen.grid_graph(60, 45)),
+     {"undirected": True, "hubs_only": True}),
     ("grid", lambda: (lambda g: (g.n, g.src, g.dst))(gen.grid_graph(60, 45)), {"undirected": True}),
     ("star", lambda: (lambda g: (g.n, g.src, g.dst))(gen.star_graph(3000)), {"undirected": True}),
     ("isolated nodes only", lambda: (100, np.zeros(0, np.int32), np.zeros(0, np.int32)), {}),
@@ -72,6 +76,31 @@ def test_device_build_equals_host_build(case):
         row = col[rp[u]:rp[u + 1]]
         assert np.all(np.diff(row) > 0) and not np.any(row == u)
     assert rp[-1] == gd.arcs == trp[-1]
+
+
+def test_storage_orders_give_the_oracle_results():
+    """The three storage orders of one graph (hubs first then breadth-first, hubs
+    first then input order, input order): the same results as the oracle,
+    reported by input id, and different stored arrays."""
+    g = gen.rmat(12, 16, 9)
+    seeds = gen.sample_seeds(g.n, 200, 4)
+    want = oracle.propagate(g.n, g.src, g.dst, seeds, False, seed_counts=True, final_sig=True)
+    perms = []
+    for kw in ({}, {"hubs_only": True}, {"keep_order": True}):
+        say("order", kw)
+        G = pp.pp_csr_build(g.n, g.src, g.dst, **kw)
+        perms.append(pp.pp_graph_get_csr(G)[4])
+        r = pp.pp_seeds_init(G, seeds, opts=pp.options(seed_counts=True, max_rounds=want["D"] + 4))
+        counts, D = pp.pp_propagate_until_converged(r)
+        assert int(D[0]) == want["D"] and list(counts[0]) == list(want["counts"])
+        assert np.array_equal(pp.pp_get_seed_counts(r, want["D"] + 1)[0], want["seed_counts"])
+        sig = pp.pp_get_signatures(r)
+        assert np.array_equal(sig[:, :want["final_sig"].shape[1]], want["final_sig"])
+        r.free()
+        G.free()
+    assert not np.array_equal(perms[0], perms[1]) and np.array_equal(perms[2], np.arange(g.n))
+    # hubs first in both orders that move nodes: the same node stored first
+    assert int(np.argmin(perms[0])) == int(np.argmin(perms[1]))
 
 
 def test_batch_of_graphs():
