@@ -647,7 +647,7 @@ def learned_object(args, torch, pp, G, g, seeds, base_opts, stream, T, res):
     if "plain" in res:
         out["vs_plain"] = round(res["plain"]["ms_per_step"] / ms, 4)
     log(f"[bench] learned scheduler: {out['ms_per_step']} ms per step (heuristic {res['ms_per_step']})")
-    return out
+    return out, L, opts, params
 
 
 def propagation_line(args, torch, pp, g, seeds, cfg, wl, sample, stream, base_opts, plain_opts=None,
@@ -684,15 +684,30 @@ def propagation_line(args, torch, pp, g, seeds, cfg, wl, sample, stream, base_op
         res["speedup_vs_plain"] = round(P["elapsed"] / T["elapsed"], 4)
         log(f"[bench] {cfg['workload']}: plain {res['plain']['ms_per_step']} ms per step")
     if learned:
-        res["learned"] = learned_object(args, torch, pp, G, g, seeds, base_opts, stream, T, res)
+        # the configuration's own form: seed groups plus the learned scheduler is
+        # the line's value; the same groups under the fixed heuristic stand beside it
+        lo, L, lopts, lparams = learned_object(args, torch, pp, G, g, seeds, base_opts, stream, T, res)
+        keys = ("value", "unit", "ms_per_step", "ms_per_step_min", "ms_per_step_median", "touched_edge_words_per_s",
+                "roofline", "run")
+        res["heuristic"] = {k: res[k] for k in keys}
+        res["heuristic"]["note"] = "the same seed groups under the fixed-threshold heuristic"
+        res.update(step_figures(args, pp, L, m, n, s, wl, lopts))
+        res["config"]["scheduler"] = ("learned: MLP 8-32-32-4 trained on the replayed round costs of another seed "
+                                      "sample of the same graph, the heuristic as fallback")
+        if "plain" in res:
+            res["speedup_vs_plain"] = round(P["elapsed"] / L["elapsed"], 4)
+        res["learned"] = lo
     if args.no_check and args.no_cpu_baseline:
         G.free()
         return res
-    # the check: the same propagation with per-seed counts (untimed) against the timed
-    # counts, its totals against its per-seed sums, and the sampled seeds against the oracle
-    opts_c = pp.Options.from_buffer_copy(base_opts)
+    # the check: the line's own form (with the learned scheduler when it is the
+    # value) with per-seed counts (untimed) against the timed counts, its totals
+    # against its per-seed sums, and the sampled seeds against the oracle
+    opts_c = pp.Options.from_buffer_copy(lopts if learned else base_opts)
     opts_c.seed_counts = 1
     chk = pp.pp_seeds_init(G, seeds, opts=opts_c, stream=stream)
+    if learned:
+        pp.pp_run_set_mlp(chk, lparams)
     pp.pp_seeds_reset(chk, T["dseeds"])
     c2, D2 = pp.pp_propagate_until_converged(chk)
     sc = pp.pp_get_seed_counts(chk, Dv + 1)[0]
@@ -832,7 +847,7 @@ def main():
            "vs_baseline": None, "dtype": "u64", "data": "synthetic", "config": head["config"],
            "touched_edge_words_per_s": head["touched_edge_words_per_s"], "roofline": head["roofline"],
            "run": head["run"]}
-    for k in ("plain", "speedup_vs_plain", "learned", "cpu_baseline", "check"):
+    for k in ("heuristic", "plain", "speedup_vs_plain", "learned", "cpu_baseline", "check"):
         if k in head:
             out[k] = head[k]
     del g
