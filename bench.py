@@ -598,6 +598,10 @@ def step_figures(args, pp, T, m, n, s, wl, opts):
             "launches_per_step": len(pull_rounds),
             "avg_launch_ms": round(t_pull * 1000.0 / max(1, len(pull_rounds)), 4),
             "bytes_per_launch": round(bytes_pull / max(1, len(pull_rounds)))}
+    if roof["traffic"] and pull_rounds and t_pull > 0:
+        # the counted HBM traffic (FETCH_SIZE + WRITE_SIZE per launch) over the same
+        # launch time, against the same peak
+        roof["traffic_frac"] = round(roof["traffic"] / (t_pull / len(pull_rounds)) / 1e9 / HBM_PEAK_GBS, 4)
     code = {pp.MODE_PULL: "P", pp.MODE_PUSH: "S", pp.MODE_PUSH_FLAT: "F", pp.MODE_SPULL: "Q"}
     modes = ["".join(code.get(int(md[r]), "-") for r in range(1, rounds + 1)) for md, _ in T["logs"]]
     return {"value": nominal * args.steps / T["elapsed"], "unit": "edge-words/s",
