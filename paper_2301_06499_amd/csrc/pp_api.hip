@@ -945,16 +945,36 @@ int alloc_run_dev(pp_graph g, RunDev &d, int s_all, int k, int sg, int W, int ca
     return PP_OK;
 }
 
-hipError_t clear_run_dev(pp_graph g, RunDev &d, hipStream_t st, bool with_acc) {
+// clean: per seed group, whether only its seeds' rows (prev_seeds, stored
+// ids, sg per group) can hold bits; those groups clear just those rows.
+hipError_t clear_run_dev(pp_graph g, RunDev &d, hipStream_t st, bool with_acc,
+                         const std::vector<char> &clean = {}, const int32_t *prev_seeds = nullptr) {
     const int64_t n = g->n;
     const int64_t k = d.ngroups;
     const int64_t KG = k * d.G;
     const int64_t cap = d.cap;
     auto seg = [](void *p, int64_t bytes, uint32_t v) { return pp::FillSeg{(uint32_t *)p, bytes / 4, v}; };
-    const pp::FillSeg segs[] = {
-        seg(d.sig[0], 2 * 8 * k * n * d.W, 0u),  // both signature buffers of every group (one allocation)
+    std::vector<pp::FillSeg> rows;   // signature rows and stamps, then the rest: one fill launch
+    bool some_clean = false;
+    for (char c : clean) some_clean |= c != 0;
+    if (!some_clean || !prev_seeds) {
+        rows.push_back(seg(d.sig[0], 2 * 8 * k * n * d.W, 0u));  // both signature buffers of every group
+        rows.push_back(seg(d.stamp, 4 * k * n, 0xFFFFFFFFu));    // -1: never queued
+    } else {
+        for (int64_t j = 0; j < k; ++j) {
+            uint64_t *sj = d.sig[0] + j * 2 * n * d.W;
+            if (clean[(size_t)j]) {
+                const int cnt = j == k - 1 ? d.s_last : d.sg;
+                const hipError_t e = pp::launch_clear_seed_rows(prev_seeds + j * d.sg, cnt, n, d.W, sj, d.stamp + j * n, st);
+                if (e != hipSuccess) return e;
+            } else {
+                rows.push_back(seg(sj, 2 * 8 * n * d.W, 0u));
+                rows.push_back(seg(d.stamp + j * n, 4 * n, 0xFFFFFFFFu));
+            }
+        }
+    }
+    const pp::FillSeg rest[] = {
         seg(d.acc, with_acc ? 8 * k * n * d.W : 0, 0u),
-        seg(d.stamp, 4 * k * n, 0xFFFFFFFFu),    // -1: never queued
         seg(d.counts, 8 * cap * KG, 0u),
         seg(d.seed_counts, d.seed_counts ? 4 * cap * KG * d.sg : 0, 0u),
         seg(d.D, 4 * KG, 0u),
@@ -968,7 +988,8 @@ hipError_t clear_run_dev(pp_graph g, RunDev &d, hipStream_t st, bool with_acc) {
         seg(d.tickets, 4 * pp::TICKET_INTS * k, 0u),
         seg(d.node_acc, d.node_acc ? 8 * n : 0, 0u),
     };
-    return pp::launch_fills(segs, (int)(sizeof(segs) / sizeof(segs[0])), st);
+    rows.insert(rows.end(), std::begin(rest), std::end(rest));
+    return pp::launch_fills(rows.data(), (int)rows.size(), st);
 }
 
 TileSet *run_tiles(pp_run r) { return &r->g->tiles[pull_edges(r->W, r->dev.pull_k)]; }
@@ -1194,7 +1215,17 @@ int reset_run(pp_run r, const int32_t *seeds, const int32_t *map) {
     pp_graph g = r->g;
     TileSet *ts = run_tiles(r);
     GraphDev gv = graph_view(g, ts, r->W);
-    hipError_t e = clear_run_dev(g, r->dev, r->stream, !r->acc_clean);
+    // Seed groups whose rows hold nothing but their seeds' bits: the last
+    // propagation converged without a new bit in the group after round 0 (a
+    // group of seeds without predecessors, as grouping by reach places them
+    // last).  Their reset clears only their seeds' rows.
+    std::vector<char> clean;
+    if (r->grouped && r->G == 1 && r->acc_clean && r->host_ctrl.converged && !r->host_ctrl.bad_seed &&
+        !r->host_ctrl.overflow && (int)r->D_host.size() == r->k) {
+        clean.assign((size_t)r->k, 0);
+        for (int j = 0; j < r->k; ++j) clean[(size_t)j] = r->D_host[(size_t)j] == 0;
+    }
+    hipError_t e = clear_run_dev(g, r->dev, r->stream, !r->acc_clean, clean, r->iseeds);
     if (e == hipSuccess) {
         r->acc_clean = true;
         if (r->grouped) {

@@ -265,6 +265,11 @@ struct FillSeg {
 };
 // Every segment in as few launches as possible (one for up to 16 segments).
 hipError_t launch_fills(const FillSeg *segs, int nseg, hipStream_t st);
+// One seed group's rows and stamps back to the initial state when only its
+// seeds' rows can hold bits: ids [count] stored ids, sig the group's two
+// buffers (n rows of W words each, one after the other), stamp its n stamps.
+hipError_t launch_clear_seed_rows(const int32_t *ids, int count, int64_t n, int W, uint64_t *sig, int32_t *stamp,
+                                  hipStream_t st);
 // out[j] = perm[in[j]] (ids outside [0, n) become -1).
 hipError_t launch_map_ids(int32_t *out, const int32_t *in, const int32_t *perm, int64_t count, int64_t n,
                           hipStream_t st);

@@ -431,6 +431,30 @@ hipError_t launch_fills(const FillSeg *segs, int nseg, hipStream_t st) {
     return flush();
 }
 
+// A seed group's rows back to their initial state where only its seeds can
+// have set bits: the rows of the given stored ids (both buffers) and their
+// stamps.  Ids outside [0, n) are skipped.
+__global__ void __launch_bounds__(BLOCK) k_clear_seed_rows(const int32_t *ids, int count, int64_t n, int W,
+                                                           uint64_t *sig, int32_t *stamp) {
+    for (int i = blockIdx.x * BLOCK + threadIdx.x; i < count; i += gridDim.x * BLOCK) {
+        const int32_t x = ids[i];
+        if (x < 0 || x >= n) continue;
+        for (int w = 0; w < W; ++w) {
+            sig[(int64_t)x * W + w] = 0;
+            sig[n * W + (int64_t)x * W + w] = 0;
+        }
+        stamp[x] = -1;
+    }
+}
+
+hipError_t launch_clear_seed_rows(const int32_t *ids, int count, int64_t n, int W, uint64_t *sig, int32_t *stamp,
+                                  hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_clear_seed_rows, dim3((count + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, st, ids, count, n, W,
+                       sig, stamp);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- node ids
 
 // out[j] = perm[in[j]] for ids in [0, n), -1 otherwise.
