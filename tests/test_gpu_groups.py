@@ -111,6 +111,51 @@ def test_by_reach_on_rmat(sched, sparse):
     assert all(int(m) in (0, 1, 3, 4) for m in modes0[1:want["D"] + 2])
 
 
+@pytest.mark.parametrize("sched", [pp.PP_SCHED_PULL, pp.PP_SCHED_PUSH, pp.PP_SCHED_HEURISTIC])
+def test_resets_after_groups_that_added_nothing(sched):
+    """A reset clears only the seeds' rows of a group whose last propagation
+    added no bit after round 0.  Seed sets that put live seeds into such groups
+    and take them out again, on one run: every count, per-seed count and final
+    signature against the oracle after each reset, including a reset after a
+    propagation stopped after one round (which clears every group in full)."""
+    g = gen.rmat(14, 16, 77)
+    pred = np.bincount(g.dst[g.src != g.dst], minlength=g.n) > 0
+    pool = gen.sample_seeds(g.n, 6000, 9)
+    lv, dd = pool[pred[pool]], pool[~pred[pool]]
+    assert len(lv) >= 600 and len(dd) >= 450
+    few = [np.concatenate([lv[:40], dd[:216]]), np.concatenate([dd[216:416], lv[40:96]])]
+    many = [lv[100:356], lv[356:612]]
+    sets = [few[0], many[0], few[1], many[1], few[0]]
+    sets = [np.ascontiguousarray(s, dtype=np.int32) for s in sets]
+    wants = [oracle.propagate(g.n, g.src, g.dst, sd, False, seed_counts=True, final_sig=True) for sd in sets]
+    G = pp.pp_csr_build(g.n, g.src, g.dst)
+    opts = pp.options(seed_counts=True, max_rounds=max(w["D"] for w in wants) + 4, scheduler=sched,
+                      seed_groups=pp.PP_GROUPS_BY_REACH)
+
+    def run_to_end(r, want, i):
+        counts, D = pp.pp_propagate_until_converged(r)
+        assert int(D[0]) == want["D"], i
+        assert list(counts[0]) == list(want["counts"]), i
+        assert np.array_equal(pp.pp_get_seed_counts(r, want["D"] + 1)[0], want["seed_counts"]), i
+        assert np.array_equal(pp.pp_get_signatures(r), pad_words(want["final_sig"], r.words)), i
+
+    say("resets after dead groups, sched", sched)
+    r = pp.pp_seeds_init(G, sets[0], opts=opts)
+    assert r.groups == 4   # 40 seeds with a predecessor: groups of 64, three of them dead
+    run_to_end(r, wants[0], 0)
+    for i in range(1, len(sets)):
+        say("  set", i)
+        pp.pp_seeds_reset(r, sets[i])
+        run_to_end(r, wants[i], i)
+    say("  stopped after one round, then a reset")
+    pp.pp_seeds_reset(r, sets[2])
+    pp.pp_propagate_round(r)
+    pp.pp_seeds_reset(r, sets[3])
+    run_to_end(r, wants[3], "after a stop")
+    r.free()
+    G.free()
+
+
 @pytest.mark.parametrize("persistent_first", [False])
 def test_batch_of_graphs_with_groups(persistent_first):
     graphs = [gen.grid_graph(20, 15), gen.path_graph(300), gen.rmat(10, 8, 4), gen.star_graph(900),
