@@ -947,8 +947,14 @@ int alloc_run_dev(pp_graph g, RunDev &d, int s_all, int k, int sg, int W, int ca
 
 // clean: per seed group, whether only its seeds' rows (prev_seeds, stored
 // ids, sg per group) can hold bits; those groups clear just those rows.
+// stale1: the other groups clear their first buffer in full and, in the
+// second, only those rows.  That is enough because the second buffer is
+// read only after a pull has made it current, and a pull writes every row
+// there except those of nodes without successors, which no round changes:
+// such a row holds nothing but its node's seed bits from the initialisation.
 hipError_t clear_run_dev(pp_graph g, RunDev &d, hipStream_t st, bool with_acc,
-                         const std::vector<char> &clean = {}, const int32_t *prev_seeds = nullptr) {
+                         const std::vector<char> &clean = {}, const int32_t *prev_seeds = nullptr,
+                         bool stale1 = false) {
     const int64_t n = g->n;
     const int64_t k = d.ngroups;
     const int64_t KG = k * d.G;
@@ -957,18 +963,20 @@ hipError_t clear_run_dev(pp_graph g, RunDev &d, hipStream_t st, bool with_acc,
     std::vector<pp::FillSeg> rows;   // signature rows and stamps, then the rest: one fill launch
     bool some_clean = false;
     for (char c : clean) some_clean |= c != 0;
-    if (!some_clean || !prev_seeds) {
+    if (!prev_seeds || (!some_clean && !stale1)) {
         rows.push_back(seg(d.sig[0], 2 * 8 * k * n * d.W, 0u));  // both signature buffers of every group
         rows.push_back(seg(d.stamp, 4 * k * n, 0xFFFFFFFFu));    // -1: never queued
     } else {
         for (int64_t j = 0; j < k; ++j) {
             uint64_t *sj = d.sig[0] + j * 2 * n * d.W;
-            if (clean[(size_t)j]) {
+            const bool cj = (size_t)j < clean.size() && clean[(size_t)j];
+            if (cj || stale1) {   // the seeds' rows in both buffers (the fill below runs after)
                 const int cnt = j == k - 1 ? d.s_last : d.sg;
                 const hipError_t e = pp::launch_clear_seed_rows(prev_seeds + j * d.sg, cnt, n, d.W, sj, d.stamp + j * n, st);
                 if (e != hipSuccess) return e;
-            } else {
-                rows.push_back(seg(sj, 2 * 8 * n * d.W, 0u));
+            }
+            if (!cj) {
+                rows.push_back(seg(sj, (stale1 ? 1 : 2) * 8 * n * d.W, 0u));
                 rows.push_back(seg(d.stamp + j * n, 4 * n, 0xFFFFFFFFu));
             }
         }
@@ -1225,7 +1233,10 @@ int reset_run(pp_run r, const int32_t *seeds, const int32_t *map) {
         clean.assign((size_t)r->k, 0);
         for (int j = 0; j < r->k; ++j) clean[(size_t)j] = r->D_host[(size_t)j] == 0;
     }
-    hipError_t e = clear_run_dev(g, r->dev, r->stream, !r->acc_clean, clean, r->iseeds);
+    // The other groups' second buffers keep their rows except the seeds'
+    // (the stored seed list of the last initialisation names them).
+    const bool stale1 = r->grouped && r->G == 1 && r->acc_clean;
+    hipError_t e = clear_run_dev(g, r->dev, r->stream, !r->acc_clean, clean, r->iseeds, stale1);
     if (e == hipSuccess) {
         r->acc_clean = true;
         if (r->grouped) {
