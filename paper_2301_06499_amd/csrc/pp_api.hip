@@ -156,6 +156,9 @@ struct pp_run_s {
     std::map<int, hipGraphExec_t> graphs;   // captured batches by round count
     std::map<int, hipGraph_t> graph_defs;
     int32_t *dseeds = nullptr;              // [G*s] mapped device seeds for the clustered engine
+    // a single graph without seed groups on the per-round engine: dseeds holds
+    // the stored ids of the seeds the last initialisation placed
+    bool seeds_kept = false;
     bool timing = false;
     bool graph_events = true;               // events recorded inside captured graphs work
     std::vector<hipEvent_t> ev;             // 2 per round slot of a batch
@@ -1234,9 +1237,14 @@ int reset_run(pp_run r, const int32_t *seeds, const int32_t *map) {
         for (int j = 0; j < r->k; ++j) clean[(size_t)j] = r->D_host[(size_t)j] == 0;
     }
     // The other groups' second buffers keep their rows except the seeds'
-    // (the stored seed list of the last initialisation names them).
-    const bool stale1 = r->grouped && r->G == 1 && r->acc_clean;
-    hipError_t e = clear_run_dev(g, r->dev, r->stream, !r->acc_clean, clean, r->iseeds, stale1);
+    // (the stored seed list of the last initialisation names them); so does
+    // the second buffer of a single graph without groups once its seeds are
+    // kept.
+    const bool plain1 = !r->grouped && !r->pgrid && r->G == 1;
+    const bool stale1 = r->acc_clean && r->G == 1 && (r->grouped || (plain1 && r->seeds_kept));
+    hipError_t e = clear_run_dev(g, r->dev, r->stream, !r->acc_clean, clean, r->grouped ? r->iseeds : r->dseeds,
+                                 stale1);
+    r->seeds_kept = false;
     if (e == hipSuccess) {
         r->acc_clean = true;
         if (r->grouped) {
@@ -1252,6 +1260,11 @@ int reset_run(pp_run r, const int32_t *seeds, const int32_t *map) {
             if (e == hipSuccess) e = pp::launch_seed_scatter_batch(gv, r->dev, seeds, r->stream);
         } else {
             e = pp::launch_seed_init(gv, r->dev, seeds, map, r->stream);
+            if (e == hipSuccess && plain1) {
+                e = map ? pp::launch_map_ids(r->dseeds, seeds, map, r->s, g->n, r->stream)
+                        : hipMemcpyAsync(r->dseeds, seeds, sizeof(int32_t) * (size_t)r->s, hipMemcpyDefault, r->stream);
+                r->seeds_kept = e == hipSuccess;
+            }
         }
     }
     if (e != hipSuccess) return fail(PP_EDEVICE, "seed initialisation: %s", hipGetErrorString(e));
@@ -1918,6 +1931,7 @@ extern "C" int pp_run_restore(pp_run r, pp_run from) {
     r->counts_host = from->counts_host;
     r->D_host = from->D_host;
     r->acc_clean = from->acc_clean;
+    r->seeds_kept = false;   // the restored rows' seeds are not in this run's list: the next reset clears all
     return PP_OK;
 }
 
